@@ -1,0 +1,339 @@
+"""Plain FP64 CPU oracle for signal-whitened FFT window matching.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py.  Never imported by the product package.
+
+Source: Wetzel et al., "Registering large volume serial-section electron
+microscopy image sets for neural circuit reconstruction using FFT signal
+whitening" (arXiv 1612.04787).  The paper states the method in prose only
+(Section III); every formula below is the plain definition of what that prose
+describes, with the readings of unstated details listed in the repository's
+design notes (taper shape and width, the epsilon floor, the correlation sign,
+the SNR background, the centroid, the projection rounding).
+
+Conventions
+  * Images are row-major [y][x].  A window of edge N has pixel (i, j) = (x, y)
+    index; its window-centred coordinates are u = i - N/2, v = j - N/2.
+  * theta (8 values): cx, cy, a11, a12, tx, a21, a22, ty.  The window samples
+    the image at x = cx + a11 u + a12 v + tx, y = cy + a21 u + a22 v + ty.
+  * Forward DFT unnormalised, inverse DFT scaled by 1/N^2.
+  * Correlation sign: X = conj(F_A) F_B, so if B(x) = A(x - d) the peak is at +d.
+
+Every function is FP64 throughout; library FFTs (NumPy pocketfft) and a few
+array primitives are used as steps, with no blocking, fusion or reordering.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+STATUS_NEAR_TIE = 1
+STATUS_DEGENERATE = 2
+STATUS_CLAMPED = 4
+NEAR_TIE_REL = 2e-4
+
+
+@dataclass
+class Params:
+    """Matching parameters.
+
+    p          whitening exponent in [0, 1]: 0 is plain correlation (NCC-like),
+               1 is phase-only correlation (Section III, whitening paragraph).
+    eps_rel    relative floor of the whitening denominator (design reading).
+    taper_frac fraction of the window edge covered by the cosine taper, both
+               edges together (apodization paragraph of Section III).
+    centroid_r half-width of the sub-pixel centroid box.
+    """
+    p: float = 0.65
+    eps_rel: float = 1e-4
+    taper_frac: float = 0.25
+    centroid_r: int = 1
+
+
+# ---------------------------------------------------------------------------
+# Window gather (tiled local patches, Section III)
+# ---------------------------------------------------------------------------
+def bilinear_clamped(img, x, y):
+    """Bilinear sample of img at real coordinates (x, y), clamp-to-edge reads.
+    Returns (values, clamped_any)."""
+    img = np.asarray(img, dtype=np.float64)
+    h, w = img.shape
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x0 = np.floor(x)
+    y0 = np.floor(y)
+    fx = x - x0
+    fy = y - y0
+    x0 = x0.astype(np.int64)
+    y0 = y0.astype(np.int64)
+    x1 = x0 + 1
+    y1 = y0 + 1
+    clamped = bool(np.any((x0 < 0) | (y0 < 0) | (x1 > w - 1) | (y1 > h - 1)))
+
+    def rd(xx, yy):
+        return img[np.clip(yy, 0, h - 1), np.clip(xx, 0, w - 1)]
+
+    v = (1 - fy) * ((1 - fx) * rd(x0, y0) + fx * rd(x1, y0)) \
+        + fy * ((1 - fx) * rd(x0, y1) + fx * rd(x1, y1))
+    return v, clamped
+
+
+def window_coords(theta, n):
+    """Sample coordinates (x, y) of an n x n window, each of shape (n, n) [j][i]."""
+    cx, cy, a11, a12, tx, a21, a22, ty = [float(t) for t in theta]
+    u = np.arange(n, dtype=np.float64) - n // 2
+    uu, vv = np.meshgrid(u, u)  # uu[j][i] = u_i, vv[j][i] = v_j
+    x = cx + a11 * uu + a12 * vv + tx
+    y = cy + a21 * uu + a22 * vv + ty
+    return x, y, uu, vv
+
+
+def gather(img, theta, n):
+    """Window of edge n sampled from img at the affine theta (bilinear,
+    clamp-to-edge).  Returns (a [n][n] float64, clamped flag)."""
+    x, y, _, _ = window_coords(theta, n)
+    return bilinear_clamped(img, x, y)
+
+
+# ---------------------------------------------------------------------------
+# Apodization: cosine taper (Section III) and mean removal
+# ---------------------------------------------------------------------------
+def taper_1d(n, taper_frac):
+    """Raised-cosine edge taper with L = round(taper_frac * n / 2) samples per
+    edge: t(i) = (1 - cos(pi (i + 1/2) / L)) / 2 for i < L, mirrored at the far
+    edge, 1 in between.  taper_frac = 0 gives all ones."""
+    L = int(np.floor(taper_frac * n / 2.0 + 0.5))
+    t = np.ones(n, dtype=np.float64)
+    for i in range(min(L, n // 2)):
+        t[i] = 0.5 * (1.0 - np.cos(np.pi * (i + 0.5) / L))
+        t[n - 1 - i] = t[i]
+    return t
+
+
+def taper_2d(n, taper_frac):
+    t = taper_1d(n, taper_frac)
+    return np.outer(t, t)
+
+
+def prepare(a, T):
+    """Subtract the taper-weighted mean, then taper: w = (a - m_T) T with
+    m_T = sum(a T) / sum(T).  Returns (w, m_T)."""
+    m = float(np.sum(a * T) / np.sum(T))
+    return (a - m) * T, m
+
+
+# ---------------------------------------------------------------------------
+# Whitened correlation surface (Section III: power scaling of Fourier
+# amplitudes, exponent 0..1; equivalently before or after the multiply)
+# ---------------------------------------------------------------------------
+def whitened_surface(wA, wB, p, eps_rel, return_parts=False):
+    """c = IDFT2( X (|X|^2 + eps^2)^(-p/2) ), X = conj(DFT2 wA) DFT2 wB,
+    eps^2 = eps_rel^2 sum(wA^2) sum(wB^2), DC bin forced to 0."""
+    n = wA.shape[0]
+    FA = np.fft.rfft2(wA)
+    FB = np.fft.rfft2(wB)
+    X = np.conj(FA) * FB
+    r = (X * np.conj(X)).real
+    eps2 = eps_rel ** 2 * float(np.sum(wA * wA)) * float(np.sum(wB * wB))
+    d = r + eps2
+    if p == 0:
+        C = X.copy()
+    else:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            C = np.where(d > 0, X * np.power(d, -0.5 * p), 0.0)
+    C[0, 0] = 0.0
+    c = np.fft.irfft2(C, s=(n, n))
+    if return_parts:
+        return c, dict(FA=FA, FB=FB, X=X, C=C, eps2=eps2)
+    return c
+
+
+def _wrap(i, n):
+    return i - n if i >= n // 2 else i
+
+
+def peak_stats(c, centroid_r=1):
+    """Integer peak (first maximum in row-major order), Z-score SNR over the
+    whole surface (population std), and a (2r+1)^2 centroid with weights
+    max(c - mean, 0), shifts wrapped to [-N/2, N/2)."""
+    n = c.shape[0]
+    flat = int(np.argmax(c.ravel()))
+    iy, ix = divmod(flat, n)
+    peak = float(c[iy, ix])
+    mu = float(np.mean(c))
+    sd = float(np.sqrt(np.mean((c - mu) ** 2)))
+    status = 0
+    if sd > 0:
+        snr = (peak - mu) / sd
+    else:
+        snr = 0.0
+        status |= STATUS_DEGENERATE
+    rest = np.delete(c.ravel(), flat)
+    second = float(np.max(rest)) if rest.size else -np.inf
+    if peak - second <= NEAR_TIE_REL * abs(peak):
+        status |= STATUS_NEAR_TIE
+    sx, sy = _wrap(ix, n), _wrap(iy, n)
+    r = int(centroid_r)
+    sw = swx = swy = 0.0
+    for dyy in range(-r, r + 1):
+        for dxx in range(-r, r + 1):
+            wv = max(float(c[(iy + dyy) % n, (ix + dxx) % n]) - mu, 0.0)
+            sw += wv
+            swx += wv * dxx
+            swy += wv * dyy
+    dx = sx + (swx / sw if sw > 0 else 0.0)
+    dy = sy + (swy / sw if sw > 0 else 0.0)
+    return dict(ix=ix, iy=iy, sx=sx, sy=sy, dx=dx, dy=dy, peak=peak, mean=mu,
+                std=sd, snr=snr, status=status, second=second)
+
+
+def match_pair(imgA, imgB, thetaA, thetaB, n, params: Params, return_surface=False):
+    """Full plain method for one window pair: gather, taper + mean, forward
+    FFTs, whitened cross-power, inverse FFT, peak + SNR + centroid."""
+    a, clA = gather(imgA, thetaA, n)
+    b, clB = gather(imgB, thetaB, n)
+    T = taper_2d(n, params.taper_frac)
+    wA, _ = prepare(a, T)
+    wB, _ = prepare(b, T)
+    c = whitened_surface(wA, wB, params.p, params.eps_rel)
+    rec = peak_stats(c, params.centroid_r)
+    if clA or clB:
+        rec["status"] |= STATUS_CLAMPED
+    if return_surface:
+        rec["surface"] = c
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# Adjoint: gradient of g_peak * c[s*] + g_snr * SNR with respect to the six
+# affine entries of each window (argmax s* held fixed).  Not in the paper; it
+# differentiates the plain definition above by the chain rule (complex
+# gradients G = dJ/dRe + i dJ/dIm over the full N x N spectrum).
+# ---------------------------------------------------------------------------
+def _bilinear_partials(img, x, y):
+    """d(bilinear)/dx and d/dy at (x, y), clamped reads, floor cell."""
+    img = np.asarray(img, dtype=np.float64)
+    h, w = img.shape
+    x0 = np.floor(x)
+    y0 = np.floor(y)
+    fx = x - x0
+    fy = y - y0
+    x0 = x0.astype(np.int64)
+    y0 = y0.astype(np.int64)
+
+    def rd(xx, yy):
+        return img[np.clip(yy, 0, h - 1), np.clip(xx, 0, w - 1)]
+
+    i00, i10 = rd(x0, y0), rd(x0 + 1, y0)
+    i01, i11 = rd(x0, y0 + 1), rd(x0 + 1, y0 + 1)
+    gx = (1 - fy) * (i10 - i00) + fy * (i11 - i01)
+    gy = (1 - fx) * (i01 - i00) + fx * (i11 - i10)
+    return gx, gy
+
+
+def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=1.0):
+    """Returns (record, dJ/dthetaA[6], dJ/dthetaB[6]) with J = g_peak c[s*] +
+    g_snr SNR; the six entries are (a11, a12, tx, a21, a22, ty)."""
+    p, eps_rel = params.p, params.eps_rel
+    a, _ = gather(imgA, thetaA, n)
+    b, _ = gather(imgB, thetaB, n)
+    T = taper_2d(n, params.taper_frac)
+    wA, _ = prepare(a, T)
+    wB, _ = prepare(b, T)
+    M = n * n
+    # forward on the full spectrum
+    FA = np.fft.fft2(wA)
+    FB = np.fft.fft2(wB)
+    X = np.conj(FA) * FB
+    r = (X * np.conj(X)).real
+    SA = float(np.sum(wA * wA))
+    SB = float(np.sum(wB * wB))
+    eps2 = eps_rel ** 2 * SA * SB
+    d = r + eps2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        h = np.where(d > 0, np.power(d, -0.5 * p), 0.0) if p != 0 else np.ones_like(d)
+        hp = np.where(d > 0, -0.5 * p * np.power(d, -0.5 * p - 1.0), 0.0) if p != 0 else np.zeros_like(d)
+    C = X * h
+    C[0, 0] = 0.0
+    c = np.fft.ifft2(C).real
+    rec = peak_stats(c, params.centroid_r)
+    iy, ix = rec["iy"], rec["ix"]
+    mu, sd, snr = rec["mean"], rec["std"], rec["snr"]
+    # cotangent of the surface
+    Gc = np.zeros((n, n))
+    Gc[iy, ix] += g_peak
+    if sd > 0:
+        Gc[iy, ix] += g_snr / sd
+        Gc += g_snr * (-1.0 / (M * sd) - snr * (c - mu) / (M * sd * sd))
+    # c = Re(IDFT2 C): G_C = DFT2(Gc) / M
+    GC = np.fft.fft2(Gc) / M
+    GC[0, 0] = 0.0
+    # C = X h(|X|^2 + eps^2)
+    GX = GC * (h + r * hp) + np.conj(GC) * X * X * hp
+    GX[0, 0] = 0.0
+    dJ_deps2 = float(np.sum((np.conj(GC) * X * hp).real))
+    # X = conj(FA) FB
+    GFA = np.conj(GX) * FB
+    GFB = GX * FA
+    # F = DFT2(w): G_w = Re(M IDFT2 G_F); plus the eps^2 path
+    GwA = (np.fft.ifft2(GFA) * M).real + dJ_deps2 * 2.0 * eps_rel ** 2 * SB * wA
+    GwB = (np.fft.ifft2(GFB) * M).real + dJ_deps2 * 2.0 * eps_rel ** 2 * SA * wB
+    # w = (a - m) T, m = sum(aT)/sum(T)
+    sT = float(np.sum(T))
+    GaA = T * GwA - (T / sT) * float(np.sum(T * GwA))
+    GaB = T * GwB - (T / sT) * float(np.sum(T * GwB))
+
+    def theta_grad(img, theta, Ga):
+        x, y, uu, vv = window_coords(theta, n)
+        gx, gy = _bilinear_partials(img, x, y)
+        return np.array([np.sum(Ga * gx * uu), np.sum(Ga * gx * vv), np.sum(Ga * gx),
+                         np.sum(Ga * gy * uu), np.sum(Ga * gy * vv), np.sum(Ga * gy)])
+
+    return rec, theta_grad(imgA, thetaA, GaA), theta_grad(imgB, thetaB, GaB)
+
+
+# ---------------------------------------------------------------------------
+# Model projection (remod): rounded mean of the z-neighbours, self and
+# damaged sections omitted (Section III, model paragraph)
+# ---------------------------------------------------------------------------
+def project(stack, s, k, exclude=None):
+    """R = round-half-up( sum_{j in J} I_j / |J| ), J = {j : 1 <= |j - s| <= k,
+    0 <= j < S, not excluded}; integer arithmetic (2 S + n) // (2 n)."""
+    S = stack.shape[0]
+    J = [j for j in range(max(0, s - k), min(S, s + k + 1))
+         if j != s and not (exclude is not None and exclude[j])]
+    if not J:
+        raise ValueError("projection has no included neighbour")
+    acc = np.zeros(stack.shape[1:], dtype=np.int64)
+    for j in J:
+        acc += stack[j].astype(np.int64)
+    nn = len(J)
+    return ((2 * acc + nn) // (2 * nn)).astype(np.uint8)
+
+
+def pyramid(img):
+    """One level of the x2 source pyramid (iscale): 2 x 2 box mean rounded half
+    up, (a + b + c + d + 2) >> 2; an odd trailing row/column is dropped."""
+    img = np.asarray(img).astype(np.int64)
+    h, w = img.shape[0] // 2, img.shape[1] // 2
+    a = img[0:2 * h:2, 0:2 * w:2]
+    b = img[0:2 * h:2, 1:2 * w:2]
+    c = img[1:2 * h:2, 0:2 * w:2]
+    d = img[1:2 * h:2, 1:2 * w:2]
+    return ((a + b + c + d + 2) >> 2).astype(np.uint8)
+
+
+# ---------------------------------------------------------------------------
+# Global affine from correspondence points (mir, least squares; Section III)
+# ---------------------------------------------------------------------------
+def fit_affine(src, dst, weights=None):
+    """Weighted linear least squares for dst ~ A [src; 1] (A is 2 x 3).
+    src, dst: [n, 2] points (x, y).  Returns A as a 2 x 3 float64 array."""
+    src = np.asarray(src, dtype=np.float64)
+    dst = np.asarray(dst, dtype=np.float64)
+    wts = np.ones(len(src)) if weights is None else np.asarray(weights, dtype=np.float64)
+    D = np.column_stack([src, np.ones(len(src))])
+    sw = np.sqrt(wts)[:, None]
+    A, *_ = np.linalg.lstsq(D * sw, dst * sw, rcond=None)
+    return A.T

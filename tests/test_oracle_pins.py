@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against things other than itself: brute force on
+tiny inputs, closed forms, library routines, invariants the paper states and
+finite differences.  CPU only."""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.swift_oracle import bilinear_clamped, STATUS_NEAR_TIE, STATUS_DEGENERATE
+from datagen import make_pair64
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+def ident(cx, cy, tx=0.0, ty=0.0):
+    return np.array([cx, cy, 1.0, 0.0, tx, 0.0, 1.0, ty])
+
+
+# ---------------------------------------------------------------- gather
+def test_gather_identity_is_pixel_copy():
+    rng = np.random.default_rng(0)
+    img = rng.integers(0, 256, size=(40, 50)).astype(np.uint8)
+    n = 16
+    a, cl = O.gather(img, ident(20, 17), n)
+    assert not cl
+    # window pixel (i, j) samples (20 + i - 8, 17 + j - 8)
+    np.testing.assert_array_equal(a, img[9:25, 12:28].astype(np.float64))
+
+
+def test_gather_integer_translation_exact():
+    rng = np.random.default_rng(1)
+    img = rng.integers(0, 256, size=(40, 40)).astype(np.uint8)
+    a, _ = O.gather(img, ident(20, 20, tx=3.0, ty=-2.0), 8)
+    np.testing.assert_array_equal(a, img[14:22, 19:27].astype(np.float64))
+
+
+def test_bilinear_reproduces_affine_ramps():
+    # closed form: bilinear interpolation is exact for f = alpha x + beta y + gamma
+    h, w = 30, 37
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    al, be, ga = 0.37, -1.21, 5.5
+    img = al * xx + be * yy + ga
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, w - 1, 500)
+    y = rng.uniform(0, h - 1, 500)
+    v, _ = bilinear_clamped(img, x, y)
+    np.testing.assert_allclose(v, al * x + be * y + ga, rtol=0, atol=1e-12)
+
+
+def test_bilinear_matches_scipy_map_coordinates_nearest():
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(3)
+    img = rng.uniform(0, 255, size=(25, 31))
+    x = rng.uniform(-3, 34, 2000)
+    y = rng.uniform(-3, 28, 2000)
+    v, cl = bilinear_clamped(img, x, y)
+    ref = map_coordinates(img, [y, x], order=1, mode="nearest")
+    assert cl
+    np.testing.assert_allclose(v, ref, rtol=0, atol=1e-10)
+
+
+def test_gather_affine_matches_scipy():
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(4)
+    img = rng.uniform(0, 255, size=(64, 64))
+    th = np.array([31.0, 30.0, 1.01, 0.02, 0.3, -0.015, 0.99, -0.7])
+    n = 32
+    a, _ = O.gather(img, th, n)
+    u = np.arange(n) - n // 2
+    uu, vv = np.meshgrid(u, u)
+    x = th[0] + th[2] * uu + th[3] * vv + th[4]
+    y = th[1] + th[5] * uu + th[6] * vv + th[7]
+    ref = map_coordinates(img, [y, x], order=1, mode="nearest")
+    np.testing.assert_allclose(a, ref, atol=1e-10)
+
+
+# ---------------------------------------------------------------- taper / mean
+@pytest.mark.parametrize("n", [16, 64, 512])
+def test_taper_raised_cosine_properties(n):
+    t = O.taper_1d(n, 0.25)
+    L = n // 8
+    # mirror symmetry, complementarity of the raised cosine, flat middle
+    np.testing.assert_allclose(t, t[::-1], atol=0)
+    for i in range(L):
+        assert abs(t[i] + t[L - 1 - i] - 1.0) < 1e-15
+    assert np.all(t[L:n - L] == 1.0)
+    assert np.all(np.diff(t[:L]) > 0)
+    # half-angle identity: t(0) = sin^2(pi / (4 L))
+    assert abs(t[0] - math.sin(math.pi / (4 * L)) ** 2) < 1e-15
+    assert np.all(O.taper_1d(n, 0.0) == 1.0)
+
+
+def test_mean_removal_zero_sum_and_offset_invariance():
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0, 255, (32, 32))
+    T = O.taper_2d(32, 0.25)
+    w, m = O.prepare(a, T)
+    assert abs(w.sum()) < 1e-9
+    w2, _ = O.prepare(a + 17.25, T)
+    np.testing.assert_allclose(w, w2, atol=1e-9)
+
+
+# ---------------------------------------------------------------- FFT conventions
+def test_rfft2_matches_bruteforce_dft():
+    n = 8
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((n, n))
+    F = np.zeros((n, n), complex)
+    for ky, kx in itertools.product(range(n), range(n)):
+        s = 0
+        for yy, xx in itertools.product(range(n), range(n)):
+            s += x[yy, xx] * np.exp(-2j * np.pi * (ky * yy + kx * xx) / n)
+        F[ky, kx] = s
+    np.testing.assert_allclose(np.fft.rfft2(x), F[:, : n // 2 + 1], atol=1e-11)
+
+
+# ---------------------------------------------------------------- p = 0: plain correlation
+@pytest.mark.parametrize("n", [16, 32])
+def test_p0_equals_bruteforce_circular_correlation(n):
+    rng = np.random.default_rng(7 + n)
+    wA, _ = O.prepare(rng.standard_normal((n, n)), O.taper_2d(n, 0.25))
+    wB, _ = O.prepare(rng.standard_normal((n, n)), O.taper_2d(n, 0.25))
+    c = O.whitened_surface(wA, wB, 0.0, 1e-4)
+    bf = np.zeros((n, n))
+    for sy in range(n):
+        for sx in range(n):
+            bf[sy, sx] = np.sum(wA * np.roll(wB, (-sy, -sx), axis=(0, 1)))
+    np.testing.assert_allclose(c, bf, rtol=0, atol=1e-12 * np.abs(bf).max())
+
+
+# ---------------------------------------------------------------- p = 1: phase-only delta
+def test_p1_delta_closed_form():
+    g = GOLD["poc_delta_n64"]
+    n = g["n"]
+    dx, dy = g["shift_dx_dy"]
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((n, n))
+    b = np.roll(a, (dy, dx), axis=(0, 1))  # b(x) = a(x - d)
+    T = O.taper_2d(n, 0.0)
+    wA, _ = O.prepare(a, T)
+    wB, _ = O.prepare(b, T)
+    c = O.whitened_surface(wA, wB, 1.0, 0.0)
+    iy, ix = dy % n, dx % n
+    assert abs(c[iy, ix] - g["peak_value"]) < 1e-12
+    mask = np.ones_like(c, bool)
+    mask[iy, ix] = False
+    assert np.max(np.abs(c[mask] - g["off_peak_value"])) < 1e-12
+    rec = O.peak_stats(c)
+    assert (rec["iy"], rec["ix"]) == (iy, ix)
+    assert (rec["sx"], rec["sy"]) == (dx, dy)
+    assert abs(rec["snr"] - g["snr"]) < 1e-9
+    assert abs(rec["snr"] - math.sqrt(n * n - 1)) < 1e-9
+
+
+# ---------------------------------------------------------------- integer shift recovery
+@pytest.mark.parametrize("p", GOLD["pair64_integer_peak"]["p_values"])
+def test_pair64_integer_peak(p):
+    g = GOLD["pair64_integer_peak"]
+    a, b = make_pair64()
+    rec = O.match_pair(a, b, ident(32, 32), ident(32, 32), 64, O.Params(p=p))
+    assert [rec["iy"], rec["ix"]] == g["peak_index_iy_ix"]
+    assert abs(rec["dx"] - 7) < 0.5 and abs(rec["dy"] + 3) < 0.5
+
+
+# ---------------------------------------------------------------- whitening before/after the multiply
+@pytest.mark.parametrize("p", [0.3, 0.65, 1.0])
+def test_whitening_before_equals_after_multiply(p):
+    n = 32
+    rng = np.random.default_rng(9)
+    T = O.taper_2d(n, 0.25)
+    wA, _ = O.prepare(rng.standard_normal((n, n)), T)
+    wB, _ = O.prepare(rng.standard_normal((n, n)), T)
+    c = O.whitened_surface(wA, wB, p, 0.0)
+    FA = np.fft.rfft2(wA)
+    FB = np.fft.rfft2(wB)
+    Cb = np.conj(FA / np.abs(FA) ** p) * (FB / np.abs(FB) ** p)
+    Cb[0, 0] = 0
+    cb = np.fft.irfft2(Cb, s=(n, n))
+    np.testing.assert_allclose(c, cb, atol=1e-12 * np.abs(cb).max())
+
+
+def test_whitening_changes_amplitudes_only():
+    # phases of C equal phases of X wherever X != 0
+    n = 16
+    rng = np.random.default_rng(10)
+    T = O.taper_2d(n, 0.25)
+    wA, _ = O.prepare(rng.standard_normal((n, n)), T)
+    wB, _ = O.prepare(rng.standard_normal((n, n)), T)
+    _, parts = O.whitened_surface(wA, wB, 0.7, 1e-4, return_parts=True)
+    X, C = parts["X"], parts["C"]
+    nz = np.abs(X) > 1e-9
+    nz[0, 0] = False
+    np.testing.assert_allclose(np.angle(C[nz]), np.angle(X[nz]), atol=1e-12)
+
+
+# ---------------------------------------------------------------- SNR
+@pytest.mark.parametrize("p", [0.0, 0.65, 1.0])
+def test_snr_invariant_to_intensity_affine(p):
+    a, b = (v.astype(np.float64) for v in make_pair64())
+    par = O.Params(p=p, eps_rel=1e-4)
+    r0 = O.match_pair(a, b, ident(32, 32), ident(32, 32), 64, par)
+    r1 = O.match_pair(3.5 * a + 11.0, 0.25 * b - 40.0, ident(32, 32), ident(32, 32), 64, par)
+    assert abs(r0["snr"] - r1["snr"]) < 1e-9 * r0["snr"]
+    assert (r0["ix"], r0["iy"]) == (r1["ix"], r1["iy"])
+
+
+def test_snr_bound_and_parseval():
+    rng = np.random.default_rng(11)
+    n = 32
+    T = O.taper_2d(n, 0.25)
+    for p in (0.0, 0.5, 1.0):
+        wA, _ = O.prepare(rng.standard_normal((n, n)), T)
+        wB, _ = O.prepare(rng.standard_normal((n, n)), T)
+        c, parts = O.whitened_surface(wA, wB, p, 1e-4, return_parts=True)
+        rec = O.peak_stats(c)
+        assert rec["snr"] <= math.sqrt(n * n - 1) + 1e-9
+        # surface mean is zero (DC bin removed) and its variance follows from
+        # the half spectrum by Parseval (multiplicity 2 off the kx = 0, N/2 columns)
+        C = parts["C"]
+        mult = np.full(C.shape, 2.0)
+        mult[:, 0] = 1.0
+        mult[:, n // 2] = 1.0
+        var = np.sum(mult * np.abs(C) ** 2) / float(n) ** 4
+        assert abs(rec["mean"]) < 1e-14 * np.abs(c).max()
+        assert abs(rec["std"] - math.sqrt(var)) < 1e-12 * rec["std"]
+
+
+def test_degenerate_constant_window():
+    a = np.full((64, 64), 100.0)
+    _, b = make_pair64()
+    rec = O.match_pair(a, b, ident(32, 32), ident(32, 32), 64, O.Params(p=0.65))
+    assert rec["snr"] == 0.0 and rec["status"] & STATUS_DEGENERATE
+
+
+# ---------------------------------------------------------------- peak / centroid
+def test_centroid_closed_forms_and_wrap():
+    n = 16
+    c = np.zeros((n, n))
+    c[3, 5] = 1.0
+    c[3, 6] = 0.5
+    rec = O.peak_stats(c)
+    mu = 1.5 / (n * n)
+    assert (rec["ix"], rec["iy"]) == (5, 3)
+    assert abs(rec["dx"] - (5 + (0.5 - mu) / (1.5 - 2 * mu))) < 1e-14
+    assert rec["dy"] == 3
+    # symmetric neighbourhood -> integer centroid; wrap of indices >= N/2
+    c = np.zeros((n, n))
+    c[8, 15] = 2.0
+    c[8, 14] = c[8, 0] = 0.7
+    c[7, 15] = c[9, 15] = 0.4
+    rec = O.peak_stats(c)
+    assert (rec["sx"], rec["sy"]) == (-1, -8)
+    assert abs(rec["dx"] + 1) < 1e-14 and abs(rec["dy"] + 8) < 1e-14
+
+
+def test_argmax_first_occurrence_and_near_tie():
+    c = np.zeros((8, 8))
+    c[2, 3] = 1.0
+    c[5, 1] = 1.0
+    rec = O.peak_stats(c)
+    assert (rec["iy"], rec["ix"]) == (2, 3)
+    assert rec["status"] & STATUS_NEAR_TIE
+
+
+# ---------------------------------------------------------------- qualitative claim (Fig. 2)
+def test_mid_whitening_beats_extremes_on_distorted_pair():
+    """Section III / Fig. 2: an intermediate exponent gives a higher SNR than
+    both plain correlation and phase-only correlation on distorted content."""
+    import torch
+    from datagen import make_section, warp_affine
+    a = make_section(320, 320, seed=21).float()
+    m = np.array([[math.cos(0.03), -math.sin(0.03)], [math.sin(0.03), math.cos(0.03)]]) * 1.01
+    cen = np.array([159.5, 159.5])
+    b = warp_affine(a, m, cen - m @ cen + np.array([3.3, -2.2]))
+    g = torch.Generator().manual_seed(5)
+    b = (b + 10 * torch.randn(b.shape, generator=g)).clamp(0, 255).numpy()
+    a = a.numpy()
+    th = ident(160, 160)
+    snr = {p: O.match_pair(a, b, th, th, 256, O.Params(p=p))["snr"] for p in (0.0, 0.65, 1.0)}
+    assert snr[0.65] > snr[0.0] and snr[0.65] > snr[1.0], snr
+
+
+# ---------------------------------------------------------------- projection / pyramid
+def _proj_bruteforce(stack, s, k, exclude):
+    S = stack.shape[0]
+    out = np.zeros(stack.shape[1:], np.uint8)
+    for y in range(stack.shape[1]):
+        for x in range(stack.shape[2]):
+            vals = [int(stack[j, y, x]) for j in range(S)
+                    if 1 <= abs(j - s) <= k and not exclude[j]]
+            q = Fraction(sum(vals), len(vals))
+            out[y, x] = math.floor(q + Fraction(1, 2))
+    return out
+
+
+def test_projection_bit_exact_vs_bruteforce():
+    rng = np.random.default_rng(12)
+    st = rng.integers(0, 256, size=(9, 6, 7)).astype(np.uint8)
+    excl = np.zeros(9, bool)
+    excl[5] = True
+    for s in range(9):
+        for k in (1, 3):
+            np.testing.assert_array_equal(O.project(st, s, k, excl), _proj_bruteforce(st, s, k, excl))
+
+
+def test_projection_noise_reduction_inv_sqrt_n():
+    # Section III: averaging n sections reduces independent noise as 1/sqrt(n)
+    rng = np.random.default_rng(13)
+    st = np.clip(rng.normal(128, 20, size=(7, 256, 256)), 0, 255).round().astype(np.uint8)
+    r = O.project(st, 3, 3).astype(np.float64)
+    ratio = r.std() / st[3].astype(np.float64).std()
+    assert abs(ratio - 1 / math.sqrt(6)) < 0.03
+
+
+def test_pyramid_bit_exact_vs_bruteforce():
+    rng = np.random.default_rng(14)
+    img = rng.integers(0, 256, size=(9, 11)).astype(np.uint8)
+    p = O.pyramid(img)
+    assert p.shape == (4, 5)
+    for y in range(4):
+        for x in range(5):
+            s = sum(int(img[2 * y + a, 2 * x + b]) for a in (0, 1) for b in (0, 1))
+            assert p[y, x] == math.floor(Fraction(s, 4) + Fraction(1, 2))
+
+
+# ---------------------------------------------------------------- affine LSQ
+def test_fit_affine_recovers_exact_affine():
+    rng = np.random.default_rng(15)
+    A = np.array([[1.01, 0.02, 3.0], [-0.01, 0.99, -4.0]])
+    src = rng.uniform(0, 1000, (64, 2))
+    dst = src @ A[:, :2].T + A[:, 2]
+    np.testing.assert_allclose(O.fit_affine(src, dst, rng.uniform(1, 5, 64)), A, atol=1e-9)
+
+
+# ---------------------------------------------------------------- adjoint vs finite differences
+def _smooth_img(h, w, seed):
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    return gaussian_filter(rng.uniform(0, 255, (h, w)), 1.5) * 3 - 200
+
+
+@pytest.mark.parametrize("p,eps", [(0.65, 1e-2), (0.0, 1e-4), (1.0, 1e-2), (0.4, 0.0)])
+def test_adjoint_matches_central_fd(p, eps):
+    n = 16
+    img = _smooth_img(48, 48, 16)
+    imgB = np.roll(img, (1, -2), axis=(0, 1)) + _smooth_img(48, 48, 17) * 0.05
+    thA = np.array([24.0, 23.0, 1.0013, 0.0021, 0.3, -0.0017, 0.9988, 0.27])
+    thB = np.array([24.0, 23.0, 0.9991, -0.0012, 0.61, 0.0008, 1.0011, 0.58])
+    par = O.Params(p=p, eps_rel=eps, taper_frac=0.5)
+    for gp, gs in ((0.0, 1.0), (1.0, 0.0), (0.3, -0.7)):
+        rec, gA, gB = O.match_grad(img, imgB, thA, thB, n, par, g_peak=gp, g_snr=gs)
+        idx = [2, 3, 4, 5, 6, 7]
+        h = 1e-6
+        for which, th, g in (("A", thA, gA), ("B", thB, gB)):
+            fd = np.zeros(6)
+            for q in range(6):
+                tp = th.copy()
+                tm = th.copy()
+                tp[idx[q]] += h
+                tm[idx[q]] -= h
+                if which == "A":
+                    rp = O.match_pair(img, imgB, tp, thB, n, par, return_surface=True)
+                    rm = O.match_pair(img, imgB, tm, thB, n, par, return_surface=True)
+                else:
+                    rp = O.match_pair(img, imgB, thA, tp, n, par, return_surface=True)
+                    rm = O.match_pair(img, imgB, thA, tm, n, par, return_surface=True)
+                # hold the argmax fixed: evaluate the objective at rec's s*
+                def J(r):
+                    cc = r["surface"]
+                    pk = cc[rec["iy"], rec["ix"]]
+                    return gp * pk + gs * (pk - cc.mean()) / cc.std()
+                fd[q] = (J(rp) - J(rm)) / (2 * h)
+            err = np.linalg.norm(g - fd) / np.linalg.norm(fd)
+            assert err < 1e-5, (which, p, eps, gp, gs, err, g, fd)
