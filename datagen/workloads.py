@@ -1,0 +1,78 @@
+"""Seeded workload assembly (input shapes of the benchmark configurations).
+
+Only inputs are made here: sections, stacks, per-section ground-truth warps
+and the per-window affine parameters of each pair.  Projections, pyramids and
+matches are computed by the code under test.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from .synth import make_section_pair, make_stack, window_grid
+
+
+def stack_warps(n_sections: int, h: int, w: int, seed: int, drift=2.0, rot_deg=0.2, scale=0.002, shear=1e-3):
+    """Ground-truth per-section affines observed(q) = clean(M_s q + b_s): a
+    random-walk drift D_s = D_{s-1} + U(-drift, drift)^2 composed with a
+    rotation / scale / shear about the centre.  Returns a list of (M, b)."""
+    rng = np.random.default_rng(seed)
+    c = np.array([(w - 1) / 2.0, (h - 1) / 2.0])
+    d = np.zeros(2)
+    out = []
+    for s in range(n_sections):
+        if s > 0:
+            d = d + rng.uniform(-drift, drift, 2)
+        th = math.radians(rng.uniform(-rot_deg, rot_deg))
+        sc = 1.0 + rng.uniform(-scale, scale)
+        sh = rng.uniform(-shear, shear)
+        m = sc * np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]]) @ np.array([[1, sh], [0, 1]])
+        b = c - m @ c + d
+        out.append((m, b))
+    return out
+
+
+def distorted_stack(n_sections=64, size=4096, seed=5, device="cuda"):
+    """The iterative-stack input: S sections of size^2 uint8 with accumulated
+    drift and per-section affine distortion.  Returns (stack, warps)."""
+    warps = stack_warps(n_sections, size, size, seed + 1000)
+    st = make_stack(n_sections, size, size, seed, device=device, warps=warps)
+    return st, warps
+
+
+def section_grid_pairs(n_sections: int, size: int, n: int, grid: int, device="cuda"):
+    """Pairs of every section s (image s) against its reference (image S + s)
+    on a grid x grid tiling of n x n windows at identity affines.
+    Returns (n_list, img_a, img_b, theta_a, theta_b, centres)."""
+    cen = window_grid(size, size, n, grid)
+    P = n_sections * len(cen)
+    th = np.zeros((P, 8), np.float32)
+    ia = np.zeros(P, np.int32)
+    ib = np.zeros(P, np.int32)
+    k = 0
+    for s in range(n_sections):
+        for (cx, cy) in cen:
+            th[k] = [cx, cy, 1, 0, 0, 0, 1, 0]
+            ia[k] = s
+            ib[k] = n_sections + s
+            k += 1
+    t = torch.from_numpy(th).to(device)
+    return [n] * P, torch.from_numpy(ia).to(device), torch.from_numpy(ib).to(device), t, t.clone(), cen
+
+
+def section_pair_1024(size=16384, device="cuda"):
+    """Plain method at real shape: a size^2 section pair (B = warped A plus
+    noise, seeds 2 / 202) and a 16 x 16 grid of 1024^2 windows at identity.
+    Returns (A, B, M, b, n_list, img_a, img_b, theta_a, theta_b)."""
+    a, b, m, bv = make_section_pair(size, size, 2, 202, device=device)
+    grid = size // 1024
+    cen = window_grid(size, size, 1024, grid)
+    th = np.zeros((len(cen), 8), np.float32)
+    for k, (cx, cy) in enumerate(cen):
+        th[k] = [cx, cy, 1, 0, 0, 0, 1, 0]
+    t = torch.from_numpy(th).to(device)
+    P = len(cen)
+    z = torch.zeros(P, dtype=torch.int32, device=device)
+    return a, b, m, bv, [1024] * P, z, z + 1, t, t.clone()

@@ -1,0 +1,192 @@
+/*
+ * swift.h -- C ABI of libswift: signal-whitened FFT window matching on MI355X.
+ *
+ * Method: Wetzel et al., "Registering large volume serial-section electron
+ * microscopy image sets for neural circuit reconstruction using FFT signal
+ * whitening" (arXiv 1612.04787), Section III.  Large sections are matched as
+ * tiled local windows; each window pair is correlated in the frequency domain
+ * with Fourier amplitudes scaled by a power 0..1 (0 = plain correlation, 1 =
+ * phase-only), edges apodized with a cosine taper, and the match is scored as
+ * a Z-score (SNR) against the background of the correlation surface.  The
+ * reference of a section is the rounded mean of its z-neighbours ("model").
+ *
+ * Conventions shared by every entry point
+ *  - All functions return 0 (SWIFT_OK) or a negative SWIFT_E_* code and never
+ *    abort or throw.  swift_last_error() gives a message for the calling thread.
+ *  - Validation of host-side arguments is synchronous.  Device work is queued
+ *    on the caller's stream; faults in device work surface at the caller's next
+ *    synchronisation.  No function synchronises the stream except
+ *    swift_create/swift_destroy/swift_autotune.
+ *  - The caller owns every buffer.  Pointers documented "device" must be
+ *    device memory of the context's GPU; "host" pointers are read during the
+ *    call only.  The library keeps no pointer beyond a call.
+ *  - Images are row-major [y][x] with a pitch in bytes.  Window pixel (i, j)
+ *    (column i, row j) of a window of edge n has window coordinates
+ *    u = i - n/2, v = j - n/2 and samples the image at
+ *        x = cx + a11*u + a12*v + tx,   y = cy + a21*u + a22*v + ty
+ *    with bilinear interpolation and clamp-to-edge reads.
+ *  - Correlation sign: if window B equals window A moved by +d, the peak is
+ *    at +d.  Shifts are wrapped to [-n/2, n/2).
+ */
+#ifndef SWIFT_H
+#define SWIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWIFT_OK             0
+#define SWIFT_E_INVAL       -1 /* bad argument (NULL, size, range, ordering)   */
+#define SWIFT_E_UNSUPPORTED -2 /* valid request this build does not implement  */
+#define SWIFT_E_WORKSPACE   -3 /* workspace or saved buffer too small          */
+#define SWIFT_E_HIP         -4 /* HIP runtime error (message has its string)   */
+#define SWIFT_E_CAPTURE     -5 /* hipGraph capture/instantiate/launch failed    */
+
+#define SWIFT_U8  0 /* uint8 pixels   */
+#define SWIFT_F32 1 /* float32 pixels */
+
+/* match status bits */
+#define SWIFT_ST_NEAR_TIE   1 /* best and second-best surface values within 2e-4 relative */
+#define SWIFT_ST_DEGENERATE 2 /* surface standard deviation 0 (e.g. a constant window)    */
+#define SWIFT_ST_CLAMPED    4 /* a window sample fell outside an image (edge clamped)     */
+
+/* Number of supported window edges and their values: n in {64,128,256,512,1024}. */
+#define SWIFT_NSIZES 5
+
+typedef struct swift_ctx swift_ctx;
+
+/* An image in device memory (32 bytes).  Width, height >= 2. */
+typedef struct {
+  const void* data;    /* device pointer to pixel (0, 0)                 */
+  int32_t width;
+  int32_t height;
+  int64_t pitch;       /* bytes between consecutive rows (>= width*elem) */
+  int32_t dtype;       /* SWIFT_U8 or SWIFT_F32                          */
+  int32_t reserved;    /* must be 0                                      */
+} swift_image;
+
+/* A batch of window pairs, structure of arrays in device memory.  Pairs are
+ * sorted by window edge ascending; size_count (host) gives how many pairs
+ * have each edge 64, 128, 256, 512, 1024, in that order. */
+typedef struct {
+  int32_t n_pairs;                   /* host: total, = sum(size_count)          */
+  int32_t size_count[SWIFT_NSIZES];  /* host                                    */
+  const int32_t* img_a;              /* device [P]: index into the image table  */
+  const int32_t* img_b;              /* device [P]                              */
+  const float* theta_a;              /* device [P][8]: cx,cy,a11,a12,tx,a21,a22,ty */
+  const float* theta_b;              /* device [P][8]                           */
+} swift_pairs;
+
+/* Matching parameters (host).
+ *  p          whitening exponent in [0, 1] (Section III: the 0..1 exponent of
+ *             the amplitude power function; 0 = NCC-like, 1 = phase-only).
+ *  eps_rel    relative floor of the whitening denominator, >= 0: the cross
+ *             power X is scaled by (|X|^2 + eps^2)^(-p/2) with
+ *             eps = eps_rel * ||w_A||_2 * ||w_B||_2 (w = tapered windows).
+ *  taper_frac fraction of the window edge covered by the raised-cosine taper,
+ *             both edges together, in [0, 1] (Section III, apodization).
+ *  centroid_r half-width of the sub-pixel centroid box; only 1 is supported.
+ *  flags      must be 0. */
+typedef struct {
+  float p;
+  float eps_rel;
+  float taper_frac;
+  int32_t centroid_r;
+  int32_t flags;
+  int32_t reserved;
+} swift_params;
+
+/* One match record (48 bytes). */
+typedef struct {
+  float dx, dy;      /* sub-pixel shift: wrapped integer peak + 3x3 centroid   */
+  int32_t ix, iy;    /* integer peak index in the n x n surface (first maximum) */
+  float peak;        /* surface value at the peak                               */
+  float snr;         /* (peak - mean) / std over the whole surface              */
+  double mean, std;  /* surface mean and population std (FP64 reduction)        */
+  int32_t status;    /* SWIFT_ST_* bits                                         */
+  int32_t n;         /* window edge of this pair                                */
+} swift_match;
+
+/* Context: owns the device twiddle table of one GPU.  Allocates (once). */
+int swift_create(int device, swift_ctx** out);
+void swift_destroy(swift_ctx* ctx);
+
+/* Bytes of device workspace swift_match_batch needs for this batch
+ * (*ws_bytes), and of the optional buffer that swift_match_batch fills for
+ * swift_match_backward (*saved_bytes). */
+int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs,
+                         const swift_params* params, size_t* ws_bytes,
+                         size_t* saved_bytes);
+
+/* Whitened FFT matching of a batch of window pairs (Section III).  For each
+ * pair: gather A and B through their affines, subtract the taper-weighted mean
+ * and taper, 2-D FFT both, X = conj(F_A) F_B, C = X (|X|^2+eps^2)^(-p/2) with
+ * the DC bin set to 0, inverse FFT to the n x n surface c (scaled 1/n^2), then
+ * the first maximum, mean/std (FP64), SNR and the 3x3 centroid.
+ *  imgs      device [n_imgs] image table, indexed by pairs->img_a/img_b.
+ *  out       device [P] records.
+ *  surfaces  device float, NULL or room for sum over pairs of n^2 values; pair
+ *            k's surface starts after those of pairs 0..k-1, row-major.
+ *  saved     device, NULL or swift_workspace_size's saved_bytes: the state
+ *            swift_match_backward reads.
+ *  ws        device workspace of ws_bytes >= swift_workspace_size's ws_bytes.
+ * Errors: SWIFT_E_INVAL (NULL pointers, counts, params out of range),
+ * SWIFT_E_UNSUPPORTED (centroid_r != 1, flags), SWIFT_E_WORKSPACE, SWIFT_E_HIP. */
+int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
+                      const swift_pairs* pairs, const swift_params* params,
+                      swift_match* out, float* surfaces, void* saved, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of swift_match_batch (not in the paper): for J = sum_k g_peak[k] *
+ * peak_k + g_snr[k] * snr_k, the gradient with respect to the six affine
+ * entries (a11, a12, tx, a21, a22, ty) of every window, the integer peak held
+ * fixed.  Inputs and params must be those of the forward call that filled
+ * `saved`.  g_peak / g_snr: device [P] or NULL (= 0).  g_theta_a: device [P][6];
+ * g_theta_b: device [P][6] or NULL.  ws as for the forward call. */
+int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
+                         const swift_pairs* pairs, const swift_params* params,
+                         const void* saved, const float* g_peak, const float* g_snr,
+                         float* g_theta_a, float* g_theta_b, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Z-projection "model" of every section of a stack (Section III, model
+ * paragraph; the remod program): out[s] = round-half-up of the mean of the
+ * included sections j with 1 <= |j - s| <= k (self always omitted, sections
+ * with exclude[j] != 0 omitted), computed exactly in integers.  A section with
+ * no included neighbour gets all zeros.
+ *  stack     device uint8, S sections of height x width; pixel (s, y, x) at
+ *            stack[s*section_stride + y*pitch + x].
+ *  exclude   device [S] uint8 or NULL.
+ *  out       device uint8 with the same geometry rules (out_pitch,
+ *            out_section_stride); must not overlap stack.
+ *  k         1..8.
+ * Errors: SWIFT_E_INVAL (NULL, S < 1, sizes, pitches smaller than width,
+ * strides smaller than height*pitch, k out of range), SWIFT_E_HIP. */
+int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width,
+                  int64_t pitch, int64_t section_stride, const uint8_t* exclude, int32_t k,
+                  uint8_t* out, int64_t out_pitch, int64_t out_section_stride, hipStream_t stream);
+
+/* One level of the x2 source pyramid (Section III: iscale): dst(x, y) =
+ * (sum of the 2x2 block at (2x, 2y) + 2) >> 2 for uint8 images; dst must be
+ * (src.width/2) x (src.height/2).  Descriptors are host structs whose data
+ * pointers are device memory. */
+int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst,
+                  hipStream_t stream);
+
+/* Peak, SNR and centroid of given correlation surfaces (the scoring step of
+ * swift_match_batch alone; Section III, Z-score paragraph).
+ *  surfaces  device [batch][n][n] float; out device [batch]. */
+int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch,
+              const swift_params* params, swift_match* out, hipStream_t stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* swift_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWIFT_H */

@@ -1,0 +1,13 @@
+"""MI355X-native signal-whitened FFT window matching (SWiFT-IR hot path).
+
+The compute lives in libswift.so (HIP for gfx950, C ABI in include/swift.h);
+this package is its thin Python binding.
+"""
+from .swift import (  # noqa: F401
+    SIZES,
+    Swift,
+    SwiftError,
+    load_library,
+    make_params,
+    parse_records,
+)

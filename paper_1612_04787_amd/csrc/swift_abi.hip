@@ -1,0 +1,318 @@
+// C ABI of libswift: argument validation, workspace layout and launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "swift_internal.hpp"
+
+using namespace swift;
+
+struct swift_ctx {
+  int device;
+  float2* tw;  // W_1024^m = exp(-2 pi i m / 1024)
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SWIFT_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SWIFT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Workspace layout of one swift_match_batch call.
+struct GroupLayout {
+  int n = 0;
+  int count = 0;
+  int first = 0;  // index of the group's first pair
+  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, end = 0;
+};
+
+struct Layout {
+  size_t taper = 0;  // SWIFT_NSIZES x (tau[1024] + TaperInfo)
+  GroupLayout g[SWIFT_NSIZES];
+  size_t total = 0;
+};
+
+constexpr size_t kTaperSlot = 1024 * sizeof(float2) + 256;
+
+size_t nslice(int n) {
+  switch (n) {
+    case 64: return 64 / RowsCfg<64>::FWD;
+    case 128: return 128 / RowsCfg<128>::FWD;
+    case 256: return 256 / RowsCfg<256>::FWD;
+    case 512: return 512 / RowsCfg<512>::FWD;
+    default: return 1024 / RowsCfg<1024>::FWD;
+  }
+}
+size_t nslice2(int n) {
+  switch (n) {
+    case 64: return 64 / RowsCfg<64>::INV;
+    case 128: return 128 / RowsCfg<128>::INV;
+    case 256: return 256 / RowsCfg<256>::INV;
+    case 512: return 512 / RowsCfg<512>::INV;
+    default: return 1024 / RowsCfg<1024>::INV;
+  }
+}
+
+Layout make_layout(const swift_pairs* pairs) {
+  Layout L;
+  size_t off = 0;
+  L.taper = off;
+  off += align256(SWIFT_NSIZES * kTaperSlot);
+  int first = 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    GroupLayout& g = L.g[i];
+    g.n = kSizes[i];
+    g.count = pairs->size_count[i];
+    g.first = first;
+    first += g.count;
+    if (g.count == 0) continue;
+    const size_t P = (size_t)g.count, n = (size_t)g.n;
+    g.z = off;
+    off += align256(P * n * n * sizeof(float2));
+    g.rowpart = off;
+    off += align256(P * nslice(g.n) * sizeof(RowPart));
+    g.pstat = off;
+    off += align256(P * sizeof(PairStat));
+    g.invpart = off;
+    off += align256(P * nslice2(g.n) * sizeof(InvPart));
+    g.end = off;
+  }
+  L.total = off;
+  return L;
+}
+
+int check_pairs(const swift_pairs* pairs) {
+  if (!pairs) return fail(SWIFT_E_INVAL, "pairs is NULL");
+  long long tot = 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    if (pairs->size_count[i] < 0) return fail(SWIFT_E_INVAL, "size_count[%d] < 0", i);
+    tot += pairs->size_count[i];
+  }
+  if (tot != pairs->n_pairs) return fail(SWIFT_E_INVAL, "n_pairs (%d) != sum(size_count) (%lld)", pairs->n_pairs, tot);
+  if (pairs->n_pairs > 0 && (!pairs->img_a || !pairs->img_b || !pairs->theta_a || !pairs->theta_b))
+    return fail(SWIFT_E_INVAL, "pair arrays must be non-NULL");
+  return SWIFT_OK;
+}
+
+int check_params(const swift_params* pr) {
+  if (!pr) return fail(SWIFT_E_INVAL, "params is NULL");
+  if (!(pr->p >= 0.0f && pr->p <= 1.0f)) return fail(SWIFT_E_INVAL, "p must be in [0, 1] (got %g)", pr->p);
+  if (!(pr->eps_rel >= 0.0f) || !isfinite(pr->eps_rel))
+    return fail(SWIFT_E_INVAL, "eps_rel must be finite and >= 0 (got %g)", pr->eps_rel);
+  if (!(pr->taper_frac >= 0.0f && pr->taper_frac <= 1.0f))
+    return fail(SWIFT_E_INVAL, "taper_frac must be in [0, 1] (got %g)", pr->taper_frac);
+  if (pr->centroid_r != 1) return fail(SWIFT_E_UNSUPPORTED, "centroid_r must be 1 (got %d)", pr->centroid_r);
+  if (pr->flags != 0) return fail(SWIFT_E_UNSUPPORTED, "flags must be 0 (got %d)", pr->flags);
+  return SWIFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* swift_last_error(void) { return g_err.c_str(); }
+
+int swift_create(int device, swift_ctx** out) {
+  if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(SWIFT_E_INVAL, "device %d out of range (%d devices)", device, ndev);
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", device);
+  float2 host[1024];
+  for (int m = 0; m < 1024; ++m) {
+    const double a = -2.0 * M_PI * (double)m / 1024.0;
+    host[m] = make_float2((float)cos(a), (float)sin(a));
+  }
+  float2* tw = nullptr;
+  e = hipMalloc((void**)&tw, sizeof(host));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddles)");
+  e = hipMemcpy(tw, host, sizeof(host), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(tw);
+    return hip_fail(e, "hipMemcpy(twiddles)");
+  }
+  swift_ctx* c = new (std::nothrow) swift_ctx;
+  if (!c) {
+    (void)hipFree(tw);
+    return fail(SWIFT_E_INVAL, "out of host memory");
+  }
+  c->device = device;
+  c->tw = tw;
+  *out = c;
+  return ok();
+}
+
+void swift_destroy(swift_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard dg(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->tw);
+  delete ctx;
+}
+
+int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs, const swift_params* params, size_t* ws_bytes,
+                         size_t* saved_bytes) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!ws_bytes) return fail(SWIFT_E_INVAL, "ws_bytes is NULL");
+  int rc = check_pairs(pairs);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  const Layout L = make_layout(pairs);
+  *ws_bytes = L.total;
+  if (saved_bytes) *saved_bytes = 0;
+  return ok();
+}
+
+int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                      const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  int rc = check_pairs(pairs);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  if (pairs->n_pairs == 0) return ok();
+  if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
+  if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
+  if (saved) return fail(SWIFT_E_UNSUPPORTED, "saved state for the adjoint is not produced by this entry point");
+  const Layout L = make_layout(pairs);
+  if (!ws || ws_bytes < L.total)
+    return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+
+  char* base = (char*)ws;
+  size_t surf_off = 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    const GroupLayout& g = L.g[i];
+    if (g.count == 0) continue;
+    float2* tau = (float2*)(base + L.taper + i * kTaperSlot);
+    TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
+    hipError_t e = launch_taper(g.n, params->taper_frac, tau, tinfo, stream);
+    if (e != hipSuccess) return hip_fail(e, "taper launch");
+    MatchArgs a;
+    a.imgs = imgs;
+    a.n_imgs = n_imgs;
+    a.img_a = pairs->img_a + g.first;
+    a.img_b = pairs->img_b + g.first;
+    a.th_a = pairs->theta_a + 8 * (size_t)g.first;
+    a.th_b = pairs->theta_b + 8 * (size_t)g.first;
+    a.out = out + g.first;
+    a.surfaces = surfaces ? surfaces + surf_off : nullptr;
+    a.Z = (float2*)(base + g.z);
+    a.rowpart = (RowPart*)(base + g.rowpart);
+    a.pstat = (PairStat*)(base + g.pstat);
+    a.invpart = (InvPart*)(base + g.invpart);
+    a.tw = ctx->tw;
+    a.tau = tau;
+    a.tinfo = tinfo;
+    a.p = params->p;
+    a.eps_rel = params->eps_rel;
+    a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
+    a.npairs = g.count;
+    e = launch_match_group(g.n, a, stream);
+    if (e != hipSuccess) return hip_fail(e, "match launch");
+    surf_off += (size_t)g.count * g.n * g.n;
+  }
+  return ok();
+}
+
+int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                         const swift_params* params, const void* saved, const float* g_peak, const float* g_snr,
+                         float* g_theta_a, float* g_theta_b, void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)imgs; (void)n_imgs; (void)pairs; (void)params; (void)saved; (void)g_peak; (void)g_snr;
+  (void)g_theta_a; (void)g_theta_b; (void)ws; (void)ws_bytes; (void)stream;
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  return fail(SWIFT_E_UNSUPPORTED, "swift_match_backward is not available in this build");
+}
+
+int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width, int64_t pitch,
+                  int64_t section_stride, const uint8_t* exclude, int32_t k, uint8_t* out, int64_t out_pitch,
+                  int64_t out_section_stride, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!stack || !out) return fail(SWIFT_E_INVAL, "stack/out is NULL");
+  if (S < 1 || height < 1 || width < 1) return fail(SWIFT_E_INVAL, "bad stack shape %d x %d x %d", S, height, width);
+  if (k < 1 || k > 8) return fail(SWIFT_E_INVAL, "k must be in [1, 8] (got %d)", k);
+  if (pitch < width || out_pitch < width) return fail(SWIFT_E_INVAL, "pitch smaller than width");
+  if (section_stride < pitch * height || out_section_stride < out_pitch * height)
+    return fail(SWIFT_E_INVAL, "section stride smaller than height * pitch");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_project(stack, pitch, section_stride, S, height, width, exclude, k, out, out_pitch,
+                                out_section_stride, stream);
+  if (e != hipSuccess) return hip_fail(e, "project launch");
+  return ok();
+}
+
+int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!src || !dst || !src->data || !dst->data) return fail(SWIFT_E_INVAL, "src/dst is NULL");
+  if (src->dtype != SWIFT_U8 || dst->dtype != SWIFT_U8) return fail(SWIFT_E_UNSUPPORTED, "pyramid needs uint8 images");
+  if (src->width < 2 || src->height < 2) return fail(SWIFT_E_INVAL, "source smaller than 2 x 2");
+  if (dst->width != src->width / 2 || dst->height != src->height / 2)
+    return fail(SWIFT_E_INVAL, "destination must be %d x %d", src->width / 2, src->height / 2);
+  if (src->pitch < src->width || dst->pitch < dst->width) return fail(SWIFT_E_INVAL, "pitch smaller than width");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_pyramid((const uint8_t*)src->data, src->pitch, src->width, src->height, (uint8_t*)dst->data,
+                                dst->pitch, dst->width, dst->height, stream);
+  if (e != hipSuccess) return hip_fail(e, "pyramid launch");
+  return ok();
+}
+
+int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch, const swift_params* params,
+              swift_match* out, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (n < 4 || n > 4096) return fail(SWIFT_E_INVAL, "n must be in [4, 4096] (got %d)", n);
+  if (batch < 0) return fail(SWIFT_E_INVAL, "batch < 0");
+  if (batch == 0) return ok();
+  if (!surfaces || !out) return fail(SWIFT_E_INVAL, "surfaces/out is NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_snr(surfaces, n, batch, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "snr launch");
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Device helpers shared by the matching and scoring kernels.
+#pragma once
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+#include "swift_fft.hpp"
+#include "swift_internal.hpp"
+
+namespace swift {
+
+__device__ __forceinline__ float taper_at(int i, int n, int L) {
+  if (L <= 0) return 1.0f;
+  const int m = i < n - 1 - i ? i : n - 1 - i;
+  if (m >= L) return 1.0f;
+  return 0.5f * (1.0f - cospif(((float)m + 0.5f) / (float)L));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+struct Top2 {
+  float m1;
+  int i1;
+  float m2;
+};
+
+__device__ __forceinline__ void top2_push(Top2& a, float v, int i) {
+  if (v > a.m1 || (v == a.m1 && i < a.i1)) {
+    a.m2 = a.m1;
+    a.m1 = v;
+    a.i1 = i;
+  } else if (v > a.m2) {
+    a.m2 = v;
+  }
+}
+
+__device__ __forceinline__ Top2 top2_merge(Top2 a, Top2 b) {
+  const bool bw = (b.m1 > a.m1) || (b.m1 == a.m1 && b.i1 < a.i1);
+  Top2 w = bw ? b : a, l = bw ? a : b;
+  Top2 r;
+  r.m1 = w.m1;
+  r.i1 = w.i1;
+  r.m2 = fmaxf(l.m1, fmaxf(a.m2, b.m2));
+  return r;
+}
+
+__device__ __forceinline__ Top2 wave_top2(Top2 a) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Top2 o;
+    o.m1 = __shfl_xor(a.m1, off);
+    o.i1 = __shfl_xor(a.i1, off);
+    o.m2 = __shfl_xor(a.m2, off);
+    a = top2_merge(a, o);
+  }
+  return a;
+}
+
+// Bilinear, clamp-to-edge sample at (x, y); coordinates in FP64 so that the
+// sub-pixel fraction keeps full precision on large sections.
+template <typename Pix>
+__device__ __forceinline__ float bilinear(const unsigned char* __restrict__ base, int64_t pitch, int w, int h,
+                                          double x, double y, bool& clamped) {
+  double xf = floor(x), yf = floor(y);
+  const float fx = (float)(x - xf), fy = (float)(y - yf);
+  xf = fmin(fmax(xf, -2.0), (double)w);
+  yf = fmin(fmax(yf, -2.0), (double)h);
+  const int x0 = (int)xf, y0 = (int)yf;
+  const int x1 = x0 + 1, y1 = y0 + 1;
+  clamped |= (x0 < 0) | (y0 < 0) | (x1 > w - 1) | (y1 > h - 1);
+  const int cx0 = min(max(x0, 0), w - 1), cx1 = min(max(x1, 0), w - 1);
+  const int cy0 = min(max(y0, 0), h - 1), cy1 = min(max(y1, 0), h - 1);
+  const Pix* r0 = (const Pix*)(base + (int64_t)cy0 * pitch);
+  const Pix* r1 = (const Pix*)(base + (int64_t)cy1 * pitch);
+  const float i00 = (float)r0[cx0], i10 = (float)r0[cx1];
+  const float i01 = (float)r1[cx0], i11 = (float)r1[cx1];
+  return (1.0f - fy) * ((1.0f - fx) * i00 + fx * i10) + fy * ((1.0f - fx) * i01 + fx * i11);
+}
+
+
+// Match record from the reduced surface statistics and the 3x3 neighbourhood
+// nb[dy+1][dx+1] of the peak (nb[1][1] is replaced by the peak value).
+// Z-score over the whole surface (population std, FP64); centroid weights
+// max(c - mean, 0); integer shifts wrapped to [-n/2, n/2).
+__device__ inline swift_match make_record(int n, Top2 tp, double sum, double sq, float (*nb)[3], int flags) {
+  const int flat = (tp.i1 >= 0 && tp.i1 < n * n) ? tp.i1 : 0;
+  const int iy = flat / n, ix = flat % n;
+  const double M = (double)n * (double)n;
+  const double mu = sum / M;
+  const double var = fmax(sq / M - mu * mu, 0.0);
+  const double sd = sqrt(var);
+  swift_match rec;
+  rec.ix = ix;
+  rec.iy = iy;
+  rec.n = n;
+  rec.peak = tp.m1;
+  rec.mean = mu;
+  rec.std = sd;
+  int st = flags;
+  if (tp.m1 - tp.m2 <= kNearTieRel * fabsf(tp.m1)) st |= SWIFT_ST_NEAR_TIE;
+  if (sd > 0.0) {
+    rec.snr = (float)(((double)tp.m1 - mu) / sd);
+  } else {
+    rec.snr = 0.0f;
+    st |= SWIFT_ST_DEGENERATE;
+  }
+  nb[1][1] = tp.m1;
+  double sw = 0.0, swx = 0.0, swy = 0.0;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const double wv = fmax((double)nb[dy + 1][dx + 1] - mu, 0.0);
+      sw += wv;
+      swx += wv * dx;
+      swy += wv * dy;
+    }
+  const int sx = ix >= n / 2 ? ix - n : ix;
+  const int sy = iy >= n / 2 ? iy - n : iy;
+  rec.dx = (float)(sx + (sw > 0.0 ? swx / sw : 0.0));
+  rec.dy = (float)(sy + (sw > 0.0 ? swy / sw : 0.0));
+  rec.status = st;
+  return rec;
+}
+
+}  // namespace swift

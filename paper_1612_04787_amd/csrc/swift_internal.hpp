@@ -1,0 +1,92 @@
+// Internal declarations shared by the kernel sources and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/swift.h"
+
+namespace swift {
+
+// Offset subtracted from every sample before the forward transform.  The
+// weighted mean is removed exactly in the frequency domain afterwards, so the
+// offset changes nothing mathematically; it only keeps the DC terms small.
+constexpr float kSampleOffset = 128.0f;
+constexpr float kNearTieRel = 2e-4f;
+
+// Per row-slice partial sums of the forward row pass (A then B):
+// s[0] = sum a'T, s[1] = sum (a'T)^2, s[2] = sum a'T^2   (a' = sample - offset)
+struct RowPart {
+  double s[6];
+  int32_t clamped;
+  int32_t pad[3];
+};
+
+// Per pair, after reducing the row partials.
+struct PairStat {
+  float mA, mB;   // taper-weighted means of the offset samples
+  float eps2;     // eps_rel^2 * ||w_A||^2 * ||w_B||^2
+  int32_t flags;  // bit 0: degenerate (a window is constant); bit 2: clamped
+};
+
+// Per row-slice partials of the inverse row pass.
+struct InvPart {
+  float m1;       // largest value
+  int32_t i1;     // its flat index (smallest on ties)
+  float m2;       // largest value elsewhere
+  int32_t pad;
+  double sum, sumsq;
+};
+
+// Taper spectrum of one window size: tau[k] = sum_i t(i) exp(-2 pi i k i / N)
+struct TaperInfo {
+  double sum_t, sum_t2;
+  int32_t L;
+  int32_t pad;
+};
+
+struct MatchArgs {
+  const swift_image* imgs;
+  const int32_t* img_a;
+  const int32_t* img_b;
+  const float* th_a;
+  const float* th_b;
+  swift_match* out;
+  float* surfaces;      // NULL or this group's first surface
+  float2* Z;            // [P][N][N] exchange buffer
+  RowPart* rowpart;     // [P][NSLICE]
+  PairStat* pstat;      // [P]
+  InvPart* invpart;     // [P][NSL2]
+  const float2* tw;     // W_1024 table
+  const float2* tau;    // [N]
+  const TaperInfo* tinfo;
+  float p, eps_rel;
+  int32_t L;            // taper samples per edge
+  int32_t npairs;
+  int32_t n_imgs;
+};
+
+// Rows per workgroup of the forward and inverse row passes.
+template <int N> struct RowsCfg;
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64; };
+template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16; };
+template <> struct RowsCfg<512>  { static constexpr int FWD = 16, INV = 16; };
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16; };
+
+constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
+
+size_t pair_ws_bytes(int n);   // exchange + partial buffers for one pair
+size_t align256(size_t x);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, hipStream_t s);
+hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s);
+hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
+hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
+                          const uint8_t* exclude, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
+                          hipStream_t s);
+hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, uint8_t* dst, int64_t dpitch,
+                          int dw, int dh, hipStream_t s);
+
+}  // namespace swift

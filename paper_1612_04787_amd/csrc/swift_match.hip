@@ -1,0 +1,513 @@
+// Whitened FFT window matching: the batched forward path.
+//
+// Method (Wetzel et al., arXiv 1612.04787, Section III): each window pair is
+// apodized with a cosine taper, correlated in the frequency domain with the
+// Fourier amplitudes scaled by a power p in [0, 1] (0 = plain correlation,
+// 1 = phase-only), transformed back, and scored by the Z-score of its peak.
+//
+// Per pair the two real windows a, b travel together as one complex field
+// z = a'T + i b'T (a' = a - offset, T the separable taper), so the forward 2-D
+// transform is a single complex FFT.  Five kernels per window size N:
+//   k_row_fwd   gather (bilinear affine, uint8/fp32 -> fp32), taper, row FFTs,
+//               per-slice sums; writes the row spectra transposed ([kx][y]).
+//   k_pair_stats  reduces the sums to the weighted means and eps^2.
+//   k_col       column FFTs of kx and N-kx, split into F_A and F_B, removes the
+//               weighted mean in the spectrum (F -= m * tau(ky) tau(kx)),
+//               whitens the cross power, inverse column FFT; writes in place.
+//   k_row_inv   inverse row FFTs (two real rows per complex FFT), per-slice
+//               top-2 / argmax and FP64 sum, sum of squares; optional surface.
+//   k_finalize  reduces the slices, recomputes the three rows around the peak
+//               for the 3x3 centroid and writes the match record.
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+#include "swift_dev.hpp"
+
+namespace swift {
+
+// ---------------------------------------------------------------- taper spectrum
+// tau[k] = sum_i t(i) exp(-2 pi i k i / N) in FP64 from the same FP32 taper
+// values the gather uses.  Since t = 1 outside the 2L edge samples,
+// tau[k] = N [k == 0] - sum_{edge i} (1 - t(i)) exp(-2 pi i k i / N).
+// Block 0 also writes sum t and sum t^2.
+__global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict__ tau, TaperInfo* info) {
+  __shared__ double red[2][4];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    double re = (k == 0) ? (double)n : 0.0, im = 0.0;
+    const int Le = min(L, n / 2);
+    for (int q = 0; q < 2 * Le; ++q) {
+      const int i = q < Le ? q : n - 2 * Le + q;
+      const double om = 1.0 - (double)taper_at(i, n, L);
+      const int m = (int)(((long long)k * i) % n);
+      double sn, cs;
+      sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+      re -= om * cs;
+      im += om * sn;
+    }
+    tau[k] = make_float2((float)re, (float)im);
+  }
+  if (blockIdx.x != 0) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double t = (double)taper_at(i, n, L);
+    s1 += t;
+    s2 += t * t;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  if (ln == 0) {
+    red[0][wv] = s1;
+    red[1][wv] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TaperInfo ti;
+    ti.sum_t = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    ti.sum_t2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    ti.L = L;
+    ti.pad = 0;
+    *info = ti;
+  }
+}
+
+// ---------------------------------------------------------------- row pass (forward)
+template <int N>
+__global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
+  constexpr int RS = lidx(N) + 1;
+  static_assert(R % G == 0, "rows per workgroup must be a multiple of transforms per workgroup");
+  __shared__ float2 stage[R * RS];
+  __shared__ double red[4][6];
+  __shared__ int redc[4];
+
+  const int pair = blockIdx.x / NSLICE, slice = blockIdx.x % NSLICE, y0 = slice * R;
+  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+
+  // image indices are clamped into the table so a bad index cannot read past it
+  const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
+  const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
+  swift_image ia = a.imgs[ka];
+  swift_image ib = a.imgs[kb];
+  ia.width = max(ia.width, 1);
+  ia.height = max(ia.height, 1);
+  ib.width = max(ib.width, 1);
+  ib.height = max(ib.height, 1);
+  const float* ta = a.th_a + 8 * (size_t)pair;
+  const float* tb = a.th_b + 8 * (size_t)pair;
+  const double acx = ta[0], acy = ta[1], a11 = ta[2], a12 = ta[3], atx = ta[4], a21 = ta[5], a22 = ta[6], aty = ta[7];
+  const double bcx = tb[0], bcy = tb[1], b11 = tb[2], b12 = tb[3], btx = tb[4], b21 = tb[5], b22 = tb[6], bty = tb[7];
+  const unsigned char* pa = (const unsigned char*)ia.data;
+  const unsigned char* pb = (const unsigned char*)ib.data;
+
+  float tx[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) tx[e] = taper_at(t + e * T, N, a.L);
+
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  bool clamped = false;
+
+#pragma unroll 1
+  for (int it = 0; it < R / G; ++it) {
+    const int r = g + it * G;
+    const int y = y0 + r;
+    const float ty = taper_at(y, N, a.L);
+    const double v = (double)(y - N / 2);
+    const double axr = acx + atx + a12 * v, ayr = acy + aty + a22 * v;
+    const double bxr = bcx + btx + b12 * v, byr = bcy + bty + b22 * v;
+    float2 d[E];
+    float s[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double u = (double)(t + e * T - N / 2);
+      float av, bv;
+      if (ia.dtype == SWIFT_U8)
+        av = bilinear<unsigned char>(pa, ia.pitch, ia.width, ia.height, axr + a11 * u, ayr + a21 * u, clamped);
+      else
+        av = bilinear<float>(pa, ia.pitch, ia.width, ia.height, axr + a11 * u, ayr + a21 * u, clamped);
+      if (ib.dtype == SWIFT_U8)
+        bv = bilinear<unsigned char>(pb, ib.pitch, ib.width, ib.height, bxr + b11 * u, byr + b21 * u, clamped);
+      else
+        bv = bilinear<float>(pb, ib.pitch, ib.width, ib.height, bxr + b11 * u, byr + b21 * u, clamped);
+      const float tap = tx[e] * ty;
+      const float at = (av - kSampleOffset) * tap, bt = (bv - kSampleOffset) * tap;
+      s[0] += at;
+      s[1] += at * at;
+      s[2] += at * tap;
+      s[3] += bt;
+      s[4] += bt * bt;
+      s[5] += bt * tap;
+      d[e] = make_float2(at, bt);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] += (double)s[i];
+    float2* row = stage + r * RS;
+    fft_wave<N, false>(d, row, t, a.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = d[e];
+  }
+
+  // slice sums
+  const int wv = tid >> 6, ln = tid & 63;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[i] = wave_sum(acc[i]);
+  const int anyc = __any(clamped) ? 1 : 0;
+  if (ln == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) red[wv][i] = acc[i];
+    redc[wv] = anyc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    RowPart rp;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) rp.s[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    rp.clamped = redc[0] | redc[1] | redc[2] | redc[3];
+    rp.pad[0] = rp.pad[1] = rp.pad[2] = 0;
+    a.rowpart[(size_t)pair * NSLICE + slice] = rp;
+  }
+
+  // transposed store: Z[pair][kx][y0 + r]
+  float2* Zp = a.Z + (size_t)pair * N * N;
+#pragma unroll 4
+  for (int idx = tid; idx < R * N; idx += 256) {
+    const int r = idx % R, kx = idx / R;
+    Zp[(size_t)kx * N + y0 + r] = stage[r * RS + lidx(kx)];
+  }
+}
+
+// ---------------------------------------------------------------- pair statistics
+template <int N>
+__global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
+  constexpr int NSLICE = N / RowsCfg<N>::FWD;
+  const int pair = blockIdx.x, ln = threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  int cl = 0;
+  for (int i = ln; i < NSLICE; i += 64) {
+    const RowPart rp = a.rowpart[(size_t)pair * NSLICE + i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] += rp.s[q];
+    cl |= rp.clamped;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s[q] = wave_sum(s[q]);
+  cl = __any(cl) ? 1 : 0;
+  if (ln == 0) {
+    const TaperInfo ti = *a.tinfo;
+    const double sT = ti.sum_t * ti.sum_t, sT2 = ti.sum_t2 * ti.sum_t2;
+    const double mA = s[0] / sT, mB = s[3] / sT;
+    const double wA = s[1] - 2.0 * mA * s[2] + mA * mA * sT2;
+    const double wB = s[4] - 2.0 * mB * s[5] + mB * mB * sT2;
+    PairStat ps;
+    ps.mA = (float)mA;
+    ps.mB = (float)mB;
+    ps.flags = (cl ? 4 : 0);
+    // a window whose weighted variance vanishes to rounding is constant
+    if (!(wA > 1e-6 * s[1]) || !(wB > 1e-6 * s[4])) ps.flags |= 1;
+    const double e2 = (double)a.eps_rel * (double)a.eps_rel * fmax(wA, 0.0) * fmax(wB, 0.0);
+    ps.eps2 = (float)e2;
+    a.pstat[pair] = ps;
+  }
+}
+
+// ---------------------------------------------------------------- column pass + whitening
+template <int N>
+__global__ void __launch_bounds__(256) k_col(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
+  constexpr int NI = N / 2 + 1, NW = (NI + IPW - 1) / IPW;
+  constexpr int SL = lidx(N);
+  __shared__ float2 lds[G * SL];
+
+  const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
+  const int tid = threadIdx.x, c = tid / T, t = tid % T;
+  const int which = c / IPW, item = c % IPW, w = wg * IPW + item;
+  const bool valid = w < NI;
+  const int col = which == 0 ? w : ((N - w) & (N - 1));
+  float2* Zp = a.Z + (size_t)pair * N * N;
+  float2* slot = lds + c * SL;
+  float2 v[E];
+
+  if (valid) {
+    const float2* src = Zp + (size_t)col * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
+    fft_wave<N, false>(v, slot, t, a.tw);
+    if (which == 1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) slot[lidx(t + e * T)] = v[e];
+    }
+  }
+  __syncthreads();
+  if (valid && which == 0) {
+    const PairStat ps = a.pstat[pair];
+    const float2* part = lds + (c + IPW) * SL;
+    const float2 tauw = a.tau[w];
+    const float p = a.p;
+    const float hp = -0.5f * p;
+    const float inv_m = 1.0f / (float)(N * N);
+    const bool zero_all = (ps.flags & 1) != 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int ky = t + e * T;
+      const float2 zp = v[e];
+      const float2 zm = cconj(part[lidx((N - ky) & (N - 1))]);
+      // F_A = (Z(k) + conj Z(-k)) / 2,  F_B = (Z(k) - conj Z(-k)) / (2i)
+      float2 fa = cscale(cadd(zp, zm), 0.5f);
+      const float2 dd = csub(zp, zm);
+      float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
+      const float2 tk = cmul(a.tau[ky], tauw);
+      fa = csub(fa, cscale(tk, ps.mA));
+      fb = csub(fb, cscale(tk, ps.mB));
+      // X = conj(F_A) F_B, C = X (|X|^2 + eps^2)^(-p/2) / N^2
+      const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
+      const float d = X.x * X.x + X.y * X.y + ps.eps2;
+      float gs;
+      if (p == 0.0f) gs = 1.0f;
+      else if (!(d > 0.0f)) gs = 0.0f;
+      else if (p == 1.0f) gs = rsqrtf(d);
+      else gs = exp2f(hp * log2f(d));
+      gs *= inv_m;
+      if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
+      v[e] = cscale(X, gs);
+    }
+    fft_wave<N, true>(v, slot, t, a.tw);
+    float2* dst = Zp + (size_t)w * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------- row pass (inverse) + statistics
+template <int N>
+__global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, E = C::E, G = 256 / T, R2 = RowsCfg<N>::INV, NT = R2 / 2, NSL2 = N / R2;
+  constexpr int NH = N / 2 + 1, RS2 = N / 2 + N / 32 + 1;
+  static_assert(2 * RS2 >= lidx(N - 1) + 1, "row pair must hold the FFT scratch");
+  __shared__ float2 stage[R2 * RS2];
+  __shared__ float rm1[4], rm2[4];
+  __shared__ int ri1[4];
+  __shared__ double rs[4], rq[4];
+
+  const int pair = blockIdx.x / NSL2, slice = blockIdx.x % NSL2, y0 = slice * R2;
+  const int tid = threadIdx.x, g = tid / T, t = tid % T;
+  const float2* Zp = a.Z + (size_t)pair * N * N;
+
+  for (int idx = tid; idx < NH * R2; idx += 256) {
+    const int r = idx % R2, kx = idx / R2;
+    stage[r * RS2 + kx] = Zp[(size_t)kx * N + y0 + r];
+  }
+  __syncthreads();
+
+  Top2 tp;
+  tp.m1 = -FLT_MAX;
+  tp.i1 = INT_MAX;
+  tp.m2 = -FLT_MAX;
+  double sum = 0.0, sq = 0.0;
+  float* surf = a.surfaces ? a.surfaces + (size_t)pair * N * N : nullptr;
+
+#pragma unroll 1
+  for (int it = 0; it < (NT + G - 1) / G; ++it) {
+    const int c = g + it * G;
+    if (c < NT) {
+      float2* r1 = stage + (2 * c) * RS2;
+      float2* r2 = r1 + RS2;
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = t + e * T;
+        float2 g1, g2;
+        if (k <= N / 2) {
+          g1 = r1[k];
+          g2 = r2[k];
+        } else {
+          g1 = cconj(r1[N - k]);
+          g2 = cconj(r2[N - k]);
+        }
+        v[e] = make_float2(g1.x - g2.y, g1.y + g2.x);
+      }
+      wave_lds_sync();
+      fft_wave<N, true>(v, r1, t, a.tw);
+      const int ya = y0 + 2 * c, yb = ya + 1;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int x = t + e * T;
+        const float ca = v[e].x, cb = v[e].y;
+        top2_push(tp, ca, ya * N + x);
+        top2_push(tp, cb, yb * N + x);
+        sum += (double)ca + (double)cb;
+        sq += (double)ca * (double)ca + (double)cb * (double)cb;
+        if (surf) {
+          surf[(size_t)ya * N + x] = ca;
+          surf[(size_t)yb * N + x] = cb;
+        }
+      }
+    }
+  }
+  tp = wave_top2(tp);
+  sum = wave_sum(sum);
+  sq = wave_sum(sq);
+  const int wv = tid >> 6, ln = tid & 63;
+  if (ln == 0) {
+    rm1[wv] = tp.m1;
+    ri1[wv] = tp.i1;
+    rm2[wv] = tp.m2;
+    rs[wv] = sum;
+    rq[wv] = sq;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Top2 b;
+    b.m1 = rm1[0];
+    b.i1 = ri1[0];
+    b.m2 = rm2[0];
+    for (int i = 1; i < 4; ++i) {
+      Top2 o;
+      o.m1 = rm1[i];
+      o.i1 = ri1[i];
+      o.m2 = rm2[i];
+      b = top2_merge(b, o);
+    }
+    InvPart ip;
+    ip.m1 = b.m1;
+    ip.i1 = b.i1;
+    ip.m2 = b.m2;
+    ip.pad = 0;
+    ip.sum = rs[0] + rs[1] + rs[2] + rs[3];
+    ip.sumsq = rq[0] + rq[1] + rq[2] + rq[3];
+    a.invpart[(size_t)pair * NSL2 + slice] = ip;
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+template <int N>
+__global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, E = C::E, NSL2 = N / RowsCfg<N>::INV;
+  constexpr int SL = lidx(N);
+  __shared__ float2 lds[SL];
+  __shared__ float nb[3][3];
+  const int pair = blockIdx.x, ln = threadIdx.x;
+
+  Top2 tp;
+  tp.m1 = -FLT_MAX;
+  tp.i1 = INT_MAX;
+  tp.m2 = -FLT_MAX;
+  double sum = 0.0, sq = 0.0;
+  for (int i = ln; i < NSL2; i += 64) {
+    const InvPart ip = a.invpart[(size_t)pair * NSL2 + i];
+    Top2 o;
+    o.m1 = ip.m1;
+    o.i1 = ip.i1;
+    o.m2 = ip.m2;
+    tp = top2_merge(tp, o);
+    sum += ip.sum;
+    sq += ip.sumsq;
+  }
+  tp = wave_top2(tp);
+  sum = wave_sum(sum);
+  sq = wave_sum(sq);
+  const int flat = (tp.i1 >= 0 && tp.i1 < N * N) ? tp.i1 : 0;
+  const int iy = flat / N, ix = flat % N;
+  const float2* Zp = a.Z + (size_t)pair * N * N;
+
+  // recompute rows iy-1, iy+1 (one complex FFT) and iy (second FFT)
+  for (int pass = 0; pass < 2; ++pass) {
+    const int ra = pass == 0 ? ((iy - 1) & (N - 1)) : iy;
+    const int rb = pass == 0 ? ((iy + 1) & (N - 1)) : -1;
+    if (ln < T) {
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = ln + e * T;
+        const int kk = k <= N / 2 ? k : N - k;
+        float2 g1 = Zp[(size_t)kk * N + ra];
+        float2 g2 = rb >= 0 ? Zp[(size_t)kk * N + rb] : make_float2(0.f, 0.f);
+        if (k > N / 2) {
+          g1 = cconj(g1);
+          g2 = cconj(g2);
+        }
+        v[e] = make_float2(g1.x - g2.y, g1.y + g2.x);
+      }
+      fft_wave<N, true>(v, lds, ln, a.tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int x = ln + e * T;
+        int dxi = x - ix;
+        if (dxi > N / 2) dxi -= N;
+        if (dxi < -N / 2) dxi += N;
+        if (dxi >= -1 && dxi <= 1) {
+          if (pass == 0) {
+            nb[0][dxi + 1] = v[e].x;
+            nb[2][dxi + 1] = v[e].y;
+          } else {
+            nb[1][dxi + 1] = v[e].x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (ln == 0) {
+    const PairStat ps = a.pstat[pair];
+    a.out[pair] = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <int N>
+static size_t pair_bytes_t() {
+  const size_t nsl = N / RowsCfg<N>::FWD, nsl2 = N / RowsCfg<N>::INV;
+  return (size_t)N * N * sizeof(float2) + nsl * sizeof(RowPart) + sizeof(PairStat) + nsl2 * sizeof(InvPart);
+}
+
+size_t pair_ws_bytes(int n) {
+  switch (n) {
+    case 64: return pair_bytes_t<64>();
+    case 128: return pair_bytes_t<128>();
+    case 256: return pair_bytes_t<256>();
+    case 512: return pair_bytes_t<512>();
+    case 1024: return pair_bytes_t<1024>();
+  }
+  return 0;
+}
+
+hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, hipStream_t s) {
+  const int L = (int)floor((double)taper_frac * n / 2.0 + 0.5);
+  k_taper<<<(n + 255) / 256, 256, 0, s>>>(n, L, tau, info);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s) {
+  using C = FftCfg<N>;
+  constexpr int NSLICE = N / RowsCfg<N>::FWD, NSL2 = N / RowsCfg<N>::INV;
+  constexpr int G = 256 / C::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
+  const unsigned P = (unsigned)a.npairs;
+  k_row_fwd<N><<<P * NSLICE, 256, 0, s>>>(a);
+  k_pair_stats<N><<<P, 64, 0, s>>>(a);
+  k_col<N><<<P * NW, 256, 0, s>>>(a);
+  k_row_inv<N><<<P * NSL2, 256, 0, s>>>(a);
+  k_finalize<N><<<P, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s) {
+  switch (n) {
+    case 64: return launch_group_t<64>(a, s);
+    case 128: return launch_group_t<128>(a, s);
+    case 256: return launch_group_t<256>(a, s);
+    case 512: return launch_group_t<512>(a, s);
+    case 1024: return launch_group_t<1024>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace swift

@@ -1,0 +1,210 @@
+// Scoring of given surfaces, z-projection models and the x2 pyramid.
+#include "swift_dev.hpp"
+
+namespace swift {
+
+// ---------------------------------------------------------------- scoring (Z-score of the peak)
+// One workgroup per surface: first maximum, top-2 margin, FP64 sum and sum of
+// squares, then the record with the 3x3 centroid read from the surface.
+__global__ void __launch_bounds__(256) k_snr(const float* __restrict__ surf, int n, swift_match* out) {
+  __shared__ float rm1[4], rm2[4];
+  __shared__ int ri1[4];
+  __shared__ double rs[4], rq[4];
+  __shared__ float nb[3][3];
+  const float* s = surf + (size_t)blockIdx.x * n * n;
+  const int tid = threadIdx.x;
+  Top2 tp;
+  tp.m1 = -FLT_MAX;
+  tp.i1 = INT_MAX;
+  tp.m2 = -FLT_MAX;
+  double sum = 0.0, sq = 0.0;
+  for (int i = tid; i < n * n; i += 256) {
+    const float v = s[i];
+    top2_push(tp, v, i);
+    sum += (double)v;
+    sq += (double)v * (double)v;
+  }
+  tp = wave_top2(tp);
+  sum = wave_sum(sum);
+  sq = wave_sum(sq);
+  const int wv = tid >> 6, ln = tid & 63;
+  if (ln == 0) {
+    rm1[wv] = tp.m1;
+    ri1[wv] = tp.i1;
+    rm2[wv] = tp.m2;
+    rs[wv] = sum;
+    rq[wv] = sq;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Top2 b;
+    b.m1 = rm1[0];
+    b.i1 = ri1[0];
+    b.m2 = rm2[0];
+    for (int i = 1; i < 4; ++i) {
+      Top2 o;
+      o.m1 = rm1[i];
+      o.i1 = ri1[i];
+      o.m2 = rm2[i];
+      b = top2_merge(b, o);
+    }
+    const int flat = (b.i1 >= 0 && b.i1 < n * n) ? b.i1 : 0;
+    const int iy = flat / n, ix = flat % n;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx)
+        nb[dy + 1][dx + 1] = s[(size_t)((iy + dy + n) % n) * n + ((ix + dx + n) % n)];
+    out[blockIdx.x] = make_record(n, b, rs[0] + rs[1] + rs[2] + rs[3], rq[0] + rq[1] + rq[2] + rq[3], nb, 0);
+  }
+}
+
+hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t st) {
+  if (batch > 0) k_snr<<<batch, 256, 0, st>>>(surf, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- z-projection model
+// Each thread owns BW consecutive pixels of one row and walks the stack in z,
+// keeping the 2K+1 sections around s in registers, so every section byte is
+// read once.  out[s] = (2 S + n) / (2 n) rounded down = the round-half-up mean
+// of the n included neighbours (exact: the quotient is formed in FP32 with a
+// 1/(4n) guard that no rounding error can cross for n <= 16).
+template <int BW> struct Pix;
+template <> struct Pix<16> { using T = uint4; };
+template <> struct Pix<1> { using T = unsigned char; };
+
+__device__ __forceinline__ uint32_t div_pack4(uint32_t lo, uint32_t hi, float inv2n, uint32_t nn) {
+  // lo holds 16-bit sums of bytes 0 and 2, hi of bytes 1 and 3
+  const uint32_t s0 = lo & 0xFFFFu, s2 = lo >> 16, s1 = hi & 0xFFFFu, s3 = hi >> 16;
+  const uint32_t q0 = (uint32_t)floorf(((float)(2u * s0 + nn) + 0.5f) * inv2n);
+  const uint32_t q1 = (uint32_t)floorf(((float)(2u * s1 + nn) + 0.5f) * inv2n);
+  const uint32_t q2 = (uint32_t)floorf(((float)(2u * s2 + nn) + 0.5f) * inv2n);
+  const uint32_t q3 = (uint32_t)floorf(((float)(2u * s3 + nn) + 0.5f) * inv2n);
+  return q0 | (q1 << 8) | (q2 << 16) | (q3 << 24);
+}
+
+template <int K, int BW>
+__global__ void __launch_bounds__(256) k_project(const uint8_t* __restrict__ src, int64_t pitch, int64_t sstride,
+                                                 int S, int H, int W, const uint8_t* __restrict__ excl,
+                                                 uint8_t* __restrict__ dst, int64_t dpitch, int64_t dstride) {
+  using PT = typename Pix<BW>::T;
+  constexpr int WN = 2 * K + 1;
+  const int cpr = W / BW;
+  const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long long)H * cpr) return;
+  const int y = (int)(gid / cpr), x = (int)(gid % cpr) * BW;
+  const uint8_t* col = src + (int64_t)y * pitch + x;
+  uint8_t* ocol = dst + (int64_t)y * dpitch + x;
+
+  PT win[WN];
+#pragma unroll
+  for (int i = 0; i < WN; ++i) {
+    const int j = i - K;
+    if (j >= 0 && j < S) win[i] = *(const PT*)(col + (int64_t)j * sstride);
+    else win[i] = PT{};
+  }
+  for (int s = 0; s < S; ++s) {
+    uint32_t nn = 0;
+    if constexpr (BW == 16) {
+      uint32_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < WN; ++i) {
+        const int j = s - K + i;
+        if (i != K && j >= 0 && j < S && !(excl && excl[j])) {
+          ++nn;
+          const uint4 v = win[i];
+          const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            lo[q] += w4[q] & 0x00FF00FFu;
+            hi[q] += (w4[q] >> 8) & 0x00FF00FFu;
+          }
+        }
+      }
+      uint4 o = make_uint4(0, 0, 0, 0);
+      if (nn > 0) {
+        const float inv2n = 1.0f / (float)(2u * nn);
+        o.x = div_pack4(lo[0], hi[0], inv2n, nn);
+        o.y = div_pack4(lo[1], hi[1], inv2n, nn);
+        o.z = div_pack4(lo[2], hi[2], inv2n, nn);
+        o.w = div_pack4(lo[3], hi[3], inv2n, nn);
+      }
+      *(uint4*)(ocol + (int64_t)s * dstride) = o;
+    } else {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int i = 0; i < WN; ++i) {
+        const int j = s - K + i;
+        if (i != K && j >= 0 && j < S && !(excl && excl[j])) {
+          ++nn;
+          acc += win[i];
+        }
+      }
+      uint8_t o = 0;
+      if (nn > 0) o = (uint8_t)floorf(((float)(2u * acc + nn) + 0.5f) / (float)(2u * nn));
+      ocol[(int64_t)s * dstride] = o;
+    }
+#pragma unroll
+    for (int i = 0; i < WN - 1; ++i) win[i] = win[i + 1];
+    const int jn = s + K + 1;
+    if (jn < S) win[WN - 1] = *(const PT*)(col + (int64_t)jn * sstride);
+    else win[WN - 1] = PT{};
+  }
+}
+
+template <int K>
+static hipError_t launch_project_k(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
+                                   const uint8_t* excl, uint8_t* dst, int64_t dpitch, int64_t dstride,
+                                   hipStream_t st) {
+  const bool vec = (W % 16 == 0) && (pitch % 16 == 0) && (sstride % 16 == 0) && (dpitch % 16 == 0) &&
+                   (dstride % 16 == 0) && (((uintptr_t)src) % 16 == 0) && (((uintptr_t)dst) % 16 == 0);
+  if (vec) {
+    const long long nthr = (long long)H * (W / 16);
+    k_project<K, 16><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
+                                                                      dpitch, dstride);
+  } else {
+    const long long nthr = (long long)H * W;
+    k_project<K, 1><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
+                                                                     dpitch, dstride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
+                          const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
+                          hipStream_t st) {
+  switch (k) {
+    case 1: return launch_project_k<1>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 2: return launch_project_k<2>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 3: return launch_project_k<3>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 4: return launch_project_k<4>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 5: return launch_project_k<5>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 6: return launch_project_k<6>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 7: return launch_project_k<7>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 8: return launch_project_k<8>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- x2 pyramid
+// dst(x, y) = (src(2x,2y) + src(2x+1,2y) + src(2x,2y+1) + src(2x+1,2y+1) + 2) >> 2
+__global__ void __launch_bounds__(256) k_pyramid(const uint8_t* __restrict__ src, int64_t spitch,
+                                                 uint8_t* __restrict__ dst, int64_t dpitch, int dw, int dh) {
+  const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long long)dw * dh) return;
+  const int y = (int)(gid / dw), x = (int)(gid % dw);
+  const uint8_t* r0 = src + (int64_t)(2 * y) * spitch + 2 * x;
+  const uint8_t* r1 = r0 + spitch;
+  const uint32_t s = (uint32_t)r0[0] + r0[1] + r1[0] + r1[1];
+  dst[(int64_t)y * dpitch + x] = (uint8_t)((s + 2u) >> 2);
+}
+
+hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, uint8_t* dst, int64_t dpitch,
+                          int dw, int dh, hipStream_t st) {
+  (void)sw;
+  (void)sh;
+  const long long n = (long long)dw * dh;
+  if (n > 0) k_pyramid<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, spitch, dst, dpitch, dw, dh);
+  return hipGetLastError();
+}
+
+}  // namespace swift

@@ -1,0 +1,237 @@
+"""ctypes binding of libswift (include/swift.h).
+
+Argument marshalling only: tensors supply device memory and the current HIP
+stream; every step of matching runs in the library's HIP kernels.  There is no
+CPU fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswift.so")
+SIZES = (64, 128, 256, 512, 1024)
+
+SWIFT_U8, SWIFT_F32 = 0, 1
+ST_NEAR_TIE, ST_DEGENERATE, ST_CLAMPED = 1, 2, 4
+ERRORS = {-1: "SWIFT_E_INVAL", -2: "SWIFT_E_UNSUPPORTED", -3: "SWIFT_E_WORKSPACE",
+          -4: "SWIFT_E_HIP", -5: "SWIFT_E_CAPTURE"}
+
+
+class SwiftError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Image(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("pitch", C.c_int64), ("dtype", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Pairs(C.Structure):
+    _fields_ = [("n_pairs", C.c_int32), ("size_count", C.c_int32 * 5),
+                ("img_a", C.c_void_p), ("img_b", C.c_void_p),
+                ("theta_a", C.c_void_p), ("theta_b", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("p", C.c_float), ("eps_rel", C.c_float), ("taper_frac", C.c_float),
+                ("centroid_r", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+REC_BYTES = 48
+assert C.sizeof(Image) == 32 and C.sizeof(Pairs) == 56 and C.sizeof(Params) == 24
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libswift.so and declares its entry points.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libswift.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = C.CDLL(path)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.swift_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.swift_destroy.argtypes = [vp]
+    lib.swift_destroy.restype = None
+    lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
+    lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
+    lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
+                                         vp, sz, vp]
+    lib.swift_project.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i64, i64, vp]
+    lib.swift_pyramid.argtypes = [vp, C.POINTER(Image), C.POINTER(Image), vp]
+    lib.swift_snr.argtypes = [vp, vp, i32, i32, C.POINTER(Params), vp, vp]
+    lib.swift_last_error.restype = C.c_char_p
+    for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
+              "swift_project", "swift_pyramid", "swift_snr"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
+            "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise SwiftError(rc, _lib.swift_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0):
+    return Params(float(p), float(eps_rel), float(taper_frac), int(centroid_r), int(flags), 0)
+
+
+def parse_records(rec: torch.Tensor) -> dict:
+    """Splits a [P, 48] uint8 record tensor into named field views."""
+    P = rec.shape[0]
+    f32 = rec.view(torch.float32).view(P, 12)
+    i32 = rec.view(torch.int32).view(P, 12)
+    f64 = rec.view(torch.float64).view(P, 6)
+    return dict(dx=f32[:, 0], dy=f32[:, 1], ix=i32[:, 2], iy=i32[:, 3], peak=f32[:, 4], snr=f32[:, 5],
+                mean=f64[:, 3], std=f64[:, 4], status=i32[:, 10], n=i32[:, 11])
+
+
+class Swift:
+    """A libswift context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libswift needs a ROCm GPU; none is visible")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        _check(self.lib.swift_create(device, C.byref(h)))
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.swift_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # ------------------------------------------------------------------ helpers
+    def image_table(self, images):
+        """Device table of swift_image descriptors for a list of 2-D uint8 or
+        float32 device tensors (row pitch from their strides)."""
+        rows = []
+        for im in images:
+            assert im.dim() == 2 and im.device == self.device and im.stride(1) == 1
+            dt = SWIFT_U8 if im.dtype == torch.uint8 else SWIFT_F32
+            assert im.dtype in (torch.uint8, torch.float32)
+            pitch = im.stride(0) * im.element_size()
+            rows.append([im.data_ptr(), (im.shape[1] & 0xFFFFFFFF) | (im.shape[0] << 32), pitch, dt])
+        t = torch.tensor(rows, dtype=torch.int64).to(self.device)
+        t._swift_keepalive = list(images)
+        return t
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    @staticmethod
+    def make_pairs(n_list, img_a, img_b, theta_a, theta_b):
+        n_list = [int(n) for n in n_list]
+        assert all(n_list[i] <= n_list[i + 1] for i in range(len(n_list) - 1)), "pairs must be sorted by n"
+        counts = [sum(1 for n in n_list if n == s) for s in SIZES]
+        assert sum(counts) == len(n_list), "window edges must be in %s" % (SIZES,)
+        pr = Pairs()
+        pr.n_pairs = len(n_list)
+        for i, c in enumerate(counts):
+            pr.size_count[i] = c
+        pr.img_a, pr.img_b = img_a.data_ptr(), img_b.data_ptr()
+        pr.theta_a, pr.theta_b = theta_a.data_ptr(), theta_b.data_ptr()
+        return pr
+
+    def workspace_size(self, pairs, params):
+        ws = C.c_size_t()
+        sv = C.c_size_t()
+        _check(self.lib.swift_workspace_size(self.h, C.byref(pairs), C.byref(params), C.byref(ws), C.byref(sv)))
+        return ws.value, sv.value
+
+    # ------------------------------------------------------------------ entry points
+    def match_batch_raw(self, table, n_imgs, pairs, params, out, surfaces=None, ws=None):
+        need, _ = self.workspace_size(pairs, params)
+        if ws is None:
+            ws = self.workspace(need)
+        _check(self.lib.swift_match_batch(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
+                                          _ptr(out), _ptr(surfaces), C.c_void_p(0), _ptr(ws), ws.numel(),
+                                          self.stream()))
+
+    def match_batch(self, images, n_list, img_a, img_b, theta_a, theta_b, params=None, surfaces=False):
+        """Whitened FFT matching of window pairs.  images: list of device
+        tensors; n_list: host list of window edges (sorted); img_a/img_b: int32
+        device [P]; theta_a/theta_b: float32 device [P, 8].  Returns a dict of
+        device tensors (dx, dy, ix, iy, peak, snr, mean, std, status, n) and,
+        with surfaces=True, 'surfaces' as a flat float32 tensor."""
+        params = params or make_params()
+        table = self.image_table(images)
+        img_a = img_a.to(self.device, torch.int32).contiguous()
+        img_b = img_b.to(self.device, torch.int32).contiguous()
+        theta_a = theta_a.to(self.device, torch.float32).contiguous()
+        theta_b = theta_b.to(self.device, torch.float32).contiguous()
+        pr = self.make_pairs(n_list, img_a, img_b, theta_a, theta_b)
+        P = pr.n_pairs
+        out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=self.device)
+        surf = None
+        if surfaces:
+            surf = torch.empty(sum(int(n) * int(n) for n in n_list), dtype=torch.float32, device=self.device)
+        self.match_batch_raw(table, len(images), pr, params, out, surf)
+        res = parse_records(out)
+        res["raw"] = out
+        if surfaces:
+            res["surfaces"] = surf
+        return res
+
+    def project(self, stack, k=3, exclude=None, out=None):
+        """Z-projection models of every section of a [S, H, W] uint8 device stack."""
+        assert stack.dtype == torch.uint8 and stack.dim() == 3 and stack.stride(2) == 1
+        S, H, W = stack.shape
+        if out is None:
+            out = torch.empty_like(stack)
+        ex = None
+        if exclude is not None:
+            ex = torch.as_tensor(exclude, dtype=torch.uint8).to(self.device).contiguous()
+        _check(self.lib.swift_project(self.h, _ptr(stack), S, H, W, stack.stride(1), stack.stride(0), _ptr(ex),
+                                      int(k), _ptr(out), out.stride(1), out.stride(0), self.stream()))
+        return out
+
+    def pyramid(self, img):
+        assert img.dtype == torch.uint8 and img.dim() == 2 and img.stride(1) == 1
+        h, w = img.shape
+        dst = torch.empty((h // 2, w // 2), dtype=torch.uint8, device=img.device)
+        si = Image(img.data_ptr(), w, h, img.stride(0), SWIFT_U8, 0)
+        di = Image(dst.data_ptr(), w // 2, h // 2, dst.stride(0), SWIFT_U8, 0)
+        _check(self.lib.swift_pyramid(self.h, C.byref(si), C.byref(di), self.stream()))
+        return dst
+
+    def snr(self, surfaces, params=None):
+        """Peak, SNR and centroid of [B, n, n] float32 device surfaces."""
+        params = params or make_params()
+        surfaces = surfaces.contiguous()
+        B, n, _ = surfaces.shape
+        out = torch.empty((B, REC_BYTES), dtype=torch.uint8, device=self.device)
+        _check(self.lib.swift_snr(self.h, _ptr(surfaces), n, B, C.byref(params), _ptr(out), self.stream()))
+        return parse_records(out)
