@@ -1,0 +1,229 @@
+"""Throughput of the whitened FFT window-matching hot path on one MI355X.
+
+Workload (512^2 headline batch): 64 synthetic 4096^2 uint8 sections with
+accumulated drift and per-section affine distortion; the reference of every
+section is its +-3 z-projection; an 8 x 8 grid of 512^2 windows per section
+gives 4096 window pairs.  One step = projection of the whole stack plus the
+whitened match of all 4096 pairs (gather, taper + mean, forward FFTs,
+whitening, inverse FFT, peak / SNR / centroid).  Inputs are resident in HBM
+before the timed region.
+
+Prints one JSON line (metric, value in pairs/s, roofline of the dominant
+kernel from live HIP-event timing, and the FP64 oracle's throughput on a
+bounded sample of the same pairs on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "512² window-pair matches/sec + HBM GB/s; plain vs batched+adjoint at 0.01px"
+HBM_PEAK_GBS = 8000.0
+S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
+
+
+def kernel_bytes(name: str, n: int, pairs: int, sections: int, size: int) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel over the whole batch:
+    what the kernel must read and write at least (inputs once, exchange
+    buffers once each way), not what the caches end up doing."""
+    nn = float(n) * n
+    half = 8.0 * n * (n // 2 + 1)  # one complex64 half spectrum
+    if name.startswith("k_row_fwd"):
+        per = 2 * nn + 8 * nn          # two uint8 windows in, packed complex row spectra out
+    elif name.startswith("k_col"):
+        per = 8 * nn + half            # packed spectra in, inverse-column half spectrum out
+    elif name.startswith("k_row_inv"):
+        per = half                     # half spectrum in (surface statistics out are tiny)
+    elif name.startswith("k_finalize"):
+        per = 24.0 * (n // 2 + 1) + 64  # three spectrum rows re-read + record
+    elif name.startswith("k_pair_stats"):
+        per = 64
+    elif name.startswith("k_project"):
+        return 2.0 * sections * size * size  # every section read once, every model written once
+    else:
+        per = 0.0
+    return per * pairs
+
+
+def pair_bytes(n: int) -> float:
+    """Algorithmic bytes per pair of the whole match path: uint8 inputs, the
+    record, and one write + read of each exchanged spectrum."""
+    return 2.0 * n * n + 64 + 48.0 * n * (n // 2 + 1)
+
+
+def pair_flops(n: int) -> float:
+    import math
+    return 7.5 * n * n * math.log2(n * n) + 40.0 * n * n
+
+
+# --------------------------------------------------------------------------- CPU oracle leg
+def _oracle_worker(job):
+    import numpy as np
+
+    import oracle as O
+    t0 = time.perf_counter()
+    out = []
+    for (wa, wb, tha, thb, n, p) in job:
+        r = O.match_pair(wa, wb, tha, thb, n, O.Params(p=p))
+        out.append((r["ix"], r["iy"], r["snr"]))
+    return out, time.perf_counter() - t0
+
+
+def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=3, cores=None):
+    """Times the FP64 oracle (one process per core) on a bounded sample of the
+    same pairs.  Windows are cropped with a margin so clamped reads at the
+    section border are reproduced exactly."""
+    import multiprocessing as mp
+
+    import numpy as np
+    cores = cores or min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(0)
+    jobs = []
+    H = stack_cpu.shape[1]
+    m = 4
+    for s in range(min(n_sample_sections, stack_cpu.shape[0])):
+        for w in rng.choice(len(centres), per_section, replace=False):
+            cx, cy = centres[w]
+            x0, y0 = int(max(cx - N // 2 - m, 0)), int(max(cy - N // 2 - m, 0))
+            x1, y1 = int(min(cx + N // 2 + m, H)), int(min(cy + N // 2 + m, H))
+            th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+            jobs.append((stack_cpu[s, y0:y1, x0:x1].copy(), refs_cpu[s, y0:y1, x0:x1].copy(), th, th, N, P_WHITEN))
+    chunks = [jobs[i::cores] for i in range(cores)]
+    ctx = mp.get_context("spawn")
+    env_keep = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        with ctx.Pool(cores) as pool:
+            pool.map(_oracle_worker, [c[:1] for c in chunks])  # warm the workers (imports)
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_worker, chunks)
+            wall = time.perf_counter() - t0
+    finally:
+        if env_keep is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_keep
+    cpu_s = sum(r[1] for r in res)
+    return dict(value=len(jobs) / wall, unit="pairs/s", cores=cores, kind="oracle",
+                sample="%d pairs of %d^2 (%d sections x %d windows) of the benchmark batch, FP64 NumPy, "
+                       "one process per core; %.1f s of CPU work" % (len(jobs), N, n_sample_sections,
+                                                                     per_section, cpu_s),
+                cpu_seconds=cpu_s, mpx_per_s_per_core=len(jobs) * N * N / cpu_s / 1e6)
+
+
+# --------------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1612_04787_amd as sw
+    from datagen.workloads import distorted_stack, section_grid_pairs
+
+    dev = torch.device("cuda", 0)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.time()
+    stack, _ = distorted_stack(S_SECTIONS, SIZE, seed=5, device=dev)
+    torch.cuda.synchronize()
+    log("workload: %d x %d^2 stack generated in %.1f s" % (S_SECTIONS, SIZE, time.time() - t0))
+
+    ctx = sw.Swift(0)
+    refs = torch.empty_like(stack)
+    images = [stack[s] for s in range(S_SECTIONS)] + [refs[s] for s in range(S_SECTIONS)]
+    table = ctx.image_table(images)
+    n_list, ia, ib, ta, tb, cen = section_grid_pairs(S_SECTIONS, SIZE, N, GRID, dev)
+    pairs = ctx.make_pairs(n_list, ia, ib, ta, tb)
+    P = pairs.n_pairs
+    params = sw.make_params(p=P_WHITEN)
+    need, _ = ctx.workspace_size(pairs, params)
+    ws = ctx.workspace(need)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
+    log("pairs: %d of %d^2, workspace %.2f GB" % (P, N, need / 1e9))
+
+    def step():
+        ctx.project(stack, k=K_PROJ, out=refs)
+        ctx.match_batch_raw(table, len(images), pairs, params, out, None, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el / args.steps * 1e3
+    value = P / (ms / 1e3)
+    log("timed: %d steps, %.3f ms/step, %.0f pairs/s" % (args.steps, ms, value))
+
+    # live per-kernel timing (HIP events on the launch stream), same work
+    ctx.profile(True)
+    prof_steps = max(3, min(args.steps, 10))
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    kt = ctx.profile_read()
+    ctx.profile(False)
+    kernels = {}
+    for name, (cnt, tot) in kt.items():
+        b = kernel_bytes(name, N, P, S_SECTIONS, SIZE)
+        avg = tot / cnt
+        kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    d = kernels[dom]
+    roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=d["gbs"] / HBM_PEAK_GBS, traffic=None,
+                bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
+    res = sw.parse_records(out)
+    snr = res["snr"].float()
+    step_bytes = P * pair_bytes(N) + kernel_bytes("k_project", N, P, S_SECTIONS, SIZE)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^2 window pairs: 64 sections of 4096^2 uint8 (drift + affine distortion), "
+                               "references = +-3 z-projections, 8x8 windows per section",
+                   "window": N, "pairs": P, "sections": S_SECTIONS, "section_px": SIZE, "p": P_WHITEN,
+                   "eps_rel": 1e-4, "taper_frac": 0.25, "projection_k": K_PROJ},
+        "hbm_gbs": step_bytes / (ms / 1e3) / 1e9,
+        "alu_tflops": P * pair_flops(N) / (ms / 1e3) / 1e12,
+        "roofline": roof,
+        "kernels": kernels,
+        "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: timing the FP64 oracle on a sample ...")
+        line["cpu_baseline"] = cpu_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)
+        log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,18 @@ int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst
 int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch,
               const swift_params* params, swift_match* out, hipStream_t stream);
 
+/* Kernel timing (instrumentation, not in the paper).  While enabled, every
+ * kernel the context launches is bracketed by a pair of HIP events recorded on
+ * the launch stream (a few microseconds per launch; no work is skipped).
+ * swift_profile_read waits for those events and returns, per kernel name
+ * ("k_col<512>" ...), the number of launches and their summed duration in ms,
+ * then forgets them.  names: host [max_kernels][64] chars; launches, total_ms:
+ * host [max_kernels]; *n_kernels receives the number of distinct kernels (may
+ * exceed max_kernels).  Not thread-safe with concurrent calls on one context. */
+int swift_profile_enable(swift_ctx* ctx, int enable);
+int swift_profile_read(swift_ctx* ctx, int32_t max_kernels, char* names, int32_t* launches,
+                       double* total_ms, int32_t* n_kernels);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* swift_last_error(void);
 

@@ -4,16 +4,70 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "swift_internal.hpp"
 
 using namespace swift;
 
+// Records a pair of HIP events around every kernel launch while enabled.
+struct EventTimer : KernelTimer {
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::string cur;
+  hipEvent_t cur_a = nullptr;
+  bool failed = false;
+  static constexpr size_t kMaxRecs = 1 << 16;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(const char* name, int n, hipStream_t s) override {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%s<%d>", name, n);
+    cur = buf;
+    cur_a = recs.size() < kMaxRecs ? get() : nullptr;
+    if (cur_a && hipEventRecord(cur_a, s) != hipSuccess) failed = true;
+  }
+  void end(hipStream_t s) override {
+    if (!cur_a) return;
+    hipEvent_t b = get();
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+      failed = true;
+      return;
+    }
+    recs.push_back(Rec{cur, cur_a, b});
+    cur_a = nullptr;
+  }
+  ~EventTimer() override {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct swift_ctx {
   int device;
   float2* tw;  // W_1024^m = exp(-2 pi i m / 1024)
+  bool profile = false;
+  EventTimer timer;
+  KernelTimer* kt() { return profile ? &timer : nullptr; }
 };
 
 namespace {
@@ -249,7 +303,7 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     a.eps_rel = params->eps_rel;
     a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     a.npairs = g.count;
-    e = launch_match_group(g.n, a, stream);
+    e = launch_match_group(g.n, a, stream, ctx->kt());
     if (e != hipSuccess) return hip_fail(e, "match launch");
     surf_off += (size_t)g.count * g.n * g.n;
   }
@@ -278,7 +332,7 @@ int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t heigh
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipError_t e = launch_project(stack, pitch, section_stride, S, height, width, exclude, k, out, out_pitch,
-                                out_section_stride, stream);
+                                out_section_stride, stream, ctx->kt());
   if (e != hipSuccess) return hip_fail(e, "project launch");
   return ok();
 }
@@ -313,6 +367,48 @@ int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch, c
   hipError_t e = launch_snr(surfaces, n, batch, out, stream);
   if (e != hipSuccess) return hip_fail(e, "snr launch");
   return ok();
+}
+
+int swift_profile_enable(swift_ctx* ctx, int enable) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  ctx->profile = enable != 0;
+  return ok();
+}
+
+int swift_profile_read(swift_ctx* ctx, int32_t max_kernels, char* names, int32_t* launches, double* total_ms,
+                       int32_t* n_kernels) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!n_kernels || max_kernels < 0 || (max_kernels > 0 && (!names || !launches || !total_ms)))
+    return fail(SWIFT_E_INVAL, "bad output arrays");
+  DeviceGuard dg(ctx->device);
+  std::map<std::string, std::pair<int, double>> agg;
+  EventTimer& t = ctx->timer;
+  int rc = SWIFT_OK;
+  for (auto& r : t.recs) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
+    auto& v = agg[r.name];
+    v.first += 1;
+    v.second += ms;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  if (t.failed) rc = fail(SWIFT_E_HIP, "event record failed while profiling");
+  t.failed = false;
+  int i = 0;
+  for (auto& kv : agg) {
+    if (i < max_kernels) {
+      snprintf(names + 64 * i, 64, "%s", kv.first.c_str());
+      launches[i] = kv.second.first;
+      total_ms[i] = kv.second.second;
+    }
+    ++i;
+  }
+  *n_kernels = i;
+  return rc ? rc : ok();
 }
 
 }  // extern "C"

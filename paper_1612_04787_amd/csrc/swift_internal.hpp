@@ -79,13 +79,21 @@ constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 size_t pair_ws_bytes(int n);   // exchange + partial buffers for one pair
 size_t align256(size_t x);
 
+// Optional kernel timing: when non-null, launchers bracket every kernel with
+// begin/end so the context can record HIP events on the launch stream.
+struct KernelTimer {
+  virtual void begin(const char* name, int n, hipStream_t s) = 0;
+  virtual void end(hipStream_t s) = 0;
+  virtual ~KernelTimer() {}
+};
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, hipStream_t s);
-hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* exclude, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
-                          hipStream_t s);
+                          hipStream_t s, KernelTimer* kt);
 hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, uint8_t* dst, int64_t dpitch,
                           int dw, int dh, hipStream_t s);
 

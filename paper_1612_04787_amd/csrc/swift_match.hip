@@ -485,27 +485,53 @@ hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, h
   return hipGetLastError();
 }
 
+struct TimerScope {
+  KernelTimer* kt;
+  hipStream_t s;
+  TimerScope(KernelTimer* k, const char* name, int n, hipStream_t st) : kt(k), s(st) {
+    if (kt) kt->begin(name, n, s);
+  }
+  ~TimerScope() {
+    if (kt) kt->end(s);
+  }
+};
+
 template <int N>
-static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s) {
+static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
   using C = FftCfg<N>;
   constexpr int NSLICE = N / RowsCfg<N>::FWD, NSL2 = N / RowsCfg<N>::INV;
   constexpr int G = 256 / C::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
   const unsigned P = (unsigned)a.npairs;
-  k_row_fwd<N><<<P * NSLICE, 256, 0, s>>>(a);
-  k_pair_stats<N><<<P, 64, 0, s>>>(a);
-  k_col<N><<<P * NW, 256, 0, s>>>(a);
-  k_row_inv<N><<<P * NSL2, 256, 0, s>>>(a);
-  k_finalize<N><<<P, 64, 0, s>>>(a);
+  {
+    TimerScope ts(kt, "k_row_fwd", N, s);
+    k_row_fwd<N><<<P * NSLICE, 256, 0, s>>>(a);
+  }
+  {
+    TimerScope ts(kt, "k_pair_stats", N, s);
+    k_pair_stats<N><<<P, 64, 0, s>>>(a);
+  }
+  {
+    TimerScope ts(kt, "k_col", N, s);
+    k_col<N><<<P * NW, 256, 0, s>>>(a);
+  }
+  {
+    TimerScope ts(kt, "k_row_inv", N, s);
+    k_row_inv<N><<<P * NSL2, 256, 0, s>>>(a);
+  }
+  {
+    TimerScope ts(kt, "k_finalize", N, s);
+    k_finalize<N><<<P, 64, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s) {
+hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
   switch (n) {
-    case 64: return launch_group_t<64>(a, s);
-    case 128: return launch_group_t<128>(a, s);
-    case 256: return launch_group_t<256>(a, s);
-    case 512: return launch_group_t<512>(a, s);
-    case 1024: return launch_group_t<1024>(a, s);
+    case 64: return launch_group_t<64>(a, s, kt);
+    case 128: return launch_group_t<128>(a, s, kt);
+    case 256: return launch_group_t<256>(a, s, kt);
+    case 512: return launch_group_t<512>(a, s, kt);
+    case 1024: return launch_group_t<1024>(a, s, kt);
   }
   return hipErrorInvalidValue;
 }

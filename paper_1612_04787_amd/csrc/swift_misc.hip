@@ -62,6 +62,10 @@ hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hip
   return hipGetLastError();
 }
 
+hipError_t launch_project_sel(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
+                              const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
+                              hipStream_t st);
+
 // ---------------------------------------------------------------- z-projection model
 // Each thread owns BW consecutive pixels of one row and walks the stack in z,
 // keeping the 2K+1 sections around s in registers, so every section byte is
@@ -171,7 +175,16 @@ static hipError_t launch_project_k(const uint8_t* src, int64_t pitch, int64_t ss
 
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
-                          hipStream_t st) {
+                          hipStream_t st, KernelTimer* kt) {
+  if (kt) kt->begin("k_project", k, st);
+  const hipError_t e = launch_project_sel(src, pitch, sstride, S, H, W, excl, k, dst, dpitch, dstride, st);
+  if (kt) kt->end(st);
+  return e;
+}
+
+hipError_t launch_project_sel(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
+                              const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
+                              hipStream_t st) {
   switch (k) {
     case 1: return launch_project_k<1>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
     case 2: return launch_project_k<2>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);

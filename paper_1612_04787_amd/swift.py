@@ -68,9 +68,11 @@ def load_library(path: str = LIB_PATH):
     lib.swift_project.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i64, i64, vp]
     lib.swift_pyramid.argtypes = [vp, C.POINTER(Image), C.POINTER(Image), vp]
     lib.swift_snr.argtypes = [vp, vp, i32, i32, C.POINTER(Params), vp, vp]
+    lib.swift_profile_enable.argtypes = [vp, C.c_int]
+    lib.swift_profile_read.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32)]
     lib.swift_last_error.restype = C.c_char_p
     for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
-              "swift_project", "swift_pyramid", "swift_snr"):
+              "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -78,7 +80,8 @@ def load_library(path: str = LIB_PATH):
 
 def exported_symbols():
     return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
-            "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error"]
+            "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
+            "swift_profile_enable", "swift_profile_read"]
 
 
 def _check(rc):
@@ -130,6 +133,23 @@ class Swift:
 
     def stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # ------------------------------------------------------------------ kernel timing
+    def profile(self, enable=True):
+        _check(self.lib.swift_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self, max_kernels=64):
+        """{kernel name: (launches, total ms)} of the kernels timed since the last read."""
+        names = C.create_string_buffer(64 * max_kernels)
+        cnt = (C.c_int32 * max_kernels)()
+        ms = (C.c_double * max_kernels)()
+        nk = C.c_int32()
+        _check(self.lib.swift_profile_read(self.h, max_kernels, names, cnt, ms, C.byref(nk)))
+        out = {}
+        for i in range(min(nk.value, max_kernels)):
+            nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (cnt[i], ms[i])
+        return out
 
     # ------------------------------------------------------------------ helpers
     def image_table(self, images):
