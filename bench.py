@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,6 +158,15 @@ def main():
     ws = ctx.workspace(need)
     out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
     log("pairs: %d of %d^2, workspace %.2f GB" % (P, N, need / 1e9))
+
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB device-to-device")
 
     def step():
         ctx.project(stack, k=K_PROJ, out=refs)

@@ -9,6 +9,16 @@
 
 namespace swift {
 
+// Pointers into the images come from the device image table, so the compiler
+// cannot prove they are global memory; this cast lets it use global (not flat)
+// loads.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(const void* p) {
+  return (gptr<T>)p;
+}
+
 __device__ __forceinline__ float taper_at(int i, int n, int L) {
   if (L <= 0) return 1.0f;
   const int m = i < n - 1 - i ? i : n - 1 - i;
@@ -38,6 +48,15 @@ __device__ __forceinline__ void top2_push(Top2& a, float v, int i) {
   }
 }
 
+// For values visited in increasing index order within a lane: a strict >
+// already keeps the first maximum.
+__device__ __forceinline__ void top2_push_ordered(Top2& a, float v, int i) {
+  const bool c1 = v > a.m1;
+  a.m2 = c1 ? a.m1 : fmaxf(a.m2, v);
+  a.i1 = c1 ? i : a.i1;
+  a.m1 = c1 ? v : a.m1;
+}
+
 __device__ __forceinline__ Top2 top2_merge(Top2 a, Top2 b) {
   const bool bw = (b.m1 > a.m1) || (b.m1 == a.m1 && b.i1 < a.i1);
   Top2 w = bw ? b : a, l = bw ? a : b;
@@ -59,28 +78,6 @@ __device__ __forceinline__ Top2 wave_top2(Top2 a) {
   }
   return a;
 }
-
-// Bilinear, clamp-to-edge sample at (x, y); coordinates in FP64 so that the
-// sub-pixel fraction keeps full precision on large sections.
-template <typename Pix>
-__device__ __forceinline__ float bilinear(const unsigned char* __restrict__ base, int64_t pitch, int w, int h,
-                                          double x, double y, bool& clamped) {
-  double xf = floor(x), yf = floor(y);
-  const float fx = (float)(x - xf), fy = (float)(y - yf);
-  xf = fmin(fmax(xf, -2.0), (double)w);
-  yf = fmin(fmax(yf, -2.0), (double)h);
-  const int x0 = (int)xf, y0 = (int)yf;
-  const int x1 = x0 + 1, y1 = y0 + 1;
-  clamped |= (x0 < 0) | (y0 < 0) | (x1 > w - 1) | (y1 > h - 1);
-  const int cx0 = min(max(x0, 0), w - 1), cx1 = min(max(x1, 0), w - 1);
-  const int cy0 = min(max(y0, 0), h - 1), cy1 = min(max(y1, 0), h - 1);
-  const Pix* r0 = (const Pix*)(base + (int64_t)cy0 * pitch);
-  const Pix* r1 = (const Pix*)(base + (int64_t)cy1 * pitch);
-  const float i00 = (float)r0[cx0], i10 = (float)r0[cx1];
-  const float i01 = (float)r1[cx0], i11 = (float)r1[cx1];
-  return (1.0f - fy) * ((1.0f - fx) * i00 + fx * i10) + fy * ((1.0f - fx) * i01 + fx * i11);
-}
-
 
 // Match record from the reduced surface statistics and the 3x3 neighbourhood
 // nb[dy+1][dx+1] of the peak (nb[1][1] is replaced by the peak value).

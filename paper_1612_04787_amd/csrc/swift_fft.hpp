@@ -133,11 +133,50 @@ template <bool INV> struct Dft<16, INV> {
   }
 };
 
+// ---------------------------------------------------------------- twiddles
+// Pass P (P >= 1) of butterfly j = t + b*T multiplies input q by
+// W_{NS*R}^(q*k), k = j mod NS.  These depend only on the lane, so kernels that
+// run several transforms per lane load them once into registers.
+template <int N>
+__host__ __device__ constexpr int tw_off(int P) {
+  int o = 0;
+  for (int p = 1; p < P; ++p) o += (FftCfg<N>::E / FftCfg<N>::rad(p)) * (FftCfg<N>::rad(p) - 1);
+  return o;
+}
+template <int N>
+__host__ __device__ constexpr int tw_count() { return tw_off<N>(FftCfg<N>::NP); }
+
+template <int N>
+struct Twiddles {
+  float2 w[tw_count<N>()];
+};
+
+// tab: W_1024^m = exp(-2 pi i m / 1024), m in [0, 1024), float2 (global memory).
+template <int N, int P, int NS>
+__device__ __forceinline__ void tw_load_pass(Twiddles<N>& tw, int t, const float2* __restrict__ tab) {
+  using C = FftCfg<N>;
+  if constexpr (P < C::NP) {
+    constexpr int R = C::rad(P), B = C::E / R, TWS = 1024 / (NS * R), O = tw_off<N>(P);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int k = (t + b * C::T) & (NS - 1);
+#pragma unroll
+      for (int q = 1; q < R; ++q) tw.w[O + b * (R - 1) + q - 1] = tab[q * k * TWS];
+    }
+    tw_load_pass<N, P + 1, NS * R>(tw, t, tab);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void tw_load(Twiddles<N>& tw, int t, const float2* __restrict__ tab) {
+  tw_load_pass<N, 1, FftCfg<N>::rad(0)>(tw, t, tab);
+}
+
 // ---------------------------------------------------------------- Stockham pass
-// tw: W_1024^m = exp(-2 pi i m / 1024), m in [0, 1024), float2 (global memory).
-template <int N, bool INV, int P, int NS>
+// REG: twiddles from registers (twr), otherwise loaded from the table per pass.
+template <int N, bool INV, int P, int NS, bool REG>
 __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
-                                         const float2* __restrict__ tw) {
+                                         const Twiddles<N>* __restrict__ twr, const float2* __restrict__ tab) {
   using C = FftCfg<N>;
   constexpr int R = C::rad(P), E = C::E, T = C::T, B = E / R;
   constexpr bool LAST = (P == C::NP - 1);
@@ -152,7 +191,9 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __re
     if constexpr (P > 0) {
 #pragma unroll
       for (int q = 1; q < R; ++q) {
-        float2 w = tw[q * k * TWS];
+        float2 w;
+        if constexpr (REG) w = twr->w[tw_off<N>(P) + b * (R - 1) + q - 1];
+        else w = tab[q * k * TWS];
         if (INV) w.y = -w.y;
         u[q] = cmul(u[q], w);
       }
@@ -172,16 +213,24 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __re
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = lds[lidx(t + e * T)];
     wave_lds_sync();
-    fft_pass<N, INV, P + 1, NS * R>(v, lds, t, tw);
+    fft_pass<N, INV, P + 1, NS * R, REG>(v, lds, t, twr, tab);
   }
 }
 
-// Full transform.  lds: this transform's private scratch of lidx(N) float2.
-// Forward: X[k] = sum_n x[n] exp(-2 pi i k n / N); inverse: exp(+...), unscaled.
+// Full transform with register twiddles.  lds: this transform's private
+// scratch of lidx(N) float2.  Forward: X[k] = sum_n x[n] exp(-2 pi i k n / N);
+// inverse: exp(+...), unscaled.
 template <int N, bool INV>
 __device__ __forceinline__ void fft_wave(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
-                                         const float2* __restrict__ tw) {
-  fft_pass<N, INV, 0, 1>(v, lds, t, tw);
+                                         const Twiddles<N>& tw) {
+  fft_pass<N, INV, 0, 1, true>(v, lds, t, &tw, nullptr);
+}
+
+// Same, reading twiddles from the W_1024 table in every pass.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_wave_tab(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
+                                             const float2* __restrict__ tab) {
+  fft_pass<N, INV, 0, 1, false>(v, lds, t, nullptr, tab);
 }
 
 }  // namespace swift

@@ -66,13 +66,15 @@ struct MatchArgs {
   int32_t n_imgs;
 };
 
-// Rows per workgroup of the forward and inverse row passes.
+// Rows per workgroup of the forward and inverse row passes, and the LDS budget
+// (bytes) of one image's source tile in the forward pass (0: always gather
+// straight from global memory).
 template <int N> struct RowsCfg;
-template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64; };
-template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32; };
-template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16; };
-template <> struct RowsCfg<512>  { static constexpr int FWD = 16, INV = 16; };
-template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16; };
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096; };
+template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216; };
+template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240; };
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0; };
 
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 

@@ -74,13 +74,221 @@ __global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict_
 }
 
 // ---------------------------------------------------------------- row pass (forward)
-template <int N>
+// Source footprint of one image for the workgroup's R window rows, staged in
+// LDS as uint8 rows of wt4 dwords: tile(ty, tx) = img[clamp(ylo + ty)][clamp(xlo + tx)].
+struct TileGeom {
+  int xlo, ylo;   // tile origin in image pixels (xlo a multiple of 4)
+  int wt4, ht;    // dwords per tile row, tile rows
+  bool use;       // the footprint fits the budget and the image allows dword loads
+};
+
+// Per image and workgroup: affine of the window rows [y0, y0 + R).
+struct RowAffine {
+  double xc, yc;  // cx + tx, cy + ty
+  double a11, a12, a21, a22;
+  float f11, f21; // a11, a21 in FP32 for the per-pixel part
+};
+
+__device__ __forceinline__ RowAffine row_affine(const float* th) {
+  RowAffine r;
+  r.xc = (double)th[0] + (double)th[4];
+  r.yc = (double)th[1] + (double)th[7];
+  r.a11 = th[2];
+  r.a12 = th[3];
+  r.a21 = th[5];
+  r.a22 = th[6];
+  r.f11 = th[2];
+  r.f21 = th[5];
+  return r;
+}
+
+__device__ __forceinline__ int floor_to4(int v) { return v - (((v % 4) + 4) % 4); }
+
+template <int N, int R, int BUDGET>
+__device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_image& im, int y0) {
+  TileGeom g;
+  const double ulo = -N / 2, uhi = N / 2 - 1;
+  const double vlo = y0 - N / 2, vhi = y0 + R - 1 - N / 2;
+  const double xmin = ra.xc + fmin(ra.a11 * ulo, ra.a11 * uhi) + fmin(ra.a12 * vlo, ra.a12 * vhi);
+  const double xmax = ra.xc + fmax(ra.a11 * ulo, ra.a11 * uhi) + fmax(ra.a12 * vlo, ra.a12 * vhi);
+  const double ymin = ra.yc + fmin(ra.a21 * ulo, ra.a21 * uhi) + fmin(ra.a22 * vlo, ra.a22 * vhi);
+  const double ymax = ra.yc + fmax(ra.a21 * ulo, ra.a21 * uhi) + fmax(ra.a22 * vlo, ra.a22 * vhi);
+  const bool finite = fabs(xmin) < 1e8 && fabs(xmax) < 1e8 && fabs(ymin) < 1e8 && fabs(ymax) < 1e8;
+  g.use = false;
+  g.xlo = g.ylo = 0;
+  g.wt4 = g.ht = 0;
+  if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || (im.pitch & 3) || (im.width & 3) ||
+      (((uintptr_t)im.data) & 3))
+    return g;
+  // one pixel of margin on both sides absorbs FP32 rounding of the per-pixel coordinates
+  const int xl = (int)floor(xmin) - 1, xh = (int)floor(xmax) + 2;
+  const int yl = (int)floor(ymin) - 1, yh = (int)floor(ymax) + 2;
+  g.xlo = floor_to4(xl);
+  g.ylo = yl;
+  g.wt4 = (xh - g.xlo + 4) / 4;
+  g.ht = yh - yl + 1;
+  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET;
+  return g;
+}
+
+// Tile dwords are fetched in two steps so all loads are in flight at once:
+// tile_fetch issues every global load of a thread into registers (dword k of
+// the thread is tile element tid + 256 k) and nothing consumes them until
+// tile_store writes them to LDS.  Border dwords are read at the nearest
+// in-image aligned dword; tile_store re-selects their bytes with v_perm so
+// that byte i holds img[y][clamp(x + i)].
+struct TileIdx {
+  int yy, xx, xc;
+};
+
+__device__ __forceinline__ TileIdx tile_idx(const TileGeom& g, const swift_image& im, int idx, float rcp) {
+  TileIdx r;
+  // idx / wt4 exactly: the quotient's fraction stays >= 0.5/wt4 from an integer
+  const int ty = (int)(((float)idx + 0.5f) * rcp);
+  const int tx4 = idx - ty * g.wt4;
+  r.yy = min(max(g.ylo + ty, 0), im.height - 1);
+  r.xx = g.xlo + 4 * tx4;
+  r.xc = min(max(r.xx, 0), im.width - 4);
+  return r;
+}
+
+template <int MAXD>
+__device__ __forceinline__ void tile_fetch(uint32_t (&buf)[MAXD], const TileGeom& g, const swift_image& im,
+                                           int tid) {
+  const gptr<unsigned char> base = to_global<unsigned char>(im.data);
+  const int total = g.wt4 * g.ht;
+  const float rcp = 1.0f / (float)g.wt4;
+  // Branch-free on purpose (a branch between a load and its use makes the
+  // compiler drain the load queue at the join).  Past the end, the last
+  // element is re-read and never stored.
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k) {
+    const TileIdx t = tile_idx(g, im, min(tid + 256 * k, total - 1), rcp);
+    buf[k] = *(gptr<uint32_t>)(base + (int64_t)t.yy * im.pitch + t.xc);
+  }
+}
+
+template <int MAXD>
+__device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint32_t (&buf)[MAXD],
+                                           const TileGeom& g, const swift_image& im, int tid) {
+  const int total = g.wt4 * g.ht;
+  const float rcp = 1.0f / (float)g.wt4;
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k) {
+    const int idx = tid + 256 * k;
+    const TileIdx t = tile_idx(g, im, min(idx, total - 1), rcp);
+    uint32_t sel = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sel |= (uint32_t)(min(max(t.xx + b, 0), im.width - 1) - t.xc) << (8 * b);
+    if (idx < total) tile[idx] = __builtin_amdgcn_perm(buf[k], buf[k], sel);
+  }
+}
+
+// Row stride (float2) of the forward stage: >= lidx(N), chosen so that the
+// transposed read-out (rows fastest) hits distinct LDS banks.
+template <int N, int R>
+__host__ __device__ constexpr int fwd_stride() {
+  const int target = R >= 16 ? 1 : 16 / R;
+  int rs = lidx(N);
+  while ((rs & 15) != target) ++rs;
+  return rs;
+}
+
+// Per-row sampling parameters of one image, computed once per workgroup: the
+// row's coordinate at u = 0 split into an integer part (relative to the tile
+// origin when a tile is used) and an FP32 fraction, so the per-pixel work is
+// FP32 on small numbers while the absolute position keeps FP64 precision.
+struct RowParam {
+  int bx, by;      // integer part (tile-relative on the tile path)
+  float fx, fy;    // fractional part in [0, 1)
+};
+
+template <int N> struct GatherCfg {
+  static constexpr int XV = N >= 256 ? N / 256 : 1;   // columns per thread and row
+  static constexpr int RPI = N >= 256 ? 1 : 256 / N;  // rows per iteration
+};
+
+// Gathers one image of the workgroup's R rows into the stage (real or
+// imaginary parts): a' T with a' = sample - offset, T = t(x) t(y), and adds
+// the three slice sums.  Iteration i covers RPI rows (row i*RPI + tid/N for
+// N < 256, row i otherwise); a thread touches the XV columns tid%N + 256 c.
+template <int N, int R, bool IM, bool TILE>
+__device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const uint32_t* __restrict__ tile,
+                                            const TileGeom& g, const RowParam* __restrict__ rp,
+                                            const float* __restrict__ trow, const float (&ku)[2][GatherCfg<N>::XV],
+                                            const swift_image& im, bool border, int tid,
+                                            const float (&tx)[GatherCfg<N>::XV], float& s1, float& s2, float& s3,
+                                            bool& cl) {
+  constexpr int RS = fwd_stride<N, R>();
+  constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+  const unsigned char* tb = (const unsigned char*)tile;
+  const int rowb = g.wt4 * 4;
+  const gptr<unsigned char> base = to_global<unsigned char>(im.data);
+  const int xt = tid % N;
+  float* st = (float*)stage + (IM ? 1 : 0);
+#pragma unroll 2
+  for (int i = 0; i < ITER; ++i) {
+    const int r = i * RPI + (RPI > 1 ? tid / N : 0);
+    const RowParam p = rp[r];
+    const float ty = trow[r];
+#pragma unroll
+    for (int c = 0; c < XV; ++c) {
+      const int x = xt + 256 * c;
+      const float xr = p.fx + ku[0][c], yr = p.fy + ku[1][c];
+      const float xf = floorf(xr), yf = floorf(yr);
+      const float fx = xr - xf, fy = yr - yf;
+      const int x0 = p.bx + (int)xf, y0 = p.by + (int)yf;
+      float i00, i10, i01, i11;
+      if constexpr (TILE) {
+        if (border) cl |= (x0 + g.xlo < 0) | (x0 + g.xlo > im.width - 2) | (y0 + g.ylo < 0) | (y0 + g.ylo > im.height - 2);
+        const int ix = min(max(x0, 0), rowb - 2), iy = min(max(y0, 0), g.ht - 2);
+        const unsigned char* q = tb + iy * rowb + ix;
+        i00 = (float)q[0];
+        i10 = (float)q[1];
+        i01 = (float)q[rowb];
+        i11 = (float)q[rowb + 1];
+      } else {
+        cl |= (x0 < 0) | (x0 > im.width - 2) | (y0 < 0) | (y0 > im.height - 2);
+        const int cx0 = min(max(x0, 0), im.width - 1), cx1 = min(max(x0 + 1, 0), im.width - 1);
+        const int cy0 = min(max(y0, 0), im.height - 1), cy1 = min(max(y0 + 1, 0), im.height - 1);
+        const gptr<unsigned char> r0 = base + (int64_t)cy0 * im.pitch;
+        const gptr<unsigned char> r1 = base + (int64_t)cy1 * im.pitch;
+        if (im.dtype == SWIFT_U8) {
+          i00 = (float)r0[cx0];
+          i10 = (float)r0[cx1];
+          i01 = (float)r1[cx0];
+          i11 = (float)r1[cx1];
+        } else {
+          i00 = ((gptr<float>)r0)[cx0];
+          i10 = ((gptr<float>)r0)[cx1];
+          i01 = ((gptr<float>)r1)[cx0];
+          i11 = ((gptr<float>)r1)[cx1];
+        }
+      }
+      // (1-fy)((1-fx) i00 + fx i10) + fy((1-fx) i01 + fx i11), in lerp form
+      const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
+      const float val = fmaf(fy, bot - top, top);
+      const float tap = tx[c] * ty;
+      const float at = (val - kSampleOffset) * tap;
+      s1 += at;
+      s2 = fmaf(at, at, s2);
+      s3 = fmaf(at, tap, s3);
+      st[2 * (r * RS + lidx(x))] = at;
+    }
+  }
+}
+
+template <int N, int BUDGET>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
-  constexpr int RS = lidx(N) + 1;
-  static_assert(R % G == 0, "rows per workgroup must be a multiple of transforms per workgroup");
+  constexpr int RS = fwd_stride<N, R>();
+  constexpr int XV = GatherCfg<N>::XV;
+  static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
+  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 : 1];
+  __shared__ RowParam rparam[2][R];
+  __shared__ float trow[R];
   __shared__ double red[4][6];
   __shared__ int redc[4];
 
@@ -90,70 +298,99 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   // image indices are clamped into the table so a bad index cannot read past it
   const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
   const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
-  swift_image ia = a.imgs[ka];
-  swift_image ib = a.imgs[kb];
-  ia.width = max(ia.width, 1);
-  ia.height = max(ia.height, 1);
-  ib.width = max(ib.width, 1);
-  ib.height = max(ib.height, 1);
-  const float* ta = a.th_a + 8 * (size_t)pair;
-  const float* tb = a.th_b + 8 * (size_t)pair;
-  const double acx = ta[0], acy = ta[1], a11 = ta[2], a12 = ta[3], atx = ta[4], a21 = ta[5], a22 = ta[6], aty = ta[7];
-  const double bcx = tb[0], bcy = tb[1], b11 = tb[2], b12 = tb[3], btx = tb[4], b21 = tb[5], b22 = tb[6], bty = tb[7];
-  const unsigned char* pa = (const unsigned char*)ia.data;
-  const unsigned char* pb = (const unsigned char*)ib.data;
-
-  float tx[E];
+  swift_image im[2] = {a.imgs[ka], a.imgs[kb]};
+  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  RowAffine ra[2];
+  TileGeom tg[2];
+  bool border[2];
 #pragma unroll
-  for (int e = 0; e < E; ++e) tx[e] = taper_at(t + e * T, N, a.L);
-
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int m = 0; m < 2; ++m) {
+    im[m].width = max(im[m].width, 2);
+    im[m].height = max(im[m].height, 2);
+    ra[m] = row_affine(th[m]);
+    tg[m] = tile_geom<N, R, BUDGET>(ra[m], im[m], y0);
+    // could any sample read outside the image?  (one pixel of slack for rounding)
+    border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
+                  tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
+  }
+  // all tile loads of both images in flight before anything waits on them
+  constexpr int MAXD = BUDGET > 0 ? (BUDGET / 4 + 255) / 256 : 1;
+  uint32_t bufA[MAXD], bufB[MAXD];
+  if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
+  if (tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
+  // per-row parameters (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
+  if (tid < 2 * R) {
+    const int m = tid / R, r = tid % R;
+    const double v = (double)(y0 + r - N / 2);
+    const double X = fmin(fmax(ra[m].xc + ra[m].a12 * v, -1e9), 1e9);
+    const double Y = fmin(fmax(ra[m].yc + ra[m].a22 * v, -1e9), 1e9);
+    const double bxd = floor(X), byd = floor(Y);
+    RowParam p;
+    p.bx = (int)bxd - (tg[m].use ? tg[m].xlo : 0);
+    p.by = (int)byd - (tg[m].use ? tg[m].ylo : 0);
+    p.fx = (float)(X - bxd);
+    p.fy = (float)(Y - byd);
+    rparam[m][r] = p;
+  } else if (tid >= 64 && tid < 64 + R) {
+    trow[tid - 64] = taper_at(y0 + tid - 64, N, a.L);
+  }
+  float tx[XV], ku[2][2][XV];
+#pragma unroll
+  for (int c = 0; c < XV; ++c) {
+    const int x = tid % N + 256 * c;
+    const float u = (float)(x - N / 2);
+    tx[c] = taper_at(x, N, a.L);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      ku[m][0][c] = ra[m].f11 * u;
+      ku[m][1][c] = ra[m].f21 * u;
+    }
+  }
+  float s[6] = {0, 0, 0, 0, 0, 0};
   bool clamped = false;
 
+  __syncthreads();  // row parameters visible
+  if (tg[0].use) {
+    tile_store(tile, bufA, tg[0], im[0], tid);
+    __syncthreads();
+    gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tid, tx, s[0],
+                                   s[1], s[2], clamped);
+  } else {
+    gather_rows<N, R, false, false>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tid, tx, s[0], s[1],
+                                    s[2], clamped);
+  }
+  if (tg[1].use) {
+    __syncthreads();  // tile of A fully consumed
+    tile_store(tile, bufB, tg[1], im[1], tid);
+    __syncthreads();
+    gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tid, tx, s[3],
+                                  s[4], s[5], clamped);
+  } else {
+    gather_rows<N, R, true, false>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tid, tx, s[3], s[4],
+                                   s[5], clamped);
+  }
+  __syncthreads();
+
+  // row FFTs in place: transform g of iteration it owns stage row g + it*G
+  Twiddles<N> tw;
+  tw_load<N>(tw, t, a.tw);
 #pragma unroll 1
   for (int it = 0; it < R / G; ++it) {
-    const int r = g + it * G;
-    const int y = y0 + r;
-    const float ty = taper_at(y, N, a.L);
-    const double v = (double)(y - N / 2);
-    const double axr = acx + atx + a12 * v, ayr = acy + aty + a22 * v;
-    const double bxr = bcx + btx + b12 * v, byr = bcy + bty + b22 * v;
+    float2* row = stage + (g + it * G) * RS;
     float2 d[E];
-    float s[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const double u = (double)(t + e * T - N / 2);
-      float av, bv;
-      if (ia.dtype == SWIFT_U8)
-        av = bilinear<unsigned char>(pa, ia.pitch, ia.width, ia.height, axr + a11 * u, ayr + a21 * u, clamped);
-      else
-        av = bilinear<float>(pa, ia.pitch, ia.width, ia.height, axr + a11 * u, ayr + a21 * u, clamped);
-      if (ib.dtype == SWIFT_U8)
-        bv = bilinear<unsigned char>(pb, ib.pitch, ib.width, ib.height, bxr + b11 * u, byr + b21 * u, clamped);
-      else
-        bv = bilinear<float>(pb, ib.pitch, ib.width, ib.height, bxr + b11 * u, byr + b21 * u, clamped);
-      const float tap = tx[e] * ty;
-      const float at = (av - kSampleOffset) * tap, bt = (bv - kSampleOffset) * tap;
-      s[0] += at;
-      s[1] += at * at;
-      s[2] += at * tap;
-      s[3] += bt;
-      s[4] += bt * bt;
-      s[5] += bt * tap;
-      d[e] = make_float2(at, bt);
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) acc[i] += (double)s[i];
-    float2* row = stage + r * RS;
-    fft_wave<N, false>(d, row, t, a.tw);
+    for (int e = 0; e < E; ++e) d[e] = row[lidx(t + e * T)];
+    wave_lds_sync();
+    fft_wave<N, false>(d, row, t, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = d[e];
   }
 
   // slice sums
   const int wv = tid >> 6, ln = tid & 63;
+  double acc[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[i] = wave_sum(acc[i]);
+  for (int i = 0; i < 6; ++i) acc[i] = wave_sum((double)s[i]);
   const int anyc = __any(clamped) ? 1 : 0;
   if (ln == 0) {
 #pragma unroll
@@ -230,12 +467,17 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
   float2* Zp = a.Z + (size_t)pair * N * N;
   float2* slot = lds + c * SL;
   float2 v[E];
+  Twiddles<N> tw;
+  tw_load<N>(tw, t, a.tw);
 
+  float2 tau[E];
   if (valid) {
     const float2* src = Zp + (size_t)col * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
-    fft_wave<N, false>(v, slot, t, a.tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) tau[e] = a.tau[t + e * T];
+    fft_wave<N, false>(v, slot, t, tw);
     if (which == 1) {
 #pragma unroll
       for (int e = 0; e < E; ++e) slot[lidx(t + e * T)] = v[e];
@@ -259,7 +501,7 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
       float2 fa = cscale(cadd(zp, zm), 0.5f);
       const float2 dd = csub(zp, zm);
       float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
-      const float2 tk = cmul(a.tau[ky], tauw);
+      const float2 tk = cmul(tau[e], tauw);
       fa = csub(fa, cscale(tk, ps.mA));
       fb = csub(fb, cscale(tk, ps.mB));
       // X = conj(F_A) F_B, C = X (|X|^2 + eps^2)^(-p/2) / N^2
@@ -268,13 +510,13 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
       float gs;
       if (p == 0.0f) gs = 1.0f;
       else if (!(d > 0.0f)) gs = 0.0f;
-      else if (p == 1.0f) gs = rsqrtf(d);
-      else gs = exp2f(hp * log2f(d));
+      else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
+      else gs = __builtin_amdgcn_exp2f(hp * __builtin_amdgcn_logf(d));
       gs *= inv_m;
       if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
       v[e] = cscale(X, gs);
     }
-    fft_wave<N, true>(v, slot, t, a.tw);
+    fft_wave<N, true>(v, slot, t, tw);
     float2* dst = Zp + (size_t)w * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
@@ -297,9 +539,19 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   const float2* Zp = a.Z + (size_t)pair * N * N;
 
-  for (int idx = tid; idx < NH * R2; idx += 256) {
-    const int r = idx % R2, kx = idx / R2;
-    stage[r * RS2 + kx] = Zp[(size_t)kx * N + y0 + r];
+  {
+    constexpr int LD = (NH * R2 + 255) / 256;
+    float2 buf[LD];
+#pragma unroll
+    for (int k = 0; k < LD; ++k) {
+      const int idx = min(tid + 256 * k, NH * R2 - 1);  // branch-free: keeps all loads in flight
+      buf[k] = Zp[(size_t)(idx / R2) * N + y0 + idx % R2];
+    }
+#pragma unroll
+    for (int k = 0; k < LD; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < NH * R2) stage[(idx % R2) * RS2 + idx / R2] = buf[k];
+    }
   }
   __syncthreads();
 
@@ -309,6 +561,8 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   tp.m2 = -FLT_MAX;
   double sum = 0.0, sq = 0.0;
   float* surf = a.surfaces ? a.surfaces + (size_t)pair * N * N : nullptr;
+  Twiddles<N> tw;
+  tw_load<N>(tw, t, a.tw);
 
 #pragma unroll 1
   for (int it = 0; it < (NT + G - 1) / G; ++it) {
@@ -331,19 +585,32 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
         v[e] = make_float2(g1.x - g2.y, g1.y + g2.x);
       }
       wave_lds_sync();
-      fft_wave<N, true>(v, r1, t, a.tw);
+      fft_wave<N, true>(v, r1, t, tw);
+      // each lane visits its flat indices in increasing order (row ya, then
+      // row yb; rows grow with the iteration), so a strict > keeps the first maximum
       const int ya = y0 + 2 * c, yb = ya + 1;
+      float ls = 0.0f, lq = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int x = t + e * T;
-        const float ca = v[e].x, cb = v[e].y;
-        top2_push(tp, ca, ya * N + x);
-        top2_push(tp, cb, yb * N + x);
-        sum += (double)ca + (double)cb;
-        sq += (double)ca * (double)ca + (double)cb * (double)cb;
-        if (surf) {
-          surf[(size_t)ya * N + x] = ca;
-          surf[(size_t)yb * N + x] = cb;
+        const float ca = v[e].x;
+        top2_push_ordered(tp, ca, ya * N + t + e * T);
+        ls += ca;
+        lq = fmaf(ca, ca, lq);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const float cb = v[e].y;
+        top2_push_ordered(tp, cb, yb * N + t + e * T);
+        ls += cb;
+        lq = fmaf(cb, cb, lq);
+      }
+      sum += (double)ls;
+      sq += (double)lq;
+      if (surf) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          surf[(size_t)ya * N + t + e * T] = v[e].x;
+          surf[(size_t)yb * N + t + e * T] = v[e].y;
         }
       }
     }
@@ -433,7 +700,7 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
         }
         v[e] = make_float2(g1.x - g2.y, g1.y + g2.x);
       }
-      fft_wave<N, true>(v, lds, ln, a.tw);
+      fft_wave_tab<N, true>(v, lds, ln, a.tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int x = ln + e * T;
@@ -504,7 +771,7 @@ static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer*
   const unsigned P = (unsigned)a.npairs;
   {
     TimerScope ts(kt, "k_row_fwd", N, s);
-    k_row_fwd<N><<<P * NSLICE, 256, 0, s>>>(a);
+    k_row_fwd<N, RowsCfg<N>::TILE><<<P * NSLICE, 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_pair_stats", N, s);

@@ -194,3 +194,30 @@ def test_pyramid_bit_exact(ctx, hw):
     got = ctx.pyramid(torch.from_numpy(img).to(dev()))
     torch.cuda.synchronize()
     np.testing.assert_array_equal(got.cpu().numpy(), O.pyramid(img))
+
+
+@pytest.mark.parametrize("n", [256, 512])
+@pytest.mark.parametrize("rot_deg", [0.4, 4.0])
+def test_rotated_windows_tile_and_direct_gather(ctx, section_pair_small, n, rot_deg):
+    """Small rotations gather through the LDS source tile, large ones straight
+    from global memory; both must match the oracle."""
+    print("case rotation n=%d rot=%g" % (n, rot_deg), flush=True)
+    a, b = section_pair_small
+    k = 3
+    th = np.zeros((k, 8), np.float32)
+    for i in range(k):
+        ang = math.radians(rot_deg * (1 if i % 2 == 0 else -1))
+        th[i] = [700 + 60 * i, 800 - 40 * i, math.cos(ang), -math.sin(ang), 0.37 * i, math.sin(ang),
+                 math.cos(ang), -0.21 * i]
+    thb = th.copy()
+    thb[:, 2:4] = [1, 0]
+    thb[:, 5:7] = [0, 1]
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(th), torch.from_numpy(thb),
+                          _params(0.65), surfaces=True)
+    torch.cuda.synchronize()
+    surf = res["surfaces"].view(k, n, n).cpu().numpy()
+    for i in range(k):
+        r = O.match_pair(a.numpy(), b.numpy(), th[i].astype(np.float64), thb[i].astype(np.float64), n,
+                         O.Params(p=0.65), return_surface=True)
+        compare(gpu_record(res, i), r, n, surf[i], "rot n=%d i=%d" % (n, i))
