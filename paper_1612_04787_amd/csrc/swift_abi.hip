@@ -121,7 +121,8 @@ struct Layout {
   size_t total = 0;
 };
 
-constexpr size_t kTaperSlot = 1024 * sizeof(float2) + 256;
+// Per window size: tau[1024] float2, taper[1024] float, TaperInfo.
+constexpr size_t kTaperSlot = 1024 * sizeof(float2) + 1024 * sizeof(float) + 256;
 
 size_t nslice(int n) {
   switch (n) {
@@ -280,8 +281,9 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     const GroupLayout& g = L.g[i];
     if (g.count == 0) continue;
     float2* tau = (float2*)(base + L.taper + i * kTaperSlot);
-    TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
-    hipError_t e = launch_taper(g.n, params->taper_frac, tau, tinfo, stream);
+    float* taper = (float*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
+    TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2) + 1024 * sizeof(float));
+    hipError_t e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, stream);
     if (e != hipSuccess) return hip_fail(e, "taper launch");
     MatchArgs a;
     a.imgs = imgs;
@@ -298,6 +300,7 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     a.invpart = (InvPart*)(base + g.invpart);
     a.tw = ctx->tw;
     a.tau = tau;
+    a.taper = taper;
     a.tinfo = tinfo;
     a.p = params->p;
     a.eps_rel = params->eps_rel;

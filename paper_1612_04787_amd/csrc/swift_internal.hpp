@@ -59,6 +59,7 @@ struct MatchArgs {
   InvPart* invpart;     // [P][NSL2]
   const float2* tw;     // W_1024 table
   const float2* tau;    // [N]
+  const float* taper;   // [N] t(i)
   const TaperInfo* tinfo;
   float p, eps_rel;
   int32_t L;            // taper samples per edge
@@ -66,15 +67,16 @@ struct MatchArgs {
   int32_t n_imgs;
 };
 
-// Rows per workgroup of the forward and inverse row passes, and the LDS budget
+// Rows per workgroup of the forward and inverse row passes; the LDS budget
 // (bytes) of one image's source tile in the forward pass (0: always gather
-// straight from global memory).
+// straight from global memory) and the tile shape limits of its fetch (at
+// most 4 TRW rows of 64 TMC dwords).
 template <int N> struct RowsCfg;
-template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096; };
-template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144; };
-template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216; };
-template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240; };
-template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0; };
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 10, TMC = 1; };
+template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 6,  TMC = 1; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 7,  TMC = 2; };
+template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,  TMC = 3; };
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,  TMC = 1; };
 
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 
@@ -90,7 +92,7 @@ struct KernelTimer {
 };
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, hipStream_t s);
+hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s);
 hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,

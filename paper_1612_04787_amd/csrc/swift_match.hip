@@ -31,10 +31,12 @@ namespace swift {
 // values the gather uses.  Since t = 1 outside the 2L edge samples,
 // tau[k] = N [k == 0] - sum_{edge i} (1 - t(i)) exp(-2 pi i k i / N).
 // Block 0 also writes sum t and sum t^2.
-__global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict__ tau, TaperInfo* info) {
+__global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict__ tau, float* __restrict__ taper,
+                                               TaperInfo* info) {
   __shared__ double red[2][4];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
+    taper[k] = taper_at(k, n, L);
     double re = (k == 0) ? (double)n : 0.0, im = 0.0;
     const int Le = min(L, n / 2);
     for (int q = 0; q < 2 * Le; ++q) {
@@ -127,60 +129,58 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.ylo = yl;
   g.wt4 = (xh - g.xlo + 4) / 4;
   g.ht = yh - yl + 1;
-  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET;
+  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET && g.ht <= 4 * RowsCfg<N>::TRW && g.wt4 <= 64 * RowsCfg<N>::TMC;
   return g;
 }
 
 // Tile dwords are fetched in two steps so all loads are in flight at once:
-// tile_fetch issues every global load of a thread into registers (dword k of
-// the thread is tile element tid + 256 k) and nothing consumes them until
-// tile_store writes them to LDS.  Border dwords are read at the nearest
-// in-image aligned dword; tile_store re-selects their bytes with v_perm so
-// that byte i holds img[y][clamp(x + i)].
-struct TileIdx {
-  int yy, xx, xc;
-};
-
-__device__ __forceinline__ TileIdx tile_idx(const TileGeom& g, const swift_image& im, int idx, float rcp) {
-  TileIdx r;
-  // idx / wt4 exactly: the quotient's fraction stays >= 0.5/wt4 from an integer
-  const int ty = (int)(((float)idx + 0.5f) * rcp);
-  const int tx4 = idx - ty * g.wt4;
-  r.yy = min(max(g.ylo + ty, 0), im.height - 1);
-  r.xx = g.xlo + 4 * tx4;
-  r.xc = min(max(r.xx, 0), im.width - 4);
-  return r;
-}
-
-template <int MAXD>
-__device__ __forceinline__ void tile_fetch(uint32_t (&buf)[MAXD], const TileGeom& g, const swift_image& im,
+// tile_fetch issues every global load of a thread into registers and nothing
+// consumes them until tile_store writes them to LDS.  Wave w fetches tile rows
+// w + 4 j, lane l dword columns l + 64 c.  Loads are unconditional (coordinates
+// clamped into the image, so every load is in bounds; a branch between a load
+// and its use would make the compiler drain the load queue); only in-range
+// elements are stored.  Border dwords are read at the nearest in-image
+// aligned dword and, on workgroups whose tile crosses the image border, their
+// bytes re-selected with v_perm so that byte i holds img[y][clamp(x + i)].
+template <int RW, int MC>
+__device__ __forceinline__ void tile_fetch(uint32_t (&buf)[RW][MC], const TileGeom& g, const swift_image& im,
                                            int tid) {
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  const int total = g.wt4 * g.ht;
-  const float rcp = 1.0f / (float)g.wt4;
-  // Branch-free on purpose (a branch between a load and its use makes the
-  // compiler drain the load queue at the join).  Past the end, the last
-  // element is re-read and never stored.
+  const int wv = tid >> 6, ln = tid & 63;
+  int xc[MC];
 #pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    const TileIdx t = tile_idx(g, im, min(tid + 256 * k, total - 1), rcp);
-    buf[k] = *(gptr<uint32_t>)(base + (int64_t)t.yy * im.pitch + t.xc);
+  for (int c = 0; c < MC; ++c) xc[c] = min(max(g.xlo + 4 * (ln + 64 * c), 0), im.width - 4);
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const int yy = min(max(g.ylo + wv + 4 * j, 0), im.height - 1);
+    const gptr<unsigned char> row = base + (int64_t)yy * im.pitch;
+#pragma unroll
+    for (int c = 0; c < MC; ++c) buf[j][c] = *(gptr<uint32_t>)(row + xc[c]);
   }
 }
 
-template <int MAXD>
-__device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint32_t (&buf)[MAXD],
-                                           const TileGeom& g, const swift_image& im, int tid) {
-  const int total = g.wt4 * g.ht;
-  const float rcp = 1.0f / (float)g.wt4;
+template <int RW, int MC>
+__device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint32_t (&buf)[RW][MC],
+                                           const TileGeom& g, const swift_image& im, bool border, int tid) {
+  const int wv = tid >> 6, ln = tid & 63;
+  uint32_t sel[MC];
 #pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    const int idx = tid + 256 * k;
-    const TileIdx t = tile_idx(g, im, min(idx, total - 1), rcp);
-    uint32_t sel = 0;
+  for (int c = 0; c < MC; ++c) {
+    const int xx = g.xlo + 4 * (ln + 64 * c);
+    const int xc = min(max(xx, 0), im.width - 4);
+    sel[c] = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) sel |= (uint32_t)(min(max(t.xx + b, 0), im.width - 1) - t.xc) << (8 * b);
-    if (idx < total) tile[idx] = __builtin_amdgcn_perm(buf[k], buf[k], sel);
+    for (int b = 0; b < 4; ++b) sel[c] |= (uint32_t)(min(max(xx + b, 0), im.width - 1) - xc) << (8 * b);
+  }
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const int ty = wv + 4 * j;
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      const int tx4 = ln + 64 * c;
+      if (ty < g.ht && tx4 < g.wt4)
+        tile[ty * g.wt4 + tx4] = border ? __builtin_amdgcn_perm(buf[j][c], buf[j][c], sel[c]) : buf[j][c];
+    }
   }
 }
 
@@ -278,6 +278,10 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
   }
 }
 
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, full = per << 3;
+  return b >= full ? b : (b & 7) * per + (b >> 3);
+}
 template <int N, int BUDGET>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
@@ -292,7 +296,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   __shared__ double red[4][6];
   __shared__ int redc[4];
 
-  const int pair = blockIdx.x / NSLICE, slice = blockIdx.x % NSLICE, y0 = slice * R;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
 
   // image indices are clamped into the table so a bad index cannot read past it
@@ -314,8 +319,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
   }
   // all tile loads of both images in flight before anything waits on them
-  constexpr int MAXD = BUDGET > 0 ? (BUDGET / 4 + 255) / 256 : 1;
-  uint32_t bufA[MAXD], bufB[MAXD];
+  constexpr int TRW = RowsCfg<N>::TRW, TMC = RowsCfg<N>::TMC;
+  uint32_t bufA[TRW][TMC], bufB[TRW][TMC];
   if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
   if (tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
   // per-row parameters (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
@@ -332,14 +337,14 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     p.fy = (float)(Y - byd);
     rparam[m][r] = p;
   } else if (tid >= 64 && tid < 64 + R) {
-    trow[tid - 64] = taper_at(y0 + tid - 64, N, a.L);
+    trow[tid - 64] = a.taper[y0 + tid - 64];
   }
   float tx[XV], ku[2][2][XV];
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     const int x = tid % N + 256 * c;
     const float u = (float)(x - N / 2);
-    tx[c] = taper_at(x, N, a.L);
+    tx[c] = a.taper[x];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       ku[m][0][c] = ra[m].f11 * u;
@@ -351,7 +356,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
 
   __syncthreads();  // row parameters visible
   if (tg[0].use) {
-    tile_store(tile, bufA, tg[0], im[0], tid);
+    tile_store(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tid, tx, s[0],
                                    s[1], s[2], clamped);
@@ -361,7 +366,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
   if (tg[1].use) {
     __syncthreads();  // tile of A fully consumed
-    tile_store(tile, bufB, tg[1], im[1], tid);
+    tile_store(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tid, tx, s[3],
                                   s[4], s[5], clamped);
@@ -390,7 +395,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   const int wv = tid >> 6, ln = tid & 63;
   double acc[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[i] = wave_sum((double)s[i]);
+  for (int i = 0; i < 6; ++i) acc[i] = (double)wave_sum_f32(s[i]);
   const int anyc = __any(clamped) ? 1 : 0;
   if (ln == 0) {
 #pragma unroll
@@ -746,9 +751,9 @@ size_t pair_ws_bytes(int n) {
   return 0;
 }
 
-hipError_t launch_taper(int n, float taper_frac, float2* tau, TaperInfo* info, hipStream_t s) {
+hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s) {
   const int L = (int)floor((double)taper_frac * n / 2.0 + 0.5);
-  k_taper<<<(n + 255) / 256, 256, 0, s>>>(n, L, tau, info);
+  k_taper<<<(n + 255) / 256, 256, 0, s>>>(n, L, tau, taper, info);
   return hipGetLastError();
 }
 
