@@ -7,6 +7,8 @@ from .swift import (  # noqa: F401
     SIZES,
     Swift,
     SwiftError,
+    SwiftMatchFn,
+    theta6_to_theta8,
     load_library,
     make_params,
     parse_records,

@@ -107,18 +107,24 @@ struct DeviceGuard {
   }
 };
 
-// Workspace layout of one swift_match_batch call.
+// Workspace and saved-state layout of one batch.  The forward and the
+// adjoint use the same workspace; its size is the larger of the two.
 struct GroupLayout {
   int n = 0;
   int count = 0;
   int first = 0;  // index of the group's first pair
-  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, end = 0;
+  // forward
+  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0;
+  // adjoint
+  size_t y = 0, dpart = 0, rpart = 0;
+  // saved state (offsets into the saved buffer)
+  size_t sz = 0, sps = 0, srec = 0;
 };
 
 struct Layout {
-  size_t taper = 0;  // SWIFT_NSIZES x (tau[1024] + TaperInfo)
+  size_t taper = 0;  // SWIFT_NSIZES x (tau, taper, TaperInfo)
   GroupLayout g[SWIFT_NSIZES];
-  size_t total = 0;
+  size_t fwd = 0, bwd = 0, total = 0, saved = 0;
 };
 
 // Per window size: tau[1024] float2, taper[1024] float, TaperInfo.
@@ -142,12 +148,16 @@ size_t nslice2(int n) {
     default: return 1024 / RowsCfg<1024>::INV;
   }
 }
+size_t ncolwg(int n) {
+  const int ipw = col_items_per_wg(n);
+  return (size_t)((n / 2 + 1 + ipw - 1) / ipw);
+}
 
 Layout make_layout(const swift_pairs* pairs) {
   Layout L;
-  size_t off = 0;
-  L.taper = off;
-  off += align256(SWIFT_NSIZES * kTaperSlot);
+  const size_t base = align256(SWIFT_NSIZES * kTaperSlot);
+  L.taper = 0;
+  size_t fo = base, bo = base, so = 0;
   int first = 0;
   for (int i = 0; i < SWIFT_NSIZES; ++i) {
     GroupLayout& g = L.g[i];
@@ -157,17 +167,31 @@ Layout make_layout(const swift_pairs* pairs) {
     first += g.count;
     if (g.count == 0) continue;
     const size_t P = (size_t)g.count, n = (size_t)g.n;
-    g.z = off;
-    off += align256(P * n * n * sizeof(float2));
-    g.rowpart = off;
-    off += align256(P * nslice(g.n) * sizeof(RowPart));
-    g.pstat = off;
-    off += align256(P * sizeof(PairStat));
-    g.invpart = off;
-    off += align256(P * nslice2(g.n) * sizeof(InvPart));
-    g.end = off;
+    g.z = fo;
+    fo += align256(P * n * n * sizeof(float2));
+    g.rowpart = fo;
+    fo += align256(P * nslice(g.n) * sizeof(RowPart));
+    g.pstat = fo;
+    fo += align256(P * sizeof(PairStat));
+    g.invpart = fo;
+    fo += align256(P * nslice2(g.n) * sizeof(InvPart));
+    g.y = bo;
+    bo += align256(P * n * n * sizeof(float2));
+    g.dpart = bo;
+    bo += align256(P * ncolwg(g.n) * sizeof(double));
+    g.rpart = bo;
+    bo += align256(P * nslice(g.n) * 2 * kBwdSums * sizeof(double));
+    g.sz = so;
+    so += align256(P * n * n * sizeof(float2));
+    g.sps = so;
+    so += align256(P * sizeof(PairStat));
+    g.srec = so;
+    so += align256(P * sizeof(swift_match));
   }
-  L.total = off;
+  L.fwd = fo;
+  L.bwd = bo;
+  L.total = fo > bo ? fo : bo;
+  L.saved = so;
   return L;
 }
 
@@ -253,7 +277,7 @@ int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs, const swift_p
   if (rc) return rc;
   const Layout L = make_layout(pairs);
   *ws_bytes = L.total;
-  if (saved_bytes) *saved_bytes = 0;
+  if (saved_bytes) *saved_bytes = L.saved;
   return ok();
 }
 
@@ -268,7 +292,6 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   if (pairs->n_pairs == 0) return ok();
   if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
   if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
-  if (saved) return fail(SWIFT_E_UNSUPPORTED, "saved state for the adjoint is not produced by this entry point");
   const Layout L = make_layout(pairs);
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
@@ -306,6 +329,9 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     a.eps_rel = params->eps_rel;
     a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     a.npairs = g.count;
+    a.saved_Z = saved ? (float2*)((char*)saved + g.sz) : nullptr;
+    a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
+    a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     e = launch_match_group(g.n, a, stream, ctx->kt());
     if (e != hipSuccess) return hip_fail(e, "match launch");
     surf_off += (size_t)g.count * g.n * g.n;
@@ -316,10 +342,58 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
 int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
                          const swift_params* params, const void* saved, const float* g_peak, const float* g_snr,
                          float* g_theta_a, float* g_theta_b, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)imgs; (void)n_imgs; (void)pairs; (void)params; (void)saved; (void)g_peak; (void)g_snr;
-  (void)g_theta_a; (void)g_theta_b; (void)ws; (void)ws_bytes; (void)stream;
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
-  return fail(SWIFT_E_UNSUPPORTED, "swift_match_backward is not available in this build");
+  int rc = check_pairs(pairs);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  if (pairs->n_pairs == 0) return ok();
+  if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
+  if (!saved) return fail(SWIFT_E_INVAL, "saved is NULL (run swift_match_batch with a saved buffer first)");
+  if (!g_theta_a) return fail(SWIFT_E_INVAL, "g_theta_a is NULL");
+  const Layout L = make_layout(pairs);
+  if (!ws || ws_bytes < L.total)
+    return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  char* base = (char*)ws;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    const GroupLayout& g = L.g[i];
+    if (g.count == 0) continue;
+    float2* tau = (float2*)(base + L.taper + i * kTaperSlot);
+    float* taper = (float*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
+    TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2) + 1024 * sizeof(float));
+    hipError_t e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, stream);
+    if (e != hipSuccess) return hip_fail(e, "taper launch");
+    BwdArgs b;
+    b.imgs = imgs;
+    b.n_imgs = n_imgs;
+    b.img_a = pairs->img_a + g.first;
+    b.img_b = pairs->img_b + g.first;
+    b.th_a = pairs->theta_a + 8 * (size_t)g.first;
+    b.th_b = pairs->theta_b + 8 * (size_t)g.first;
+    b.Zf = (const float2*)((const char*)saved + g.sz);
+    b.ps = (const PairStat*)((const char*)saved + g.sps);
+    b.rec = (const swift_match*)((const char*)saved + g.srec);
+    b.g_peak = g_peak ? g_peak + g.first : nullptr;
+    b.g_snr = g_snr ? g_snr + g.first : nullptr;
+    b.g_th_a = g_theta_a + 6 * (size_t)g.first;
+    b.g_th_b = g_theta_b ? g_theta_b + 6 * (size_t)g.first : nullptr;
+    b.Y = (float2*)(base + g.y);
+    b.dpart = (double*)(base + g.dpart);
+    b.rpart = (double*)(base + g.rpart);
+    b.tw = ctx->tw;
+    b.tau = tau;
+    b.taper = taper;
+    b.tinfo = tinfo;
+    b.p = params->p;
+    b.eps_rel = params->eps_rel;
+    b.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
+    b.npairs = g.count;
+    e = launch_backward_group(g.n, b, stream, ctx->kt());
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+  }
+  return ok();
 }
 
 int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width, int64_t pitch,

@@ -27,6 +27,7 @@ struct PairStat {
   float mA, mB;   // taper-weighted means of the offset samples
   float eps2;     // eps_rel^2 * ||w_A||^2 * ||w_B||^2
   int32_t flags;  // bit 0: degenerate (a window is constant); bit 2: clamped
+  float swA, swB; // ||w_A||^2, ||w_B||^2
 };
 
 // Per row-slice partials of the inverse row pass.
@@ -65,7 +66,39 @@ struct MatchArgs {
   int32_t L;            // taper samples per edge
   int32_t npairs;
   int32_t n_imgs;
+  // state kept for the adjoint (all NULL when not requested)
+  float2* saved_Z;         // [P][N][N]: forward 2-D spectrum of z, [kx][ky]
+  PairStat* saved_ps;      // [P]
+  swift_match* saved_rec;  // [P]
 };
+
+// Arguments of the adjoint kernels of one window size.
+struct BwdArgs {
+  const swift_image* imgs;
+  const int32_t* img_a;
+  const int32_t* img_b;
+  const float* th_a;
+  const float* th_b;
+  const float2* Zf;         // saved forward spectrum [P][kx][ky]
+  const PairStat* ps;       // saved
+  const swift_match* rec;   // saved
+  const float* g_peak;      // [P] or NULL
+  const float* g_snr;       // [P] or NULL
+  float* g_th_a;            // [P][6]
+  float* g_th_b;            // [P][6] or NULL
+  float2* Y;                // [P][kx][y] inverse-column output
+  double* dpart;            // [P][NW] partial dJ/d(eps^2)
+  double* rpart;            // [P][NSLICE][40] partial pixel sums
+  const float2* tw;
+  const float2* tau;
+  const float* taper;
+  const TaperInfo* tinfo;
+  float p, eps_rel;
+  int32_t L;
+  int32_t npairs;
+  int32_t n_imgs;
+};
+constexpr int kBwdSums = 20;  // per image: P1[6], P2[6], P3[6], Q, R
 
 // Rows per workgroup of the forward and inverse row passes; the LDS budget
 // (bytes) of one image's source tile in the forward pass (0: always gather
@@ -94,6 +127,8 @@ struct KernelTimer {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s);
 hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
+hipError_t launch_backward_group(int n, const BwdArgs& a, hipStream_t s, KernelTimer* kt);
+int col_items_per_wg(int n);  // column-pass workgroups per pair
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* exclude, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,

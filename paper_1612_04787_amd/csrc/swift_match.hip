@@ -446,12 +446,15 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
     PairStat ps;
     ps.mA = (float)mA;
     ps.mB = (float)mB;
+    ps.swA = (float)fmax(wA, 0.0);
+    ps.swB = (float)fmax(wB, 0.0);
     ps.flags = (cl ? 4 : 0);
     // a window whose weighted variance vanishes to rounding is constant
     if (!(wA > 1e-6 * s[1]) || !(wB > 1e-6 * s[4])) ps.flags |= 1;
     const double e2 = (double)a.eps_rel * (double)a.eps_rel * fmax(wA, 0.0) * fmax(wB, 0.0);
     ps.eps2 = (float)e2;
     a.pstat[pair] = ps;
+    if (a.saved_ps) a.saved_ps[pair] = ps;
   }
 }
 
@@ -483,6 +486,11 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) tau[e] = a.tau[t + e * T];
     fft_wave<N, false>(v, slot, t, tw);
+    if (a.saved_Z && (which == 0 || (col != w))) {
+      float2* sz = a.saved_Z + (size_t)pair * N * N + (size_t)col * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) sz[t + e * T] = v[e];
+    }
     if (which == 1) {
 #pragma unroll
       for (int e = 0; e < E; ++e) slot[lidx(t + e * T)] = v[e];
@@ -727,7 +735,9 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
 
   if (ln == 0) {
     const PairStat ps = a.pstat[pair];
-    a.out[pair] = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0);
+    const swift_match rec = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0);
+    a.out[pair] = rec;
+    if (a.saved_rec) a.saved_rec[pair] = rec;
   }
 }
 
@@ -796,6 +806,8 @@ static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   return hipGetLastError();
 }
+
+int col_items_per_wg(int n) { return (256 / (n <= 512 ? n / 8 : 64)) / 2; }
 
 hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
   switch (n) {

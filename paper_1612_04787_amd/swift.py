@@ -192,38 +192,73 @@ class Swift:
         return ws.value, sv.value
 
     # ------------------------------------------------------------------ entry points
-    def match_batch_raw(self, table, n_imgs, pairs, params, out, surfaces=None, ws=None):
+    def match_batch_raw(self, table, n_imgs, pairs, params, out, surfaces=None, ws=None, saved=None):
         need, _ = self.workspace_size(pairs, params)
         if ws is None:
             ws = self.workspace(need)
         _check(self.lib.swift_match_batch(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
-                                          _ptr(out), _ptr(surfaces), C.c_void_p(0), _ptr(ws), ws.numel(),
+                                          _ptr(out), _ptr(surfaces), _ptr(saved), _ptr(ws), ws.numel(),
                                           self.stream()))
 
-    def match_batch(self, images, n_list, img_a, img_b, theta_a, theta_b, params=None, surfaces=False):
-        """Whitened FFT matching of window pairs.  images: list of device
-        tensors; n_list: host list of window edges (sorted); img_a/img_b: int32
-        device [P]; theta_a/theta_b: float32 device [P, 8].  Returns a dict of
-        device tensors (dx, dy, ix, iy, peak, snr, mean, std, status, n) and,
-        with surfaces=True, 'surfaces' as a flat float32 tensor."""
-        params = params or make_params()
+    def match_backward_raw(self, table, n_imgs, pairs, params, saved, g_peak, g_snr, g_theta_a, g_theta_b=None,
+                           ws=None):
+        need, _ = self.workspace_size(pairs, params)
+        if ws is None:
+            ws = self.workspace(need)
+        _check(self.lib.swift_match_backward(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
+                                             _ptr(saved), _ptr(g_peak), _ptr(g_snr), _ptr(g_theta_a),
+                                             _ptr(g_theta_b), _ptr(ws), ws.numel(), self.stream()))
+
+    def prepare(self, images, n_list, img_a, img_b, theta_a, theta_b):
+        """Device image table and pair descriptor (tensors kept alive in the dict)."""
         table = self.image_table(images)
         img_a = img_a.to(self.device, torch.int32).contiguous()
         img_b = img_b.to(self.device, torch.int32).contiguous()
         theta_a = theta_a.to(self.device, torch.float32).contiguous()
         theta_b = theta_b.to(self.device, torch.float32).contiguous()
         pr = self.make_pairs(n_list, img_a, img_b, theta_a, theta_b)
+        return dict(table=table, n_imgs=len(images), pairs=pr, keep=(img_a, img_b, theta_a, theta_b))
+
+    def match_batch(self, images, n_list, img_a, img_b, theta_a, theta_b, params=None, surfaces=False, save=False):
+        """Whitened FFT matching of window pairs.  images: list of device
+        tensors; n_list: host list of window edges (sorted); img_a/img_b: int32
+        device [P]; theta_a/theta_b: float32 device [P, 8].  Returns a dict of
+        device tensors (dx, dy, ix, iy, peak, snr, mean, std, status, n) and,
+        with surfaces=True, 'surfaces' as a flat float32 tensor; with save=True,
+        'saved' (state for match_backward) and 'prep'."""
+        params = params or make_params()
+        prep = self.prepare(images, n_list, img_a, img_b, theta_a, theta_b)
+        pr = prep["pairs"]
         P = pr.n_pairs
         out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=self.device)
         surf = None
         if surfaces:
             surf = torch.empty(sum(int(n) * int(n) for n in n_list), dtype=torch.float32, device=self.device)
-        self.match_batch_raw(table, len(images), pr, params, out, surf)
+        saved = None
+        if save:
+            _, sv = self.workspace_size(pr, params)
+            saved = torch.empty(max(sv, 256), dtype=torch.uint8, device=self.device)
+        self.match_batch_raw(prep["table"], prep["n_imgs"], pr, params, out, surf, saved=saved)
         res = parse_records(out)
         res["raw"] = out
         if surfaces:
             res["surfaces"] = surf
+        if save:
+            res["saved"] = saved
+            res["prep"] = prep
         return res
+
+    def match_backward(self, fwd, params, g_peak=None, g_snr=None, want_b=True):
+        """Gradients [P, 6] (a11, a12, tx, a21, a22, ty) of sum(g_peak*peak +
+        g_snr*snr) for windows A (and B) of a forward run made with save=True."""
+        prep = fwd["prep"]
+        P = prep["pairs"].n_pairs
+        ga = torch.empty((P, 6), dtype=torch.float32, device=self.device)
+        gb = torch.empty((P, 6), dtype=torch.float32, device=self.device) if want_b else None
+        gp = g_peak.to(self.device, torch.float32).contiguous() if g_peak is not None else None
+        gs = g_snr.to(self.device, torch.float32).contiguous() if g_snr is not None else None
+        self.match_backward_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, fwd["saved"], gp, gs, ga, gb)
+        return ga, gb
 
     def project(self, stack, k=3, exclude=None, out=None):
         """Z-projection models of every section of a [S, H, W] uint8 device stack."""
@@ -255,3 +290,27 @@ class Swift:
         out = torch.empty((B, REC_BYTES), dtype=torch.uint8, device=self.device)
         _check(self.lib.swift_snr(self.h, _ptr(surfaces), n, B, C.byref(params), _ptr(out), self.stream()))
         return parse_records(out)
+
+
+def theta6_to_theta8(g6):
+    """Gradient with respect to (a11, a12, tx, a21, a22, ty) -> with respect to
+    the 8-entry window parameter (cx, cy, a11, a12, tx, a21, a22, ty); the
+    centre enters the sample position exactly like the translation."""
+    return torch.stack([g6[:, 2], g6[:, 5], g6[:, 0], g6[:, 1], g6[:, 2], g6[:, 3], g6[:, 4], g6[:, 5]], dim=1)
+
+
+class SwiftMatchFn(torch.autograd.Function):
+    """(peak, snr) of whitened window matches as a differentiable function of
+    the window parameters theta_a, theta_b [P, 8]; the backward runs the
+    library's adjoint kernels (the integer peak is held fixed)."""
+
+    @staticmethod
+    def forward(fctx, theta_a, theta_b, sw, images, n_list, img_a, img_b, params):
+        res = sw.match_batch(images, n_list, img_a, img_b, theta_a.detach(), theta_b.detach(), params, save=True)
+        fctx.sw, fctx.res, fctx.params = sw, res, params
+        return res["peak"].clone(), res["snr"].clone()
+
+    @staticmethod
+    def backward(fctx, g_peak, g_snr):
+        ga, gb = fctx.sw.match_backward(fctx.res, fctx.params, g_peak, g_snr, want_b=True)
+        return theta6_to_theta8(ga), theta6_to_theta8(gb), None, None, None, None, None, None
