@@ -100,7 +100,7 @@ typedef struct {
   int32_t reserved;
 } swift_params;
 
-/* One match record (48 bytes). */
+/* One match record (64 bytes). */
 typedef struct {
   float dx, dy;      /* sub-pixel shift: wrapped integer peak + 3x3 centroid   */
   int32_t ix, iy;    /* integer peak index in the n x n surface (first maximum) */
@@ -109,6 +109,9 @@ typedef struct {
   double mean, std;  /* surface mean and population std (FP64 reduction)        */
   int32_t status;    /* SWIFT_ST_* bits                                         */
   int32_t n;         /* window edge of this pair                                */
+  float hxx, hyy;    /* surface curvature at the peak: second differences in x, y */
+  float hxy;         /* and the mixed difference (c11 - c1-1 - c-11 + c-1-1) / 4  */
+  int32_t reserved;
 } swift_match;
 
 /* Context: owns the device twiddle table of one GPU.  Allocates (once). */
@@ -146,11 +149,15 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
  * entries (a11, a12, tx, a21, a22, ty) of every window, the integer peak held
  * fixed.  Inputs and params must be those of the forward call that filled
  * `saved`.  g_peak / g_snr: device [P] or NULL (= 0).  g_theta_a: device [P][6];
- * g_theta_b: device [P][6] or NULL.  ws as for the forward call. */
+ * g_theta_b: device [P][6] or NULL.  peak_hess: device [P][3] or NULL, receives
+ * the Hessian (d2c/dx2, d2c/dy2, d2c/dxdy) of the surface's trigonometric
+ * interpolant at the integer peak, sum_k C(k) (2 pi i k/n)^2 e^{2 pi i k.s/n} / n^2
+ * over signed frequencies (the Nyquist frequency contributes (n/2)^2 to the
+ * pure terms and nothing to the mixed one).  ws as for the forward call. */
 int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
                          const swift_pairs* pairs, const swift_params* params,
                          const void* saved, const float* g_peak, const float* g_snr,
-                         float* g_theta_a, float* g_theta_b, void* ws,
+                         float* g_theta_a, float* g_theta_b, float* peak_hess, void* ws,
                          size_t ws_bytes, hipStream_t stream);
 
 /* Z-projection "model" of every section of a stack (Section III, model
@@ -182,6 +189,38 @@ int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst
  *  surfaces  device [batch][n][n] float; out device [batch]. */
 int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch,
               const swift_params* params, swift_match* out, hipStream_t stream);
+
+/* Jacobian of the centroid shift (not in the paper; for the Newton refinement
+ * below): jac [P][2][6] receives d(dx)/d theta_A and d(dy)/d theta_A, the
+ * six affine entries (a11, a12, tx, a21, a22, ty) of window A, with the integer
+ * peak and the set of positive centroid weights (3x3 box, weight = c - mean)
+ * held fixed.  One adjoint pass: the two objectives share one packed inverse
+ * 2-D FFT.  A pair whose record is degenerate, or whose box has no positive
+ * weight, gets zeros.  Inputs, params and `saved` as for swift_match_backward;
+ * jac is device memory.  Errors as for swift_match_backward. */
+int swift_centroid_jacobian(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
+                            const swift_pairs* pairs, const swift_params* params,
+                            const void* saved, float* jac, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* One step of iterative window refinement (Section IV: matching is iterated
+ * until the scores stabilise), applied in place to the window-A parameters
+ * theta [P][8] on the device, one thread per pair:
+ *  mode SWIFT_REFINE_CENTROID: t <- t - d with d = (dx, dy), the record's
+ *    sub-pixel shift;
+ *  mode SWIFT_REFINE_NEWTON: Newton's method on d(t) = 0.  If the integer peak
+ *    is at the origin, the record is not degenerate and det J > 1e-6 for
+ *    J = [[jac[2], jac[5]], [jac[8], jac[11]]] (d d / d (tx, ty) from
+ *    swift_centroid_jacobian), t <- t - J^-1 d; otherwise the centroid step.
+ * Steps longer than max_step pixels are scaled down to max_step (> 0).
+ * step_out: device [P] receives the length of each applied step (may be NULL).
+ * recs, jac: device, as produced for the same pairs; jac may be NULL in
+ * centroid mode. */
+#define SWIFT_REFINE_CENTROID 0
+#define SWIFT_REFINE_NEWTON   1
+int swift_refine_update(swift_ctx* ctx, int32_t P, const swift_match* recs, const float* jac,
+                        float* theta, int32_t mode, float max_step, float* step_out,
+                        hipStream_t stream);
 
 /* Kernel timing (instrumentation, not in the paper).  While enabled, every
  * kernel the context launches is bracketed by a pair of HIP events recorded on

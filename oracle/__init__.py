@@ -17,4 +17,7 @@ from .swift_oracle import (  # noqa: F401
     project,
     pyramid,
     fit_affine,
+    refine_step,
+    centroid_jacobian,
+    surface_hessian,
 )

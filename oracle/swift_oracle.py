@@ -184,8 +184,77 @@ def peak_stats(c, centroid_r=1):
             swy += wv * dyy
     dx = sx + (swx / sw if sw > 0 else 0.0)
     dy = sy + (swy / sw if sw > 0 else 0.0)
+
+    def cv(ddx, ddy):
+        return float(c[(iy + ddy) % n, (ix + ddx) % n])
+
+    # curvature of the surface at the integer peak (central second differences)
+    hxx = cv(1, 0) - 2 * peak + cv(-1, 0)
+    hyy = cv(0, 1) - 2 * peak + cv(0, -1)
+    hxy = 0.25 * (cv(1, 1) - cv(1, -1) - cv(-1, 1) + cv(-1, -1))
     return dict(ix=ix, iy=iy, sx=sx, sy=sy, dx=dx, dy=dy, peak=peak, mean=mu,
-                std=sd, snr=snr, status=status, second=second)
+                std=sd, snr=snr, status=status, second=second, hxx=hxx, hyy=hyy, hxy=hxy)
+
+
+def surface_hessian(c, iy, ix):
+    """Hessian (d2/dx2, d2/dy2, d2/dxdy) at (ix, iy) of the trigonometric
+    interpolant of the n x n surface c, from its spectrum over signed
+    frequencies; the Nyquist frequency counts in the pure terms with (n/2)^2 and
+    not in the mixed term."""
+    n = c.shape[0]
+    C = np.fft.fft2(c)
+    f = np.arange(n, dtype=np.float64)
+    f = np.where(f < n // 2, f, f - n)
+    fm = f.copy()
+    fm[n // 2] = 0.0
+    f2 = f * f
+    f2[n // 2] = (n // 2) ** 2
+    ky, kx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    e = np.exp(2j * np.pi * (ky * iy + kx * ix) / n)
+    sc = -(2 * np.pi / n) ** 2 / (n * n)
+    hxx = sc * float(np.sum((C * e).real * f2[None, :]))
+    hyy = sc * float(np.sum((C * e).real * f2[:, None]))
+    hxy = sc * float(np.sum((C * e).real * fm[:, None] * fm[None, :]))
+    return hxx, hyy, hxy
+
+
+# ---------------------------------------------------------------------------
+# Iterative refinement (Section IV: match, update, repeat until the scores
+# stabilise).  One step on the translation (tx, ty) of window A.
+# ---------------------------------------------------------------------------
+def refine_step(rec, theta, mode="centroid", jac=None, max_step=0.5):
+    """Returns (new theta, step length).
+
+    centroid: t <- t - d with d = (dx, dy), the centroid shift of the peak.
+    newton: Newton's method on d(t) = 0, with the 2 x 2 Jacobian J = d d / d t
+    taken from jac = [d(dx)/d theta_A, d(dy)/d theta_A] (six entries each,
+    translations at 2 and 5): t <- t - J^-1 d, used when the peak is at the
+    origin, the window is not degenerate and det J > 1e-6; otherwise the
+    centroid step.  Steps longer than max_step are scaled to max_step."""
+    theta = np.array(theta, dtype=np.float64)
+    d = np.array([rec["dx"], rec["dy"]], dtype=np.float64)
+    step = -d
+    at_origin = rec["sx"] == 0 and rec["sy"] == 0
+    if mode == "newton" and jac is not None and at_origin and not (rec["status"] & STATUS_DEGENERATE):
+        jac = np.asarray(jac, dtype=np.float64).reshape(2, 6)
+        J = np.array([[jac[0, 2], jac[0, 5]], [jac[1, 2], jac[1, 5]]])
+        if np.linalg.det(J) > 1e-6:
+            step = -np.linalg.solve(J, d)
+    ln = float(np.hypot(step[0], step[1]))
+    if not ln <= max_step:
+        step = step * (max_step / ln) if ln > 0 else np.zeros(2)
+        ln = max_step
+    theta[4] += step[0]
+    theta[7] += step[1]
+    return theta, ln
+
+
+def centroid_jacobian(imgA, imgB, thetaA, thetaB, n, params: Params):
+    """Returns (record, [d(dx)/d theta_A, d(dy)/d theta_A]) as a 2 x 6 array,
+    with the integer peak held fixed."""
+    rec, gx, _ = match_grad(imgA, imgB, thetaA, thetaB, n, params, g_peak=0.0, g_snr=0.0, g_dx=1.0)
+    _, gy, _ = match_grad(imgA, imgB, thetaA, thetaB, n, params, g_peak=0.0, g_snr=0.0, g_dy=1.0)
+    return rec, np.stack([gx, gy])
 
 
 def match_pair(imgA, imgB, thetaA, thetaB, n, params: Params, return_surface=False):
@@ -232,9 +301,10 @@ def _bilinear_partials(img, x, y):
     return gx, gy
 
 
-def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=1.0):
+def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=1.0, g_dx=0.0, g_dy=0.0):
     """Returns (record, dJ/dthetaA[6], dJ/dthetaB[6]) with J = g_peak c[s*] +
-    g_snr SNR; the six entries are (a11, a12, tx, a21, a22, ty)."""
+    g_snr SNR + g_dx dx + g_dy dy (dx, dy: the centroid shift); the six
+    entries are (a11, a12, tx, a21, a22, ty)."""
     p, eps_rel = params.p, params.eps_rel
     a, _ = gather(imgA, thetaA, n)
     b, _ = gather(imgB, thetaB, n)
@@ -266,6 +336,23 @@ def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=
     if sd > 0:
         Gc[iy, ix] += g_snr / sd
         Gc += g_snr * (-1.0 / (M * sd) - snr * (c - mu) / (M * sd * sd))
+    # centroid: d = s* + sum w_d delta / sum w_d, w_d = max(c(s* + delta) - mean, 0).
+    # d(dx)/dc(s* + delta) = (delta_x - (dx - sx)) / sum w on the positive weights;
+    # the mean's share is uniform over the surface and vanishes with the DC bin.
+    if g_dx != 0.0 or g_dy != 0.0:
+        wsum = 0.0
+        cells = []
+        for dyy in (-1, 0, 1):
+            for dxx in (-1, 0, 1):
+                yy, xx = (iy + dyy) % n, (ix + dxx) % n
+                wv = c[yy, xx] - mu
+                if wv > 0:
+                    wsum += wv
+                    cells.append((yy, xx, dxx, dyy))
+        if wsum > 0:
+            fx, fy = rec["dx"] - rec["sx"], rec["dy"] - rec["sy"]
+            for (yy, xx, dxx, dyy) in cells:
+                Gc[yy, xx] += (g_dx * (dxx - fx) + g_dy * (dyy - fy)) / wsum
     # c = Re(IDFT2 C): G_C = DFT2(Gc) / M
     GC = np.fft.fft2(Gc) / M
     GC[0, 0] = 0.0

@@ -13,6 +13,9 @@
 
 using namespace swift;
 
+static_assert(sizeof(swift_image) == 32 && sizeof(swift_params) == 24 && sizeof(swift_match) == 64,
+              "C ABI struct sizes");
+
 // Records a pair of HIP events around every kernel launch while enabled.
 struct EventTimer : KernelTimer {
   struct Rec {
@@ -118,7 +121,7 @@ struct GroupLayout {
   // adjoint
   size_t y = 0, dpart = 0, rpart = 0;
   // saved state (offsets into the saved buffer)
-  size_t sz = 0, sps = 0, srec = 0;
+  size_t sz = 0, sps = 0, srec = 0, snb = 0;
 };
 
 struct Layout {
@@ -178,7 +181,7 @@ Layout make_layout(const swift_pairs* pairs) {
     g.y = bo;
     bo += align256(P * n * n * sizeof(float2));
     g.dpart = bo;
-    bo += align256(P * ncolwg(g.n) * sizeof(double));
+    bo += align256(P * ncolwg(g.n) * kDpart * sizeof(double));
     g.rpart = bo;
     bo += align256(P * nslice(g.n) * 2 * kBwdSums * sizeof(double));
     g.sz = so;
@@ -187,6 +190,8 @@ Layout make_layout(const swift_pairs* pairs) {
     so += align256(P * sizeof(PairStat));
     g.srec = so;
     so += align256(P * sizeof(swift_match));
+    g.snb = so;
+    so += align256(P * 9 * sizeof(float));
   }
   L.fwd = fo;
   L.bwd = bo;
@@ -332,6 +337,7 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     a.saved_Z = saved ? (float2*)((char*)saved + g.sz) : nullptr;
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
+    a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
     e = launch_match_group(g.n, a, stream, ctx->kt());
     if (e != hipSuccess) return hip_fail(e, "match launch");
     surf_off += (size_t)g.count * g.n * g.n;
@@ -339,18 +345,13 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   return ok();
 }
 
-int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
-                         const swift_params* params, const void* saved, const float* g_peak, const float* g_snr,
-                         float* g_theta_a, float* g_theta_b, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
-  int rc = check_pairs(pairs);
-  if (rc) return rc;
-  rc = check_params(params);
-  if (rc) return rc;
-  if (pairs->n_pairs == 0) return ok();
-  if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
-  if (!saved) return fail(SWIFT_E_INVAL, "saved is NULL (run swift_match_batch with a saved buffer first)");
-  if (!g_theta_a) return fail(SWIFT_E_INVAL, "g_theta_a is NULL");
+// Shared body of the two adjoint entry points: per size group, the taper
+// tables and one backward launch (centroid_jac selects the objective).
+static int run_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                        const swift_params* params, const void* saved, const float* g_peak, const float* g_snr,
+                        float* g_theta_a, float* g_theta_b, float* peak_hess, float* jac, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  const bool cj = jac != nullptr;
   const Layout L = make_layout(pairs);
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
@@ -375,10 +376,13 @@ int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     b.Zf = (const float2*)((const char*)saved + g.sz);
     b.ps = (const PairStat*)((const char*)saved + g.sps);
     b.rec = (const swift_match*)((const char*)saved + g.srec);
+    b.nb = (const float*)((const char*)saved + g.snb);
     b.g_peak = g_peak ? g_peak + g.first : nullptr;
     b.g_snr = g_snr ? g_snr + g.first : nullptr;
-    b.g_th_a = g_theta_a + 6 * (size_t)g.first;
+    b.g_th_a = g_theta_a ? g_theta_a + 6 * (size_t)g.first : nullptr;
     b.g_th_b = g_theta_b ? g_theta_b + 6 * (size_t)g.first : nullptr;
+    b.peak_hess = peak_hess ? peak_hess + 3 * (size_t)g.first : nullptr;
+    b.jac = jac ? jac + 12 * (size_t)g.first : nullptr;
     b.Y = (float2*)(base + g.y);
     b.dpart = (double*)(base + g.dpart);
     b.rpart = (double*)(base + g.rpart);
@@ -390,10 +394,50 @@ int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     b.eps_rel = params->eps_rel;
     b.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     b.npairs = g.count;
-    e = launch_backward_group(g.n, b, stream, ctx->kt());
+    e = launch_backward_group(g.n, b, cj, stream, ctx->kt());
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }
   return ok();
+}
+
+static int check_backward_common(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                                 const swift_params* params, const void* saved, bool* empty) {
+  *empty = false;
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  int rc = check_pairs(pairs);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  if (pairs->n_pairs == 0) {
+    *empty = true;
+    return ok();
+  }
+  if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
+  if (!saved) return fail(SWIFT_E_INVAL, "saved is NULL (run swift_match_batch with a saved buffer first)");
+  return ok();
+}
+
+int swift_match_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                         const swift_params* params, const void* saved, const float* g_peak, const float* g_snr,
+                         float* g_theta_a, float* g_theta_b, float* peak_hess, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  bool empty;
+  int rc = check_backward_common(ctx, imgs, n_imgs, pairs, params, saved, &empty);
+  if (rc || empty) return rc;
+  if (!g_theta_a) return fail(SWIFT_E_INVAL, "g_theta_a is NULL");
+  return run_backward(ctx, imgs, n_imgs, pairs, params, saved, g_peak, g_snr, g_theta_a, g_theta_b, peak_hess,
+                      nullptr, ws, ws_bytes, stream);
+}
+
+int swift_centroid_jacobian(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                            const swift_params* params, const void* saved, float* jac, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  bool empty;
+  int rc = check_backward_common(ctx, imgs, n_imgs, pairs, params, saved, &empty);
+  if (rc || empty) return rc;
+  if (!jac) return fail(SWIFT_E_INVAL, "jac is NULL");
+  return run_backward(ctx, imgs, n_imgs, pairs, params, saved, nullptr, nullptr, nullptr, nullptr, nullptr, jac,
+                      ws, ws_bytes, stream);
 }
 
 int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width, int64_t pitch,
@@ -443,6 +487,22 @@ int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch, c
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipError_t e = launch_snr(surfaces, n, batch, out, stream);
   if (e != hipSuccess) return hip_fail(e, "snr launch");
+  return ok();
+}
+
+int swift_refine_update(swift_ctx* ctx, int32_t P, const swift_match* recs, const float* jac, float* theta,
+                        int32_t mode, float max_step, float* step_out, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (P < 0) return fail(SWIFT_E_INVAL, "P < 0");
+  if (P == 0) return ok();
+  if (!recs || !theta) return fail(SWIFT_E_INVAL, "recs/theta is NULL");
+  if (mode != SWIFT_REFINE_CENTROID && mode != SWIFT_REFINE_NEWTON) return fail(SWIFT_E_INVAL, "bad mode %d", mode);
+  if (mode == SWIFT_REFINE_NEWTON && !jac) return fail(SWIFT_E_INVAL, "Newton steps need jac");
+  if (!(max_step > 0.0f)) return fail(SWIFT_E_INVAL, "max_step must be > 0");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_refine(P, recs, jac, theta, mode, max_step, step_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "refine launch");
   return ok();
 }
 

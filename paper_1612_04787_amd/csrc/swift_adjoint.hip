@@ -23,19 +23,29 @@
 //
 // Kernels per window size: k_bwd_col (column stage), k_bwd_row (inverse row
 // FFTs + gather recomputation + sums), k_bwd_fin (per pair).
+//
+// Centroid-Jacobian mode (CJ): the objectives are the two components of the
+// centroid shift d = s* + sum_delta w_delta delta / sum w (w = max(c - mean, 0)
+// on the 3 x 3 box), whose surface cotangent is nine weighted deltas,
+//   d(dx)/dc(s* + delta) = (delta_x - (dx - sx)) / sum w   (w > 0),
+// (the mean's share is uniform and vanishes with the DC bin), so again
+// G_C = e^{-2 pi i k.s*/N} / M sum_delta omega_delta e^{-2 pi i k.delta/N}.
+// Only window A is differentiated: G_FA of the x objective goes to the real
+// channel and that of the y objective to the imaginary channel of the one
+// inverse 2-D FFT, giving d(dx, dy) / d theta_A in a single pass.
 #include "swift_dev.hpp"
 
 namespace swift {
 
 // ---------------------------------------------------------------- column stage
-template <int N>
+template <int N, bool CJ>
 __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
   constexpr int NI = N / 2 + 1, NW = (NI + IPW - 1) / IPW;
   constexpr int SL = lidx(N);
   __shared__ float2 lds[G * SL];
-  __shared__ double red[4];
+  __shared__ double red[4][kDpart];
 
   const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
   const int tid = threadIdx.x, c = tid / T, t = tid % T;
@@ -61,7 +71,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   }
   __syncthreads();
 
-  float dj = 0.0f;
+  float dj = 0.0f, dj1 = 0.0f, hxx = 0.0f, hyy = 0.0f, hxy = 0.0f;
   float2 gb[E];
   if (valid && which == 0) {
     const PairStat ps = a.ps[pair];
@@ -74,11 +84,33 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       alpha = (float)((double)gp + (double)gsn / rec.std);
       gamma = (float)(-(double)gsn * snr / ((double)N * N * rec.std * rec.std));
     }
-    const bool zero_all = (ps.flags & 1) != 0;
+    bool zero_all = (ps.flags & 1) != 0;
+    // centroid weights (CJ): omega_x, omega_y on the 3 x 3 box, from the saved values
+    float omx[9], omy[9];
+    if constexpr (CJ) {
+      const float* q = a.nb + (size_t)pair * 9;
+      double sw = 0.0, swx = 0.0, swy = 0.0;
+      for (int j = 0; j < 9; ++j) {
+        const double wv = fmax((double)q[j] - rec.mean, 0.0);
+        sw += wv;
+        swx += wv * (double)(j % 3 - 1);
+        swy += wv * (double)(j / 3 - 1);
+      }
+      const double fxc = sw > 0.0 ? swx / sw : 0.0, fyc = sw > 0.0 ? swy / sw : 0.0;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const bool on = sw > 0.0 && (double)q[j] - rec.mean > 0.0;
+        omx[j] = on ? (float)(((double)(j % 3 - 1) - fxc) / sw) : 0.0f;
+        omy[j] = on ? (float)(((double)(j / 3 - 1) - fyc) / sw) : 0.0f;
+      }
+      if (!(sw > 0.0)) zero_all = true;
+    }
     const float p = a.p, hp2 = -0.5f * p;
     const float inv_m = 1.0f / (float)(N * N);
     const float mw = (w == 0 || w == N / 2) ? 1.0f : 2.0f;  // column w and its mirror N - w
     const float2 tauw = a.tau[w];
+    // signed frequency of the column (Nyquist: squared terms only)
+    const float fw = (float)w, fwm = (w == N / 2) ? 0.0f : (float)w;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = t + e * T;
@@ -107,15 +139,50 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       // e^{-2 pi i (ky iy + w ix) / N} from the W_1024 table
       const int m = (ky * rec.iy + w * rec.ix) & (N - 1);
       const float2 ph = a.tw[m * (1024 / N)];
-      float2 gc = cscale(cadd(cscale(ph, alpha), cscale(X, gamma * h)), inv_m);
-      if (zero_all || (ky == 0 && w == 0)) gc = make_float2(0.0f, 0.0f);
-      // G_X = G_C (h + r h') + conj(G_C) X^2 h'
+      // surface Hessian sums: Re(X h e^{+i phi}) times the frequency products
+      if (!zero_all && !(ky == 0 && w == 0)) {
+        const float2 cc = cmul(cscale(X, h), cconj(ph));
+        const float fy = (ky < N / 2) ? (float)ky : (float)(ky - N);
+        const float fym = (ky == N / 2) ? 0.0f : fy;
+        hxx += mw * cc.x * fw * fw;
+        hyy += mw * cc.x * fy * fy;
+        hxy += mw * cc.x * fwm * fym;
+      }
       const float2 x2 = cmul(X, X);
-      const float2 gx = cadd(cscale(gc, h + r * hd), cscale(cmul(cconj(gc), x2), hd));
-      const float2 cx = cmul(cconj(gc), X);
-      dj += mw * cx.x * hd;
-      const float2 gfa = cmul(cconj(gx), fb);
-      const float2 gfb = cmul(gx, fa);
+      const bool zb = zero_all || (ky == 0 && w == 0);
+      float2 gfa, gfb;
+      if constexpr (!CJ) {
+        float2 gc = cscale(cadd(cscale(ph, alpha), cscale(X, gamma * h)), inv_m);
+        if (zb) gc = make_float2(0.0f, 0.0f);
+        // G_X = G_C (h + r h') + conj(G_C) X^2 h'
+        const float2 gx = cadd(cscale(gc, h + r * hd), cscale(cmul(cconj(gc), x2), hd));
+        dj += mw * cmul(cconj(gc), X).x * hd;
+        gfa = cmul(cconj(gx), fb);
+        gfb = cmul(gx, fa);
+      } else {
+        // 3 x 3 sums S = sum omega e_x^dx e_y^dy with e = e^{-2 pi i k/N}
+        const float2 ex = a.tw[w * (1024 / N)], ey = a.tw[ky * (1024 / N)];
+        const float2 exc = cconj(ex), eyc = cconj(ey);
+        float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r3 = 0; r3 < 3; ++r3) {
+          const float2 rx = cadd(cadd(cscale(exc, omx[3 * r3]), make_float2(omx[3 * r3 + 1], 0.f)),
+                                 cscale(ex, omx[3 * r3 + 2]));
+          const float2 ry = cadd(cadd(cscale(exc, omy[3 * r3]), make_float2(omy[3 * r3 + 1], 0.f)),
+                                 cscale(ex, omy[3 * r3 + 2]));
+          const float2 ef = r3 == 0 ? eyc : (r3 == 1 ? make_float2(1.f, 0.f) : ey);
+          sx = cadd(sx, cmul(rx, ef));
+          sy = cadd(sy, cmul(ry, ef));
+        }
+        float2 gcx = cscale(cmul(ph, sx), inv_m), gcy = cscale(cmul(ph, sy), inv_m);
+        if (zb) gcx = gcy = make_float2(0.0f, 0.0f);
+        const float2 gxx = cadd(cscale(gcx, h + r * hd), cscale(cmul(cconj(gcx), x2), hd));
+        const float2 gxy = cadd(cscale(gcy, h + r * hd), cscale(cmul(cconj(gcy), x2), hd));
+        dj += mw * cmul(cconj(gcx), X).x * hd;
+        dj1 += mw * cmul(cconj(gcy), X).x * hd;
+        gfa = cmul(cconj(gxx), fb);  // real channel: d(dx)
+        gfb = cmul(cconj(gxy), fb);  // imaginary channel: d(dy)
+      }
       v[e] = make_float2(gfa.x - gfb.y, gfa.y + gfb.x);  // Q(ky, w) = G_FA + i G_FB
       // keep G_FA, G_FB of column w for the mirrored column (read after the barrier)
       tau[e] = gfa;
@@ -147,19 +214,30 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
   }
-  // per-workgroup partial of dJ/d(eps^2)
-  const float wsum = wave_sum_f32(dj);
-  if ((tid & 63) == 0) red[tid >> 6] = (double)wsum;
+  // per-workgroup partials of dJ/d(eps^2) and of the Hessian sums
+  const float vals[kDpart] = {wave_sum_f32(dj), wave_sum_f32(dj1), wave_sum_f32(hxx), wave_sum_f32(hyy),
+                              wave_sum_f32(hxy), 0.0f};
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < kDpart; ++q) red[tid >> 6][q] = (double)vals[q];
+  }
   __syncthreads();
-  if (tid == 0) a.dpart[(size_t)pair * NW + wg] = red[0] + red[1] + red[2] + red[3];
+  if (tid < kDpart)
+    a.dpart[((size_t)pair * NW + wg) * kDpart + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
 // ---------------------------------------------------------------- row stage
 // Per image, the 20 pixel sums of the header comment; acc layout:
 // [0..5] P1, [6..11] P2, [12..17] P3, [18] Q, [19] R.
+struct PixelTerms {
+  float D[6];  // (a_x u, a_x v, a_x, a_y u, a_y v, a_y)
+  float tap;   // T
+  float w;     // (a - m) T
+};
+
 template <int N>
-__device__ __forceinline__ void bwd_pixel(float (&acc)[kBwdSums], const swift_image& im, const float* th, double vrow,
-                                          int x, float tap, float gw, float mean_off, bool& cl) {
+__device__ __forceinline__ PixelTerms bwd_terms(const swift_image& im, const float* th, double vrow, int x,
+                                                float tap, float mean_off, bool& cl) {
   const double u = (double)(x - N / 2);
   const double X = fmin(fmax((double)th[0] + (double)th[4] + (double)th[2] * u + (double)th[3] * vrow, -1e9), 1e9);
   const double Y = fmin(fmax((double)th[1] + (double)th[7] + (double)th[5] * u + (double)th[6] * vrow, -1e9), 1e9);
@@ -189,21 +267,32 @@ __device__ __forceinline__ void bwd_pixel(float (&acc)[kBwdSums], const swift_im
   // bilinear partials (floor cell; clamped reads give zero outside)
   const float ax = (1.0f - fy) * (i10 - i00) + fy * (i11 - i01);
   const float ay = (1.0f - fx) * (i01 - i00) + fx * (i11 - i10);
-  const float wv = (val - kSampleOffset - mean_off) * tap;  // w = (a - m) T
+  PixelTerms p;
   const float uf = (float)u, vf = (float)vrow;
-  const float D[6] = {ax * uf, ax * vf, ax, ay * uf, ay * vf, ay};
-  const float tg = tap * gw, tw = tap * wv;
+  p.D[0] = ax * uf;
+  p.D[1] = ax * vf;
+  p.D[2] = ax;
+  p.D[3] = ay * uf;
+  p.D[4] = ay * vf;
+  p.D[5] = ay;
+  p.tap = tap;
+  p.w = (val - kSampleOffset - mean_off) * tap;
+  return p;
+}
+
+__device__ __forceinline__ void bwd_accumulate(float (&acc)[kBwdSums], const PixelTerms& p, float gw) {
+  const float tg = p.tap * gw, tw = p.tap * p.w;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    acc[j] = fmaf(tg, D[j], acc[j]);
-    acc[6 + j] = fmaf(tap, D[j], acc[6 + j]);
-    acc[12 + j] = fmaf(tw, D[j], acc[12 + j]);
+    acc[j] = fmaf(tg, p.D[j], acc[j]);
+    acc[6 + j] = fmaf(p.tap, p.D[j], acc[6 + j]);
+    acc[12 + j] = fmaf(tw, p.D[j], acc[12 + j]);
   }
   acc[18] += tg;
   acc[19] += tw;
 }
 
-template <int N>
+template <int N, bool CJ>
 __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
@@ -234,16 +323,17 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 
   const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
   const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
-  swift_image im[2] = {a.imgs[ka], a.imgs[kb]};
-  im[0].width = max(im[0].width, 2);
-  im[0].height = max(im[0].height, 2);
-  im[1].width = max(im[1].width, 2);
-  im[1].height = max(im[1].height, 2);
-  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  swift_image imA = a.imgs[ka], imB = a.imgs[kb];
+  imA.width = max(imA.width, 2);
+  imA.height = max(imA.height, 2);
+  imB.width = max(imB.width, 2);
+  imB.height = max(imB.height, 2);
+  const float* thA = a.th_a + 8 * (size_t)pair;
+  const float* thB = a.th_b + 8 * (size_t)pair;
   const PairStat ps = a.ps[pair];
-  float accA[kBwdSums], accB[kBwdSums];
+  float acc0[kBwdSums], acc1[kBwdSums];
 #pragma unroll
-  for (int j = 0; j < kBwdSums; ++j) accA[j] = accB[j] = 0.0f;
+  for (int j = 0; j < kBwdSums; ++j) acc0[j] = acc1[j] = 0.0f;
   bool cl = false;
   Twiddles<N> tw;
   tw_load<N>(tw, t, a.tw);
@@ -256,23 +346,35 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = row[lidx(t + e * T)];
     wave_lds_sync();
-    fft_wave<N, true>(v, row, t, tw);  // v[e].x = G_wA(x), v[e].y = G_wB(x), x = t + e T
+    fft_wave<N, true>(v, row, t, tw);  // real / imaginary channel at x = t + e T
+    // park the transformed row in LDS (each lane its own elements) so that the
+    // pixel loop below indexes LDS, not a register array
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = v[e];
     const float ty = a.taper[y];
     const double vrow = (double)(y - N / 2);
 #pragma unroll 2
     for (int e = 0; e < E; ++e) {
       const int x = t + e * T;
+      const float2 g = row[lidx(x)];
       const float tap = a.taper[x] * ty;
-      bwd_pixel<N>(accA, im[0], th[0], vrow, x, tap, v[e].x, ps.mA, cl);
-      bwd_pixel<N>(accB, im[1], th[1], vrow, x, tap, v[e].y, ps.mB, cl);
+      const PixelTerms pa = bwd_terms<N>(imA, thA, vrow, x, tap, ps.mA, cl);
+      bwd_accumulate(acc0, pa, g.x);
+      if constexpr (CJ) {
+        bwd_accumulate(acc1, pa, g.y);
+      } else {
+        const PixelTerms pb = bwd_terms<N>(imB, thB, vrow, x, tap, ps.mB, cl);
+        bwd_accumulate(acc1, pb, g.y);
+      }
     }
   }
   // block reduction to FP64 slice partials
   const int wv = tid >> 6, ln = tid & 63;
 #pragma unroll
   for (int j = 0; j < kBwdSums; ++j) {
-    const float sa = wave_sum_f32(accA[j]);
-    const float sb = wave_sum_f32(accB[j]);
+    const float sa = wave_sum_f32(acc0[j]);
+    const float sb = wave_sum_f32(acc1[j]);
     if (ln == 0) {
       red[wv][j] = (double)sa;
       red[wv][kBwdSums + j] = (double)sb;
@@ -284,15 +386,31 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 }
 
 // ---------------------------------------------------------------- per pair
-template <int N>
+template <int N, bool CJ>
 __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
   constexpr int G = 256 / FftCfg<N>::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
   constexpr int NSLICE = N / RowsCfg<N>::FWD;
   __shared__ double tot[2 * kBwdSums];
   const int pair = blockIdx.x, ln = threadIdx.x;
-  double dj = 0.0;
-  for (int i = ln; i < NW; i += 64) dj += a.dpart[(size_t)pair * NW + i];
+  double dj = 0.0, dj1 = 0.0, hs[3] = {0.0, 0.0, 0.0};
+  for (int i = ln; i < NW; i += 64) {
+    const double* q = a.dpart + ((size_t)pair * NW + i) * kDpart;
+    dj += q[0];
+    dj1 += q[1];
+    hs[0] += q[2];
+    hs[1] += q[3];
+    hs[2] += q[4];
+  }
   dj = wave_sum(dj);
+  dj1 = wave_sum(dj1);
+  hs[0] = wave_sum(hs[0]);
+  hs[1] = wave_sum(hs[1]);
+  hs[2] = wave_sum(hs[2]);
+  if (!CJ && a.peak_hess && ln < 3) {
+    // d2c/ds2 = -(2 pi / N)^2 / M sum C(k) f f' e^{+i phi}, C = X h
+    const double sc = -4.0 * M_PI * M_PI / ((double)N * N * (double)N * N);
+    a.peak_hess[(size_t)pair * 3 + ln] = (float)(sc * hs[ln]);
+  }
   if (ln < 2 * kBwdSums) {
     double s = 0.0;
     for (int sl = 0; sl < NSLICE; ++sl) s += a.rpart[((size_t)pair * NSLICE + sl) * 2 * kBwdSums + ln];
@@ -305,42 +423,54 @@ __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
     const TaperInfo ti = *a.tinfo;
     const double sT = ti.sum_t * ti.sum_t;
     const double e2 = (double)a.eps_rel * (double)a.eps_rel;
-    const double lam = dj * 2.0 * e2 * (img == 0 ? (double)ps.swB : (double)ps.swA);
+    // eps^2 = eps_rel^2 |w_A|^2 |w_B|^2: each channel's lambda multiplies the
+    // differentiated window's w by the other window's norm
+    const double lam = CJ ? (img == 0 ? dj : dj1) * 2.0 * e2 * (double)ps.swB
+                          : dj * 2.0 * e2 * (img == 0 ? (double)ps.swB : (double)ps.swA);
     const double* q = tot + img * kBwdSums;
     double g = q[j] + lam * q[12 + j] - (q[18] + lam * q[19]) / sT * q[6 + j];
     if (ps.flags & 1) g = 0.0;
-    float* dst = img == 0 ? a.g_th_a : a.g_th_b;
-    if (dst) dst[(size_t)pair * 6 + j] = (float)g;
+    if (CJ) {
+      a.jac[((size_t)pair * 2 + img) * 6 + j] = (float)g;
+    } else {
+      float* dst = img == 0 ? a.g_th_a : a.g_th_b;
+      if (dst) dst[(size_t)pair * 6 + j] = (float)g;
+    }
   }
 }
 
 // ---------------------------------------------------------------- launcher
-template <int N>
+template <int N, bool CJ>
 static hipError_t launch_bwd_t(const BwdArgs& a, hipStream_t s, KernelTimer* kt) {
   constexpr int G = 256 / FftCfg<N>::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
   constexpr int NSLICE = N / RowsCfg<N>::FWD;
   const unsigned P = (unsigned)a.npairs;
-  if (kt) kt->begin("k_bwd_col", N, s);
-  k_bwd_col<N><<<P * NW, 256, 0, s>>>(a);
+  if (kt) kt->begin(CJ ? "k_cj_col" : "k_bwd_col", N, s);
+  k_bwd_col<N, CJ><<<P * NW, 256, 0, s>>>(a);
   if (kt) kt->end(s);
-  if (kt) kt->begin("k_bwd_row", N, s);
-  k_bwd_row<N><<<P * NSLICE, 256, 0, s>>>(a);
+  if (kt) kt->begin(CJ ? "k_cj_row" : "k_bwd_row", N, s);
+  k_bwd_row<N, CJ><<<P * NSLICE, 256, 0, s>>>(a);
   if (kt) kt->end(s);
-  if (kt) kt->begin("k_bwd_fin", N, s);
-  k_bwd_fin<N><<<P, 64, 0, s>>>(a);
+  if (kt) kt->begin(CJ ? "k_cj_fin" : "k_bwd_fin", N, s);
+  k_bwd_fin<N, CJ><<<P, 64, 0, s>>>(a);
   if (kt) kt->end(s);
   return hipGetLastError();
 }
 
-hipError_t launch_backward_group(int n, const BwdArgs& a, hipStream_t s, KernelTimer* kt) {
+template <bool CJ>
+static hipError_t launch_bwd_n(int n, const BwdArgs& a, hipStream_t s, KernelTimer* kt) {
   switch (n) {
-    case 64: return launch_bwd_t<64>(a, s, kt);
-    case 128: return launch_bwd_t<128>(a, s, kt);
-    case 256: return launch_bwd_t<256>(a, s, kt);
-    case 512: return launch_bwd_t<512>(a, s, kt);
-    case 1024: return launch_bwd_t<1024>(a, s, kt);
+    case 64: return launch_bwd_t<64, CJ>(a, s, kt);
+    case 128: return launch_bwd_t<128, CJ>(a, s, kt);
+    case 256: return launch_bwd_t<256, CJ>(a, s, kt);
+    case 512: return launch_bwd_t<512, CJ>(a, s, kt);
+    case 1024: return launch_bwd_t<1024, CJ>(a, s, kt);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt) {
+  return centroid_jac ? launch_bwd_n<true>(n, a, s, kt) : launch_bwd_n<false>(n, a, s, kt);
 }
 
 }  // namespace swift

@@ -134,6 +134,10 @@ __device__ inline swift_match make_record(int n, Top2 tp, double sum, double sq,
   rec.dx = (float)(sx + (sw > 0.0 ? swx / sw : 0.0));
   rec.dy = (float)(sy + (sw > 0.0 ? swy / sw : 0.0));
   rec.status = st;
+  rec.hxx = nb[1][0] - 2.0f * nb[1][1] + nb[1][2];
+  rec.hyy = nb[0][1] - 2.0f * nb[1][1] + nb[2][1];
+  rec.hxy = 0.25f * (nb[2][2] - nb[0][2] - nb[2][0] + nb[0][0]);
+  rec.reserved = 0;
   return rec;
 }
 

@@ -70,6 +70,7 @@ struct MatchArgs {
   float2* saved_Z;         // [P][N][N]: forward 2-D spectrum of z, [kx][ky]
   PairStat* saved_ps;      // [P]
   swift_match* saved_rec;  // [P]
+  float* saved_nb;         // [P][9] surface values around the peak ([dy+1][dx+1])
 };
 
 // Arguments of the adjoint kernels of one window size.
@@ -82,12 +83,15 @@ struct BwdArgs {
   const float2* Zf;         // saved forward spectrum [P][kx][ky]
   const PairStat* ps;       // saved
   const swift_match* rec;   // saved
+  const float* nb;          // saved [P][9]
   const float* g_peak;      // [P] or NULL
   const float* g_snr;       // [P] or NULL
   float* g_th_a;            // [P][6]
   float* g_th_b;            // [P][6] or NULL
   float2* Y;                // [P][kx][y] inverse-column output
-  double* dpart;            // [P][NW] partial dJ/d(eps^2)
+  double* dpart;            // [P][NW][kDpart] partial dJ/d(eps^2) (two objectives) and Hessian sums
+  float* peak_hess;         // [P][3] or NULL
+  float* jac;               // [P][2][6] (centroid-Jacobian mode)
   double* rpart;            // [P][NSLICE][40] partial pixel sums
   const float2* tw;
   const float2* tau;
@@ -99,6 +103,7 @@ struct BwdArgs {
   int32_t n_imgs;
 };
 constexpr int kBwdSums = 20;  // per image: P1[6], P2[6], P3[6], Q, R
+constexpr int kDpart = 6;     // dJ0/de2, dJ1/de2, hxx, hyy, hxy, unused
 
 // Rows per workgroup of the forward and inverse row passes; the LDS budget
 // (bytes) of one image's source tile in the forward pass (0: always gather
@@ -127,9 +132,11 @@ struct KernelTimer {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s);
 hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
-hipError_t launch_backward_group(int n, const BwdArgs& a, hipStream_t s, KernelTimer* kt);
+hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);
 int col_items_per_wg(int n);  // column-pass workgroups per pair
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
+hipError_t launch_refine(int P, const swift_match* rec, const float* jac, float* th, int mode, float max_step,
+                         float* step_out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* exclude, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
                           hipStream_t s, KernelTimer* kt);

@@ -738,6 +738,8 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
     const swift_match rec = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0);
     a.out[pair] = rec;
     if (a.saved_rec) a.saved_rec[pair] = rec;
+    if (a.saved_nb)
+      for (int q = 0; q < 9; ++q) a.saved_nb[(size_t)pair * 9 + q] = nb[q / 3][q % 3];
   }
 }
 

@@ -198,6 +198,45 @@ hipError_t launch_project_sel(const uint8_t* src, int64_t pitch, int64_t sstride
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- refinement step
+__global__ void __launch_bounds__(256) k_refine(int P, const swift_match* __restrict__ rec,
+                                                const float* __restrict__ jac, float* __restrict__ th, int mode,
+                                                float max_step, float* __restrict__ step_out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P) return;
+  const swift_match r = rec[i];
+  const int n = r.n > 0 ? r.n : 1;
+  const int sx = r.ix >= n / 2 ? r.ix - n : r.ix, sy = r.iy >= n / 2 ? r.iy - n : r.iy;
+  float dx = -r.dx, dy = -r.dy;  // centroid step
+  if (mode == SWIFT_REFINE_NEWTON && jac && sx == 0 && sy == 0 && !(r.status & SWIFT_ST_DEGENERATE)) {
+    // Newton on the centroid shift d(t) = 0: t <- t - J^-1 d, J = d d / d t
+    const float* q = jac + (size_t)i * 12;
+    const double j00 = q[2], j01 = q[5], j10 = q[8], j11 = q[11];
+    const double det = j00 * j11 - j01 * j10;
+    if (det > 1e-6) {
+      const double ex = r.dx, ey = r.dy;
+      dx = (float)(-(j11 * ex - j01 * ey) / det);
+      dy = (float)(-(-j10 * ex + j00 * ey) / det);
+    }
+  }
+  float len = sqrtf(dx * dx + dy * dy);
+  if (!(len <= max_step)) {  // also catches NaN
+    const float sc = (len > 0.0f && len == len) ? max_step / len : 0.0f;
+    dx *= sc;
+    dy *= sc;
+    len = (len == len) ? max_step : 0.0f;
+  }
+  th[(size_t)i * 8 + 4] += dx;
+  th[(size_t)i * 8 + 7] += dy;
+  if (step_out) step_out[i] = len;
+}
+
+hipError_t launch_refine(int P, const swift_match* rec, const float* jac, float* th, int mode, float max_step,
+                         float* step_out, hipStream_t st) {
+  if (P > 0) k_refine<<<(P + 255) / 256, 256, 0, st>>>(P, rec, jac, th, mode, max_step, step_out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- x2 pyramid
 // dst(x, y) = (src(2x,2y) + src(2x+1,2y) + src(2x,2y+1) + src(2x+1,2y+1) + 2) >> 2
 __global__ void __launch_bounds__(256) k_pyramid(const uint8_t* __restrict__ src, int64_t spitch,

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("centroid_r", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
 
 
-REC_BYTES = 48
+REC_BYTES = 64
 assert C.sizeof(Image) == 32 and C.sizeof(Pairs) == 56 and C.sizeof(Params) == 24
 
 _lib = None
@@ -64,15 +64,18 @@ def load_library(path: str = LIB_PATH):
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
     lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
     lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
-                                         vp, sz, vp]
+                                         vp, vp, sz, vp]
     lib.swift_project.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i64, i64, vp]
     lib.swift_pyramid.argtypes = [vp, C.POINTER(Image), C.POINTER(Image), vp]
     lib.swift_snr.argtypes = [vp, vp, i32, i32, C.POINTER(Params), vp, vp]
+    lib.swift_centroid_jacobian.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, sz, vp]
+    lib.swift_refine_update.argtypes = [vp, i32, vp, vp, vp, i32, C.c_float, vp, vp]
     lib.swift_profile_enable.argtypes = [vp, C.c_int]
     lib.swift_profile_read.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32)]
     lib.swift_last_error.restype = C.c_char_p
     for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
-              "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read"):
+              "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read",
+              "swift_refine_update", "swift_centroid_jacobian"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -81,7 +84,8 @@ def load_library(path: str = LIB_PATH):
 def exported_symbols():
     return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
             "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
-            "swift_profile_enable", "swift_profile_read"]
+            "swift_profile_enable", "swift_profile_read", "swift_refine_update",
+            "swift_centroid_jacobian"]
 
 
 def _check(rc):
@@ -98,13 +102,14 @@ def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0):
 
 
 def parse_records(rec: torch.Tensor) -> dict:
-    """Splits a [P, 48] uint8 record tensor into named field views."""
+    """Splits a [P, 64] uint8 record tensor into named field views."""
     P = rec.shape[0]
-    f32 = rec.view(torch.float32).view(P, 12)
-    i32 = rec.view(torch.int32).view(P, 12)
-    f64 = rec.view(torch.float64).view(P, 6)
+    f32 = rec.view(torch.float32).view(P, 16)
+    i32 = rec.view(torch.int32).view(P, 16)
+    f64 = rec.view(torch.float64).view(P, 8)
     return dict(dx=f32[:, 0], dy=f32[:, 1], ix=i32[:, 2], iy=i32[:, 3], peak=f32[:, 4], snr=f32[:, 5],
-                mean=f64[:, 3], std=f64[:, 4], status=i32[:, 10], n=i32[:, 11])
+                mean=f64[:, 3], std=f64[:, 4], status=i32[:, 10], n=i32[:, 11], hxx=f32[:, 12], hyy=f32[:, 13],
+                hxy=f32[:, 14])
 
 
 class Swift:
@@ -201,13 +206,20 @@ class Swift:
                                           self.stream()))
 
     def match_backward_raw(self, table, n_imgs, pairs, params, saved, g_peak, g_snr, g_theta_a, g_theta_b=None,
-                           ws=None):
+                           peak_hess=None, ws=None):
         need, _ = self.workspace_size(pairs, params)
         if ws is None:
             ws = self.workspace(need)
         _check(self.lib.swift_match_backward(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
                                              _ptr(saved), _ptr(g_peak), _ptr(g_snr), _ptr(g_theta_a),
-                                             _ptr(g_theta_b), _ptr(ws), ws.numel(), self.stream()))
+                                             _ptr(g_theta_b), _ptr(peak_hess), _ptr(ws), ws.numel(), self.stream()))
+
+    def centroid_jacobian_raw(self, table, n_imgs, pairs, params, saved, jac, ws=None):
+        need, _ = self.workspace_size(pairs, params)
+        if ws is None:
+            ws = self.workspace(need)
+        _check(self.lib.swift_centroid_jacobian(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
+                                                _ptr(saved), _ptr(jac), _ptr(ws), ws.numel(), self.stream()))
 
     def prepare(self, images, n_list, img_a, img_b, theta_a, theta_b):
         """Device image table and pair descriptor (tensors kept alive in the dict)."""
@@ -248,16 +260,21 @@ class Swift:
             res["prep"] = prep
         return res
 
-    def match_backward(self, fwd, params, g_peak=None, g_snr=None, want_b=True):
+    def match_backward(self, fwd, params, g_peak=None, g_snr=None, want_b=True, want_hess=False):
         """Gradients [P, 6] (a11, a12, tx, a21, a22, ty) of sum(g_peak*peak +
-        g_snr*snr) for windows A (and B) of a forward run made with save=True."""
+        g_snr*snr) for windows A (and B) of a forward run made with save=True;
+        with want_hess also the surface Hessian at the peak [P, 3]."""
         prep = fwd["prep"]
         P = prep["pairs"].n_pairs
         ga = torch.empty((P, 6), dtype=torch.float32, device=self.device)
         gb = torch.empty((P, 6), dtype=torch.float32, device=self.device) if want_b else None
+        hs = torch.empty((P, 3), dtype=torch.float32, device=self.device) if want_hess else None
         gp = g_peak.to(self.device, torch.float32).contiguous() if g_peak is not None else None
         gs = g_snr.to(self.device, torch.float32).contiguous() if g_snr is not None else None
-        self.match_backward_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, fwd["saved"], gp, gs, ga, gb)
+        self.match_backward_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, fwd["saved"], gp, gs, ga, gb,
+                                hs)
+        if want_hess:
+            return ga, gb, hs
         return ga, gb
 
     def project(self, stack, k=3, exclude=None, out=None):
@@ -281,6 +298,22 @@ class Swift:
         di = Image(dst.data_ptr(), w // 2, h // 2, dst.stride(0), SWIFT_U8, 0)
         _check(self.lib.swift_pyramid(self.h, C.byref(si), C.byref(di), self.stream()))
         return dst
+
+    def centroid_jacobian(self, fwd, params):
+        """[P, 2, 6]: d(dx)/d theta_A and d(dy)/d theta_A for a forward run
+        made with save=True."""
+        prep = fwd["prep"]
+        P = prep["pairs"].n_pairs
+        jac = torch.empty((P, 2, 6), dtype=torch.float32, device=self.device)
+        self.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, fwd["saved"], jac)
+        return jac
+
+    def refine_update(self, recs_raw, theta, mode=0, jac=None, max_step=0.5, step_out=None):
+        """One refinement step applied in place to theta [P, 8] (device);
+        Newton mode takes jac [P, 2, 6] from centroid_jacobian."""
+        P = theta.shape[0]
+        _check(self.lib.swift_refine_update(self.h, P, _ptr(recs_raw), _ptr(jac), _ptr(theta), int(mode),
+                                            float(max_step), _ptr(step_out), self.stream()))
 
     def snr(self, surfaces, params=None):
         """Peak, SNR and centroid of [B, n, n] float32 device surfaces."""

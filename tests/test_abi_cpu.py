@@ -40,7 +40,7 @@ def test_binding_struct_layouts_match_header():
     from paper_1612_04787_amd import swift as S
     assert C.sizeof(S.Image) == 32
     assert C.sizeof(S.Params) == 24
-    assert S.REC_BYTES == 48
+    assert S.REC_BYTES == 64
 
 
 def test_validation_without_gpu(lib):
@@ -54,3 +54,6 @@ def test_validation_without_gpu(lib):
     assert lib.swift_project(None, None, 1, 1, 1, 1, 1, None, 3, None, 1, 1, None) == -1
     assert lib.swift_snr(None, None, 64, 1, C.byref(pa), None, None) == -1
     assert lib.swift_pyramid(None, None, None, None) == -1
+    assert lib.swift_centroid_jacobian(None, None, 0, C.byref(pr), C.byref(pa), None, None, None, 0, None) == -1
+    assert lib.swift_refine_update(None, 1, None, None, None, 0, 0.5, None, None) == -1
+    assert b"ctx" in lib.swift_last_error()

@@ -68,9 +68,9 @@ def test_adjoint_matches_oracle(ctx, pair_small, n, p, gpgs):
                           save=True)
     gpk = torch.full((k,), gp, device=dev())
     gsn = torch.full((k,), gs, device=dev())
-    ga, gb = ctx.match_backward(res, params, gpk, gsn)
+    ga, gb, hs = ctx.match_backward(res, params, gpk, gsn, want_hess=True)
     torch.cuda.synchronize()
-    ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+    ga, gb, hs = ga.cpu().numpy(), gb.cpu().numpy(), hs.cpu().numpy()
     an, bn = a.numpy(), b.numpy()
     checked = 0
     for i in range(k):
@@ -79,11 +79,51 @@ def test_adjoint_matches_oracle(ctx, pair_small, n, p, gpgs):
         if (rec["peak"] - rec["second"]) <= TIE_REL * abs(rec["peak"]):
             continue  # near-tie: the held-fixed peak may differ
         assert (int(res["ix"][i]), int(res["iy"][i])) == (rec["ix"], rec["iy"])
+        if gpgs == (0.0, 1.0):
+            c = O.match_pair(an, bn, ta[i].astype(np.float64), tb[i].astype(np.float64), n, O.Params(p=p),
+                             return_surface=True)["surface"]
+            href = np.array(O.surface_hessian(c, rec["iy"], rec["ix"]))
+            herr = np.abs(hs[i] - href).max() / np.abs(href).max()
+            print("    ", i, "hessian rel err %.2e" % herr, flush=True)
+            assert herr <= 1e-3, (i, hs[i], href)
         for g_gpu, g_ref, tag in ((ga[i], ra, "A"), (gb[i], rb, "B")):
             x, y = normalised(g_gpu, n), normalised(g_ref, n)
             err = np.linalg.norm(x - y) / np.linalg.norm(y)
             print("   ", i, tag, "rel err %.2e" % err, flush=True)
             assert err <= GRAD_RTOL, (i, tag, err, x, y)
+        checked += 1
+    assert checked >= 1
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("p", [0.65, 0.0, 1.0])
+def test_centroid_jacobian_matches_oracle(ctx, pair_small, n, p):
+    import paper_1612_04787_amd as sw
+    print("case centroid jacobian n=%d p=%g" % (n, p), flush=True)
+    a, b = pair_small
+    rng = np.random.default_rng(5 * n + int(10 * p))
+    k = 3 if n <= 256 else 2
+    ta, tb = _thetas(rng, k, n, 1200)
+    params = sw.make_params(p=p)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(ta), torch.from_numpy(tb), params,
+                          save=True)
+    jac = ctx.centroid_jacobian(res, params)
+    torch.cuda.synchronize()
+    jac = jac.cpu().numpy()
+    an, bn = a.numpy(), b.numpy()
+    checked = 0
+    for i in range(k):
+        rec, ref = O.centroid_jacobian(an, bn, ta[i].astype(np.float64), tb[i].astype(np.float64), n,
+                                       O.Params(p=p))
+        if (rec["peak"] - rec["second"]) <= TIE_REL * abs(rec["peak"]):
+            continue
+        assert (int(res["ix"][i]), int(res["iy"][i])) == (rec["ix"], rec["iy"])
+        for row in range(2):
+            x, y = normalised(jac[i, row], n), normalised(ref[row], n)
+            err = np.linalg.norm(x - y) / np.linalg.norm(y)
+            print("   ", i, "d%s rel err %.2e" % ("xy"[row], err), flush=True)
+            assert err <= GRAD_RTOL, (i, row, err, x, y)
         checked += 1
     assert checked >= 1
 

@@ -377,3 +377,92 @@ def test_adjoint_matches_central_fd(p, eps):
                 fd[q] = (J(rp) - J(rm)) / (2 * h)
             err = np.linalg.norm(g - fd) / np.linalg.norm(fd)
             assert err < 1e-5, (which, p, eps, gp, gs, err, g, fd)
+
+
+# ---------------------------------------------------------------- curvature and refinement steps
+def test_peak_curvature_exact_on_quadratic():
+    # second differences are exact for a quadratic surface around the peak
+    n = 16
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    X, Y = xx - 5, yy - 7
+    c = 10 - (0.8 * X * X + 0.3 * X * Y + 0.5 * Y * Y)
+    rec = O.peak_stats(c)
+    assert (rec["ix"], rec["iy"]) == (5, 7)
+    assert abs(rec["hxx"] + 1.6) < 1e-12 and abs(rec["hyy"] + 1.0) < 1e-12 and abs(rec["hxy"] + 0.3) < 1e-12
+
+
+def test_newton_step_is_exact_for_linear_centroid():
+    # d(t) = J (t - t*): one Newton step from anywhere lands on t*
+    J = np.array([[0.29, -0.02], [0.03, 0.31]])
+    tstar = np.array([0.23, -0.31])
+    t0 = np.array([-0.1, 0.15])
+    d = J @ (t0 - tstar)
+    rec = dict(dx=d[0], dy=d[1], sx=0, sy=0, status=0)
+    jac = np.zeros((2, 6))
+    jac[:, 2] = J[:, 0]
+    jac[:, 5] = J[:, 1]
+    th = np.array([10, 10, 1, 0, t0[0], 0, 1, t0[1]])
+    th2, ln = O.refine_step(rec, th, "newton", jac=jac, max_step=5.0)
+    np.testing.assert_allclose(th2[[4, 7]], tstar, atol=1e-12)
+    assert abs(ln - np.hypot(*(tstar - t0))) < 1e-12
+    # a singular Jacobian falls back to the centroid step
+    th3, _ = O.refine_step(rec, th, "newton", jac=np.zeros((2, 6)), max_step=5.0)
+    np.testing.assert_allclose(th3[[4, 7]], t0 - d, atol=1e-15)
+
+
+def test_centroid_step_and_clamp():
+    rec = dict(dx=0.3, dy=-0.4, sx=0, sy=0, status=0, hxx=-1, hyy=-1, hxy=0)
+    th = np.zeros(8)
+    th2, ln = O.refine_step(rec, th, "centroid")
+    assert (th2[4], th2[7], ln) == (-0.3, 0.4, 0.5)
+    th3, ln = O.refine_step(dict(rec, dx=3.0, dy=4.0), th, "centroid", max_step=1.0)
+    np.testing.assert_allclose([th3[4], th3[7], ln], [-0.6, -0.8, 1.0])
+    # a peak away from the origin takes the centroid (integer) step even in Newton mode
+    th4, _ = O.refine_step(dict(rec, sx=2, dx=2.1), th, "newton", jac=np.eye(2, 6, 2), max_step=5.0)
+    assert th4[4] == -2.1
+
+
+def test_surface_hessian_of_trigonometric_surface():
+    # closed form: second derivatives of a sum of plane waves
+    n = 32
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    w1 = 2 * np.pi * np.array([3, 2]) / n      # (x, y) frequencies
+    w2 = 2 * np.pi * np.array([-5, 1]) / n
+    c = np.cos(w1[0] * xx + w1[1] * yy) + 0.5 * np.sin(w2[0] * xx + w2[1] * yy)
+    x0, y0 = 7, 11
+    p1 = w1[0] * x0 + w1[1] * y0
+    p2 = w2[0] * x0 + w2[1] * y0
+    hxx = -w1[0] ** 2 * np.cos(p1) - 0.5 * w2[0] ** 2 * np.sin(p2)
+    hyy = -w1[1] ** 2 * np.cos(p1) - 0.5 * w2[1] ** 2 * np.sin(p2)
+    hxy = -w1[0] * w1[1] * np.cos(p1) - 0.5 * w2[0] * w2[1] * np.sin(p2)
+    got = O.surface_hessian(c, y0, x0)
+    np.testing.assert_allclose(got, [hxx, hyy, hxy], atol=1e-12)
+
+
+def test_centroid_jacobian_matches_central_fd():
+    # d(dx, dy)/d theta_A with the integer peak and the positive-weight set
+    # held fixed, against central differences of the oracle's own centroid
+    n = 16
+    img = _smooth_img(48, 48, 16)
+    imgB = np.roll(img, (1, -2), axis=(0, 1)) + _smooth_img(48, 48, 17) * 0.05
+    thA = np.array([24.0, 23.0, 1.0013, 0.0021, 0.3, -0.0017, 0.9988, 0.27])
+    thB = np.array([24.0, 23.0, 0.9991, -0.0012, 0.61, 0.0008, 1.0011, 0.58])
+    for p in (0.65, 0.0, 1.0):
+        par = O.Params(p=p, eps_rel=1e-2, taper_frac=0.5)
+        rec, jac = O.centroid_jacobian(img, imgB, thA, thB, n, par)
+        idx = [2, 3, 4, 5, 6, 7]
+        h = 1e-6
+        fd = np.zeros((2, 6))
+        for q in range(6):
+            tp, tm = thA.copy(), thA.copy()
+            tp[idx[q]] += h
+            tm[idx[q]] -= h
+            rp = O.match_pair(img, imgB, tp, thB, n, par)
+            rm = O.match_pair(img, imgB, tm, thB, n, par)
+            assert (rp["ix"], rp["iy"]) == (rm["ix"], rm["iy"]) == (rec["ix"], rec["iy"])
+            fd[0, q] = (rp["dx"] - rm["dx"]) / (2 * h)
+            fd[1, q] = (rp["dy"] - rm["dy"]) / (2 * h)
+        err = np.linalg.norm(jac - fd) / np.linalg.norm(fd)
+        assert err < 1e-5, (p, err, jac, fd)
+        # the translation block is far from zero (the Newton system is well posed)
+        assert abs(np.linalg.det(jac[:, [2, 5]])) > 1e-3
