@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 METRIC = "512² window-pair matches/sec + HBM GB/s; plain vs batched+adjoint at 0.01px"
 HBM_PEAK_GBS = 8000.0
 S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_match_512_headline.txt")
 
 
 def kernel_bytes(name: str, n: int, pairs: int, sections: int, size: int) -> float:
@@ -118,6 +119,70 @@ def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section
                 cpu_seconds=cpu_s, mpx_per_s_per_core=len(jobs) * N * N / cpu_s / 1e6)
 
 
+# --------------------------------------------------------------------------- refinement comparison
+def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
+    """Plain (centroid) vs batched + adjoint (Newton on the centroid) window
+    refinement to a known sub-pixel truth, over the benchmark's 4096 window
+    positions: window B samples section s at a fractional translation t*
+    (U(-0.5, 0.5)^2), window A samples the same section starting U(-0.5,
+    0.5)^2 px away from t*, so the aligned translation of A is exactly t*
+    (bilinear sampling on both sides).  Both drivers stop when the longest
+    step of the batch is below `tol` px.  Reports wall time, iterations, the
+    final RMS / max error, and the iteration and time at which the RMS error
+    first reaches `target`."""
+    import numpy as np
+    import torch
+
+    from paper_1612_04787_amd.refine import refine_adjoint, refine_plain
+    S = stack.shape[0]
+    rng = np.random.default_rng(seed)
+    P = S * len(cen)
+    tb = np.zeros((P, 8), np.float32)
+    k = 0
+    for s in range(S):
+        for (cx, cy) in cen:
+            tb[k] = [cx, cy, 1, 0, rng.uniform(-0.5, 0.5), 0, 1, rng.uniform(-0.5, 0.5)]
+            k += 1
+    ta = tb.copy()
+    ta[:, 4] += rng.uniform(-0.5, 0.5, P).astype(np.float32)
+    ta[:, 7] += rng.uniform(-0.5, 0.5, P).astype(np.float32)
+    images = [stack[s] for s in range(S)]
+    idx = torch.arange(S, device=dev, dtype=torch.int32).repeat_interleave(len(cen))
+    tha, thb = torch.from_numpy(ta).to(dev), torch.from_numpy(tb).to(dev)
+    truth = thb[:, [4, 7]].clone()
+    params = sw.make_params(p=P_WHITEN)
+    n_list = [N] * P
+
+    def rms_max(th):
+        e = (th[:, [4, 7]] - truth).norm(dim=1)
+        return float(e.pow(2).mean().sqrt()), float(e.max())
+
+    out = {}
+    for name, fn, cap in (("plain", refine_plain, 80), ("adjoint", refine_adjoint, 20)):
+        fn(ctx, images, n_list, idx, idx, tha, thb, params, tol=tol, max_iter=2)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th, iters, _ = fn(ctx, images, n_list, idx, idx, tha, thb, params, tol=tol, max_iter=cap)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r, mx = rms_max(th)
+        # untimed: RMS error after each iteration count, to find when it reaches the target
+        hit = None
+        for it in range(1, iters + 1):
+            thi, _, _ = fn(ctx, images, n_list, idx, idx, tha, thb, params, tol=0.0, max_iter=it)
+            if rms_max(thi)[0] <= target:
+                hit = it
+                break
+        out[name] = dict(iterations=iters, wall_ms=wall * 1e3, rms_px=r, max_px=mx,
+                         iters_to_target=hit,
+                         ms_to_target=(wall * 1e3 * hit / iters) if hit else None,
+                         windows_per_s=P / wall)
+    r0 = rms_max(tha)[0]
+    return dict(workload="%d windows of %d^2 (the benchmark's window grid), truth = fractional translation of "
+                         "window B, start U(-0.5, 0.5)^2 px away" % (P, N),
+                start_rms_px=r0, tol_px=tol, target_rms_px=target, **out)
+
+
 # --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -125,6 +190,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-refine", action="store_true", help="skip the plain vs adjoint refinement comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -199,8 +265,14 @@ def main():
         kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     d = kernels[dom]
+    # measured HBM bytes per launch of the dominant kernel (rocprofv3 FETCH_SIZE +
+    # WRITE_SIZE, copy-calibrated), valid only for the kernel sources it was taken on
+    from paper_1612_04787_amd.counters import read_traffic, source_digest
+    traffic, digest = read_traffic(TRAFFIC_FILE, dom)
+    if digest != source_digest():
+        traffic = None
     roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=d["gbs"] / HBM_PEAK_GBS, traffic=None,
+                frac=d["gbs"] / HBM_PEAK_GBS, traffic=traffic,
                 bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
     res = sw.parse_records(out)
     snr = res["snr"].float()
@@ -228,6 +300,14 @@ def main():
         "kernels": kernels,
         "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
     }
+    if not args.no_refine:
+        log("refinement: plain vs batched + adjoint to 0.01 px ...")
+        del ws
+        line["refine"] = refine_comparison(ctx, sw, stack, cen, dev)
+        rf = line["refine"]
+        log("refinement: plain %d it %.1f ms (rms %.2e) | adjoint %d it %.1f ms (rms %.2e)"
+            % (rf["plain"]["iterations"], rf["plain"]["wall_ms"], rf["plain"]["rms_px"],
+               rf["adjoint"]["iterations"], rf["adjoint"]["wall_ms"], rf["adjoint"]["rms_px"]))
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)

@@ -1,0 +1,168 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+  python -m paper_1612_04787_amd.counters stats  KERNEL_STATS_CSV
+  python -m paper_1612_04787_amd.counters pmc    COUNTER_COLLECTION_CSV
+  python -m paper_1612_04787_amd.counters traffic FETCH_CSV WRITE_CSV [--copy-bytes B]
+
+`stats` condenses a `--kernel-trace --stats` run to one line per kernel
+(calls, average and total duration).  `pmc` averages every counter per
+dispatch of each kernel.  `traffic` turns one FETCH_SIZE run and one
+WRITE_SIZE run (KiB per dispatch) into HBM bytes per launch, each scaled by
+the factor that makes the same counter read exactly `copy-bytes` for a plain
+device-to-device copy of that size launched in the same program, and records
+the digest of the kernel sources the numbers belong to.
+
+Kernel names are shortened to `name<N>` (the first template argument is the
+window size), the form the library's own HIP-event timer uses.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import re
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources and headers of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "swift.h")
+    if os.path.exists(inc):
+        with open(inc, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_name(full: str) -> str | None:
+    m = re.search(r"swift::(k_\w+)<(\d+)", full)
+    if m:
+        return "%s<%s>" % (m.group(1), m.group(2))
+    m = re.search(r"swift::(k_\w+)\(", full)
+    if m:
+        return m.group(1)
+    if "copyBuffer" in full or ("elementwise" in full and "copy" in full.lower()):
+        return "copy:" + full.split("(")[0][-60:]
+    return None
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        yield from csv.DictReader(f)
+
+
+def stats(path):
+    out = []
+    for r in _rows(path):
+        name = short_name(r.get("Name", "") or r.get("Kernel_Name", ""))
+        if not name:
+            continue
+        calls = int(r["Calls"])
+        tot = float(r["TotalDurationNs"])
+        out.append((name, calls, tot / calls, tot))
+    out.sort(key=lambda x: -x[3])
+    lines = ["%-26s %7s %12s %12s" % ("kernel", "calls", "avg_ms", "total_ms")]
+    for name, calls, avg, tot in out:
+        lines.append("%-26s %7d %12.4f %12.3f" % (name, calls, avg / 1e6, tot / 1e6))
+    return "\n".join(lines)
+
+
+def per_kernel_counters(path):
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in _rows(path):
+        name = short_name(r.get("Kernel_Name", ""))
+        if not name:
+            continue
+        acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return acc
+
+
+def pmc(path):
+    acc = per_kernel_counters(path)
+    lines = []
+    for name in sorted(acc):
+        lines.append(name)
+        for c, vals in sorted(acc[name].items()):
+            lines.append("    %-28s dispatches=%-5d mean=%.6g min=%.6g max=%.6g"
+                         % (c, len(vals), sum(vals) / len(vals), min(vals), max(vals)))
+    return "\n".join(lines)
+
+
+def traffic(fetch_csv, write_csv, copy_bytes):
+    f = per_kernel_counters(fetch_csv)
+    w = per_kernel_counters(write_csv)
+
+    def mean(d, name, ctr):
+        v = d.get(name, {}).get(ctr, [])
+        return sum(v) / len(v) if v else None
+
+    copies = [k for k in f if k.startswith("copy:")]
+    if not copies:
+        raise SystemExit("no copy kernel in %s: run the program with its calibration copy" % fetch_csv)
+    # the calibration copy is the largest copy dispatch
+    cf = max(max(f[k]["FETCH_SIZE"]) for k in copies)
+    cw = max(max(w[k]["WRITE_SIZE"]) for k in copies if k in w)
+    kf = copy_bytes / (cf * 1024.0)
+    kw = copy_bytes / (cw * 1024.0)
+    lines = ["calibration: %d-byte copy reads FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB" % (copy_bytes, cf, cw),
+             "scale_fetch %.4f" % kf, "scale_write %.4f" % kw, "source_digest %s" % source_digest(),
+             "%-26s %16s %16s %16s" % ("kernel", "read_B/launch", "write_B/launch", "traffic_B/launch")]
+    for name in sorted(k for k in f if not k.startswith("copy:")):
+        fr, wr = mean(f, name, "FETCH_SIZE"), mean(w, name, "WRITE_SIZE")
+        if fr is None or wr is None:
+            continue
+        rb, wb = fr * 1024.0 * kf, wr * 1024.0 * kw
+        lines.append("%-26s %16.4g %16.4g %16.4g" % (name, rb, wb, rb + wb))
+    return "\n".join(lines)
+
+
+def read_traffic(path, kernel):
+    """(traffic bytes per launch of `kernel`, digest) from a `traffic` summary,
+    or (None, None) if the file or the kernel is absent."""
+    if not os.path.exists(path):
+        return None, None
+    digest, val = None, None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_digest":
+                digest = parts[1]
+            if len(parts) == 4 and parts[0] == kernel:
+                try:
+                    val = float(parts[3])
+                except ValueError:
+                    pass
+    return val, digest
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="rocprofv3 summaries for the library's kernels")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a = sub.add_parser("pmc")
+    a.add_argument("csv")
+    a = sub.add_parser("traffic")
+    a.add_argument("fetch_csv")
+    a.add_argument("write_csv")
+    a.add_argument("--copy-bytes", type=int, default=1 << 30)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        print(stats(args.csv))
+    elif args.cmd == "pmc":
+        print(pmc(args.csv))
+    else:
+        print(traffic(args.fetch_csv, args.write_csv, args.copy_bytes))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -325,17 +325,24 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   if (tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
   // per-row parameters (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
   if (tid < 2 * R) {
-    const int m = tid / R, r = tid % R;
+    // image chosen by value selects (an index into the per-image arrays would
+    // send them to per-lane scratch memory)
+    const bool mb = tid >= R;
+    const int r = tid % R;
+    const double xc = mb ? ra[1].xc : ra[0].xc, yc = mb ? ra[1].yc : ra[0].yc;
+    const double a12 = mb ? ra[1].a12 : ra[0].a12, a22 = mb ? ra[1].a22 : ra[0].a22;
+    const int xo = mb ? (tg[1].use ? tg[1].xlo : 0) : (tg[0].use ? tg[0].xlo : 0);
+    const int yo = mb ? (tg[1].use ? tg[1].ylo : 0) : (tg[0].use ? tg[0].ylo : 0);
     const double v = (double)(y0 + r - N / 2);
-    const double X = fmin(fmax(ra[m].xc + ra[m].a12 * v, -1e9), 1e9);
-    const double Y = fmin(fmax(ra[m].yc + ra[m].a22 * v, -1e9), 1e9);
+    const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
+    const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
     const double bxd = floor(X), byd = floor(Y);
     RowParam p;
-    p.bx = (int)bxd - (tg[m].use ? tg[m].xlo : 0);
-    p.by = (int)byd - (tg[m].use ? tg[m].ylo : 0);
+    p.bx = (int)bxd - xo;
+    p.by = (int)byd - yo;
     p.fx = (float)(X - bxd);
     p.fy = (float)(Y - byd);
-    rparam[m][r] = p;
+    rparam[mb ? 1 : 0][r] = p;
   } else if (tid >= 64 && tid < 64 + R) {
     trow[tid - 64] = a.taper[y0 + tid - 64];
   }

@@ -1,0 +1,112 @@
+"""Parity at full size, in the launch configuration the benchmark times: the
+whole batch goes through the C ABI in one call and sampled outputs are checked
+one by one against the FP64 oracle (which reads the same input bytes, cropped
+with a margin that reproduces every read of the window, including clamped
+reads at the section border).  Properties that hold for every output are
+checked on all of them."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from parity_util import compare, gpu_record
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1612_04787_amd as sw
+    c = sw.Swift(0)
+    yield c
+    c.close()
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def _crop(cx, cy, n, H, W, m=4):
+    x0, y0 = int(max(cx - n // 2 - m, 0)), int(max(cy - n // 2 - m, 0))
+    x1, y1 = int(min(cx + n // 2 + m, W)), int(min(cy + n // 2 + m, H))
+    return x0, y0, x1, y1
+
+
+def _check_all_records(res, n, P):
+    assert res["n"].shape[0] == P
+    assert bool((res["n"] == n).all())
+    for key in ("dx", "dy", "peak", "snr"):
+        assert bool(torch.isfinite(res[key]).all()), key
+    assert bool((res["std"] > 0).all())
+    assert bool((res["snr"] > 0).all())
+    # the record's shift is the wrapped integer peak plus a centroid inside the 3 x 3 box
+    ix, iy = res["ix"].long(), res["iy"].long()
+    sx = torch.where(ix >= n // 2, ix - n, ix).float()
+    sy = torch.where(iy >= n // 2, iy - n, iy).float()
+    assert bool(((res["dx"] - sx).abs() <= 1.0).all()) and bool(((res["dy"] - sy).abs() <= 1.0).all())
+
+
+def test_headline_batch_4096_pairs_512(ctx):
+    """64 sections of 4096^2 (drift + affine distortion), references = +-3
+    z-projections, 8 x 8 windows of 512^2 per section: 4096 pairs in one call."""
+    import paper_1612_04787_amd as sw
+    from datagen.workloads import distorted_stack, section_grid_pairs
+    S, size, n, k = 64, 4096, 512, 3
+    print("case headline generate", flush=True)
+    stack, _ = distorted_stack(S, size, seed=5, device=dev())
+    refs = ctx.project(stack, k=k)
+    images = [stack[s] for s in range(S)] + [refs[s] for s in range(S)]
+    n_list, ia, ib, ta, tb, cen = section_grid_pairs(S, size, n, 8, dev())
+    P = len(n_list)
+    print("case headline match P=%d" % P, flush=True)
+    res = ctx.match_batch(images, n_list, ia, ib, ta, tb, sw.make_params(p=0.65))
+    torch.cuda.synchronize()
+    _check_all_records(res, n, P)
+    rng = np.random.default_rng(2024)
+    picks = rng.choice(P, 12, replace=False)
+    for i in picks:
+        s, w = int(i) // len(cen), int(i) % len(cen)
+        cx, cy = cen[w]
+        x0, y0, x1, y1 = _crop(cx, cy, n, size, size)
+        lo, hi = max(0, s - k), min(S, s + k + 1)
+        sub = stack[lo:hi, y0:y1, x0:x1].cpu().numpy()
+        ref_o = O.project(sub, s - lo, k)
+        ref_g = refs[s, y0:y1, x0:x1].cpu().numpy()
+        assert np.array_equal(ref_g, ref_o), ("projection", s, w)
+        th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+        r = O.match_pair(sub[s - lo], ref_o, th, th, n, O.Params(p=0.65))
+        e = compare(gpu_record(res, int(i)), r, n, tag="headline pair %d" % i)
+        print("   pair %d (section %d window %d):" % (i, s, w), e, flush=True)
+
+
+def test_section_pair_256_windows_1024(ctx):
+    """A 16384^2 section pair (B = bilinear affine warp of A plus noise) on a
+    16 x 16 grid of 1024^2 windows: 256 pairs in one call; sampled windows
+    against the oracle, and every window's shift against the known warp."""
+    import paper_1612_04787_amd as sw
+    from datagen.workloads import section_pair_1024
+    print("case 1024 generate", flush=True)
+    a, b, m, bv, n_list, ia, ib, ta, tb = section_pair_1024(16384, dev())
+    P, n = len(n_list), 1024
+    print("case 1024 match P=%d" % P, flush=True)
+    res = ctx.match_batch([a, b], n_list, ia, ib, ta, tb, sw.make_params(p=0.65))
+    torch.cuda.synchronize()
+    _check_all_records(res, n, P)
+    # B(q) = A(M q + b) = A(q - d(q)) with d(q) = q - M q - b, so the peak of a
+    # window centred at q is near +d(q) (the centroid is biased toward the integer)
+    cen = ta[:, :2].cpu().numpy().astype(np.float64)
+    d_true = cen - cen @ np.asarray(m, np.float64).T - np.asarray(bv, np.float64)
+    got = np.stack([res["dx"].cpu().numpy(), res["dy"].cpu().numpy()], 1)
+    err = np.abs(got - d_true).max(1)
+    print("   |d - d_true|: median %.3f max %.3f px" % (np.median(err), err.max()), flush=True)
+    assert np.median(err) <= 0.5 and err.max() <= 1.5
+    rng = np.random.default_rng(7)
+    for i in rng.choice(P, 4, replace=False):
+        cx, cy = cen[i]
+        x0, y0, x1, y1 = _crop(cx, cy, n, 16384, 16384)
+        ca = a[y0:y1, x0:x1].cpu().numpy()
+        cb = b[y0:y1, x0:x1].cpu().numpy()
+        th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+        r = O.match_pair(ca, cb, th, th, n, O.Params(p=0.65))
+        e = compare(gpu_record(res, int(i)), r, n, tag="1024 pair %d" % i)
+        print("   pair %d:" % i, e, flush=True)
