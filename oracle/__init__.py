@@ -17,6 +17,14 @@ from .swift_oracle import (  # noqa: F401
     project,
     pyramid,
     fit_affine,
+    level_to_base,
+    base_to_level,
+    apply_affine,
+    render,
+    stack_windows,
+    correspondence,
+    match_weight,
+    fit_section,
     refine_step,
     centroid_jacobian,
     surface_hessian,

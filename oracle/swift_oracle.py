@@ -424,3 +424,101 @@ def fit_affine(src, dst, weights=None):
     sw = np.sqrt(wts)[:, None]
     A, *_ = np.linalg.lstsq(D * sw, dst * sw, rcond=None)
     return A.T
+
+
+# ---------------------------------------------------------------------------
+# Stack loop (Sections III-IV): iscale levels, mir rendering by a section
+# affine, swim windows through the affine against the remod model, and the
+# least-squares affine of the correspondences.
+#
+# A section affine maps aligned-frame points p to raw-section points q, both in
+# level-0 pixels: q = L p + t, stored as (a11, a12, tx, a21, a22, ty).  A level-l
+# pyramid pixel x_l covers level-0 pixels 2^l x_l .. 2^l x_l + 2^l - 1, so its
+# centre is x_0 = 2^l x_l + (2^l - 1) / 2.
+# ---------------------------------------------------------------------------
+STACK_FIT_SINGULAR = 1
+
+
+def level_to_base(x, level):
+    s = float(1 << level)
+    return np.asarray(x, dtype=np.float64) * s + (s - 1.0) / 2.0
+
+
+def base_to_level(x0, level):
+    s = float(1 << level)
+    return (np.asarray(x0, dtype=np.float64) - (s - 1.0) / 2.0) / s
+
+
+def apply_affine(aff, x, y):
+    a11, a12, tx, a21, a22, ty = [float(v) for v in aff]
+    return a11 * x + a12 * y + tx, a21 * x + a22 * y + ty
+
+
+def render(img, aff, level, out_h, out_w):
+    """mir, one section: out[y][x] = bilinear value of the level-l image img at
+    the raw point of aligned pixel (x, y), rounded half up to uint8:
+    q_l = base_to_level(aff(level_to_base(x, y)))."""
+    yy, xx = np.meshgrid(np.arange(out_h, dtype=np.float64), np.arange(out_w, dtype=np.float64), indexing="ij")
+    qx, qy = apply_affine(aff, level_to_base(xx, level), level_to_base(yy, level))
+    v, _ = bilinear_clamped(img, base_to_level(qx, level), base_to_level(qy, level))
+    return np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8)
+
+
+def stack_windows(aff, level, n, grid, h_l, w_l):
+    """swim windows of one section at level l: a grid x grid tiling of n x n
+    windows of the level-l aligned frame.  Window B reads the model at the
+    tile centre p (identity); window A reads the raw section around the raw
+    point of p, with the section's linear part.  The raw centre is split into
+    a rounded part (cx, cy) and the remainder (tx, ty).  Returns float64
+    (theta_a [grid^2, 8], theta_b [grid^2, 8])."""
+    a11, a12, _, a21, a22, _ = [float(v) for v in aff]
+    sx, sy = w_l // grid, h_l // grid
+    ta = np.zeros((grid * grid, 8))
+    tb = np.zeros((grid * grid, 8))
+    for j in range(grid):
+        for i in range(grid):
+            k = j * grid + i
+            px, py = sx // 2 + i * sx, sy // 2 + j * sy
+            qx, qy = apply_affine(aff, level_to_base(px, level), level_to_base(py, level))
+            cx, cy = base_to_level(qx, level), base_to_level(qy, level)
+            rx, ry = np.rint(cx), np.rint(cy)
+            ta[k] = [rx, ry, a11, a12, cx - rx, a21, a22, cy - ry]
+            tb[k] = [px, py, 1, 0, 0, 0, 1, 0]
+    return ta, tb
+
+
+def correspondence(theta_a, theta_b, dx, dy, level):
+    """Level-0 (p, q) of one match: the model point at the centre of window B,
+    and the raw point that window A maps to it.  A window pair whose content
+    satisfies B(x) = A(x - d) aligns A's window point -d with B's centre."""
+    cxa, cya, a11, a12, txa, a21, a22, tya = [float(v) for v in theta_a]
+    cxb, cyb, _, _, txb, _, _, tyb = [float(v) for v in theta_b]
+    p = (level_to_base(cxb + txb, level), level_to_base(cyb + tyb, level))
+    qx = cxa + txa - a11 * dx - a12 * dy
+    qy = cya + tya - a21 * dx - a22 * dy
+    return p, (level_to_base(qx, level), level_to_base(qy, level))
+
+
+def match_weight(snr, status, min_snr):
+    """Weight of a correspondence in the section fit: its SNR, or 0 for a
+    degenerate window or an SNR below min_snr."""
+    if (status & STATUS_DEGENERATE) or not (snr >= min_snr):
+        return 0.0
+    return float(snr)
+
+
+def fit_section(p, q, w, prev):
+    """mir's least-squares affine of one section from its correspondences (p ->
+    q, weights w).  Fewer than three weighted points, or points on one line,
+    keep `prev` and report STACK_FIT_SINGULAR.  Returns (aff [6], status)."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    if np.count_nonzero(w > 0) < 3:
+        return np.asarray(prev, dtype=np.float64).copy(), STACK_FIT_SINGULAR
+    pc = p - np.sum(w[:, None] * p, 0) / np.sum(w)
+    G = (w[:, None, None] * pc[:, :, None] * pc[:, None, :]).sum(0)
+    if np.linalg.det(G) <= 1e-12 * np.trace(G) ** 2:
+        return np.asarray(prev, dtype=np.float64).copy(), STACK_FIT_SINGULAR
+    A = fit_affine(p, q, w)
+    return np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 0], A[1, 1], A[1, 2]]), 0

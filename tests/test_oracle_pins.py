@@ -466,3 +466,99 @@ def test_centroid_jacobian_matches_central_fd():
         assert err < 1e-5, (p, err, jac, fd)
         # the translation block is far from zero (the Newton system is well posed)
         assert abs(np.linalg.det(jac[:, [2, 5]])) > 1e-3
+
+
+# ---------------------------------------------------------------- stack loop: levels, render, windows, fit
+def test_level_coordinates_match_the_pyramid_of_a_ramp():
+    # the 2 x 2 box mean of a linear ramp is the ramp at the block centre, so the
+    # x2 pyramid of an integer ramp is the ramp at level_to_base, rounded half up
+    yy, xx = np.mgrid[0:64, 0:96].astype(np.int64)
+    ramp = (xx + 2 * yy + 7).astype(np.uint8)  # stays below 256
+    lvl = ramp
+    for level in (1, 2):
+        lvl = O.pyramid(lvl)
+        h, w = lvl.shape
+        y1, x1 = np.mgrid[0:h, 0:w].astype(np.float64)
+        exact = O.level_to_base(x1, level) + 2 * O.level_to_base(y1, level) + 7
+        np.testing.assert_array_equal(lvl, np.floor(exact + 0.5).astype(np.uint8))
+    np.testing.assert_allclose(O.base_to_level(O.level_to_base(np.arange(5.0), 3), 3), np.arange(5.0))
+
+
+def test_render_identity_and_integer_translation():
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, (40, 56)).astype(np.uint8)
+    out = O.render(img, [1, 0, 0, 0, 1, 0], 0, 40, 56)
+    np.testing.assert_array_equal(out, img)
+    # q = p + (3, -2): out[y][x] = img[clamp(y - 2)][clamp(x + 3)]
+    out = O.render(img, [1, 0, 3, 0, 1, -2], 0, 40, 56)
+    yy, xx = np.mgrid[0:40, 0:56]
+    np.testing.assert_array_equal(out, img[np.clip(yy - 2, 0, 39), np.clip(xx + 3, 0, 55)])
+    # at level 2 a level-0 translation of (8, -4) moves level-2 pixels by (2, -1)
+    out = O.render(img, [1, 0, 8, 0, 1, -4], 2, 40, 56)
+    np.testing.assert_array_equal(out, img[np.clip(yy - 1, 0, 39), np.clip(xx + 2, 0, 55)])
+
+
+def test_render_reproduces_an_affine_ramp():
+    # bilinear interpolation is exact on a linear ramp, so rendering a ramp by
+    # any affine gives the ramp at the mapped points (rounded half up)
+    yy, xx = np.mgrid[0:80, 0:80].astype(np.float64)
+    img = (40 + xx + 1.0 * yy).astype(np.uint8)
+    aff = [0.999, 0.012, 3.37, -0.011, 1.002, 2.71]
+    out = O.render(img, aff, 0, 60, 60).astype(np.int64)
+    y1, x1 = np.mgrid[0:60, 0:60].astype(np.float64)
+    qx, qy = O.apply_affine(aff, x1, y1)
+    exact = 40 + qx + qy
+    ref = np.floor(exact + 0.5)
+    safe = np.abs(exact - np.floor(exact) - 0.5) > 1e-6
+    np.testing.assert_array_equal(out[safe], ref[safe])
+
+
+def test_render_matches_scipy_map_coordinates():
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(8)
+    img = rng.integers(0, 256, (50, 70)).astype(np.float64)
+    aff = [1.01, -0.02, 1.3, 0.015, 0.99, -2.2]
+    for level in (0, 1):
+        out = O.render(img.astype(np.uint8), aff, level, 45, 66)
+        y1, x1 = np.mgrid[0:45, 0:66].astype(np.float64)
+        qx, qy = O.apply_affine(aff, O.level_to_base(x1, level), O.level_to_base(y1, level))
+        v = map_coordinates(img, [O.base_to_level(qy, level), O.base_to_level(qx, level)], order=1, mode="nearest")
+        np.testing.assert_array_equal(out, np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8))
+
+
+def test_stack_windows_and_correspondence():
+    ta, tb = O.stack_windows([1, 0, 0, 0, 1, 0], 1, 64, 4, 256, 256)
+    np.testing.assert_array_equal(ta, tb)
+    assert tuple(tb[5, :2]) == (96, 96)
+    # a level-0 translation (8, -6) shifts level-1 raw centres by (4, -3)
+    ta, tb = O.stack_windows([1, 0, 8, 0, 1, -6], 1, 64, 4, 256, 256)
+    np.testing.assert_allclose(ta[:, 0] + ta[:, 4] - tb[:, 0], 4.0)
+    np.testing.assert_allclose(ta[:, 1] + ta[:, 7] - tb[:, 1], -3.0)
+    # fractional centres: rounded part plus remainder
+    ta, _ = O.stack_windows([1.001, 0, 0.3, 0, 1, 0.2], 0, 64, 4, 256, 256)
+    assert np.all(np.abs(ta[:, 4]) <= 0.5) and np.all(ta[:, 0] == np.rint(ta[:, 0]))
+    # correspondence at level 1: model centre p, raw point = A's centre - L d
+    p, q = O.correspondence([100, 50, 1, 0, 0.25, 0, 1, -0.5], [96, 52, 1, 0, 0, 0, 1, 0], 1.0, 2.0, 1)
+    np.testing.assert_allclose(p, (2 * 96 + 0.5, 2 * 52 + 0.5))
+    np.testing.assert_allclose(q, (2 * (100.25 - 1.0) + 0.5, 2 * (49.5 - 2.0) + 0.5))
+
+
+def test_fit_section_exact_and_singular():
+    rng = np.random.default_rng(21)
+    A = np.array([1.002, -0.003, 4.5, 0.001, 0.998, -7.25])
+    p = rng.uniform(0, 4096, (64, 2))
+    q = np.stack(O.apply_affine(A, p[:, 0], p[:, 1]), 1)
+    w = rng.uniform(5, 40, 64)
+    aff, st = O.fit_section(p, q, w, np.zeros(6))
+    assert st == 0
+    np.testing.assert_allclose(aff, A, rtol=0, atol=1e-9)
+    # two weighted points, and collinear points, keep the previous affine
+    prev = np.array([1, 0, 1, 0, 1, 2.0])
+    w2 = np.zeros(64)
+    w2[:2] = 1
+    assert O.fit_section(p, q, w2, prev)[1] == O.swift_oracle.STACK_FIT_SINGULAR
+    pl = np.stack([np.linspace(0, 100, 64), np.linspace(0, 50, 64)], 1)
+    aff, st = O.fit_section(pl, pl, np.ones(64), prev)
+    assert st == O.swift_oracle.STACK_FIT_SINGULAR and np.array_equal(aff, prev)
+    assert O.match_weight(20.0, 0, 6.0) == 20.0 and O.match_weight(5.0, 0, 6.0) == 0.0
+    assert O.match_weight(20.0, O.swift_oracle.STATUS_DEGENERATE, 6.0) == 0.0
