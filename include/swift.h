@@ -222,6 +222,55 @@ int swift_refine_update(swift_ctx* ctx, int32_t P, const swift_match* recs, cons
                         float* theta, int32_t mode, float max_step, float* step_out,
                         hipStream_t stream);
 
+/* ---- Stack loop (Sections III-IV: swim matches a section to its remod model,
+ * mir renders it by the least-squares affine of the matches, repeated over
+ * iscale levels).  A section affine maps aligned-frame points p to raw-section
+ * points q, both in level-0 pixels: q = L p + t, stored as double
+ * (a11, a12, tx, a21, a22, ty).  Pixel x_l of pyramid level l has its centre at
+ * level-0 coordinate 2^l x_l + (2^l - 1)/2. */
+
+/* mir rendering of S sections: dst(s, y, x) = bilinear value (clamp to edge)
+ * of the level-l raw section src(s) at the raw point of aligned pixel (x, y),
+ * rounded half up to uint8.  Coordinates and interpolation are FP64 with every
+ * operation rounded separately, so the result is reproducible bit for bit.
+ *  src   device uint8, pixel (s, y, x) at src[s*src_stride + y*src_pitch + x].
+ *  aff   device double [S][6], level-0 affines.
+ *  dst   device uint8 [S] x dst_h x dst_w with dst_pitch, dst_stride; must not
+ *        overlap src.
+ * Errors: SWIFT_E_INVAL (NULL, sizes < 1, pitches/strides too small, level
+ * outside 0..12), SWIFT_E_HIP. */
+int swift_render(swift_ctx* ctx, const uint8_t* src, int32_t S, int32_t src_h, int32_t src_w,
+                 int64_t src_pitch, int64_t src_stride, const double* aff, int32_t level,
+                 uint8_t* dst, int32_t dst_h, int32_t dst_w, int64_t dst_pitch, int64_t dst_stride,
+                 hipStream_t stream);
+
+/* swim window set-up for S sections at level l: a grid x grid tiling of n x n
+ * windows of the h_l x w_l aligned frame (tile size h_l/grid, w_l/grid, centres
+ * at half a tile).  Pair i = s*grid^2 + k (k row-major).  Window B reads the
+ * model at the tile centre at identity: theta_b = (px, py, 1, 0, 0, 0, 1, 0).
+ * Window A reads the raw section around the raw point c of that centre with
+ * the section's linear part: theta_a = (rint(cx), rint(cy), a11, a12,
+ * cx - rint(cx), a21, a22, cy - rint(cy)).  img_a[i] = img_a0 + s, img_b[i] =
+ * img_b0 + s.  All outputs are device arrays of S*grid^2 entries (theta [8]).
+ * Errors: SWIFT_E_INVAL. */
+int swift_stack_windows(swift_ctx* ctx, int32_t S, const double* aff, int32_t level, int32_t grid,
+                        int32_t h_l, int32_t w_l, int32_t img_a0, int32_t img_b0,
+                        float* theta_a, float* theta_b, int32_t* img_a, int32_t* img_b,
+                        hipStream_t stream);
+
+/* mir's affine of each section from its `per_section` window matches (pairs
+ * s*per_section .. (s+1)*per_section - 1): model point p = centre of window B,
+ * raw point q = window A's point -(dx, dy) (a pair with B(x) = A(x - d) aligns
+ * them), both mapped to level 0; weight = snr, or 0 when the record is
+ * degenerate or snr < min_snr.  aff [S][6] (device, double) holds the previous
+ * affines and receives the weighted least-squares fit q ~ L p + t; a section
+ * with fewer than three weighted points, or with collinear points, keeps its
+ * previous affine and gets status 1 (else 0).  status: device [S] or NULL.
+ * Errors: SWIFT_E_INVAL. */
+int swift_fit_sections(swift_ctx* ctx, int32_t S, int32_t per_section, const float* theta_a,
+                       const float* theta_b, const swift_match* recs, int32_t level, float min_snr,
+                       double* aff, int32_t* status, hipStream_t stream);
+
 /* Kernel timing (instrumentation, not in the paper).  While enabled, every
  * kernel the context launches is bracketed by a pair of HIP events recorded on
  * the launch stream (a few microseconds per launch; no work is skipped).

@@ -506,6 +506,55 @@ int swift_refine_update(swift_ctx* ctx, int32_t P, const swift_match* recs, cons
   return ok();
 }
 
+int swift_render(swift_ctx* ctx, const uint8_t* src, int32_t S, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                 int64_t src_stride, const double* aff, int32_t level, uint8_t* dst, int32_t dst_h, int32_t dst_w,
+                 int64_t dst_pitch, int64_t dst_stride, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!src || !dst || !aff) return fail(SWIFT_E_INVAL, "src/dst/aff is NULL");
+  if (S < 1 || src_h < 1 || src_w < 1 || dst_h < 1 || dst_w < 1) return fail(SWIFT_E_INVAL, "bad sizes");
+  if (dst_h > 65535 || S > 65535) return fail(SWIFT_E_INVAL, "dst_h and S must be at most 65535");
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  if (src_pitch < src_w || dst_pitch < dst_w) return fail(SWIFT_E_INVAL, "pitch smaller than width");
+  if (src_stride < src_pitch * src_h || dst_stride < dst_pitch * dst_h)
+    return fail(SWIFT_E_INVAL, "section stride smaller than height * pitch");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_render(src, src_pitch, src_stride, S, src_h, src_w, aff, level, dst, dst_pitch, dst_stride,
+                               dst_h, dst_w, stream);
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  return ok();
+}
+
+int swift_stack_windows(swift_ctx* ctx, int32_t S, const double* aff, int32_t level, int32_t grid, int32_t h_l,
+                        int32_t w_l, int32_t img_a0, int32_t img_b0, float* theta_a, float* theta_b, int32_t* img_a,
+                        int32_t* img_b, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!aff || !theta_a || !theta_b || !img_a || !img_b) return fail(SWIFT_E_INVAL, "NULL output or affine");
+  if (S < 1 || grid < 1 || h_l < grid || w_l < grid) return fail(SWIFT_E_INVAL, "bad sizes");
+  if ((long long)S * grid * grid > (1LL << 30)) return fail(SWIFT_E_INVAL, "too many windows");
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_stack_windows(S, aff, level, grid, h_l, w_l, img_a0, img_b0, theta_a, theta_b, img_a, img_b,
+                                      stream);
+  if (e != hipSuccess) return hip_fail(e, "window launch");
+  return ok();
+}
+
+int swift_fit_sections(swift_ctx* ctx, int32_t S, int32_t per_section, const float* theta_a, const float* theta_b,
+                       const swift_match* recs, int32_t level, float min_snr, double* aff, int32_t* status,
+                       hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!theta_a || !theta_b || !recs || !aff) return fail(SWIFT_E_INVAL, "NULL input or affine");
+  if (S < 1 || per_section < 1) return fail(SWIFT_E_INVAL, "bad sizes");
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_fit_sections(S, per_section, theta_a, theta_b, recs, level, min_snr, aff, status, stream);
+  if (e != hipSuccess) return hip_fail(e, "fit launch");
+  return ok();
+}
+
 int swift_profile_enable(swift_ctx* ctx, int enable) {
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   ctx->profile = enable != 0;

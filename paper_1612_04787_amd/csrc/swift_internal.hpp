@@ -135,6 +135,13 @@ hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTi
 hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);
 int col_items_per_wg(int n);  // column-pass workgroups per pair
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
+hipError_t launch_render(const uint8_t* src, int64_t spitch, int64_t sstride, int S, int sh, int sw,
+                         const double* aff, int level, uint8_t* dst, int64_t dpitch, int64_t dstride, int dh, int dw,
+                         hipStream_t st);
+hipError_t launch_stack_windows(int S, const double* aff, int level, int grid, int hl, int wl, int img_a0,
+                                int img_b0, float* th_a, float* th_b, int32_t* ia, int32_t* ib, hipStream_t st);
+hipError_t launch_fit_sections(int S, int per, const float* th_a, const float* th_b, const swift_match* rec,
+                               int level, float min_snr, double* aff, int32_t* status, hipStream_t st);
 hipError_t launch_refine(int P, const swift_match* rec, const float* jac, float* th, int mode, float max_step,
                          float* step_out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,

@@ -28,8 +28,20 @@ def _state(sw, images, n_list, img_a, img_b, theta_a, theta_b):
     return prep, prep["keep"][2]  # device theta_a updated in place
 
 
+def _done(step, tol, stop_frac):
+    """Longest step of the batch (for the history) and whether to stop: every
+    step below tol, or (stop_frac > 0) at most that fraction of them not."""
+    if step.numel() == 0:
+        return 0.0, True
+    if stop_frac > 0.0:
+        m, frac = torch.stack([step.max(), (step >= tol).float().mean()]).tolist()
+        return m, frac <= stop_frac
+    m = float(step.max())
+    return m, m < tol
+
+
 def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=60,
-                 max_step=0.5):
+                 max_step=0.5, stop_frac=0.0):
     """Returns (theta_a [P, 8], iterations, list of longest steps)."""
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
     P = prep["pairs"].n_pairs
@@ -39,16 +51,20 @@ def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol
     for it in range(1, max_iter + 1):
         sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out)
         sw.refine_update(out, th, CENTROID, None, max_step, step)
-        m = float(step.max()) if P else 0.0
+        m, stop = _done(step, tol, stop_frac)
         hist.append(m)
-        if m < tol:
+        if stop:
             return th, it, hist
     return th, max_iter, hist
 
 
 def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                   max_step=0.5):
-    """Returns (theta_a [P, 8], iterations, list of longest steps)."""
+                   max_step=0.5, stop_frac=0.0, jac_iters=None):
+    """Returns (theta_a [P, 8], iterations, list of longest steps).
+
+    jac_iters: the Jacobian is recomputed on the first jac_iters iterations
+    and reused afterwards (a chord Newton step, with a plain forward pass);
+    None recomputes it every iteration."""
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
     P = prep["pairs"].n_pairs
     out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=sw.device)
@@ -58,11 +74,14 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
     step = torch.empty(P, dtype=torch.float32, device=sw.device)
     hist = []
     for it in range(1, max_iter + 1):
-        sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved)
-        sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, saved, jac)
+        fresh = jac_iters is None or it <= jac_iters
+        sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out,
+                           saved=saved if fresh else None)
+        if fresh:
+            sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, saved, jac)
         sw.refine_update(out, th, NEWTON, jac, max_step, step)
-        m = float(step.max()) if P else 0.0
+        m, stop = _done(step, tol, stop_frac)
         hist.append(m)
-        if m < tol:
+        if stop:
             return th, it, hist
     return th, max_iter, hist

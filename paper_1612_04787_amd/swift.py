@@ -70,12 +70,16 @@ def load_library(path: str = LIB_PATH):
     lib.swift_snr.argtypes = [vp, vp, i32, i32, C.POINTER(Params), vp, vp]
     lib.swift_centroid_jacobian.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, sz, vp]
     lib.swift_refine_update.argtypes = [vp, i32, vp, vp, vp, i32, C.c_float, vp, vp]
+    lib.swift_render.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i32, i32, i64, i64, vp]
+    lib.swift_stack_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.swift_fit_sections.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp]
     lib.swift_profile_enable.argtypes = [vp, C.c_int]
     lib.swift_profile_read.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32)]
     lib.swift_last_error.restype = C.c_char_p
     for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
               "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read",
-              "swift_refine_update", "swift_centroid_jacobian"):
+              "swift_refine_update", "swift_centroid_jacobian", "swift_render", "swift_stack_windows",
+              "swift_fit_sections"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -85,7 +89,7 @@ def exported_symbols():
     return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
             "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
             "swift_profile_enable", "swift_profile_read", "swift_refine_update",
-            "swift_centroid_jacobian"]
+            "swift_centroid_jacobian", "swift_render", "swift_stack_windows", "swift_fit_sections"]
 
 
 def _check(rc):
@@ -290,10 +294,11 @@ class Swift:
                                       int(k), _ptr(out), out.stride(1), out.stride(0), self.stream()))
         return out
 
-    def pyramid(self, img):
+    def pyramid(self, img, out=None):
         assert img.dtype == torch.uint8 and img.dim() == 2 and img.stride(1) == 1
         h, w = img.shape
-        dst = torch.empty((h // 2, w // 2), dtype=torch.uint8, device=img.device)
+        dst = out if out is not None else torch.empty((h // 2, w // 2), dtype=torch.uint8, device=img.device)
+        assert dst.shape == (h // 2, w // 2) and dst.stride(1) == 1
         si = Image(img.data_ptr(), w, h, img.stride(0), SWIFT_U8, 0)
         di = Image(dst.data_ptr(), w // 2, h // 2, dst.stride(0), SWIFT_U8, 0)
         _check(self.lib.swift_pyramid(self.h, C.byref(si), C.byref(di), self.stream()))
@@ -314,6 +319,46 @@ class Swift:
         P = theta.shape[0]
         _check(self.lib.swift_refine_update(self.h, P, _ptr(recs_raw), _ptr(jac), _ptr(theta), int(mode),
                                             float(max_step), _ptr(step_out), self.stream()))
+
+    # ------------------------------------------------------------------ stack loop
+    def render(self, src, aff, level, out_hw=None, out=None):
+        """mir rendering of a [S, H, W] uint8 device stack (level-l raw
+        sections) by level-0 affines aff [S, 6] float64 (device)."""
+        assert src.dtype == torch.uint8 and src.dim() == 3 and src.stride(2) == 1
+        assert aff.dtype == torch.float64 and aff.is_contiguous() and aff.shape == (src.shape[0], 6)
+        S, H, W = src.shape
+        if out is None:
+            oh, ow = out_hw if out_hw is not None else (H, W)
+            out = torch.empty((S, oh, ow), dtype=torch.uint8, device=src.device)
+        _check(self.lib.swift_render(self.h, _ptr(src), S, H, W, src.stride(1), src.stride(0), _ptr(aff), int(level),
+                                     _ptr(out), out.shape[1], out.shape[2], out.stride(1), out.stride(0),
+                                     self.stream()))
+        return out
+
+    def stack_windows(self, aff, level, grid, h_l, w_l, img_a0, img_b0):
+        """Window pairs of every section: (img_a, img_b [P] int32, theta_a,
+        theta_b [P, 8] float32), P = S * grid^2, all on the device."""
+        S = aff.shape[0]
+        P = S * grid * grid
+        ta = torch.empty((P, 8), dtype=torch.float32, device=self.device)
+        tb = torch.empty((P, 8), dtype=torch.float32, device=self.device)
+        ia = torch.empty(P, dtype=torch.int32, device=self.device)
+        ib = torch.empty(P, dtype=torch.int32, device=self.device)
+        _check(self.lib.swift_stack_windows(self.h, S, _ptr(aff), int(level), int(grid), int(h_l), int(w_l),
+                                            int(img_a0), int(img_b0), _ptr(ta), _ptr(tb), _ptr(ia), _ptr(ib),
+                                            self.stream()))
+        return ia, ib, ta, tb
+
+    def fit_sections(self, theta_a, theta_b, recs_raw, per_section, level, aff, min_snr=6.0, status=None):
+        """Refits aff [S, 6] float64 (device, in place) from the window
+        matches; returns the per-section status tensor."""
+        S = aff.shape[0]
+        if status is None:
+            status = torch.empty(S, dtype=torch.int32, device=self.device)
+        _check(self.lib.swift_fit_sections(self.h, S, int(per_section), _ptr(theta_a), _ptr(theta_b),
+                                           _ptr(recs_raw), int(level), float(min_snr), _ptr(aff), _ptr(status),
+                                           self.stream()))
+        return status
 
     def snr(self, surfaces, params=None):
         """Peak, SNR and centroid of [B, n, n] float32 device surfaces."""

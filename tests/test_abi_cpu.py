@@ -56,4 +56,7 @@ def test_validation_without_gpu(lib):
     assert lib.swift_pyramid(None, None, None, None) == -1
     assert lib.swift_centroid_jacobian(None, None, 0, C.byref(pr), C.byref(pa), None, None, None, 0, None) == -1
     assert lib.swift_refine_update(None, 1, None, None, None, 0, 0.5, None, None) == -1
+    assert lib.swift_render(None, None, 1, 1, 1, 1, 1, None, 0, None, 1, 1, 1, 1, None) == -1
+    assert lib.swift_stack_windows(None, 1, None, 0, 8, 64, 64, 0, 1, None, None, None, None, None) == -1
+    assert lib.swift_fit_sections(None, 1, 64, None, None, None, 0, 6.0, None, None, None) == -1
     assert b"ctx" in lib.swift_last_error()
