@@ -178,9 +178,107 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
                          ms_to_target=(wall * 1e3 * hit / iters) if hit else None,
                          windows_per_s=P / wall)
     r0 = rms_max(tha)[0]
-    return dict(workload="%d windows of %d^2 (the benchmark's window grid), truth = fractional translation of "
+    return dict(note="adjoint: Newton steps on the centroid shift, Jacobian from one adjoint pass per iteration",
+                workload="%d windows of %d^2 (the benchmark's window grid), truth = fractional translation of "
                          "window B, start U(-0.5, 0.5)^2 px away" % (P, N),
                 start_rms_px=r0, tol_px=tol, target_rms_px=target, **out)
+
+
+# --------------------------------------------------------------------------- ragged levels
+def ragged_levels(ctx, sw, dev, sections=32, size=8192, reps=20):
+    """Every pyramid level of a 32 x 8192^2 stack at once: 8 x 8 windows per
+    section and level (1024^2 at level 0 down to 128^2 at level 3), 8192
+    pairs against +-3 projections of each level.  Compares four plain calls
+    (one per level, in sequence) with one call for the whole ragged batch
+    (size groups concurrent) and with the same batch as one replayed hipGraph.
+    Median of `reps` runs each."""
+    import torch
+
+    from datagen.workloads import level_stack, ragged_level_pairs
+    from paper_1612_04787_amd.stack import build_pyramid
+    stack = level_stack(sections, size, seed=3, device=dev)
+    pyr = build_pyramid(ctx, stack, 3)
+    images = []
+    for lv in pyr:
+        ref = ctx.project(lv, k=K_PROJ)
+        images += [lv[s] for s in range(sections)] + [ref[s] for s in range(sections)]
+    n_list, ia, ib, ta, tb = ragged_level_pairs(sections, size, 4, 8, dev)
+    P = len(n_list)
+    params = sw.make_params(p=P_WHITEN, flags=sw.FLAG_CONCURRENT_SIZES)
+    params_seq = sw.make_params(p=P_WHITEN)
+    prep = ctx.prepare(images, n_list, ia, ib, ta, tb)
+    need, _ = ctx.workspace_size(prep["pairs"], params)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
+    # per-level descriptors over the same arrays (pairs are sorted by size)
+    levels = []
+    off = 0
+    for n in sorted(set(n_list)):
+        c = n_list.count(n)
+        sl = slice(off, off + c)
+        pr = ctx.make_pairs(n_list[sl], prep["keep"][0][sl], prep["keep"][1][sl], prep["keep"][2][sl],
+                            prep["keep"][3][sl])
+        levels.append((pr, out[sl]))
+        off += c
+
+    def per_level():
+        for pr, o in levels:
+            ctx.match_batch_raw(prep["table"], len(images), pr, params_seq, o, ws=ws)
+
+    def one_call():
+        ctx.match_batch_raw(prep["table"], len(images), prep["pairs"], params, out, ws=ws)
+
+    def graph():
+        ctx.match_batch_raw(prep["table"], len(images), prep["pairs"], params, out, ws=ws, graph=True)
+
+    res = {}
+    for name, fn in (("per_level_calls", per_level), ("one_call_concurrent", one_call), ("graph", graph)):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        med = times[len(times) // 2]
+        res[name] = dict(ms=med * 1e3, pairs_per_s=P / med)
+    r = sw.parse_records(out)
+    res["workload"] = ("%d sections of %d^2, 4 pyramid levels, 8x8 windows per level: %s pairs of 128/256/512/1024"
+                       % (sections, size, "/".join(str(n_list.count(n)) for n in sorted(set(n_list)))))
+    res["median_snr"] = float(r["snr"].float().median())
+    res["graph_speedup_vs_per_level"] = res["per_level_calls"]["ms"] / res["graph"]["ms"]
+    return res
+
+
+# --------------------------------------------------------------------------- stack loop
+def stack_loop(ctx, stack, warps, refine="adjoint"):
+    """The iterative stack alignment on the benchmark stack: passes at pyramid
+    levels 2, 1, 0 (4, 2 and 1 of them) with 8 x 8 windows of 128^2, 256^2,
+    512^2 per section (render, project over +-8 / +-4 / +-3 sections, match +
+    refine, per-section affine fit).
+    Residuals against the generator's section warps: RMS about the best global
+    affine (gauge removed) and between neighbouring sections."""
+    import numpy as np
+    import torch
+
+    from datagen.evaluate import residuals
+    from paper_1612_04787_amd.stack import align_stack
+    S, H, W = stack.shape
+    pts = np.array([(W // 16 + W // 8 * i, H // 16 + H // 8 * j) for j in range(8) for i in range(8)], np.float64)
+    g0, n0 = residuals(np.tile([1.0, 0, 0, 0, 1.0, 0], (S, 1)), warps, pts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    aff, rep = align_stack(ctx, stack, levels=(2, 1, 0), ns=(128, 256, 512), iters=(4, 2, 1), ks=(8, 4, 3),
+                           refine=refine)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g1, n1 = residuals(aff.cpu().numpy(), warps, pts)
+    return dict(workload="%d sections of %d^2: levels 2/1/0 x 4/2/1 passes, 8x8 windows of 128/256/512, "
+                         "models +-8/+-4/+-3, refine=%s" % (S, H, refine),
+                wall_ms=wall * 1e3, passes=rep, residual_px={"global_before": g0, "global_after": g1,
+                                                             "neighbour_before": n0, "neighbour_after": n1})
 
 
 # --------------------------------------------------------------------------- main
@@ -191,6 +289,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the plain vs adjoint refinement comparison")
+    ap.add_argument("--no-stack", action="store_true", help="skip the iterative stack-alignment run")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the multi-level ragged batch comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -208,7 +308,7 @@ def main():
     dev = torch.device("cuda", 0)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.time()
-    stack, _ = distorted_stack(S_SECTIONS, SIZE, seed=5, device=dev)
+    stack, warps = distorted_stack(S_SECTIONS, SIZE, seed=5, device=dev)
     torch.cuda.synchronize()
     log("workload: %d x %d^2 stack generated in %.1f s" % (S_SECTIONS, SIZE, time.time() - t0))
 
@@ -308,10 +408,25 @@ def main():
         log("refinement: plain %d it %.1f ms (rms %.2e) | adjoint %d it %.1f ms (rms %.2e)"
             % (rf["plain"]["iterations"], rf["plain"]["wall_ms"], rf["plain"]["rms_px"],
                rf["adjoint"]["iterations"], rf["adjoint"]["wall_ms"], rf["adjoint"]["rms_px"]))
+    if not args.no_stack:
+        log("stack loop: 3 passes of render / project / match + refine / fit ...")
+        line["stack_loop"] = stack_loop(ctx, stack, warps)
+        r = line["stack_loop"]["residual_px"]
+        log("stack loop: %.0f ms, residual global %.2f -> %.2f px, neighbour %.2f -> %.2f px"
+            % (line["stack_loop"]["wall_ms"], r["global_before"], r["global_after"], r["neighbour_before"],
+               r["neighbour_after"]))
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)
         log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
+    if not args.no_ragged:
+        log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
+        del stack, refs, images, table, out
+        torch.cuda.empty_cache()
+        line["ragged"] = ragged_levels(ctx, sw, dev)
+        g = line["ragged"]
+        log("ragged levels: per-level %.2f ms, one call %.2f ms, graph %.2f ms"
+            % (g["per_level_calls"]["ms"], g["one_call_concurrent"]["ms"], g["graph"]["ms"]))
     ctx.close()
     print(json.dumps(line), flush=True)
 

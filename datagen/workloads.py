@@ -76,3 +76,32 @@ def section_pair_1024(size=16384, device="cuda"):
     P = len(cen)
     z = torch.zeros(P, dtype=torch.int32, device=device)
     return a, b, m, bv, [1024] * P, z, z + 1, t, t.clone()
+
+
+def level_stack(n_sections=32, size=8192, seed=3, device="cuda"):
+    """The multi-level input: S sections of size^2 from the stack generator
+    (keyframes every 8 sections, drifting membranes, noise sigma 8)."""
+    return make_stack(n_sections, size, size, seed, device=device)
+
+
+def ragged_level_pairs(n_sections: int, size: int, levels: int = 4, grid: int = 8, device="cuda"):
+    """Window pairs of every section against its reference at every pyramid
+    level l = 0 .. levels-1: a grid x grid tiling of the level image, so the
+    window edge is (size >> l) / grid.  Image table layout: level l's raw
+    sections at 2 S l + s, its references at 2 S l + S + s.  Pairs are sorted
+    by window edge (coarsest level first).  Returns (n_list, img_a, img_b,
+    theta_a, theta_b) with device tensors."""
+    S = n_sections
+    ns, ia, ib, th = [], [], [], []
+    for l in reversed(range(levels)):
+        side = size >> l
+        n = side // grid
+        for s in range(S):
+            for (cx, cy) in window_grid(side, side, n, grid):
+                ns.append(n)
+                ia.append(2 * S * l + s)
+                ib.append(2 * S * l + S + s)
+                th.append([cx, cy, 1, 0, 0, 0, 1, 0])
+    t = torch.tensor(np.array(th, np.float32), device=device)
+    return (ns, torch.tensor(ia, dtype=torch.int32, device=device),
+            torch.tensor(ib, dtype=torch.int32, device=device), t, t.clone())

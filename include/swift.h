@@ -90,7 +90,11 @@ typedef struct {
  *  taper_frac fraction of the window edge covered by the raised-cosine taper,
  *             both edges together, in [0, 1] (Section III, apodization).
  *  centroid_r half-width of the sub-pixel centroid box; only 1 is supported.
- *  flags      must be 0. */
+ *  flags      0 or SWIFT_FLAG_CONCURRENT_SIZES: the size groups of a ragged
+ *             batch run concurrently on the context's own streams (forked
+ *             from and joined back into the call's stream with events, so
+ *             the call stays stream-ordered and capturable). */
+#define SWIFT_FLAG_CONCURRENT_SIZES 1
 typedef struct {
   float p;
   float eps_rel;
@@ -138,8 +142,25 @@ int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs,
  *            swift_match_backward reads.
  *  ws        device workspace of ws_bytes >= swift_workspace_size's ws_bytes.
  * Errors: SWIFT_E_INVAL (NULL pointers, counts, params out of range),
- * SWIFT_E_UNSUPPORTED (centroid_r != 1, flags), SWIFT_E_WORKSPACE, SWIFT_E_HIP. */
+ * SWIFT_E_UNSUPPORTED (centroid_r != 1, unknown flags), SWIFT_E_WORKSPACE,
+ * SWIFT_E_HIP.  Calls on one context must not overlap in time from several
+ * host threads (the context's streams and events are shared). */
 int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
+                      const swift_pairs* pairs, const swift_params* params,
+                      swift_match* out, float* surfaces, void* saved, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* swift_match_batch as one hipGraph launch (ragged batching, not in the
+ * paper): the first call with a given argument tuple (every pointer, n_imgs,
+ * size_count, params) captures the whole batch, with all size groups as
+ * concurrent branches, and instantiates it; later calls with the same tuple
+ * only launch the cached graph on `stream`.  Buffer contents may change
+ * between calls (the image table, pairs and thetas are read when the graph
+ * runs); pointers and counts may not without a new capture.  Up to 16 graphs
+ * are cached per context (least recently used evicted).  Kernel timing
+ * (swift_profile_enable) does not apply to graph launches.
+ * Errors: as swift_match_batch, plus SWIFT_E_CAPTURE. */
+int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
                       const swift_pairs* pairs, const swift_params* params,
                       swift_match* out, float* surfaces, void* saved, void* ws,
                       size_t ws_bytes, hipStream_t stream);

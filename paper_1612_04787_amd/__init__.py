@@ -4,6 +4,7 @@ The compute lives in libswift.so (HIP for gfx950, C ABI in include/swift.h);
 this package is its thin Python binding.
 """
 from .swift import (  # noqa: F401
+    FLAG_CONCURRENT_SIZES,
     SIZES,
     Swift,
     SwiftError,

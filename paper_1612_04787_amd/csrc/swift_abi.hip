@@ -65,13 +65,45 @@ struct EventTimer : KernelTimer {
   }
 };
 
+// A captured and instantiated match batch, keyed by its argument tuple.
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
 struct swift_ctx {
   int device;
   float2* tw;  // W_1024^m = exp(-2 pi i m / 1024)
   bool profile = false;
   EventTimer timer;
   KernelTimer* kt() { return profile ? &timer : nullptr; }
+  // one stream per window size for concurrent size groups (default priority),
+  // the fork/join events, and a capture stream for graphs
+  hipStream_t gs[SWIFT_NSIZES] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[SWIFT_NSIZES] = {};
+  hipStream_t cap = nullptr;
+  std::map<std::string, GraphEntry> graphs;
+  uint64_t tick = 0;
 };
+
+static constexpr size_t kMaxGraphs = 16;
+
+static void ctx_release(swift_ctx* c) {
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  c->graphs.clear();
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    if (c->gs[i]) (void)hipStreamDestroy(c->gs[i]);
+    if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->tw) (void)hipFree(c->tw);
+}
 
 namespace {
 
@@ -221,7 +253,7 @@ int check_params(const swift_params* pr) {
   if (!(pr->taper_frac >= 0.0f && pr->taper_frac <= 1.0f))
     return fail(SWIFT_E_INVAL, "taper_frac must be in [0, 1] (got %g)", pr->taper_frac);
   if (pr->centroid_r != 1) return fail(SWIFT_E_UNSUPPORTED, "centroid_r must be 1 (got %d)", pr->centroid_r);
-  if (pr->flags != 0) return fail(SWIFT_E_UNSUPPORTED, "flags must be 0 (got %d)", pr->flags);
+  if (pr->flags & ~SWIFT_FLAG_CONCURRENT_SIZES) return fail(SWIFT_E_UNSUPPORTED, "unknown flags %#x", pr->flags);
   return SWIFT_OK;
 }
 
@@ -260,6 +292,17 @@ int swift_create(int device, swift_ctx** out) {
   }
   c->device = device;
   c->tw = tw;
+  for (int i = 0; i < SWIFT_NSIZES && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&c->gs[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    ctx_release(c);
+    delete c;
+    return hip_fail(e, "context streams/events");
+  }
   *out = c;
   return ok();
 }
@@ -268,7 +311,7 @@ void swift_destroy(swift_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard dg(ctx->device);
   (void)hipDeviceSynchronize();
-  (void)hipFree(ctx->tw);
+  ctx_release(ctx);
   delete ctx;
 }
 
@@ -286,32 +329,59 @@ int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs, const swift_p
   return ok();
 }
 
-int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
-                      const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
-                      size_t ws_bytes, hipStream_t stream) {
+// Validation shared by swift_match_batch and swift_match_graph; sets *empty
+// for a batch without pairs.
+static int check_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                       const swift_params* params, swift_match* out, void* ws, size_t ws_bytes, bool* empty) {
+  *empty = false;
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   int rc = check_pairs(pairs);
   if (rc) return rc;
   rc = check_params(params);
   if (rc) return rc;
-  if (pairs->n_pairs == 0) return ok();
+  if (pairs->n_pairs == 0) {
+    *empty = true;
+    return ok();
+  }
   if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
   if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
   const Layout L = make_layout(pairs);
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  return SWIFT_OK;
+}
 
+// Enqueues the whole batch on `stream`: per size group the taper tables and
+// the five match kernels.  With `concurrent` and more than one group, each
+// group runs on the context's stream for its size, forked from `stream` by
+// an event and joined back into it.
+static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                         const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
+                         hipStream_t stream, bool concurrent, KernelTimer* kt) {
+  const Layout L = make_layout(pairs);
+  int groups = 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) groups += L.g[i].count > 0 ? 1 : 0;
+  concurrent = concurrent && groups > 1;
+  hipError_t e = hipSuccess;
+  if (concurrent) {
+    e = hipEventRecord(ctx->fork_ev, stream);
+    if (e != hipSuccess) return hip_fail(e, "fork event");
+  }
   char* base = (char*)ws;
   size_t surf_off = 0;
   for (int i = 0; i < SWIFT_NSIZES; ++i) {
     const GroupLayout& g = L.g[i];
     if (g.count == 0) continue;
+    hipStream_t s = stream;
+    if (concurrent) {
+      s = ctx->gs[i];
+      e = hipStreamWaitEvent(s, ctx->fork_ev, 0);
+      if (e != hipSuccess) return hip_fail(e, "fork wait");
+    }
     float2* tau = (float2*)(base + L.taper + i * kTaperSlot);
     float* taper = (float*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
     TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2) + 1024 * sizeof(float));
-    hipError_t e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, stream);
+    e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, s);
     if (e != hipSuccess) return hip_fail(e, "taper launch");
     MatchArgs a;
     a.imgs = imgs;
@@ -338,10 +408,89 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    e = launch_match_group(g.n, a, stream, ctx->kt());
+    e = launch_match_group(g.n, a, s, kt);
     if (e != hipSuccess) return hip_fail(e, "match launch");
+    if (concurrent) {
+      e = hipEventRecord(ctx->join_ev[i], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, ctx->join_ev[i], 0);
+      if (e != hipSuccess) return hip_fail(e, "join");
+    }
     surf_off += (size_t)g.count * g.n * g.n;
   }
+  return ok();
+}
+
+int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                      const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  bool empty;
+  int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
+  if (rc || empty) return rc;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  return enqueue_match(ctx, imgs, n_imgs, pairs, params, out, surfaces, saved, ws, stream,
+                       (params->flags & SWIFT_FLAG_CONCURRENT_SIZES) != 0, ctx->kt());
+}
+
+int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                      const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  bool empty;
+  int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
+  if (rc || empty) return rc;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  // key: every value the captured launches bake in
+  struct {
+    const void* p[9];
+    int32_t n_imgs, n_pairs, counts[SWIFT_NSIZES];
+    swift_params prm;
+  } key;
+  memset(&key, 0, sizeof(key));
+  key.p[0] = imgs;
+  key.p[1] = pairs->img_a;
+  key.p[2] = pairs->img_b;
+  key.p[3] = pairs->theta_a;
+  key.p[4] = pairs->theta_b;
+  key.p[5] = out;
+  key.p[6] = surfaces;
+  key.p[7] = saved;
+  key.p[8] = ws;
+  key.n_imgs = n_imgs;
+  key.n_pairs = pairs->n_pairs;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) key.counts[i] = pairs->size_count[i];
+  key.prm = *params;
+  const std::string k((const char*)&key, sizeof(key));
+  auto it = ctx->graphs.find(k);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= kMaxGraphs) {  // evict the least recently used
+      auto lru = ctx->graphs.begin();
+      for (auto j = ctx->graphs.begin(); j != ctx->graphs.end(); ++j)
+        if (j->second.last_use < lru->second.last_use) lru = j;
+      (void)hipGraphExecDestroy(lru->second.exec);
+      (void)hipGraphDestroy(lru->second.graph);
+      ctx->graphs.erase(lru);
+    }
+    GraphEntry ge;
+    hipError_t e = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(SWIFT_E_CAPTURE, "begin capture: %s", hipGetErrorString(e));
+    rc = enqueue_match(ctx, imgs, n_imgs, pairs, params, out, surfaces, saved, ws, ctx->cap, true, nullptr);
+    e = hipStreamEndCapture(ctx->cap, &ge.graph);
+    if (rc) {
+      if (ge.graph) (void)hipGraphDestroy(ge.graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(SWIFT_E_CAPTURE, "end capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(ge.graph);
+      return fail(SWIFT_E_CAPTURE, "instantiate: %s", hipGetErrorString(e));
+    }
+    it = ctx->graphs.emplace(k, ge).first;
+  }
+  it->second.last_use = ++ctx->tick;
+  hipError_t e = hipGraphLaunch(it->second.exec, stream);
+  if (e != hipSuccess) return fail(SWIFT_E_CAPTURE, "graph launch: %s", hipGetErrorString(e));
   return ok();
 }
 

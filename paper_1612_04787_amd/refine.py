@@ -59,12 +59,10 @@ def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol
 
 
 def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                   max_step=0.5, stop_frac=0.0, jac_iters=None):
-    """Returns (theta_a [P, 8], iterations, list of longest steps).
-
-    jac_iters: the Jacobian is recomputed on the first jac_iters iterations
-    and reused afterwards (a chord Newton step, with a plain forward pass);
-    None recomputes it every iteration."""
+                   max_step=0.5, stop_frac=0.0):
+    """Returns (theta_a [P, 8], iterations, list of longest steps).  The
+    Jacobian is recomputed every iteration: it changes across a pixel cell
+    (bilinear sampling), and reusing the first one (chord steps) stalls."""
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
     P = prep["pairs"].n_pairs
     out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=sw.device)
@@ -74,11 +72,8 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
     step = torch.empty(P, dtype=torch.float32, device=sw.device)
     hist = []
     for it in range(1, max_iter + 1):
-        fresh = jac_iters is None or it <= jac_iters
-        sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out,
-                           saved=saved if fresh else None)
-        if fresh:
-            sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, saved, jac)
+        sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved)
+        sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, saved, jac)
         sw.refine_update(out, th, NEWTON, jac, max_step, step)
         m, stop = _done(step, tol, stop_frac)
         hist.append(m)

@@ -38,11 +38,13 @@ def build_pyramid(sw, stack, max_level):
     return levels
 
 
-def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), grid=8, k=3, p=0.65,
+def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), ks=(3, 3, 3), grid=8, p=0.65,
                 refine="adjoint", min_snr=6.0, tol=0.005, stop_frac=0.01, aff=None, on_pass=None):
     """Aligns a [S, H, W] uint8 device stack.  Returns (affines [S, 6] float64
     device, level-0 aligned frame -> raw section, and a list of per-pass
-    reports).  refine: "adjoint", "plain" or None (one match, no refinement);
+    reports).  ks: model half-span per level (wider models at coarse levels
+    smooth the alignment globally, Section III).  refine: "adjoint", "plain"
+    or None (one match, no refinement);
     the refinement of a pass stops when at most stop_frac of the windows still
     step by tol px or more (windows on damaged or featureless content may never
     settle).
@@ -56,7 +58,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
         aff[:, 4] = 1.0
     params = make_params(p=p)
     reports = []
-    for level, n, reps in zip(levels, ns, iters):
+    for level, n, reps, k in zip(levels, ns, iters, ks):
         src = pyr[level]
         _, hl, wl = src.shape
         for rep in range(reps):
@@ -82,7 +84,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             el = time.perf_counter() - t0
             rec = parse_records(out)
             snr = rec["snr"].float()
-            rep_d = dict(level=level, n=n, repeat=rep, pairs=P, refine_iters=it, ms=el * 1e3,
+            rep_d = dict(level=level, n=n, k=k, repeat=rep, pairs=P, refine_iters=it, ms=el * 1e3,
                          median_snr=float(snr.median()), frac_snr_gt_15=float((snr > 15).float().mean()),
                          frac_weighted=float((snr >= min_snr).float().mean()),
                          singular_sections=int((status != 0).sum()))

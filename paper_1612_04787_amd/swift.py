@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libswift.so")
 SIZES = (64, 128, 256, 512, 1024)
 
 SWIFT_U8, SWIFT_F32 = 0, 1
+FLAG_CONCURRENT_SIZES = 1
 ST_NEAR_TIE, ST_DEGENERATE, ST_CLAMPED = 1, 2, 4
 ERRORS = {-1: "SWIFT_E_INVAL", -2: "SWIFT_E_UNSUPPORTED", -3: "SWIFT_E_WORKSPACE",
           -4: "SWIFT_E_HIP", -5: "SWIFT_E_CAPTURE"}
@@ -63,6 +64,7 @@ def load_library(path: str = LIB_PATH):
     lib.swift_destroy.restype = None
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
     lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
+    lib.swift_match_graph.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
     lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
                                          vp, vp, sz, vp]
     lib.swift_project.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i64, i64, vp]
@@ -79,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
               "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read",
               "swift_refine_update", "swift_centroid_jacobian", "swift_render", "swift_stack_windows",
-              "swift_fit_sections"):
+              "swift_fit_sections", "swift_match_graph"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -89,7 +91,8 @@ def exported_symbols():
     return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
             "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
             "swift_profile_enable", "swift_profile_read", "swift_refine_update",
-            "swift_centroid_jacobian", "swift_render", "swift_stack_windows", "swift_fit_sections"]
+            "swift_centroid_jacobian", "swift_render", "swift_stack_windows", "swift_fit_sections",
+            "swift_match_graph"]
 
 
 def _check(rc):
@@ -201,13 +204,15 @@ class Swift:
         return ws.value, sv.value
 
     # ------------------------------------------------------------------ entry points
-    def match_batch_raw(self, table, n_imgs, pairs, params, out, surfaces=None, ws=None, saved=None):
+    def match_batch_raw(self, table, n_imgs, pairs, params, out, surfaces=None, ws=None, saved=None, graph=False):
+        """swift_match_batch, or with graph=True swift_match_graph (captured
+        once per argument tuple, then replayed)."""
         need, _ = self.workspace_size(pairs, params)
         if ws is None:
             ws = self.workspace(need)
-        _check(self.lib.swift_match_batch(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params),
-                                          _ptr(out), _ptr(surfaces), _ptr(saved), _ptr(ws), ws.numel(),
-                                          self.stream()))
+        fn = self.lib.swift_match_graph if graph else self.lib.swift_match_batch
+        _check(fn(self.h, _ptr(table), int(n_imgs), C.byref(pairs), C.byref(params), _ptr(out), _ptr(surfaces),
+                  _ptr(saved), _ptr(ws), ws.numel(), self.stream()))
 
     def match_backward_raw(self, table, n_imgs, pairs, params, saved, g_peak, g_snr, g_theta_a, g_theta_b=None,
                            peak_hess=None, ws=None):
