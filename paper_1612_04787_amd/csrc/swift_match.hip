@@ -278,6 +278,55 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
   }
 }
 
+// Gather of a translation window (identity linear part): every sample of the
+// window has the same bilinear weights (fx, fy), so a thread walks down its
+// column and reuses the horizontal interpolation of each tile row for the
+// next output row.  Thread (column x = tid % N + 256 c) covers ITER
+// consecutive rows starting at (tid / N) * ITER.  Same sums and stage layout
+// as gather_rows.
+template <int N, int R, bool IM>
+__device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, const uint32_t* __restrict__ tile,
+                                                  const TileGeom& g, const RowParam* __restrict__ rp,
+                                                  const float* __restrict__ trow, const swift_image& im,
+                                                  bool border, int tid, const float (&tx)[GatherCfg<N>::XV],
+                                                  float& s1, float& s2, float& s3, bool& cl) {
+  constexpr int RS = fwd_stride<N, R>();
+  constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+  const unsigned char* tb = (const unsigned char*)tile;
+  const int rowb = g.wt4 * 4;
+  const int xt = tid % N, r0 = (RPI > 1 ? tid / N : 0) * ITER;
+  const RowParam p0 = rp[r0];
+  const float fx = p0.fx, fy = p0.fy;  // the same for every row of the window
+  float* st = (float*)stage + (IM ? 1 : 0);
+#pragma unroll
+  for (int c = 0; c < XV; ++c) {
+    const int x = xt + 256 * c;
+    const int x0 = p0.bx + (x - N / 2);
+    const int ix = min(max(x0, 0), rowb - 2);
+    const float txc = tx[c];
+    auto hrow = [&](int yy) {
+      const unsigned char* q = tb + min(max(yy, 0), g.ht - 1) * rowb + ix;
+      const float a0 = (float)q[0], a1 = (float)q[1];
+      return fmaf(fx, a1 - a0, a0);
+    };
+    float h0 = hrow(p0.by);
+#pragma unroll 4
+    for (int i = 0; i < ITER; ++i) {
+      const int r = r0 + i, y0 = p0.by + i;
+      if (border) cl |= (x0 + g.xlo < 0) | (x0 + g.xlo > im.width - 2) | (y0 + g.ylo < 0) | (y0 + g.ylo > im.height - 2);
+      const float h1 = hrow(y0 + 1);
+      const float val = fmaf(fy, h1 - h0, h0);
+      h0 = h1;
+      const float tap = txc * trow[r];
+      const float at = (val - kSampleOffset) * tap;
+      s1 += at;
+      s2 = fmaf(at, at, s2);
+      s3 = fmaf(at, tap, s3);
+      st[2 * (r * RS + lidx(x))] = at;
+    }
+  }
+}
+
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int per = nb >> 3, full = per << 3;
   return b >= full ? b : (b & 7) * per + (b >> 3);
@@ -360,13 +409,20 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
   float s[6] = {0, 0, 0, 0, 0, 0};
   bool clamped = false;
+  // translation windows (identity linear part) take the constant-weight gather
+  const bool trans[2] = {ra[0].a11 == 1.0 && ra[0].a12 == 0.0 && ra[0].a21 == 0.0 && ra[0].a22 == 1.0,
+                         ra[1].a11 == 1.0 && ra[1].a12 == 0.0 && ra[1].a21 == 0.0 && ra[1].a22 == 1.0};
 
   __syncthreads();  // row parameters visible
   if (tg[0].use) {
     tile_store(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
-    gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tid, tx, s[0],
-                                   s[1], s[2], clamped);
+    if (trans[0])
+      gather_rows_trans<N, R, false>(stage, tile, tg[0], rparam[0], trow, im[0], border[0], tid, tx, s[0], s[1], s[2],
+                                     clamped);
+    else
+      gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tid, tx, s[0],
+                                     s[1], s[2], clamped);
   } else {
     gather_rows<N, R, false, false>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tid, tx, s[0], s[1],
                                     s[2], clamped);
@@ -375,8 +431,12 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     __syncthreads();  // tile of A fully consumed
     tile_store(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
-    gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tid, tx, s[3],
-                                  s[4], s[5], clamped);
+    if (trans[1])
+      gather_rows_trans<N, R, true>(stage, tile, tg[1], rparam[1], trow, im[1], border[1], tid, tx, s[3], s[4], s[5],
+                                    clamped);
+    else
+      gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tid, tx, s[3],
+                                    s[4], s[5], clamped);
   } else {
     gather_rows<N, R, true, false>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tid, tx, s[3], s[4],
                                    s[5], clamped);

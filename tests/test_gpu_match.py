@@ -89,6 +89,38 @@ def test_sizes_random_affines(ctx, section_pair_small, n, p):
         print("  ", i, e, flush=True)
 
 
+@pytest.mark.parametrize("n", SIZES)
+def test_translation_windows(ctx, section_pair_small, n):
+    """Windows with an identity linear part (the constant-weight gather):
+    fractional translations on both sides, one window partly outside the
+    section (clamped reads), one at an integer position."""
+    print("case translation n=%d" % n, flush=True)
+    a, b = section_pair_small
+    rng = np.random.default_rng(3000 + n)
+    k = {64: 6, 128: 5, 256: 4, 512: 3, 1024: 3}[n]
+    tha = np.zeros((k, 8), np.float32)
+    for i in range(k):
+        tha[i] = [rng.uniform(n / 2 + 8, 1600 - n / 2 - 8), rng.uniform(n / 2 + 8, 1600 - n / 2 - 8), 1, 0,
+                  rng.uniform(-3, 3), 0, 1, rng.uniform(-3, 3)]
+    tha[-1] = [n / 2 - 5.5, 1600 - n / 2 + 3.25, 1, 0, 0.375, 0, 1, -0.625]
+    tha[0, 4] = tha[0, 7] = 0.0
+    thb = tha.copy()
+    thb[:, 4] += rng.uniform(-2, 2, k).astype(np.float32)
+    thb[:, 7] += rng.uniform(-2, 2, k).astype(np.float32)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(tha), torch.from_numpy(thb),
+                          _params(0.65), surfaces=True)
+    torch.cuda.synchronize()
+    surf = res["surfaces"].view(k, n, n).cpu().numpy()
+    an, bn = a.numpy(), b.numpy()
+    for i in range(k):
+        r = O.match_pair(an, bn, tha[i].astype(np.float64), thb[i].astype(np.float64), n, O.Params(p=0.65),
+                         return_surface=True)
+        e = compare(gpu_record(res, i), r, n, surf[i], "translation n=%d i=%d" % (n, i))
+        print("  ", i, e, flush=True)
+    assert int(res["status"][k - 1]) & O.swift_oracle.STATUS_CLAMPED
+
+
 def test_ragged_batch_all_sizes(ctx, section_pair_small):
     print("case ragged", flush=True)
     a, b = section_pair_small
