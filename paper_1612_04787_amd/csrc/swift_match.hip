@@ -203,6 +203,15 @@ struct RowParam {
   float fx, fy;    // fractional part in [0, 1)
 };
 
+// Bytes off and off + 1 of the LDS tile in the low half of a word.  Lanes
+// reading neighbouring bytes share dwords; byte-wide LDS reads of one dword by
+// several lanes serialise, dword reads of one dword do not, so the pair is
+// cut out of the two aligned dwords that hold it.
+__device__ __forceinline__ uint32_t tile_pair(const uint32_t* __restrict__ tile, int off) {
+  const uint32_t* w = tile + (off >> 2);
+  return __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(off & 3));
+}
+
 template <int N> struct GatherCfg {
   static constexpr int XV = N >= 256 ? N / 256 : 1;   // columns per thread and row
   static constexpr int RPI = N >= 256 ? 1 : 256 / N;  // rows per iteration
@@ -221,7 +230,6 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
                                             bool& cl) {
   constexpr int RS = fwd_stride<N, R>();
   constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
-  const unsigned char* tb = (const unsigned char*)tile;
   const int rowb = g.wt4 * 4;
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
   const int xt = tid % N;
@@ -242,11 +250,12 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
       if constexpr (TILE) {
         if (border) cl |= (x0 + g.xlo < 0) | (x0 + g.xlo > im.width - 2) | (y0 + g.ylo < 0) | (y0 + g.ylo > im.height - 2);
         const int ix = min(max(x0, 0), rowb - 2), iy = min(max(y0, 0), g.ht - 2);
-        const unsigned char* q = tb + iy * rowb + ix;
-        i00 = (float)q[0];
-        i10 = (float)q[1];
-        i01 = (float)q[rowb];
-        i11 = (float)q[rowb + 1];
+        const int off = iy * rowb + ix;
+        const uint32_t vt = tile_pair(tile, off), vb = tile_pair(tile, off + rowb);
+        i00 = (float)(vt & 255u);
+        i10 = (float)((vt >> 8) & 255u);
+        i01 = (float)(vb & 255u);
+        i11 = (float)((vb >> 8) & 255u);
       } else {
         cl |= (x0 < 0) | (x0 > im.width - 2) | (y0 < 0) | (y0 > im.height - 2);
         const int cx0 = min(max(x0, 0), im.width - 1), cx1 = min(max(x0 + 1, 0), im.width - 1);
@@ -292,7 +301,6 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, co
                                                   float& s1, float& s2, float& s3, bool& cl) {
   constexpr int RS = fwd_stride<N, R>();
   constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
-  const unsigned char* tb = (const unsigned char*)tile;
   const int rowb = g.wt4 * 4;
   const int xt = tid % N, r0 = (RPI > 1 ? tid / N : 0) * ITER;
   const RowParam p0 = rp[r0];
@@ -305,8 +313,8 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, co
     const int ix = min(max(x0, 0), rowb - 2);
     const float txc = tx[c];
     auto hrow = [&](int yy) {
-      const unsigned char* q = tb + min(max(yy, 0), g.ht - 1) * rowb + ix;
-      const float a0 = (float)q[0], a1 = (float)q[1];
+      const uint32_t v = tile_pair(tile, min(max(yy, 0), g.ht - 1) * rowb + ix);
+      const float a0 = (float)(v & 255u), a1 = (float)((v >> 8) & 255u);
       return fmaf(fx, a1 - a0, a0);
     };
     float h0 = hrow(p0.by);
@@ -339,7 +347,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   constexpr int XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
-  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 : 1];
+  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
   __shared__ RowParam rparam[2][R];
   __shared__ float trow[R];
   __shared__ double red[4][6];
