@@ -34,6 +34,7 @@
 // channel and that of the y objective to the imaginary channel of the one
 // inverse 2-D FFT, giving d(dx, dy) / d theta_A in a single pass.
 #include "swift_dev.hpp"
+#include "swift_tile.hpp"
 
 namespace swift {
 
@@ -87,6 +88,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
     bool zero_all = (ps.flags & 1) != 0;
     // centroid weights (CJ): omega_x, omega_y on the 3 x 3 box, from the saved values
     float omx[9], omy[9];
+    float2 rxw[3], ryw[3];
     if constexpr (CJ) {
       const float* q = a.nb + (size_t)pair * 9;
       double sw = 0.0, swx = 0.0, swy = 0.0;
@@ -104,6 +106,12 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         omy[j] = on ? (float)(((double)(j / 3 - 1) - fyc) / sw) : 0.0f;
       }
       if (!(sw > 0.0)) zero_all = true;
+      const float2 ex = a.tw[w * (1024 / N)], exc = cconj(ex);
+#pragma unroll
+      for (int r3 = 0; r3 < 3; ++r3) {
+        rxw[r3] = cadd(cadd(cscale(exc, omx[3 * r3]), make_float2(omx[3 * r3 + 1], 0.f)), cscale(ex, omx[3 * r3 + 2]));
+        ryw[r3] = cadd(cadd(cscale(exc, omy[3 * r3]), make_float2(omy[3 * r3 + 1], 0.f)), cscale(ex, omy[3 * r3 + 2]));
+      }
     }
     const float p = a.p, hp2 = -0.5f * p;
     const float inv_m = 1.0f / (float)(N * N);
@@ -140,7 +148,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       const int m = (ky * rec.iy + w * rec.ix) & (N - 1);
       const float2 ph = a.tw[m * (1024 / N)];
       // surface Hessian sums: Re(X h e^{+i phi}) times the frequency products
-      if (!zero_all && !(ky == 0 && w == 0)) {
+      if (!CJ && !zero_all && !(ky == 0 && w == 0)) {
         const float2 cc = cmul(cscale(X, h), cconj(ph));
         const float fy = (ky < N / 2) ? (float)ky : (float)(ky - N);
         const float fym = (ky == N / 2) ? 0.0f : fy;
@@ -160,20 +168,11 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         gfa = cmul(cconj(gx), fb);
         gfb = cmul(gx, fa);
       } else {
-        // 3 x 3 sums S = sum omega e_x^dx e_y^dy with e = e^{-2 pi i k/N}
-        const float2 ex = a.tw[w * (1024 / N)], ey = a.tw[ky * (1024 / N)];
-        const float2 exc = cconj(ex), eyc = cconj(ey);
-        float2 sx = make_float2(0.f, 0.f), sy = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int r3 = 0; r3 < 3; ++r3) {
-          const float2 rx = cadd(cadd(cscale(exc, omx[3 * r3]), make_float2(omx[3 * r3 + 1], 0.f)),
-                                 cscale(ex, omx[3 * r3 + 2]));
-          const float2 ry = cadd(cadd(cscale(exc, omy[3 * r3]), make_float2(omy[3 * r3 + 1], 0.f)),
-                                 cscale(ex, omy[3 * r3 + 2]));
-          const float2 ef = r3 == 0 ? eyc : (r3 == 1 ? make_float2(1.f, 0.f) : ey);
-          sx = cadd(sx, cmul(rx, ef));
-          sy = cadd(sy, cmul(ry, ef));
-        }
+        // 3 x 3 sums S = sum omega e_x^dx e_y^dy with e = e^{-2 pi i k/N}; the
+        // x part (rows of the box summed over dx) is the same for the whole column
+        const float2 ey = a.tw[ky * (1024 / N)], eyc = cconj(ey);
+        const float2 sx = cadd(cadd(cmul(eyc, rxw[0]), rxw[1]), cmul(ey, rxw[2]));
+        const float2 sy = cadd(cadd(cmul(eyc, ryw[0]), ryw[1]), cmul(ey, ryw[2]));
         float2 gcx = cscale(cmul(ph, sx), inv_m), gcy = cscale(cmul(ph, sy), inv_m);
         if (zb) gcx = gcy = make_float2(0.0f, 0.0f);
         const float2 gxx = cadd(cscale(gcx, h + r * hd), cscale(cmul(cconj(gcx), x2), hd));
@@ -228,68 +227,138 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
 
 // ---------------------------------------------------------------- row stage
 // Per image, the 20 pixel sums of the header comment; acc layout:
-// [0..5] P1, [6..11] P2, [12..17] P3, [18] Q, [19] R.
-struct PixelTerms {
-  float D[6];  // (a_x u, a_x v, a_x, a_y u, a_y v, a_y)
-  float tap;   // T
-  float w;     // (a - m) T
+// [0..5] P1, [6..11] P2, [12..17] P3, [18] Q, [19] R.  In CJ mode the second
+// channel differentiates the same image A, so it shares P2, P3 and R with the
+// first and keeps only its own P1 and Q (layout [0..5] P1, [18] Q).
+//
+// The block's R window rows: the inverse row FFTs of G_w first (both
+// channels, written back to the stage), then one pass over the pixels per
+// image, sampled as in the forward row pass (uint8 source tile in LDS when
+// the footprint fits, per-row FP64 parameters with FP32 per-pixel offsets,
+// constant weights for translation windows).
+// Per-pixel offsets of the sample point from the row's point at u = 0: u a
+// split into u round(a), an exact integer, and u (a - round(a)), small enough
+// that FP32 keeps it to ~1e-7 px.  The derivative of the bilinear sample jumps
+// at integer coordinates, so the cell must be chosen as FP64 would.
+template <int XV>
+struct PixelOffsets {
+  int ix[XV], iy[XV];
+  float fx[XV], fy[XV];
 };
 
-template <int N>
-__device__ __forceinline__ PixelTerms bwd_terms(const swift_image& im, const float* th, double vrow, int x,
-                                                float tap, float mean_off, bool& cl) {
-  const double u = (double)(x - N / 2);
-  const double X = fmin(fmax((double)th[0] + (double)th[4] + (double)th[2] * u + (double)th[3] * vrow, -1e9), 1e9);
-  const double Y = fmin(fmax((double)th[1] + (double)th[7] + (double)th[5] * u + (double)th[6] * vrow, -1e9), 1e9);
-  const double xfd = floor(X), yfd = floor(Y);
-  const float fx = (float)(X - xfd), fy = (float)(Y - yfd);
-  const int x0 = (int)xfd, y0 = (int)yfd;
-  cl |= (x0 < 0) | (x0 > im.width - 2) | (y0 < 0) | (y0 > im.height - 2);
-  const int cx0 = min(max(x0, 0), im.width - 1), cx1 = min(max(x0 + 1, 0), im.width - 1);
-  const int cy0 = min(max(y0, 0), im.height - 1), cy1 = min(max(y0 + 1, 0), im.height - 1);
+template <int N, int R, bool TILE, bool TRANS, bool TWO>
+__device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int RS, const uint32_t* __restrict__ tile,
+                                           const TileGeom& g, const RowParam* __restrict__ rp,
+                                           const float* __restrict__ trow, const PixelOffsets<GatherCfg<N>::XV>& ku,
+                                           const float (&tx)[GatherCfg<N>::XV], const swift_image& im, int y0,
+                                           int tid, float mean_off, bool ch1, float (&acc)[kBwdSums],
+                                           float (&acc2)[kBwdSums]) {
+  constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+  const int rowb = g.wt4 * 4;
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  const gptr<unsigned char> r0 = base + (int64_t)cy0 * im.pitch;
-  const gptr<unsigned char> r1 = base + (int64_t)cy1 * im.pitch;
-  float i00, i10, i01, i11;
-  if (im.dtype == SWIFT_U8) {
-    i00 = (float)r0[cx0];
-    i10 = (float)r0[cx1];
-    i01 = (float)r1[cx0];
-    i11 = (float)r1[cx1];
-  } else {
-    i00 = ((gptr<float>)r0)[cx0];
-    i10 = ((gptr<float>)r0)[cx1];
-    i01 = ((gptr<float>)r1)[cx0];
-    i11 = ((gptr<float>)r1)[cx1];
+  const int xt = tid % N, r0 = (RPI > 1 ? tid / N : 0) * ITER;
+#pragma unroll
+  for (int c = 0; c < XV; ++c) {
+    const int x = xt + 256 * c;
+    const float u = (float)(x - N / 2);
+    uint32_t prev = 0;  // translation windows: the tile byte pair of the previous row's bottom
+#pragma unroll 2
+    for (int i = 0; i < ITER; ++i) {
+      const int r = r0 + i;
+      const RowParam p = rp[TRANS ? r0 : r];
+      float fx, fy, i00, i10, i01, i11;
+      if constexpr (TRANS) {
+        // same weights for every pixel; rows step by one tile row
+        fx = p.fx;
+        fy = p.fy;
+        const int ix = min(max(p.bx + (x - N / 2), 0), rowb - 2);
+        const int iy = p.by + i;
+        const uint32_t vt = i == 0 ? tile_pair(tile, min(max(iy, 0), g.ht - 1) * rowb + ix) : prev;
+        const uint32_t vb = tile_pair(tile, min(max(iy + 1, 0), g.ht - 1) * rowb + ix);
+        prev = vb;
+        i00 = (float)(vt & 255u);
+        i10 = (float)((vt >> 8) & 255u);
+        i01 = (float)(vb & 255u);
+        i11 = (float)((vb >> 8) & 255u);
+      } else {
+        const float xr = p.fx + ku.fx[c], yr = p.fy + ku.fy[c];
+        const float xf = floorf(xr), yf = floorf(yr);
+        fx = xr - xf;
+        fy = yr - yf;
+        const int x0 = p.bx + ku.ix[c] + (int)xf, yy0 = p.by + ku.iy[c] + (int)yf;
+        if constexpr (TILE) {
+          const int ix = min(max(x0, 0), rowb - 2), iy = min(max(yy0, 0), g.ht - 2);
+          const int off = iy * rowb + ix;
+          const uint32_t vt = tile_pair(tile, off), vb = tile_pair(tile, off + rowb);
+          i00 = (float)(vt & 255u);
+          i10 = (float)((vt >> 8) & 255u);
+          i01 = (float)(vb & 255u);
+          i11 = (float)((vb >> 8) & 255u);
+        } else {
+          const int cx0 = min(max(x0, 0), im.width - 1), cx1 = min(max(x0 + 1, 0), im.width - 1);
+          const int cy0 = min(max(yy0, 0), im.height - 1), cy1 = min(max(yy0 + 1, 0), im.height - 1);
+          const gptr<unsigned char> q0 = base + (int64_t)cy0 * im.pitch;
+          const gptr<unsigned char> q1 = base + (int64_t)cy1 * im.pitch;
+          if (im.dtype == SWIFT_U8) {
+            i00 = (float)q0[cx0];
+            i10 = (float)q0[cx1];
+            i01 = (float)q1[cx0];
+            i11 = (float)q1[cx1];
+          } else {
+            i00 = ((gptr<float>)q0)[cx0];
+            i10 = ((gptr<float>)q0)[cx1];
+            i01 = ((gptr<float>)q1)[cx0];
+            i11 = ((gptr<float>)q1)[cx1];
+          }
+        }
+      }
+      const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
+      const float val = fmaf(fy, bot - top, top);
+      // bilinear partials (floor cell; clamped reads give zero outside)
+      const float ax = (1.0f - fy) * (i10 - i00) + fy * (i11 - i01);
+      const float ay = (1.0f - fx) * (i01 - i00) + fx * (i11 - i10);
+      const float v = (float)(y0 + r - N / 2);
+      const float D[6] = {ax * u, ax * v, ax, ay * u, ay * v, ay};
+      const float tap = tx[c] * trow[r];
+      const float wv = (val - kSampleOffset - mean_off) * tap;
+      const float2 gw = stage[r * RS + lidx(x)];
+      const float g0 = ch1 ? gw.y : gw.x;
+      const float tg = tap * g0, tw = tap * wv;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        acc[j] = fmaf(tg, D[j], acc[j]);
+        acc[6 + j] = fmaf(tap, D[j], acc[6 + j]);
+        acc[12 + j] = fmaf(tw, D[j], acc[12 + j]);
+      }
+      acc[18] += tg;
+      acc[19] += tw;
+      if constexpr (TWO) {
+        const float tg2 = tap * gw.y;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc2[j] = fmaf(tg2, D[j], acc2[j]);
+        acc2[18] += tg2;
+      }
+    }
   }
-  const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
-  const float val = fmaf(fy, bot - top, top);
-  // bilinear partials (floor cell; clamped reads give zero outside)
-  const float ax = (1.0f - fy) * (i10 - i00) + fy * (i11 - i01);
-  const float ay = (1.0f - fx) * (i01 - i00) + fx * (i11 - i10);
-  PixelTerms p;
-  const float uf = (float)u, vf = (float)vrow;
-  p.D[0] = ax * uf;
-  p.D[1] = ax * vf;
-  p.D[2] = ax;
-  p.D[3] = ay * uf;
-  p.D[4] = ay * vf;
-  p.D[5] = ay;
-  p.tap = tap;
-  p.w = (val - kSampleOffset - mean_off) * tap;
-  return p;
 }
 
-__device__ __forceinline__ void bwd_accumulate(float (&acc)[kBwdSums], const PixelTerms& p, float gw) {
-  const float tg = p.tap * gw, tw = p.tap * p.w;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    acc[j] = fmaf(tg, p.D[j], acc[j]);
-    acc[6 + j] = fmaf(p.tap, p.D[j], acc[6 + j]);
-    acc[12 + j] = fmaf(tw, p.D[j], acc[12 + j]);
+template <int N, bool TWO>
+__device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t* tile, const TileGeom& g,
+                                          const RowParam* rp, const float* trow,
+                                          const PixelOffsets<GatherCfg<N>::XV>& ku,
+                                          const float (&tx)[GatherCfg<N>::XV], const swift_image& im, bool trans,
+                                          int y0, int tid, float mean_off, bool ch1, float (&acc)[kBwdSums],
+                                          float (&acc2)[kBwdSums]) {
+  constexpr int R = RowsCfg<N>::FWD;
+  if (g.use) {
+    if (trans)
+      bwd_pixels<N, R, true, true, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
+    else
+      bwd_pixels<N, R, true, false, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc,
+                                         acc2);
+  } else {
+    bwd_pixels<N, R, false, false, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
   }
-  acc[18] += tg;
-  acc[19] += tw;
 }
 
 template <int N, bool CJ>
@@ -297,14 +366,81 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
   constexpr int RS = lidx(N) + 1;
-  static_assert(R % G == 0, "row split");
+  constexpr int BUDGET = RowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
+  static_assert(R % G == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
+  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
+  __shared__ RowParam rparam[2][R];
+  __shared__ float trow[R];
   __shared__ double red[4][2 * kBwdSums];
 
-  const int pair = blockIdx.x / NSLICE, slice = blockIdx.x % NSLICE, y0 = slice * R;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
   const int tid = threadIdx.x, gi = tid / T, t = tid % T;
+
+  // sampling set-up of both images (as in the forward row pass)
+  const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
+  const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
+  swift_image im[2] = {a.imgs[ka], a.imgs[kb]};
+  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  RowAffine ra[2];
+  TileGeom tg[2];
+  bool border[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    im[m].width = max(im[m].width, 2);
+    im[m].height = max(im[m].height, 2);
+    ra[m] = row_affine(th[m]);
+    tg[m] = tile_geom<N, R, BUDGET>(ra[m], im[m], y0);
+    // tiles that reach past the image edge need their edge bytes replicated
+    border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
+                  tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
+  }
+  constexpr int TRW = RowsCfg<N>::TRW, TMC = RowsCfg<N>::TMC;
+  uint32_t bufA[TRW][TMC], bufB[TRW][TMC];
+  if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
+  if (!CJ && tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
+  if (tid < 2 * R) {
+    const bool mb = tid >= R;
+    const int r = tid % R;
+    const double xc = mb ? ra[1].xc : ra[0].xc, yc = mb ? ra[1].yc : ra[0].yc;
+    const double a12 = mb ? ra[1].a12 : ra[0].a12, a22 = mb ? ra[1].a22 : ra[0].a22;
+    const int xo = mb ? (tg[1].use ? tg[1].xlo : 0) : (tg[0].use ? tg[0].xlo : 0);
+    const int yo = mb ? (tg[1].use ? tg[1].ylo : 0) : (tg[0].use ? tg[0].ylo : 0);
+    const double v = (double)(y0 + r - N / 2);
+    const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
+    const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
+    const double bxd = floor(X), byd = floor(Y);
+    RowParam p;
+    p.bx = (int)bxd - xo;
+    p.by = (int)byd - yo;
+    p.fx = (float)(X - bxd);
+    p.fy = (float)(Y - byd);
+    rparam[mb ? 1 : 0][r] = p;
+  } else if (tid >= 64 && tid < 64 + R) {
+    trow[tid - 64] = a.taper[y0 + tid - 64];
+  }
+  float tx[XV];
+  PixelOffsets<XV> ku[2];
+#pragma unroll
+  for (int c = 0; c < XV; ++c) {
+    const int x = tid % N + 256 * c;
+    const float u = (float)(x - N / 2);
+    tx[c] = a.taper[x];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const float rx = rintf(ra[m].f11), ry = rintf(ra[m].f21);
+      ku[m].ix[c] = (int)(rx * u);
+      ku[m].iy[c] = (int)(ry * u);
+      ku[m].fx[c] = (ra[m].f11 - rx) * u;
+      ku[m].fy[c] = (ra[m].f21 - ry) * u;
+    }
+  }
+  const bool trans[2] = {ra[0].a11 == 1.0 && ra[0].a12 == 0.0 && ra[0].a21 == 0.0 && ra[0].a22 == 1.0,
+                         ra[1].a11 == 1.0 && ra[1].a12 == 0.0 && ra[1].a21 == 0.0 && ra[1].a22 == 1.0};
+
+  // stage[r][kx] = Y[kx][y0 + r], then the inverse row FFTs of G_w in place
   const float2* Yp = a.Y + (size_t)pair * N * N;
-  // stage[r][kx] = Y[kx][y0 + r]
   {
     constexpr int LD = (N * R + 255) / 256;
     float2 buf[LD];
@@ -320,61 +456,47 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
     }
   }
   __syncthreads();
+  {
+    Twiddles<N> tw;
+    tw_load<N>(tw, t, a.tw);
+#pragma unroll 1
+    for (int it = 0; it < R / G; ++it) {
+      float2* row = stage + (gi + it * G) * RS;
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = row[lidx(t + e * T)];
+      wave_lds_sync();
+      fft_wave<N, true>(v, row, t, tw);  // real / imaginary channel at x = t + e T
+      wave_lds_sync();
+#pragma unroll
+      for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = v[e];
+    }
+  }
 
-  const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
-  const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
-  swift_image imA = a.imgs[ka], imB = a.imgs[kb];
-  imA.width = max(imA.width, 2);
-  imA.height = max(imA.height, 2);
-  imB.width = max(imB.width, 2);
-  imB.height = max(imB.height, 2);
-  const float* thA = a.th_a + 8 * (size_t)pair;
-  const float* thB = a.th_b + 8 * (size_t)pair;
   const PairStat ps = a.ps[pair];
   float acc0[kBwdSums], acc1[kBwdSums];
 #pragma unroll
   for (int j = 0; j < kBwdSums; ++j) acc0[j] = acc1[j] = 0.0f;
-  bool cl = false;
-  Twiddles<N> tw;
-  tw_load<N>(tw, t, a.tw);
-
-#pragma unroll 1
-  for (int it = 0; it < R / G; ++it) {
-    const int r = gi + it * G, y = y0 + r;
-    float2* row = stage + r * RS;
-    float2 v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = row[lidx(t + e * T)];
-    wave_lds_sync();
-    fft_wave<N, true>(v, row, t, tw);  // real / imaginary channel at x = t + e T
-    // park the transformed row in LDS (each lane its own elements) so that the
-    // pixel loop below indexes LDS, not a register array
-    wave_lds_sync();
-#pragma unroll
-    for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = v[e];
-    const float ty = a.taper[y];
-    const double vrow = (double)(y - N / 2);
-#pragma unroll 2
-    for (int e = 0; e < E; ++e) {
-      const int x = t + e * T;
-      const float2 g = row[lidx(x)];
-      const float tap = a.taper[x] * ty;
-      const PixelTerms pa = bwd_terms<N>(imA, thA, vrow, x, tap, ps.mA, cl);
-      bwd_accumulate(acc0, pa, g.x);
-      if constexpr (CJ) {
-        bwd_accumulate(acc1, pa, g.y);
-      } else {
-        const PixelTerms pb = bwd_terms<N>(imB, thB, vrow, x, tap, ps.mB, cl);
-        bwd_accumulate(acc1, pb, g.y);
-      }
-    }
+  if (tg[0].use) tile_store(tile, bufA, tg[0], im[0], border[0], tid);
+  __syncthreads();  // G rows and tile A visible
+  // image A: channel 0 (and, in CJ mode, channel 1 on the same pixels)
+  bwd_image<N, CJ>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.mA, false, acc0,
+                   acc1);
+  if constexpr (!CJ) {
+    __syncthreads();  // tile A consumed
+    if (tg[1].use) tile_store(tile, bufB, tg[1], im[1], border[1], tid);
+    __syncthreads();
+    bwd_image<N, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid, ps.mB, true,
+                        acc1, acc1);
   }
   // block reduction to FP64 slice partials
   const int wv = tid >> 6, ln = tid & 63;
 #pragma unroll
   for (int j = 0; j < kBwdSums; ++j) {
     const float sa = wave_sum_f32(acc0[j]);
-    const float sb = wave_sum_f32(acc1[j]);
+    // CJ: channel 1 shares P2, P3 and R with channel 0
+    const bool own = !CJ || j < 6 || j == 18;
+    const float sb = own ? wave_sum_f32(acc1[j]) : sa;
     if (ln == 0) {
       red[wv][j] = (double)sa;
       red[wv][kBwdSums + j] = (double)sb;
