@@ -229,11 +229,15 @@ int swift_centroid_jacobian(swift_ctx* ctx, const swift_image* imgs, int32_t n_i
  * theta [P][8] on the device, one thread per pair:
  *  mode SWIFT_REFINE_CENTROID: t <- t - d with d = (dx, dy), the record's
  *    sub-pixel shift;
- *  mode SWIFT_REFINE_NEWTON: Newton's method on d(t) = 0.  If the integer peak
- *    is at the origin, the record is not degenerate and det J > 1e-6 for
- *    J = [[jac[2], jac[5]], [jac[8], jac[11]]] (d d / d (tx, ty) from
- *    swift_centroid_jacobian), t <- t - J^-1 d; otherwise the centroid step.
- * Steps longer than max_step pixels are scaled down to max_step (> 0).
+ *  mode SWIFT_REFINE_NEWTON: Newton's method on the centroid.  Within the
+ *    cell of the integer peak s the centroid moves as d = s + J (t - t* - s)
+ *    with J = [[jac[2], jac[5]], [jac[8], jac[11]]] (d d / d (tx, ty) from
+ *    swift_centroid_jacobian), so t <- t - (s + J^-1 (d - s)).  Used when s
+ *    is the origin, or one of its eight neighbours with J^-1 (d - s) inside
+ *    [-0.6, 0.6]^2, the record is not degenerate and det J > 1e-6; otherwise
+ *    the centroid step.
+ * Steps longer than max_step pixels are scaled down to max_step (> 0); a
+ * Newton step may be longer by |s| (its whole-pixel part is never cut).
  * step_out: device [P] receives the length of each applied step (may be NULL).
  * recs, jac: device, as produced for the same pairs; jac may be NULL in
  * centroid mode. */

@@ -226,24 +226,35 @@ def refine_step(rec, theta, mode="centroid", jac=None, max_step=0.5):
     """Returns (new theta, step length).
 
     centroid: t <- t - d with d = (dx, dy), the centroid shift of the peak.
-    newton: Newton's method on d(t) = 0, with the 2 x 2 Jacobian J = d d / d t
-    taken from jac = [d(dx)/d theta_A, d(dy)/d theta_A] (six entries each,
-    translations at 2 and 5): t <- t - J^-1 d, used when the peak is at the
-    origin, the window is not degenerate and det J > 1e-6; otherwise the
-    centroid step.  Steps longer than max_step are scaled to max_step."""
+    Steps longer than max_step are scaled to max_step.
+
+    newton: Newton's method on the centroid, with the 2 x 2 Jacobian J =
+    d d / d t taken from jac = [d(dx)/d theta_A, d(dy)/d theta_A] (six
+    entries each, translations at 2 and 5).  Within the cell of the integer
+    peak s the centroid moves as d = s + J (t - t* - s), so
+    t <- t - (s + J^-1 (d - s)).  It applies when s is the origin, or one of
+    its eight neighbours with J^-1 (d - s) inside [-0.6, 0.6]^2 (the model
+    places t in the peak's cell), the window is not degenerate and det J >
+    1e-6; otherwise the centroid step.  The Newton step is scaled down to at most
+    |s| + max_step, so the whole-pixel part is never cut."""
     theta = np.array(theta, dtype=np.float64)
     d = np.array([rec["dx"], rec["dy"]], dtype=np.float64)
     step = -d
-    at_origin = rec["sx"] == 0 and rec["sy"] == 0
-    if mode == "newton" and jac is not None and at_origin and not (rec["status"] & STATUS_DEGENERATE):
+    limit = max_step
+    near = abs(rec["sx"]) <= 1 and abs(rec["sy"]) <= 1
+    if mode == "newton" and jac is not None and near and not (rec["status"] & STATUS_DEGENERATE):
         jac = np.asarray(jac, dtype=np.float64).reshape(2, 6)
         J = np.array([[jac[0, 2], jac[0, 5]], [jac[1, 2], jac[1, 5]]])
         if np.linalg.det(J) > 1e-6:
-            step = -np.linalg.solve(J, d)
+            sv = np.array([rec["sx"], rec["sy"]], dtype=np.float64)
+            off = np.linalg.solve(J, d - sv)
+            if (sv[0] == 0 and sv[1] == 0) or np.all(np.abs(off) <= 0.6):
+                step = -(sv + off)
+                limit = max_step + float(np.hypot(sv[0], sv[1]))
     ln = float(np.hypot(step[0], step[1]))
-    if not ln <= max_step:
-        step = step * (max_step / ln) if ln > 0 else np.zeros(2)
-        ln = max_step
+    if not ln <= limit:
+        step = step * (limit / ln) if ln > 0 else np.zeros(2)
+        ln = limit
     theta[4] += step[0]
     theta[7] += step[1]
     return theta, ln

@@ -208,23 +208,30 @@ __global__ void __launch_bounds__(256) k_refine(int P, const swift_match* __rest
   const int n = r.n > 0 ? r.n : 1;
   const int sx = r.ix >= n / 2 ? r.ix - n : r.ix, sy = r.iy >= n / 2 ? r.iy - n : r.iy;
   float dx = -r.dx, dy = -r.dy;  // centroid step
-  if (mode == SWIFT_REFINE_NEWTON && jac && sx == 0 && sy == 0 && !(r.status & SWIFT_ST_DEGENERATE)) {
-    // Newton on the centroid shift d(t) = 0: t <- t - J^-1 d, J = d d / d t
+  float limit = max_step;
+  if (mode == SWIFT_REFINE_NEWTON && jac && abs(sx) <= 1 && abs(sy) <= 1 && !(r.status & SWIFT_ST_DEGENERATE)) {
+    // Newton on the centroid within the cell of the integer peak s:
+    // d = s + J (t - t* - s)  =>  t <- t - (s + J^-1 (d - s)), J = d d / d t
     const float* q = jac + (size_t)i * 12;
     const double j00 = q[2], j01 = q[5], j10 = q[8], j11 = q[11];
     const double det = j00 * j11 - j01 * j10;
     if (det > 1e-6) {
-      const double ex = r.dx, ey = r.dy;
-      dx = (float)(-(j11 * ex - j01 * ey) / det);
-      dy = (float)(-(-j10 * ex + j00 * ey) / det);
+      const double ex = (double)r.dx - sx, ey = (double)r.dy - sy;
+      const double ox = (j11 * ex - j01 * ey) / det, oy = (-j10 * ex + j00 * ey) / det;  // offset within the cell
+      // away from the origin the linear model must place t inside the peak's cell
+      if ((sx == 0 && sy == 0) || (fabs(ox) <= 0.6 && fabs(oy) <= 0.6)) {
+        dx = (float)(-(sx + ox));
+        dy = (float)(-(sy + oy));
+        limit = max_step + sqrtf((float)(sx * sx + sy * sy));  // never cut the whole-pixel part
+      }
     }
   }
   float len = sqrtf(dx * dx + dy * dy);
-  if (!(len <= max_step)) {  // also catches NaN
-    const float sc = (len > 0.0f && len == len) ? max_step / len : 0.0f;
+  if (!(len <= limit)) {  // also catches NaN
+    const float sc = (len > 0.0f && len == len) ? limit / len : 0.0f;
     dx *= sc;
     dy *= sc;
-    len = (len == len) ? max_step : 0.0f;
+    len = (len == len) ? limit : 0.0f;
   }
   th[(size_t)i * 8 + 4] += dx;
   th[(size_t)i * 8 + 7] += dy;

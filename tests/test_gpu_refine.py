@@ -60,7 +60,7 @@ def test_refine_update_matches_oracle_rule(ctx, section, mode):
     ctx.refine_update(res["raw"], th, mode, jac, 0.5, step)
     torch.cuda.synchronize()
     thg, stg, jn = th.cpu().numpy(), step.cpu().numpy(), jac.cpu().numpy()
-    newton_steps = 0
+    newton_steps = near_steps = 0
     for i in range(k):
         rec = {key: res[key][i].item() for key in ("dx", "dy", "status")}
         ix, iy = int(res["ix"][i]), int(res["iy"][i])
@@ -70,7 +70,9 @@ def test_refine_update_matches_oracle_rule(ctx, section, mode):
         np.testing.assert_allclose(thg[i], ref, rtol=0, atol=2e-6)
         assert abs(stg[i] - ln) < 2e-6
         newton_steps += int(mode == 1 and rec["sx"] == 0 and rec["sy"] == 0)
-    assert mode == 0 or newton_steps >= 3
+        near_steps += int(mode == 1 and (rec["sx"], rec["sy"]) != (0, 0) and abs(rec["sx"]) <= 1
+                          and abs(rec["sy"]) <= 1)
+    assert mode == 0 or (newton_steps >= 3 and near_steps >= 3)
 
 
 @pytest.mark.parametrize("n", [128, 256])

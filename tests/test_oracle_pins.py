@@ -408,6 +408,18 @@ def test_newton_step_is_exact_for_linear_centroid():
     # a singular Jacobian falls back to the centroid step
     th3, _ = O.refine_step(rec, th, "newton", jac=np.zeros((2, 6)), max_step=5.0)
     np.testing.assert_allclose(th3[[4, 7]], t0 - d, atol=1e-15)
+    # the integer peak one cell off: d = s + J (t - t* - s) within that cell,
+    # and the step s + J^-1 (d - s) lands on t* even with max_step below |s|
+    t1 = np.array([0.8, -0.6])
+    s_ = np.array([1.0, -1.0])
+    d1 = s_ + J @ (t1 - s_)  # t1 is the offset t - t*
+    rec1 = dict(dx=d1[0], dy=d1[1], sx=1, sy=-1, status=0)
+    th1 = np.array([10, 10, 1, 0, t1[0] + tstar[0], 0, 1, t1[1] + tstar[1]])
+    th4, _ = O.refine_step(rec1, th1, "newton", jac=jac, max_step=0.5)
+    np.testing.assert_allclose(th4[[4, 7]], tstar + 0.0, atol=1e-12)
+    # two cells off: the centroid step, clamped
+    th5, ln5 = O.refine_step(dict(rec1, sx=2, dx=2.1), th1, "newton", jac=jac, max_step=0.5)
+    assert abs(ln5 - 0.5) < 1e-12
 
 
 def test_centroid_step_and_clamp():
