@@ -77,7 +77,7 @@ def _oracle_worker(job):
     return out, time.perf_counter() - t0
 
 
-def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=3, cores=None):
+def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=8, cores=None):
     """Times the FP64 oracle (one process per core) on a bounded sample of the
     same pairs.  Windows are cropped with a margin so clamped reads at the
     section border are reproduced exactly."""
