@@ -324,6 +324,9 @@ def main():
     ws = ctx.workspace(need)
     out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
     log("pairs: %d of %d^2, workspace %.2f GB" % (P, N, need / 1e9))
+    # row-count variants chosen on the device (synthetic batch, untimed set-up)
+    tuned = ctx.autotune(sw.SIZES, pairs_per_size=512)
+    log("autotune: " + ", ".join("%d: rows %s" % (n, v[1]) for n, v in tuned.items()))
 
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
@@ -398,6 +401,7 @@ def main():
         "alu_tflops": P * pair_flops(N) / (ms / 1e3) / 1e12,
         "roofline": roof,
         "kernels": kernels,
+        "plan": {str(n): {"fwd_rows": v[1][0], "inv_rows": v[1][1], "variant_ms": v[0]} for n, v in tuned.items()},
         "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
     }
     if not args.no_refine:

@@ -296,6 +296,26 @@ int swift_fit_sections(swift_ctx* ctx, int32_t S, int32_t per_section, const flo
                        const float* theta_b, const swift_match* recs, int32_t level, float min_snr,
                        double* aff, int32_t* status, hipStream_t stream);
 
+/* Row-count variants of the match kernels (a tuning choice, not in the
+ * paper).  Each window size has two row counts per block for the forward row
+ * pass and two for the inverse row pass (variant 0 = the default, 1 = the
+ * alternative); the results agree to rounding.  swift_plan sets the variants
+ * of size n (a value < 0 keeps the current one) and reports the rows per
+ * block in *fwd_rows / *inv_rows (either may be NULL).  Plans are per
+ * context; cached graphs are keyed by them.  Errors: SWIFT_E_INVAL. */
+int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant,
+               int32_t* fwd_rows, int32_t* inv_rows);
+
+/* Times every variant pair of each listed window size on a synthetic batch
+ * (pairs_per_size translation windows of hashed uint8 noise, p = 0.65;
+ * <= 0 means 512) and keeps the fastest in the context's plan.  Synchronous;
+ * allocates and frees its own device buffers, so it is a set-up call, not
+ * one for a capture or a serving loop.  times_ms: host [n_sizes][4] or NULL,
+ * receives the mean time per batch of variant (fwd + 2 inv) = 0..3, -1 where
+ * a variant equals another.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
+int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_t pairs_per_size,
+                   float* times_ms);
+
 /* Kernel timing (instrumentation, not in the paper).  While enabled, every
  * kernel the context launches is bracketed by a pair of HIP events recorded on
  * the launch stream (a few microseconds per launch; no work is skipped).

@@ -86,6 +86,9 @@ struct swift_ctx {
   hipStream_t cap = nullptr;
   std::map<std::string, GraphEntry> graphs;
   uint64_t tick = 0;
+  // row-count variant per window size (swift_plan / swift_autotune)
+  uint8_t alt_fwd[SWIFT_NSIZES] = {};
+  uint8_t alt_inv[SWIFT_NSIZES] = {};
 };
 
 static constexpr size_t kMaxGraphs = 16;
@@ -174,15 +177,6 @@ size_t nslice(int n) {
     default: return 1024 / RowsCfg<1024>::FWD;
   }
 }
-size_t nslice2(int n) {
-  switch (n) {
-    case 64: return 64 / RowsCfg<64>::INV;
-    case 128: return 128 / RowsCfg<128>::INV;
-    case 256: return 256 / RowsCfg<256>::INV;
-    case 512: return 512 / RowsCfg<512>::INV;
-    default: return 1024 / RowsCfg<1024>::INV;
-  }
-}
 size_t ncolwg(int n) {
   const int ipw = col_items_per_wg(n);
   return (size_t)((n / 2 + 1 + ipw - 1) / ipw);
@@ -205,11 +199,11 @@ Layout make_layout(const swift_pairs* pairs) {
     g.z = fo;
     fo += align256(P * n * n * sizeof(float2));
     g.rowpart = fo;
-    fo += align256(P * nslice(g.n) * sizeof(RowPart));
+    fo += align256(P * (size_t)max(fwd_blocks_n(g.n, false), fwd_blocks_n(g.n, true)) * sizeof(RowPart));
     g.pstat = fo;
     fo += align256(P * sizeof(PairStat));
     g.invpart = fo;
-    fo += align256(P * nslice2(g.n) * sizeof(InvPart));
+    fo += align256(P * (size_t)max(inv_blocks_n(g.n, false), inv_blocks_n(g.n, true)) * sizeof(InvPart));
     g.y = bo;
     bo += align256(P * n * n * sizeof(float2));
     g.dpart = bo;
@@ -404,11 +398,13 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.eps_rel = params->eps_rel;
     a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     a.npairs = g.count;
+    a.nsl_fwd = fwd_blocks_n(g.n, ctx->alt_fwd[i] != 0);
+    a.nsl_inv = inv_blocks_n(g.n, ctx->alt_inv[i] != 0);
     a.saved_Z = saved ? (float2*)((char*)saved + g.sz) : nullptr;
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    e = launch_match_group(g.n, a, s, kt);
+    e = launch_match_group(g.n, a, ctx->alt_fwd[i] != 0, ctx->alt_inv[i] != 0, s, kt);
     if (e != hipSuccess) return hip_fail(e, "match launch");
     if (concurrent) {
       e = hipEventRecord(ctx->join_ev[i], s);
@@ -445,6 +441,7 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     const void* p[9];
     int32_t n_imgs, n_pairs, counts[SWIFT_NSIZES];
     swift_params prm;
+    uint8_t plan[2 * SWIFT_NSIZES];
   } key;
   memset(&key, 0, sizeof(key));
   key.p[0] = imgs;
@@ -460,6 +457,10 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   key.n_pairs = pairs->n_pairs;
   for (int i = 0; i < SWIFT_NSIZES; ++i) key.counts[i] = pairs->size_count[i];
   key.prm = *params;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    key.plan[i] = ctx->alt_fwd[i];
+    key.plan[SWIFT_NSIZES + i] = ctx->alt_inv[i];
+  }
   const std::string k((const char*)&key, sizeof(key));
   auto it = ctx->graphs.find(k);
   if (it == ctx->graphs.end()) {
@@ -701,6 +702,161 @@ int swift_fit_sections(swift_ctx* ctx, int32_t S, int32_t per_section, const flo
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipError_t e = launch_fit_sections(S, per_section, theta_a, theta_b, recs, level, min_snr, aff, status, stream);
   if (e != hipSuccess) return hip_fail(e, "fit launch");
+  return ok();
+}
+
+static int size_index(int n) {
+  for (int i = 0; i < SWIFT_NSIZES; ++i)
+    if (kSizes[i] == n) return i;
+  return -1;
+}
+
+int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant, int32_t* fwd_rows,
+               int32_t* inv_rows) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  const int i = size_index(n);
+  if (i < 0) return fail(SWIFT_E_INVAL, "n must be one of 64, 128, 256, 512, 1024 (got %d)", n);
+  if (fwd_variant > 1 || inv_variant > 1) return fail(SWIFT_E_INVAL, "variants are 0, 1 or -1 (keep)");
+  if (fwd_variant >= 0) ctx->alt_fwd[i] = (uint8_t)fwd_variant;
+  if (inv_variant >= 0) ctx->alt_inv[i] = (uint8_t)inv_variant;
+  if (fwd_rows) *fwd_rows = n / fwd_blocks_n(n, ctx->alt_fwd[i] != 0);
+  if (inv_rows) *inv_rows = n / inv_blocks_n(n, ctx->alt_inv[i] != 0);
+  return ok();
+}
+
+// Synthetic tuning input: a uint8 image of hashed noise.
+__global__ void k_tune_image(uint8_t* img, int64_t n_px) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_px) return;
+  uint32_t h = (uint32_t)i * 2654435761u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  img[i] = (uint8_t)(h >> 24);
+}
+
+namespace {
+// Device buffers of one tuning batch, freed on scope exit.
+struct TuneBufs {
+  void* p[6] = {};
+  ~TuneBufs() {
+    for (void* q : p)
+      if (q) (void)hipFree(q);
+  }
+};
+}  // namespace
+
+int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_t pairs_per_size,
+                   float* times_ms) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (n_sizes < 0 || (n_sizes > 0 && !sizes)) return fail(SWIFT_E_INVAL, "bad size list");
+  for (int k = 0; k < n_sizes; ++k)
+    if (size_index(sizes[k]) < 0) return fail(SWIFT_E_INVAL, "unsupported window size %d", sizes[k]);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipStream_t st = ctx->gs[0];
+  for (int k = 0; k < n_sizes; ++k) {
+    const int n = sizes[k], si = size_index(n);
+    // square grid of windows on one image, capped at 1 GiB of pixels
+    int P = pairs_per_size > 0 ? pairs_per_size : 512;
+    int grid = (int)ceil(sqrt((double)P));
+    while (grid > 1 && (double)(grid + 2) * n * (grid + 2) * n > (double)(1u << 30)) --grid;
+    P = min(P, grid * grid);
+    const int side = (grid + 2) * n;
+    TuneBufs b;
+    hipError_t e = hipMalloc(&b.p[0], (size_t)side * side);
+    const size_t npairs = (size_t)P;
+    if (e == hipSuccess) e = hipMalloc(&b.p[1], sizeof(swift_image));
+    if (e == hipSuccess) e = hipMalloc(&b.p[2], 2 * npairs * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&b.p[3], 2 * npairs * 8 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&b.p[4], npairs * sizeof(swift_match));
+    if (e != hipSuccess) return hip_fail(e, "autotune buffers");
+    const int64_t npx = (int64_t)side * side;
+    k_tune_image<<<(unsigned)((npx + 255) / 256), 256, 0, st>>>((uint8_t*)b.p[0], npx);
+    swift_image im;
+    memset(&im, 0, sizeof(im));
+    im.data = b.p[0];
+    im.width = side;
+    im.height = side;
+    im.pitch = side;
+    im.dtype = SWIFT_U8;
+    std::vector<int32_t> idx(2 * npairs, 0);
+    std::vector<float> th(2 * npairs * 8);
+    for (size_t q = 0; q < npairs; ++q) {
+      const float cx = (float)((q % grid) + 1) * n + n / 2, cy = (float)((q / grid) + 1) * n + n / 2;
+      const float a[8] = {cx, cy, 1, 0, 0.3f, 0, 1, -0.2f};
+      const float bb[8] = {cx, cy, 1, 0, -0.1f, 0, 1, 0.4f};
+      for (int j = 0; j < 8; ++j) {
+        th[q * 8 + j] = a[j];
+        th[(npairs + q) * 8 + j] = bb[j];
+      }
+    }
+    e = hipMemcpyAsync(b.p[1], &im, sizeof(im), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.p[2], idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.p[3], th.data(), th.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "autotune inputs");
+    swift_pairs pr;
+    memset(&pr, 0, sizeof(pr));
+    pr.n_pairs = P;
+    pr.size_count[si] = P;
+    pr.img_a = (const int32_t*)b.p[2];
+    pr.img_b = (const int32_t*)b.p[2] + npairs;
+    pr.theta_a = (const float*)b.p[3];
+    pr.theta_b = (const float*)b.p[3] + npairs * 8;
+    swift_params prm;
+    memset(&prm, 0, sizeof(prm));
+    prm.p = 0.65f;
+    prm.eps_rel = 1e-4f;
+    prm.taper_frac = 0.25f;
+    prm.centroid_r = 1;
+    const Layout L = make_layout(&pr);
+    e = hipMalloc(&b.p[5], L.total);
+    if (e != hipSuccess) return hip_fail(e, "autotune workspace");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(SWIFT_E_HIP, "autotune events");
+    }
+    float best = 0.0f;
+    int best_v = 0;
+    const uint8_t keep_f = ctx->alt_fwd[si], keep_i = ctx->alt_inv[si];
+    int rc = SWIFT_OK;
+    for (int v = 0; v < 4 && rc == SWIFT_OK; ++v) {
+      const bool af = (v & 1) != 0, ai = (v & 2) != 0;
+      float ms = -1.0f;
+      const bool distinct = (!af || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
+                            (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false));
+      if (distinct) {
+        ctx->alt_fwd[si] = af;
+        ctx->alt_inv[si] = ai;
+        rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
+                           b.p[5], st, false, nullptr);  // warm-up
+        if (rc == SWIFT_OK) rc = hipEventRecord(e0, st) == hipSuccess ? SWIFT_OK : fail(SWIFT_E_HIP, "event");
+        for (int r = 0; r < 3 && rc == SWIFT_OK; ++r)
+          rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
+                             b.p[5], st, false, nullptr);
+        if (rc == SWIFT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(SWIFT_E_HIP, "autotune timing");
+        ms /= 3.0f;
+        if (rc == SWIFT_OK && (v == 0 || ms < best)) {  // variant 0 (the defaults) always runs first
+          best = ms;
+          best_v = v;
+        }
+      }
+      if (times_ms) times_ms[k * 4 + v] = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SWIFT_OK) {
+      ctx->alt_fwd[si] = keep_f;
+      ctx->alt_inv[si] = keep_i;
+      return rc;
+    }
+    ctx->alt_fwd[si] = (best_v & 1) != 0;
+    ctx->alt_inv[si] = (best_v & 2) != 0;
+  }
   return ok();
 }
 

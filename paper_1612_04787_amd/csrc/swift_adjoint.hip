@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET>(ra[m], im[m], y0);
+    tg[m] = tile_geom<N, R, BUDGET, RowsCfg<N>::TRW, RowsCfg<N>::TMC>(ra[m], im[m], y0);
     // tiles that reach past the image edge need their edge bytes replicated
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);

@@ -65,6 +65,7 @@ struct MatchArgs {
   float p, eps_rel;
   int32_t L;            // taper samples per edge
   int32_t npairs;
+  int32_t nsl_fwd, nsl_inv;  // row blocks per pair of the forward / inverse row passes
   int32_t n_imgs;
   // state kept for the adjoint (all NULL when not requested)
   float2* saved_Z;         // [P][N][N]: forward 2-D spectrum of z, [kx][ky]
@@ -105,20 +106,26 @@ struct BwdArgs {
 constexpr int kBwdSums = 20;  // per image: P1[6], P2[6], P3[6], Q, R
 constexpr int kDpart = 6;     // dJ0/de2, dJ1/de2, hxx, hyy, hxy, unused
 
-// Rows per workgroup of the forward and inverse row passes; the LDS budget
-// (bytes) of one image's source tile in the forward pass (0: always gather
-// straight from global memory) and the tile shape limits of its fetch (at
-// most 4 TRW rows of 64 TMC dwords).
+// Rows per block of the row passes, per window size.  FWD: forward row pass
+// (and adjoint row pass); INV: inverse row pass; TILE: LDS bytes of the uint8
+// source tile of a forward block (0: gather straight from memory); TRW x TMC:
+// tile dwords fetched per thread (rows w + 4j, columns lane + 64c).  FWD2 /
+// INV2 (with TILE2, TRW2) are the alternative row counts swift_autotune can
+// choose; the defaults are FWD / INV.
 template <int N> struct RowsCfg;
-template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 10, TMC = 1; };
-template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 6,  TMC = 1; };
-template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 7,  TMC = 2; };
-template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,  TMC = 3; };
-template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,  TMC = 1; };
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 10, TMC = 1,
+                                   FWD2 = 32, INV2 = 32, TILE2 = 4096, TRW2 = 10; };
+template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 6,  TMC = 1,
+                                   FWD2 = 32, INV2 = 64, TILE2 = 6720, TRW2 = 11; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 7,  TMC = 2,
+                                   FWD2 = 8,  INV2 = 32, TILE2 = 5632, TRW2 = 5; };
+template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,  TMC = 3,
+                                   FWD2 = 4,  INV2 = 8,  TILE2 = 8576, TRW2 = 4; };
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,  TMC = 1,
+                                   FWD2 = 4,  INV2 = 8,  TILE2 = 0,    TRW2 = 1; };
 
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 
-size_t pair_ws_bytes(int n);   // exchange + partial buffers for one pair
 size_t align256(size_t x);
 
 // Optional kernel timing: when non-null, launchers bracket every kernel with
@@ -131,7 +138,11 @@ struct KernelTimer {
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s);
-hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
+// alt_fwd / alt_inv select the alternative row counts (FWD2 / INV2); the
+// slice counts a.nsl_fwd and a.nsl_inv must match the choice.
+hipError_t launch_match_group(int n, const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt);
+int fwd_blocks_n(int n, bool alt);  // forward row blocks per pair
+int inv_blocks_n(int n, bool alt);  // inverse row blocks per pair
 hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);
 int col_items_per_wg(int n);  // column-pass workgroups per pair
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);

@@ -195,10 +195,10 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, co
   }
 }
 
-template <int N, int BUDGET>
+template <int N, int R, int BUDGET, int TRW>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
+  constexpr int T = C::T, E = C::E, G = 256 / T, NSLICE = N / R;
   constexpr int RS = fwd_stride<N, R>();
   constexpr int XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
@@ -226,13 +226,13 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET>(ra[m], im[m], y0);
+    tg[m] = tile_geom<N, R, BUDGET, TRW, RowsCfg<N>::TMC>(ra[m], im[m], y0);
     // could any sample read outside the image?  (one pixel of slack for rounding)
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
   }
   // all tile loads of both images in flight before anything waits on them
-  constexpr int TRW = RowsCfg<N>::TRW, TMC = RowsCfg<N>::TMC;
+  constexpr int TMC = RowsCfg<N>::TMC;
   uint32_t bufA[TRW][TMC], bufB[TRW][TMC];
   if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
   if (tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
 // ---------------------------------------------------------------- pair statistics
 template <int N>
 __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
-  constexpr int NSLICE = N / RowsCfg<N>::FWD;
+  const int NSLICE = a.nsl_fwd;
   const int pair = blockIdx.x, ln = threadIdx.x;
   double s[6] = {0, 0, 0, 0, 0, 0};
   int cl = 0;
@@ -468,10 +468,10 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
 }
 
 // ---------------------------------------------------------------- row pass (inverse) + statistics
-template <int N>
+template <int N, int R2>
 __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, G = 256 / T, R2 = RowsCfg<N>::INV, NT = R2 / 2, NSL2 = N / R2;
+  constexpr int T = C::T, E = C::E, G = 256 / T, NT = R2 / 2, NSL2 = N / R2;
   constexpr int NH = N / 2 + 1, RS2 = N / 2 + N / 32 + 1;
   static_assert(2 * RS2 >= lidx(N - 1) + 1, "row pair must hold the FFT scratch");
   __shared__ float2 stage[R2 * RS2];
@@ -598,7 +598,8 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
 template <int N>
 __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
   using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, NSL2 = N / RowsCfg<N>::INV;
+  constexpr int T = C::T, E = C::E;
+  const int NSL2 = a.nsl_inv;
   constexpr int SL = lidx(N);
   __shared__ float2 lds[SL];
   __shared__ float nb[3][3];
@@ -677,23 +678,6 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
 // ---------------------------------------------------------------- launchers
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-template <int N>
-static size_t pair_bytes_t() {
-  const size_t nsl = N / RowsCfg<N>::FWD, nsl2 = N / RowsCfg<N>::INV;
-  return (size_t)N * N * sizeof(float2) + nsl * sizeof(RowPart) + sizeof(PairStat) + nsl2 * sizeof(InvPart);
-}
-
-size_t pair_ws_bytes(int n) {
-  switch (n) {
-    case 64: return pair_bytes_t<64>();
-    case 128: return pair_bytes_t<128>();
-    case 256: return pair_bytes_t<256>();
-    case 512: return pair_bytes_t<512>();
-    case 1024: return pair_bytes_t<1024>();
-  }
-  return 0;
-}
-
 hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s) {
   const int L = (int)floor((double)taper_frac * n / 2.0 + 0.5);
   k_taper<<<(n + 255) / 256, 256, 0, s>>>(n, L, tau, taper, info);
@@ -711,15 +695,15 @@ struct TimerScope {
   }
 };
 
-template <int N>
-static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
+template <int N, int R, int BUDGET, int TRW, int R2>
+static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
   using C = FftCfg<N>;
-  constexpr int NSLICE = N / RowsCfg<N>::FWD, NSL2 = N / RowsCfg<N>::INV;
   constexpr int G = 256 / C::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
   const unsigned P = (unsigned)a.npairs;
+  if (a.nsl_fwd != N / R || a.nsl_inv != N / R2) return hipErrorInvalidValue;
   {
     TimerScope ts(kt, "k_row_fwd", N, s);
-    k_row_fwd<N, RowsCfg<N>::TILE><<<P * NSLICE, 256, 0, s>>>(a);
+    k_row_fwd<N, R, BUDGET, TRW><<<P * (N / R), 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_pair_stats", N, s);
@@ -731,7 +715,7 @@ static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   {
     TimerScope ts(kt, "k_row_inv", N, s);
-    k_row_inv<N><<<P * NSL2, 256, 0, s>>>(a);
+    k_row_inv<N, R2><<<P * (N / R2), 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_finalize", N, s);
@@ -740,15 +724,44 @@ static hipError_t launch_group_t(const MatchArgs& a, hipStream_t s, KernelTimer*
   return hipGetLastError();
 }
 
+template <int N>
+static hipError_t launch_group_t(const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt) {
+  using RC = RowsCfg<N>;
+  if (!alt_fwd && !alt_inv) return launch_group_v<N, RC::FWD, RC::TILE, RC::TRW, RC::INV>(a, s, kt);
+  if (!alt_fwd && alt_inv) return launch_group_v<N, RC::FWD, RC::TILE, RC::TRW, RC::INV2>(a, s, kt);
+  if (alt_fwd && !alt_inv) return launch_group_v<N, RC::FWD2, RC::TILE2, RC::TRW2, RC::INV>(a, s, kt);
+  return launch_group_v<N, RC::FWD2, RC::TILE2, RC::TRW2, RC::INV2>(a, s, kt);
+}
+
 int col_items_per_wg(int n) { return (256 / (n <= 512 ? n / 8 : 64)) / 2; }
 
-hipError_t launch_match_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
+int fwd_blocks_n(int n, bool alt) {
   switch (n) {
-    case 64: return launch_group_t<64>(a, s, kt);
-    case 128: return launch_group_t<128>(a, s, kt);
-    case 256: return launch_group_t<256>(a, s, kt);
-    case 512: return launch_group_t<512>(a, s, kt);
-    case 1024: return launch_group_t<1024>(a, s, kt);
+    case 64: return 64 / (alt ? RowsCfg<64>::FWD2 : RowsCfg<64>::FWD);
+    case 128: return 128 / (alt ? RowsCfg<128>::FWD2 : RowsCfg<128>::FWD);
+    case 256: return 256 / (alt ? RowsCfg<256>::FWD2 : RowsCfg<256>::FWD);
+    case 512: return 512 / (alt ? RowsCfg<512>::FWD2 : RowsCfg<512>::FWD);
+    default: return 1024 / (alt ? RowsCfg<1024>::FWD2 : RowsCfg<1024>::FWD);
+  }
+}
+
+int inv_blocks_n(int n, bool alt) {
+  switch (n) {
+    case 64: return 64 / (alt ? RowsCfg<64>::INV2 : RowsCfg<64>::INV);
+    case 128: return 128 / (alt ? RowsCfg<128>::INV2 : RowsCfg<128>::INV);
+    case 256: return 256 / (alt ? RowsCfg<256>::INV2 : RowsCfg<256>::INV);
+    case 512: return 512 / (alt ? RowsCfg<512>::INV2 : RowsCfg<512>::INV);
+    default: return 1024 / (alt ? RowsCfg<1024>::INV2 : RowsCfg<1024>::INV);
+  }
+}
+
+hipError_t launch_match_group(int n, const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt) {
+  switch (n) {
+    case 64: return launch_group_t<64>(a, alt_fwd, alt_inv, s, kt);
+    case 128: return launch_group_t<128>(a, alt_fwd, alt_inv, s, kt);
+    case 256: return launch_group_t<256>(a, alt_fwd, alt_inv, s, kt);
+    case 512: return launch_group_t<512>(a, alt_fwd, alt_inv, s, kt);
+    case 1024: return launch_group_t<1024>(a, alt_fwd, alt_inv, s, kt);
   }
   return hipErrorInvalidValue;
 }

@@ -37,7 +37,7 @@ __device__ __forceinline__ RowAffine row_affine(const float* th) {
 
 __device__ __forceinline__ int floor_to4(int v) { return v - (((v % 4) + 4) % 4); }
 
-template <int N, int R, int BUDGET>
+template <int N, int R, int BUDGET, int TRW, int TMC>
 __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_image& im, int y0) {
   TileGeom g;
   const double ulo = -N / 2, uhi = N / 2 - 1;
@@ -60,7 +60,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.ylo = yl;
   g.wt4 = (xh - g.xlo + 4) / 4;
   g.ht = yh - yl + 1;
-  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET && g.ht <= 4 * RowsCfg<N>::TRW && g.wt4 <= 64 * RowsCfg<N>::TMC;
+  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET && g.ht <= 4 * TRW && g.wt4 <= 64 * TMC;
   return g;
 }
 

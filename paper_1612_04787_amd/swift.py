@@ -65,6 +65,8 @@ def load_library(path: str = LIB_PATH):
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
     lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
     lib.swift_match_graph.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
+    lib.swift_plan.argtypes = [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+    lib.swift_autotune.argtypes = [vp, C.POINTER(i32), i32, i32, C.POINTER(C.c_float)]
     lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
                                          vp, vp, sz, vp]
     lib.swift_project.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i64, i64, vp]
@@ -81,7 +83,7 @@ def load_library(path: str = LIB_PATH):
     for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
               "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read",
               "swift_refine_update", "swift_centroid_jacobian", "swift_render", "swift_stack_windows",
-              "swift_fit_sections", "swift_match_graph"):
+              "swift_fit_sections", "swift_match_graph", "swift_plan", "swift_autotune"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -92,7 +94,7 @@ def exported_symbols():
             "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
             "swift_profile_enable", "swift_profile_read", "swift_refine_update",
             "swift_centroid_jacobian", "swift_render", "swift_stack_windows", "swift_fit_sections",
-            "swift_match_graph"]
+            "swift_match_graph", "swift_plan", "swift_autotune"]
 
 
 def _check(rc):
@@ -324,6 +326,23 @@ class Swift:
         P = theta.shape[0]
         _check(self.lib.swift_refine_update(self.h, P, _ptr(recs_raw), _ptr(jac), _ptr(theta), int(mode),
                                             float(max_step), _ptr(step_out), self.stream()))
+
+    # ------------------------------------------------------------------ tuning
+    def plan(self, n, fwd_variant=-1, inv_variant=-1):
+        """Sets (values >= 0) and returns the row-count variants of size n as
+        (forward rows per block, inverse rows per block)."""
+        fr, ir = C.c_int32(), C.c_int32()
+        _check(self.lib.swift_plan(self.h, int(n), int(fwd_variant), int(inv_variant), C.byref(fr), C.byref(ir)))
+        return fr.value, ir.value
+
+    def autotune(self, sizes=SIZES, pairs_per_size=512):
+        """Times the row-count variants of each size and keeps the fastest.
+        Returns {n: (times_ms[4], (fwd_rows, inv_rows))}."""
+        sizes = [int(n) for n in sizes]
+        arr = (C.c_int32 * len(sizes))(*sizes)
+        times = (C.c_float * (4 * len(sizes)))()
+        _check(self.lib.swift_autotune(self.h, arr, len(sizes), int(pairs_per_size), times))
+        return {n: (list(times[4 * k:4 * k + 4]), self.plan(n)) for k, n in enumerate(sizes)}
 
     # ------------------------------------------------------------------ stack loop
     def render(self, src, aff, level, out_hw=None, out=None):

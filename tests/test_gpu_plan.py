@@ -1,0 +1,78 @@
+"""Row-count variants of the match kernels: every variant of every window
+size matches the FP64 oracle; the autotuner times them and keeps one."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from parity_util import compare, gpu_record
+
+pytestmark = pytest.mark.gpu
+SIZES = (64, 128, 256, 512, 1024)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1612_04787_amd as sw
+    c = sw.Swift(0)
+    yield c
+    c.close()
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def pair():
+    from datagen import make_section_pair
+    a, b, _, _ = make_section_pair(1500, 1500, 71, 771, device="cpu", max_shift=5.0)
+    return a, b
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("variant", [(0, 1), (1, 0), (1, 1)])
+def test_variants_match_oracle(ctx, pair, n, variant):
+    import paper_1612_04787_amd as sw
+    fv, iv = variant
+    rows = ctx.plan(n, fv, iv)
+    print("case plan n=%d variant=%s rows=%s" % (n, variant, rows), flush=True)
+    try:
+        a, b = pair
+        rng = np.random.default_rng(500 + n + 10 * fv + iv)
+        k = 3
+        th = np.zeros((k, 8), np.float32)
+        for i in range(k):
+            lin = [1, 0, 0, 1] if i == 0 else list(1 + rng.uniform(-2e-3, 2e-3, 1)) + \
+                list(rng.uniform(-5e-3, 5e-3, 2)) + list(1 + rng.uniform(-2e-3, 2e-3, 1))
+            th[i] = [rng.uniform(n / 2 + 8, 1500 - n / 2 - 8), rng.uniform(n / 2 + 8, 1500 - n / 2 - 8),
+                     lin[0], lin[1], rng.uniform(-2, 2), lin[2], lin[3], rng.uniform(-2, 2)]
+        thb = th.copy()
+        thb[:, 4] += 0.7
+        res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                              torch.ones(k, dtype=torch.int32), torch.from_numpy(th), torch.from_numpy(thb),
+                              sw.make_params(p=0.65), surfaces=True)
+        torch.cuda.synchronize()
+        surf = res["surfaces"].view(k, n, n).cpu().numpy()
+        for i in range(k):
+            r = O.match_pair(a.numpy(), b.numpy(), th[i].astype(np.float64), thb[i].astype(np.float64), n,
+                             O.Params(p=0.65), return_surface=True)
+            e = compare(gpu_record(res, i), r, n, surf[i], "plan n=%d %s i=%d" % (n, variant, i))
+            print("  ", i, e, flush=True)
+    finally:
+        ctx.plan(n, 0, 0)
+
+
+def test_autotune_picks_a_timed_variant(ctx):
+    print("case autotune", flush=True)
+    out = ctx.autotune(SIZES, pairs_per_size=128)
+    for n, (times, rows) in out.items():
+        print("   n=%d times_ms=%s -> rows %s" % (n, ["%.3f" % t for t in times], rows), flush=True)
+        assert times[0] > 0
+        valid = [(t, v) for v, t in enumerate(times) if t > 0]
+        best = min(valid)[1]
+        assert rows == ctx.plan(n)
+        ctx.plan(n, best & 1, best >> 1)
+        assert ctx.plan(n) == rows
+    for n in SIZES:
+        ctx.plan(n, 0, 0)
