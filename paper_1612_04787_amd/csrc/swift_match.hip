@@ -467,6 +467,96 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
   }
 }
 
+// Column pass with one FFT group per column pair: the group transforms
+// columns N - kx and kx, splits, whitens and inverse-transforms column kx,
+// exchanging the mirror column through its own LDS slot (no block barrier,
+// no idle groups).  Same results as k_col.
+template <int N>
+__global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, E = C::E, G = 256 / T;
+  constexpr int NI = N / 2 + 1, NW = (NI + G - 1) / G;
+  constexpr int SL = lidx(N);
+  __shared__ float2 lds[G * SL];
+
+  const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
+  const int tid = threadIdx.x, c = tid / T, t = tid % T;
+  const int w = wg * G + c;
+  if (w >= NI) return;  // whole groups only; no block-level barrier follows
+  const int wm = (N - w) & (N - 1);  // mirror column
+  float2* Zp = a.Z + (size_t)pair * N * N;
+  float2* slot = lds + c * SL;
+  Twiddles<N> tw;
+  tw_load<N>(tw, t, a.tw);
+
+  float2 v[E], u[E];
+  {
+    const float2* src = Zp + (size_t)w * N;
+    const float2* srm = Zp + (size_t)wm * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = srm[t + e * T];
+  }
+  fft_wave<N, false>(v, slot, t, tw);
+  wave_lds_sync();
+  if (wm != w) {
+    fft_wave<N, false>(u, slot, t, tw);
+    wave_lds_sync();
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = v[e];
+  }
+  if (a.saved_Z) {
+    float2* sz = a.saved_Z + (size_t)pair * N * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sz[(size_t)w * N + t + e * T] = v[e];
+    if (wm != w) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sz[(size_t)wm * N + t + e * T] = u[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) slot[lidx(t + e * T)] = u[e];
+  wave_lds_sync();
+
+  const PairStat ps = a.pstat[pair];
+  const float2 tauw = a.tau[w];
+  const float p = a.p;
+  const float hp = -0.5f * p;
+  const float inv_m = 1.0f / (float)(N * N);
+  const bool zero_all = (ps.flags & 1) != 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int ky = t + e * T;
+    const float2 zp = v[e];
+    const float2 zm = cconj(slot[lidx((N - ky) & (N - 1))]);
+    // F_A = (Z(k) + conj Z(-k)) / 2,  F_B = (Z(k) - conj Z(-k)) / (2i)
+    float2 fa = cscale(cadd(zp, zm), 0.5f);
+    const float2 dd = csub(zp, zm);
+    float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
+    const float2 tk = cmul(a.tau[ky], tauw);
+    fa = csub(fa, cscale(tk, ps.mA));
+    fb = csub(fb, cscale(tk, ps.mB));
+    // X = conj(F_A) F_B, C = X (|X|^2 + eps^2)^(-p/2) / N^2
+    const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
+    const float d = X.x * X.x + X.y * X.y + ps.eps2;
+    float gs;
+    if (p == 0.0f) gs = 1.0f;
+    else if (!(d > 0.0f)) gs = 0.0f;
+    else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
+    else gs = __builtin_amdgcn_exp2f(hp * __builtin_amdgcn_logf(d));
+    gs *= inv_m;
+    if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
+    v[e] = cscale(X, gs);
+  }
+  wave_lds_sync();  // every lane has read its mirror values
+  fft_wave<N, true>(v, slot, t, tw);
+  float2* dst = Zp + (size_t)w * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+}
+
 // ---------------------------------------------------------------- row pass (inverse) + statistics
 template <int N, int R2>
 __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
@@ -711,7 +801,12 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   {
     TimerScope ts(kt, "k_col", N, s);
-    k_col<N><<<P * NW, 256, 0, s>>>(a);
+    if constexpr (N <= 512) {
+      constexpr int NW2 = (N / 2 + 1 + G - 1) / G;
+      k_col_pair<N><<<P * NW2, 256, 0, s>>>(a);
+    } else {
+      k_col<N><<<P * NW, 256, 0, s>>>(a);
+    }
   }
   {
     TimerScope ts(kt, "k_row_inv", N, s);
