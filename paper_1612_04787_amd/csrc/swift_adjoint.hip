@@ -39,42 +39,47 @@
 namespace swift {
 
 // ---------------------------------------------------------------- column stage
+// One FFT group per column pair (kx = w and its mirror N - w): the group
+// reads both saved forward spectra, forms Q(., w) = G_FA + i G_FB and, through
+// its own two LDS slots, Q(., N - w), and inverse-transforms both columns.
+template <int N>
+constexpr int bwd_col_blocks() {
+  return (N / 2 + 1 + 256 / FftCfg<N>::T - 1) / (256 / FftCfg<N>::T);
+}
+
 template <int N, bool CJ>
 __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
-  constexpr int NI = N / 2 + 1, NW = (NI + IPW - 1) / IPW;
+  constexpr int T = C::T, E = C::E, G = 256 / T;
+  constexpr int NI = N / 2 + 1, NW = bwd_col_blocks<N>();
   constexpr int SL = lidx(N);
-  __shared__ float2 lds[G * SL];
+  __shared__ float2 lds[2 * G * SL];
   __shared__ double red[4][kDpart];
 
   const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
   const int tid = threadIdx.x, c = tid / T, t = tid % T;
-  const int which = c / IPW, item = c % IPW, w = wg * IPW + item;
+  const int w = wg * G + c;
   const bool valid = w < NI;
-  const int col = which == 0 ? w : ((N - w) & (N - 1));
-  float2* slotA = lds + item * SL;          // transform of column w
-  float2* slotB = lds + (item + IPW) * SL;  // transform of column N - w
-  float2 v[E];
+  const int wm = (N - w) & (N - 1);  // mirror column
+  float2* slotA = lds + (2 * c) * SL;
+  float2* slotB = lds + (2 * c + 1) * SL;
+  float2 v[E], u[E];
   Twiddles<N> tw;
   tw_load<N>(tw, t, a.tw);
-  float2 tau[E];
   if (valid) {
-    const float2* src = a.Zf + (size_t)pair * N * N + (size_t)col * N;
+    const float2* src = a.Zf + (size_t)pair * N * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
+    for (int e = 0; e < E; ++e) v[e] = src[(size_t)w * N + t + e * T];
 #pragma unroll
-    for (int e = 0; e < E; ++e) tau[e] = a.tau[t + e * T];
-    if (which == 1) {
+    for (int e = 0; e < E; ++e) u[e] = src[(size_t)wm * N + t + e * T];
 #pragma unroll
-      for (int e = 0; e < E; ++e) slotB[lidx(t + e * T)] = v[e];
-    }
+    for (int e = 0; e < E; ++e) slotB[lidx(t + e * T)] = u[e];
   }
-  __syncthreads();
+  wave_lds_sync();
 
   float dj = 0.0f, dj1 = 0.0f, hxx = 0.0f, hyy = 0.0f, hxy = 0.0f;
   float2 gb[E];
-  if (valid && which == 0) {
+  if (valid) {
     const PairStat ps = a.ps[pair];
     const swift_match rec = a.rec[pair];
     const float gp = a.g_peak ? a.g_peak[pair] : 0.0f;
@@ -127,7 +132,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       float2 fa = cscale(cadd(zp, zm), 0.5f);
       const float2 dd = csub(zp, zm);
       float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
-      const float2 tk = cmul(tau[e], tauw);
+      const float2 tk = cmul(a.tau[ky], tauw);
       fa = csub(fa, cscale(tk, ps.mA));
       fb = csub(fb, cscale(tk, ps.mB));
       const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
@@ -183,35 +188,36 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         gfb = cmul(cconj(gxy), fb);  // imaginary channel: d(dy)
       }
       v[e] = make_float2(gfa.x - gfb.y, gfa.y + gfb.x);  // Q(ky, w) = G_FA + i G_FB
-      // keep G_FA, G_FB of column w for the mirrored column (read after the barrier)
-      tau[e] = gfa;
+      // G_FA, G_FB of column w for the mirrored column (slot A is free; slot
+      // B still holds mirror spectra other lanes read)
+      slotA[lidx(ky)] = gfa;
       gb[e] = gfb;
     }
-    // slot B is overwritten only after every lane of this wave has read its mirror value
     wave_lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      slotA[lidx(t + e * T)] = tau[e];
-      slotB[lidx(t + e * T)] = gb[e];
-    }
-  }
-  __syncthreads();
-  if (valid && which == 1) {
-    // Q(ky, N - w) = conj(G_FA(-ky, w)) + i conj(G_FB(-ky, w))
+    for (int e = 0; e < E; ++e) slotB[lidx(t + e * T)] = gb[e];
+    wave_lds_sync();
+    if (wm != w) {
+      // Q(ky, N - w) = conj(G_FA(-ky, w)) + i conj(G_FB(-ky, w))
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int ky = t + e * T;
-      const float2 ga = cconj(slotA[lidx((N - ky) & (N - 1))]);
-      const float2 gb = cconj(slotB[lidx((N - ky) & (N - 1))]);
-      v[e] = make_float2(ga.x - gb.y, ga.y + gb.x);
+      for (int e = 0; e < E; ++e) {
+        const int ky = t + e * T;
+        const float2 ga = cconj(slotA[lidx((N - ky) & (N - 1))]);
+        const float2 gbm = cconj(slotB[lidx((N - ky) & (N - 1))]);
+        u[e] = make_float2(ga.x - gbm.y, ga.y + gbm.x);
+      }
     }
-  }
-  __syncthreads();
-  if (valid && (which == 0 || col != w)) {
-    fft_wave<N, true>(v, which == 0 ? slotA : slotB, t, tw);
-    float2* dst = a.Y + (size_t)pair * N * N + (size_t)col * N;
+    wave_lds_sync();
+    float2* dst = a.Y + (size_t)pair * N * N;
+    fft_wave<N, true>(v, slotA, t, tw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+    for (int e = 0; e < E; ++e) dst[(size_t)w * N + t + e * T] = v[e];
+    if (wm != w) {
+      wave_lds_sync();
+      fft_wave<N, true>(u, slotB, t, tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[(size_t)wm * N + t + e * T] = u[e];
+    }
   }
   // per-workgroup partials of dJ/d(eps^2) and of the Hessian sums
   const float vals[kDpart] = {wave_sum_f32(dj), wave_sum_f32(dj1), wave_sum_f32(hxx), wave_sum_f32(hyy),
@@ -510,7 +516,7 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 // ---------------------------------------------------------------- per pair
 template <int N, bool CJ>
 __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
-  constexpr int G = 256 / FftCfg<N>::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
+  constexpr int NW = bwd_col_blocks<N>();
   constexpr int NSLICE = N / RowsCfg<N>::FWD;
   __shared__ double tot[2 * kBwdSums];
   const int pair = blockIdx.x, ln = threadIdx.x;
@@ -564,7 +570,7 @@ __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
 // ---------------------------------------------------------------- launcher
 template <int N, bool CJ>
 static hipError_t launch_bwd_t(const BwdArgs& a, hipStream_t s, KernelTimer* kt) {
-  constexpr int G = 256 / FftCfg<N>::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
+  constexpr int NW = bwd_col_blocks<N>();
   constexpr int NSLICE = N / RowsCfg<N>::FWD;
   const unsigned P = (unsigned)a.npairs;
   if (kt) kt->begin(CJ ? "k_cj_col" : "k_bwd_col", N, s);
