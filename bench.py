@@ -291,6 +291,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the plain vs adjoint refinement comparison")
     ap.add_argument("--no-stack", action="store_true", help="skip the iterative stack-alignment run")
     ap.add_argument("--no-ragged", action="store_true", help="skip the multi-level ragged batch comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default row-count plan (no tuning launches)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -325,8 +326,11 @@ def main():
     out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
     log("pairs: %d of %d^2, workspace %.2f GB" % (P, N, need / 1e9))
     # row-count variants chosen on the device (synthetic batch, untimed set-up)
-    tuned = ctx.autotune(sw.SIZES, pairs_per_size=512)
-    log("autotune: " + ", ".join("%d: rows %s" % (n, v[1]) for n, v in tuned.items()))
+    if args.no_autotune:
+        tuned = {n: ([], ctx.plan(n)) for n in sw.SIZES}
+    else:
+        tuned = ctx.autotune(sw.SIZES, pairs_per_size=512)
+    log("plan: " + ", ".join("%d: rows %s" % (n, v[1]) for n, v in tuned.items()))
 
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)

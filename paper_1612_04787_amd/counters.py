@@ -7,7 +7,8 @@
 `stats` condenses a `--kernel-trace --stats` run to one line per kernel
 (calls, average and total duration).  `pmc` averages every counter per
 dispatch of each kernel.  `traffic` turns one FETCH_SIZE run and one
-WRITE_SIZE run (KiB per dispatch) into HBM bytes per launch, each scaled by
+WRITE_SIZE run (KiB per dispatch; each kernel's largest-grid dispatches)
+into HBM bytes per launch, each scaled by
 the factor that makes the same counter read exactly `copy-bytes` for a plain
 device-to-device copy of that size launched in the same program, and records
 the digest of the kernel sources the numbers belong to.
@@ -79,13 +80,24 @@ def stats(path):
     return "\n".join(lines)
 
 
-def per_kernel_counters(path):
-    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+def per_kernel_counters(path, largest_grid=False):
+    """{kernel: {counter: [value per dispatch]}}; with largest_grid only the
+    dispatches of each kernel's largest grid (the production batch, not the
+    smaller set-up or tuning launches of the same kernel)."""
+    rows = []
     for r in _rows(path):
         name = short_name(r.get("Kernel_Name", ""))
-        if not name:
+        if name:
+            rows.append((name, int(float(r.get("Grid_Size", 0) or 0)), r["Counter_Name"],
+                         float(r["Counter_Value"])))
+    top = collections.defaultdict(int)
+    for name, grid, _, _ in rows:
+        top[name] = max(top[name], grid)
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, grid, ctr, val in rows:
+        if largest_grid and not name.startswith("copy:") and grid != top[name]:
             continue
-        acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        acc[name][ctr].append(val)
     return acc
 
 
@@ -101,8 +113,8 @@ def pmc(path):
 
 
 def traffic(fetch_csv, write_csv, copy_bytes):
-    f = per_kernel_counters(fetch_csv)
-    w = per_kernel_counters(write_csv)
+    f = per_kernel_counters(fetch_csv, largest_grid=True)
+    w = per_kernel_counters(write_csv, largest_grid=True)
 
     def mean(d, name, ctr):
         v = d.get(name, {}).get(ctr, [])
