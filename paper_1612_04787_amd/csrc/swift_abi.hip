@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "swift_fft.hpp"
 #include "swift_internal.hpp"
 
 using namespace swift;
@@ -74,7 +75,7 @@ struct GraphEntry {
 
 struct swift_ctx {
   int device;
-  float2* tw;  // W_1024^m = exp(-2 pi i m / 1024)
+  float2* tw;  // W_1024^m = exp(-2 pi i m / 1024), then the lane-major register twiddles
   bool profile = false;
   EventTimer timer;
   KernelTimer* kt() { return profile ? &timer : nullptr; }
@@ -253,6 +254,15 @@ int check_params(const swift_params* pr) {
 
 }  // namespace
 
+// Lane-major register twiddles of size N, copied from the W_1024 table.
+template <int N>
+static void fill_lane_twiddles(float2* host) {
+  for (int t = 0; t < FftCfg<N>::T; ++t) {
+    float2* row = host + twl_off(N) + t * tw_pad<N>();
+    for (int i = 0; i < tw_pad<N>(); ++i) row[i] = i < tw_count<N>() ? host[tw_index<N>(t, i)] : make_float2(0.f, 0.f);
+  }
+}
+
 extern "C" {
 
 const char* swift_last_error(void) { return g_err.c_str(); }
@@ -266,15 +276,20 @@ int swift_create(int device, swift_ctx** out) {
   if (device < 0 || device >= ndev) return fail(SWIFT_E_INVAL, "device %d out of range (%d devices)", device, ndev);
   DeviceGuard dg(device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", device);
-  float2 host[1024];
+  std::vector<float2> host(kTwTotal);
   for (int m = 0; m < 1024; ++m) {
     const double a = -2.0 * M_PI * (double)m / 1024.0;
     host[m] = make_float2((float)cos(a), (float)sin(a));
   }
+  fill_lane_twiddles<64>(host.data());
+  fill_lane_twiddles<128>(host.data());
+  fill_lane_twiddles<256>(host.data());
+  fill_lane_twiddles<512>(host.data());
+  fill_lane_twiddles<1024>(host.data());
   float2* tw = nullptr;
-  e = hipMalloc((void**)&tw, sizeof(host));
+  e = hipMalloc((void**)&tw, host.size() * sizeof(float2));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddles)");
-  e = hipMemcpy(tw, host, sizeof(host), hipMemcpyHostToDevice);
+  e = hipMemcpy(tw, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(tw);
     return hip_fail(e, "hipMemcpy(twiddles)");

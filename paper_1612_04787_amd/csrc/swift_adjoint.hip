@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   constexpr int BUDGET = RowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
-  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
+  __shared__ __align__(16) uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
   __shared__ RowParam rparam[2][R];
   __shared__ float trow[R];
   __shared__ double red[4][2 * kBwdSums];
@@ -397,15 +397,15 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET, RowsCfg<N>::TRW, RowsCfg<N>::TMC>(ra[m], im[m], y0);
+    tg[m] = tile_geom<N, R, BUDGET, RowsCfg<N>::TRW>(ra[m], im[m], y0);
     // tiles that reach past the image edge need their edge bytes replicated
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
   }
-  constexpr int TRW = RowsCfg<N>::TRW, TMC = RowsCfg<N>::TMC;
-  uint32_t bufA[TRW][TMC], bufB[TRW][TMC];
-  if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
-  if (!CJ && tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
+  constexpr int TRW = RowsCfg<N>::TRW;
+  uint4 bufA[TRW], bufB[TRW];
+  if (tg[0].use) tile_fetch<tile_cw<N>()>(bufA, tg[0], im[0], tid);
+  if (!CJ && tg[1].use) tile_fetch<tile_cw<N>()>(bufB, tg[1], im[1], tid);
   if (tid < 2 * R) {
     const bool mb = tid >= R;
     const int r = tid % R;
@@ -483,14 +483,14 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   float acc0[kBwdSums], acc1[kBwdSums];
 #pragma unroll
   for (int j = 0; j < kBwdSums; ++j) acc0[j] = acc1[j] = 0.0f;
-  if (tg[0].use) tile_store(tile, bufA, tg[0], im[0], border[0], tid);
+  if (tg[0].use) tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
   __syncthreads();  // G rows and tile A visible
   // image A: channel 0 (and, in CJ mode, channel 1 on the same pixels)
   bwd_image<N, CJ>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.mA, false, acc0,
                    acc1);
   if constexpr (!CJ) {
     __syncthreads();  // tile A consumed
-    if (tg[1].use) tile_store(tile, bufB, tg[1], im[1], border[1], tid);
+    if (tg[1].use) tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     bwd_image<N, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid, ps.mB, true,
                         acc1, acc1);

@@ -151,25 +151,53 @@ struct Twiddles {
   float2 w[tw_count<N>()];
 };
 
-// tab: W_1024^m = exp(-2 pi i m / 1024), m in [0, 1024), float2 (global memory).
-template <int N, int P, int NS>
-__device__ __forceinline__ void tw_load_pass(Twiddles<N>& tw, int t, const float2* __restrict__ tab) {
+// Index m (into W_1024^m) of register twiddle i of lane t: pass P's block of
+// (E/R) (R-1) values holds, for butterfly b and input q >= 1, W_{NS R}^(q k)
+// with k = (t + b T) mod NS, i.e. m = q k (1024 / (NS R)).
+template <int N>
+__host__ __device__ constexpr int tw_index(int t, int i) {
   using C = FftCfg<N>;
-  if constexpr (P < C::NP) {
-    constexpr int R = C::rad(P), B = C::E / R, TWS = 1024 / (NS * R), O = tw_off<N>(P);
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int k = (t + b * C::T) & (NS - 1);
-#pragma unroll
-      for (int q = 1; q < R; ++q) tw.w[O + b * (R - 1) + q - 1] = tab[q * k * TWS];
+  int ns = C::rad(0);
+  for (int p = 1; p < C::NP; ++p) {
+    const int r = C::rad(p), nb = (C::E / r) * (r - 1);
+    if (i < nb) {
+      const int b = i / (r - 1), q = i % (r - 1) + 1;
+      const int k = (t + b * C::T) & (ns - 1);
+      return q * k * (1024 / (ns * r));
     }
-    tw_load_pass<N, P + 1, NS * R>(tw, t, tab);
+    i -= nb;
+    ns *= r;
   }
+  return 0;
 }
 
+// Lane-major copies of the register twiddles, stored after the W_1024 table:
+// lane t of size N reads tw_pad<N>() consecutive values (an even count, so the
+// rows are 16-byte aligned) starting at twl_off(N) + t tw_pad<N>().
+template <int N>
+__host__ __device__ constexpr int tw_pad() { return (tw_count<N>() + 1) & ~1; }
+__host__ __device__ constexpr int twl_off(int n) {
+  int o = 1024;
+  if (n > 64) o += FftCfg<64>::T * tw_pad<64>();
+  if (n > 128) o += FftCfg<128>::T * tw_pad<128>();
+  if (n > 256) o += FftCfg<256>::T * tw_pad<256>();
+  if (n > 512) o += FftCfg<512>::T * tw_pad<512>();
+  return o;
+}
+constexpr int kTwTotal = twl_off(1024) + FftCfg<1024>::T * tw_pad<1024>();
+
+// tab: W_1024^m = exp(-2 pi i m / 1024), m in [0, 1024), followed by the
+// lane-major copies (global memory).
 template <int N>
 __device__ __forceinline__ void tw_load(Twiddles<N>& tw, int t, const float2* __restrict__ tab) {
-  tw_load_pass<N, 1, FftCfg<N>::rad(0)>(tw, t, tab);
+  constexpr int TC = tw_count<N>(), TP = tw_pad<N>();
+  const float4* row = reinterpret_cast<const float4*>(tab + twl_off(N) + t * TP);
+#pragma unroll
+  for (int i = 0; i < TP / 2; ++i) {
+    const float4 v = row[i];
+    tw.w[2 * i] = make_float2(v.x, v.y);
+    if (2 * i + 1 < TC) tw.w[2 * i + 1] = make_float2(v.z, v.w);
+  }
 }
 
 // ---------------------------------------------------------------- Stockham pass

@@ -108,20 +108,20 @@ constexpr int kDpart = 6;     // dJ0/de2, dJ1/de2, hxx, hyy, hxy, unused
 
 // Rows per block of the row passes, per window size.  FWD: forward row pass
 // (and adjoint row pass); INV: inverse row pass; TILE: LDS bytes of the uint8
-// source tile of a forward block (0: gather straight from memory); TRW x TMC:
-// tile dwords fetched per thread (rows w + 4j, columns lane + 64c).  FWD2 /
-// INV2 (with TILE2, TRW2) are the alternative row counts swift_autotune can
-// choose; the defaults are FWD / INV.
+// source tile of a forward block (0: gather straight from memory); TRW:
+// 16-byte tile loads per thread (each wave load covers 64 / tile_cw<N> tile
+// rows).  FWD2 / INV2 (with TILE2, TRW2) are the alternative row counts
+// swift_autotune can choose; the defaults are FWD / INV.
 template <int N> struct RowsCfg;
-template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 10, TMC = 1,
-                                   FWD2 = 32, INV2 = 32, TILE2 = 4096, TRW2 = 10; };
-template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 6,  TMC = 1,
-                                   FWD2 = 32, INV2 = 64, TILE2 = 6720, TRW2 = 11; };
-template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 7,  TMC = 2,
-                                   FWD2 = 8,  INV2 = 32, TILE2 = 5632, TRW2 = 5; };
-template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,  TMC = 3,
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 2,
+                                   FWD2 = 32, INV2 = 32, TILE2 = 4096, TRW2 = 2; };
+template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 2,
+                                   FWD2 = 32, INV2 = 64, TILE2 = 6720, TRW2 = 3; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 4,
+                                   FWD2 = 8,  INV2 = 32, TILE2 = 5632, TRW2 = 3; };
+template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 8576, TRW2 = 4; };
-template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,  TMC = 1,
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 0,    TRW2 = 1; };
 
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};

@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   constexpr int XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
-  __shared__ uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
+  __shared__ __align__(16) uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
   __shared__ RowParam rparam[2][R];
   __shared__ float trow[R];
   __shared__ double red[4][6];
@@ -226,16 +226,15 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET, TRW, RowsCfg<N>::TMC>(ra[m], im[m], y0);
+    tg[m] = tile_geom<N, R, BUDGET, TRW>(ra[m], im[m], y0);
     // could any sample read outside the image?  (one pixel of slack for rounding)
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
   }
   // all tile loads of both images in flight before anything waits on them
-  constexpr int TMC = RowsCfg<N>::TMC;
-  uint32_t bufA[TRW][TMC], bufB[TRW][TMC];
-  if (tg[0].use) tile_fetch(bufA, tg[0], im[0], tid);
-  if (tg[1].use) tile_fetch(bufB, tg[1], im[1], tid);
+  uint4 bufA[TRW], bufB[TRW];
+  if (tg[0].use) tile_fetch<tile_cw<N>()>(bufA, tg[0], im[0], tid);
+  if (tg[1].use) tile_fetch<tile_cw<N>()>(bufB, tg[1], im[1], tid);
   // per-row parameters (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
   if (tid < 2 * R) {
     // image chosen by value selects (an index into the per-image arrays would
@@ -279,7 +278,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
 
   __syncthreads();  // row parameters visible
   if (tg[0].use) {
-    tile_store(tile, bufA, tg[0], im[0], border[0], tid);
+    tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
       gather_rows_trans<N, R, false>(stage, tile, tg[0], rparam[0], trow, im[0], border[0], tid, tx, s[0], s[1], s[2],
@@ -293,7 +292,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
   if (tg[1].use) {
     __syncthreads();  // tile of A fully consumed
-    tile_store(tile, bufB, tg[1], im[1], border[1], tid);
+    tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
       gather_rows_trans<N, R, true>(stage, tile, tg[1], rparam[1], trow, im[1], border[1], tid, tx, s[3], s[4], s[5],
@@ -344,11 +343,28 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
 
   // transposed store: Z[pair][kx][y0 + r]
-  float2* Zp = a.Z + (size_t)pair * N * N;
+  if constexpr (256 % (16 * R) == 0) {
+    // thread: row r = tid % R, columns kx0 + j KS.  KS is a multiple of 16, so
+    // the LDS index advances by the constant lidx(KS) and every read takes an
+    // immediate offset; the global address is the pair's base (uniform) plus
+    // a 32-bit byte offset.
+    constexpr int KS = 256 / R;
+    const int r = tid % R, kx0 = tid / R;
+    const float2* sp = stage + r * RS + lidx(kx0);
+    char* zb = reinterpret_cast<char*>(a.Z + (size_t)pair * N * N);
+    uint32_t off = (uint32_t)(kx0 * N + y0 + r) * (uint32_t)sizeof(float2);
+#pragma unroll
+    for (int j = 0; j < N / KS; ++j) {
+      *reinterpret_cast<float2*>(zb + off) = sp[j * lidx(KS)];
+      off += (uint32_t)(KS * N * sizeof(float2));
+    }
+  } else {
+    float2* Zp = a.Z + (size_t)pair * N * N;
 #pragma unroll 4
-  for (int idx = tid; idx < R * N; idx += 256) {
-    const int r = idx % R, kx = idx / R;
-    Zp[(size_t)kx * N + y0 + r] = stage[r * RS + lidx(kx)];
+    for (int idx = tid; idx < R * N; idx += 256) {
+      const int r = idx % R, kx = idx / R;
+      Zp[(size_t)kx * N + y0 + r] = stage[r * RS + lidx(kx)];
+    }
   }
 }
 

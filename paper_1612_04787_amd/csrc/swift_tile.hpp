@@ -9,11 +9,24 @@ namespace swift {
 
 // Source footprint of one image for the workgroup's R window rows, staged in
 // LDS as uint8 rows of wt4 dwords: tile(ty, tx) = img[clamp(ylo + ty)][clamp(xlo + tx)].
+// Rows are read in 16-byte chunks: a load instruction of a wave covers
+// 64 / CW tile rows of CW chunks each (CW = tile_cw<N>, a power of two).
 struct TileGeom {
-  int xlo, ylo;   // tile origin in image pixels (xlo a multiple of 4)
-  int wt4, ht;    // dwords per tile row, tile rows
-  bool use;       // the footprint fits the budget and the image allows dword loads
+  int xlo, ylo;   // tile origin in image pixels (xlo a multiple of 16)
+  int wt4, ht;    // dwords per tile row (a multiple of 4), tile rows
+  bool use;       // the footprint fits the budget and the image allows 16-byte loads
 };
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Chunks per tile row that one load covers: a power of two >= N/16 + 2 (the
+// chunks of a translation window's rows), at most 64.
+template <int N>
+__host__ __device__ constexpr int tile_cw() {
+  int c = 1;
+  while (c < N / 16 + 2 && c < 64) c *= 2;
+  return c;
+}
 
 // Per image and workgroup: affine of the window rows [y0, y0 + R).
 struct RowAffine {
@@ -35,9 +48,7 @@ __device__ __forceinline__ RowAffine row_affine(const float* th) {
   return r;
 }
 
-__device__ __forceinline__ int floor_to4(int v) { return v - (((v % 4) + 4) % 4); }
-
-template <int N, int R, int BUDGET, int TRW, int TMC>
+template <int N, int R, int BUDGET, int TRW>
 __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_image& im, int y0) {
   TileGeom g;
   const double ulo = -N / 2, uhi = N / 2 - 1;
@@ -50,67 +61,65 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.use = false;
   g.xlo = g.ylo = 0;
   g.wt4 = g.ht = 0;
-  if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || (im.pitch & 3) || (im.width & 3) ||
-      (((uintptr_t)im.data) & 3))
+  // every 16-byte chunk is either inside the image or wholly outside it
+  if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || im.width < 16 || (im.width & 15) || (im.pitch & 15) ||
+      (((uintptr_t)im.data) & 15))
     return g;
   // one pixel of margin on both sides absorbs FP32 rounding of the per-pixel coordinates
   const int xl = (int)floor(xmin) - 1, xh = (int)floor(xmax) + 2;
   const int yl = (int)floor(ymin) - 1, yh = (int)floor(ymax) + 2;
-  g.xlo = floor_to4(xl);
+  g.xlo = xl - (((xl % 16) + 16) % 16);
   g.ylo = yl;
-  g.wt4 = (xh - g.xlo + 4) / 4;
+  const int w16 = (xh - g.xlo + 16) / 16;
+  g.wt4 = 4 * w16;
   g.ht = yh - yl + 1;
-  g.use = (long long)g.wt4 * 4 * g.ht <= BUDGET && g.ht <= 4 * TRW && g.wt4 <= 64 * TMC;
+  constexpr int CW = tile_cw<N>();
+  g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
   return g;
 }
 
-// Tile dwords are fetched in two steps so all loads are in flight at once:
+// Tiles are fetched in two steps so all loads are in flight at once:
 // tile_fetch issues every global load of a thread into registers and nothing
-// consumes them until tile_store writes them to LDS.  Wave w fetches tile rows
-// w + 4 j, lane l dword columns l + 64 c.  Loads are unconditional (coordinates
-// clamped into the image, so every load is in bounds; a branch between a load
-// and its use would make the compiler drain the load queue); only in-range
-// elements are stored.  Border dwords are read at the nearest in-image
-// aligned dword and, on workgroups whose tile crosses the image border, their
-// bytes re-selected with v_perm so that byte i holds img[y][clamp(x + i)].
-template <int RW, int MC>
-__device__ __forceinline__ void tile_fetch(uint32_t (&buf)[RW][MC], const TileGeom& g, const swift_image& im,
-                                           int tid) {
+// consumes them until tile_store writes them to LDS.  Lane l of wave w takes
+// chunk c = l % CW of tile row (4 j + w) (64 / CW) + l / CW in load j (rows
+// past the tile repeat its last row, which the cache serves).  Loads are
+// unconditional and in bounds: rows are clamped into the image and a chunk
+// left or right of the image is read at the nearest in-image chunk; on
+// workgroups whose tile crosses the border, tile_store replaces such a chunk
+// by its edge byte repeated, so byte i holds img[clamp(y)][clamp(x + i)].
+template <int CW, int RW>
+__device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, const swift_image& im, int tid) {
+  constexpr int RPL = 64 / CW;  // tile rows per load of a wave
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  const int wv = tid >> 6, ln = tid & 63;
-  int xc[MC];
-#pragma unroll
-  for (int c = 0; c < MC; ++c) xc[c] = min(max(g.xlo + 4 * (ln + 64 * c), 0), im.width - 4);
+  const int wv = tid >> 6, ln = tid & 63, c = ln % CW, sr = ln / CW;
+  const uint32_t xc = (uint32_t)min(max(g.xlo + 16 * c, 0), im.width - 16);
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int yy = min(max(g.ylo + wv + 4 * j, 0), im.height - 1);
+    const int ty = (4 * j + wv) * RPL + sr;
+    const int yy = min(max(g.ylo + min(ty, g.ht - 1), 0), im.height - 1);
     const gptr<unsigned char> row = base + (int64_t)yy * im.pitch;
-#pragma unroll
-    for (int c = 0; c < MC; ++c) buf[j][c] = *(gptr<uint32_t>)(row + xc[c]);
+    const u32x4 v = *(gptr<u32x4>)(row + xc);
+    buf[j] = make_uint4(v.x, v.y, v.z, v.w);
   }
 }
 
-template <int RW, int MC>
-__device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint32_t (&buf)[RW][MC],
-                                           const TileGeom& g, const swift_image& im, bool border, int tid) {
-  const int wv = tid >> 6, ln = tid & 63;
-  uint32_t sel[MC];
-#pragma unroll
-  for (int c = 0; c < MC; ++c) {
-    const int xx = g.xlo + 4 * (ln + 64 * c);
-    const int xc = min(max(xx, 0), im.width - 4);
-    sel[c] = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) sel[c] |= (uint32_t)(min(max(xx + b, 0), im.width - 1) - xc) << (8 * b);
-  }
+template <int CW, int RW>
+__device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint4 (&buf)[RW], const TileGeom& g,
+                                           const swift_image& im, bool border, int tid) {
+  constexpr int RPL = 64 / CW;
+  const int wv = tid >> 6, ln = tid & 63, c = ln % CW, sr = ln / CW;
+  const int x = g.xlo + 16 * c;
+  const bool left = border && x < 0, right = border && x >= im.width;
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int ty = wv + 4 * j;
-#pragma unroll
-    for (int c = 0; c < MC; ++c) {
-      const int tx4 = ln + 64 * c;
-      if (ty < g.ht && tx4 < g.wt4)
-        tile[ty * g.wt4 + tx4] = border ? __builtin_amdgcn_perm(buf[j][c], buf[j][c], sel[c]) : buf[j][c];
+    const int ty = (4 * j + wv) * RPL + sr;
+    if (ty < g.ht && 4 * c < g.wt4) {
+      uint4 v = buf[j];
+      if (left | right) {
+        const uint32_t sp = (left ? (v.x & 255u) : (v.w >> 24)) * 0x01010101u;
+        v = make_uint4(sp, sp, sp, sp);
+      }
+      *reinterpret_cast<uint4*>(tile + ty * g.wt4 + 4 * c) = v;
     }
   }
 }
