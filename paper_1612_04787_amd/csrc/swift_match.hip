@@ -77,31 +77,42 @@ __global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict_
 }
 
 // ---------------------------------------------------------------- row pass (forward)
-// Gathers one image of the workgroup's R rows into the stage (real or
-// imaginary parts): a' T with a' = sample - offset, T = t(x) t(y), and adds
-// the three slice sums.  Iteration i covers RPI rows (row i*RPI + tid/N for
-// N < 256, row i otherwise); a thread touches the XV columns tid%N + 256 c.
+// Window samples of the forward row pass.  A thread covers ITER consecutive
+// rows r0 + i of the slice (r0 = (tid / N) ITER) and XV columns: tid % N for
+// N <= 256, the XV adjacent columns XV tid + c otherwise, so that one aligned
+// tile read serves the bilinear pairs of several columns.
+template <int N, int R>
+struct FwdMap {
+  static constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+  __device__ static int col(int tid, int c) { return XV > 1 ? XV * tid + c : tid % N; }
+  __device__ static int row0(int tid) { return RPI > 1 ? (tid / N) * ITER : 0; }
+};
+
+// Gathers one image of the thread's samples into the stage (real parts for
+// A, imaginary parts for B): a' T with a' = sample - offset and T = t(x) t(y),
+// formed as (a t(x) - offset t(x)) t(y).  Adds the slice sums s1 = sum a'T,
+// s2 = sum (a'T)^2 and, per column, s3c[c] = sum_r (a'T) t(y), so that
+// sum (a'T) T = sum_c t(x_c) s3c[c].
 template <int N, int R, bool IM, bool TILE>
-__device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const uint32_t* __restrict__ tile,
-                                            const TileGeom& g, const RowParam* __restrict__ rp,
-                                            const float* __restrict__ trow, const float (&ku)[2][GatherCfg<N>::XV],
-                                            const swift_image& im, bool border, int tid,
-                                            const float (&tx)[GatherCfg<N>::XV], float& s1, float& s2, float& s3,
-                                            bool& cl) {
-  constexpr int RS = fwd_stride<N, R>();
-  constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+__device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const uint32_t* __restrict__ tile, const TileGeom& g,
+                                            const RowParam* __restrict__ rp, const float* __restrict__ trow,
+                                            const float (&ku)[2][GatherCfg<N>::XV], const swift_image& im,
+                                            bool border, const float (&tx)[GatherCfg<N>::XV],
+                                            const float (&ntx)[GatherCfg<N>::XV], int tid, float& s1, float& s2,
+                                            float (&s3c)[GatherCfg<N>::XV], bool& cl) {
+  using M = FwdMap<N, R>;
+  constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  const int xt = tid % N;
+  const int r0 = M::row0(tid);
   float* st = (float*)stage + (IM ? 1 : 0);
 #pragma unroll 2
   for (int i = 0; i < ITER; ++i) {
-    const int r = i * RPI + (RPI > 1 ? tid / N : 0);
+    const int r = r0 + i;
     const RowParam p = rp[r];
     const float ty = trow[r];
 #pragma unroll
     for (int c = 0; c < XV; ++c) {
-      const int x = xt + 256 * c;
       const float xr = p.fx + ku[0][c], yr = p.fy + ku[1][c];
       const float xf = floorf(xr), yf = floorf(yr);
       const float fx = xr - xf, fy = yr - yf;
@@ -120,77 +131,95 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
         cl |= (x0 < 0) | (x0 > im.width - 2) | (y0 < 0) | (y0 > im.height - 2);
         const int cx0 = min(max(x0, 0), im.width - 1), cx1 = min(max(x0 + 1, 0), im.width - 1);
         const int cy0 = min(max(y0, 0), im.height - 1), cy1 = min(max(y0 + 1, 0), im.height - 1);
-        const gptr<unsigned char> r0 = base + (int64_t)cy0 * im.pitch;
-        const gptr<unsigned char> r1 = base + (int64_t)cy1 * im.pitch;
+        const gptr<unsigned char> r0p = base + (int64_t)cy0 * im.pitch;
+        const gptr<unsigned char> r1p = base + (int64_t)cy1 * im.pitch;
         if (im.dtype == SWIFT_U8) {
-          i00 = (float)r0[cx0];
-          i10 = (float)r0[cx1];
-          i01 = (float)r1[cx0];
-          i11 = (float)r1[cx1];
+          i00 = (float)r0p[cx0];
+          i10 = (float)r0p[cx1];
+          i01 = (float)r1p[cx0];
+          i11 = (float)r1p[cx1];
         } else {
-          i00 = ((gptr<float>)r0)[cx0];
-          i10 = ((gptr<float>)r0)[cx1];
-          i01 = ((gptr<float>)r1)[cx0];
-          i11 = ((gptr<float>)r1)[cx1];
+          i00 = ((gptr<float>)r0p)[cx0];
+          i10 = ((gptr<float>)r0p)[cx1];
+          i01 = ((gptr<float>)r1p)[cx0];
+          i11 = ((gptr<float>)r1p)[cx1];
         }
       }
       // (1-fy)((1-fx) i00 + fx i10) + fy((1-fx) i01 + fx i11), in lerp form
       const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
       const float val = fmaf(fy, bot - top, top);
-      const float tap = tx[c] * ty;
-      const float at = (val - kSampleOffset) * tap;
+      const float at = fmaf(val, tx[c], ntx[c]) * ty;
       s1 += at;
       s2 = fmaf(at, at, s2);
-      s3 = fmaf(at, tap, s3);
-      st[2 * (r * RS + lidx(x))] = at;
+      s3c[c] = fmaf(at, ty, s3c[c]);
+      st[2 * (r * RS + lidx(M::col(tid, c)))] = at;
     }
   }
 }
 
 // Gather of a translation window (identity linear part): every sample of the
 // window has the same bilinear weights (fx, fy), so a thread walks down its
-// column and reuses the horizontal interpolation of each tile row for the
-// next output row.  Thread (column x = tid % N + 256 c) covers ITER
-// consecutive rows starting at (tid / N) * ITER.  Same sums and stage layout
-// as gather_rows.
+// columns and reuses the horizontal interpolation of each tile row for the
+// next output row.  One aligned read of a tile row gives the bytes of two
+// adjacent columns.  Same outputs and sums as gather_rows.
 template <int N, int R, bool IM>
-__device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, const uint32_t* __restrict__ tile,
-                                                  const TileGeom& g, const RowParam* __restrict__ rp,
-                                                  const float* __restrict__ trow, const swift_image& im,
-                                                  bool border, int tid, const float (&tx)[GatherCfg<N>::XV],
-                                                  float& s1, float& s2, float& s3, bool& cl) {
-  constexpr int RS = fwd_stride<N, R>();
-  constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
+__device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, const uint32_t* __restrict__ tile, const TileGeom& g,
+                                                  const RowParam* __restrict__ rp, const float* __restrict__ trow,
+                                                  const swift_image& im, bool border,
+                                                  const float (&tx)[GatherCfg<N>::XV],
+                                                  const float (&ntx)[GatherCfg<N>::XV], int tid, float& s1,
+                                                  float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
+  using M = FwdMap<N, R>;
+  constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
-  const int xt = tid % N, r0 = (RPI > 1 ? tid / N : 0) * ITER;
+  const int r0 = M::row0(tid);
+  float* st = (float*)stage + (IM ? 1 : 0);
   const RowParam p0 = rp[r0];
   const float fx = p0.fx, fy = p0.fy;  // the same for every row of the window
-  float* st = (float*)stage + (IM ? 1 : 0);
+  // first column's byte in the tile row; the thread reads bytes ix .. ix + XV
+  const int xs = p0.bx + (M::col(tid, 0) - N / 2);
+  const int ix = min(max(xs, 0), rowb - 1 - XV);
+  // samples span columns xs .. xs + XV and rows p0.by .. p0.by + ITER (tile
+  // coordinates), so one range test gives the clamp flag of all of them
+  if (border)
+    cl |= (xs + g.xlo < 0) | (xs + XV - 1 + g.xlo > im.width - 2) | (p0.by + g.ylo < 0) |
+          (p0.by + ITER - 1 + g.ylo > im.height - 2);
+  // rows start on dword boundaries (rowb is a multiple of 16): the row part
+  // of the dword index is uniform, the lane part and the byte shift fixed
+  const int ixd = ix >> 2;
+  const uint32_t sh = (uint32_t)(ix & 3);
+  auto hrow = [&](int yy, float (&h)[XV]) {
+    const uint32_t* w = tile + min(max(yy, 0), g.ht - 1) * g.wt4 + ixd;
 #pragma unroll
-  for (int c = 0; c < XV; ++c) {
-    const int x = xt + 256 * c;
-    const int x0 = p0.bx + (x - N / 2);
-    const int ix = min(max(x0, 0), rowb - 2);
-    const float txc = tx[c];
-    auto hrow = [&](int yy) {
-      const uint32_t v = tile_pair(tile, min(max(yy, 0), g.ht - 1) * rowb + ix);
-      const float a0 = (float)(v & 255u), a1 = (float)((v >> 8) & 255u);
-      return fmaf(fx, a1 - a0, a0);
-    };
-    float h0 = hrow(p0.by);
+    for (int c = 0; c < XV; c += 2) {
+      // bytes ix + c .. ix + c + 3
+      const int oc = (int)sh + c;
+      const uint32_t v = __builtin_amdgcn_alignbyte(w[(oc >> 2) + 1], w[oc >> 2], (uint32_t)(oc & 3));
+      const float b0 = (float)(v & 255u), b1 = (float)((v >> 8) & 255u);
+      h[c] = fmaf(fx, b1 - b0, b0);
+      if (c + 1 < XV) {
+        const float b2 = (float)((v >> 16) & 255u);
+        h[c + 1] = fmaf(fx, b2 - b1, b1);
+      }
+    }
+  };
+  float h0[XV];
+  hrow(p0.by, h0);
 #pragma unroll 4
-    for (int i = 0; i < ITER; ++i) {
-      const int r = r0 + i, y0 = p0.by + i;
-      if (border) cl |= (x0 + g.xlo < 0) | (x0 + g.xlo > im.width - 2) | (y0 + g.ylo < 0) | (y0 + g.ylo > im.height - 2);
-      const float h1 = hrow(y0 + 1);
-      const float val = fmaf(fy, h1 - h0, h0);
-      h0 = h1;
-      const float tap = txc * trow[r];
-      const float at = (val - kSampleOffset) * tap;
+  for (int i = 0; i < ITER; ++i) {
+    const int r = r0 + i, y0 = p0.by + i;
+    float h1[XV];
+    hrow(y0 + 1, h1);
+    const float ty = trow[r];
+#pragma unroll
+    for (int c = 0; c < XV; ++c) {
+      const float val = fmaf(fy, h1[c] - h0[c], h0[c]);
+      h0[c] = h1[c];
+      const float at = fmaf(val, tx[c], ntx[c]) * ty;
       s1 += at;
       s2 = fmaf(at, at, s2);
-      s3 = fmaf(at, tap, s3);
-      st[2 * (r * RS + lidx(x))] = at;
+      s3c[c] = fmaf(at, ty, s3c[c]);
+      st[2 * (r * RS + lidx(M::col(tid, c)))] = at;
     }
   }
 }
@@ -258,12 +287,14 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   } else if (tid >= 64 && tid < 64 + R) {
     trow[tid - 64] = a.taper[y0 + tid - 64];
   }
-  float tx[XV], ku[2][2][XV];
+  using M = FwdMap<N, R>;
+  float tx[XV], ntx[XV], ku[2][2][XV];
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
-    const int x = tid % N + 256 * c;
+    const int x = M::col(tid, c);
     const float u = (float)(x - N / 2);
     tx[c] = a.taper[x];
+    ntx[c] = -kSampleOffset * tx[c];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       ku[m][0][c] = ra[m].f11 * u;
@@ -271,6 +302,9 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     }
   }
   float s[6] = {0, 0, 0, 0, 0, 0};
+  float s3c[2][XV];
+#pragma unroll
+  for (int c = 0; c < XV; ++c) s3c[0][c] = s3c[1][c] = 0.0f;
   bool clamped = false;
   // translation windows (identity linear part) take the constant-weight gather
   const bool trans[2] = {ra[0].a11 == 1.0 && ra[0].a12 == 0.0 && ra[0].a21 == 0.0 && ra[0].a22 == 1.0,
@@ -281,28 +315,33 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
-      gather_rows_trans<N, R, false>(stage, tile, tg[0], rparam[0], trow, im[0], border[0], tid, tx, s[0], s[1], s[2],
-                                     clamped);
+      gather_rows_trans<N, R, false>(stage, tile, tg[0], rparam[0], trow, im[0], border[0], tx, ntx, tid, s[0], s[1],
+                                     s3c[0], clamped);
     else
-      gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tid, tx, s[0],
-                                     s[1], s[2], clamped);
+      gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx, ntx, tid, s[0],
+                                     s[1], s3c[0], clamped);
   } else {
-    gather_rows<N, R, false, false>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tid, tx, s[0], s[1],
-                                    s[2], clamped);
+    gather_rows<N, R, false, false>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx, ntx, tid, s[0], s[1],
+                                    s3c[0], clamped);
   }
   if (tg[1].use) {
     __syncthreads();  // tile of A fully consumed
     tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
-      gather_rows_trans<N, R, true>(stage, tile, tg[1], rparam[1], trow, im[1], border[1], tid, tx, s[3], s[4], s[5],
-                                    clamped);
+      gather_rows_trans<N, R, true>(stage, tile, tg[1], rparam[1], trow, im[1], border[1], tx, ntx, tid, s[3], s[4],
+                                    s3c[1], clamped);
     else
-      gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tid, tx, s[3],
-                                    s[4], s[5], clamped);
+      gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx, ntx, tid, s[3],
+                                    s[4], s3c[1], clamped);
   } else {
-    gather_rows<N, R, true, false>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tid, tx, s[3], s[4],
-                                   s[5], clamped);
+    gather_rows<N, R, true, false>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx, ntx, tid, s[3], s[4],
+                                   s3c[1], clamped);
+  }
+#pragma unroll
+  for (int c = 0; c < XV; ++c) {
+    s[2] = fmaf(tx[c], s3c[0][c], s[2]);
+    s[5] = fmaf(tx[c], s3c[1][c], s[5]);
   }
   __syncthreads();
 
@@ -590,18 +629,26 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   const float2* Zp = a.Z + (size_t)pair * N * N;
 
   {
-    constexpr int LD = (NH * R2 + 255) / 256;
+    // thread: row r = tid % R2 of columns c0 + k CPL.  Only the last round
+    // can pass column N/2 (ceil(NH / CPL) rounds); its column is clamped so
+    // every load stays in bounds and all of them are in flight at once.
+    static_assert(256 % R2 == 0, "rows per block divide the block");
+    constexpr int CPL = 256 / R2, LD = (NH + CPL - 1) / CPL;
+    const int r = tid % R2, c0 = tid / R2;
+    const char* zb = reinterpret_cast<const char*>(Zp);
+    const uint32_t off0 = (uint32_t)(c0 * N + y0 + r) * (uint32_t)sizeof(float2);
     float2 buf[LD];
 #pragma unroll
-    for (int k = 0; k < LD; ++k) {
-      const int idx = min(tid + 256 * k, NH * R2 - 1);  // branch-free: keeps all loads in flight
-      buf[k] = Zp[(size_t)(idx / R2) * N + y0 + idx % R2];
+    for (int k = 0; k < LD - 1; ++k)
+      buf[k] = *reinterpret_cast<const float2*>(zb + off0 + (uint32_t)(k * CPL * N * sizeof(float2)));
+    {
+      const int cl = min(c0 + (LD - 1) * CPL, NH - 1);
+      buf[LD - 1] = Zp[(size_t)cl * N + y0 + r];
     }
+    float2* sp = stage + r * RS2 + c0;
 #pragma unroll
-    for (int k = 0; k < LD; ++k) {
-      const int idx = tid + 256 * k;
-      if (idx < NH * R2) stage[(idx % R2) * RS2 + idx / R2] = buf[k];
-    }
+    for (int k = 0; k < LD - 1; ++k) sp[k * CPL] = buf[k];
+    if (c0 + (LD - 1) * CPL < NH) sp[(LD - 1) * CPL] = buf[LD - 1];
   }
   __syncthreads();
 
