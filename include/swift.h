@@ -90,11 +90,17 @@ typedef struct {
  *  taper_frac fraction of the window edge covered by the raised-cosine taper,
  *             both edges together, in [0, 1] (Section III, apodization).
  *  centroid_r half-width of the sub-pixel centroid box; only 1 is supported.
- *  flags      0 or SWIFT_FLAG_CONCURRENT_SIZES: the size groups of a ragged
- *             batch run concurrently on the context's own streams (forked
- *             from and joined back into the call's stream with events, so
- *             the call stays stream-ordered and capturable). */
+ *  flags      an OR of
+ *             SWIFT_FLAG_CONCURRENT_SIZES: the size groups of a ragged batch
+ *               run concurrently on the context's own streams (forked from
+ *               and joined back into the call's stream with events, so the
+ *               call stays stream-ordered and capturable);
+ *             SWIFT_FLAG_JAC_TRANSLATION: swift_centroid_jacobian computes
+ *               only the translation columns (tx, ty) of the Jacobian, the
+ *               ones the Newton refinement step uses, and writes zeros in
+ *               the other four (fewer per-pixel sums); other calls ignore it. */
 #define SWIFT_FLAG_CONCURRENT_SIZES 1
+#define SWIFT_FLAG_JAC_TRANSLATION 2
 typedef struct {
   float p;
   float eps_rel;

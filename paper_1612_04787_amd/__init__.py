@@ -5,6 +5,7 @@ this package is its thin Python binding.
 """
 from .swift import (  # noqa: F401
     FLAG_CONCURRENT_SIZES,
+    FLAG_JAC_TRANSLATION,
     SIZES,
     Swift,
     SwiftError,

@@ -45,7 +45,7 @@ def source_digest() -> str:
 
 
 def short_name(full: str) -> str | None:
-    m = re.search(r"swift::k_bwd_(col|row|fin)<(\d+), true>", full)
+    m = re.search(r"swift::k_bwd_(col|row|fin)<(\d+), true(, (true|false))?>", full)
     if m:  # centroid-Jacobian instance of the adjoint kernels
         return "k_cj_%s<%s>" % (m.group(1), m.group(2))
     m = re.search(r"swift::(k_\w+)<(\d+)", full)

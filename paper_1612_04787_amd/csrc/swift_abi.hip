@@ -248,7 +248,8 @@ int check_params(const swift_params* pr) {
   if (!(pr->taper_frac >= 0.0f && pr->taper_frac <= 1.0f))
     return fail(SWIFT_E_INVAL, "taper_frac must be in [0, 1] (got %g)", pr->taper_frac);
   if (pr->centroid_r != 1) return fail(SWIFT_E_UNSUPPORTED, "centroid_r must be 1 (got %d)", pr->centroid_r);
-  if (pr->flags & ~SWIFT_FLAG_CONCURRENT_SIZES) return fail(SWIFT_E_UNSUPPORTED, "unknown flags %#x", pr->flags);
+  if (pr->flags & ~(SWIFT_FLAG_CONCURRENT_SIZES | SWIFT_FLAG_JAC_TRANSLATION))
+    return fail(SWIFT_E_UNSUPPORTED, "unknown flags %#x", pr->flags);
   return SWIFT_OK;
 }
 
@@ -559,6 +560,7 @@ static int run_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
     b.eps_rel = params->eps_rel;
     b.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     b.npairs = g.count;
+    b.jac_trans = (cj && (params->flags & SWIFT_FLAG_JAC_TRANSLATION)) ? 1 : 0;
     e = launch_backward_group(g.n, b, cj, stream, ctx->kt());
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }

@@ -64,8 +64,6 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   float2* slotA = lds + (2 * c) * SL;
   float2* slotB = lds + (2 * c + 1) * SL;
   float2 v[E], u[E];
-  Twiddles<N> tw;
-  tw_load<N>(tw, t, a.tw);
   if (valid) {
     const float2* src = a.Zf + (size_t)pair * N * N;
 #pragma unroll
@@ -112,11 +110,21 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       }
       if (!(sw > 0.0)) zero_all = true;
       const float2 ex = a.tw[w * (1024 / N)], exc = cconj(ex);
+      const float im_ = 1.0f / (float)(N * N);
 #pragma unroll
       for (int r3 = 0; r3 < 3; ++r3) {
-        rxw[r3] = cadd(cadd(cscale(exc, omx[3 * r3]), make_float2(omx[3 * r3 + 1], 0.f)), cscale(ex, omx[3 * r3 + 2]));
-        ryw[r3] = cadd(cadd(cscale(exc, omy[3 * r3]), make_float2(omy[3 * r3 + 1], 0.f)), cscale(ex, omy[3 * r3 + 2]));
+        rxw[r3] = cscale(cadd(cadd(cscale(exc, omx[3 * r3]), make_float2(omx[3 * r3 + 1], 0.f)),
+                              cscale(ex, omx[3 * r3 + 2])), im_);
+        ryw[r3] = cscale(cadd(cadd(cscale(exc, omy[3 * r3]), make_float2(omy[3 * r3 + 1], 0.f)),
+                              cscale(ex, omy[3 * r3 + 2])), im_);
       }
+      // S(ky) = e_y^-1 rw[0] + rw[1] + e_y rw[2] with e_y = (cy, sy):
+      //       = rw[1] + cy (rw[0] + rw[2]) + sy i (rw[2] - rw[0])
+      const float2 dx2 = csub(rxw[2], rxw[0]), dy2 = csub(ryw[2], ryw[0]);
+      rxw[0] = cadd(rxw[0], rxw[2]);
+      ryw[0] = cadd(ryw[0], ryw[2]);
+      rxw[2] = make_float2(-dx2.y, dx2.x);
+      ryw[2] = make_float2(-dy2.y, dy2.x);
     }
     const float p = a.p, hp2 = -0.5f * p;
     const float inv_m = 1.0f / (float)(N * N);
@@ -147,7 +155,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         hd = 0.0f;
       } else {
         h = (p == 1.0f) ? __builtin_amdgcn_rsqf(d) : __builtin_amdgcn_exp2f(hp2 * __builtin_amdgcn_logf(d));
-        hd = hp2 * h / d;
+        hd = hp2 * h * __builtin_amdgcn_rcpf(d);
       }
       // e^{-2 pi i (ky iy + w ix) / N} from the W_1024 table
       const int m = (ky * rec.iy + w * rec.ix) & (N - 1);
@@ -161,29 +169,34 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         hyy += mw * cc.x * fy * fy;
         hxy += mw * cc.x * fwm * fym;
       }
-      const float2 x2 = cmul(X, X);
+      // G_X = G_C (h + r h') + conj(G_C) X^2 h'
+      const float hr = fmaf(r, hd, h);
+      const float2 x2h = cscale(cmul(X, X), hd);
+      const float2 xh = cscale(X, mw * hd);
       const bool zb = zero_all || (ky == 0 && w == 0);
       float2 gfa, gfb;
       if constexpr (!CJ) {
         float2 gc = cscale(cadd(cscale(ph, alpha), cscale(X, gamma * h)), inv_m);
         if (zb) gc = make_float2(0.0f, 0.0f);
-        // G_X = G_C (h + r h') + conj(G_C) X^2 h'
-        const float2 gx = cadd(cscale(gc, h + r * hd), cscale(cmul(cconj(gc), x2), hd));
-        dj += mw * cmul(cconj(gc), X).x * hd;
+        const float2 gx = cadd(cscale(gc, hr), cmul(cconj(gc), x2h));
+        dj = fmaf(gc.x, xh.x, fmaf(gc.y, xh.y, dj));
         gfa = cmul(cconj(gx), fb);
         gfb = cmul(gx, fa);
       } else {
-        // 3 x 3 sums S = sum omega e_x^dx e_y^dy with e = e^{-2 pi i k/N}; the
-        // x part (rows of the box summed over dx) is the same for the whole column
-        const float2 ey = a.tw[ky * (1024 / N)], eyc = cconj(ey);
-        const float2 sx = cadd(cadd(cmul(eyc, rxw[0]), rxw[1]), cmul(ey, rxw[2]));
-        const float2 sy = cadd(cadd(cmul(eyc, ryw[0]), ryw[1]), cmul(ey, ryw[2]));
-        float2 gcx = cscale(cmul(ph, sx), inv_m), gcy = cscale(cmul(ph, sy), inv_m);
+        // 3 x 3 sums S = sum omega e_x^dx e_y^dy / M with e = e^{-2 pi i k/N};
+        // the x part (rows of the box summed over dx) is the same for the whole
+        // column and is folded into rw so that S = rw[1] + cy rw[0] + sy rw[2]
+        const float2 ey = a.tw[ky * (1024 / N)];
+        const float2 sx = make_float2(fmaf(ey.y, rxw[2].x, fmaf(ey.x, rxw[0].x, rxw[1].x)),
+                                      fmaf(ey.y, rxw[2].y, fmaf(ey.x, rxw[0].y, rxw[1].y)));
+        const float2 sy = make_float2(fmaf(ey.y, ryw[2].x, fmaf(ey.x, ryw[0].x, ryw[1].x)),
+                                      fmaf(ey.y, ryw[2].y, fmaf(ey.x, ryw[0].y, ryw[1].y)));
+        float2 gcx = cmul(ph, sx), gcy = cmul(ph, sy);
         if (zb) gcx = gcy = make_float2(0.0f, 0.0f);
-        const float2 gxx = cadd(cscale(gcx, h + r * hd), cscale(cmul(cconj(gcx), x2), hd));
-        const float2 gxy = cadd(cscale(gcy, h + r * hd), cscale(cmul(cconj(gcy), x2), hd));
-        dj += mw * cmul(cconj(gcx), X).x * hd;
-        dj1 += mw * cmul(cconj(gcy), X).x * hd;
+        const float2 gxx = cadd(cscale(gcx, hr), cmul(cconj(gcx), x2h));
+        const float2 gxy = cadd(cscale(gcy, hr), cmul(cconj(gcy), x2h));
+        dj = fmaf(gcx.x, xh.x, fmaf(gcx.y, xh.y, dj));
+        dj1 = fmaf(gcy.x, xh.x, fmaf(gcy.y, xh.y, dj1));
         gfa = cmul(cconj(gxx), fb);  // real channel: d(dx)
         gfb = cmul(cconj(gxy), fb);  // imaginary channel: d(dy)
       }
@@ -208,6 +221,9 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       }
     }
     wave_lds_sync();
+    // twiddles loaded only now: they are not live during the gradient loop
+    Twiddles<N> tw;
+    tw_load<N>(tw, t, a.tw);
     float2* dst = a.Y + (size_t)pair * N * N;
     fft_wave<N, true>(v, slotA, t, tw);
 #pragma unroll
@@ -252,7 +268,7 @@ struct PixelOffsets {
   float fx[XV], fy[XV];
 };
 
-template <int N, int R, bool TILE, bool TRANS, bool TWO>
+template <int N, int R, bool TILE, bool TRANS, bool TWO, bool TO>
 __device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int RS, const uint32_t* __restrict__ tile,
                                            const TileGeom& g, const RowParam* __restrict__ rp,
                                            const float* __restrict__ trow, const PixelOffsets<GatherCfg<N>::XV>& ku,
@@ -268,6 +284,9 @@ __device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int
     const int x = xt + 256 * c;
     const float u = (float)(x - N / 2);
     uint32_t prev = 0;  // translation windows: the tile byte pair of the previous row's bottom
+    // the column's sums without the factor u (u is the same down the column):
+    // tg ax, tg ay, tap ax, tap ay, tw ax, tw ay, and tg2 ax, tg2 ay
+    float cs[6] = {0, 0, 0, 0, 0, 0}, cs2[2] = {0, 0};
 #pragma unroll 2
     for (int i = 0; i < ITER; ++i) {
       const int r = r0 + i;
@@ -323,32 +342,61 @@ __device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int
       // bilinear partials (floor cell; clamped reads give zero outside)
       const float ax = (1.0f - fy) * (i10 - i00) + fy * (i11 - i01);
       const float ay = (1.0f - fx) * (i01 - i00) + fx * (i11 - i10);
+      // D = (ax u, ax v, ax, ay u, ay v, ay): the v entries here, the u
+      // entries from the column sums after the loop
       const float v = (float)(y0 + r - N / 2);
-      const float D[6] = {ax * u, ax * v, ax, ay * u, ay * v, ay};
       const float tap = tx[c] * trow[r];
       const float wv = (val - kSampleOffset - mean_off) * tap;
       const float2 gw = stage[r * RS + lidx(x)];
       const float g0 = ch1 ? gw.y : gw.x;
       const float tg = tap * g0, tw = tap * wv;
+      const float wt[3] = {tg, tap, tw};
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        acc[j] = fmaf(tg, D[j], acc[j]);
-        acc[6 + j] = fmaf(tap, D[j], acc[6 + j]);
-        acc[12 + j] = fmaf(tw, D[j], acc[12 + j]);
+      for (int q = 0; q < 3; ++q) {
+        cs[2 * q] = fmaf(wt[q], ax, cs[2 * q]);
+        cs[2 * q + 1] = fmaf(wt[q], ay, cs[2 * q + 1]);
+        if constexpr (!TO) {
+          const float wq = wt[q] * v;
+          acc[6 * q + 1] = fmaf(wq, ax, acc[6 * q + 1]);
+          acc[6 * q + 4] = fmaf(wq, ay, acc[6 * q + 4]);
+        }
       }
       acc[18] += tg;
       acc[19] += tw;
       if constexpr (TWO) {
         const float tg2 = tap * gw.y;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc2[j] = fmaf(tg2, D[j], acc2[j]);
+        cs2[0] = fmaf(tg2, ax, cs2[0]);
+        cs2[1] = fmaf(tg2, ay, cs2[1]);
+        if constexpr (!TO) {
+          const float wq = tg2 * v;
+          acc2[1] = fmaf(wq, ax, acc2[1]);
+          acc2[4] = fmaf(wq, ay, acc2[4]);
+        }
         acc2[18] += tg2;
+      }
+    }
+    // translation-only: the u and v entries stay zero
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      acc[6 * q + 2] += cs[2 * q];
+      acc[6 * q + 5] += cs[2 * q + 1];
+      if constexpr (!TO) {
+        acc[6 * q + 0] = fmaf(u, cs[2 * q], acc[6 * q + 0]);
+        acc[6 * q + 3] = fmaf(u, cs[2 * q + 1], acc[6 * q + 3]);
+      }
+    }
+    if constexpr (TWO) {
+      acc2[2] += cs2[0];
+      acc2[5] += cs2[1];
+      if constexpr (!TO) {
+        acc2[0] = fmaf(u, cs2[0], acc2[0]);
+        acc2[3] = fmaf(u, cs2[1], acc2[3]);
       }
     }
   }
 }
 
-template <int N, bool TWO>
+template <int N, bool TWO, bool TO>
 __device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t* tile, const TileGeom& g,
                                           const RowParam* rp, const float* trow,
                                           const PixelOffsets<GatherCfg<N>::XV>& ku,
@@ -358,16 +406,16 @@ __device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t*
   constexpr int R = RowsCfg<N>::FWD;
   if (g.use) {
     if (trans)
-      bwd_pixels<N, R, true, true, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
+      bwd_pixels<N, R, true, true, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
     else
-      bwd_pixels<N, R, true, false, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc,
+      bwd_pixels<N, R, true, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc,
                                          acc2);
   } else {
-    bwd_pixels<N, R, false, false, TWO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
+    bwd_pixels<N, R, false, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
   }
 }
 
-template <int N, bool CJ>
+template <int N, bool CJ, bool TO>
 __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
@@ -447,7 +495,22 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 
   // stage[r][kx] = Y[kx][y0 + r], then the inverse row FFTs of G_w in place
   const float2* Yp = a.Y + (size_t)pair * N * N;
-  {
+  if constexpr (256 % (16 * R) == 0) {
+    // thread: row r = tid % R of columns c0 + k CPL (CPL a multiple of 16, so
+    // the stage index advances by the constant lidx(CPL)); the global address
+    // is the pair's base plus a 32-bit offset
+    constexpr int CPL = 256 / R, LD = N / CPL;
+    const int r = tid % R, c0 = tid / R;
+    const char* yb = reinterpret_cast<const char*>(Yp);
+    const uint32_t off0 = (uint32_t)(c0 * N + y0 + r) * (uint32_t)sizeof(float2);
+    float2 buf[LD];
+#pragma unroll
+    for (int k = 0; k < LD; ++k)
+      buf[k] = *reinterpret_cast<const float2*>(yb + off0 + (uint32_t)(k * CPL * N * sizeof(float2)));
+    float2* sp = stage + r * RS + lidx(c0);
+#pragma unroll
+    for (int k = 0; k < LD; ++k) sp[k * lidx(CPL)] = buf[k];
+  } else {
     constexpr int LD = (N * R + 255) / 256;
     float2 buf[LD];
 #pragma unroll
@@ -486,14 +549,14 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   if (tg[0].use) tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
   __syncthreads();  // G rows and tile A visible
   // image A: channel 0 (and, in CJ mode, channel 1 on the same pixels)
-  bwd_image<N, CJ>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.mA, false, acc0,
-                   acc1);
+  bwd_image<N, CJ, TO>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.mA, false,
+                       acc0, acc1);
   if constexpr (!CJ) {
     __syncthreads();  // tile A consumed
     if (tg[1].use) tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
-    bwd_image<N, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid, ps.mB, true,
-                        acc1, acc1);
+    bwd_image<N, false, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid, ps.mB,
+                               true, acc1, acc1);
   }
   // block reduction to FP64 slice partials
   const int wv = tid >> 6, ln = tid & 63;
@@ -577,7 +640,14 @@ static hipError_t launch_bwd_t(const BwdArgs& a, hipStream_t s, KernelTimer* kt)
   k_bwd_col<N, CJ><<<P * NW, 256, 0, s>>>(a);
   if (kt) kt->end(s);
   if (kt) kt->begin(CJ ? "k_cj_row" : "k_bwd_row", N, s);
-  k_bwd_row<N, CJ><<<P * NSLICE, 256, 0, s>>>(a);
+  if constexpr (CJ) {
+    if (a.jac_trans)
+      k_bwd_row<N, true, true><<<P * NSLICE, 256, 0, s>>>(a);
+    else
+      k_bwd_row<N, true, false><<<P * NSLICE, 256, 0, s>>>(a);
+  } else {
+    k_bwd_row<N, false, false><<<P * NSLICE, 256, 0, s>>>(a);
+  }
   if (kt) kt->end(s);
   if (kt) kt->begin(CJ ? "k_cj_fin" : "k_bwd_fin", N, s);
   k_bwd_fin<N, CJ><<<P, 64, 0, s>>>(a);

@@ -102,6 +102,7 @@ struct BwdArgs {
   int32_t L;
   int32_t npairs;
   int32_t n_imgs;
+  int32_t jac_trans;  // centroid-Jacobian mode: translation columns only
 };
 constexpr int kBwdSums = 20;  // per image: P1[6], P2[6], P3[6], Q, R
 constexpr int kDpart = 6;     // dJ0/de2, dJ1/de2, hxx, hyy, hxy, unused

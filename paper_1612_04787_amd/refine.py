@@ -62,7 +62,11 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
                    max_step=0.5, stop_frac=0.0):
     """Returns (theta_a [P, 8], iterations, list of longest steps).  The
     Jacobian is recomputed every iteration: it changes across a pixel cell
-    (bilinear sampling), and reusing the first one (chord steps) stalls."""
+    (bilinear sampling), and reusing the first one (chord steps) stalls.  Only
+    its translation columns are computed (the Newton step uses no others)."""
+    from .swift import FLAG_JAC_TRANSLATION, make_params
+    jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
+                          params.flags | FLAG_JAC_TRANSLATION)
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
     P = prep["pairs"].n_pairs
     out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=sw.device)
@@ -73,7 +77,7 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
     hist = []
     for it in range(1, max_iter + 1):
         sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved)
-        sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, saved, jac)
+        sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], jparams, saved, jac)
         sw.refine_update(out, th, NEWTON, jac, max_step, step)
         m, stop = _done(step, tol, stop_frac)
         hist.append(m)

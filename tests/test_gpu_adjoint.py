@@ -128,6 +128,30 @@ def test_centroid_jacobian_matches_oracle(ctx, pair_small, n, p):
     assert checked >= 1
 
 
+@pytest.mark.parametrize("n", [64, 256, 512])
+def test_centroid_jacobian_translation_only(ctx, pair_small, n):
+    """SWIFT_FLAG_JAC_TRANSLATION: the translation columns equal those of the
+    full pass (same sums in the same order), the other four are zero; an
+    unknown flag bit is refused."""
+    import paper_1612_04787_amd as sw
+    print("case centroid jacobian translation-only n=%d" % n, flush=True)
+    a, b = pair_small
+    rng = np.random.default_rng(11 * n)
+    k = 3
+    ta, tb = _thetas(rng, k, n, 1200)
+    params = sw.make_params(p=0.65)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(ta), torch.from_numpy(tb), params,
+                          save=True)
+    full = ctx.centroid_jacobian(res, params).cpu().numpy()
+    trans = ctx.centroid_jacobian(res, sw.make_params(p=0.65, flags=sw.FLAG_JAC_TRANSLATION)).cpu().numpy()
+    np.testing.assert_array_equal(trans[:, :, [2, 5]], full[:, :, [2, 5]])
+    assert not trans[:, :, [0, 1, 3, 4]].any()
+    assert np.abs(full[:, :, [2, 5]]).max() > 0
+    with pytest.raises(sw.SwiftError):
+        ctx.centroid_jacobian(res, sw.make_params(p=0.65, flags=4))
+
+
 def test_autograd_function(ctx, pair_small):
     import paper_1612_04787_amd as sw
     print("case autograd", flush=True)
