@@ -329,7 +329,7 @@ def main():
     if args.no_autotune:
         tuned = {n: ([], ctx.plan(n)) for n in sw.SIZES}
     else:
-        tuned = ctx.autotune(sw.SIZES, pairs_per_size=512)
+        tuned = ctx.autotune(sw.SIZES, pairs_per_size=2048)
     log("plan: " + ", ".join("%d: rows %s" % (n, v[1]) for n, v in tuned.items()))
 
     if args.calib_copy:

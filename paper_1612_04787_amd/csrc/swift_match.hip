@@ -547,15 +547,17 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   float2 v[E], u[E];
   {
     const float2* src = Zp + (size_t)w * N;
-    const float2* srm = Zp + (size_t)wm * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
-#pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = srm[t + e * T];
   }
   fft_wave<N, false>(v, slot, t, tw);
   wave_lds_sync();
   if (wm != w) {
+    // the mirror column is loaded only now, so it is not live during the
+    // first transform
+    const float2* srm = Zp + (size_t)wm * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = srm[t + e * T];
     fft_wave<N, false>(u, slot, t, tw);
     wave_lds_sync();
   } else {
