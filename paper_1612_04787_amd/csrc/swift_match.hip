@@ -88,13 +88,29 @@ struct FwdMap {
   __device__ static int row0(int tid) { return RPI > 1 ? (tid / N) * ITER : 0; }
 };
 
+// LDS layout of the forward row pass.  When a thread's rows are the slice's
+// rows (N >= 256) the source tile sits at the end of the stage instead of in
+// an array of its own: stage rows [0, FL) lie below it and are written during
+// the gather, rows [FL, R) overlap it and are held in registers until both
+// images are gathered.  Less LDS per workgroup, more workgroups per CU.
+template <int N, int R, int BUDGET>
+struct FwdStage {
+  static constexpr int RS = fwd_stride<N, R>();
+  static constexpr int BYTES = R * RS * 8;
+  static constexpr bool ALIAS = GatherCfg<N>::RPI == 1 && BUDGET > 0 && BUDGET + 4 + 16 <= BYTES;
+  static constexpr int TOFF = ALIAS ? ((BYTES - BUDGET - 4) & ~15) : 0;  // tile offset, bytes (16-aligned)
+  static constexpr int FL = ALIAS ? TOFF / (RS * 8) : R;                  // first row the tile overlaps
+  static constexpr int NL = R - FL > 0 ? R - FL : 1;                      // late-row registers (at least 1)
+};
+
 // Gathers one image of the thread's samples into the stage (real parts for
 // A, imaginary parts for B): a' T with a' = sample - offset and T = t(x) t(y),
 // formed as (a t(x) - offset t(x)) t(y).  Adds the slice sums s1 = sum a'T,
 // s2 = sum (a'T)^2 and, per column, s3c[c] = sum_r (a'T) t(y), so that
 // sum (a'T) T = sum_c t(x_c) s3c[c].
-template <int N, int R, bool IM, bool TILE>
-__device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const uint32_t* __restrict__ tile, const TileGeom& g,
+template <int N, int R, int FL, int NL, bool IM, bool TILE>
+__device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
+                                            const uint32_t* __restrict__ tile, const TileGeom& g,
                                             const RowParam* __restrict__ rp, const float* __restrict__ trow,
                                             const float (&ku)[2][GatherCfg<N>::XV], const swift_image& im,
                                             bool border, const float (&tx)[GatherCfg<N>::XV],
@@ -106,8 +122,10 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
   const int r0 = M::row0(tid);
   float* st = (float*)stage + (IM ? 1 : 0);
-#pragma unroll 2
-  for (int i = 0; i < ITER; ++i) {
+  // rows i < FL go to the stage, the others (only when rows are compile-time
+  // indices, RPI == 1) to late[i - FL]
+  constexpr int FLI = FL < ITER ? FL : ITER;
+  auto row = [&](int i, auto sink) {
     const int r = r0 + i;
     const RowParam p = rp[r];
     const float ty = trow[r];
@@ -152,9 +170,13 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
       s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
-      st[2 * (r * RS + lidx(M::col(tid, c)))] = at;
+      sink(r, c, at);
     }
-  }
+  };
+#pragma unroll 2
+  for (int i = 0; i < FLI; ++i) row(i, [&](int r, int c, float at) { st[2 * (r * RS + lidx(M::col(tid, c)))] = at; });
+#pragma unroll
+  for (int i = FLI; i < ITER; ++i) row(i, [&](int r, int c, float at) { late[r - FL][c] = at; });
 }
 
 // Gather of a translation window (identity linear part): every sample of the
@@ -162,8 +184,9 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, const ui
 // columns and reuses the horizontal interpolation of each tile row for the
 // next output row.  One aligned read of a tile row gives the bytes of two
 // adjacent columns.  Same outputs and sums as gather_rows.
-template <int N, int R, bool IM>
-__device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, const uint32_t* __restrict__ tile, const TileGeom& g,
+template <int N, int R, int FL, int NL, bool IM>
+__device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
+                                                  const uint32_t* __restrict__ tile, const TileGeom& g,
                                                   const RowParam* __restrict__ rp, const float* __restrict__ trow,
                                                   const swift_image& im, bool border,
                                                   const float (&tx)[GatherCfg<N>::XV],
@@ -205,8 +228,8 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, co
   };
   float h0[XV];
   hrow(p0.by, h0);
-#pragma unroll 4
-  for (int i = 0; i < ITER; ++i) {
+  constexpr int FLI = FL < ITER ? FL : ITER;
+  auto row = [&](int i, auto sink) {
     const int r = r0 + i, y0 = p0.by + i;
     float h1[XV];
     hrow(y0 + 1, h1);
@@ -219,20 +242,27 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, co
       s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
-      st[2 * (r * RS + lidx(M::col(tid, c)))] = at;
+      sink(r, c, at);
     }
-  }
+  };
+#pragma unroll 4
+  for (int i = 0; i < FLI; ++i) row(i, [&](int r, int c, float at) { st[2 * (r * RS + lidx(M::col(tid, c)))] = at; });
+#pragma unroll
+  for (int i = FLI; i < ITER; ++i) row(i, [&](int r, int c, float at) { late[r - FL][c] = at; });
 }
 
 template <int N, int R, int BUDGET, int TRW>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NSLICE = N / R;
-  constexpr int RS = fwd_stride<N, R>();
+  using SL = FwdStage<N, R, BUDGET>;
+  constexpr int RS = SL::RS, FL = SL::FL, NL = SL::NL;
   constexpr int XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
-  __shared__ float2 stage[R * RS];
-  __shared__ __align__(16) uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
+  __shared__ __align__(16) float2 stage[R * RS];
+  // + 1: tile_pair reads the dword after a pair
+  __shared__ __align__(16) uint32_t tile_own[(BUDGET > 0 && !SL::ALIAS) ? BUDGET / 4 + 1 : 1];
+  uint32_t* const tile = SL::ALIAS ? reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(stage) + SL::TOFF) : tile_own;
   __shared__ RowParam rparam[2][R];
   __shared__ float trow[R];
   __shared__ double red[4][6];
@@ -305,43 +335,61 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   float s3c[2][XV];
 #pragma unroll
   for (int c = 0; c < XV; ++c) s3c[0][c] = s3c[1][c] = 0.0f;
+  float lateA[NL][XV], lateB[NL][XV];  // stage rows [FL, R) of each image
   bool clamped = false;
   // translation windows (identity linear part) take the constant-weight gather
   const bool trans[2] = {ra[0].a11 == 1.0 && ra[0].a12 == 0.0 && ra[0].a21 == 0.0 && ra[0].a22 == 1.0,
                          ra[1].a11 == 1.0 && ra[1].a12 == 0.0 && ra[1].a21 == 0.0 && ra[1].a22 == 1.0};
 
   __syncthreads();  // row parameters visible
+  // Tiled images first: their tile sits at the end of the stage (when FL <
+  // R), so an image gathered straight from memory writes all its rows only
+  // after every tile has been consumed.
   if (tg[0].use) {
     tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
-      gather_rows_trans<N, R, false>(stage, tile, tg[0], rparam[0], trow, im[0], border[0], tx, ntx, tid, s[0], s[1],
-                                     s3c[0], clamped);
+      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], rparam[0], trow, im[0], border[0], tx, ntx,
+                                             tid, s[0], s[1], s3c[0], clamped);
     else
-      gather_rows<N, R, false, true>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx, ntx, tid, s[0],
-                                     s[1], s3c[0], clamped);
-  } else {
-    gather_rows<N, R, false, false>(stage, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx, ntx, tid, s[0], s[1],
-                                    s3c[0], clamped);
+      gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx,
+                                             ntx, tid, s[0], s[1], s3c[0], clamped);
   }
   if (tg[1].use) {
-    __syncthreads();  // tile of A fully consumed
+    if (tg[0].use) __syncthreads();  // tile of A fully consumed
     tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
-      gather_rows_trans<N, R, true>(stage, tile, tg[1], rparam[1], trow, im[1], border[1], tx, ntx, tid, s[3], s[4],
-                                    s3c[1], clamped);
+      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], rparam[1], trow, im[1], border[1], tx, ntx,
+                                            tid, s[3], s[4], s3c[1], clamped);
     else
-      gather_rows<N, R, true, true>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx, ntx, tid, s[3],
-                                    s[4], s3c[1], clamped);
-  } else {
-    gather_rows<N, R, true, false>(stage, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx, ntx, tid, s[3], s[4],
-                                   s3c[1], clamped);
+      gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx,
+                                            ntx, tid, s[3], s[4], s3c[1], clamped);
   }
+  if (FL < R && (tg[0].use || tg[1].use) && !(tg[0].use && tg[1].use)) __syncthreads();  // tile consumed
+  if (!tg[0].use)
+    gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx, ntx,
+                                           tid, s[0], s[1], s3c[0], clamped);
+  if (!tg[1].use)
+    gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx, ntx,
+                                          tid, s[3], s[4], s3c[1], clamped);
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     s[2] = fmaf(tx[c], s3c[0][c], s[2]);
     s[5] = fmaf(tx[c], s3c[1][c], s[5]);
+  }
+  if constexpr (FL < R) {
+    // rows [FL, R) of the tiled images (they overlap the tile)
+    if (tg[0].use && tg[1].use) __syncthreads();  // tile of B fully consumed
+    float* st = reinterpret_cast<float*>(stage);
+#pragma unroll
+    for (int i = 0; i < R - FL; ++i)
+#pragma unroll
+      for (int c = 0; c < XV; ++c) {
+        const int q = 2 * ((FL + i) * RS + lidx(FwdMap<N, R>::col(tid, c)));
+        if (tg[0].use) st[q] = lateA[i][c];
+        if (tg[1].use) st[q + 1] = lateB[i][c];
+      }
   }
   __syncthreads();
 
