@@ -378,10 +378,31 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     if (e != hipSuccess) return hip_fail(e, "fork event");
   }
   char* base = (char*)ws;
-  size_t surf_off = 0;
-  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+  // surfaces are laid out by ascending window size; the groups are launched
+  // longest first (LPT order, work ~ pairs x n^2 log2 n), which matters when
+  // they run as concurrent branches
+  size_t surf_at[SWIFT_NSIZES];
+  int order[SWIFT_NSIZES];
+  {
+    size_t off = 0;
+    for (int i = 0; i < SWIFT_NSIZES; ++i) {
+      surf_at[i] = off;
+      off += (size_t)L.g[i].count * L.g[i].n * L.g[i].n;
+      order[i] = i;
+    }
+    auto work = [&](int i) { return (double)L.g[i].count * L.g[i].n * L.g[i].n * log2((double)L.g[i].n); };
+    for (int i = 1; i < SWIFT_NSIZES; ++i)
+      for (int j = i; j > 0 && work(order[j]) > work(order[j - 1]); --j) {
+        const int t = order[j];
+        order[j] = order[j - 1];
+        order[j - 1] = t;
+      }
+  }
+  for (int oi = 0; oi < SWIFT_NSIZES; ++oi) {
+    const int i = order[oi];
     const GroupLayout& g = L.g[i];
     if (g.count == 0) continue;
+    const size_t surf_off = surf_at[i];
     hipStream_t s = stream;
     if (concurrent) {
       s = ctx->gs[i];
@@ -427,7 +448,6 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, ctx->join_ev[i], 0);
       if (e != hipSuccess) return hip_fail(e, "join");
     }
-    surf_off += (size_t)g.count * g.n * g.n;
   }
   return ok();
 }

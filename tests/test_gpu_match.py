@@ -253,3 +253,39 @@ def test_rotated_windows_tile_and_direct_gather(ctx, section_pair_small, n, rot_
         r = O.match_pair(a.numpy(), b.numpy(), th[i].astype(np.float64), thb[i].astype(np.float64), n,
                          O.Params(p=0.65), return_surface=True)
         compare(gpu_record(res, i), r, n, surf[i], "rot n=%d i=%d" % (n, i))
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_mixed_tile_and_direct_images(ctx, section_pair_small, n):
+    """Pairs whose two images take different gathers: a 16-aligned uint8
+    section (LDS source tile), the same section cut to an odd width and an
+    fp32 copy (both gathered straight from memory).  Covers every order of
+    tiled and direct images within one workgroup."""
+    print("case mixed tile/direct n=%d" % n, flush=True)
+    a, b = section_pair_small
+    b_odd = b[:, :1599].contiguous()
+    a_f32 = a.to(torch.float32)
+    imgs = [a, b, b_odd, a_f32]
+    pairs = [(0, 2), (2, 0), (3, 2), (0, 1), (3, 1)]
+    k = len(pairs)
+    rng = np.random.default_rng(4100 + n)
+    tha = np.zeros((k, 8), np.float32)
+    for i in range(k):
+        tha[i] = [rng.uniform(n / 2 + 8, 1599 - n / 2 - 8), rng.uniform(n / 2 + 8, 1600 - n / 2 - 8), 1, 0,
+                  rng.uniform(-3, 3), 0, 1, rng.uniform(-3, 3)]
+    tha[1, 2:4] = [math.cos(0.004), -math.sin(0.004)]  # a general affine on one side
+    tha[1, 5:7] = [math.sin(0.004), math.cos(0.004)]
+    thb = tha.copy()
+    thb[:, 4] += rng.uniform(-2, 2, k).astype(np.float32)
+    ia = torch.tensor([p[0] for p in pairs], dtype=torch.int32)
+    ib = torch.tensor([p[1] for p in pairs], dtype=torch.int32)
+    res = ctx.match_batch([x.to(dev()) for x in imgs], [n] * k, ia, ib, torch.from_numpy(tha),
+                          torch.from_numpy(thb), _params(0.65), surfaces=True)
+    torch.cuda.synchronize()
+    surf = res["surfaces"].view(k, n, n).cpu().numpy()
+    host = [x.numpy().astype(np.float64) for x in imgs]
+    for i, (pa, pb) in enumerate(pairs):
+        r = O.match_pair(host[pa], host[pb], tha[i].astype(np.float64), thb[i].astype(np.float64), n,
+                         O.Params(p=0.65), return_surface=True)
+        e = compare(gpu_record(res, i), r, n, surf[i], "mixed n=%d i=%d (%d,%d)" % (n, i, pa, pb))
+        print("  ", i, e, flush=True)
