@@ -3,10 +3,14 @@ is repeated, each time from the updated alignment, until the scores settle).
 
 Two drivers over the same library calls:
   refine_plain    match, then move each window A by its centroid shift;
-  refine_adjoint  match + one adjoint pass for the Jacobian J of the centroid
-                  shift d with respect to the translation of window A, then a
-                  Newton step t <- t - J^-1 d on d(t) = 0 (centroid step while
-                  the integer peak is not yet at the origin).
+  refine_adjoint  centroid steps while the batch's longest step is at least
+                  `newton_below` px (far from the solution the centroid step
+                  is cheap and halves the error, and the Jacobian measured
+                  there does not hold at the solution), then match + one
+                  adjoint pass for the Jacobian J of the centroid shift d with
+                  respect to the translation of window A and a Newton step
+                  t <- t - J^-1 d on d(t) = 0 (centroid step while the integer
+                  peak is not yet at the origin).
 The centroid of a bilinearly resampled window underestimates the shift (its
 slope J is well below 1), so the plain iteration contracts the error by only
 |1 - J| per step, while Newton's reaches the 0.01 px level in a few steps.
@@ -59,11 +63,13 @@ def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol
 
 
 def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                   max_step=0.5, stop_frac=0.0):
-    """Returns (theta_a [P, 8], iterations, list of longest steps).  The
-    Jacobian is recomputed every iteration: it changes across a pixel cell
-    (bilinear sampling), and reusing the first one (chord steps) stalls.  Only
-    its translation columns are computed (the Newton step uses no others)."""
+                   max_step=0.5, stop_frac=0.0, newton_below=0.25):
+    """Returns (theta_a [P, 8], iterations, list of longest steps).  Centroid
+    steps until the longest step of the batch is below newton_below px, Newton
+    steps from then on.  The Jacobian is recomputed every Newton iteration: it
+    changes across a pixel cell (bilinear sampling), and reusing an earlier
+    one (chord steps) stalls.  Only its translation columns are computed (the
+    Newton step uses no others)."""
     from .swift import FLAG_JAC_TRANSLATION, make_params
     jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
                           params.flags | FLAG_JAC_TRANSLATION)
@@ -75,12 +81,21 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
     jac = torch.empty((P, 2, 6), dtype=torch.float32, device=sw.device)
     step = torch.empty(P, dtype=torch.float32, device=sw.device)
     hist = []
+    newton = False
     for it in range(1, max_iter + 1):
-        sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved)
-        sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], jparams, saved, jac)
-        sw.refine_update(out, th, NEWTON, jac, max_step, step)
+        if newton:
+            sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved)
+            sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], jparams, saved, jac)
+            sw.refine_update(out, th, NEWTON, jac, max_step, step)
+        else:
+            sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out)
+            sw.refine_update(out, th, CENTROID, None, max_step, step)
         m, stop = _done(step, tol, stop_frac)
         hist.append(m)
-        if stop:
+        if stop and newton:
             return th, it, hist
+        if not newton:
+            # switch when the steps are small; with stop_frac, up to that
+            # fraction of windows may still step further (as in _done)
+            newton = _done(step, newton_below, stop_frac)[1]
     return th, max_iter, hist
