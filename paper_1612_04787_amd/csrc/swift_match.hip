@@ -11,9 +11,11 @@
 //   k_row_fwd   gather (bilinear affine, uint8/fp32 -> fp32), taper, row FFTs,
 //               per-slice sums; writes the row spectra transposed ([kx][y]).
 //   k_pair_stats  reduces the sums to the weighted means and eps^2.
-//   k_col       column FFTs of kx and N-kx, split into F_A and F_B, removes the
+//   k_col_pair  column FFTs of kx and N-kx, split into F_A and F_B, removes the
 //               weighted mean in the spectrum (F -= m * tau(ky) tau(kx)),
-//               whitens the cross power, inverse column FFT; writes in place.
+//               whitens the cross power, inverse column FFT; writes in place
+//               (one FFT group per column pair; k_col, two groups per pair of
+//               columns, at N = 1024).
 //   k_row_inv   inverse row FFTs (two real rows per complex FFT), per-slice
 //               top-2 / argmax and FP64 sum, sum of squares; optional surface.
 //   k_finalize  reduces the slices, recomputes the three rows around the peak
@@ -493,6 +495,10 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
 }
 
 // ---------------------------------------------------------------- column pass + whitening
+// Two FFT groups per column pair (used at N = 1024, where a group is a whole
+// wavefront of 16 elements per lane): group 0 transforms column kx, group 1
+// its mirror N - kx and hands it over through LDS behind a workgroup barrier;
+// group 0 then splits, whitens and inverse-transforms column kx.
 template <int N>
 __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
   using C = FftCfg<N>;
