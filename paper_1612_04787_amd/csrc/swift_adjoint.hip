@@ -562,10 +562,13 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   const int wv = tid >> 6, ln = tid & 63;
 #pragma unroll
   for (int j = 0; j < kBwdSums; ++j) {
-    const float sa = wave_sum_f32(acc0[j]);
+    // translation only: the tx / ty entries of P1, P2, P3 (j % 6 = 2, 5), Q
+    // and R; the others are zero and are not reduced
+    const bool used = !TO || j >= 18 || j % 6 == 2 || j % 6 == 5;
+    const float sa = used ? wave_sum_f32(acc0[j]) : 0.0f;
     // CJ: channel 1 shares P2, P3 and R with channel 0
     const bool own = !CJ || j < 6 || j == 18;
-    const float sb = own ? wave_sum_f32(acc1[j]) : sa;
+    const float sb = own ? (used ? wave_sum_f32(acc1[j]) : 0.0f) : sa;
     if (ln == 0) {
       red[wv][j] = (double)sa;
       red[wv][kBwdSums + j] = (double)sb;
