@@ -118,7 +118,11 @@ def taper_2d(n, taper_frac):
 
 def prepare(a, T):
     """Subtract the taper-weighted mean, then taper: w = (a - m_T) T with
-    m_T = sum(a T) / sum(T).  Returns (w, m_T)."""
+    m_T = sum(a T) / sum(T).  Returns (w, m_T).  For a window whose samples
+    are all equal, m_T is that value and w is exactly zero (the FP64 quotient
+    could miss the constant by an ulp and leave rounding noise in w)."""
+    if a.size and np.all(a == a.flat[0]):
+        return np.zeros_like(a, dtype=np.float64), float(a.flat[0])
     m = float(np.sum(a * T) / np.sum(T))
     return (a - m) * T, m
 

@@ -289,3 +289,38 @@ def test_mixed_tile_and_direct_images(ctx, section_pair_small, n):
                          O.Params(p=0.65), return_surface=True)
         e = compare(gpu_record(res, i), r, n, surf[i], "mixed n=%d i=%d (%d,%d)" % (n, i, pa, pb))
         print("  ", i, e, flush=True)
+
+
+@pytest.mark.parametrize("n", [128, 512])
+@pytest.mark.parametrize("p,eps,taper", [(1.0, 0.0, 0.25), (0.65, 0.0, 0.0), (0.0, 1e-4, 1.0), (0.65, 1e-2, 0.5)])
+def test_parameter_edge_cases(ctx, section_pair_small, n, p, eps, taper):
+    """No whitening floor (eps = 0), no taper (T = 1: the deferred mean falls
+    entirely on the DC term), a taper over the whole window, a large floor;
+    translation and affine windows, one wholly outside the section (every
+    sample clamped to the border)."""
+    print("case params n=%d p=%g eps=%g taper=%g" % (n, p, eps, taper), flush=True)
+    a, b = section_pair_small
+    rng = np.random.default_rng(int(5000 + n + 100 * p + 1e4 * eps + 10 * taper))
+    k = 3
+    tha = _random_thetas(rng, k, n, 1600, 1600)
+    tha[0, 2:4] = [1, 0]
+    tha[0, 5:7] = [0, 1]
+    tha[2, 0:2] = [-n - 40.5, 1600 + n + 17.25]  # outside: all samples clamped
+    thb = tha.copy()
+    thb[:, 4] += rng.uniform(-2, 2, k).astype(np.float32)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(tha), torch.from_numpy(thb),
+                          _params(p, eps=eps, taper=taper), surfaces=True)
+    torch.cuda.synchronize()
+    surf = res["surfaces"].view(k, n, n).cpu().numpy()
+    for i in range(k):
+        r = O.match_pair(a.numpy(), b.numpy(), tha[i].astype(np.float64), thb[i].astype(np.float64), n,
+                         O.Params(p=p, eps_rel=eps, taper_frac=taper), return_surface=True)
+        g = gpu_record(res, i)
+        if r["status"] & O.swift_oracle.STATUS_DEGENERATE:
+            # a constant window: sigma = 0, SNR 0, flagged on both sides
+            assert g["status"] & O.swift_oracle.STATUS_DEGENERATE and g["snr"] == 0.0, (i, g)
+            continue
+        e = compare(g, r, n, surf[i], "params n=%d i=%d" % (n, i))
+        print("  ", i, e, flush=True)
+    assert int(res["status"][2]) & O.swift_oracle.STATUS_CLAMPED

@@ -230,10 +230,18 @@ def test_snr_bound_and_parseval():
         assert abs(rec["std"] - math.sqrt(var)) < 1e-12 * rec["std"]
 
 
-def test_degenerate_constant_window():
-    a = np.full((64, 64), 100.0)
-    _, b = make_pair64()
-    rec = O.match_pair(a, b, ident(32, 32), ident(32, 32), 64, O.Params(p=0.65))
+@pytest.mark.parametrize("value", [100.0, 37.0, 211.5])
+@pytest.mark.parametrize("taper", [0.25, 0.0, 1.0])
+@pytest.mark.parametrize("n", [64, 256])
+def test_degenerate_constant_window(value, taper, n):
+    """A constant window is exactly zero after the taper-weighted mean removal
+    (w = (a - m_T) T with m_T = a), so its surface is zero, sigma = 0 and the
+    match is degenerate, whatever the taper and the constant."""
+    a = np.full((n, n), value)
+    b = np.random.default_rng(3).normal(128.0, 30.0, (n, n))
+    w, m = O.prepare(a, O.taper_2d(n, taper))
+    assert m == value and not w.any()
+    rec = O.match_pair(a, b, ident(n / 2, n / 2), ident(n / 2, n / 2), n, O.Params(p=0.65, taper_frac=taper))
     assert rec["snr"] == 0.0 and rec["status"] & STATUS_DEGENERATE
 
 
