@@ -110,3 +110,55 @@ def test_section_pair_256_windows_1024(ctx):
         r = O.match_pair(ca, cb, th, th, n, O.Params(p=0.65))
         e = compare(gpu_record(res, int(i)), r, n, tag="1024 pair %d" % i)
         print("   pair %d:" % i, e, flush=True)
+
+
+def test_headline_jacobian_4096_pairs_512(ctx):
+    """The centroid Jacobian in the configuration the refinement benchmark
+    times: 4096 windows of 512^2 on the 64-section stack, window B at a
+    fractional translation t*, window A U(-0.5, 0.5)^2 px away, translation
+    columns only (SWIFT_FLAG_JAC_TRANSLATION).  Sampled pairs against the FP64
+    oracle; every pair finite with zeros outside the translation columns."""
+    import paper_1612_04787_amd as sw
+    from datagen.workloads import distorted_stack, section_grid_pairs
+    S, size, n = 64, 4096, 512
+    print("case headline jacobian generate", flush=True)
+    stack, _ = distorted_stack(S, size, seed=5, device=dev())
+    _, _, _, _, _, cen = section_grid_pairs(S, size, n, 8, dev())
+    rng = np.random.default_rng(9)
+    P = S * len(cen)
+    tb = np.zeros((P, 8), np.float32)
+    k = 0
+    for s in range(S):
+        for (cx, cy) in cen:
+            tb[k] = [cx, cy, 1, 0, rng.uniform(-0.5, 0.5), 0, 1, rng.uniform(-0.5, 0.5)]
+            k += 1
+    ta = tb.copy()
+    ta[:, 4] += rng.uniform(-0.5, 0.5, P).astype(np.float32)
+    ta[:, 7] += rng.uniform(-0.5, 0.5, P).astype(np.float32)
+    idx = torch.arange(S, dtype=torch.int32).repeat_interleave(len(cen))
+    params = sw.make_params(p=0.65)
+    print("case headline jacobian P=%d" % P, flush=True)
+    res = ctx.match_batch([stack[s] for s in range(S)], [n] * P, idx, idx, torch.from_numpy(ta),
+                          torch.from_numpy(tb), params, save=True)
+    jac = ctx.centroid_jacobian(res, sw.make_params(p=0.65, flags=sw.FLAG_JAC_TRANSLATION))
+    torch.cuda.synchronize()
+    jac = jac.cpu().numpy()
+    assert np.isfinite(jac).all()
+    assert not jac[:, :, [0, 1, 3, 4]].any()
+    for i in rng.choice(P, 3, replace=False):
+        s = int(i) // len(cen)
+        cx, cy = float(tb[i, 0]), float(tb[i, 1])
+        x0, y0, x1, y1 = _crop(cx, cy, n, size, size, m=6)
+        img = stack[s, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+        tha, thb = ta[i].astype(np.float64), tb[i].astype(np.float64)
+        tha[0] -= x0
+        tha[1] -= y0
+        thb[0] -= x0
+        thb[1] -= y0
+        rec, ref = O.centroid_jacobian(img, img, tha, thb, n, O.Params(p=0.65))
+        assert (int(res["ix"][i]), int(res["iy"][i])) == (rec["ix"], rec["iy"])
+        for row in range(2):
+            g, r = jac[i, row, [2, 5]].astype(np.float64), ref[row][[2, 5]]
+            err = np.linalg.norm(g - r) / np.linalg.norm(r)
+            print("   pair %d d%s/dt rel err %.2e" % (i, "xy"[row], err), flush=True)
+            assert err <= 1e-3, (i, row, g, r)
