@@ -223,8 +223,12 @@ int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch,
  * peak and the set of positive centroid weights (3x3 box, weight = c - mean)
  * held fixed.  One adjoint pass: the two objectives share one packed inverse
  * 2-D FFT.  A pair whose record is degenerate, or whose box has no positive
- * weight, gets zeros.  Inputs, params and `saved` as for swift_match_backward;
- * jac is device memory.  Errors as for swift_match_backward. */
+ * weight, gets zeros.  With SWIFT_FLAG_JAC_TRANSLATION in params->flags only
+ * the tx and ty columns (jac[.][.][2], jac[.][.][5], the ones the Newton step
+ * reads) are computed and the other four are written as zeros; the computed
+ * columns equal those of the full pass.  Inputs, params and `saved` as for
+ * swift_match_backward; jac is device memory.  Errors as for
+ * swift_match_backward. */
 int swift_centroid_jacobian(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
                             const swift_pairs* pairs, const swift_params* params,
                             const void* saved, float* jac, void* ws, size_t ws_bytes,
