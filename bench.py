@@ -59,6 +59,21 @@ def pair_bytes(n: int) -> float:
     return 2.0 * n * n + 64 + 48.0 * n * (n // 2 + 1)
 
 
+FP32_PEAK_TFLOPS = 157.3
+
+
+def path_roofline(pairs_per_s: float, n: int) -> dict:
+    """Achieved pairs/s against min(HBM bound, ALU bound) of the per-pair
+    model, and against the input-only bound (2 N^2 + 64 bytes per pair, or the
+    ALU bound if that is lower)."""
+    hbm = HBM_PEAK_GBS * 1e9 / pair_bytes(n)
+    alu = FP32_PEAK_TFLOPS * 1e12 / pair_flops(n)
+    inp = min(HBM_PEAK_GBS * 1e9 / (2.0 * n * n + 64), alu)
+    bound = min(hbm, alu)
+    return dict(bound="hbm" if hbm <= alu else "alu", bound_pairs_per_s=bound, frac=pairs_per_s / bound,
+                input_only_bound_pairs_per_s=inp, input_only_frac=pairs_per_s / inp)
+
+
 def pair_flops(n: int) -> float:
     import math
     return 7.5 * n * n * math.log2(n * n) + 40.0 * n * n
@@ -409,6 +424,10 @@ def main():
         "hbm_gbs": step_bytes / (ms / 1e3) / 1e9,
         "alu_tflops": P * pair_flops(N) / (ms / 1e3) / 1e12,
         "roofline": roof,
+        # whole path against its traffic / flop model (uint8 inputs, the
+        # record and one write + read of each exchanged spectrum per pair):
+        # the binding bound, and the stricter bound of the inputs alone
+        "path_roofline": path_roofline(value, N),
         "kernels": kernels,
         "plan": {str(n): {"fwd_rows": v[1][0], "inv_rows": v[1][1], "variant_ms": v[0]} for n, v in tuned.items()},
         "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
