@@ -32,19 +32,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Wave-wide FP32 sum: DPP within rows of 16 lanes, then two lane swaps.
-template <int CTRL>
+// Wave-wide FP32 sum, all in registers: DPP within rows of 16 lanes (every
+// lane of a row then holds the row's sum), then the row broadcasts of the
+// wave64 DPP controls fold rows 0..2 into row 3; lane 63 holds the total,
+// returned to every lane.
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ float wave_sum_f32(float v) {
-  v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f32<0x124>(v);  // row_ror:4
-  v += dpp_f32<0x128>(v);  // row_ror:8
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+  v += dpp_f32<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f32<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f32<0x124>(v);       // row_ror:4
+  v += dpp_f32<0x128>(v);       // row_ror:8
+  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 struct Top2 {

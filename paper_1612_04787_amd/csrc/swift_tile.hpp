@@ -91,7 +91,9 @@ template <int CW, int RW>
 __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, const swift_image& im, int tid) {
   constexpr int RPL = 64 / CW;  // tile rows per load of a wave
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  const int wv = tid >> 6, ln = tid & 63, c = ln % CW, sr = ln / CW;
+  // the wave index is uniform: with one tile row per load (RPL = 1) the row
+  // address is scalar and a load adds only the lane's 32-bit offset
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63, c = ln % CW, sr = ln / CW;
   const uint32_t xc = (uint32_t)min(max(g.xlo + 16 * c, 0), im.width - 16);
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
@@ -107,7 +109,7 @@ template <int CW, int RW>
 __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint4 (&buf)[RW], const TileGeom& g,
                                            const swift_image& im, bool border, int tid) {
   constexpr int RPL = 64 / CW;
-  const int wv = tid >> 6, ln = tid & 63, c = ln % CW, sr = ln / CW;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63, c = ln % CW, sr = ln / CW;
   const int x = g.xlo + 16 * c;
   const bool left = border && x < 0, right = border && x >= im.width;
 #pragma unroll
