@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the library's kernels.
 
   python -m paper_1612_04787_amd.counters stats  KERNEL_STATS_CSV
-  python -m paper_1612_04787_amd.counters pmc    COUNTER_COLLECTION_CSV
+  python -m paper_1612_04787_amd.counters pmc    COUNTER_COLLECTION_CSV [--largest-grid]
   python -m paper_1612_04787_amd.counters traffic FETCH_CSV WRITE_CSV [--copy-bytes B]
 
 `stats` condenses a `--kernel-trace --stats` run to one line per kernel
@@ -101,8 +101,8 @@ def per_kernel_counters(path, largest_grid=False):
     return acc
 
 
-def pmc(path):
-    acc = per_kernel_counters(path)
+def pmc(path, largest_grid=False):
+    acc = per_kernel_counters(path, largest_grid)
     lines = []
     for name in sorted(acc):
         lines.append(name)
@@ -166,6 +166,7 @@ def main(argv=None):
     a.add_argument("csv")
     a = sub.add_parser("pmc")
     a.add_argument("csv")
+    a.add_argument("--largest-grid", action="store_true", help="only each kernel's largest-grid dispatches")
     a = sub.add_parser("traffic")
     a.add_argument("fetch_csv")
     a.add_argument("write_csv")
@@ -174,7 +175,7 @@ def main(argv=None):
     if args.cmd == "stats":
         print(stats(args.csv))
     elif args.cmd == "pmc":
-        print(pmc(args.csv))
+        print(pmc(args.csv, args.largest_grid))
     else:
         print(traffic(args.fetch_csv, args.write_csv, args.copy_bytes))
 
