@@ -28,4 +28,11 @@ from .swift_oracle import (  # noqa: F401
     refine_step,
     centroid_jacobian,
     surface_hessian,
+    mesh_node_xy,
+    mesh_triangles,
+    mesh_band,
+    mesh_triangle_of,
+    fit_mesh,
+    render_mesh,
+    mesh_windows,
 )

@@ -537,3 +537,129 @@ def fit_section(p, q, w, prev):
         return np.asarray(prev, dtype=np.float64).copy(), STACK_FIT_SINGULAR
     A = fit_affine(p, q, w)
     return np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 0], A[1, 1], A[1, 2]]), 0
+
+
+# ---------------------------------------------------------------------------
+# Local-affine triangle mesh (mir at the finest stages, Section IV; texture
+# mapping of a triangulated mesh, Section III).  Every triangle carries its own
+# affine, the weighted least-squares fit of the swim points in the triangle and
+# in the band of triangles around it; every output pixel is rendered by the
+# affine of the triangle it falls in.
+#
+# Mesh of one section (design reading): the nodes are the swim window centres
+# of a grid x grid layout of the level-l aligned frame, node (i, j) at
+# (sx//2 + i sx, sy//2 + j sy) with sx = w_l // grid, sy = h_l // grid, node
+# index k = j grid + i.  Cell (ci, cj), 0 <= ci, cj < grid - 1, spans nodes
+# ci..ci+1 by cj..cj+1 and is cut along the diagonal from node (ci+1, cj) to
+# node (ci, cj+1).  Triangle 2 c holds nodes (ci, cj), (ci+1, cj), (ci, cj+1);
+# triangle 2 c + 1 holds (ci+1, cj), (ci+1, cj+1), (ci, cj+1); c = cj (grid-1)
+# + ci.  A pixel outside the hull of the nodes belongs to the nearest cell's
+# triangle on its side of that cell's diagonal (the border triangles extend
+# to the frame edges).
+# ---------------------------------------------------------------------------
+MESH_FIT_SINGULAR = 1
+
+
+def mesh_node_xy(grid, h_l, w_l):
+    """Level-l positions of the nodes: [grid^2, 2] int64 (x, y)."""
+    sx, sy = w_l // grid, h_l // grid
+    jj, ii = np.meshgrid(np.arange(grid), np.arange(grid), indexing="ij")
+    return np.stack([sx // 2 + ii.ravel() * sx, sy // 2 + jj.ravel() * sy], 1).astype(np.int64)
+
+
+def mesh_triangles(grid):
+    """Node indices of every triangle, [2 (grid-1)^2, 3]."""
+    tris = []
+    for cj in range(grid - 1):
+        for ci in range(grid - 1):
+            k00 = cj * grid + ci
+            k10, k01, k11 = k00 + 1, k00 + grid, k00 + grid + 1
+            tris.append([k00, k10, k01])
+            tris.append([k10, k11, k01])
+    return np.array(tris, dtype=np.int64)
+
+
+def mesh_band(grid, t):
+    """The swim points that fit triangle t: its three vertices and every node
+    that shares a mesh edge (a side of some triangle) with one of them.  Sorted
+    node indices."""
+    tris = mesh_triangles(grid)
+    verts = set(int(v) for v in tris[t])
+    band = set(verts)
+    for tri in tris:
+        for a in range(3):
+            for b in range(3):
+                if a != b and int(tri[a]) in verts:
+                    band.add(int(tri[b]))
+    return np.array(sorted(band), dtype=np.int64)
+
+
+def mesh_triangle_of(x, y, grid, h_l, w_l):
+    """Triangle index of level-l pixel (x, y) (integer arrays): the cell is
+    (floor((x - x_0) / sx), floor((y - y_0) / sy)) clamped to the cells, and the
+    pixel takes the cell's first triangle when (x - x_c)/sx + (y - y_c)/sy <= 1
+    (x_c, y_c its first node), decided exactly in integers."""
+    sx, sy = w_l // grid, h_l // grid
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    ci = np.clip(np.floor_divide(x - sx // 2, sx), 0, grid - 2)
+    cj = np.clip(np.floor_divide(y - sy // 2, sy), 0, grid - 2)
+    dx = x - (sx // 2 + ci * sx)
+    dy = y - (sy // 2 + cj * sy)
+    second = dx * sy + dy * sx > sx * sy
+    return 2 * (cj * (grid - 1) + ci) + second.astype(np.int64)
+
+
+def fit_mesh(p, q, w, grid, section_aff):
+    """mir's affine of every triangle of one section from its grid^2 node
+    correspondences (node k: model point p[k], raw point q[k], weight w[k], as
+    for fit_section).  A triangle whose band has fewer than three weighted
+    points, or collinear ones, takes the section's affine and status
+    MESH_FIT_SINGULAR.  Returns (tri_aff [2 (grid-1)^2, 6], status [...])."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    T = 2 * (grid - 1) ** 2
+    out = np.zeros((T, 6))
+    st = np.zeros(T, dtype=np.int64)
+    for t in range(T):
+        b = mesh_band(grid, t)
+        out[t], s = fit_section(p[b], q[b], w[b], section_aff)
+        st[t] = MESH_FIT_SINGULAR if s else 0
+    return out, st
+
+
+def render_mesh(img, tri_aff, level, grid, out_h, out_w):
+    """mir texture mapping of one section: out[y][x] is the bilinear value of
+    the level-l image at the raw point of aligned pixel (x, y) under the affine
+    of its triangle (mesh of the out_h x out_w frame), rounded half up to uint8.
+    Same arithmetic as render, per pixel."""
+    yy, xx = np.meshgrid(np.arange(out_h), np.arange(out_w), indexing="ij")
+    t = mesh_triangle_of(xx, yy, grid, out_h, out_w)
+    a = np.asarray(tri_aff, dtype=np.float64)[t]
+    px = level_to_base(xx.astype(np.float64), level)
+    py = level_to_base(yy.astype(np.float64), level)
+    qx = a[..., 0] * px + a[..., 1] * py + a[..., 2]
+    qy = a[..., 3] * px + a[..., 4] * py + a[..., 5]
+    v, _ = bilinear_clamped(img, base_to_level(qx, level), base_to_level(qy, level))
+    return np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8)
+
+
+def mesh_windows(tri_aff, level, n, grid, h_l, w_l):
+    """swim windows of one section through its mesh: window k sits at node k of
+    the level-l aligned frame exactly as in stack_windows, and window A reads
+    the raw section through the affine of the triangle the node's pixel belongs
+    to (mesh_triangle_of).  Returns float64 (theta_a, theta_b) [grid^2, 8]."""
+    nodes = mesh_node_xy(grid, h_l, w_l)
+    t = mesh_triangle_of(nodes[:, 0], nodes[:, 1], grid, h_l, w_l)
+    ta = np.zeros((grid * grid, 8))
+    tb = np.zeros((grid * grid, 8))
+    for k in range(grid * grid):
+        aff = np.asarray(tri_aff[t[k]], dtype=np.float64)
+        px, py = int(nodes[k, 0]), int(nodes[k, 1])
+        qx, qy = apply_affine(aff, level_to_base(px, level), level_to_base(py, level))
+        cx, cy = base_to_level(qx, level), base_to_level(qy, level)
+        rx, ry = np.rint(cx), np.rint(cy)
+        ta[k] = [rx, ry, aff[0], aff[1], cx - rx, aff[3], aff[4], cy - ry]
+        tb[k] = [px, py, 1, 0, 0, 0, 1, 0]
+    return ta, tb

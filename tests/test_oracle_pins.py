@@ -582,3 +582,145 @@ def test_fit_section_exact_and_singular():
     assert st == O.swift_oracle.STACK_FIT_SINGULAR and np.array_equal(aff, prev)
     assert O.match_weight(20.0, 0, 6.0) == 20.0 and O.match_weight(5.0, 0, 6.0) == 0.0
     assert O.match_weight(20.0, O.swift_oracle.STATUS_DEGENERATE, 6.0) == 0.0
+
+
+# --------------------------------------------------------------------------- local-affine mesh
+def _orient(a, b, c):
+    """Twice the signed area of triangle (a, b, c), exact on integers."""
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+
+
+def test_mesh_triangles_tile_the_hull():
+    grid, h, w = 6, 47, 61
+    nodes = O.mesh_node_xy(grid, h, w)
+    tris = O.mesh_triangles(grid)
+    sx, sy = w // grid, h // grid
+    areas = np.array([_orient(*nodes[t]) for t in tris])
+    # every triangle is half a cell, all with one orientation, and they add up to the hull
+    assert np.all(areas == areas[0]) and abs(int(areas[0])) == sx * sy
+    hull = (nodes[:, 0].max() - nodes[:, 0].min()) * (nodes[:, 1].max() - nodes[:, 1].min())
+    assert abs(int(areas.sum())) == 2 * hull
+
+
+def test_mesh_triangle_of_matches_orientation_tests():
+    # the integer rule against containment by orientation signs: every pixel in
+    # the hull lies in its triangle, and a pixel strictly inside one triangle
+    # lies in no other; outside the hull, the clamped cell and the side of its
+    # diagonal decide
+    grid, h, w = 5, 47, 61
+    nodes = O.mesh_node_xy(grid, h, w)
+    tris = O.mesh_triangles(grid)
+    yy, xx = np.mgrid[0:h, 0:w]
+    t = O.mesh_triangle_of(xx, yy, grid, h, w)
+    sgn = np.sign(_orient(*nodes[tris[0]]))
+    sx, sy = w // grid, h // grid
+    for y in range(h):
+        for x in range(w):
+            p = (x, y)
+            o = [sgn * _orient(nodes[tris[t[y, x]]][a], nodes[tris[t[y, x]]][(a + 1) % 3], p) for a in range(3)]
+            in_hull = nodes[0, 0] <= x <= nodes[-1, 0] and nodes[0, 1] <= y <= nodes[-1, 1]
+            if in_hull:
+                assert min(o) >= 0, (x, y)
+                if min(o) > 0:
+                    others = [k for k, tri in enumerate(tris)
+                              if k != t[y, x] and min(sgn * _orient(nodes[tri][a], nodes[tri][(a + 1) % 3], p)
+                                                      for a in range(3)) >= 0]
+                    assert others == [], (x, y, others)
+            ci = min(max((x - sx // 2) // sx, 0), grid - 2)
+            cj = min(max((y - sy // 2) // sy, 0), grid - 2)
+            assert t[y, x] // 2 == cj * (grid - 1) + ci
+            k00 = cj * grid + ci
+            d0, d1 = nodes[k00 + 1], nodes[k00 + grid]
+            first = np.sign(_orient(d0, d1, p)) in (0, np.sign(_orient(d0, d1, nodes[k00])))
+            assert t[y, x] % 2 == (0 if first else 1), (x, y)
+
+
+def test_mesh_band_is_the_vertex_one_ring():
+    # the band is the set of vertices of every triangle touching t (brute force)
+    grid = 6
+    tris = O.mesh_triangles(grid)
+    for t in range(len(tris)):
+        touch = [tri for tri in tris if set(tri) & set(tris[t])]
+        ref = sorted(set(int(v) for tri in touch for v in tri))
+        assert O.mesh_band(grid, t).tolist() == ref
+    # interior triangles see twelve points, the corner triangle at the origin six
+    assert len(O.mesh_band(grid, 2 * (2 * (grid - 1) + 2))) == 12
+    assert len(O.mesh_band(grid, 2 * (2 * (grid - 1) + 2) + 1)) == 12
+    assert len(O.mesh_band(grid, 0)) == 6
+
+
+def test_fit_mesh_exact_on_piecewise_affine_points():
+    # nodes in columns i <= 2 follow A1, columns i >= 3 follow A2.  A triangle of
+    # cell ci reaches columns ci-1 .. ci+2 through its band, so cell 0 fits A1
+    # exactly, cells >= 4 fit A2 exactly, and the cells between mix the two.
+    grid, h, w, level = 7, 700, 840, 0
+    nodes = O.mesh_node_xy(grid, h, w).astype(np.float64)
+    A1 = np.array([1.001, -0.002, 3.5, 0.0015, 0.999, -2.25])
+    A2 = np.array([0.997, 0.003, -4.0, -0.001, 1.002, 6.5])
+    col = np.arange(grid * grid) % grid
+    q = np.where((col <= 2)[:, None], np.stack(O.apply_affine(A1, nodes[:, 0], nodes[:, 1]), 1),
+                 np.stack(O.apply_affine(A2, nodes[:, 0], nodes[:, 1]), 1))
+    rng = np.random.default_rng(4)
+    wts = rng.uniform(6, 40, grid * grid)
+    # an outlier of weight 0 changes nothing
+    q[3 * grid + 5] += 50.0
+    wts[3 * grid + 5] = 0.0
+    sec = np.array([1, 0, 0, 0, 1, 0.0])
+    tri, st = O.fit_mesh(nodes, q, wts, grid, sec)
+    assert np.all(st == 0)
+    for t in range(len(tri)):
+        ci = (t // 2) % (grid - 1)
+        if ci == 0:
+            np.testing.assert_allclose(tri[t], A1, rtol=0, atol=1e-9)
+        elif ci >= 4:
+            np.testing.assert_allclose(tri[t], A2, rtol=0, atol=1e-9)
+        else:
+            assert not np.allclose(tri[t], A1, atol=1e-6) and not np.allclose(tri[t], A2, atol=1e-6)
+    # no weighted points in the top-left corner: those triangles keep the section's affine
+    w0 = wts.copy()
+    for j in range(3):
+        for i in range(3):
+            w0[j * grid + i] = 0.0
+    tri, st = O.fit_mesh(nodes, q, w0, grid, sec)
+    assert st[0] == O.swift_oracle.MESH_FIT_SINGULAR and np.array_equal(tri[0], sec)
+    assert np.all(st[2 * (grid - 1) * 4:] == 0)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_render_mesh_reduces_to_render(level):
+    rng = np.random.default_rng(12 + level)
+    img = rng.integers(0, 256, (70, 90)).astype(np.uint8)
+    A = [1.004, -0.01, 2.6, 0.008, 0.995, -1.7]
+    grid = 4
+    T = 2 * (grid - 1) ** 2
+    out = O.render_mesh(img, np.tile(A, (T, 1)), level, grid, 64, 88)
+    np.testing.assert_array_equal(out, O.render(img, A, level, 64, 88))
+    # distinct affines: each pixel is the plain render by its own triangle's affine
+    tri = np.tile(A, (T, 1)) + rng.uniform(-0.5, 0.5, (T, 6)) * [0.01, 0.01, 3, 0.01, 0.01, 3]
+    out = O.render_mesh(img, tri, level, grid, 64, 88)
+    yy, xx = np.mgrid[0:64, 0:88]
+    t = O.mesh_triangle_of(xx, yy, grid, 64, 88)
+    for k in range(T):
+        ref = O.render(img, tri[k], level, 64, 88)
+        np.testing.assert_array_equal(out[t == k], ref[t == k])
+
+
+def test_mesh_windows_reduce_to_stack_windows():
+    grid, level, h, w = 4, 1, 256, 320
+    A = np.array([1.002, 0.001, 8.3, -0.002, 0.999, -5.6])
+    T = 2 * (grid - 1) ** 2
+    ta, tb = O.mesh_windows(np.tile(A, (T, 1)), level, 64, grid, h, w)
+    ra, rb = O.stack_windows(A, level, 64, grid, h, w)
+    np.testing.assert_array_equal(ta, ra)
+    np.testing.assert_array_equal(tb, rb)
+    # distinct affines: node (i, j) reads through the first triangle of its
+    # cell, the last row and column through the cells before them
+    rng = np.random.default_rng(2)
+    tri = np.tile(A, (T, 1)) + rng.uniform(-1, 1, (T, 6)) * [0.001, 0.001, 2, 0.001, 0.001, 2]
+    ta, _ = O.mesh_windows(tri, level, 64, grid, h, w)
+    for j in range(grid):
+        for i in range(grid):
+            ci, cj = min(i, grid - 2), min(j, grid - 2)
+            t = 2 * (cj * (grid - 1) + ci) + (1 if (i == grid - 1 and j == grid - 1) else 0)
+            k = j * grid + i
+            np.testing.assert_array_equal(ta[k, [2, 3, 5, 6]], tri[t, [0, 1, 3, 4]])
