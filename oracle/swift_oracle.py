@@ -44,11 +44,17 @@ class Params:
     taper_frac fraction of the window edge covered by the cosine taper, both
                edges together (apodization paragraph of Section III).
     centroid_r half-width of the sub-pixel centroid box.
+    max_shift  radius r of the expected-shift neighbourhood: r > 0 (and below
+               N/2) restricts the integer peak to wrapped shifts |sx|, |sy| <= r
+               (the pruned inverse transform, a speed-up the paper names in
+               Section V); 0 searches the whole surface.  The SNR background
+               is the whole surface either way.
     """
     p: float = 0.65
     eps_rel: float = 1e-4
     taper_frac: float = 0.25
     centroid_r: int = 1
+    max_shift: int = 0
 
 
 # ---------------------------------------------------------------------------
@@ -157,12 +163,24 @@ def _wrap(i, n):
     return i - n if i >= n // 2 else i
 
 
-def peak_stats(c, centroid_r=1):
-    """Integer peak (first maximum in row-major order), Z-score SNR over the
-    whole surface (population std), and a (2r+1)^2 centroid with weights
-    max(c - mean, 0), shifts wrapped to [-N/2, N/2)."""
+def search_mask(n, max_shift):
+    """Surface entries the integer peak may take: all of them for max_shift
+    0 (or >= n/2), else those whose wrapped shifts satisfy |sx|, |sy| <=
+    max_shift."""
+    if max_shift <= 0 or max_shift >= n // 2:
+        return np.ones((n, n), dtype=bool)
+    s = np.array([abs(_wrap(i, n)) <= max_shift for i in range(n)])
+    return s[:, None] & s[None, :]
+
+
+def peak_stats(c, centroid_r=1, max_shift=0):
+    """Integer peak (first maximum in row-major order among the entries of
+    search_mask), Z-score SNR over the whole surface (population std), and a
+    (2r+1)^2 centroid with weights max(c - mean, 0), shifts wrapped to
+    [-N/2, N/2)."""
     n = c.shape[0]
-    flat = int(np.argmax(c.ravel()))
+    cand = np.where(search_mask(n, max_shift), c, -np.inf).ravel()
+    flat = int(np.argmax(cand))
     iy, ix = divmod(flat, n)
     peak = float(c[iy, ix])
     mu = float(np.mean(c))
@@ -173,7 +191,7 @@ def peak_stats(c, centroid_r=1):
     else:
         snr = 0.0
         status |= STATUS_DEGENERATE
-    rest = np.delete(c.ravel(), flat)
+    rest = np.delete(cand, flat)
     second = float(np.max(rest)) if rest.size else -np.inf
     if peak - second <= NEAR_TIE_REL * abs(peak):
         status |= STATUS_NEAR_TIE
@@ -281,7 +299,7 @@ def match_pair(imgA, imgB, thetaA, thetaB, n, params: Params, return_surface=Fal
     wA, _ = prepare(a, T)
     wB, _ = prepare(b, T)
     c = whitened_surface(wA, wB, params.p, params.eps_rel)
-    rec = peak_stats(c, params.centroid_r)
+    rec = peak_stats(c, params.centroid_r, params.max_shift)
     if clA or clB:
         rec["status"] |= STATUS_CLAMPED
     if return_surface:
@@ -342,7 +360,7 @@ def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=
     C = X * h
     C[0, 0] = 0.0
     c = np.fft.ifft2(C).real
-    rec = peak_stats(c, params.centroid_r)
+    rec = peak_stats(c, params.centroid_r, params.max_shift)
     iy, ix = rec["iy"], rec["ix"]
     mu, sd, snr = rec["mean"], rec["std"], rec["snr"]
     # cotangent of the surface
@@ -629,20 +647,29 @@ def fit_mesh(p, q, w, grid, section_aff):
     return out, st
 
 
-def render_mesh(img, tri_aff, level, grid, out_h, out_w):
-    """mir texture mapping of one section: out[y][x] is the bilinear value of
-    the level-l image at the raw point of aligned pixel (x, y) under the affine
-    of its triangle (mesh of the out_h x out_w frame), rounded half up to uint8.
-    Same arithmetic as render, per pixel."""
-    yy, xx = np.meshgrid(np.arange(out_h), np.arange(out_w), indexing="ij")
-    t = mesh_triangle_of(xx, yy, grid, out_h, out_w)
+def render_mesh_at(img, tri_aff, level, grid, out_h, out_w, x, y):
+    """Pixels (x, y) (integer arrays) of render_mesh(img, tri_aff, level, grid,
+    out_h, out_w): the bilinear value of the level-l image at the raw point of
+    aligned pixel (x, y) under the affine of its triangle in the mesh of the
+    out_h x out_w frame, rounded half up to uint8; the arithmetic of render,
+    per pixel."""
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    t = mesh_triangle_of(x, y, grid, out_h, out_w)
     a = np.asarray(tri_aff, dtype=np.float64)[t]
-    px = level_to_base(xx.astype(np.float64), level)
-    py = level_to_base(yy.astype(np.float64), level)
+    px = level_to_base(x.astype(np.float64), level)
+    py = level_to_base(y.astype(np.float64), level)
     qx = a[..., 0] * px + a[..., 1] * py + a[..., 2]
     qy = a[..., 3] * px + a[..., 4] * py + a[..., 5]
     v, _ = bilinear_clamped(img, base_to_level(qx, level), base_to_level(qy, level))
     return np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8)
+
+
+def render_mesh(img, tri_aff, level, grid, out_h, out_w):
+    """mir texture mapping of one section: every pixel of the out_h x out_w
+    aligned frame by render_mesh_at."""
+    yy, xx = np.meshgrid(np.arange(out_h), np.arange(out_w), indexing="ij")
+    return render_mesh_at(img, tri_aff, level, grid, out_h, out_w, xx, yy)
 
 
 def mesh_windows(tri_aff, level, n, grid, h_l, w_l):

@@ -275,6 +275,41 @@ def test_argmax_first_occurrence_and_near_tie():
     assert rec["status"] & STATUS_NEAR_TIE
 
 
+def test_search_window_brute_force_and_decoy():
+    # the windowed peak is the first row-major maximum among the entries with
+    # wrapped |sx|, |sy| <= r (brute force over the window), the background
+    # stays the whole surface, and a stronger decoy outside the window loses
+    rng = np.random.default_rng(17)
+    n, r = 32, 5
+    c = rng.normal(0, 1, (n, n))
+    c[3, n - 2] = 9.0    # inside: shift (-2, 3)
+    c[12, 20] = 15.0     # outside
+    full = O.peak_stats(c)
+    assert (full["iy"], full["ix"]) == (12, 20)
+    win = O.peak_stats(c, max_shift=r)
+    best, arg = -np.inf, None
+    for iy in range(n):
+        for ix in range(n):
+            sy = iy - n if iy >= n // 2 else iy
+            sx = ix - n if ix >= n // 2 else ix
+            if abs(sx) <= r and abs(sy) <= r and c[iy, ix] > best:
+                best, arg = c[iy, ix], (iy, ix)
+    assert (win["iy"], win["ix"]) == arg == (3, n - 2)
+    assert (win["sx"], win["sy"]) == (-2, 3)
+    assert win["mean"] == full["mean"] and win["std"] == full["std"]
+    assert win["snr"] == (9.0 - full["mean"]) / full["std"]
+    # the near-tie test compares within the window only
+    c2 = c.copy()
+    c2[n - 1, 1] = 9.0
+    assert O.peak_stats(c2, max_shift=r)["status"] & STATUS_NEAR_TIE
+    assert not (O.peak_stats(c2)["status"] & STATUS_NEAR_TIE)
+    # radius 0 and radii of half the surface or more search everything
+    for rr in (0, n // 2, n):
+        assert (O.peak_stats(c, max_shift=rr)["iy"], O.peak_stats(c, max_shift=rr)["ix"]) == (12, 20)
+    # a window of radius r holds (2r + 1)^2 entries
+    assert O.swift_oracle.search_mask(n, r).sum() == (2 * r + 1) ** 2
+
+
 # ---------------------------------------------------------------- qualitative claim (Fig. 2)
 def test_mid_whitening_beats_extremes_on_distorted_pair():
     """Section III / Fig. 2: an intermediate exponent gives a higher SNR than
