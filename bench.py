@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 METRIC = "512² window-pair matches/sec + HBM GB/s; plain vs batched+adjoint at 0.01px"
 HBM_PEAK_GBS = 8000.0
 S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
+PRUNE_R = N // 8  # search radius of the pruned-inverse variant (64 px at 512^2)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_match_512_headline.txt")
 
 
@@ -301,6 +302,94 @@ def stack_loop(ctx, stack, warps, refine="adjoint"):
                                                              "neighbour_before": n0, "neighbour_after": n1})
 
 
+# --------------------------------------------------------------------------- local-affine mesh
+MESH_SECTIONS, MESH_GRID, MESH_N, MESH_BEND = 16, 16, 256, 3.0
+# FP64 operations per rendered pixel in the render definition (contraction
+# off, so no FMA): level -> base 4, affine 8, base -> level 4, floor and
+# fraction 4, bilinear weights and blend 11, rounding and clamp 4.
+RENDER_FP64_OPS = 35
+# non-FMA FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def mesh_block(ctx, dev, sections=MESH_SECTIONS, size=SIZE, grid=MESH_GRID, n=MESH_N, reps=10):
+    """Local-affine triangle mesh (mir, Section IV) on a stack with nonlinear
+    section warps: global affines first (levels 2/1/0), then two mesh passes
+    at level 0 (grid x grid nodes at the window centres, n^2 windows).
+    Residuals against the generator's warps at the triangle centroids; the
+    mesh render timed per launch with HIP events over the whole stack."""
+    import torch
+
+    from datagen.evaluate import mesh_centroids, residuals
+    from datagen.workloads import bent_stack
+    from paper_1612_04787_amd.stack import align_mesh, align_stack, build_pyramid
+    stack, warps = bent_stack(sections, size, seed=11, bend=MESH_BEND, device=dev)
+    pyr = build_pyramid(ctx, stack, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    aff, _ = align_stack(ctx, stack, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), ks=(4, 3, 3), grid=8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tri, mrep = align_mesh(ctx, stack, aff, level=0, n=n, grid=grid, k=3, passes=2, pyr=pyr)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cen = mesh_centroids(grid, size, size)
+    g0, n0 = residuals(aff.cpu().numpy(), warps, cen)
+    g1, n1 = residuals(tri.cpu().numpy(), warps, cen)
+    out = torch.empty_like(stack)
+    ctx.render_mesh(stack, tri, grid, 0, out=out)
+    ctx.render(stack, aff, 0, out=out)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.render_mesh(stack, tri, grid, 0, out=out)
+        ctx.render(stack, aff, 0, out=out)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    px = float(sections) * size * size
+
+    def rate(name):
+        cnt, tot = prof[name]
+        ms = tot / cnt
+        return dict(ms=ms, gpix_s=px / (ms / 1e3) / 1e9, hbm_gbs=2.0 * px / (ms / 1e3) / 1e9,
+                    fp64_tops=RENDER_FP64_OPS * px / (ms / 1e3) / 1e12)
+
+    rm, rg = rate("k_render_mesh<0>"), rate("k_render<0>")
+    roof = {"bound": "alu", "achieved": rm["fp64_tops"], "peak": FP64_VALU_PEAK_TOPS, "unit": "TFLOP/s",
+            "frac": rm["fp64_tops"] / FP64_VALU_PEAK_TOPS, "traffic": None}
+    res = dict(workload="%d sections of %d^2 with drift, affine distortion and a smooth bend of up to %.0f px; "
+                        "global affines (levels 2/1/0), then 2 mesh passes at level 0 with %d x %d nodes and "
+                        "%d^2 windows" % (sections, size, MESH_BEND, grid, grid, n),
+               affine_ms=(t1 - t0) * 1e3, mesh_ms=(t2 - t1) * 1e3, passes=mrep,
+               residual_px={"neighbour_affine": n0, "neighbour_mesh": n1, "global_affine": g0, "global_mesh": g1},
+               render_mesh=dict(rm, roofline=roof), render_affine=rg,
+               note="render roofline: %d FP64 operations per pixel of the definition against the non-FMA FP64 "
+                    "vector rate; HBM bytes 2 per pixel (uint8 in and out)" % RENDER_FP64_OPS)
+    sample = (stack[0].cpu().numpy(), tri[0].cpu().numpy(), grid)
+    del stack, pyr, out
+    torch.cuda.empty_cache()
+    return res, sample
+
+
+def cpu_baseline_mesh(sample, n_px=1 << 21):
+    """The oracle's mesh render on a bounded sample of pixels of one section
+    (one process, FP64 NumPy), in Mpixel/s."""
+    import numpy as np
+
+    import oracle as O
+    img, tri, grid = sample
+    H, W = img.shape
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, W, n_px)
+    ys = rng.integers(0, H, n_px)
+    t0 = time.perf_counter()
+    O.render_mesh_at(img, tri, 0, grid, H, W, xs, ys)
+    el = time.perf_counter() - t0
+    return dict(value=n_px / el / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
+                sample="%d random pixels of one %d^2 section through its %d x %d mesh, FP64 NumPy; %.1f s"
+                       % (n_px, H, grid, grid, el))
+
+
 # --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -312,6 +401,8 @@ def main():
     ap.add_argument("--no-stack", action="store_true", help="skip the iterative stack-alignment run")
     ap.add_argument("--no-ragged", action="store_true", help="skip the multi-level ragged batch comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default row-count plan (no tuning launches)")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the local-affine mesh run")
+    ap.add_argument("--no-prune", action="store_true", help="skip the pruned-inverse (search radius) variant")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -404,6 +495,41 @@ def main():
     res = sw.parse_records(out)
     snr = res["snr"].float()
     step_bytes = P * pair_bytes(N) + kernel_bytes("k_project", N, P, S_SECTIONS, SIZE)
+
+    pruned = None
+    if not args.no_prune:
+        # the same step with the pruned inverse: peak searched within +-PRUNE_R
+        # px, only the surface rows near the origin transformed back
+        prm_p = sw.make_params(p=P_WHITEN, max_shift=PRUNE_R)
+        out_p = torch.empty_like(out)
+
+        def step_p():
+            ctx.project(stack, k=K_PROJ, out=refs)
+            ctx.match_batch_raw(table, len(images), pairs, prm_p, out_p, None, ws)
+
+        for _ in range(args.warmup):
+            step_p()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_p()
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) / args.steps * 1e3
+        ctx.profile(True)
+        for _ in range(prof_steps):
+            step_p()
+        torch.cuda.synchronize()
+        kp = {name: dict(launches=cnt, avg_ms=tot / cnt) for name, (cnt, tot) in ctx.profile_read().items()}
+        ctx.profile(False)
+        rp = sw.parse_records(out_p)
+        same = (rp["ix"] == res["ix"]) & (rp["iy"] == res["iy"])
+        dd = torch.maximum((rp["dx"] - res["dx"]).abs(), (rp["dy"] - res["dy"]).abs())[same]
+        pruned = dict(radius_px=PRUNE_R, ms_per_step=ms_p, pairs_per_s=P / (ms_p / 1e3), speedup=ms / ms_p,
+                      kernels=kp, same_peak_frac=float(same.float().mean()),
+                      max_subpixel_diff_px=float(dd.max()) if dd.numel() else None,
+                      max_snr_rel_diff=float(((rp["snr"] - res["snr"]).abs() / res["snr"].abs()).max()))
+        log("pruned (r=%d): %.3f ms/step (%.2fx), same peak %.4f" % (PRUNE_R, ms_p, ms / ms_p,
+                                                                     pruned["same_peak_frac"]))
     line = {
         "metric": METRIC,
         "value": value,
@@ -432,6 +558,8 @@ def main():
         "plan": {str(n): {"fwd_rows": v[1][0], "inv_rows": v[1][1], "variant_ms": v[0]} for n, v in tuned.items()},
         "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
     }
+    if pruned is not None:
+        line["pruned"] = pruned
     if not args.no_refine:
         log("refinement: plain vs batched + adjoint to 0.01 px ...")
         del ws
@@ -447,10 +575,21 @@ def main():
         log("stack loop: %.0f ms, residual global %.2f -> %.2f px, neighbour %.2f -> %.2f px"
             % (line["stack_loop"]["wall_ms"], r["global_before"], r["global_after"], r["neighbour_before"],
                r["neighbour_after"]))
+    mesh_sample = None
+    if not args.no_mesh:
+        log("mesh: global affines then two local-affine mesh passes on a bent stack ...")
+        line["mesh"], mesh_sample = mesh_block(ctx, dev)
+        m = line["mesh"]
+        log("mesh: neighbour residual %.3f -> %.3f px; passes %.0f ms; render_mesh %.3f ms (%.0f Gpix/s), "
+            "render %.3f ms" % (m["residual_px"]["neighbour_affine"], m["residual_px"]["neighbour_mesh"],
+                                m["mesh_ms"], m["render_mesh"]["ms"], m["render_mesh"]["gpix_s"],
+                                m["render_affine"]["ms"]))
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)
         log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
+        if mesh_sample is not None:
+            line["cpu_baseline"]["mesh_render"] = cpu_baseline_mesh(mesh_sample)
     if not args.no_ragged:
         log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
         del stack, refs, images, table, out

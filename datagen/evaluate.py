@@ -10,16 +10,42 @@ from __future__ import annotations
 import numpy as np
 
 
+def _generator_map(warp, q):
+    """G_s(q) = M q + b + D(q) of one section's warp (M, b) or (M, b, bend)."""
+    from .synth import bend_displacement
+    g = q @ np.asarray(warp[0], np.float64).T + np.asarray(warp[1], np.float64)
+    if len(warp) > 2 and warp[2] is not None:
+        dx, dy = bend_displacement(warp[2], q[:, 0], q[:, 1])
+        g = g + np.stack([dx, dy], 1)
+    return g
+
+
 def composed_points(aff, warps, pts):
-    """C_s(p) for every section and point: [S, n, 2]."""
+    """C_s(p) for every section and point: [S, n, 2].  aff [S, 6] applies one
+    affine per section to every point; aff [S, n, 6] one affine per point."""
     out = []
-    for s, (m, b) in enumerate(warps):
+    for s, warp in enumerate(warps):
         a = np.asarray(aff[s], dtype=np.float64)
-        L = np.array([[a[0], a[1]], [a[3], a[4]]])
-        t = np.array([a[2], a[5]])
-        q = pts @ L.T + t
-        out.append(q @ np.asarray(m, np.float64).T + np.asarray(b, np.float64))
+        if a.ndim == 1:
+            a = np.broadcast_to(a, (len(pts), 6))
+        q = np.stack([a[:, 0] * pts[:, 0] + a[:, 1] * pts[:, 1] + a[:, 2],
+                      a[:, 3] * pts[:, 0] + a[:, 4] * pts[:, 1] + a[:, 5]], 1)
+        out.append(_generator_map(warp, q))
     return np.stack(out)
+
+
+def mesh_centroids(grid, h, w):
+    """Level-0 centroids of the triangles of a level-0 mesh on an h x w frame
+    (nodes at the centres of a grid x grid window tiling, each cell cut along
+    its (i+1, j) - (i, j+1) diagonal), in triangle order: [2 (grid-1)^2, 2]."""
+    sx, sy = w // grid, h // grid
+    node = lambda i, j: np.array([sx // 2 + i * sx, sy // 2 + j * sy], np.float64)  # noqa: E731
+    out = []
+    for cj in range(grid - 1):
+        for ci in range(grid - 1):
+            out.append((node(ci, cj) + node(ci + 1, cj) + node(ci, cj + 1)) / 3.0)
+            out.append((node(ci + 1, cj) + node(ci + 1, cj + 1) + node(ci, cj + 1)) / 3.0)
+    return np.array(out)
 
 
 def residuals(aff, warps, pts):

@@ -144,8 +144,19 @@ def random_affine_about_center(h: int, w: int, seed: int, max_rot_deg=0.5,
     return m, b
 
 
-def warp_affine(img_f32, m, b, out_hw=None):
-    """out(q) = img(M q + b), bilinear, clamp-to-edge, via grid_sample.
+def bend_displacement(bend, x, y):
+    """Smooth nonlinear displacement of a bend (ax, ay, phx, phy, period):
+    (ax sin(2 pi y / period + phx), ay sin(2 pi x / period + phy))."""
+    ax, ay, phx, phy, lam = bend
+    k = 2.0 * math.pi / lam
+    if isinstance(x, torch.Tensor):
+        return ax * torch.sin(k * y + phx), ay * torch.sin(k * x + phy)
+    return ax * np.sin(k * np.asarray(y) + phx), ay * np.sin(k * np.asarray(x) + phy)
+
+
+def warp_affine(img_f32, m, b, out_hw=None, bend=None):
+    """out(q) = img(M q + b + D(q)), bilinear, clamp-to-edge, via grid_sample;
+    D is the bend displacement (zero when bend is None).
     img_f32: (H, W) float32 tensor. q = (x, y) in pixels of the output grid."""
     h, w = img_f32.shape
     oh, ow = out_hw if out_hw is not None else (h, w)
@@ -155,6 +166,11 @@ def warp_affine(img_f32, m, b, out_hw=None):
     yy, xx = torch.meshgrid(ys, xs, indexing="ij")
     sx = m[0][0] * xx + m[0][1] * yy + b[0]
     sy = m[1][0] * xx + m[1][1] * yy + b[1]
+    if bend is not None:
+        dx, dy = bend_displacement(bend, xx, yy)
+        sx = sx + dx
+        sy = sy + dy
+        del dx, dy
     gx = (2.0 * sx / (w - 1) - 1.0).float()
     gy = (2.0 * sy / (h - 1) - 1.0).float()
     del sx, sy, xx, yy
@@ -183,8 +199,9 @@ def make_stack(n_sections: int, h: int, w: int, seed: int, device="cpu",
     """A (S, H, W) uint8 stack whose content varies smoothly in z: keyframe
     textures every `keyframe_every` sections blended linearly, membrane control
     points drifting slowly with z, independent noise per section.
-    `warps`, if given, is a list of (M, b) per section applied to the clean
-    section before noise (observed(q) = clean(M q + b))."""
+    `warps`, if given, is a list of (M, b) or (M, b, bend) per section applied
+    to the clean section before noise (observed(q) = clean(M q + b + D(q)), D
+    the bend displacement)."""
     g = _gen(seed, device)
     n_key = n_sections // keyframe_every + 2
     keys = [_texture(h, w, g, device) for _ in range(n_key)]
@@ -200,8 +217,8 @@ def make_stack(n_sections: int, h: int, w: int, seed: int, device="cpu",
         tex = (1.0 - al) * keys[k] + al * keys[k + 1]
         _draw_curves(tex, p0 + s * v0, p1 + s * v1, p2 + s * v2, 40.0)
         if warps is not None and warps[s] is not None:
-            m, b = warps[s]
-            tex = warp_affine(tex, m, b)
+            m, b = warps[s][0], warps[s][1]
+            tex = warp_affine(tex, m, b, bend=warps[s][2] if len(warps[s]) > 2 else None)
         tex = tex + noise_sigma * torch.randn(tex.shape, generator=g, device=device)
         out[s] = _to_u8(tex)
         del tex

@@ -34,6 +34,30 @@ def stack_warps(n_sections: int, h: int, w: int, seed: int, drift=2.0, rot_deg=0
     return out
 
 
+def bent_warps(n_sections: int, h: int, w: int, seed: int, bend=3.0, period=None, **kw):
+    """stack_warps plus a smooth nonlinear bend per section: amplitudes
+    U(-bend, bend) px in x and y, random phases, one period across the section
+    by default.  Returns a list of (M, b, (ax, ay, phx, phy, period))."""
+    base = stack_warps(n_sections, h, w, seed, **kw)
+    rng = np.random.default_rng(seed + 77)
+    lam = float(period if period is not None else w)
+    out = []
+    for (m, b) in base:
+        ax, ay = rng.uniform(-bend, bend, 2)
+        phx, phy = rng.uniform(0, 2 * math.pi, 2)
+        out.append((m, b, (float(ax), float(ay), float(phx), float(phy), lam)))
+    return out
+
+
+def bent_stack(n_sections=16, size=4096, seed=11, bend=3.0, device="cuda"):
+    """The mesh input: S sections of size^2 uint8 with the drift and affine
+    distortion of distorted_stack plus a smooth nonlinear bend per section.
+    Returns (stack, warps)."""
+    warps = bent_warps(n_sections, size, size, seed + 1000, bend=bend)
+    st = make_stack(n_sections, size, size, seed, device=device, warps=warps)
+    return st, warps
+
+
 def distorted_stack(n_sections=64, size=4096, seed=5, device="cuda"):
     """The iterative-stack input: S sections of size^2 uint8 with accumulated
     drift and per-section affine distortion.  Returns (stack, warps)."""

@@ -98,7 +98,18 @@ typedef struct {
  *             SWIFT_FLAG_JAC_TRANSLATION: swift_centroid_jacobian computes
  *               only the translation columns (tx, ty) of the Jacobian, the
  *               ones the Newton refinement step uses, and writes zeros in
- *               the other four (fewer per-pixel sums); other calls ignore it. */
+ *               the other four (fewer per-pixel sums); other calls ignore it.
+ *  max_shift  radius r >= 0 of the expected-shift neighbourhood (the pruned
+ *             inverse FFT, an algorithmic speed-up named in Section V).  For a
+ *             window edge n with 0 < r < n/2 the integer peak is the first
+ *             row-major maximum among the surface entries with wrapped shifts
+ *             |sx|, |sy| <= r, and only the surface rows within r + 1 of the
+ *             origin (rounded out to the inverse row blocks) are transformed
+ *             back.  The SNR background stays the whole surface: mean 0 (the
+ *             DC bin is 0) and the population std from the whitened spectrum
+ *             by Parseval, std^2 = sum_k |C(k)|^2 / n^4.  r = 0, or r >= n/2,
+ *             searches the whole surface.  With 0 < r < n/2 for some size in
+ *             the batch, `surfaces` must be NULL. */
 #define SWIFT_FLAG_CONCURRENT_SIZES 1
 #define SWIFT_FLAG_JAC_TRANSLATION 2
 typedef struct {
@@ -107,7 +118,7 @@ typedef struct {
   float taper_frac;
   int32_t centroid_r;
   int32_t flags;
-  int32_t reserved;
+  int32_t max_shift;
 } swift_params;
 
 /* One match record (64 bytes). */
@@ -305,6 +316,55 @@ int swift_stack_windows(swift_ctx* ctx, int32_t S, const double* aff, int32_t le
 int swift_fit_sections(swift_ctx* ctx, int32_t S, int32_t per_section, const float* theta_a,
                        const float* theta_b, const swift_match* recs, int32_t level, float min_snr,
                        double* aff, int32_t* status, hipStream_t stream);
+
+/* ---- Local-affine triangle mesh (mir at the finest stages, Section IV; texture
+ * mapping of a triangulated mesh, Section III).
+ *
+ * The mesh of a section lives on an h_l x w_l level-l aligned frame with a
+ * grid x grid layout (2 <= grid <= 1024, grid <= h_l, w_l <= 65535): node (i, j), index
+ * k = j*grid + i, sits at the centre of swim window k, (sx/2 + i*sx, sy/2 +
+ * j*sy) with sx = w_l/grid, sy = h_l/grid (integer division).  Cell (ci, cj),
+ * 0 <= ci, cj < grid-1, is cut along the diagonal from node (ci+1, cj) to node
+ * (ci, cj+1) into triangle 2c (nodes (ci,cj), (ci+1,cj), (ci,cj+1)) and
+ * triangle 2c+1 (nodes (ci+1,cj), (ci+1,cj+1), (ci,cj+1)), c = cj*(grid-1) + ci;
+ * T = 2*(grid-1)^2 triangles per section.  Level-l pixel (x, y) belongs to cell
+ * (clamp(floor((x - sx/2)/sx)), clamp(floor((y - sy/2)/sy))), clamped to the
+ * cells so that the border triangles reach the frame edges, and to its first
+ * triangle iff (x - x_c)*sy + (y - y_c)*sx <= sx*sy, (x_c, y_c) the cell's node
+ * (ci, cj).  Triangle affines are level-0 maps from aligned-frame points to
+ * raw-section points, like the section affines: tri_aff [S][T][6] doubles
+ * (a11, a12, tx, a21, a22, ty), device. */
+
+/* mir texture mapping: as swift_render, except that every output pixel takes
+ * the affine of its triangle in the mesh of the dst_h x dst_w output frame.
+ * Output is bit-exact to that definition (FP64, fixed operation order).
+ * Errors: SWIFT_E_INVAL (sizes as swift_render; grid out of range or larger
+ * than dst_h or dst_w), SWIFT_E_HIP. */
+int swift_render_mesh(swift_ctx* ctx, const uint8_t* src, int32_t S, int32_t src_h, int32_t src_w,
+                      int64_t src_pitch, int64_t src_stride, const double* tri_aff, int32_t grid,
+                      int32_t level, uint8_t* dst, int32_t dst_h, int32_t dst_w, int64_t dst_pitch,
+                      int64_t dst_stride, hipStream_t stream);
+
+/* swim window set-up through a mesh: the windows of swift_stack_windows (same
+ * layout, pair i = s*grid^2 + k at node k, same outputs), except that window A
+ * reads the raw section through the affine of the triangle node k's pixel
+ * belongs to.  Errors: SWIFT_E_INVAL. */
+int swift_mesh_windows(swift_ctx* ctx, int32_t S, const double* tri_aff, int32_t level, int32_t grid,
+                       int32_t h_l, int32_t w_l, int32_t img_a0, int32_t img_b0, float* theta_a,
+                       float* theta_b, int32_t* img_a, int32_t* img_b, hipStream_t stream);
+
+/* mir's local affines (Section IV): each triangle's affine is the weighted
+ * least-squares fit q ~ L p + t of the window matches in its band, the
+ * triangle's three nodes and every node sharing a mesh edge with one of them
+ * (12 nodes inside the mesh, fewer at its border).  Matches are pairs
+ * s*grid^2 + k (node k), read as in swift_fit_sections (p, q, weights).  A
+ * triangle with fewer than three weighted band points, or collinear ones,
+ * takes its section's affine aff [S][6] (device, double, read only) and status
+ * 1, else 0.  tri_aff: device [S][T][6] output; status: device [S][T] or NULL.
+ * Errors: SWIFT_E_INVAL (S outside [1, 65535], grid outside [2, 1024]). */
+int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a, const float* theta_b,
+                   const swift_match* recs, int32_t level, float min_snr, const double* aff,
+                   double* tri_aff, int32_t* status, hipStream_t stream);
 
 /* Row-count variants of the match kernels (a tuning choice, not in the
  * paper).  Each window size has two row counts per block for the forward row

@@ -34,5 +34,6 @@ from .swift_oracle import (  # noqa: F401
     mesh_triangle_of,
     fit_mesh,
     render_mesh,
+    render_mesh_at,
     mesh_windows,
 )

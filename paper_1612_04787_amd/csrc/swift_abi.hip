@@ -153,7 +153,7 @@ struct GroupLayout {
   int count = 0;
   int first = 0;  // index of the group's first pair
   // forward
-  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0;
+  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, colsq = 0;
   // adjoint
   size_t y = 0, dpart = 0, rpart = 0;
   // saved state (offsets into the saved buffer)
@@ -205,6 +205,8 @@ Layout make_layout(const swift_pairs* pairs) {
     fo += align256(P * sizeof(PairStat));
     g.invpart = fo;
     fo += align256(P * (size_t)max(inv_blocks_n(g.n, false), inv_blocks_n(g.n, true)) * sizeof(InvPart));
+    g.colsq = fo;
+    fo += align256(P * (n / 2 + 1) * sizeof(double));
     g.y = bo;
     bo += align256(P * n * n * sizeof(float2));
     g.dpart = bo;
@@ -250,6 +252,20 @@ int check_params(const swift_params* pr) {
   if (pr->centroid_r != 1) return fail(SWIFT_E_UNSUPPORTED, "centroid_r must be 1 (got %d)", pr->centroid_r);
   if (pr->flags & ~(SWIFT_FLAG_CONCURRENT_SIZES | SWIFT_FLAG_JAC_TRANSLATION))
     return fail(SWIFT_E_UNSUPPORTED, "unknown flags %#x", pr->flags);
+  if (pr->max_shift < 0) return fail(SWIFT_E_INVAL, "max_shift must be >= 0 (got %d)", pr->max_shift);
+  return SWIFT_OK;
+}
+
+// The search radius restricts window edge n only when 0 < r < n/2.
+bool prunes(const swift_params* pr, int n) { return pr->max_shift > 0 && pr->max_shift < n / 2; }
+
+// Surfaces are whole only without a search radius.
+int check_surfaces(const swift_pairs* pairs, const swift_params* pr, const float* surfaces) {
+  if (!surfaces) return SWIFT_OK;
+  for (int i = 0; i < SWIFT_NSIZES; ++i)
+    if (pairs->size_count[i] > 0 && prunes(pr, kSizes[i]))
+      return fail(SWIFT_E_INVAL, "surfaces must be NULL with max_shift %d (window edge %d)", pr->max_shift,
+                  kSizes[i]);
   return SWIFT_OK;
 }
 
@@ -437,6 +453,23 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.npairs = g.count;
     a.nsl_fwd = fwd_blocks_n(g.n, ctx->alt_fwd[i] != 0);
     a.nsl_inv = inv_blocks_n(g.n, ctx->alt_inv[i] != 0);
+    a.colsq = (double*)(base + g.colsq);
+    a.max_shift = 0;
+    a.nsl_lo = a.nsl_inv;
+    a.zlo = a.zhi = g.n;
+    if (prunes(params, g.n)) {
+      // rows |y| <= r + 1 (the centroid reads one row past the window),
+      // rounded out to whole inverse row blocks of R2 rows
+      const int full = a.nsl_inv, R2 = g.n / full, rr = params->max_shift + 1;
+      const int lo = rr / R2 + 1, hs = (g.n - rr) / R2;
+      a.max_shift = params->max_shift;
+      if (lo < hs) {
+        a.nsl_lo = lo;
+        a.nsl_inv = lo + (full - hs);
+        a.zlo = lo * R2;
+        a.zhi = hs * R2;
+      }
+    }
     a.saved_Z = saved ? (float2*)((char*)saved + g.sz) : nullptr;
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
@@ -458,6 +491,8 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   bool empty;
   int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
   if (rc || empty) return rc;
+  rc = check_surfaces(pairs, params, surfaces);
+  if (rc) return rc;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   return enqueue_match(ctx, imgs, n_imgs, pairs, params, out, surfaces, saved, ws, stream,
@@ -470,6 +505,8 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   bool empty;
   int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
   if (rc || empty) return rc;
+  rc = check_surfaces(pairs, params, surfaces);
+  if (rc) return rc;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   // key: every value the captured launches bake in
@@ -707,7 +744,7 @@ int swift_render(swift_ctx* ctx, const uint8_t* src, int32_t S, int32_t src_h, i
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipError_t e = launch_render(src, src_pitch, src_stride, S, src_h, src_w, aff, level, dst, dst_pitch, dst_stride,
-                               dst_h, dst_w, stream);
+                               dst_h, dst_w, stream, ctx->kt());
   if (e != hipSuccess) return hip_fail(e, "render launch");
   return ok();
 }
@@ -723,8 +760,71 @@ int swift_stack_windows(swift_ctx* ctx, int32_t S, const double* aff, int32_t le
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipError_t e = launch_stack_windows(S, aff, level, grid, h_l, w_l, img_a0, img_b0, theta_a, theta_b, img_a, img_b,
-                                      stream);
+                                      false, stream);
   if (e != hipSuccess) return hip_fail(e, "window launch");
+  return ok();
+}
+
+// A mesh needs two nodes per axis and a frame of at least one pixel per node;
+// the kernels' cell search assumes frame coordinates below 2^16.
+static int check_mesh(int grid, int h_l, int w_l) {
+  if (grid < 2 || grid > 1024) return fail(SWIFT_E_INVAL, "mesh grid must be in [2, 1024] (got %d)", grid);
+  if (h_l < grid || w_l < grid) return fail(SWIFT_E_INVAL, "mesh frame %d x %d smaller than grid %d", h_l, w_l, grid);
+  if (h_l > 65535 || w_l > 65535) return fail(SWIFT_E_INVAL, "mesh frame %d x %d above 65535", h_l, w_l);
+  return SWIFT_OK;
+}
+
+int swift_render_mesh(swift_ctx* ctx, const uint8_t* src, int32_t S, int32_t src_h, int32_t src_w,
+                      int64_t src_pitch, int64_t src_stride, const double* tri_aff, int32_t grid, int32_t level,
+                      uint8_t* dst, int32_t dst_h, int32_t dst_w, int64_t dst_pitch, int64_t dst_stride,
+                      hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!src || !dst || !tri_aff) return fail(SWIFT_E_INVAL, "src/dst/tri_aff is NULL");
+  if (S < 1 || src_h < 1 || src_w < 1 || dst_h < 1 || dst_w < 1) return fail(SWIFT_E_INVAL, "bad sizes");
+  if (dst_h > 65535 || S > 65535) return fail(SWIFT_E_INVAL, "dst_h and S must be at most 65535");
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  if (src_pitch < src_w || dst_pitch < dst_w) return fail(SWIFT_E_INVAL, "pitch smaller than width");
+  if (src_stride < src_pitch * src_h || dst_stride < dst_pitch * dst_h)
+    return fail(SWIFT_E_INVAL, "section stride smaller than height * pitch");
+  if (check_mesh(grid, dst_h, dst_w) != SWIFT_OK) return SWIFT_E_INVAL;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_render_mesh(src, src_pitch, src_stride, S, src_h, src_w, tri_aff, grid, level, dst,
+                                    dst_pitch, dst_stride, dst_h, dst_w, stream, ctx->kt());
+  if (e != hipSuccess) return hip_fail(e, "mesh render launch");
+  return ok();
+}
+
+int swift_mesh_windows(swift_ctx* ctx, int32_t S, const double* tri_aff, int32_t level, int32_t grid, int32_t h_l,
+                       int32_t w_l, int32_t img_a0, int32_t img_b0, float* theta_a, float* theta_b, int32_t* img_a,
+                       int32_t* img_b, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!tri_aff || !theta_a || !theta_b || !img_a || !img_b) return fail(SWIFT_E_INVAL, "NULL output or affine");
+  if (S < 1) return fail(SWIFT_E_INVAL, "bad sizes");
+  if (check_mesh(grid, h_l, w_l) != SWIFT_OK) return SWIFT_E_INVAL;
+  if ((long long)S * grid * grid > (1LL << 30)) return fail(SWIFT_E_INVAL, "too many windows");
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_stack_windows(S, tri_aff, level, grid, h_l, w_l, img_a0, img_b0, theta_a, theta_b, img_a,
+                                      img_b, true, stream);
+  if (e != hipSuccess) return hip_fail(e, "mesh window launch");
+  return ok();
+}
+
+int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a, const float* theta_b,
+                   const swift_match* recs, int32_t level, float min_snr, const double* aff, double* tri_aff,
+                   int32_t* status, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!theta_a || !theta_b || !recs || !aff || !tri_aff) return fail(SWIFT_E_INVAL, "NULL input or affine");
+  if (S < 1 || S > 65535) return fail(SWIFT_E_INVAL, "S must be in [1, 65535] (got %d)", S);
+  if (grid < 2 || grid > 1024) return fail(SWIFT_E_INVAL, "mesh grid must be in [2, 1024] (got %d)", grid);
+  if (level < 0 || level > 12) return fail(SWIFT_E_INVAL, "level must be in [0, 12] (got %d)", level);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_fit_mesh(S, grid, theta_a, theta_b, recs, level, min_snr, aff, tri_aff, status, stream,
+                                 ctx->kt());
+  if (e != hipSuccess) return hip_fail(e, "mesh fit launch");
   return ok();
 }
 

@@ -67,6 +67,15 @@ struct MatchArgs {
   int32_t npairs;
   int32_t nsl_fwd, nsl_inv;  // row blocks per pair of the forward / inverse row passes
   int32_t n_imgs;
+  // Pruned inverse (max_shift = r > 0): the peak is searched among wrapped
+  // shifts |sx|, |sy| <= r; the column pass stores surface rows [0, zlo) and
+  // [zhi, N) only, which the inverse row pass covers with its first nsl_lo
+  // row blocks and its last nsl_inv - nsl_lo (nsl_inv counts the launched
+  // blocks); colsq [P][N/2+1] receives the column sums of |C|^2 (Hermitian
+  // weights) that give the background std by Parseval.  Unpruned: r = 0,
+  // zlo = zhi = N, nsl_lo = nsl_inv.
+  int32_t max_shift, zlo, zhi, nsl_lo;
+  double* colsq;
   // state kept for the adjoint (all NULL when not requested)
   float2* saved_Z;         // [P][N][N]: forward 2-D spectrum of z, [kx][ky]
   PairStat* saved_ps;      // [P]
@@ -149,11 +158,19 @@ int col_items_per_wg(int n);  // column-pass workgroups per pair
 hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
 hipError_t launch_render(const uint8_t* src, int64_t spitch, int64_t sstride, int S, int sh, int sw,
                          const double* aff, int level, uint8_t* dst, int64_t dpitch, int64_t dstride, int dh, int dw,
-                         hipStream_t st);
+                         hipStream_t st, KernelTimer* kt);
+hipError_t launch_render_mesh(const uint8_t* src, int64_t spitch, int64_t sstride, int S, int sh, int sw,
+                              const double* tri_aff, int grid, int level, uint8_t* dst, int64_t dpitch,
+                              int64_t dstride, int dh, int dw, hipStream_t st, KernelTimer* kt);
+// mesh: aff holds per-triangle affines [S][2 (grid-1)^2][6] instead of [S][6]
 hipError_t launch_stack_windows(int S, const double* aff, int level, int grid, int hl, int wl, int img_a0,
-                                int img_b0, float* th_a, float* th_b, int32_t* ia, int32_t* ib, hipStream_t st);
+                                int img_b0, float* th_a, float* th_b, int32_t* ia, int32_t* ib, bool mesh,
+                                hipStream_t st);
 hipError_t launch_fit_sections(int S, int per, const float* th_a, const float* th_b, const swift_match* rec,
                                int level, float min_snr, double* aff, int32_t* status, hipStream_t st);
+hipError_t launch_fit_mesh(int S, int grid, const float* th_a, const float* th_b, const swift_match* rec, int level,
+                           float min_snr, const double* aff, double* tri_aff, int32_t* status, hipStream_t st,
+                           KernelTimer* kt);
 hipError_t launch_refine(int P, const swift_match* rec, const float* jac, float* th, int mode, float max_step,
                          float* step_out, hipStream_t s);
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,

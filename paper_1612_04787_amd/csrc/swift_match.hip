@@ -18,6 +18,9 @@
 //               columns, at N = 1024).
 //   k_row_inv   inverse row FFTs (two real rows per complex FFT), per-slice
 //               top-2 / argmax and FP64 sum, sum of squares; optional surface.
+//               With a search radius r (the pruned inverse) only the row
+//               blocks near the origin run, the peak is searched within
+//               |shift| <= r, and the column pass supplies sum |C|^2 instead.
 //   k_finalize  reduces the slices, recomputes the three rows around the peak
 //               for the 3x3 centroid and writes the match record.
 #include <float.h>
@@ -494,6 +497,41 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
   }
 }
 
+// Sum over the T lanes of one FFT group (groups are aligned runs of T lanes;
+// a group is either wholly active or wholly exited).
+template <int T>
+__device__ __forceinline__ float group_sum_f32(float v) {
+  if constexpr (T == 64) {
+    return wave_sum_f32(v);
+  } else {
+#pragma unroll
+    for (int off = T / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+  }
+}
+
+// Pruned inverse: the column sum of |C|^2 over ky for column kx (weight 2 for
+// the columns that stand for their mirror N - kx too), and the stored rows.
+template <int N, int T>
+__device__ __forceinline__ void col_sumsq(const MatchArgs& a, int pair, int w, int t, float csq) {
+  const float tot = group_sum_f32<T>(csq);
+  if (t == 0) a.colsq[(size_t)pair * (N / 2 + 1) + w] = (double)tot * ((w == 0 || w == N / 2) ? 1.0 : 2.0);
+}
+
+template <int N, int T, int E>
+__device__ __forceinline__ void store_column(const MatchArgs& a, float2* dst, int t, const float2 (&v)[E]) {
+  if (a.zlo >= N) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int y = t + e * T;
+      if (y < a.zlo || y >= a.zhi) dst[y] = v[e];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- column pass + whitening
 // Two FFT groups per column pair (used at N = 1024, where a group is a whole
 // wavefront of 16 elements per lane): group 0 transforms column kx, group 1
@@ -569,10 +607,14 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
       if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
       v[e] = cscale(X, gs);
     }
-    fft_wave<N, true>(v, slot, t, tw);
-    float2* dst = Zp + (size_t)w * N;
+    if (a.max_shift > 0) {
+      float csq = 0.0f;
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+      for (int e = 0; e < E; ++e) csq = fmaf(v[e].x, v[e].x, fmaf(v[e].y, v[e].y, csq));
+      col_sumsq<N, T>(a, pair, w, t, csq);
+    }
+    fft_wave<N, true>(v, slot, t, tw);
+    store_column<N, T, E>(a, Zp + (size_t)w * N, t, v);
   }
 }
 
@@ -661,15 +703,23 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
     if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
     v[e] = cscale(X, gs);
   }
+  if (a.max_shift > 0) {
+    float csq = 0.0f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) csq = fmaf(v[e].x, v[e].x, fmaf(v[e].y, v[e].y, csq));
+    col_sumsq<N, T>(a, pair, w, t, csq);
+  }
   wave_lds_sync();  // every lane has read its mirror values
   fft_wave<N, true>(v, slot, t, tw);
-  float2* dst = Zp + (size_t)w * N;
-#pragma unroll
-  for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+  store_column<N, T, E>(a, Zp + (size_t)w * N, t, v);
 }
 
 // ---------------------------------------------------------------- row pass (inverse) + statistics
-template <int N, int R2>
+// PRUNE: the launched row blocks are the first a.nsl_lo and the last
+// a.nsl_inv - a.nsl_lo of the N / R2 blocks of a pair; the peak is searched
+// among wrapped shifts |sx|, |sy| <= a.max_shift; no sums (the background
+// comes from the spectrum).
+template <int N, int R2, bool PRUNE>
 __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NT = R2 / 2, NSL2 = N / R2;
@@ -680,7 +730,11 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   __shared__ int ri1[4];
   __shared__ double rs[4], rq[4];
 
-  const int pair = blockIdx.x / NSL2, slice = blockIdx.x % NSL2, y0 = slice * R2;
+  const int NSP = PRUNE ? a.nsl_inv : NSL2;
+  const int pair = blockIdx.x / NSP, sl = blockIdx.x % NSP;
+  const int slice = (!PRUNE || sl < a.nsl_lo) ? sl : NSL2 - (NSP - sl);
+  const int y0 = slice * R2;
+  const int rmax = PRUNE ? a.max_shift : 0;
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   const float2* Zp = a.Z + (size_t)pair * N * N;
 
@@ -742,6 +796,20 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
       // each lane visits its flat indices in increasing order (row ya, then
       // row yb; rows grow with the iteration), so a strict > keeps the first maximum
       const int ya = y0 + 2 * c, yb = ya + 1;
+      if constexpr (PRUNE) {
+        const bool ina = ya <= rmax || ya >= N - rmax, inb = yb <= rmax || yb >= N - rmax;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int x = t + e * T;
+          if (ina && (x <= rmax || x >= N - rmax)) top2_push_ordered(tp, v[e].x, ya * N + x);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int x = t + e * T;
+          if (inb && (x <= rmax || x >= N - rmax)) top2_push_ordered(tp, v[e].y, yb * N + x);
+        }
+        continue;
+      }
       float ls = 0.0f, lq = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -799,7 +867,7 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
     ip.pad = 0;
     ip.sum = rs[0] + rs[1] + rs[2] + rs[3];
     ip.sumsq = rq[0] + rq[1] + rq[2] + rq[3];
-    a.invpart[(size_t)pair * NSL2 + slice] = ip;
+    a.invpart[(size_t)pair * NSP + sl] = ip;
   }
 }
 
@@ -832,6 +900,15 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
   tp = wave_top2(tp);
   sum = wave_sum(sum);
   sq = wave_sum(sq);
+  if (a.max_shift > 0) {
+    // pruned: sum_x c = C(0) = 0, and by Parseval sum_x c^2 = N^2 sum_k |C(k)|^2
+    // (C here carries the inverse transform's 1/N^2)
+    double cs = 0.0;
+    for (int i = ln; i < N / 2 + 1; i += 64) cs += a.colsq[(size_t)pair * (N / 2 + 1) + i];
+    cs = wave_sum(cs);
+    sum = 0.0;
+    sq = (double)N * (double)N * cs;
+  }
   const int flat = (tp.i1 >= 0 && tp.i1 < N * N) ? tp.i1 : 0;
   const int iy = flat / N, ix = flat % N;
   const float2* Zp = a.Z + (size_t)pair * N * N;
@@ -909,7 +986,9 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   using C = FftCfg<N>;
   constexpr int G = 256 / C::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
   const unsigned P = (unsigned)a.npairs;
-  if (a.nsl_fwd != N / R || a.nsl_inv != N / R2) return hipErrorInvalidValue;
+  if (a.nsl_fwd != N / R) return hipErrorInvalidValue;
+  if (a.max_shift > 0 ? (a.nsl_inv > N / R2 || a.nsl_lo > a.nsl_inv) : (a.nsl_inv != N / R2))
+    return hipErrorInvalidValue;
   {
     TimerScope ts(kt, "k_row_fwd", N, s);
     k_row_fwd<N, R, BUDGET, TRW><<<P * (N / R), 256, 0, s>>>(a);
@@ -929,7 +1008,10 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   {
     TimerScope ts(kt, "k_row_inv", N, s);
-    k_row_inv<N, R2><<<P * (N / R2), 256, 0, s>>>(a);
+    if (a.max_shift > 0)
+      k_row_inv<N, R2, true><<<P * (unsigned)a.nsl_inv, 256, 0, s>>>(a);
+    else
+      k_row_inv<N, R2, false><<<P * (N / R2), 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_finalize", N, s);

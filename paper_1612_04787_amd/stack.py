@@ -1,4 +1,4 @@
-"""Iterative stack alignment with global section affines (Sections III-IV).
+"""Iterative stack alignment: global section affines, then a local-affine mesh (Sections III-IV).
 
 Each pass works at one pyramid level (iscale), coarse to fine:
 
@@ -9,9 +9,12 @@ Each pass works at one pyramid level (iscale), coarse to fine:
      against the model (swim), and refine them to the 0.01 px level (plain
      centroid iteration or Newton steps from the adjoint Jacobian);
   4. refit each section's affine to the window correspondences, weighted by
-     SNR (mir's least squares, global affine only).
+     SNR (mir's least squares, global affine).
 
 A pass can repeat steps 1-4 (the paper iterates until the SNR scores settle).
+align_mesh then replaces the section affines by a triangulated mesh of local
+affines (Section IV): the window centres are the mesh nodes and every
+triangle's affine is the least-squares fit of the matches in its band.
 Every step is a library call on the current stream; Python only sequences
 them and reads a few scalars for reporting.
 """
@@ -36,6 +39,21 @@ def build_pyramid(sw, stack, max_level):
             sw.pyramid(prev[s], out=nxt[s])
         levels.append(nxt)
     return levels
+
+
+def _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac):
+    """swim with refinement; returns (theta_a, records, iterations)."""
+    P = ta.shape[0]
+    n_list = [n] * P
+    it = 0
+    if refine == "adjoint":
+        ta, it, _ = refine_adjoint(sw, images, n_list, ia, ib, ta, tb, params, tol=tol, stop_frac=stop_frac)
+    elif refine == "plain":
+        ta, it, _ = refine_plain(sw, images, n_list, ia, ib, ta, tb, params, tol=tol, stop_frac=stop_frac)
+    prep = sw.prepare(images, n_list, ia, ib, ta, tb)
+    out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=ta.device)
+    sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out)
+    return ta, out, it
 
 
 def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), ks=(3, 3, 3), grid=8, p=0.65,
@@ -69,16 +87,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             images = [src[s] for s in range(S)] + [model[s] for s in range(S)]
             ia, ib, ta, tb = sw.stack_windows(aff, level, grid, hl, wl, 0, S)
             P = ta.shape[0]
-            n_list = [n] * P
-            it = 0
-            if refine == "adjoint":
-                ta, it, _ = refine_adjoint(sw, images, n_list, ia, ib, ta, tb, params, tol=tol,
-                                           stop_frac=stop_frac)
-            elif refine == "plain":
-                ta, it, _ = refine_plain(sw, images, n_list, ia, ib, ta, tb, params, tol=tol, stop_frac=stop_frac)
-            prep = sw.prepare(images, n_list, ia, ib, ta, tb)
-            out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
-            sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out)
+            ta, out, it = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
             status = sw.fit_sections(ta, tb, out, grid * grid, level, aff, min_snr=min_snr)
             torch.cuda.synchronize(dev)
             el = time.perf_counter() - t0
@@ -92,3 +101,47 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             if on_pass is not None:
                 on_pass(rep_d, aff)
     return aff, reports
+
+
+def align_mesh(sw, raw, aff, level=0, n=256, grid=16, k=3, passes=2, p=0.65, refine="adjoint", min_snr=6.0,
+               tol=0.005, stop_frac=0.01, pyr=None, on_pass=None):
+    """Local-affine alignment of a globally aligned [S, H, W] uint8 device
+    stack at one pyramid level (Section IV).  aff [S, 6] float64 (device):
+    the section affines, the starting point and the fallback of triangles
+    without enough weighted matches.  Each pass renders the stack (through
+    the mesh after the first pass), builds the models, matches a grid x grid
+    window layout at the mesh nodes (window A read through its node's
+    triangle) with refinement, and fits every triangle's affine.  Returns
+    (tri_aff [S, 2 (grid-1)^2, 6] float64 device, reports)."""
+    S, H, W = raw.shape
+    if pyr is None:
+        pyr = build_pyramid(sw, raw, level)
+    src = pyr[level]
+    _, hl, wl = src.shape
+    params = make_params(p=p)
+    tri = None
+    reports = []
+    for rep in range(passes):
+        torch.cuda.synchronize(raw.device)
+        t0 = time.perf_counter()
+        if tri is None:
+            rendered = sw.render(src, aff, level)
+            ia, ib, ta, tb = sw.stack_windows(aff, level, grid, hl, wl, 0, S)
+        else:
+            rendered = sw.render_mesh(src, tri, grid, level)
+            ia, ib, ta, tb = sw.mesh_windows(tri, level, grid, hl, wl, 0, S)
+        model = sw.project(rendered, k=k)
+        images = [src[s] for s in range(S)] + [model[s] for s in range(S)]
+        ta, out, it = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
+        tri, status = sw.fit_mesh(ta, tb, out, grid, level, aff, min_snr=min_snr)
+        torch.cuda.synchronize(raw.device)
+        el = time.perf_counter() - t0
+        snr = parse_records(out)["snr"].float()
+        rep_d = dict(level=level, n=n, grid=grid, k=k, repeat=rep, pairs=ta.shape[0], refine_iters=it,
+                     ms=el * 1e3, median_snr=float(snr.median()),
+                     frac_weighted=float((snr >= min_snr).float().mean()),
+                     singular_triangles=int((status != 0).sum()))
+        reports.append(rep_d)
+        if on_pass is not None:
+            on_pass(rep_d, tri)
+    return tri, reports

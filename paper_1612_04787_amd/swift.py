@@ -42,7 +42,7 @@ class Pairs(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("p", C.c_float), ("eps_rel", C.c_float), ("taper_frac", C.c_float),
-                ("centroid_r", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("centroid_r", C.c_int32), ("flags", C.c_int32), ("max_shift", C.c_int32)]
 
 
 REC_BYTES = 64
@@ -78,6 +78,9 @@ def load_library(path: str = LIB_PATH):
     lib.swift_render.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i32, i32, i64, i64, vp]
     lib.swift_stack_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.swift_fit_sections.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp]
+    lib.swift_render_mesh.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i32, i32, i64, i64, vp]
+    lib.swift_mesh_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.swift_fit_mesh.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp, vp]
     lib.swift_profile_enable.argtypes = [vp, C.c_int]
     lib.swift_profile_read.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32)]
     lib.swift_last_error.restype = C.c_char_p
@@ -107,8 +110,8 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
-def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0):
-    return Params(float(p), float(eps_rel), float(taper_frac), int(centroid_r), int(flags), 0)
+def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0, max_shift=0):
+    return Params(float(p), float(eps_rel), float(taper_frac), int(centroid_r), int(flags), int(max_shift))
 
 
 def parse_records(rec: torch.Tensor) -> dict:
@@ -384,6 +387,60 @@ class Swift:
                                            _ptr(recs_raw), int(level), float(min_snr), _ptr(aff), _ptr(status),
                                            self.stream()))
         return status
+
+    # ---- local-affine triangle mesh: tri_aff [S, 2 (grid-1)^2, 6] float64 (device)
+    @staticmethod
+    def mesh_triangles(grid):
+        return 2 * (grid - 1) * (grid - 1)
+
+    def render_mesh(self, src, tri_aff, grid, level, out_hw=None, out=None):
+        """mir texture mapping of a [S, H, W] uint8 device stack: every output
+        pixel through the affine of its triangle in the mesh of the output
+        frame."""
+        assert src.dtype == torch.uint8 and src.dim() == 3 and src.stride(2) == 1
+        S, H, W = src.shape
+        assert tri_aff.dtype == torch.float64 and tri_aff.is_contiguous()
+        assert tri_aff.shape == (S, self.mesh_triangles(grid), 6)
+        if out is None:
+            oh, ow = out_hw if out_hw is not None else (H, W)
+            out = torch.empty((S, oh, ow), dtype=torch.uint8, device=src.device)
+        _check(self.lib.swift_render_mesh(self.h, _ptr(src), S, H, W, src.stride(1), src.stride(0), _ptr(tri_aff),
+                                          int(grid), int(level), _ptr(out), out.shape[1], out.shape[2],
+                                          out.stride(1), out.stride(0), self.stream()))
+        return out
+
+    def mesh_windows(self, tri_aff, level, grid, h_l, w_l, img_a0, img_b0):
+        """Window pairs at the mesh nodes, window A through its node's
+        triangle: (img_a, img_b [P] int32, theta_a, theta_b [P, 8] float32)."""
+        S = tri_aff.shape[0]
+        assert tri_aff.dtype == torch.float64 and tri_aff.is_contiguous()
+        assert tri_aff.shape == (S, self.mesh_triangles(grid), 6)
+        P = S * grid * grid
+        ta = torch.empty((P, 8), dtype=torch.float32, device=self.device)
+        tb = torch.empty((P, 8), dtype=torch.float32, device=self.device)
+        ia = torch.empty(P, dtype=torch.int32, device=self.device)
+        ib = torch.empty(P, dtype=torch.int32, device=self.device)
+        _check(self.lib.swift_mesh_windows(self.h, S, _ptr(tri_aff), int(level), int(grid), int(h_l), int(w_l),
+                                           int(img_a0), int(img_b0), _ptr(ta), _ptr(tb), _ptr(ia), _ptr(ib),
+                                           self.stream()))
+        return ia, ib, ta, tb
+
+    def fit_mesh(self, theta_a, theta_b, recs_raw, grid, level, aff, min_snr=6.0, tri_aff=None, status=None):
+        """Per-triangle affines [S, T, 6] float64 from the node matches (pairs
+        s grid^2 + k); singular triangles take their section's affine aff
+        [S, 6].  Returns (tri_aff, status [S, T] int32)."""
+        S = aff.shape[0]
+        T = self.mesh_triangles(grid)
+        assert aff.dtype == torch.float64 and aff.is_contiguous() and aff.shape == (S, 6)
+        assert theta_a.shape[0] == S * grid * grid and recs_raw.shape[0] == S * grid * grid
+        if tri_aff is None:
+            tri_aff = torch.empty((S, T, 6), dtype=torch.float64, device=self.device)
+        if status is None:
+            status = torch.empty((S, T), dtype=torch.int32, device=self.device)
+        _check(self.lib.swift_fit_mesh(self.h, S, int(grid), _ptr(theta_a), _ptr(theta_b), _ptr(recs_raw),
+                                       int(level), float(min_snr), _ptr(aff), _ptr(tri_aff), _ptr(status),
+                                       self.stream()))
+        return tri_aff, status
 
     def snr(self, surfaces, params=None):
         """Peak, SNR and centroid of [B, n, n] float32 device surfaces."""

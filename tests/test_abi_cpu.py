@@ -62,4 +62,7 @@ def test_validation_without_gpu(lib):
     assert lib.swift_render(None, None, 1, 1, 1, 1, 1, None, 0, None, 1, 1, 1, 1, None) == -1
     assert lib.swift_stack_windows(None, 1, None, 0, 8, 64, 64, 0, 1, None, None, None, None, None) == -1
     assert lib.swift_fit_sections(None, 1, 64, None, None, None, 0, 6.0, None, None, None) == -1
+    assert lib.swift_render_mesh(None, None, 1, 1, 1, 1, 1, None, 8, 0, None, 1, 1, 1, 1, None) == -1
+    assert lib.swift_mesh_windows(None, 1, None, 0, 8, 64, 64, 0, 1, None, None, None, None, None) == -1
+    assert lib.swift_fit_mesh(None, 1, 8, None, None, None, 0, 6.0, None, None, None, None) == -1
     assert b"ctx" in lib.swift_last_error()

@@ -77,6 +77,29 @@ def test_headline_batch_4096_pairs_512(ctx):
         r = O.match_pair(sub[s - lo], ref_o, th, th, n, O.Params(p=0.65))
         e = compare(gpu_record(res, int(i)), r, n, tag="headline pair %d" % i)
         print("   pair %d (section %d window %d):" % (i, s, w), e, flush=True)
+    # the same batch with the pruned inverse at the benchmark's radius n/8
+    print("case headline pruned r=%d" % (n // 8), flush=True)
+    rp = ctx.match_batch(images, n_list, ia, ib, ta, tb, sw.make_params(p=0.65, max_shift=n // 8))
+    torch.cuda.synchronize()
+    _check_all_records(rp, n, P)
+    assert bool((rp["mean"] == 0).all())
+    for i in picks:
+        s, w = int(i) // len(cen), int(i) % len(cen)
+        cx, cy = cen[w]
+        x0, y0, x1, y1 = _crop(cx, cy, n, size, size)
+        lo, hi = max(0, s - k), min(S, s + k + 1)
+        sub = stack[lo:hi, y0:y1, x0:x1].cpu().numpy()
+        ref_o = O.project(sub, s - lo, k)
+        th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+        r = O.match_pair(sub[s - lo], ref_o, th, th, n, O.Params(p=0.65, max_shift=n // 8))
+        e = compare(gpu_record(rp, int(i)), r, n, tag="pruned pair %d" % i)
+        print("   pruned pair %d:" % i, e, flush=True)
+    # every shift of this batch lies well inside the radius: the pruned records
+    # agree with the full ones on all pairs (peak exact, background to rounding)
+    same = (rp["ix"] == res["ix"]) & (rp["iy"] == res["iy"])
+    assert float(same.float().mean()) > 0.999
+    assert float((rp["dx"] - res["dx"])[same].abs().max()) <= 0.01
+    assert float(((rp["snr"] - res["snr"]) / res["snr"]).abs().max()) <= 1e-3
 
 
 def test_section_pair_256_windows_1024(ctx):
