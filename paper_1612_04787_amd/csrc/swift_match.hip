@@ -518,9 +518,9 @@ __device__ __forceinline__ void col_sumsq(const MatchArgs& a, int pair, int w, i
   if (t == 0) a.colsq[(size_t)pair * (N / 2 + 1) + w] = (double)tot * ((w == 0 || w == N / 2) ? 1.0 : 2.0);
 }
 
-template <int N, int T, int E>
+template <int N, int T, int E, bool PRUNE>
 __device__ __forceinline__ void store_column(const MatchArgs& a, float2* dst, int t, const float2 (&v)[E]) {
-  if (a.zlo >= N) {
+  if (!PRUNE || a.zlo >= N) {
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
   } else {
@@ -537,7 +537,7 @@ __device__ __forceinline__ void store_column(const MatchArgs& a, float2* dst, in
 // wavefront of 16 elements per lane): group 0 transforms column kx, group 1
 // its mirror N - kx and hands it over through LDS behind a workgroup barrier;
 // group 0 then splits, whitens and inverse-transforms column kx.
-template <int N>
+template <int N, bool PRUNE>
 __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
@@ -607,14 +607,14 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
       if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
       v[e] = cscale(X, gs);
     }
-    if (a.max_shift > 0) {
+    if constexpr (PRUNE) {
       float csq = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) csq = fmaf(v[e].x, v[e].x, fmaf(v[e].y, v[e].y, csq));
       col_sumsq<N, T>(a, pair, w, t, csq);
     }
     fft_wave<N, true>(v, slot, t, tw);
-    store_column<N, T, E>(a, Zp + (size_t)w * N, t, v);
+    store_column<N, T, E, PRUNE>(a, Zp + (size_t)w * N, t, v);
   }
 }
 
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
 // columns N - kx and kx, splits, whitens and inverse-transforms column kx,
 // exchanging the mirror column through its own LDS slot (no block barrier,
 // no idle groups).  Same results as k_col.
-template <int N>
+template <int N, bool PRUNE>
 __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T;
@@ -703,7 +703,7 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
     if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
     v[e] = cscale(X, gs);
   }
-  if (a.max_shift > 0) {
+  if constexpr (PRUNE) {
     float csq = 0.0f;
 #pragma unroll
     for (int e = 0; e < E; ++e) csq = fmaf(v[e].x, v[e].x, fmaf(v[e].y, v[e].y, csq));
@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   }
   wave_lds_sync();  // every lane has read its mirror values
   fft_wave<N, true>(v, slot, t, tw);
-  store_column<N, T, E>(a, Zp + (size_t)w * N, t, v);
+  store_column<N, T, E, PRUNE>(a, Zp + (size_t)w * N, t, v);
 }
 
 // ---------------------------------------------------------------- row pass (inverse) + statistics
@@ -1001,9 +1001,15 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
     TimerScope ts(kt, "k_col", N, s);
     if constexpr (N <= 512) {
       constexpr int NW2 = (N / 2 + 1 + G - 1) / G;
-      k_col_pair<N><<<P * NW2, 256, 0, s>>>(a);
+      if (a.max_shift > 0)
+        k_col_pair<N, true><<<P * NW2, 256, 0, s>>>(a);
+      else
+        k_col_pair<N, false><<<P * NW2, 256, 0, s>>>(a);
     } else {
-      k_col<N><<<P * NW, 256, 0, s>>>(a);
+      if (a.max_shift > 0)
+        k_col<N, true><<<P * NW, 256, 0, s>>>(a);
+      else
+        k_col<N, false><<<P * NW, 256, 0, s>>>(a);
     }
   }
   {
