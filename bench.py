@@ -10,7 +10,10 @@ before the timed region.
 
 Prints one JSON line (metric, value in pairs/s, roofline of the dominant
 kernel from live HIP-event timing, and the FP64 oracle's throughput on a
-bounded sample of the same pairs on the host cores).
+bounded sample of the same pairs on the host cores).  Further blocks of the
+line: the same step with a pruned inverse (search radius 64 px), plain vs
+adjoint refinement to 0.01 px, the iterative stack loop, the local-affine
+mesh on a bent stack, and ragged multi-level batches.
 """
 from __future__ import annotations
 
@@ -371,7 +374,7 @@ def mesh_block(ctx, dev, sections=MESH_SECTIONS, size=SIZE, grid=MESH_GRID, n=ME
     return res, sample
 
 
-def cpu_baseline_mesh(sample, n_px=1 << 21):
+def cpu_baseline_mesh(sample, n_px=1 << 23):
     """The oracle's mesh render on a bounded sample of pixels of one section
     (one process, FP64 NumPy), in Mpixel/s."""
     import numpy as np
