@@ -36,4 +36,7 @@ from .swift_oracle import (  # noqa: F401
     render_mesh,
     render_mesh_at,
     mesh_windows,
+    pearson_surface,
+    pearson_peak,
+    pearson_pair,
 )

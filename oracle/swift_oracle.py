@@ -690,3 +690,87 @@ def mesh_windows(tri_aff, level, n, grid, h_l, w_l):
         ta[k] = [rx, ry, aff[0], aff[1], cx - rx, aff[3], aff[4], cy - ry]
         tb[k] = [px, py, 1, 0, 0, 0, 1, 0]
     return ta, tb
+
+
+# ---------------------------------------------------------------------------
+# Pearson-normalised correlation (Section II: the NCC of other registration
+# codes; an FFT correlation gives it after a cumulative-area correction).
+# Design reading: the template is the central m x m part of window A, m = n/2,
+# and it is scored against every placement inside window B, shifts |sx|, |sy|
+# <= R = n/4 (no placement wraps around), by the Pearson correlation
+# coefficient of the two m x m patches.  The peak and its record follow the
+# whitened match: first maximum in row-major order of the wrapped n x n index,
+# Z score over the (2R+1)^2 placements, 3 x 3 centroid with weights
+# max(gamma - mean, 0) (placements outside the search range weigh 0).
+# ---------------------------------------------------------------------------
+def pearson_surface(a, f):
+    """gamma [2R+1, 2R+1] (row sy + R, column sx + R) of the central n/2 x n/2
+    template of the n x n window a against window f; a placement whose patch
+    (or the template) is constant gets 0.  Returns (gamma, template energy)."""
+    n = a.shape[0]
+    m, c0, R = n // 2, n // 4, n // 4
+    t = np.asarray(a, dtype=np.float64)[c0:c0 + m, c0:c0 + m]
+    tc = t - t.mean()
+    st = float(np.sum(tc * tc))
+    f = np.asarray(f, dtype=np.float64)
+    g = np.zeros((2 * R + 1, 2 * R + 1))
+    for sy in range(-R, R + 1):
+        for sx in range(-R, R + 1):
+            p = f[c0 + sy:c0 + sy + m, c0 + sx:c0 + sx + m]
+            pc = p - p.mean()
+            sp = float(np.sum(pc * pc))
+            if st > 0 and sp > 0:
+                g[sy + R, sx + R] = float(np.sum(tc * pc)) / np.sqrt(st * sp)
+    return g, st
+
+
+def pearson_peak(g, n, st):
+    """Record of a Pearson surface (see pearson_surface): integer peak, Z
+    score over the placements, 3 x 3 centroid, near-tie and degenerate bits."""
+    R = n // 4
+    full = np.full((n, n), -np.inf)
+    for sy in range(-R, R + 1):
+        for sx in range(-R, R + 1):
+            full[sy % n, sx % n] = g[sy + R, sx + R]
+    flat = int(np.argmax(full.ravel()))
+    iy, ix = divmod(flat, n)
+    sx, sy = _wrap(ix, n), _wrap(iy, n)
+    peak = float(full[iy, ix])
+    mu = float(g.mean())
+    sd = float(np.sqrt(np.mean((g - mu) ** 2)))
+    status = 0
+    snr = (peak - mu) / sd if sd > 0 else 0.0
+    if not (st > 0 and sd > 0):
+        status |= STATUS_DEGENERATE
+        snr = 0.0
+    rest = np.delete(full.ravel(), flat)
+    second = float(np.max(rest))
+    if peak - second <= NEAR_TIE_REL * abs(peak):
+        status |= STATUS_NEAR_TIE
+    sw = swx = swy = 0.0
+    for ddy in (-1, 0, 1):
+        for ddx in (-1, 0, 1):
+            if abs(sx + ddx) <= R and abs(sy + ddy) <= R:
+                wv = max(float(g[sy + ddy + R, sx + ddx + R]) - mu, 0.0)
+                sw += wv
+                swx += wv * ddx
+                swy += wv * ddy
+    dx = sx + (swx / sw if sw > 0 else 0.0)
+    dy = sy + (swy / sw if sw > 0 else 0.0)
+    return dict(ix=ix, iy=iy, sx=sx, sy=sy, dx=dx, dy=dy, peak=peak, mean=mu, std=sd, snr=snr,
+                status=status, second=second)
+
+
+def pearson_pair(imgA, imgB, thetaA, thetaB, n, return_surface=False):
+    """Pearson-normalised match of one window pair: gather both windows
+    (bilinear, clamp to edge; no taper, no whitening), then pearson_surface
+    and pearson_peak."""
+    a, clA = gather(imgA, thetaA, n)
+    f, clB = gather(imgB, thetaB, n)
+    g, st = pearson_surface(a, f)
+    rec = pearson_peak(g, n, st)
+    if clA or clB:
+        rec["status"] |= STATUS_CLAMPED
+    if return_surface:
+        rec["surface"] = g
+    return rec

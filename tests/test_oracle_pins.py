@@ -759,3 +759,76 @@ def test_mesh_windows_reduce_to_stack_windows():
             t = 2 * (cj * (grid - 1) + ci) + (1 if (i == grid - 1 and j == grid - 1) else 0)
             k = j * grid + i
             np.testing.assert_array_equal(ta[k, [2, 3, 5, 6]], tri[t, [0, 1, 3, 4]])
+
+
+# --------------------------------------------------------------------------- Pearson-normalised correlation
+def test_pearson_matches_numpy_corrcoef():
+    rng = np.random.default_rng(41)
+    for n in (16, 32):
+        a = rng.normal(0, 1, (n, n))
+        f = rng.normal(0, 1, (n, n))
+        g, st = O.pearson_surface(a, f)
+        m, c0, R = n // 2, n // 4, n // 4
+        t = a[c0:c0 + m, c0:c0 + m].ravel()
+        for sy in range(-R, R + 1):
+            for sx in range(-R, R + 1):
+                p = f[c0 + sy:c0 + sy + m, c0 + sx:c0 + sx + m].ravel()
+                assert abs(g[sy + R, sx + R] - np.corrcoef(t, p)[0, 1]) < 1e-12
+        assert abs(st - np.sum((t - t.mean()) ** 2)) < 1e-9
+
+
+def test_pearson_equals_fft_correlation_with_cumulative_area_correction():
+    # Section II: an FFT correlation becomes the Pearson coefficient after a
+    # cumulative-area correction.  Numerator: circular correlation of the
+    # zero-padded, mean-free template with the window; denominator: the
+    # patch energies from summed-area tables of f and f^2.
+    rng = np.random.default_rng(42)
+    n = 32
+    m, c0, R = n // 2, n // 4, n // 4
+    a = rng.integers(0, 256, (n, n)).astype(np.float64)
+    f = rng.integers(0, 256, (n, n)).astype(np.float64)
+    g, _ = O.pearson_surface(a, f)
+    tz = np.zeros((n, n))
+    t = a[c0:c0 + m, c0:c0 + m]
+    tz[c0:c0 + m, c0:c0 + m] = t - t.mean()
+    c = np.real(np.fft.ifft2(np.conj(np.fft.fft2(tz)) * np.fft.fft2(f)))
+    sat1 = np.zeros((n + 1, n + 1))
+    sat2 = np.zeros((n + 1, n + 1))
+    sat1[1:, 1:] = np.cumsum(np.cumsum(f, 0), 1)
+    sat2[1:, 1:] = np.cumsum(np.cumsum(f * f, 0), 1)
+
+    def box(S, y, x):
+        return S[y + m, x + m] - S[y, x + m] - S[y + m, x] + S[y, x]
+
+    st = np.sum(tz * tz)
+    for sy in range(-R, R + 1):
+        for sx in range(-R, R + 1):
+            y, x = c0 + sy, c0 + sx
+            e1, e2 = box(sat1, y, x), box(sat2, y, x)
+            v = e2 - e1 * e1 / (m * m)
+            ref = c[sy % n, sx % n] / np.sqrt(st * v)
+            assert abs(g[sy + R, sx + R] - ref) < 1e-9
+
+
+def test_pearson_exact_shift_sign_and_invariance():
+    rng = np.random.default_rng(43)
+    img = rng.integers(0, 256, (200, 200)).astype(np.float64)
+    n = 64
+    thA = np.array([100, 100, 1, 0, 0, 0, 1, 0], np.float64)
+    # window B sits 5 px right and 3 px up: its content is A's moved by d = (-5, 3)
+    thB = np.array([105, 97, 1, 0, 0, 0, 1, 0], np.float64)
+    r = O.pearson_pair(img, img, thA, thB, n, return_surface=True)
+    assert (r["sx"], r["sy"]) == (-5, 3) and abs(r["peak"] - 1.0) < 1e-12
+    assert abs(r["dx"] + 5) < 0.5 and abs(r["dy"] - 3) < 0.5 and r["snr"] > 10
+    g = r["surface"]
+    assert np.all(np.abs(g) <= 1 + 1e-12)
+    # an affine intensity map of either image leaves every coefficient unchanged,
+    # a negative one flips the sign
+    r2 = O.pearson_pair(img, 3.5 * img - 40, thA, thB, n, return_surface=True)
+    np.testing.assert_allclose(r2["surface"], g, atol=1e-12)
+    r3 = O.pearson_pair(img, 255 - img, thA, thB, n, return_surface=True)
+    np.testing.assert_allclose(r3["surface"], -g, atol=1e-12)
+    assert abs(r3["surface"][3 + n // 4, -5 + n // 4] + 1.0) < 1e-12
+    # a constant window is degenerate
+    r4 = O.pearson_pair(np.full((200, 200), 9.0), img, thA, thB, n)
+    assert r4["status"] & STATUS_DEGENERATE and r4["snr"] == 0.0
