@@ -11,7 +11,8 @@ before the timed region.
 Prints one JSON line (metric, value in pairs/s, roofline of the dominant
 kernel from live HIP-event timing, and the FP64 oracle's throughput on a
 bounded sample of the same pairs on the host cores).  Further blocks of the
-line: the same step with a pruned inverse (search radius 64 px), plain vs
+line: the same step with a pruned inverse (search radius 64 px), the same
+pairs scored by Pearson-normalised correlation, plain vs
 adjoint refinement to 0.01 px, the iterative stack loop, the local-affine
 mesh on a bent stack, and ragged multi-level batches.
 """
@@ -305,6 +306,51 @@ def stack_loop(ctx, stack, warps, refine="adjoint"):
                                                              "neighbour_before": n0, "neighbour_after": n1})
 
 
+# --------------------------------------------------------------------------- Pearson-normalised correlation
+def pearson_block(ctx, sw, stack, refs, table, images, pairs, res_w, args, prof_steps):
+    """The headline batch scored by Pearson-normalised correlation (the
+    central 256^2 template of each raw window against every placement within
+    +-128 px in the model window; FFT correlation plus the cumulative-area
+    correction).  Timed like the headline step (projection included); match
+    quality set against the whitened records of the same pairs."""
+    import torch
+    P = pairs.n_pairs
+    prm = sw.make_params(flags=sw.FLAG_PEARSON)
+    need, _ = ctx.workspace_size(pairs, prm)
+    ws = ctx.workspace(need)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=stack.device)
+
+    def step():
+        ctx.project(stack, k=K_PROJ, out=refs)
+        ctx.match_batch_raw(table, len(images), pairs, prm, out, None, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    ctx.profile(True)
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    kp = {name: dict(launches=cnt, avg_ms=tot / cnt) for name, (cnt, tot) in ctx.profile_read().items()}
+    ctx.profile(False)
+    r = sw.parse_records(out)
+    same = (r["ix"] == res_w["ix"]) & (r["iy"] == res_w["iy"])
+    dd = torch.maximum((r["dx"] - res_w["dx"]).abs(), (r["dy"] - res_w["dy"]).abs())
+    del ws
+    # single-shot shifts of both scores sit near whole pixels (3 x 3 centroid),
+    # so they are compared within one pixel; the SNR is the paper's comparison
+    return dict(template_px=N // 2, range_px=N // 4, ms_per_step=ms, pairs_per_s=P / (ms / 1e3),
+                workspace_gb=need / 1e9, kernels=kp, same_peak_frac=float(same.float().mean()),
+                frac_shift_within_1px=float((dd <= 1.0).float().mean()),
+                median_abs_shift_diff_px=float(dd.median()), median_peak_coefficient=float(r["peak"].median()),
+                median_snr=float(r["snr"].median()), median_snr_whitened=float(res_w["snr"].median()))
+
+
 # --------------------------------------------------------------------------- local-affine mesh
 MESH_SECTIONS, MESH_GRID, MESH_N, MESH_BEND = 16, 16, 256, 3.0
 # FP64 operations per rendered pixel in the render definition (contraction
@@ -406,6 +452,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default row-count plan (no tuning launches)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the local-affine mesh run")
     ap.add_argument("--no-prune", action="store_true", help="skip the pruned-inverse (search radius) variant")
+    ap.add_argument("--no-pearson", action="store_true", help="skip the Pearson-normalised correlation variant")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -563,6 +610,13 @@ def main():
     }
     if pruned is not None:
         line["pruned"] = pruned
+    if not args.no_pearson:
+        log("pearson: the same batch scored by Pearson-normalised correlation ...")
+        line["pearson"] = pearson_block(ctx, sw, stack, refs, table, images, pairs, res, args, prof_steps)
+        pb = line["pearson"]
+        log("pearson: %.3f ms/step (%.0f pairs/s), same peak as whitened %.4f, median SNR %.1f (whitened %.1f)"
+            % (pb["ms_per_step"], pb["pairs_per_s"], pb["same_peak_frac"], pb["median_snr"],
+               pb["median_snr_whitened"]))
     if not args.no_refine:
         log("refinement: plain vs batched + adjoint to 0.01 px ...")
         del ws

@@ -98,7 +98,23 @@ typedef struct {
  *             SWIFT_FLAG_JAC_TRANSLATION: swift_centroid_jacobian computes
  *               only the translation columns (tx, ty) of the Jacobian, the
  *               ones the Newton refinement step uses, and writes zeros in
- *               the other four (fewer per-pixel sums); other calls ignore it.
+ *               the other four (fewer per-pixel sums); other calls ignore it;
+ *             SWIFT_FLAG_PEARSON: Pearson-normalised correlation instead of
+ *               the whitened match (Section II: NCC via an FFT correlation
+ *               and a cumulative-area correction).  The central n/2 x n/2
+ *               template of window A is scored against every placement
+ *               inside window B, shifts |sx|, |sy| <= n/4, by the Pearson
+ *               coefficient of the two patches (in [-1, 1]; 0 where the patch
+ *               of B is constant).  Windows are gathered without taper; p,
+ *               eps_rel and taper_frac are ignored and max_shift must be 0.
+ *               The record's peak is the best coefficient (first row-major
+ *               maximum of the wrapped index, as usual), mean/std/snr are
+ *               taken over the (n/2+1)^2 placements, and the centroid weighs
+ *               max(coefficient - mean, 0) over the placements among the 3x3
+ *               neighbours (curvatures 0 when a neighbour lies beyond the
+ *               range).  A constant template is degenerate.  surfaces and
+ *               saved must be NULL; the adjoint entry points reject it
+ *               (SWIFT_E_UNSUPPORTED).
  *  max_shift  radius r >= 0 of the expected-shift neighbourhood (the pruned
  *             inverse FFT, an algorithmic speed-up named in Section V).  For a
  *             window edge n with 0 < r < n/2 the integer peak is the first
@@ -112,6 +128,7 @@ typedef struct {
  *             the batch, `surfaces` must be NULL. */
 #define SWIFT_FLAG_CONCURRENT_SIZES 1
 #define SWIFT_FLAG_JAC_TRANSLATION 2
+#define SWIFT_FLAG_PEARSON 4
 typedef struct {
   float p;
   float eps_rel;

@@ -6,6 +6,7 @@ this package is its thin Python binding.
 from .swift import (  # noqa: F401
     FLAG_CONCURRENT_SIZES,
     FLAG_JAC_TRANSLATION,
+    FLAG_PEARSON,
     SIZES,
     Swift,
     SwiftError,

@@ -153,7 +153,7 @@ struct GroupLayout {
   int count = 0;
   int first = 0;  // index of the group's first pair
   // forward
-  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, colsq = 0;
+  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, colsq = 0, ncc_rows = 0, ncc_var = 0;
   // adjoint
   size_t y = 0, dpart = 0, rpart = 0;
   // saved state (offsets into the saved buffer)
@@ -183,7 +183,8 @@ size_t ncolwg(int n) {
   return (size_t)((n / 2 + 1 + ipw - 1) / ipw);
 }
 
-Layout make_layout(const swift_pairs* pairs) {
+// pearson: room for the Pearson row sums and patch energies.
+Layout make_layout(const swift_pairs* pairs, bool pearson = false) {
   Layout L;
   const size_t base = align256(SWIFT_NSIZES * kTaperSlot);
   L.taper = 0;
@@ -207,6 +208,12 @@ Layout make_layout(const swift_pairs* pairs) {
     fo += align256(P * (size_t)max(inv_blocks_n(g.n, false), inv_blocks_n(g.n, true)) * sizeof(InvPart));
     g.colsq = fo;
     fo += align256(P * (n / 2 + 1) * sizeof(double));
+    if (pearson) {
+      g.ncc_rows = fo;
+      fo += align256(P * n * (n / 2 + 1) * sizeof(float2));
+      g.ncc_var = fo;
+      fo += align256(P * (n / 2 + 1) * (n / 2 + 1) * sizeof(float));
+    }
     g.y = bo;
     bo += align256(P * n * n * sizeof(float2));
     g.dpart = bo;
@@ -250,17 +257,24 @@ int check_params(const swift_params* pr) {
   if (!(pr->taper_frac >= 0.0f && pr->taper_frac <= 1.0f))
     return fail(SWIFT_E_INVAL, "taper_frac must be in [0, 1] (got %g)", pr->taper_frac);
   if (pr->centroid_r != 1) return fail(SWIFT_E_UNSUPPORTED, "centroid_r must be 1 (got %d)", pr->centroid_r);
-  if (pr->flags & ~(SWIFT_FLAG_CONCURRENT_SIZES | SWIFT_FLAG_JAC_TRANSLATION))
+  if (pr->flags & ~(SWIFT_FLAG_CONCURRENT_SIZES | SWIFT_FLAG_JAC_TRANSLATION | SWIFT_FLAG_PEARSON))
     return fail(SWIFT_E_UNSUPPORTED, "unknown flags %#x", pr->flags);
   if (pr->max_shift < 0) return fail(SWIFT_E_INVAL, "max_shift must be >= 0 (got %d)", pr->max_shift);
+  if ((pr->flags & SWIFT_FLAG_PEARSON) && pr->max_shift != 0)
+    return fail(SWIFT_E_INVAL, "max_shift must be 0 with SWIFT_FLAG_PEARSON (its range is n/4)");
   return SWIFT_OK;
 }
+
+bool pearson_mode(const swift_params* pr) { return (pr->flags & SWIFT_FLAG_PEARSON) != 0; }
 
 // The search radius restricts window edge n only when 0 < r < n/2.
 bool prunes(const swift_params* pr, int n) { return pr->max_shift > 0 && pr->max_shift < n / 2; }
 
-// Surfaces are whole only without a search radius.
-int check_surfaces(const swift_pairs* pairs, const swift_params* pr, const float* surfaces) {
+// Surfaces are whole only without a search radius; the Pearson mode keeps
+// neither surfaces nor adjoint state.
+int check_surfaces(const swift_pairs* pairs, const swift_params* pr, const float* surfaces, const void* saved) {
+  if (pearson_mode(pr) && (surfaces || saved))
+    return fail(SWIFT_E_INVAL, "surfaces and saved must be NULL with SWIFT_FLAG_PEARSON");
   if (!surfaces) return SWIFT_OK;
   for (int i = 0; i < SWIFT_NSIZES; ++i)
     if (pairs->size_count[i] > 0 && prunes(pr, kSizes[i]))
@@ -349,7 +363,7 @@ int swift_workspace_size(swift_ctx* ctx, const swift_pairs* pairs, const swift_p
   if (rc) return rc;
   rc = check_params(params);
   if (rc) return rc;
-  const Layout L = make_layout(pairs);
+  const Layout L = make_layout(pairs, pearson_mode(params));
   *ws_bytes = L.total;
   if (saved_bytes) *saved_bytes = L.saved;
   return ok();
@@ -371,7 +385,7 @@ static int check_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, 
   }
   if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
   if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
-  const Layout L = make_layout(pairs);
+  const Layout L = make_layout(pairs, pearson_mode(params));
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
   return SWIFT_OK;
@@ -384,7 +398,8 @@ static int check_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, 
 static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
                          const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
                          hipStream_t stream, bool concurrent, KernelTimer* kt) {
-  const Layout L = make_layout(pairs);
+  const bool pearson = pearson_mode(params);
+  const Layout L = make_layout(pairs, pearson);
   int groups = 0;
   for (int i = 0; i < SWIFT_NSIZES; ++i) groups += L.g[i].count > 0 ? 1 : 0;
   concurrent = concurrent && groups > 1;
@@ -428,7 +443,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     float2* tau = (float2*)(base + L.taper + i * kTaperSlot);
     float* taper = (float*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2));
     TaperInfo* tinfo = (TaperInfo*)(base + L.taper + i * kTaperSlot + 1024 * sizeof(float2) + 1024 * sizeof(float));
-    e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, s);
+    e = launch_taper(g.n, params->taper_frac, tau, taper, tinfo, s, pearson);
     if (e != hipSuccess) return hip_fail(e, "taper launch");
     MatchArgs a;
     a.imgs = imgs;
@@ -457,12 +472,17 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.max_shift = 0;
     a.nsl_lo = a.nsl_inv;
     a.zlo = a.zhi = g.n;
-    if (prunes(params, g.n)) {
+    a.pearson = pearson ? 1 : 0;
+    a.ncc_rows = pearson ? (float2*)(base + g.ncc_rows) : nullptr;
+    a.ncc_var = pearson ? (float*)(base + g.ncc_var) : nullptr;
+    if (pearson) a.p = 0.0f;
+    const int radius = pearson ? g.n / 4 : params->max_shift;
+    if (radius > 0 && radius < g.n / 2) {
       // rows |y| <= r + 1 (the centroid reads one row past the window),
       // rounded out to whole inverse row blocks of R2 rows
-      const int full = a.nsl_inv, R2 = g.n / full, rr = params->max_shift + 1;
+      const int full = a.nsl_inv, R2 = g.n / full, rr = radius + 1;
       const int lo = rr / R2 + 1, hs = (g.n - rr) / R2;
-      a.max_shift = params->max_shift;
+      a.max_shift = radius;
       if (lo < hs) {
         a.nsl_lo = lo;
         a.nsl_inv = lo + (full - hs);
@@ -491,7 +511,7 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   bool empty;
   int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
   if (rc || empty) return rc;
-  rc = check_surfaces(pairs, params, surfaces);
+  rc = check_surfaces(pairs, params, surfaces, saved);
   if (rc) return rc;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
@@ -505,7 +525,7 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   bool empty;
   int rc = check_match(ctx, imgs, n_imgs, pairs, params, out, ws, ws_bytes, &empty);
   if (rc || empty) return rc;
-  rc = check_surfaces(pairs, params, surfaces);
+  rc = check_surfaces(pairs, params, surfaces, saved);
   if (rc) return rc;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
@@ -575,6 +595,8 @@ static int run_backward(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
                         float* g_theta_a, float* g_theta_b, float* peak_hess, float* jac, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   const bool cj = jac != nullptr;
+  if (pearson_mode(params))
+    return fail(SWIFT_E_UNSUPPORTED, "the adjoint of the Pearson-normalised match is not implemented");
   const Layout L = make_layout(pairs);
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);

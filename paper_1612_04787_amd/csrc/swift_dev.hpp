@@ -26,6 +26,17 @@ __device__ __forceinline__ float taper_at(int i, int n, int L) {
   return 0.5f * (1.0f - cospif(((float)m + 0.5f) / (float)L));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ float wave_incl_scan_f32(float v) {
+  const int ln = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const float u = __shfl_up(v, off, 64);
+    if (ln >= off) v += u;
+  }
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -101,10 +112,12 @@ __device__ __forceinline__ Top2 wave_top2(Top2 a) {
 // nb[dy+1][dx+1] of the peak (nb[1][1] is replaced by the peak value).
 // Z-score over the whole surface (population std, FP64); centroid weights
 // max(c - mean, 0); integer shifts wrapped to [-n/2, n/2).
-__device__ inline swift_match make_record(int n, Top2 tp, double sum, double sq, float (*nb)[3], int flags) {
+// count: number of surface entries the sums cover (n^2 unless given).
+__device__ inline swift_match make_record(int n, Top2 tp, double sum, double sq, float (*nb)[3], int flags,
+                                          double count = 0.0) {
   const int flat = (tp.i1 >= 0 && tp.i1 < n * n) ? tp.i1 : 0;
   const int iy = flat / n, ix = flat % n;
-  const double M = (double)n * (double)n;
+  const double M = count > 0.0 ? count : (double)n * (double)n;
   const double mu = sum / M;
   const double var = fmax(sq / M - mu * mu, 0.0);
   const double sd = sqrt(var);

@@ -76,6 +76,13 @@ struct MatchArgs {
   // zlo = zhi = N, nsl_lo = nsl_inv.
   int32_t max_shift, zlo, zhi, nsl_lo;
   double* colsq;
+  // Pearson mode (max_shift = N/4, p = 0, box taper tables): ncc_rows
+  // [P][N][N/2+1] holds window B's row sums (f', f'^2) over the template
+  // width at every placement, ncc_var [P][N/2+1][N/2+1] the patch energy
+  // sum (f - mean)^2 of every placement.
+  int32_t pearson;
+  float2* ncc_rows;
+  float* ncc_var;
   // state kept for the adjoint (all NULL when not requested)
   float2* saved_Z;         // [P][N][N]: forward 2-D spectrum of z, [kx][ky]
   PairStat* saved_ps;      // [P]
@@ -147,7 +154,10 @@ struct KernelTimer {
 };
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s);
+// box = true: the Pearson tables (unit gather taper, tau = DFT of the central
+// n/2 template box, box sums).
+hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s,
+                        bool box = false);
 // alt_fwd / alt_inv select the alternative row counts (FWD2 / INV2); the
 // slice counts a.nsl_fwd and a.nsl_inv must match the choice.
 hipError_t launch_match_group(int n, const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt);

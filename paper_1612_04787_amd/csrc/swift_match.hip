@@ -23,6 +23,10 @@
 //               |shift| <= r, and the column pass supplies sum |C|^2 instead.
 //   k_finalize  reduces the slices, recomputes the three rows around the peak
 //               for the 3x3 centroid and writes the match record.
+// Pearson mode runs the same kernels at p = 0 with window A cut to its
+// central template (a box taper for the mean, unit taper for the gather),
+// plus k_ncc_energy for the per-placement patch energies, and searches the
+// Pearson coefficients c / sqrt(template energy x patch energy).
 #include <float.h>
 #include <limits.h>
 #include <math.h>
@@ -76,6 +80,35 @@ __global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict_
     ti.sum_t = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     ti.sum_t2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     ti.L = L;
+    ti.pad = 0;
+    *info = ti;
+  }
+}
+
+// Pearson tables: the gather runs with a unit taper, and the template of
+// window A is the box [n/4, 3n/4) in both axes, so tau[k] = sum over the box
+// of exp(-2 pi i k i / n) (FP64) and the taper sums are those of the box.
+__global__ void __launch_bounds__(256) k_taper_box(int n, float2* __restrict__ tau, float* __restrict__ taper,
+                                                   TaperInfo* info) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = n / 2, c0 = n / 4;
+  if (k < n) {
+    taper[k] = 1.0f;
+    double re = 0.0, im = 0.0;
+    for (int i = c0; i < c0 + m; ++i) {
+      const int q = (int)(((long long)k * i) % n);
+      double sn, cs;
+      sincospi(2.0 * (double)q / (double)n, &sn, &cs);
+      re += cs;
+      im -= sn;
+    }
+    tau[k] = make_float2((float)re, (float)im);
+  }
+  if (k == 0) {
+    TaperInfo ti;
+    ti.sum_t = (double)m;
+    ti.sum_t2 = (double)m;
+    ti.L = 0;
     ti.pad = 0;
     *info = ti;
   }
@@ -256,7 +289,57 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
   for (int i = FLI; i < ITER; ++i) row(i, [&](int r, int c, float at) { late[r - FL][c] = at; });
 }
 
-template <int N, int R, int BUDGET, int TRW>
+// Pearson mode, between the gather (unit taper) and the row FFTs: window A
+// keeps only its central m x m template (m = N/2 from c0 = N/4) and its sums
+// are taken over the template alone; every row of window B gives its sums of
+// f' and f'^2 over the m columns of every placement j = sx + N/4 in [0, N/2]
+// (prefix sums along the row: the row half of the cumulative-area
+// correction).  One wave per stage row; pre: per-wave scratch of 2 (N+1).
+template <int N, int R, int RS>
+__device__ void pearson_rows(float2* __restrict__ stage, float* __restrict__ pre, const MatchArgs& a, int pair,
+                             int y0, int tid, float (&s)[6]) {
+  constexpr int M = N / 2, C0 = N / 4, NP = N / 2 + 1, EL = N / 64;
+  const int wv = tid >> 6, ln = tid & 63;
+  float* p1 = pre + wv * 2 * (N + 1);
+  float* p2 = p1 + (N + 1);
+  s[0] = s[1] = 0.0f;
+  for (int r = wv; r < R; r += 4) {
+    float2* row = stage + r * RS;
+    const int y = y0 + r;
+    const bool yin = y >= C0 && y < C0 + M;
+    float v1[EL], v2[EL];
+    float c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      const int x = ln * EL + e;
+      const float2 z = row[lidx(x)];
+      if (yin && x >= C0 && x < C0 + M) {
+        s[0] += z.x;
+        s[1] = fmaf(z.x, z.x, s[1]);
+      } else {
+        row[lidx(x)] = make_float2(0.0f, z.y);
+      }
+      c1 += z.y;
+      c2 = fmaf(z.y, z.y, c2);
+      v1[e] = c1;
+      v2[e] = c2;
+    }
+    const float e1 = wave_incl_scan_f32(c1) - c1, e2 = wave_incl_scan_f32(c2) - c2;
+    if (ln == 0) p1[0] = p2[0] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      p1[ln * EL + e + 1] = e1 + v1[e];
+      p2[ln * EL + e + 1] = e2 + v2[e];
+    }
+    wave_lds_sync();
+    float2* dst = a.ncc_rows + ((size_t)pair * N + y) * NP;
+    for (int j = ln; j < NP; j += 64) dst[j] = make_float2(p1[j + M] - p1[j], p2[j + M] - p2[j]);
+    wave_lds_sync();  // the next row reuses the scratch
+  }
+  s[2] = s[0];  // sum a' T^2 with a 0/1 template mask
+}
+
+template <int N, int R, int BUDGET, int TRW, bool PEARSON>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NSLICE = N / R;
@@ -272,6 +355,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   __shared__ float trow[R];
   __shared__ double red[4][6];
   __shared__ int redc[4];
+  __shared__ float pre[PEARSON ? 4 * 2 * (N + 1) : 1];
 
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
@@ -397,6 +481,10 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
       }
   }
   __syncthreads();
+  if constexpr (PEARSON) {
+    pearson_rows<N, R, RS>(stage, pre, a, pair, y0, tid, s);
+    __syncthreads();
+  }
 
   // row FFTs in place: transform g of iteration it owns stage row g + it*G
   Twiddles<N> tw;
@@ -492,6 +580,14 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
     if (!(wA > 1e-6 * s[1]) || !(wB > 1e-6 * s[4])) ps.flags |= 1;
     const double e2 = (double)a.eps_rel * (double)a.eps_rel * fmax(wA, 0.0) * fmax(wB, 0.0);
     ps.eps2 = (float)e2;
+    if (a.pearson) {
+      // the template carries the mean (its spectrum has no DC), so window B is
+      // used as gathered; only a constant template is degenerate (a constant
+      // patch of B gets a zero coefficient per placement)
+      ps.mB = 0.0f;
+      ps.eps2 = 0.0f;
+      ps.flags = (cl ? 4 : 0) | (!(wA > 1e-6 * s[1]) ? 1 : 0);
+    }
     a.pstat[pair] = ps;
     if (a.saved_ps) a.saved_ps[pair] = ps;
   }
@@ -714,13 +810,55 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   store_column<N, T, E, PRUNE>(a, Zp + (size_t)w * N, t, v);
 }
 
+// ---------------------------------------------------------------- Pearson patch energies
+// Column half of the cumulative-area correction: for placement (i, j) =
+// (sy + N/4, sx + N/4) the patch covers rows [i, i + N/2) of the row sums of
+// column j, so a running FP64 window down the rows gives E1 = sum f', E2 =
+// sum f'^2 and the energy E2 - E1^2 / m^2 (m^2 patch pixels).  One thread per
+// placement column j.
+template <int N>
+__global__ void __launch_bounds__(64) k_ncc_energy(MatchArgs a) {
+  constexpr int M = N / 2, NP = N / 2 + 1, NB = (NP + 63) / 64;
+  const int pair = blockIdx.x / NB, j = (blockIdx.x % NB) * 64 + threadIdx.x;
+  if (j >= NP) return;
+  const float2* rb = a.ncc_rows + (size_t)pair * N * NP + j;
+  float* V = a.ncc_var + (size_t)pair * NP * NP + j;
+  double e1 = 0.0, e2 = 0.0;
+  for (int y = 0; y < M; ++y) {
+    const float2 r = rb[(size_t)y * NP];
+    e1 += r.x;
+    e2 += r.y;
+  }
+  const double inv = 1.0 / ((double)M * (double)M);
+  V[0] = (float)fmax(e2 - e1 * e1 * inv, 0.0);
+  for (int i = 1; i < NP; ++i) {
+    const float2 ro = rb[(size_t)(i - 1) * NP], rn = rb[(size_t)(i + M - 1) * NP];
+    e1 += (double)rn.x - (double)ro.x;
+    e2 += (double)rn.y - (double)ro.y;
+    V[(size_t)i * NP] = (float)fmax(e2 - e1 * e1 * inv, 0.0);
+  }
+}
+
+// Pearson coefficient of placement (sy, sx) from the correlation value c, the
+// template energy st and the patch energy; 0 when either energy is 0.
+template <int N>
+__device__ __forceinline__ float pearson_gamma(const MatchArgs& a, int pair, int sy, int sx, float c, float st) {
+  constexpr int NP = N / 2 + 1;
+  const float v = a.ncc_var[((size_t)pair * NP + (sy + N / 4)) * NP + (sx + N / 4)];
+  const float den = st * v;
+  return den > 0.0f ? c * rsqrtf(den) : 0.0f;
+}
+
 // ---------------------------------------------------------------- row pass (inverse) + statistics
 // PRUNE: the launched row blocks are the first a.nsl_lo and the last
 // a.nsl_inv - a.nsl_lo of the N / R2 blocks of a pair; the peak is searched
 // among wrapped shifts |sx|, |sy| <= a.max_shift; no sums (the background
 // comes from the spectrum).
-template <int N, int R2, bool PRUNE>
+// PEARSON (with PRUNE, radius N/4): the candidates are the Pearson
+// coefficients of the placements, and the sums are over those coefficients.
+template <int N, int R2, bool PRUNE, bool PEARSON>
 __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
+  static_assert(PRUNE || !PEARSON, "the Pearson search runs on the pruned rows");
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NT = R2 / 2, NSL2 = N / R2;
   constexpr int NH = N / 2 + 1, RS2 = N / 2 + N / 32 + 1;
@@ -735,6 +873,7 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   const int slice = (!PRUNE || sl < a.nsl_lo) ? sl : NSL2 - (NSP - sl);
   const int y0 = slice * R2;
   const int rmax = PRUNE ? a.max_shift : 0;
+  const float st = PEARSON ? a.pstat[pair].swA : 0.0f;
   const int tid = threadIdx.x, g = tid / T, t = tid % T;
   const float2* Zp = a.Z + (size_t)pair * N * N;
 
@@ -796,7 +935,34 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
       // each lane visits its flat indices in increasing order (row ya, then
       // row yb; rows grow with the iteration), so a strict > keeps the first maximum
       const int ya = y0 + 2 * c, yb = ya + 1;
-      if constexpr (PRUNE) {
+      if constexpr (PEARSON) {
+        const bool ina = ya <= rmax || ya >= N - rmax, inb = yb <= rmax || yb >= N - rmax;
+        const int sya = ya >= N / 2 ? ya - N : ya, syb = yb >= N / 2 ? yb - N : yb;
+        float ls = 0.0f, lq = 0.0f;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int x = t + e * T;
+          if (ina && (x <= rmax || x >= N - rmax)) {
+            const float gv = pearson_gamma<N>(a, pair, sya, x >= N / 2 ? x - N : x, v[e].x, st);
+            top2_push_ordered(tp, gv, ya * N + x);
+            ls += gv;
+            lq = fmaf(gv, gv, lq);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int x = t + e * T;
+          if (inb && (x <= rmax || x >= N - rmax)) {
+            const float gv = pearson_gamma<N>(a, pair, syb, x >= N / 2 ? x - N : x, v[e].y, st);
+            top2_push_ordered(tp, gv, yb * N + x);
+            ls += gv;
+            lq = fmaf(gv, gv, lq);
+          }
+        }
+        sum += (double)ls;
+        sq += (double)lq;
+        continue;
+      } else if constexpr (PRUNE) {
         const bool ina = ya <= rmax || ya >= N - rmax, inb = yb <= rmax || yb >= N - rmax;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -900,7 +1066,7 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
   tp = wave_top2(tp);
   sum = wave_sum(sum);
   sq = wave_sum(sq);
-  if (a.max_shift > 0) {
+  if (a.max_shift > 0 && !a.pearson) {
     // pruned: sum_x c = C(0) = 0, and by Parseval sum_x c^2 = N^2 sum_k |C(k)|^2
     // (C here carries the inverse transform's 1/N^2)
     double cs = 0.0;
@@ -953,7 +1119,27 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
 
   if (ln == 0) {
     const PairStat ps = a.pstat[pair];
-    const swift_match rec = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0);
+    double count = 0.0;
+    bool outside = false;
+    if (a.pearson) {
+      // neighbours as Pearson coefficients; placements beyond the search range
+      // get the lowest value, so they weigh nothing in the centroid
+      constexpr int RP = N / 4;
+      const int sy0 = iy >= N / 2 ? iy - N : iy, sx0 = ix >= N / 2 ? ix - N : ix;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int sy = sy0 + dy, sx = sx0 + dx;
+          if (sy < -RP || sy > RP || sx < -RP || sx > RP) {
+            nb[dy + 1][dx + 1] = -FLT_MAX;
+            outside = true;
+          } else {
+            nb[dy + 1][dx + 1] = pearson_gamma<N>(a, pair, sy, sx, nb[dy + 1][dx + 1], ps.swA);
+          }
+        }
+      count = (double)(2 * RP + 1) * (double)(2 * RP + 1);
+    }
+    swift_match rec = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0, count);
+    if (outside) rec.hxx = rec.hyy = rec.hxy = 0.0f;
     a.out[pair] = rec;
     if (a.saved_rec) a.saved_rec[pair] = rec;
     if (a.saved_nb)
@@ -964,7 +1150,12 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
 // ---------------------------------------------------------------- launchers
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s) {
+hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s,
+                        bool box) {
+  if (box) {
+    k_taper_box<<<(n + 255) / 256, 256, 0, s>>>(n, tau, taper, info);
+    return hipGetLastError();
+  }
   const int L = (int)floor((double)taper_frac * n / 2.0 + 0.5);
   k_taper<<<(n + 255) / 256, 256, 0, s>>>(n, L, tau, taper, info);
   return hipGetLastError();
@@ -989,13 +1180,22 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   if (a.nsl_fwd != N / R) return hipErrorInvalidValue;
   if (a.max_shift > 0 ? (a.nsl_inv > N / R2 || a.nsl_lo > a.nsl_inv) : (a.nsl_inv != N / R2))
     return hipErrorInvalidValue;
+  if (a.pearson && a.max_shift != N / 4) return hipErrorInvalidValue;
   {
     TimerScope ts(kt, "k_row_fwd", N, s);
-    k_row_fwd<N, R, BUDGET, TRW><<<P * (N / R), 256, 0, s>>>(a);
+    if (a.pearson)
+      k_row_fwd<N, R, BUDGET, TRW, true><<<P * (N / R), 256, 0, s>>>(a);
+    else
+      k_row_fwd<N, R, BUDGET, TRW, false><<<P * (N / R), 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_pair_stats", N, s);
     k_pair_stats<N><<<P, 64, 0, s>>>(a);
+  }
+  if (a.pearson) {
+    TimerScope ts(kt, "k_ncc_energy", N, s);
+    constexpr int NB = (N / 2 + 1 + 63) / 64;
+    k_ncc_energy<N><<<P * NB, 64, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_col", N, s);
@@ -1014,10 +1214,12 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   {
     TimerScope ts(kt, "k_row_inv", N, s);
-    if (a.max_shift > 0)
-      k_row_inv<N, R2, true><<<P * (unsigned)a.nsl_inv, 256, 0, s>>>(a);
+    if (a.pearson)
+      k_row_inv<N, R2, true, true><<<P * (unsigned)a.nsl_inv, 256, 0, s>>>(a);
+    else if (a.max_shift > 0)
+      k_row_inv<N, R2, true, false><<<P * (unsigned)a.nsl_inv, 256, 0, s>>>(a);
     else
-      k_row_inv<N, R2, false><<<P * (N / R2), 256, 0, s>>>(a);
+      k_row_inv<N, R2, false, false><<<P * (N / R2), 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_finalize", N, s);

@@ -18,6 +18,7 @@ SIZES = (64, 128, 256, 512, 1024)
 SWIFT_U8, SWIFT_F32 = 0, 1
 FLAG_CONCURRENT_SIZES = 1
 FLAG_JAC_TRANSLATION = 2
+FLAG_PEARSON = 4
 ST_NEAR_TIE, ST_DEGENERATE, ST_CLAMPED = 1, 2, 4
 ERRORS = {-1: "SWIFT_E_INVAL", -2: "SWIFT_E_UNSUPPORTED", -3: "SWIFT_E_WORKSPACE",
           -4: "SWIFT_E_HIP", -5: "SWIFT_E_CAPTURE"}
