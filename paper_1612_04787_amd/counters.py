@@ -15,7 +15,8 @@ the digest of the kernel sources the numbers belong to.
 
 Kernel names are shortened to `name<N>` (the first template argument is the
 window size), the form the library's own HIP-event timer uses; the instances
-of the pruned inverse (a search radius) become `name_pruned<N>`.
+of the pruned inverse (a search radius) become `name_pruned<N>`, those of the
+Pearson mode `name_pearson<N>`.
 """
 from __future__ import annotations
 
@@ -49,7 +50,13 @@ def short_name(full: str) -> str | None:
     m = re.search(r"swift::k_bwd_(col|row|fin)<(\d+), true(, (true|false))?>", full)
     if m:  # centroid-Jacobian instance of the adjoint kernels
         return "k_cj_%s<%s>" % (m.group(1), m.group(2))
-    m = re.search(r"swift::(k_col_pair|k_col|k_row_inv)<(\d+)(, \d+)?, true>", full)
+    m = re.search(r"swift::(k_row_fwd)<(\d+)(, \d+)+, true>", full)
+    if m:  # Pearson instance of the forward row pass
+        return "%s_pearson<%s>" % (m.group(1), m.group(2))
+    m = re.search(r"swift::(k_row_inv)<(\d+), \d+, true, true>", full)
+    if m:  # Pearson instance of the inverse row pass
+        return "%s_pearson<%s>" % (m.group(1), m.group(2))
+    m = re.search(r"swift::(k_col_pair|k_col|k_row_inv)<(\d+)(, \d+)?, true(, false)?>", full)
     if m:  # pruned-inverse instance (a search radius)
         return "%s_pruned<%s>" % (m.group(1), m.group(2))
     m = re.search(r"swift::(k_\w+)<(\d+)", full)

@@ -26,17 +26,6 @@ __device__ __forceinline__ float taper_at(int i, int n, int L) {
   return 0.5f * (1.0f - cospif(((float)m + 0.5f) / (float)L));
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
-__device__ __forceinline__ float wave_incl_scan_f32(float v) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const float u = __shfl_up(v, off, 64);
-    if (ln >= off) v += u;
-  }
-  return v;
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -59,6 +48,20 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// within each row of 16 lanes (lanes with no source add 0), then row 0's
+// total into row 1 and row 2's into row 3, then lanes 0..31's total into rows
+// 2 and 3.
+__device__ __forceinline__ float wave_incl_scan_f32(float v) {
+  v += dpp_f32<0x111>(v);
+  v += dpp_f32<0x112>(v);
+  v += dpp_f32<0x114>(v);
+  v += dpp_f32<0x118>(v);
+  v += dpp_f32<0x142, 0xA>(v);
+  v += dpp_f32<0x143, 0xC>(v);
+  return v;
 }
 
 struct Top2 {

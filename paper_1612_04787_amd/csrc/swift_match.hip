@@ -294,24 +294,25 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
 // are taken over the template alone; every row of window B gives its sums of
 // f' and f'^2 over the m columns of every placement j = sx + N/4 in [0, N/2]
 // (prefix sums along the row: the row half of the cumulative-area
-// correction).  One wave per stage row; pre: per-wave scratch of 2 (N+1).
+// correction).  One wave per stage row; lane l holds x = l + 64 e, so each
+// segment of 64 columns is one wave scan and a placement's sum P(j + m) -
+// P(j) reads two entries of one lane (at N = 64 the upper one is a lane
+// 32 away).
 template <int N, int R, int RS>
-__device__ void pearson_rows(float2* __restrict__ stage, float* __restrict__ pre, const MatchArgs& a, int pair,
-                             int y0, int tid, float (&s)[6]) {
+__device__ void pearson_rows(float2* __restrict__ stage, const MatchArgs& a, int pair, int y0, int tid,
+                             float (&s)[6]) {
   constexpr int M = N / 2, C0 = N / 4, NP = N / 2 + 1, EL = N / 64;
   const int wv = tid >> 6, ln = tid & 63;
-  float* p1 = pre + wv * 2 * (N + 1);
-  float* p2 = p1 + (N + 1);
   s[0] = s[1] = 0.0f;
   for (int r = wv; r < R; r += 4) {
     float2* row = stage + r * RS;
     const int y = y0 + r;
     const bool yin = y >= C0 && y < C0 + M;
-    float v1[EL], v2[EL];
-    float c1 = 0.0f, c2 = 0.0f;
+    float q1[EL], q2[EL];  // exclusive prefix sums at x = ln + 64 e
+    float c1 = 0.0f, c2 = 0.0f;  // totals of the earlier segments
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
-      const int x = ln * EL + e;
+      const int x = ln + 64 * e;
       const float2 z = row[lidx(x)];
       if (yin && x >= C0 && x < C0 + M) {
         s[0] += z.x;
@@ -319,22 +320,23 @@ __device__ void pearson_rows(float2* __restrict__ stage, float* __restrict__ pre
       } else {
         row[lidx(x)] = make_float2(0.0f, z.y);
       }
-      c1 += z.y;
-      c2 = fmaf(z.y, z.y, c2);
-      v1[e] = c1;
-      v2[e] = c2;
+      const float f = z.y, f2 = z.y * z.y;
+      const float i1 = wave_incl_scan_f32(f), i2 = wave_incl_scan_f32(f2);
+      q1[e] = c1 + (i1 - f);
+      q2[e] = c2 + (i2 - f2);
+      c1 += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(i1), 63));
+      c2 += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(i2), 63));
     }
-    const float e1 = wave_incl_scan_f32(c1) - c1, e2 = wave_incl_scan_f32(c2) - c2;
-    if (ln == 0) p1[0] = p2[0] = 0.0f;
-#pragma unroll
-    for (int e = 0; e < EL; ++e) {
-      p1[ln * EL + e + 1] = e1 + v1[e];
-      p2[ln * EL + e + 1] = e2 + v2[e];
-    }
-    wave_lds_sync();
     float2* dst = a.ncc_rows + ((size_t)pair * N + y) * NP;
-    for (int j = ln; j < NP; j += 64) dst[j] = make_float2(p1[j + M] - p1[j], p2[j + M] - p2[j]);
-    wave_lds_sync();  // the next row reuses the scratch
+    if constexpr (EL == 1) {
+      const float u1 = __shfl_down(q1[0], 32, 64), u2 = __shfl_down(q2[0], 32, 64);
+      if (ln < 32) dst[ln] = make_float2(u1 - q1[0], u2 - q2[0]);
+      if (ln == 32) dst[32] = make_float2(c1 - q1[0], c2 - q2[0]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < EL / 2; ++k) dst[ln + 64 * k] = make_float2(q1[k + EL / 2] - q1[k], q2[k + EL / 2] - q2[k]);
+      if (ln == 0) dst[M] = make_float2(c1 - q1[EL / 2], c2 - q2[EL / 2]);
+    }
   }
   s[2] = s[0];  // sum a' T^2 with a 0/1 template mask
 }
@@ -355,7 +357,6 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   __shared__ float trow[R];
   __shared__ double red[4][6];
   __shared__ int redc[4];
-  __shared__ float pre[PEARSON ? 4 * 2 * (N + 1) : 1];
 
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
@@ -482,7 +483,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
   __syncthreads();
   if constexpr (PEARSON) {
-    pearson_rows<N, R, RS>(stage, pre, a, pair, y0, tid, s);
+    pearson_rows<N, R, RS>(stage, a, pair, y0, tid, s);
     __syncthreads();
   }
 
