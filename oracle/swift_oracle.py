@@ -774,3 +774,67 @@ def pearson_pair(imgA, imgB, thetaA, thetaB, n, return_surface=False):
     if return_surface:
         rec["surface"] = g
     return rec
+
+
+# ---------------------------------------------------------------------------
+# Jump repair (Section III, model paragraphs): where an abrupt content or
+# magnification change makes a section's match lock to one side of its
+# two-sided model, the offending sections are matched separately to the
+# models on either side, and a smoothing curve is built across the failed
+# span.  Design readings: the one-sided models are the rounded means of the
+# k sections before (side -1) or after (side +1), offending ones omitted; the
+# curve is the cubic Bezier with control values 0, 0, 1, 1 (zero slope at
+# both ends) blending, per affine entry, the left-model fit into the
+# right-model fit across the span.
+# ---------------------------------------------------------------------------
+def project_side(stack, s, k, side, exclude=None):
+    """One-sided model of section s: round-half-up of the mean of sections
+    s-k..s-1 (side -1) or s+1..s+k (side +1) inside the stack and not
+    excluded; zeros when there is none.  Integer arithmetic as project."""
+    S = stack.shape[0]
+    J = range(max(0, s - k), s) if side < 0 else range(s + 1, min(S, s + k + 1))
+    J = [j for j in J if not (exclude is not None and exclude[j])]
+    if not J:
+        return np.zeros(stack.shape[1:], dtype=np.uint8)
+    acc = np.zeros(stack.shape[1:], dtype=np.int64)
+    for j in J:
+        acc += stack[j].astype(np.int64)
+    nn = len(J)
+    return ((2 * acc + nn) // (2 * nn)).astype(np.uint8)
+
+
+def span_weight(s, a, b):
+    """Weight of the right-model fit for section s of the failed span [a, b]:
+    t = (s - a + 1) / (b - a + 2) (the span's good neighbours a - 1 and b + 1
+    sit at t = 0 and 1), w = 3 t^2 - 2 t^3."""
+    t = (s - a + 1) / (b - a + 2)
+    return 3.0 * t * t - 2.0 * t * t * t
+
+
+def blend_span(aff_left, aff_right, a, b):
+    """Repaired affines [b - a + 1, 6] of the span: (1 - w) A_left + w A_right
+    entry by entry, with w = span_weight; aff_left, aff_right indexed by
+    section."""
+    out = []
+    for s in range(a, b + 1):
+        w = span_weight(s, a, b)
+        out.append((1.0 - w) * np.asarray(aff_left[s], dtype=np.float64) + w * np.asarray(aff_right[s], dtype=np.float64))
+    return np.array(out)
+
+
+def failed_spans(section_snr, frac):
+    """Maximal runs [a, b] of sections whose SNR is below frac times the
+    median over all sections."""
+    v = np.asarray(section_snr, dtype=np.float64)
+    bad = v < frac * np.median(v)
+    spans, s = [], 0
+    while s < len(v):
+        if bad[s]:
+            e = s
+            while e + 1 < len(v) and bad[e + 1]:
+                e += 1
+            spans.append((s, e))
+            s = e + 1
+        else:
+            s += 1
+    return spans

@@ -157,3 +157,36 @@ def test_pruned_rejects_surfaces_and_negative_radius(ctx, section_pair_small):
     torch.cuda.synchronize()
     for key in ("dx", "dy", "ix", "iy", "snr", "std"):
         assert torch.equal(res[key], full[key]), key
+
+
+def test_pruned_forward_feeds_the_adjoint(ctx, section_pair_small):
+    """The adjoint reads the saved forward spectra and records, not the
+    surface rows: after a pruned forward whose shifts all lie inside the
+    radius, the centroid Jacobian and the SNR gradient equal those after the
+    full forward (to rounding of the background statistics)."""
+    import paper_1612_04787_amd as sw
+    print("case prune adjoint", flush=True)
+    a, b = section_pair_small
+    rng = np.random.default_rng(7300)
+    n, k, r = 256, 4, 16
+    tha = np.zeros((k, 8), np.float32)
+    for i in range(k):
+        tha[i] = [rng.uniform(300, 1300), rng.uniform(300, 1300), 1, 0, rng.uniform(-0.5, 0.5), 0, 1,
+                  rng.uniform(-0.5, 0.5)]
+    thb = tha.copy()
+    thb[:, 4] += rng.uniform(-3, 3, k).astype(np.float32)
+    thb[:, 7] += rng.uniform(-3, 3, k).astype(np.float32)
+    args = ([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32), torch.ones(k, dtype=torch.int32),
+            torch.from_numpy(tha), torch.from_numpy(thb))
+    pf, pp = sw.make_params(p=0.65), sw.make_params(p=0.65, max_shift=r)
+    full = ctx.match_batch(*args, pf, save=True)
+    prun = ctx.match_batch(*args, pp, save=True)
+    jf = ctx.centroid_jacobian(full, pf)
+    jp = ctx.centroid_jacobian(prun, pp)
+    gf, _ = ctx.match_backward(full, pf, g_snr=torch.ones(k))
+    gp, _ = ctx.match_backward(prun, pp, g_snr=torch.ones(k))
+    torch.cuda.synchronize()
+    assert torch.equal(full["ix"], prun["ix"]) and torch.equal(full["iy"], prun["iy"])
+    scale = jf.abs().max().item()
+    assert (jf - jp).abs().max().item() <= 1e-4 * scale
+    assert (gf - gp).abs().max().item() <= 1e-3 * gf.abs().max().item()

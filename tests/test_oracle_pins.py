@@ -832,3 +832,56 @@ def test_pearson_exact_shift_sign_and_invariance():
     # a constant window is degenerate
     r4 = O.pearson_pair(np.full((200, 200), 9.0), img, thA, thB, n)
     assert r4["status"] & STATUS_DEGENERATE and r4["snr"] == 0.0
+
+
+# --------------------------------------------------------------------------- jump repair
+def test_one_sided_models_brute_force():
+    rng = np.random.default_rng(51)
+    st = rng.integers(0, 256, (9, 5, 7)).astype(np.uint8)
+    excl = np.zeros(9, bool)
+    excl[3] = True
+    for s in range(9):
+        for side in (-1, 1):
+            J = [j for j in range(9) if (0 < (s - j) <= 3 if side < 0 else 0 < (j - s) <= 3) and not excl[j]]
+            got = O.project_side(st, s, 3, side, excl)
+            if not J:
+                assert not got.any()
+                continue
+            mean = st[J].astype(np.float64).mean(0)
+            np.testing.assert_array_equal(got, np.floor(mean + 0.5).astype(np.uint8))
+        # the two sides together hold the two-sided model's neighbours
+        left = [j for j in range(max(0, s - 3), s) if not excl[j]]
+        right = [j for j in range(s + 1, min(9, s + 4)) if not excl[j]]
+        if left or right:
+            both = np.floor(st[left + right].astype(np.float64).mean(0) + 0.5).astype(np.uint8)
+            np.testing.assert_array_equal(O.project(st, s, 3, excl), both)
+
+
+def test_span_blend_is_the_cubic_bezier():
+    def casteljau(t, c):
+        c = list(c)
+        while len(c) > 1:
+            c = [(1 - t) * c[i] + t * c[i + 1] for i in range(len(c) - 1)]
+        return c[0]
+    for a, b in ((4, 4), (2, 5), (0, 9)):
+        for s in range(a, b + 1):
+            t = (s - a + 1) / (b - a + 2)
+            assert abs(O.span_weight(s, a, b) - casteljau(t, (0, 0, 1, 1))) < 1e-15
+    # symmetric about the middle of the span, zero slope at its ends
+    assert abs(O.span_weight(2, 2, 4) + O.span_weight(4, 2, 4) - 1) < 1e-15
+    h = 1e-6
+    w = lambda t: 3 * t * t - 2 * t ** 3  # noqa: E731
+    assert abs((w(h) - w(0)) / h) < 1e-5 and abs((w(1) - w(1 - h)) / h) < 1e-5
+    L = np.tile([1, 0, 2, 0, 1, -1.0], (10, 1))
+    R = np.tile([1.01, 0, -3, 0, 0.99, 4.0], (10, 1))
+    out = O.blend_span(L, R, 3, 5)
+    assert out.shape == (3, 6)
+    # entries move monotonically from the left fit toward the right fit
+    assert np.all(np.diff(out[:, 2]) < 0) and np.all(np.diff(out[:, 5]) > 0)
+    np.testing.assert_allclose(out[1], 0.5 * (L[4] + R[4]), atol=1e-15)
+
+
+def test_failed_spans_runs():
+    snr = [30, 31, 29, 8, 7, 30, 32, 10, 31]
+    assert O.failed_spans(snr, 0.5) == [(3, 4), (7, 7)]
+    assert O.failed_spans([20] * 5, 0.5) == []
