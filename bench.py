@@ -13,8 +13,9 @@ kernel from live HIP-event timing, and the FP64 oracle's throughput on a
 bounded sample of the same pairs on the host cores).  Further blocks of the
 line: the same step with a pruned inverse (search radius 64 px), the same
 pairs scored by Pearson-normalised correlation, plain vs
-adjoint refinement to 0.01 px, the iterative stack loop, the local-affine
-mesh on a bent stack, and ragged multi-level batches.
+adjoint refinement to 0.01 px, the iterative stack loop, jump repair on a
+stack with a magnification change, the local-affine mesh on a bent stack,
+and ragged multi-level batches.
 """
 from __future__ import annotations
 
@@ -439,6 +440,42 @@ def cpu_baseline_mesh(sample, n_px=1 << 23):
                        % (n_px, H, grid, grid, el))
 
 
+# --------------------------------------------------------------------------- jump repair
+def jump_block(ctx, dev, sections=16, size=SIZE, j0=8, mag=0.02):
+    """Jump repair (Section III, model paragraphs) on a stack with a
+    magnification change: the section-affine loop (levels 2/1/0), then
+    repair_jumps at level 0 (512^2 windows, 8 x 8 per section).  Residuals
+    between neighbouring sections against the generator's warps, per pair."""
+    import numpy as np
+    import torch
+
+    from datagen.evaluate import composed_points
+    from datagen.workloads import jump_stack
+    from paper_1612_04787_amd.stack import align_stack, build_pyramid, repair_jumps
+    stack, warps = jump_stack(sections, size, seed=13, j0=j0, mag=mag, device=dev)
+    pyr = build_pyramid(ctx, stack, 2)
+    aff, _ = align_stack(ctx, stack, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), ks=(4, 3, 3), grid=8)
+    pts = np.array([(size // 16 + size // 8 * i, size // 16 + size // 8 * j) for j in range(8) for i in range(8)],
+                   np.float64)
+
+    def pair_res(a):
+        c = composed_points(a.cpu().numpy(), warps, pts)
+        return np.sqrt(np.mean(np.sum((c[1:] - c[:-1]) ** 2, 2), 1))
+
+    r0 = pair_res(aff)
+    aff2, rep = repair_jumps(ctx, stack, aff.clone(), level=0, n=512, grid=8, k=3, pyr=pyr)
+    r1 = pair_res(aff2)
+    del stack, pyr
+    torch.cuda.empty_cache()
+    return dict(workload="%d sections of %d^2 with drift and section affines, magnification change of %.0f%% at "
+                         "section %d; section-affine loop at levels 2/1/0, then repair at level 0 (512^2 windows)"
+                         % (sections, size, 100 * mag, j0),
+                breaks=rep["breaks"], spans=rep["spans"], repair_ms=rep["ms"],
+                pair_residual_px={"max_before": float(r0.max()), "at_jump_before": float(r0[j0 - 1]),
+                                  "max_after": float(r1.max()), "at_jump_after": float(r1[j0 - 1]),
+                                  "median_after": float(np.median(r1))})
+
+
 # --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -453,6 +490,7 @@ def main():
     ap.add_argument("--no-mesh", action="store_true", help="skip the local-affine mesh run")
     ap.add_argument("--no-prune", action="store_true", help="skip the pruned-inverse (search radius) variant")
     ap.add_argument("--no-pearson", action="store_true", help="skip the Pearson-normalised correlation variant")
+    ap.add_argument("--no-jump", action="store_true", help="skip the jump-repair run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -632,6 +670,13 @@ def main():
         log("stack loop: %.0f ms, residual global %.2f -> %.2f px, neighbour %.2f -> %.2f px"
             % (line["stack_loop"]["wall_ms"], r["global_before"], r["global_after"], r["neighbour_before"],
                r["neighbour_after"]))
+    if not args.no_jump:
+        log("jump repair: a stack with a magnification change ...")
+        line["jump_repair"] = jump_block(ctx, dev)
+        jr = line["jump_repair"]["pair_residual_px"]
+        log("jump repair: break %.2f px -> %.2f px (max pair %.2f -> %.2f), %.0f ms"
+            % (jr["at_jump_before"], jr["at_jump_after"], jr["max_before"], jr["max_after"],
+               line["jump_repair"]["repair_ms"]))
     mesh_sample = None
     if not args.no_mesh:
         log("mesh: global affines then two local-affine mesh passes on a bent stack ...")

@@ -58,6 +58,29 @@ def bent_stack(n_sections=16, size=4096, seed=11, bend=3.0, device="cuda"):
     return st, warps
 
 
+def jump_warps(n_sections: int, h: int, w: int, seed: int, j0: int, mag=0.02, **kw):
+    """stack_warps with a magnification change between sections j0 - 1 and
+    j0: sections from j0 on see the clean content scaled by 1 + mag about the
+    centre.  Returns a list of (M, b)."""
+    c = np.array([(w - 1) / 2.0, (h - 1) / 2.0])
+    out = []
+    for s, (m, b) in enumerate(stack_warps(n_sections, h, w, seed, **kw)):
+        if s >= j0:
+            m = (1.0 + mag) * np.asarray(m)
+            b = c + (1.0 + mag) * (np.asarray(b) - c)
+        out.append((m, b))
+    return out
+
+
+def jump_stack(n_sections=16, size=4096, seed=13, j0=8, mag=0.02, device="cuda"):
+    """The jump-repair input: the distorted stack's drift and section affines
+    plus a magnification change of mag at section j0.  Returns (stack,
+    warps)."""
+    warps = jump_warps(n_sections, size, size, seed + 1000, j0, mag)
+    st = make_stack(n_sections, size, size, seed, device=device, warps=warps)
+    return st, warps
+
+
 def distorted_stack(n_sections=64, size=4096, seed=5, device="cuda"):
     """The iterative-stack input: S sections of size^2 uint8 with accumulated
     drift and per-section affine distortion.  Returns (stack, warps)."""

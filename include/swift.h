@@ -232,6 +232,40 @@ int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t heigh
                   int64_t pitch, int64_t section_stride, const uint8_t* exclude, int32_t k,
                   uint8_t* out, int64_t out_pitch, int64_t out_section_stride, hipStream_t stream);
 
+/* Jump repair (Section III, model paragraphs): where an abrupt content or
+ * magnification change locks a section's match to one side of its model, the
+ * offending sections are matched separately to the models on either side and
+ * a smoothing curve is built across the failed span.
+ *
+ * One-sided models: as swift_project, but out[s] is the rounded mean of the
+ * included sections s-k..s-1 (side = -1) or s+1..s+k (side = +1) only.
+ * Errors: as swift_project, and SWIFT_E_INVAL for side not -1 or +1. */
+int swift_project_side(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width,
+                       int64_t pitch, int64_t section_stride, const uint8_t* exclude, int32_t k,
+                       int32_t side, uint8_t* out, int64_t out_pitch, int64_t out_section_stride,
+                       hipStream_t stream);
+
+/* The smoothing curve across a failed span [a, b] of sections: for s in
+ * [a, b], aff[s] = (1 - w) aff_left[s] + w aff_right[s] entry by entry, where
+ * w = 3 t^2 - 2 t^3 is the cubic Bezier with control values 0, 0, 1, 1 and
+ * t = (s - a + 1) / (b - a + 2) (the span's good neighbours a - 1 and b + 1
+ * sit at t = 0 and 1).  aff_left / aff_right: the section affines [S][6]
+ * fitted against the left / right one-sided models; aff [S][6] receives the
+ * span's entries (others untouched).  All device, double.  Errors:
+ * SWIFT_E_INVAL (NULL, span outside [0, S)), SWIFT_E_HIP. */
+int swift_blend_span(swift_ctx* ctx, int32_t S, int32_t a, int32_t b, const double* aff_left,
+                     const double* aff_right, double* aff, hipStream_t stream);
+
+/* Joins the sections after a break to the frame before it: with A_j the
+ * affine of section j and L_j = aff_left[j] its fit against the left
+ * one-sided model, the aligned-frame correction D = A_j^-1 L_j is composed
+ * into every section s >= j (out[s] = A_s o D, so out[j] = L_j); sections
+ * before j are copied.  aff, aff_left, out: device [S][6] double; out must not
+ * alias aff.  A singular A_j gives non-finite output.  Errors: SWIFT_E_INVAL
+ * (NULL, aliasing, j outside [0, S)), SWIFT_E_HIP. */
+int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, const double* aff_left,
+                     double* out, hipStream_t stream);
+
 /* One level of the x2 source pyramid (Section III: iscale): dst(x, y) =
  * (sum of the 2x2 block at (2x, 2y) + 2) >> 2 for uint8 images; dst must be
  * (src.width/2) x (src.height/2).  Descriptors are host structs whose data

@@ -838,3 +838,22 @@ def failed_spans(section_snr, frac):
         else:
             s += 1
     return spans
+
+
+def join_break(aff, aff_left, j):
+    """Joins the sections from j on to the frame of the sections before a
+    break at j: with A_j the affine of section j and L_j its fit against the
+    left one-sided model, the aligned-frame correction D = A_j^-1 L_j is
+    composed into every section s >= j (A_s <- A_s D), so that section j
+    becomes L_j.  Affines (a11, a12, tx, a21, a22, ty) map aligned to raw
+    points."""
+    def mat(a):
+        a = np.asarray(a, dtype=np.float64)
+        return np.array([[a[0], a[1], a[2]], [a[3], a[4], a[5]], [0.0, 0.0, 1.0]])
+
+    D = np.linalg.inv(mat(aff[j])) @ mat(aff_left[j])
+    out = np.array(aff, dtype=np.float64).copy()
+    for s in range(j, len(out)):
+        m = mat(out[s]) @ D
+        out[s] = [m[0, 0], m[0, 1], m[0, 2], m[1, 0], m[1, 1], m[1, 2]]
+    return out

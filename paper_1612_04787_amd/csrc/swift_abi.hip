@@ -704,6 +704,50 @@ int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t heigh
   return ok();
 }
 
+int swift_project_side(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t height, int32_t width, int64_t pitch,
+                       int64_t section_stride, const uint8_t* exclude, int32_t k, int32_t side, uint8_t* out,
+                       int64_t out_pitch, int64_t out_section_stride, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (side != -1 && side != 1) return fail(SWIFT_E_INVAL, "side must be -1 or +1 (got %d)", side);
+  if (!stack || !out) return fail(SWIFT_E_INVAL, "stack/out is NULL");
+  if (S < 1 || height < 1 || width < 1) return fail(SWIFT_E_INVAL, "bad stack shape %d x %d x %d", S, height, width);
+  if (k < 1 || k > 8) return fail(SWIFT_E_INVAL, "k must be in [1, 8] (got %d)", k);
+  if (pitch < width || out_pitch < width) return fail(SWIFT_E_INVAL, "pitch smaller than width");
+  if (section_stride < pitch * height || out_section_stride < out_pitch * height)
+    return fail(SWIFT_E_INVAL, "section stride smaller than height * pitch");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_project(stack, pitch, section_stride, S, height, width, exclude, k, out, out_pitch,
+                                out_section_stride, stream, ctx->kt(), side);
+  if (e != hipSuccess) return hip_fail(e, "one-sided project launch");
+  return ok();
+}
+
+int swift_blend_span(swift_ctx* ctx, int32_t S, int32_t a, int32_t b, const double* aff_left,
+                     const double* aff_right, double* aff, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!aff_left || !aff_right || !aff) return fail(SWIFT_E_INVAL, "NULL affine array");
+  if (!(0 <= a && a <= b && b < S)) return fail(SWIFT_E_INVAL, "span [%d, %d] outside [0, %d)", a, b, S);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_blend_span(a, b, aff_left, aff_right, aff, stream);
+  if (e != hipSuccess) return hip_fail(e, "blend launch");
+  return ok();
+}
+
+int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, const double* aff_left, double* out,
+                     hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (!aff || !aff_left || !out) return fail(SWIFT_E_INVAL, "NULL affine array");
+  if (aff == out) return fail(SWIFT_E_INVAL, "out must not alias aff");
+  if (!(0 <= j && j < S)) return fail(SWIFT_E_INVAL, "break %d outside [0, %d)", j, S);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_join_break(S, j, aff, aff_left, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "join launch");
+  return ok();
+}
+
 int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst, hipStream_t stream) {
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   if (!src || !dst || !src->data || !dst->data) return fail(SWIFT_E_INVAL, "src/dst is NULL");

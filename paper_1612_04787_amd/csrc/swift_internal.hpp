@@ -183,9 +183,12 @@ hipError_t launch_fit_mesh(int S, int grid, const float* th_a, const float* th_b
                            KernelTimer* kt);
 hipError_t launch_refine(int P, const swift_match* rec, const float* jac, float* th, int mode, float max_step,
                          float* step_out, hipStream_t s);
+// side 0: two-sided model; -1 / +1: one-sided (sections before / after).
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* exclude, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
-                          hipStream_t s, KernelTimer* kt);
+                          hipStream_t s, KernelTimer* kt, int side = 0);
+hipError_t launch_blend_span(int a, int b, const double* left, const double* right, double* aff, hipStream_t st);
+hipError_t launch_join_break(int S, int j, const double* in, const double* left, double* out, hipStream_t st);
 hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, uint8_t* dst, int64_t dpitch,
                           int dw, int dh, hipStream_t s);
 

@@ -62,6 +62,7 @@ hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hip
   return hipGetLastError();
 }
 
+template <int SIDE>
 hipError_t launch_project_sel(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                               const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
                               hipStream_t st);
@@ -86,7 +87,9 @@ __device__ __forceinline__ uint32_t div_pack4(uint32_t lo, uint32_t hi, float in
   return q0 | (q1 << 8) | (q2 << 16) | (q3 << 24);
 }
 
-template <int K, int BW>
+// SIDE 0: the two-sided model (neighbours on both sides); SIDE -1 / +1: the
+// one-sided models of jump repair (only the k sections before / after).
+template <int K, int BW, int SIDE>
 __global__ void __launch_bounds__(256) k_project(const uint8_t* __restrict__ src, int64_t pitch, int64_t sstride,
                                                  int S, int H, int W, const uint8_t* __restrict__ excl,
                                                  uint8_t* __restrict__ dst, int64_t dpitch, int64_t dstride) {
@@ -113,7 +116,7 @@ __global__ void __launch_bounds__(256) k_project(const uint8_t* __restrict__ src
 #pragma unroll
       for (int i = 0; i < WN; ++i) {
         const int j = s - K + i;
-        if (i != K && j >= 0 && j < S && !(excl && excl[j])) {
+        if (i != K && (SIDE == 0 || (SIDE < 0 ? i < K : i > K)) && j >= 0 && j < S && !(excl && excl[j])) {
           ++nn;
           const uint4 v = win[i];
           const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(256) k_project(const uint8_t* __restrict__ src
 #pragma unroll
       for (int i = 0; i < WN; ++i) {
         const int j = s - K + i;
-        if (i != K && j >= 0 && j < S && !(excl && excl[j])) {
+        if (i != K && (SIDE == 0 || (SIDE < 0 ? i < K : i > K)) && j >= 0 && j < S && !(excl && excl[j])) {
           ++nn;
           acc += win[i];
         }
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(256) k_project(const uint8_t* __restrict__ src
   }
 }
 
-template <int K>
+template <int K, int SIDE>
 static hipError_t launch_project_k(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                                    const uint8_t* excl, uint8_t* dst, int64_t dpitch, int64_t dstride,
                                    hipStream_t st) {
@@ -163,37 +166,44 @@ static hipError_t launch_project_k(const uint8_t* src, int64_t pitch, int64_t ss
                    (dstride % 16 == 0) && (((uintptr_t)src) % 16 == 0) && (((uintptr_t)dst) % 16 == 0);
   if (vec) {
     const long long nthr = (long long)H * (W / 16);
-    k_project<K, 16><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
-                                                                      dpitch, dstride);
+    k_project<K, 16, SIDE><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
+                                                                            dpitch, dstride);
   } else {
     const long long nthr = (long long)H * W;
-    k_project<K, 1><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
-                                                                     dpitch, dstride);
+    k_project<K, 1, SIDE><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(src, pitch, sstride, S, H, W, excl, dst,
+                                                                           dpitch, dstride);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                           const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
-                          hipStream_t st, KernelTimer* kt) {
-  if (kt) kt->begin("k_project", k, st);
-  const hipError_t e = launch_project_sel(src, pitch, sstride, S, H, W, excl, k, dst, dpitch, dstride, st);
+                          hipStream_t st, KernelTimer* kt, int side) {
+  if (kt) kt->begin(side == 0 ? "k_project" : (side < 0 ? "k_project_left" : "k_project_right"), k, st);
+  hipError_t e;
+  if (side == 0)
+    e = launch_project_sel<0>(src, pitch, sstride, S, H, W, excl, k, dst, dpitch, dstride, st);
+  else if (side < 0)
+    e = launch_project_sel<-1>(src, pitch, sstride, S, H, W, excl, k, dst, dpitch, dstride, st);
+  else
+    e = launch_project_sel<1>(src, pitch, sstride, S, H, W, excl, k, dst, dpitch, dstride, st);
   if (kt) kt->end(st);
   return e;
 }
 
+template <int SIDE>
 hipError_t launch_project_sel(const uint8_t* src, int64_t pitch, int64_t sstride, int S, int H, int W,
                               const uint8_t* excl, int k, uint8_t* dst, int64_t dpitch, int64_t dstride,
                               hipStream_t st) {
   switch (k) {
-    case 1: return launch_project_k<1>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 2: return launch_project_k<2>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 3: return launch_project_k<3>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 4: return launch_project_k<4>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 5: return launch_project_k<5>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 6: return launch_project_k<6>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 7: return launch_project_k<7>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
-    case 8: return launch_project_k<8>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 1: return launch_project_k<1, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 2: return launch_project_k<2, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 3: return launch_project_k<3, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 4: return launch_project_k<4, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 5: return launch_project_k<5, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 6: return launch_project_k<6, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 7: return launch_project_k<7, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
+    case 8: return launch_project_k<8, SIDE>(src, pitch, sstride, S, H, W, excl, dst, dpitch, dstride, st);
   }
   return hipErrorInvalidValue;
 }
@@ -263,6 +273,66 @@ hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, ui
   (void)sh;
   const long long n = (long long)dw * dh;
   if (n > 0) k_pyramid<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, spitch, dst, dpitch, dw, dh);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- jump repair blend
+// Affines of the failed span [a, b]: aff[s] = (1 - w) left[s] + w right[s]
+// per entry, w = 3 t^2 - 2 t^3 (the cubic Bezier with control values 0, 0,
+// 1, 1), t = (s - a + 1) / (b - a + 2).  One thread per entry.
+__global__ void __launch_bounds__(64) k_blend_span(int a, int b, const double* __restrict__ left,
+                                                   const double* __restrict__ right, double* __restrict__ aff) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= 6 * (b - a + 1)) return;
+  const int s = a + i / 6, e = i % 6;
+  const double t = (double)(s - a + 1) / (double)(b - a + 2);
+  const double w = 3.0 * t * t - 2.0 * t * t * t;
+  aff[6 * (size_t)s + e] = (1.0 - w) * left[6 * (size_t)s + e] + w * right[6 * (size_t)s + e];
+}
+
+hipError_t launch_blend_span(int a, int b, const double* left, const double* right, double* aff, hipStream_t st) {
+  const int n = 6 * (b - a + 1);
+  if (n > 0) k_blend_span<<<(n + 63) / 64, 64, 0, st>>>(a, b, left, right, aff);
+  return hipGetLastError();
+}
+
+// Break join: D = A_j^-1 L_j (aligned-frame correction from section j's fit
+// against its left one-sided model); out[s] = in[s] o D for s >= j, in[s]
+// otherwise.  Out of place: every thread reads A_j from `in`.
+__global__ void __launch_bounds__(64) k_join_break(int S, int j, const double* __restrict__ in,
+                                                   const double* __restrict__ left, double* __restrict__ out) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= S) return;
+  const double* A = in + 6 * (size_t)s;
+  double* O = out + 6 * (size_t)s;
+  if (s < j) {
+    for (int e = 0; e < 6; ++e) O[e] = A[e];
+    return;
+  }
+  const double* Aj = in + 6 * (size_t)j;
+  const double* Lj = left + 6 * (size_t)j;
+  // A_j^-1 = [M^-1, -M^-1 t]
+  const double det = Aj[0] * Aj[4] - Aj[1] * Aj[3];
+  const double i00 = Aj[4] / det, i01 = -Aj[1] / det, i10 = -Aj[3] / det, i11 = Aj[0] / det;
+  const double it0 = -(i00 * Aj[2] + i01 * Aj[5]), it1 = -(i10 * Aj[2] + i11 * Aj[5]);
+  // D = A_j^-1 L_j
+  const double d00 = i00 * Lj[0] + i01 * Lj[3], d01 = i00 * Lj[1] + i01 * Lj[4];
+  const double d10 = i10 * Lj[0] + i11 * Lj[3], d11 = i10 * Lj[1] + i11 * Lj[4];
+  const double dt0 = i00 * Lj[2] + i01 * Lj[5] + it0, dt1 = i10 * Lj[2] + i11 * Lj[5] + it1;
+  // out = A o D
+  const double o00 = A[0] * d00 + A[1] * d10, o01 = A[0] * d01 + A[1] * d11;
+  const double o10 = A[3] * d00 + A[4] * d10, o11 = A[3] * d01 + A[4] * d11;
+  const double ot0 = A[0] * dt0 + A[1] * dt1 + A[2], ot1 = A[3] * dt0 + A[4] * dt1 + A[5];
+  O[0] = o00;
+  O[1] = o01;
+  O[2] = ot0;
+  O[3] = o10;
+  O[4] = o11;
+  O[5] = ot1;
+}
+
+hipError_t launch_join_break(int S, int j, const double* in, const double* left, double* out, hipStream_t st) {
+  if (S > 0) k_join_break<<<(S + 63) / 64, 64, 0, st>>>(S, j, in, left, out);
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ A pass can repeat steps 1-4 (the paper iterates until the SNR scores settle).
 align_mesh then replaces the section affines by a triangulated mesh of local
 affines (Section IV): the window centres are the mesh nodes and every
 triangle's affine is the least-squares fit of the matches in its band.
+repair_jumps mends breaks at abrupt content or magnification changes with
+one-sided models (Section III, model paragraphs).
 Every step is a library call on the current stream; Python only sequences
 them and reads a few scalars for reporting.
 """
@@ -145,3 +147,105 @@ def align_mesh(sw, raw, aff, level=0, n=256, grid=16, k=3, passes=2, p=0.65, ref
         if on_pass is not None:
             on_pass(rep_d, tri)
     return tri, reports
+
+
+def _spans(bad):
+    """Maximal runs [a, b] of True in a host list."""
+    spans, s = [], 0
+    while s < len(bad):
+        if bad[s]:
+            e = s
+            while e + 1 < len(bad) and bad[e + 1]:
+                e += 1
+            spans.append((s, e))
+            s = e + 1
+        else:
+            s += 1
+    return spans
+
+
+def _fit_against(sw, src, models, aff, level, grid, n, params, refine, tol, stop_frac, min_snr, idx=None):
+    """Windows of every section (or of the sections idx) through aff,
+    matched against models[s] with refinement; returns (fitted affines [S, 6]
+    (aff where not fitted), window theta_b, records)."""
+    S = src.shape[0]
+    g2 = grid * grid
+    _, hl, wl = src.shape
+    images = [src[s] for s in range(S)] + [models[s] for s in range(S)]
+    ia, ib, ta, tb = sw.stack_windows(aff, level, grid, hl, wl, 0, S)
+    if idx is not None:
+        sel = lambda t: t.view(S, g2, *t.shape[1:])[idx].reshape(-1, *t.shape[1:]).contiguous()  # noqa: E731
+        ia, ib, ta, tb = sel(ia), sel(ib), sel(ta), sel(tb)
+    ta, out, _ = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
+    fit = aff.clone()
+    if idx is None:
+        sw.fit_sections(ta, tb, out, g2, level, fit, min_snr=min_snr)
+    else:
+        part = aff[idx].contiguous()
+        sw.fit_sections(ta, tb, out, g2, level, part, min_snr=min_snr)
+        fit[idx] = part
+    return fit, tb, out
+
+
+def repair_jumps(sw, raw, aff, level=0, n=512, grid=8, k=3, break_px=2.0, frac=0.75, p=0.65, refine="adjoint",
+                 min_snr=6.0, tol=0.005, stop_frac=0.01, max_breaks=4, pyr=None):
+    """Jump repair (Section III, model paragraphs) of an aligned [S, H, W]
+    uint8 device stack with section affines aff [S, 6] (float64 device;
+    returns the repaired affines and a report).
+
+    1. Breaks: every section is matched (windows through its affine,
+       refined) against its left one-sided model and an affine is fitted.
+       The first section whose fit moves its window centres by more than
+       break_px (RMS, level-0 px) starts a break: the sections from it on are
+       joined to the frame before it (swift_join_break).  Repeated, left to
+       right, until no break is left (at most max_breaks).
+    2. Failed spans: runs of sections whose median window SNR against the
+       two-sided model is below frac times the stack median are matched
+       against the models on either side (offending sections omitted from
+       both) and fitted, and each span gets the Bezier blend from the left
+       fit to the right fit (swift_blend_span)."""
+    S, H, W = raw.shape
+    if pyr is None:
+        pyr = build_pyramid(sw, raw, level)
+    src = pyr[level]
+    params = make_params(p=p)
+    g2 = grid * grid
+    sc, hf = float(1 << level), (float(1 << level) - 1.0) / 2.0
+    torch.cuda.synchronize(raw.device)
+    t0 = time.perf_counter()
+    breaks = []
+    for _ in range(max_breaks):
+        rendered = sw.render(src, aff, level)
+        left = sw.project_side(rendered, k, -1)
+        fit, tb, _ = _fit_against(sw, src, left, aff, level, grid, n, params, refine, tol, stop_frac, min_snr)
+        # level-0 window centres and how far the left fit moves them
+        c = tb.view(S, g2, 8)[:, :, 0:2].double() * sc + hf
+        def move(a):
+            return torch.stack([a[:, None, 0] * c[..., 0] + a[:, None, 1] * c[..., 1] + a[:, None, 2],
+                                a[:, None, 3] * c[..., 0] + a[:, None, 4] * c[..., 1] + a[:, None, 5]], -1)
+        score = (move(fit) - move(aff)).square().sum(-1).mean(-1).sqrt().cpu().tolist()
+        j = next((s for s in range(1, S) if score[s] > break_px), None)
+        if j is None:
+            break
+        breaks.append(dict(section=j, rms_px=score[j]))
+        aff = sw.join_break(j, aff, fit)
+    rendered = sw.render(src, aff, level)
+    model = sw.project(rendered, k=k)
+    _, _, out = _fit_against(sw, src, model, aff, level, grid, n, params, None, tol, stop_frac, min_snr)
+    snr = parse_records(out)["snr"].float().view(S, g2).median(dim=1).values
+    bad = (snr < frac * snr.median()).cpu().tolist()
+    spans = _spans(bad)
+    if spans:
+        idx = torch.tensor([s for s in range(S) if bad[s]], dtype=torch.long, device=raw.device)
+        excl = torch.tensor(bad, dtype=torch.uint8, device=raw.device)
+        fits = {}
+        for side in (-1, 1):
+            one = sw.project_side(rendered, k, side, exclude=excl)
+            fits[side], _, _ = _fit_against(sw, src, one, aff, level, grid, n, params, refine, tol, stop_frac,
+                                            min_snr, idx=idx)
+        aff = aff.clone()
+        for (a, b) in spans:
+            sw.blend_span(a, b, fits[-1], fits[1], aff)
+    torch.cuda.synchronize(raw.device)
+    report = dict(breaks=breaks, spans=spans, section_snr=snr.cpu().tolist(), ms=(time.perf_counter() - t0) * 1e3)
+    return aff, report

@@ -79,6 +79,9 @@ def load_library(path: str = LIB_PATH):
     lib.swift_render.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, vp, i32, i32, i64, i64, vp]
     lib.swift_stack_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.swift_fit_sections.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp]
+    lib.swift_project_side.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i64, i64, vp]
+    lib.swift_blend_span.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+    lib.swift_join_break.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.swift_render_mesh.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i32, i32, i64, i64, vp]
     lib.swift_mesh_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.swift_fit_mesh.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp, vp]
@@ -388,6 +391,41 @@ class Swift:
                                            _ptr(recs_raw), int(level), float(min_snr), _ptr(aff), _ptr(status),
                                            self.stream()))
         return status
+
+    # ---- jump repair
+    def project_side(self, stack, k, side, exclude=None, out=None):
+        """One-sided models (side -1: the k sections before, +1: after) of a
+        [S, H, W] uint8 device stack; exclude: [S] uint8 device or None."""
+        assert stack.dtype == torch.uint8 and stack.dim() == 3 and stack.stride(2) == 1
+        S, H, W = stack.shape
+        if out is None:
+            out = torch.empty_like(stack)
+        ex = None if exclude is None else exclude.to(self.device, torch.uint8).contiguous()
+        _check(self.lib.swift_project_side(self.h, _ptr(stack), S, H, W, stack.stride(1), stack.stride(0), _ptr(ex),
+                                           int(k), int(side), _ptr(out), out.stride(1), out.stride(0),
+                                           self.stream()))
+        return out
+
+    def blend_span(self, a, b, aff_left, aff_right, aff):
+        """aff[a..b] <- Bezier blend of aff_left and aff_right (all [S, 6]
+        float64 device)."""
+        S = aff.shape[0]
+        for t in (aff_left, aff_right, aff):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.shape == (S, 6)
+        _check(self.lib.swift_blend_span(self.h, S, int(a), int(b), _ptr(aff_left), _ptr(aff_right), _ptr(aff),
+                                         self.stream()))
+        return aff
+
+    def join_break(self, j, aff, aff_left, out=None):
+        """Sections from j on composed with D = A_j^-1 L_j ([S, 6] float64
+        device; returns out)."""
+        S = aff.shape[0]
+        if out is None:
+            out = torch.empty_like(aff)
+        for t in (aff, aff_left, out):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.shape == (S, 6)
+        _check(self.lib.swift_join_break(self.h, S, int(j), _ptr(aff), _ptr(aff_left), _ptr(out), self.stream()))
+        return out
 
     # ---- local-affine triangle mesh: tri_aff [S, 2 (grid-1)^2, 6] float64 (device)
     @staticmethod

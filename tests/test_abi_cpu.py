@@ -65,4 +65,7 @@ def test_validation_without_gpu(lib):
     assert lib.swift_render_mesh(None, None, 1, 1, 1, 1, 1, None, 8, 0, None, 1, 1, 1, 1, None) == -1
     assert lib.swift_mesh_windows(None, 1, None, 0, 8, 64, 64, 0, 1, None, None, None, None, None) == -1
     assert lib.swift_fit_mesh(None, 1, 8, None, None, None, 0, 6.0, None, None, None, None) == -1
+    assert lib.swift_project_side(None, None, 1, 1, 1, 1, 1, None, 3, -1, None, 1, 1, None) == -1
+    assert lib.swift_blend_span(None, 4, 1, 2, None, None, None, None) == -1
+    assert lib.swift_join_break(None, 4, 1, None, None, None, None) == -1
     assert b"ctx" in lib.swift_last_error()

@@ -1,0 +1,87 @@
+"""Jump repair on the GPU (Section III, model paragraphs): one-sided models
+bit-exact against the oracle, the span blend and the break join against the
+oracle's FP64 formulas, and the whole repair on a stack with a magnification
+change against the generator's known section warps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1612_04787_amd as sw
+    c = sw.Swift(0)
+    yield c
+    c.close()
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("w", [48, 45])
+def test_project_side_bit_exact(ctx, k, w):
+    print("case project_side k=%d w=%d" % (k, w), flush=True)
+    rng = np.random.default_rng(70 + k + w)
+    st = rng.integers(0, 256, (11, 21, w)).astype(np.uint8)
+    excl = np.zeros(11, np.uint8)
+    excl[[2, 7]] = 1
+    t = torch.from_numpy(st).to(dev())
+    for side in (-1, 1):
+        for ex in (None, excl):
+            got = ctx.project_side(t, k, side, exclude=None if ex is None else torch.from_numpy(ex)).cpu().numpy()
+            for s in range(11):
+                ref = O.project_side(st, s, k, side, None if ex is None else ex.astype(bool))
+                np.testing.assert_array_equal(got[s], ref, err_msg="side %d section %d" % (side, s))
+
+
+def test_blend_and_join_match_oracle(ctx):
+    print("case blend / join", flush=True)
+    rng = np.random.default_rng(71)
+    S = 9
+    base = np.array([[1 + rng.uniform(-1e-3, 1e-3), rng.uniform(-1e-3, 1e-3), rng.uniform(-9, 9),
+                      rng.uniform(-1e-3, 1e-3), 1 + rng.uniform(-1e-3, 1e-3), rng.uniform(-9, 9)] for _ in range(S)])
+    L = base + rng.uniform(-0.5, 0.5, (S, 6)) * [1e-3, 1e-3, 2, 1e-3, 1e-3, 2]
+    R = base + rng.uniform(-0.5, 0.5, (S, 6)) * [1e-3, 1e-3, 2, 1e-3, 1e-3, 2]
+    aff = torch.from_numpy(base.copy()).to(dev())
+    ctx.blend_span(3, 5, torch.from_numpy(L).to(dev()), torch.from_numpy(R).to(dev()), aff)
+    got = aff.cpu().numpy()
+    np.testing.assert_array_equal(got[:3], base[:3])
+    np.testing.assert_array_equal(got[6:], base[6:])
+    np.testing.assert_allclose(got[3:6], O.blend_span(L, R, 3, 5), rtol=0, atol=1e-12)
+    Lj = base.copy()
+    Lj[4] = [1.02, 0.001, -30.0, -0.002, 1.019, 42.0]
+    out = ctx.join_break(4, torch.from_numpy(base).to(dev()), torch.from_numpy(Lj).to(dev())).cpu().numpy()
+    np.testing.assert_allclose(out, O.join_break(base, Lj, 4), rtol=0, atol=1e-9)
+
+
+def test_repair_joins_a_magnification_break(ctx):
+    """10 sections of 2048^2 with drift, section affines and a 3% magnification
+    change at section 5: the section-affine loop leaves a break between
+    sections 4 and 5; the repair finds it and joins the two sides."""
+    from datagen.evaluate import composed_points
+    from datagen.workloads import jump_stack
+    from paper_1612_04787_amd.stack import align_stack, repair_jumps
+    print("case repair 10 x 2048^2", flush=True)
+    S, size, j0 = 10, 2048, 5
+    stack, warps = jump_stack(S, size, seed=17, j0=j0, mag=0.03, device=dev())
+    aff, _ = align_stack(ctx, stack, levels=(1, 0), ns=(128, 256), iters=(2, 1), ks=(4, 3), grid=8)
+    pts = np.array([(size // 16 + size // 8 * i, size // 16 + size // 8 * j) for j in range(8) for i in range(8)],
+                   np.float64)
+
+    def pair_res(a):
+        c = composed_points(a.cpu().numpy(), warps, pts)
+        return np.sqrt(np.mean(np.sum((c[1:] - c[:-1]) ** 2, 2), 1))
+
+    r0 = pair_res(aff)
+    aff2, rep = repair_jumps(ctx, stack, aff.clone(), level=0, n=256, grid=8, k=3)
+    r1 = pair_res(aff2)
+    print("pair residuals before", np.round(r0, 2), "after", np.round(r1, 2), rep["breaks"], rep["spans"], flush=True)
+    assert r0[j0 - 1] > 5.0  # the loop left a break
+    assert [b["section"] for b in rep["breaks"]] == [j0]
+    assert r1.max() < 0.25 * r0.max()

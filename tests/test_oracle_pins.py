@@ -885,3 +885,29 @@ def test_failed_spans_runs():
     snr = [30, 31, 29, 8, 7, 30, 32, 10, 31]
     assert O.failed_spans(snr, 0.5) == [(3, 4), (7, 7)]
     assert O.failed_spans([20] * 5, 0.5) == []
+
+
+def test_join_break_closed_forms():
+    rng = np.random.default_rng(61)
+    S, j = 7, 3
+    aff = np.array([[1 + rng.uniform(-1e-3, 1e-3), rng.uniform(-1e-3, 1e-3), rng.uniform(-5, 5),
+                     rng.uniform(-1e-3, 1e-3), 1 + rng.uniform(-1e-3, 1e-3), rng.uniform(-5, 5)] for _ in range(S)])
+    left = aff.copy()
+    left[j] = [1.02, 0.001, -30.0, -0.002, 1.019, 42.0]
+    out = O.join_break(aff, left, j)
+    # sections before the break are untouched, section j becomes its left fit
+    np.testing.assert_array_equal(out[:j], aff[:j])
+    np.testing.assert_allclose(out[j], left[j], rtol=0, atol=1e-12)
+    # every later section moves by the same aligned-frame correction: mapping
+    # its new affine back through its old one gives that correction
+    p = rng.uniform(0, 4096, (20, 2))
+    def app(a, q):
+        return np.stack(O.apply_affine(a, q[:, 0], q[:, 1]), 1)
+    def inv(a):
+        m = np.array([[a[0], a[1]], [a[3], a[4]]])
+        mi = np.linalg.inv(m)
+        t = -mi @ np.array([a[2], a[5]])
+        return [mi[0, 0], mi[0, 1], t[0], mi[1, 0], mi[1, 1], t[1]]
+    d_j = app(inv(aff[j]), app(out[j], p))
+    for s in range(j + 1, S):
+        np.testing.assert_allclose(app(inv(aff[s]), app(out[s], p)), d_j, rtol=0, atol=1e-8)
