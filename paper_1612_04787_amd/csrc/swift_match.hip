@@ -824,19 +824,34 @@ __global__ void __launch_bounds__(64) k_ncc_energy(MatchArgs a) {
   if (j >= NP) return;
   const float2* rb = a.ncc_rows + (size_t)pair * N * NP + j;
   float* V = a.ncc_var + (size_t)pair * NP * NP + j;
+  constexpr int U = 8;  // rows per batch of loads, all issued before any store
+  static_assert(M % U == 0, "placements per column minus one divide into batches");
   double e1 = 0.0, e2 = 0.0;
-  for (int y = 0; y < M; ++y) {
-    const float2 r = rb[(size_t)y * NP];
-    e1 += r.x;
-    e2 += r.y;
+  for (int y0 = 0; y0 < M; y0 += U) {
+    float2 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = rb[(size_t)(y0 + u) * NP];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      e1 += r[u].x;
+      e2 += r[u].y;
+    }
   }
   const double inv = 1.0 / ((double)M * (double)M);
   V[0] = (float)fmax(e2 - e1 * e1 * inv, 0.0);
-  for (int i = 1; i < NP; ++i) {
-    const float2 ro = rb[(size_t)(i - 1) * NP], rn = rb[(size_t)(i + M - 1) * NP];
-    e1 += (double)rn.x - (double)ro.x;
-    e2 += (double)rn.y - (double)ro.y;
-    V[(size_t)i * NP] = (float)fmax(e2 - e1 * e1 * inv, 0.0);
+  for (int i0 = 1; i0 < NP; i0 += U) {
+    float2 ro[U], rn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ro[u] = rb[(size_t)(i0 + u - 1) * NP];
+      rn[u] = rb[(size_t)(i0 + u + M - 1) * NP];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      e1 += (double)rn[u].x - (double)ro[u].x;
+      e2 += (double)rn[u].y - (double)ro[u].y;
+      V[(size_t)(i0 + u) * NP] = (float)fmax(e2 - e1 * e1 * inv, 0.0);
+    }
   }
 }
 
