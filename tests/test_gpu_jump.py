@@ -85,3 +85,20 @@ def test_repair_joins_a_magnification_break(ctx):
     assert r0[j0 - 1] > 5.0  # the loop left a break
     assert [b["section"] for b in rep["breaks"]] == [j0]
     assert r1.max() < 0.25 * r0.max()
+
+
+def test_repair_leaves_a_smooth_stack_alone(ctx):
+    """The same stack without the magnification change: no break, no failed
+    span, affines unchanged."""
+    from datagen.workloads import jump_stack
+    from paper_1612_04787_amd.stack import align_stack, repair_jumps
+    print("case repair without a jump", flush=True)
+    S, size = 10, 2048
+    stack, _ = jump_stack(S, size, seed=17, j0=S, mag=0.03, device=dev())  # j0 = S: no section changes
+    aff, _ = align_stack(ctx, stack, levels=(1, 0), ns=(128, 256), iters=(2, 1), ks=(4, 3), grid=8)
+    before = aff.clone()
+    aff2, rep = repair_jumps(ctx, stack, aff, level=0, n=256, grid=8, k=3)
+    torch.cuda.synchronize()
+    print("breaks", rep["breaks"], "spans", rep["spans"], flush=True)
+    assert rep["breaks"] == [] and rep["spans"] == []
+    assert torch.equal(aff2, before)
