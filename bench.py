@@ -59,6 +59,50 @@ def kernel_bytes(name: str, n: int, pairs: int, sections: int, size: int) -> flo
     return per * pairs
 
 
+def kept_rows(n: int, radius: int, inv_rows: int) -> int:
+    """Surface rows the pruned column pass writes back for a search radius:
+    |y| <= radius + 1, rounded out to whole inverse row blocks (the library's
+    rule; every row when the blocks would overlap)."""
+    rr, blocks = radius + 1, n // inv_rows
+    lo, hs = rr // inv_rows + 1, (n - rr) // inv_rows
+    return n if lo >= hs else (lo + blocks - hs) * inv_rows
+
+
+def variant_bytes(name: str, n: int, pairs: int, rows: int, pearson: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel of the pruned or
+    Pearson step: as kernel_bytes, with rows surface rows written back by the
+    column pass and read by the inverse row pass, and the Pearson row sums
+    (f', f'^2 per row and placement) and patch energies."""
+    nn = float(n) * n
+    npl = n // 2 + 1
+    if name.startswith("k_row_fwd"):
+        per = 2 * nn + 8 * nn + (8.0 * n * npl if pearson else 0.0)
+    elif name.startswith("k_col"):
+        per = 8 * nn + 8.0 * rows * npl
+    elif name.startswith("k_row_inv"):
+        per = 8.0 * rows * npl + (4.0 * npl * npl if pearson else 0.0)
+    elif name.startswith("k_ncc_energy"):
+        per = 8.0 * n * npl + 4.0 * npl * npl
+    else:
+        return kernel_bytes(name, n, pairs, S_SECTIONS, SIZE)
+    return per * pairs
+
+
+def variant_kernels(prof, n, pairs, rows, pearson):
+    """Per-kernel launches, average ms, algorithmic bytes and GB/s of a step
+    variant, and the HBM roofline of its longest kernel."""
+    kernels = {}
+    for name, (cnt, tot) in prof.items():
+        avg = tot / cnt
+        b = variant_bytes(name, n, pairs, rows, pearson)
+        kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    d = kernels[dom]
+    roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=d["gbs"] / HBM_PEAK_GBS, traffic=None, bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
+    return kernels, roof
+
+
 def pair_bytes(n: int) -> float:
     """Algorithmic bytes per pair of the whole match path: uint8 inputs, the
     record, and one write + read of each exchanged spectrum."""
@@ -337,7 +381,8 @@ def pearson_block(ctx, sw, stack, refs, table, images, pairs, res_w, args, prof_
     for _ in range(prof_steps):
         step()
     torch.cuda.synchronize()
-    kp = {name: dict(launches=cnt, avg_ms=tot / cnt) for name, (cnt, tot) in ctx.profile_read().items()}
+    rows = kept_rows(N, N // 4, ctx.plan(N)[1])
+    kp, roof = variant_kernels(ctx.profile_read(), N, P, rows, True)
     ctx.profile(False)
     r = sw.parse_records(out)
     same = (r["ix"] == res_w["ix"]) & (r["iy"] == res_w["iy"])
@@ -346,7 +391,7 @@ def pearson_block(ctx, sw, stack, refs, table, images, pairs, res_w, args, prof_
     # single-shot shifts of both scores sit near whole pixels (3 x 3 centroid),
     # so they are compared within one pixel; the SNR is the paper's comparison
     return dict(template_px=N // 2, range_px=N // 4, ms_per_step=ms, pairs_per_s=P / (ms / 1e3),
-                workspace_gb=need / 1e9, kernels=kp, same_peak_frac=float(same.float().mean()),
+                workspace_gb=need / 1e9, kernels=kp, roofline=roof, same_peak_frac=float(same.float().mean()),
                 frac_shift_within_1px=float((dd <= 1.0).float().mean()),
                 median_abs_shift_diff_px=float(dd.median()), median_peak_coefficient=float(r["peak"].median()),
                 median_snr=float(r["snr"].median()), median_snr_whitened=float(res_w["snr"].median()))
@@ -419,6 +464,41 @@ def mesh_block(ctx, dev, sections=MESH_SECTIONS, size=SIZE, grid=MESH_GRID, n=ME
     del stack, pyr, out
     torch.cuda.empty_cache()
     return res, sample
+
+
+def cpu_baseline_variants(stack_cpu, refs_cpu, centres, n_pruned=32):
+    """The oracle on the pruned and Pearson variants of the benchmark pairs,
+    one process: n_pruned pairs with the search radius (the oracle computes
+    the whole surface either way), and one pair scored by Pearson
+    coefficients at every placement (direct per-placement sums)."""
+    import numpy as np
+
+    import oracle as O
+    rng = np.random.default_rng(3)
+    H = stack_cpu.shape[1]
+    m = 4
+    crops = []
+    for _ in range(n_pruned):
+        s = int(rng.integers(0, stack_cpu.shape[0]))
+        cx, cy = centres[int(rng.integers(0, len(centres)))]
+        x0, y0 = int(max(cx - N // 2 - m, 0)), int(max(cy - N // 2 - m, 0))
+        x1, y1 = int(min(cx + N // 2 + m, H)), int(min(cy + N // 2 + m, H))
+        th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+        crops.append((stack_cpu[s, y0:y1, x0:x1].copy(), refs_cpu[s, y0:y1, x0:x1].copy(), th))
+    t0 = time.perf_counter()
+    for (wa, wb, th) in crops:
+        O.match_pair(wa, wb, th, th, N, O.Params(p=P_WHITEN, max_shift=PRUNE_R))
+    tp = time.perf_counter() - t0
+    wa, wb, th = crops[0]
+    t0 = time.perf_counter()
+    O.pearson_pair(wa, wb, th, th, N)
+    tq = time.perf_counter() - t0
+    return dict(pruned=dict(value=n_pruned / tp, unit="pairs/s", cores=1, kind="oracle",
+                            sample="%d pairs of %d^2 of the benchmark batch, radius %d, FP64 NumPy, one process; "
+                                   "%.1f s" % (n_pruned, N, PRUNE_R, tp)),
+                pearson=dict(value=1.0 / tq, unit="pairs/s", cores=1, kind="oracle",
+                             sample="1 pair of %d^2 of the benchmark batch, Pearson coefficient at each of the "
+                                    "%d placements, FP64 NumPy, one process; %.1f s" % (N, (N // 2 + 1) ** 2, tq)))
 
 
 def cpu_baseline_mesh(sample, n_px=1 << 23):
@@ -607,13 +687,14 @@ def main():
         for _ in range(prof_steps):
             step_p()
         torch.cuda.synchronize()
-        kp = {name: dict(launches=cnt, avg_ms=tot / cnt) for name, (cnt, tot) in ctx.profile_read().items()}
+        rows_p = kept_rows(N, PRUNE_R, ctx.plan(N)[1])
+        kp, roof_p = variant_kernels(ctx.profile_read(), N, P, rows_p, False)
         ctx.profile(False)
         rp = sw.parse_records(out_p)
         same = (rp["ix"] == res["ix"]) & (rp["iy"] == res["iy"])
         dd = torch.maximum((rp["dx"] - res["dx"]).abs(), (rp["dy"] - res["dy"]).abs())[same]
-        pruned = dict(radius_px=PRUNE_R, ms_per_step=ms_p, pairs_per_s=P / (ms_p / 1e3), speedup=ms / ms_p,
-                      kernels=kp, same_peak_frac=float(same.float().mean()),
+        pruned = dict(radius_px=PRUNE_R, rows_kept=rows_p, ms_per_step=ms_p, pairs_per_s=P / (ms_p / 1e3),
+                      speedup=ms / ms_p, kernels=kp, roofline=roof_p, same_peak_frac=float(same.float().mean()),
                       max_subpixel_diff_px=float(dd.max()) if dd.numel() else None,
                       max_snr_rel_diff=float(((rp["snr"] - res["snr"]).abs() / res["snr"].abs()).max()))
         log("pruned (r=%d): %.3f ms/step (%.2fx), same peak %.4f" % (PRUNE_R, ms_p, ms / ms_p,
@@ -692,6 +773,8 @@ def main():
         log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
         if mesh_sample is not None:
             line["cpu_baseline"]["mesh_render"] = cpu_baseline_mesh(mesh_sample)
+        if not (args.no_prune and args.no_pearson):
+            line["cpu_baseline"].update(cpu_baseline_variants(stack.cpu().numpy(), refs.cpu().numpy(), cen))
     if not args.no_ragged:
         log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
         del stack, refs, images, table, out
