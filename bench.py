@@ -501,6 +501,23 @@ def cpu_baseline_variants(stack_cpu, refs_cpu, centres, n_pruned=32):
                                     "%d placements, FP64 NumPy, one process; %.1f s" % (N, (N // 2 + 1) ** 2, tq)))
 
 
+def cpu_baseline_jump(sample):
+    """The oracle's one-sided models (left and right, k = 3) of every section
+    of a crop of the jump stack (the top eighth of each section), one
+    process, in Mpixel/s of models."""
+    import oracle as O
+    S = sample.shape[0]
+    t0 = time.perf_counter()
+    for side in (-1, 1):
+        for s in range(S):
+            O.project_side(sample, s, 3, side)
+    el = time.perf_counter() - t0
+    px = 2.0 * S * sample.shape[1] * sample.shape[2]
+    return dict(value=px / el / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
+                sample="left and right models (k = 3) of %d sections of %d x %d px, integer NumPy, one "
+                       "process; %.1f s" % (S, sample.shape[1], sample.shape[2], el))
+
+
 def cpu_baseline_mesh(sample, n_px=1 << 23):
     """The oracle's mesh render on a bounded sample of pixels of one section
     (one process, FP64 NumPy), in Mpixel/s."""
@@ -543,17 +560,27 @@ def jump_block(ctx, dev, sections=16, size=SIZE, j0=8, mag=0.02):
         return np.sqrt(np.mean(np.sum((c[1:] - c[:-1]) ** 2, 2), 1))
 
     r0 = pair_res(aff)
+    torch.cuda.synchronize()
+    ctx.profile(True)
     aff2, rep = repair_jumps(ctx, stack, aff.clone(), level=0, n=512, grid=8, k=3, pyr=pyr)
+    prof = ctx.profile_read()
+    ctx.profile(False)
     r1 = pair_res(aff2)
+    kernels = {}
+    for name, (cnt, tot) in prof.items():
+        kernels[name] = dict(launches=cnt, avg_ms=tot / cnt)
+        if name.startswith("k_project"):  # every section read once, every model written once
+            kernels[name]["gbs"] = 2.0 * sections * size * size / (tot / cnt / 1e3) / 1e9
+    sample = stack[:, : size // 8].cpu().numpy()
     del stack, pyr
     torch.cuda.empty_cache()
     return dict(workload="%d sections of %d^2 with drift and section affines, magnification change of %.0f%% at "
                          "section %d; section-affine loop at levels 2/1/0, then repair at level 0 (512^2 windows)"
                          % (sections, size, 100 * mag, j0),
-                breaks=rep["breaks"], spans=rep["spans"], repair_ms=rep["ms"],
+                breaks=rep["breaks"], spans=rep["spans"], repair_ms=rep["ms"], kernels=kernels,
                 pair_residual_px={"max_before": float(r0.max()), "at_jump_before": float(r0[j0 - 1]),
                                   "max_after": float(r1.max()), "at_jump_after": float(r1[j0 - 1]),
-                                  "median_after": float(np.median(r1))})
+                                  "median_after": float(np.median(r1))}), sample
 
 
 # --------------------------------------------------------------------------- main
@@ -751,9 +778,10 @@ def main():
         log("stack loop: %.0f ms, residual global %.2f -> %.2f px, neighbour %.2f -> %.2f px"
             % (line["stack_loop"]["wall_ms"], r["global_before"], r["global_after"], r["neighbour_before"],
                r["neighbour_after"]))
+    jump_sample = None
     if not args.no_jump:
         log("jump repair: a stack with a magnification change ...")
-        line["jump_repair"] = jump_block(ctx, dev)
+        line["jump_repair"], jump_sample = jump_block(ctx, dev)
         jr = line["jump_repair"]["pair_residual_px"]
         log("jump repair: break %.2f px -> %.2f px (max pair %.2f -> %.2f), %.0f ms"
             % (jr["at_jump_before"], jr["at_jump_after"], jr["max_before"], jr["max_after"],
@@ -773,6 +801,8 @@ def main():
         log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
         if mesh_sample is not None:
             line["cpu_baseline"]["mesh_render"] = cpu_baseline_mesh(mesh_sample)
+        if jump_sample is not None:
+            line["cpu_baseline"]["jump_models"] = cpu_baseline_jump(jump_sample)
         if not (args.no_prune and args.no_pearson):
             line["cpu_baseline"].update(cpu_baseline_variants(stack.cpu().numpy(), refs.cpu().numpy(), cen))
     if not args.no_ragged:
