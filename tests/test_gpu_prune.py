@@ -190,3 +190,40 @@ def test_pruned_forward_feeds_the_adjoint(ctx, section_pair_small):
     scale = jf.abs().max().item()
     assert (jf - jp).abs().max().item() <= 1e-4 * scale
     assert (gf - gp).abs().max().item() <= 1e-3 * gf.abs().max().item()
+
+
+def test_pruned_and_pearson_with_alternative_row_plans(ctx, section_pair_small):
+    """The pruned row blocks follow the inverse pass's row count: with the
+    alternative row-count variants the pruned and Pearson records agree with
+    the default plan's (same peaks; sums in another order)."""
+    import paper_1612_04787_amd as sw
+    print("case prune / pearson plans", flush=True)
+    a, b = section_pair_small
+    rng = np.random.default_rng(7400)
+    ns, tha, thb = [], [], []
+    for n in (128, 256, 512):
+        ta, tb = _windows(rng, 2, n, 8)
+        ns += [n, n]
+        tha.append(ta)
+        thb.append(tb)
+    tha, thb = np.concatenate(tha), np.concatenate(thb)
+    k = len(ns)
+    args = ([a.to(dev()), b.to(dev())], ns, torch.zeros(k, dtype=torch.int32), torch.ones(k, dtype=torch.int32),
+            torch.from_numpy(tha), torch.from_numpy(thb))
+    prms = [sw.make_params(p=0.65, max_shift=8), sw.make_params(flags=sw.FLAG_PEARSON)]
+    ref = [ctx.match_batch(*args, pr) for pr in prms]
+    saved = {n: ctx.plan(n) for n in (128, 256, 512)}
+    try:
+        for n in (128, 256, 512):
+            ctx.plan(n, 1, 1)
+        alt = [ctx.match_batch(*args, pr) for pr in prms]
+        torch.cuda.synchronize()
+    finally:
+        for n in (128, 256, 512):
+            ctx.plan(n, 0, 0)
+    for r0, r1 in zip(ref, alt):
+        assert torch.equal(r0["ix"], r1["ix"]) and torch.equal(r0["iy"], r1["iy"])
+        assert float((r0["dx"] - r1["dx"]).abs().max()) <= 1e-4
+        assert float((r0["dy"] - r1["dy"]).abs().max()) <= 1e-4
+        assert float(((r0["snr"] - r1["snr"]) / r0["snr"]).abs().max()) <= 1e-4
+    assert saved[512] == ctx.plan(512)
