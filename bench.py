@@ -33,6 +33,7 @@ METRIC = "512² window-pair matches/sec + HBM GB/s; plain vs batched+adjoint at 
 HBM_PEAK_GBS = 8000.0
 S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
 PRUNE_R = N // 8  # search radius of the pruned-inverse variant (64 px at 512^2)
+REFINE_R = 8      # search radius of the pruned refinement (its shifts stay below a pixel)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_match_512_headline.txt")
 
 
@@ -185,7 +186,7 @@ def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section
 
 
 # --------------------------------------------------------------------------- refinement comparison
-def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
+def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9, max_shift=0):
     """Plain (centroid) vs batched + adjoint (Newton on the centroid) window
     refinement to a known sub-pixel truth, over the benchmark's 4096 window
     positions: window B samples section s at a fractional translation t*
@@ -194,7 +195,9 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
     (bilinear sampling on both sides).  Both drivers stop when the longest
     step of the batch is below `tol` px.  Reports wall time, iterations, the
     final RMS / max error, and the iteration and time at which the RMS error
-    first reaches `target`."""
+    first reaches `target`.  max_shift > 0 runs every match of both drivers
+    with the pruned inverse (peak searched within that radius; the
+    refinement's shifts stay below a pixel)."""
     import numpy as np
     import torch
 
@@ -215,7 +218,7 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
     idx = torch.arange(S, device=dev, dtype=torch.int32).repeat_interleave(len(cen))
     tha, thb = torch.from_numpy(ta).to(dev), torch.from_numpy(tb).to(dev)
     truth = thb[:, [4, 7]].clone()
-    params = sw.make_params(p=P_WHITEN)
+    params = sw.make_params(p=P_WHITEN, max_shift=max_shift)
     n_list = [N] * P
 
     def rms_max(th):
@@ -251,7 +254,7 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9):
                      "centroid shift with the Jacobian (translation columns) from one adjoint pass per iteration",
                 workload="%d windows of %d^2 (the benchmark's window grid), truth = fractional translation of "
                          "window B, start U(-0.5, 0.5)^2 px away" % (P, N),
-                start_rms_px=r0, tol_px=tol, target_rms_px=target, **out)
+                search_radius_px=max_shift, start_rms_px=r0, tol_px=tol, target_rms_px=target, **out)
 
 
 # --------------------------------------------------------------------------- ragged levels
@@ -767,10 +770,13 @@ def main():
         log("refinement: plain vs batched + adjoint to 0.01 px ...")
         del ws
         line["refine"] = refine_comparison(ctx, sw, stack, cen, dev)
-        rf = line["refine"]
-        log("refinement: plain %d it %.1f ms (rms %.2e) | adjoint %d it %.1f ms (rms %.2e)"
-            % (rf["plain"]["iterations"], rf["plain"]["wall_ms"], rf["plain"]["rms_px"],
-               rf["adjoint"]["iterations"], rf["adjoint"]["wall_ms"], rf["adjoint"]["rms_px"]))
+        line["refine_pruned"] = refine_comparison(ctx, sw, stack, cen, dev, max_shift=REFINE_R)
+        for key in ("refine", "refine_pruned"):
+            rf = line[key]
+            log("%s: to 0.01 px plain %s it %.1f ms | adjoint %s it %.1f ms; final rms plain %.2e adjoint %.2e"
+                % (key, rf["plain"]["iters_to_target"], rf["plain"]["ms_to_target"] or -1,
+                   rf["adjoint"]["iters_to_target"], rf["adjoint"]["ms_to_target"] or -1, rf["plain"]["rms_px"],
+                   rf["adjoint"]["rms_px"]))
     if not args.no_stack:
         log("stack loop: 3 passes of render / project / match + refine / fit ...")
         line["stack_loop"] = stack_loop(ctx, stack, warps)
