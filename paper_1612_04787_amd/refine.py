@@ -16,7 +16,9 @@ slope J is well below 1), so the plain iteration contracts the error by only
 |1 - J| per step, while Newton's reaches the 0.01 px level in a few steps.
 Both stop when the longest step of the batch is below `tol` pixels.  Each
 iteration is a fixed sequence of launches on the current stream; the only
-host synchronisation is reading the longest step.
+host synchronisation is reading the longest step.  params may carry a search
+radius (max_shift): every match of the driver then uses the pruned inverse,
+which finds the full search's peaks while the shifts stay inside it.
 """
 from __future__ import annotations
 
@@ -72,7 +74,7 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
     Newton step uses no others)."""
     from .swift import FLAG_JAC_TRANSLATION, make_params
     jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
-                          params.flags | FLAG_JAC_TRANSLATION)
+                          params.flags | FLAG_JAC_TRANSLATION, params.max_shift)
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
     P = prep["pairs"].n_pairs
     out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=sw.device)
