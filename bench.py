@@ -89,9 +89,10 @@ def variant_bytes(name: str, n: int, pairs: int, rows: int, pearson: bool) -> fl
     return per * pairs
 
 
-def variant_kernels(prof, n, pairs, rows, pearson):
+def variant_kernels(prof, n, pairs, rows, pearson, traffic_file=None):
     """Per-kernel launches, average ms, algorithmic bytes and GB/s of a step
-    variant, and the HBM roofline of its longest kernel."""
+    variant, and the HBM roofline of its longest kernel (with the measured
+    traffic of traffic_file when it belongs to the current kernel sources)."""
     kernels = {}
     for name, (cnt, tot) in prof.items():
         avg = tot / cnt
@@ -99,8 +100,17 @@ def variant_kernels(prof, n, pairs, rows, pearson):
         kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     d = kernels[dom]
+    traffic = None
+    if traffic_file is not None:
+        from paper_1612_04787_amd.counters import read_traffic, source_digest
+        # the library timer names the Pearson row pass k_row_fwd<N>; its
+        # rocprofv3 summary names the instance apart
+        name = dom.replace("k_row_fwd", "k_row_fwd_pearson") if pearson else dom
+        traffic, digest = read_traffic(traffic_file, name)
+        if digest != source_digest():
+            traffic = None
     roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=d["gbs"] / HBM_PEAK_GBS, traffic=None, bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
+                frac=d["gbs"] / HBM_PEAK_GBS, traffic=traffic, bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
     return kernels, roof
 
 
@@ -385,7 +395,8 @@ def pearson_block(ctx, sw, stack, refs, table, images, pairs, res_w, args, prof_
         step()
     torch.cuda.synchronize()
     rows = kept_rows(N, N // 4, ctx.plan(N)[1])
-    kp, roof = variant_kernels(ctx.profile_read(), N, P, rows, True)
+    kp, roof = variant_kernels(ctx.profile_read(), N, P, rows, True,
+                               os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pearson.txt"))
     ctx.profile(False)
     r = sw.parse_records(out)
     same = (r["ix"] == res_w["ix"]) & (r["iy"] == res_w["iy"])
@@ -718,7 +729,8 @@ def main():
             step_p()
         torch.cuda.synchronize()
         rows_p = kept_rows(N, PRUNE_R, ctx.plan(N)[1])
-        kp, roof_p = variant_kernels(ctx.profile_read(), N, P, rows_p, False)
+        kp, roof_p = variant_kernels(ctx.profile_read(), N, P, rows_p, False,
+                                     os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pruned_r64.txt"))
         ctx.profile(False)
         rp = sw.parse_records(out_p)
         same = (rp["ix"] == res["ix"]) & (rp["iy"] == res["iy"])
