@@ -464,8 +464,13 @@ def mesh_block(ctx, dev, sections=MESH_SECTIONS, size=SIZE, grid=MESH_GRID, n=ME
                     fp64_tops=RENDER_FP64_OPS * px / (ms / 1e3) / 1e12)
 
     rm, rg = rate("k_render_mesh<0>"), rate("k_render<0>")
+    from paper_1612_04787_amd.counters import read_traffic, source_digest
+    traffic, digest = read_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_mesh_render_16x4096.txt"),
+                                   "k_render_mesh")
+    if digest != source_digest():
+        traffic = None
     roof = {"bound": "alu", "achieved": rm["fp64_tops"], "peak": FP64_VALU_PEAK_TOPS, "unit": "TFLOP/s",
-            "frac": rm["fp64_tops"] / FP64_VALU_PEAK_TOPS, "traffic": None}
+            "frac": rm["fp64_tops"] / FP64_VALU_PEAK_TOPS, "traffic": traffic}
     res = dict(workload="%d sections of %d^2 with drift, affine distortion and a smooth bend of up to %.0f px; "
                         "global affines (levels 2/1/0), then 2 mesh passes at level 0 with %d x %d nodes and "
                         "%d^2 windows" % (sections, size, MESH_BEND, grid, grid, n),
