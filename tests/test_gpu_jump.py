@@ -102,3 +102,22 @@ def test_repair_leaves_a_smooth_stack_alone(ctx):
     print("breaks", rep["breaks"], "spans", rep["spans"], flush=True)
     assert rep["breaks"] == [] and rep["spans"] == []
     assert torch.equal(aff2, before)
+
+
+def test_jump_entry_points_reject_bad_arguments(ctx):
+    import paper_1612_04787_amd as sw
+    print("case jump validation", flush=True)
+    lib = ctx.lib
+    p = lambda t: sw.swift._ptr(t)  # noqa: E731
+    st = torch.zeros((4, 8, 16), dtype=torch.uint8, device=dev())
+    out = torch.empty_like(st)
+    assert lib.swift_project_side(ctx.h, p(st), 4, 8, 16, 16, 128, None, 3, 0, p(out), 16, 128, ctx.stream()) == -1
+    assert b"side" in lib.swift_last_error()
+    assert lib.swift_project_side(ctx.h, p(st), 4, 8, 16, 16, 128, None, 9, 1, p(out), 16, 128, ctx.stream()) == -1
+    aff = torch.zeros((4, 6), dtype=torch.float64, device=dev())
+    other = torch.zeros_like(aff)
+    assert lib.swift_blend_span(ctx.h, 4, 2, 4, p(aff), p(other), p(aff), ctx.stream()) == -1
+    assert lib.swift_blend_span(ctx.h, 4, 3, 2, p(aff), p(other), p(aff), ctx.stream()) == -1
+    assert lib.swift_join_break(ctx.h, 4, 1, p(aff), p(other), p(aff), ctx.stream()) == -1
+    assert b"alias" in lib.swift_last_error()
+    assert lib.swift_join_break(ctx.h, 4, 4, p(aff), p(other), p(other), ctx.stream()) == -1

@@ -173,3 +173,28 @@ def test_align_mesh_reduces_nonlinear_misalignment(ctx):
           % (n_aff, n_mesh, g_aff, g_mesh, [(r["median_snr"], r["singular_triangles"]) for r in rep]), flush=True)
     assert n_mesh < 0.5 * n_aff
     assert rep[-1]["singular_triangles"] == 0
+
+
+def test_mesh_entry_points_reject_bad_arguments(ctx):
+    import paper_1612_04787_amd as sw
+    print("case mesh validation", flush=True)
+    lib = ctx.lib
+    src = torch.zeros((1, 64, 64), dtype=torch.uint8, device=dev())
+    tri = torch.zeros((1, 2, 6), dtype=torch.float64, device=dev())
+    out = torch.empty_like(src)
+    p = lambda t: sw.swift._ptr(t)  # noqa: E731
+    # grid 1 (no cell), a grid larger than the frame, a frame beyond 65535
+    assert lib.swift_render_mesh(ctx.h, p(src), 1, 64, 64, 64, 4096, p(tri), 1, 0, p(out), 64, 64, 64, 4096,
+                                 ctx.stream()) == -1
+    assert lib.swift_render_mesh(ctx.h, p(src), 1, 64, 64, 64, 4096, p(tri), 65, 0, p(out), 64, 64, 64, 4096,
+                                 ctx.stream()) == -1
+    assert b"grid" in lib.swift_last_error()
+    ta = torch.empty((4, 8), dtype=torch.float32, device=dev())
+    ii = torch.empty(4, dtype=torch.int32, device=dev())
+    assert lib.swift_mesh_windows(ctx.h, 1, p(tri), 0, 2, 70000, 64, 0, 1, p(ta), p(ta), p(ii), p(ii),
+                                  ctx.stream()) == -1
+    assert b"65535" in lib.swift_last_error()
+    rec = torch.zeros((4, 64), dtype=torch.uint8, device=dev())
+    aff = torch.zeros((1, 6), dtype=torch.float64, device=dev())
+    assert lib.swift_fit_mesh(ctx.h, 1, 1025, p(ta), p(ta), p(rec), 0, 6.0, p(aff), p(tri), None, ctx.stream()) == -1
+    assert lib.swift_fit_mesh(ctx.h, 0, 2, p(ta), p(ta), p(rec), 0, 6.0, p(aff), p(tri), None, ctx.stream()) == -1
