@@ -780,9 +780,9 @@ def main():
         log("pearson: the same batch scored by Pearson-normalised correlation ...")
         line["pearson"] = pearson_block(ctx, sw, stack, refs, table, images, pairs, res, args, prof_steps)
         pb = line["pearson"]
-        log("pearson: %.3f ms/step (%.0f pairs/s), same peak as whitened %.4f, median SNR %.1f (whitened %.1f)"
-            % (pb["ms_per_step"], pb["pairs_per_s"], pb["same_peak_frac"], pb["median_snr"],
-               pb["median_snr_whitened"]))
+        log("pearson: %.3f ms/step (%.0f pairs/s), shifts within 1 px of the whitened ones %.3f, median SNR %.1f "
+            "(whitened %.1f)" % (pb["ms_per_step"], pb["pairs_per_s"], pb["frac_shift_within_1px"], pb["median_snr"],
+                                 pb["median_snr_whitened"]))
     if not args.no_refine:
         log("refinement: plain vs batched + adjoint to 0.01 px ...")
         del ws
