@@ -857,3 +857,25 @@ def join_break(aff, aff_left, j):
         m = mat(out[s]) @ D
         out[s] = [m[0, 0], m[0, 1], m[0, 2], m[1, 0], m[1, 1], m[1, 2]]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Search with an SNR stop (Section III, SNR paragraph: an SNR above 15 marks
+# a correct match, so a search for better matches can stop there).  Design
+# reading: a window whose placement is unknown beyond the capture range is
+# matched at candidate translations in a fixed order; it keeps its best
+# (highest SNR) match so far and leaves the search at the first candidate
+# whose SNR reaches the threshold.
+# ---------------------------------------------------------------------------
+def search_select(snrs, accept):
+    """snrs: SNR of each candidate in search order (one window).  Returns
+    (index of the kept candidate, candidates matched): the first candidate
+    whose SNR reaches accept ends the search; otherwise all are matched and
+    the best (first of equals) is kept."""
+    best, arg = -np.inf, -1
+    for k, v in enumerate(snrs):
+        if v > best:
+            best, arg = v, k
+        if v >= accept:
+            return arg, k + 1
+    return arg, len(snrs)

@@ -911,3 +911,15 @@ def test_join_break_closed_forms():
     d_j = app(inv(aff[j]), app(out[j], p))
     for s in range(j + 1, S):
         np.testing.assert_allclose(app(inv(aff[s]), app(out[s], p)), d_j, rtol=0, atol=1e-8)
+
+
+def test_search_select_stops_at_the_threshold():
+    # the first candidate at or above the threshold ends the search (even if a
+    # later one would be better); otherwise every candidate runs and the first
+    # best is kept
+    assert O.search_select([3.0, 20.0, 40.0], 15.0) == (1, 2)
+    assert O.search_select([15.0, 2.0], 15.0) == (0, 1)
+    assert O.search_select([3.0, 9.0, 9.0, 4.0], 15.0) == (1, 4)
+    assert O.search_select([], 15.0) == (-1, 0)
+    # with no threshold the search is exhaustive and keeps the best
+    assert O.search_select([3.0, 20.0, 40.0, 1.0], np.inf) == (2, 4)
