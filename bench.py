@@ -602,6 +602,83 @@ def jump_block(ctx, dev, sections=16, size=SIZE, j0=8, mag=0.02):
                                   "median_after": float(np.median(r1))}), sample
 
 
+# --------------------------------------------------------------------------- search with an SNR stop
+def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, accept=15.0, reps=3):
+    """Search with an SNR stop (Section III, SNR paragraph) on a section pair
+    misplaced by about a window edge and rotated 1 degree: 25 candidate
+    offsets (spiral, n/2 apart), each window leaving at its first candidate
+    with SNR >= 15, against the same driver searching every candidate.
+    Found offsets against the generator's displacement."""
+    import numpy as np
+    import torch
+
+    from datagen.workloads import search_pair
+    from paper_1612_04787_amd.search import search_offsets, spiral_offsets
+    a, b, m, bv, nl, ia, ib, ta, tb, cen = search_pair(size, n, grid, device=dev)
+    radius = int(step // 2) + 4  # each candidate owns its cell of the spiral
+    params = sw.make_params(p=0.65, max_shift=radius)
+    offs = spiral_offsets(step, rings)
+    P, K = len(nl), offs.shape[0]
+
+    def run(acc):
+        search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            got = search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc)
+        torch.cuda.synchronize()
+        return got, (time.perf_counter() - t0) / reps * 1e3
+
+    got, ms = run(accept)
+    full, ms_full = run(float("inf"))
+    rec = sw.parse_records(got["best"])
+    cand = got["cand"].cpu().numpy()
+    done = got["done"].cpu().numpy().astype(bool)
+    def found(g):
+        r = sw.parse_records(g["best"])
+        d = np.stack([r["dx"].cpu().numpy(), r["dy"].cpu().numpy()], 1)
+        return offs.numpy().astype(np.float64)[g["cand"].cpu().numpy()] - d
+
+    est = found(got)
+    err = np.abs(est - (cen @ m.T + bv - cen)).max(1)
+    agree = np.abs(est - found(full)).max(1) <= 1.0
+    sample = (a.cpu().numpy(), b.cpu().numpy(), ta.cpu().numpy(), offs.numpy(), accept, radius)
+    del a, b
+    torch.cuda.empty_cache()
+    return dict(workload="%d^2 section pair misplaced by (230, -150) px and rotated 1 degree; %d windows of %d^2, "
+                         "%d candidate offsets %g px apart, each matched within radius %d (pruned inverse), stop at "
+                         "SNR >= %g" % (size, P, n, K, step, radius, accept),
+                ms=ms, windows_per_s=P / (ms / 1e3), matches=int(sum(got["matched"])),
+                exhaustive=dict(ms=ms_full, matches=P * K), speedup=ms_full / ms,
+                done_frac=float(done.mean()), max_err_px_done=float(err[done].max()) if done.any() else None,
+                max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean())), sample
+
+
+def cpu_baseline_search(sample, n=256, windows=range(0, 576, 16)):
+    """The oracle's search (FP64 matches over the candidate list, stopping at
+    the threshold) for a few windows of the search pair, one process, in
+    windows/s."""
+    import oracle as O
+    a, b, ta, offs, accept, radius = sample
+    t0 = time.perf_counter()
+    matches = 0
+    for w in windows:
+        snrs = []
+        for k in range(offs.shape[0]):
+            th = ta[w].astype("float64").copy()
+            th[4] += offs[k, 0]
+            th[7] += offs[k, 1]
+            snrs.append(O.match_pair(a, b, th, ta[w].astype("float64"), n, O.Params(p=0.65, max_shift=radius))["snr"])
+            matches += 1
+            if snrs[-1] >= accept:
+                break
+        O.search_select(snrs, accept)
+    el = time.perf_counter() - t0
+    return dict(value=len(windows) / el, unit="windows/s", cores=1, kind="oracle",
+                sample="search of %d windows (%d FP64 matches of %d^2), one process; %.1f s"
+                       % (len(windows), matches, n, el))
+
+
 # --------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -617,6 +694,7 @@ def main():
     ap.add_argument("--no-prune", action="store_true", help="skip the pruned-inverse (search radius) variant")
     ap.add_argument("--no-pearson", action="store_true", help="skip the Pearson-normalised correlation variant")
     ap.add_argument("--no-jump", action="store_true", help="skip the jump-repair run")
+    ap.add_argument("--no-search", action="store_true", help="skip the SNR-stop search run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -809,6 +887,15 @@ def main():
         log("jump repair: break %.2f px -> %.2f px (max pair %.2f -> %.2f), %.0f ms"
             % (jr["at_jump_before"], jr["at_jump_after"], jr["max_before"], jr["max_after"],
                line["jump_repair"]["repair_ms"]))
+    search_sample = None
+    if not args.no_search:
+        log("search: candidate offsets with an SNR stop vs every candidate ...")
+        line["search"], search_sample = search_block(ctx, sw, dev)
+        q = line["search"]
+        log("search: %.2f ms (%d matches) vs %.2f ms exhaustive (%d), %.2fx; done %.3f, max err %.3f px, "
+            "same offset as exhaustive %.3f" % (q["ms"], q["matches"], q["exhaustive"]["ms"],
+                                                q["exhaustive"]["matches"], q["speedup"], q["done_frac"],
+                                                q["max_err_px_done"] or -1, q["same_offset_as_exhaustive"]))
     mesh_sample = None
     if not args.no_mesh:
         log("mesh: global affines then two local-affine mesh passes on a bent stack ...")
@@ -826,6 +913,8 @@ def main():
             line["cpu_baseline"]["mesh_render"] = cpu_baseline_mesh(mesh_sample)
         if jump_sample is not None:
             line["cpu_baseline"]["jump_models"] = cpu_baseline_jump(jump_sample)
+        if search_sample is not None:
+            line["cpu_baseline"]["search"] = cpu_baseline_search(search_sample)
         if not (args.no_prune and args.no_pearson):
             line["cpu_baseline"].update(cpu_baseline_variants(stack.cpu().numpy(), refs.cpu().numpy(), cen))
     if not args.no_ragged:

@@ -11,7 +11,7 @@ import math
 import numpy as np
 import torch
 
-from .synth import make_section_pair, make_stack, window_grid
+from .synth import make_section, make_section_pair, make_stack, warp_affine, window_grid
 
 
 def stack_warps(n_sections: int, h: int, w: int, seed: int, drift=2.0, rot_deg=0.2, scale=0.002, shear=1e-3):
@@ -152,3 +152,36 @@ def ragged_level_pairs(n_sections: int, size: int, levels: int = 4, grid: int = 
     t = torch.tensor(np.array(th, np.float32), device=device)
     return (ns, torch.tensor(ia, dtype=torch.int32, device=device),
             torch.tensor(ib, dtype=torch.int32, device=device), t, t.clone())
+
+
+def search_pair(size=4096, n=256, grid=8, seed=17, shift=(230.0, -150.0), rot_deg=1.0, noise_sigma=8.0,
+                device="cuda"):
+    """A section pair misplaced by more than one window match captures:
+    B(q) = A(M q + b) plus noise, M a rotation of rot_deg about the centre and b
+    adding `shift` px, and a grid x grid layout of n x n windows at identity
+    whose centres keep 1.75 n + |shift| px from the border (so candidate
+    offsets up to n px per axis read no clamped pixels).  Window A of each pair
+    starts at window B's centre.  The true offset of window A at centre c is
+    M c + b - c.  Returns (A, B, M, b, n_list, img_a, img_b, theta_a,
+    theta_b, centres)."""
+    a = make_section(size, size, seed, device)
+    th = math.radians(rot_deg)
+    m = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    c0 = np.array([(size - 1) / 2.0, (size - 1) / 2.0])
+    bv = c0 - m @ c0 + np.asarray(shift, np.float64)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 500)
+    bw = warp_affine(a.float(), m, bv)
+    bw = bw + noise_sigma * torch.randn(bw.shape, generator=g, device=device)
+    b = bw.clamp(0, 255).round().to(torch.uint8)
+    del bw
+    lo = 1.75 * n + max(abs(shift[0]), abs(shift[1]))
+    ax = np.round(np.linspace(lo, size - 1 - lo, grid))
+    cen = np.array([(x, y) for y in ax for x in ax], np.float64)
+    P = len(cen)
+    t = np.zeros((P, 8), np.float32)
+    t[:, 0], t[:, 1] = cen[:, 0], cen[:, 1]
+    t[:, 2] = t[:, 6] = 1.0
+    tt = torch.from_numpy(t).to(device)
+    z = torch.zeros(P, dtype=torch.int32, device=device)
+    return a, b, m, bv, [n] * P, z, z + 1, tt, tt.clone(), cen

@@ -266,6 +266,21 @@ int swift_blend_span(swift_ctx* ctx, int32_t S, int32_t a, int32_t b, const doub
 int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, const double* aff_left,
                      double* out, hipStream_t stream);
 
+/* Search with an SNR stop (Section III, SNR paragraph: an SNR above 15 marks
+ * a correct match, so a search for better matches can stop there).  After a
+ * round that matched the n active windows idx[i] (of P) at candidate `cand`
+ * (records recs[i], device [n]), every such window keeps the higher-SNR of
+ * its kept record best[w] and the new one (its candidate in best_cand[w];
+ * the earlier candidate on equal SNR) and gets done[w] = 1 once the kept
+ * SNR reaches `accept`.  Before the first round the caller sets best_cand to
+ * -1 and done to 0.  idx: device [n]; best: device [P] records; best_cand:
+ * device [P] int32; done: device [P] uint8.  Entries of idx outside [0, P)
+ * are ignored.  Errors: SWIFT_E_INVAL (NULL, n outside [0, P], cand < 0),
+ * SWIFT_E_HIP. */
+int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, const swift_match* recs,
+                      int32_t cand, float accept, swift_match* best, int32_t* best_cand, uint8_t* done,
+                      hipStream_t stream);
+
 /* One level of the x2 source pyramid (Section III: iscale): dst(x, y) =
  * (sum of the 2x2 block at (2x, 2y) + 2) >> 2 for uint8 images; dst must be
  * (src.width/2) x (src.height/2).  Descriptors are host structs whose data

@@ -748,6 +748,20 @@ int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, co
   return ok();
 }
 
+int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, const swift_match* recs,
+                      int32_t cand, float accept, swift_match* best, int32_t* best_cand, uint8_t* done,
+                      hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (P < 0 || n < 0 || n > P) return fail(SWIFT_E_INVAL, "bad sizes (P %d, n %d)", P, n);
+  if (n > 0 && (!idx || !recs || !best || !best_cand || !done)) return fail(SWIFT_E_INVAL, "NULL array");
+  if (cand < 0) return fail(SWIFT_E_INVAL, "cand must be >= 0 (got %d)", cand);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_search_keep(P, n, idx, recs, cand, accept, best, best_cand, done, stream);
+  if (e != hipSuccess) return hip_fail(e, "search launch");
+  return ok();
+}
+
 int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst, hipStream_t stream) {
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   if (!src || !dst || !src->data || !dst->data) return fail(SWIFT_E_INVAL, "src/dst is NULL");

@@ -336,4 +336,31 @@ hipError_t launch_join_break(int S, int j, const double* in, const double* left,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- search with an SNR stop
+// The n active windows idx[i] (of P) were matched at candidate `cand`
+// (records recs[i]): each keeps the higher-SNR of its kept record and the
+// new one (the earlier candidate on equal SNR) and is done once the kept SNR
+// reaches `accept`.  Window indices outside [0, P) are ignored.
+__global__ void __launch_bounds__(256) k_search_keep(int P, int n, const int32_t* __restrict__ idx,
+                                                     const swift_match* __restrict__ recs, int cand, float accept,
+                                                     swift_match* __restrict__ best, int32_t* __restrict__ best_cand,
+                                                     uint8_t* __restrict__ done) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int w = idx[i];
+  if (w < 0 || w >= P) return;
+  const swift_match r = recs[i];
+  if (best_cand[w] < 0 || r.snr > best[w].snr) {
+    best[w] = r;
+    best_cand[w] = cand;
+  }
+  if (best[w].snr >= accept) done[w] = 1;
+}
+
+hipError_t launch_search_keep(int P, int n, const int32_t* idx, const swift_match* recs, int cand, float accept,
+                              swift_match* best, int32_t* best_cand, uint8_t* done, hipStream_t st) {
+  if (n > 0) k_search_keep<<<(n + 255) / 256, 256, 0, st>>>(P, n, idx, recs, cand, accept, best, best_cand, done);
+  return hipGetLastError();
+}
+
 }  // namespace swift

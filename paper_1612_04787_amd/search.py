@@ -1,0 +1,72 @@
+"""Search with an SNR stop (Section III, SNR paragraph: an SNR above 15 marks a
+correct match, so a search for better matches can end there).
+
+A window whose placement is off by more than a window match can capture is
+matched at candidate translations in a fixed order (offsets[k] moves window
+A's translation).  Every round matches only the windows still searching, and
+swift_search_keep keeps each window's best (highest SNR) match and marks it
+done once that SNR reaches `accept`.  The only host synchronisation per round
+is counting the windows still searching (it sizes the next batch).
+
+With candidates spaced `step` apart, give params a search radius (max_shift)
+of about step / 2: a window then scores each candidate only within that
+candidate's cell.  Without it, a candidate whose content only partly overlaps
+(a residual between n/2 and n px) can still reach the threshold with its peak
+wrapped around the window, which gives a wrong offset.
+"""
+from __future__ import annotations
+
+import torch
+
+from .swift import REC_BYTES
+
+
+def spiral_offsets(step: float, rings: int):
+    """Candidate translations ordered by ring: the origin, then the 8 cells of
+    ring 1, ... on a square grid of `step` px, each ring row-major.  Returns a
+    float32 host tensor [(2 rings + 1)^2, 2]."""
+    out = [(0.0, 0.0)]
+    for r in range(1, rings + 1):
+        for j in range(-r, r + 1):
+            for i in range(-r, r + 1):
+                if max(abs(i), abs(j)) == r:
+                    out.append((i * step, j * step))
+    return torch.tensor(out, dtype=torch.float32)
+
+
+def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, offsets, accept=15.0):
+    """Returns dict(best [P, 64] uint8 records, cand [P] int32 kept candidate,
+    done [P] uint8, matched [K] windows matched per candidate).  n_list must be
+    sorted (any subset of the windows then is too)."""
+    dev = sw.device
+    P = len(n_list)
+    K = int(offsets.shape[0])
+    img_a = img_a.to(dev, torch.int32).contiguous()
+    img_b = img_b.to(dev, torch.int32).contiguous()
+    theta_a = theta_a.to(dev, torch.float32).contiguous()
+    theta_b = theta_b.to(dev, torch.float32).contiguous()
+    best = torch.zeros((P, REC_BYTES), dtype=torch.uint8, device=dev)
+    cand = torch.full((P,), -1, dtype=torch.int32, device=dev)
+    done = torch.zeros(P, dtype=torch.uint8, device=dev)
+    table = sw.image_table(images)
+    n_host = [int(n) for n in n_list]
+    matched = []
+    recs = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
+    for k in range(K):
+        idx = torch.nonzero(done == 0).flatten().to(torch.int32)
+        n = int(idx.numel())
+        matched.append(n)
+        if n == 0:
+            matched.extend([0] * (K - k - 1))
+            break
+        il = idx.long()
+        ta = theta_a.index_select(0, il)
+        ta[:, 4] += float(offsets[k, 0])
+        ta[:, 7] += float(offsets[k, 1])
+        ia, ib, tb = img_a.index_select(0, il), img_b.index_select(0, il), theta_b.index_select(0, il)
+        sub = [n_host[i] for i in idx.tolist()] if len(set(n_host)) > 1 else [n_host[0]] * n
+        pr = sw.make_pairs(sub, ia, ib, ta, tb)
+        out = recs[:n]
+        sw.match_batch_raw(table, len(images), pr, params, out)
+        sw.search_keep(P, idx, out, k, accept, best, cand, done)
+    return dict(best=best, cand=cand, done=done, matched=matched)

@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     lib.swift_project_side.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i64, i64, vp]
     lib.swift_blend_span.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     lib.swift_join_break.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.swift_search_keep.argtypes = [vp, i32, i32, vp, vp, i32, C.c_float, vp, vp, vp, vp]
     lib.swift_render_mesh.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i32, i32, i64, i64, vp]
     lib.swift_mesh_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.swift_fit_mesh.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp, vp]
@@ -426,6 +427,15 @@ class Swift:
             assert t.dtype == torch.float64 and t.is_contiguous() and t.shape == (S, 6)
         _check(self.lib.swift_join_break(self.h, S, int(j), _ptr(aff), _ptr(aff_left), _ptr(out), self.stream()))
         return out
+
+    def search_keep(self, P, idx, recs_raw, cand, accept, best, best_cand, done):
+        """One round of the SNR-stop search: idx [n] int32, recs_raw [n, 64]
+        uint8, best [P, 64] uint8, best_cand [P] int32, done [P] uint8 (all
+        device, updated in place)."""
+        n = idx.shape[0]
+        assert recs_raw.shape[0] == n and best.shape[0] == P and best_cand.shape[0] == P and done.shape[0] == P
+        _check(self.lib.swift_search_keep(self.h, int(P), int(n), _ptr(idx), _ptr(recs_raw), int(cand), float(accept),
+                                          _ptr(best), _ptr(best_cand), _ptr(done), self.stream()))
 
     # ---- local-affine triangle mesh: tri_aff [S, 2 (grid-1)^2, 6] float64 (device)
     @staticmethod

@@ -68,4 +68,15 @@ def test_validation_without_gpu(lib):
     assert lib.swift_project_side(None, None, 1, 1, 1, 1, 1, None, 3, -1, None, 1, 1, None) == -1
     assert lib.swift_blend_span(None, 4, 1, 2, None, None, None, None) == -1
     assert lib.swift_join_break(None, 4, 1, None, None, None, None) == -1
+    assert lib.swift_search_keep(None, 4, 1, None, None, 0, 15.0, None, None, None, None) == -1
     assert b"ctx" in lib.swift_last_error()
+
+
+def test_spiral_offsets_order():
+    # host logic of the search driver: the origin, then each ring row-major
+    from paper_1612_04787_amd.search import spiral_offsets
+    o = spiral_offsets(10.0, 2).tolist()
+    assert len(o) == 25 and o[0] == [0.0, 0.0]
+    assert o[1:9] == [[-10, -10], [0, -10], [10, -10], [-10, 0], [10, 0], [-10, 10], [0, 10], [10, 10]]
+    assert sorted(map(tuple, o)) == sorted((10.0 * i, 10.0 * j) for i in range(-2, 3) for j in range(-2, 3))
+    assert all(max(abs(x), abs(y)) == 20 for x, y in o[9:])
