@@ -631,6 +631,11 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
 
     got, ms = run(accept)
     full, ms_full = run(float("inf"))
+    ctx.profile(True)
+    search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=accept)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kernels = {name: dict(launches=cnt, avg_ms=tot / cnt, total_ms=tot) for name, (cnt, tot) in prof.items()}
     rec = sw.parse_records(got["best"])
     cand = got["cand"].cpu().numpy()
     done = got["done"].cpu().numpy().astype(bool)
@@ -651,7 +656,7 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
                 ms=ms, windows_per_s=P / (ms / 1e3), matches=int(sum(got["matched"])),
                 exhaustive=dict(ms=ms_full, matches=P * K), speedup=ms_full / ms,
                 done_frac=float(done.mean()), max_err_px_done=float(err[done].max()) if done.any() else None,
-                max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean())), sample
+                max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean()), kernels=kernels), sample
 
 
 def cpu_baseline_search(sample, n=256, windows=range(0, 576, 16)):
