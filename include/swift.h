@@ -277,6 +277,20 @@ int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, co
  * device [P] int32; done: device [P] uint8.  Entries of idx outside [0, P)
  * are ignored.  Errors: SWIFT_E_INVAL (NULL, n outside [0, P], cand < 0),
  * SWIFT_E_HIP. */
+/* Next round of the search with an SNR stop (Section III, SNR paragraph):
+ * gathers the windows w with done[w] == 0, in ascending order, into
+ * idx[0..n) (their indices), img_a_out/img_b_out and theta_a_out/theta_b_out
+ * [n][8], window A's translation (entries 4 and 7) moved by (ox, oy); n is
+ * written to count (device int32).  A batch sorted by window edge stays
+ * sorted.  done: device [P] uint8; img_a/img_b: device [P] int32;
+ * theta_a/theta_b: device [P][8]; the outputs: device, room for P entries,
+ * not aliasing the inputs.  Runs as one workgroup (cost grows with P / 1024).
+ * Errors: SWIFT_E_INVAL (NULL, P < 0, aliasing), SWIFT_E_HIP. */
+int swift_search_next(swift_ctx* ctx, int32_t P, const uint8_t* done, float ox, float oy, const int32_t* img_a,
+                      const int32_t* img_b, const float* theta_a, const float* theta_b, int32_t* idx,
+                      int32_t* img_a_out, int32_t* img_b_out, float* theta_a_out, float* theta_b_out,
+                      int32_t* count, hipStream_t stream);
+
 int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, const swift_match* recs,
                       int32_t cand, float accept, swift_match* best, int32_t* best_cand, uint8_t* done,
                       hipStream_t stream);

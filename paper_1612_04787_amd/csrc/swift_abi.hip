@@ -762,6 +762,26 @@ int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, 
   return ok();
 }
 
+int swift_search_next(swift_ctx* ctx, int32_t P, const uint8_t* done, float ox, float oy, const int32_t* img_a,
+                      const int32_t* img_b, const float* theta_a, const float* theta_b, int32_t* idx,
+                      int32_t* img_a_out, int32_t* img_b_out, float* theta_a_out, float* theta_b_out,
+                      int32_t* count, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  if (P < 0) return fail(SWIFT_E_INVAL, "bad size (P %d)", P);
+  if (!count) return fail(SWIFT_E_INVAL, "count is NULL");
+  if (P > 0 && (!done || !img_a || !img_b || !theta_a || !theta_b || !idx || !img_a_out || !img_b_out ||
+                !theta_a_out || !theta_b_out))
+    return fail(SWIFT_E_INVAL, "NULL array");
+  if (P > 0 && (theta_a_out == theta_a || theta_b_out == theta_b || img_a_out == img_a || img_b_out == img_b))
+    return fail(SWIFT_E_INVAL, "outputs must not alias the inputs");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  hipError_t e = launch_search_next(P, done, ox, oy, img_a, img_b, theta_a, theta_b, idx, img_a_out, img_b_out,
+                                    theta_a_out, theta_b_out, count, stream);
+  if (e != hipSuccess) return hip_fail(e, "search gather launch");
+  return ok();
+}
+
 int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst, hipStream_t stream) {
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   if (!src || !dst || !src->data || !dst->data) return fail(SWIFT_E_INVAL, "src/dst is NULL");

@@ -189,6 +189,9 @@ hipError_t launch_project(const uint8_t* src, int64_t pitch, int64_t sstride, in
                           hipStream_t s, KernelTimer* kt, int side = 0);
 hipError_t launch_blend_span(int a, int b, const double* left, const double* right, double* aff, hipStream_t st);
 hipError_t launch_join_break(int S, int j, const double* in, const double* left, double* out, hipStream_t st);
+hipError_t launch_search_next(int P, const uint8_t* done, float ox, float oy, const int32_t* img_a,
+                              const int32_t* img_b, const float* theta_a, const float* theta_b, int32_t* idx,
+                              int32_t* ia, int32_t* ib, float* ta, float* tb, int32_t* count, hipStream_t st);
 hipError_t launch_search_keep(int P, int n, const int32_t* idx, const swift_match* recs, int cand, float accept,
                               swift_match* best, int32_t* best_cand, uint8_t* done, hipStream_t st);
 hipError_t launch_pyramid(const uint8_t* src, int64_t spitch, int sw, int sh, uint8_t* dst, int64_t dpitch,

@@ -363,4 +363,58 @@ hipError_t launch_search_keep(int P, int n, const int32_t* idx, const swift_matc
   return hipGetLastError();
 }
 
+// Next round of the search: the windows not yet done, in ascending order
+// (a sorted batch stays sorted), gathered with window A moved by (ox, oy).
+// One workgroup walks the windows 1024 at a time; a wave's ballot gives each
+// searching window its place within the wave, and the per-wave counts in LDS
+// give the wave's base.  count receives the number gathered.
+__global__ void __launch_bounds__(1024) k_search_next(int P, const uint8_t* __restrict__ done, float ox, float oy,
+                                                      const int32_t* __restrict__ img_a,
+                                                      const int32_t* __restrict__ img_b,
+                                                      const float* __restrict__ theta_a,
+                                                      const float* __restrict__ theta_b, int32_t* __restrict__ idx,
+                                                      int32_t* __restrict__ ia, int32_t* __restrict__ ib,
+                                                      float* __restrict__ ta, float* __restrict__ tb,
+                                                      int32_t* __restrict__ count) {
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int base = 0;
+  for (int c0 = 0; c0 < P; c0 += 1024) {
+    const int w = c0 + (int)threadIdx.x;
+    const bool f = w < P && done[w] == 0;
+    const unsigned long long b = __ballot(f);
+    const int pre = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(b);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      off += i < wid ? wsum[i] : 0;
+      tot += wsum[i];
+    }
+    if (f) {
+      const int o = base + off + pre;
+      idx[o] = w;
+      ia[o] = img_a[w];
+      ib[o] = img_b[w];
+      for (int k = 0; k < 8; ++k) {
+        float va = theta_a[(size_t)w * 8 + k];
+        if (k == 4) va += ox;
+        if (k == 7) va += oy;
+        ta[(size_t)o * 8 + k] = va;
+        tb[(size_t)o * 8 + k] = theta_b[(size_t)w * 8 + k];
+      }
+    }
+    base += tot;
+    __syncthreads();  // wsum is rewritten by the next chunk
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+hipError_t launch_search_next(int P, const uint8_t* done, float ox, float oy, const int32_t* img_a,
+                              const int32_t* img_b, const float* theta_a, const float* theta_b, int32_t* idx,
+                              int32_t* ia, int32_t* ib, float* ta, float* tb, int32_t* count, hipStream_t st) {
+  k_search_next<<<1, 1024, 0, st>>>(P, done, ox, oy, img_a, img_b, theta_a, theta_b, idx, ia, ib, ta, tb, count);
+  return hipGetLastError();
+}
+
 }  // namespace swift

@@ -5,8 +5,9 @@ A window whose placement is off by more than a window match can capture is
 matched at candidate translations in a fixed order (offsets[k] moves window
 A's translation).  Every round matches only the windows still searching, and
 swift_search_keep keeps each window's best (highest SNR) match and marks it
-done once that SNR reaches `accept`.  The only host synchronisation per round
-is counting the windows still searching (it sizes the next batch).
+done once that SNR reaches `accept`.  swift_search_next gathers the windows
+still searching; the only host synchronisation per round is reading their
+count (it sizes the next batch).
 
 With candidates spaced `step` apart, give params a search radius (max_shift)
 of about step / 2: a window then scores each candidate only within that
@@ -37,7 +38,9 @@ def spiral_offsets(step: float, rings: int):
 def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, offsets, accept=15.0):
     """Returns dict(best [P, 64] uint8 records, cand [P] int32 kept candidate,
     done [P] uint8, matched [K] windows matched per candidate).  n_list must be
-    sorted (any subset of the windows then is too)."""
+    sorted (any subset of the windows then is too).  Each round is
+    swift_search_next (gather the windows still searching), one match of that
+    batch, and swift_search_keep; the host reads the batch size in between."""
     dev = sw.device
     P = len(n_list)
     K = int(offsets.shape[0])
@@ -48,25 +51,30 @@ def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, o
     best = torch.zeros((P, REC_BYTES), dtype=torch.uint8, device=dev)
     cand = torch.full((P,), -1, dtype=torch.int32, device=dev)
     done = torch.zeros(P, dtype=torch.uint8, device=dev)
+    idx = torch.empty(P, dtype=torch.int32, device=dev)
+    ia = torch.empty(P, dtype=torch.int32, device=dev)
+    ib = torch.empty(P, dtype=torch.int32, device=dev)
+    ta = torch.empty((P, 8), dtype=torch.float32, device=dev)
+    tb = torch.empty((P, 8), dtype=torch.float32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    recs = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
     table = sw.image_table(images)
     n_host = [int(n) for n in n_list]
+    mixed = len(set(n_host)) > 1
+    offs = offsets.tolist()
     matched = []
-    recs = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
     for k in range(K):
-        idx = torch.nonzero(done == 0).flatten().to(torch.int32)
-        n = int(idx.numel())
+        if P == 0:
+            matched.append(0)
+            continue
+        sw.search_next(done, offs[k][0], offs[k][1], img_a, img_b, theta_a, theta_b, idx, ia, ib, ta, tb, count)
+        n = int(count.item())
         matched.append(n)
         if n == 0:
             matched.extend([0] * (K - k - 1))
             break
-        il = idx.long()
-        ta = theta_a.index_select(0, il)
-        ta[:, 4] += float(offsets[k, 0])
-        ta[:, 7] += float(offsets[k, 1])
-        ia, ib, tb = img_a.index_select(0, il), img_b.index_select(0, il), theta_b.index_select(0, il)
-        sub = [n_host[i] for i in idx.tolist()] if len(set(n_host)) > 1 else [n_host[0]] * n
+        sub = [n_host[i] for i in idx[:n].tolist()] if mixed else [n_host[0]] * n
         pr = sw.make_pairs(sub, ia, ib, ta, tb)
-        out = recs[:n]
-        sw.match_batch_raw(table, len(images), pr, params, out)
-        sw.search_keep(P, idx, out, k, accept, best, cand, done)
+        sw.match_batch_raw(table, len(images), pr, params, recs[:n])
+        sw.search_keep(P, idx[:n], recs[:n], k, accept, best, cand, done)
     return dict(best=best, cand=cand, done=done, matched=matched)

@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.swift_blend_span.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     lib.swift_join_break.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     lib.swift_search_keep.argtypes = [vp, i32, i32, vp, vp, i32, C.c_float, vp, vp, vp, vp]
+    lib.swift_search_next.argtypes = [vp, i32, vp, C.c_float, C.c_float, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.swift_render_mesh.argtypes = [vp, vp, i32, i32, i32, i64, i64, vp, i32, i32, vp, i32, i32, i64, i64, vp]
     lib.swift_mesh_windows.argtypes = [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.swift_fit_mesh.argtypes = [vp, i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp, vp]
@@ -427,6 +428,17 @@ class Swift:
             assert t.dtype == torch.float64 and t.is_contiguous() and t.shape == (S, 6)
         _check(self.lib.swift_join_break(self.h, S, int(j), _ptr(aff), _ptr(aff_left), _ptr(out), self.stream()))
         return out
+
+    def search_next(self, done, ox, oy, img_a, img_b, theta_a, theta_b, idx, ia, ib, ta, tb, count):
+        """Gathers the windows not yet done (device tensors: done [P] uint8,
+        img_a/img_b [P] int32, theta_a/theta_b [P, 8]; outputs with room for
+        P, count [1] int32)."""
+        P = done.shape[0]
+        assert img_a.shape[0] == P and img_b.shape[0] == P and theta_a.shape[0] == P and theta_b.shape[0] == P
+        assert idx.shape[0] >= P and ia.shape[0] >= P and ib.shape[0] >= P and ta.shape[0] >= P and tb.shape[0] >= P
+        _check(self.lib.swift_search_next(self.h, int(P), _ptr(done), float(ox), float(oy), _ptr(img_a), _ptr(img_b),
+                                          _ptr(theta_a), _ptr(theta_b), _ptr(idx), _ptr(ia), _ptr(ib), _ptr(ta),
+                                          _ptr(tb), _ptr(count), self.stream()))
 
     def search_keep(self, P, idx, recs_raw, cand, accept, best, best_cand, done):
         """One round of the SNR-stop search: idx [n] int32, recs_raw [n, 64]

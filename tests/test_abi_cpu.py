@@ -69,6 +69,8 @@ def test_validation_without_gpu(lib):
     assert lib.swift_blend_span(None, 4, 1, 2, None, None, None, None) == -1
     assert lib.swift_join_break(None, 4, 1, None, None, None, None) == -1
     assert lib.swift_search_keep(None, 4, 1, None, None, 0, 15.0, None, None, None, None) == -1
+    assert lib.swift_search_next(None, 4, None, 0.0, 0.0, None, None, None, None, None, None, None, None, None, None,
+                                 None) == -1
     assert b"ctx" in lib.swift_last_error()
 
 

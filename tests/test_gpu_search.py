@@ -198,3 +198,75 @@ def test_search_keep_rules(ctx):
         ctx.search_keep(P, idx, _records([1.0, 2.0, 3.0, 4.0]), -1, 10.0, best, cand, done)
     torch.cuda.synchronize()
     assert cand.tolist() == [0, -1, 2, 2]
+
+
+@pytest.mark.parametrize("P", [1, 100, 1024, 2500])
+def test_search_next_gathers_in_order(ctx, P):
+    import paper_1612_04787_amd as sw
+    print("case search_next P=%d" % P, flush=True)
+    g = torch.Generator().manual_seed(P)
+    done = (torch.rand(P, generator=g) < 0.4).to(torch.uint8)
+    ia = torch.randint(0, 9, (P,), generator=g, dtype=torch.int32)
+    ib = torch.randint(0, 9, (P,), generator=g, dtype=torch.int32)
+    ta = torch.randn((P, 8), generator=g) * 100
+    tb = torch.randn((P, 8), generator=g) * 100
+    d = [t.to(dev()) for t in (done, ia, ib, ta, tb)]
+    outs = [torch.full((P,), -7, dtype=torch.int32, device=dev()) for _ in range(3)]
+    touts = [torch.full((P, 8), -7.0, device=dev()) for _ in range(2)]
+    count = torch.zeros(1, dtype=torch.int32, device=dev())
+    ctx.search_next(d[0], 64.0, -32.5, d[1], d[2], d[3], d[4], outs[0], outs[1], outs[2], touts[0], touts[1], count)
+    torch.cuda.synchronize()
+    keep = torch.nonzero(done == 0).flatten()
+    n = int(count.item())
+    assert n == keep.numel()
+    assert torch.equal(outs[0][:n].cpu(), keep.to(torch.int32))
+    assert torch.equal(outs[1][:n].cpu(), ia[keep]) and torch.equal(outs[2][:n].cpu(), ib[keep])
+    want = ta[keep].clone()
+    want[:, 4] += 64.0
+    want[:, 7] += -32.5
+    assert torch.equal(touts[0][:n].cpu(), want) and torch.equal(touts[1][:n].cpu(), tb[keep])
+    # nothing past the count is written
+    assert bool((outs[0][n:] == -7).all()) and bool((touts[0][n:] == -7.0).all())
+    # every window done: nothing gathered; no windows at all: count 0
+    ctx.search_next(torch.ones(P, dtype=torch.uint8, device=dev()), 0.0, 0.0, d[1], d[2], d[3], d[4], outs[0],
+                    outs[1], outs[2], touts[0], touts[1], count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
+    e = torch.zeros(0, dtype=torch.int32, device=dev())
+    count.fill_(5)
+    ctx.search_next(torch.zeros(0, dtype=torch.uint8, device=dev()), 0.0, 0.0, e, e, torch.zeros((0, 8), device=dev()),
+                    torch.zeros((0, 8), device=dev()), e, e, e, torch.zeros((0, 8), device=dev()),
+                    torch.zeros((0, 8), device=dev()), count)
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
+    # outputs aliasing the inputs are rejected
+    with pytest.raises(sw.SwiftError):
+        ctx.search_next(d[0], 0.0, 0.0, d[1], d[2], d[3], d[4], outs[0], outs[1], outs[2], d[3], touts[1], count)
+
+
+def test_search_mixed_window_sizes(ctx, case):
+    # a batch of two window edges stays sorted through every round; the
+    # selection still matches the exhaustive search
+    import paper_1612_04787_amd as sw
+    from paper_1612_04787_amd.search import search_offsets, spiral_offsets
+    print("case search mixed sizes", flush=True)
+    params = sw.make_params(p=0.65)
+    offs = spiral_offsets(64.0, 1)
+    K = offs.shape[0]
+    c = dict(case)
+    c["nl"] = [64] * 18 + [128] * 18
+    full = _exhaustive(ctx, c, params, offs)
+    snr = full.view(torch.float32).view(K, -1, 16)[:, :, 5].cpu().numpy()
+    got = search_offsets(ctx, [c["a"], c["b"]], c["nl"], c["ia"], c["ib"], c["ta"], c["tb"], params, offs, accept=15.0)
+    torch.cuda.synchronize()
+    cand = got["cand"].cpu().numpy()
+    best = got["best"].cpu()
+    counts = []
+    for w in range(36):
+        arg, cnt = O.search_select(snr[:, w].tolist(), 15.0)
+        counts.append(cnt)
+        assert cand[w] == arg, (w, cand[w], arg)
+        assert torch.equal(best[w], full[arg, w].cpu()), w
+    assert got["matched"] == [sum(1 for x in counts if x > k) for k in range(K)]
+    assert int(sw.parse_records(got["best"])["n"].cpu()[0]) == 64
+    print("   matched per candidate:", got["matched"], flush=True)
