@@ -275,8 +275,9 @@ int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, co
  * SNR reaches `accept`.  Before the first round the caller sets best_cand to
  * -1 and done to 0.  idx: device [n]; best: device [P] records; best_cand:
  * device [P] int32; done: device [P] uint8.  Entries of idx outside [0, P)
- * are ignored.  Errors: SWIFT_E_INVAL (NULL, n outside [0, P], cand < 0),
- * SWIFT_E_HIP. */
+ * are ignored; the others must be distinct (one thread owns each window's
+ * record), as swift_search_next's output is.  Errors: SWIFT_E_INVAL (NULL,
+ * n outside [0, P], cand < 0), SWIFT_E_HIP. */
 /* Next round of the search with an SNR stop (Section III, SNR paragraph):
  * gathers the windows w with done[w] == 0, in ascending order, into
  * idx[0..n) (their indices), img_a_out/img_b_out and theta_a_out/theta_b_out
