@@ -40,23 +40,34 @@ namespace swift {
 // tau[k] = sum_i t(i) exp(-2 pi i k i / N) in FP64 from the same FP32 taper
 // values the gather uses.  Since t = 1 outside the 2L edge samples,
 // tau[k] = N [k == 0] - sum_{edge i} (1 - t(i)) exp(-2 pi i k i / N).
-// Block 0 also writes sum t and sum t^2.
+// Block 0 also writes sum t and sum t^2.  Each block first puts the n
+// roots of unity and the 2L edge weights 1 - t(i) in LDS (the same values a
+// per-term evaluation gives), so a bin costs 2L table reads.
 __global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict__ tau, float* __restrict__ taper,
                                                TaperInfo* info) {
   __shared__ double red[2][4];
+  __shared__ double wc[1024], ws[1024], om[1024];
+  const int Le = min(L, n / 2);
+  for (int m = threadIdx.x; m < n; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+    wc[m] = cs;
+    ws[m] = sn;
+  }
+  for (int q = threadIdx.x; q < 2 * Le; q += blockDim.x) {
+    const int i = q < Le ? q : n - 2 * Le + q;
+    om[q] = 1.0 - (double)taper_at(i, n, L);
+  }
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
     taper[k] = taper_at(k, n, L);
     double re = (k == 0) ? (double)n : 0.0, im = 0.0;
-    const int Le = min(L, n / 2);
     for (int q = 0; q < 2 * Le; ++q) {
       const int i = q < Le ? q : n - 2 * Le + q;
-      const double om = 1.0 - (double)taper_at(i, n, L);
       const int m = (int)(((long long)k * i) % n);
-      double sn, cs;
-      sincospi(2.0 * (double)m / (double)n, &sn, &cs);
-      re -= om * cs;
-      im += om * sn;
+      re -= om[q] * wc[m];
+      im += om[q] * ws[m];
     }
     tau[k] = make_float2((float)re, (float)im);
   }
@@ -87,9 +98,18 @@ __global__ void __launch_bounds__(256) k_taper(int n, int L, float2* __restrict_
 
 // Pearson tables: the gather runs with a unit taper, and the template of
 // window A is the box [n/4, 3n/4) in both axes, so tau[k] = sum over the box
-// of exp(-2 pi i k i / n) (FP64) and the taper sums are those of the box.
+// of exp(-2 pi i k i / n) (FP64, the roots of unity tabled in LDS) and the
+// taper sums are those of the box.
 __global__ void __launch_bounds__(256) k_taper_box(int n, float2* __restrict__ tau, float* __restrict__ taper,
                                                    TaperInfo* info) {
+  __shared__ double wc[1024], ws[1024];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)j / (double)n, &sn, &cs);
+    wc[j] = cs;
+    ws[j] = sn;
+  }
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = n / 2, c0 = n / 4;
   if (k < n) {
@@ -97,10 +117,8 @@ __global__ void __launch_bounds__(256) k_taper_box(int n, float2* __restrict__ t
     double re = 0.0, im = 0.0;
     for (int i = c0; i < c0 + m; ++i) {
       const int q = (int)(((long long)k * i) % n);
-      double sn, cs;
-      sincospi(2.0 * (double)q / (double)n, &sn, &cs);
-      re += cs;
-      im -= sn;
+      re += wc[q];
+      im -= ws[q];
     }
     tau[k] = make_float2((float)re, (float)im);
   }
