@@ -129,13 +129,14 @@ def test_search_records_and_offsets(ctx, case):
         print("   window %d cand %d err %.3f px:" % (w, cand[w], err[w]), e, flush=True)
 
 
-def test_search_oracle_selection(ctx, case):
+@pytest.mark.parametrize("radius", [0, 36])
+def test_search_oracle_selection(ctx, case, radius):
     # the oracle's own SNRs over the whole candidate list pick the same
     # candidate (unless an SNR lies within rounding of the threshold)
     import paper_1612_04787_amd as sw
     from paper_1612_04787_amd.search import search_offsets, spiral_offsets
-    print("case search oracle selection", flush=True)
-    params = sw.make_params(p=0.65)
+    print("case search oracle selection radius=%d" % radius, flush=True)
+    params = sw.make_params(p=0.65, max_shift=radius)
     offs = spiral_offsets(64.0, 2)
     got = search_offsets(ctx, [case["a"], case["b"]], case["nl"], case["ia"], case["ib"], case["ta"], case["tb"],
                          params, offs, accept=15.0)
@@ -148,7 +149,7 @@ def test_search_oracle_selection(ctx, case):
             th = ta[w].copy()
             th[4] += float(offs[k, 0])
             th[7] += float(offs[k, 1])
-            snrs.append(O.match_pair(an, bn, th, ta[w], 128, O.Params(p=0.65))["snr"])
+            snrs.append(O.match_pair(an, bn, th, ta[w], 128, O.Params(p=0.65, max_shift=radius))["snr"])
         arg, cnt = O.search_select(snrs, 15.0)
         near = [v for v in snrs[:cnt] if abs(v - 15.0) <= 1e-3 * 15.0]
         srt = sorted(snrs[:cnt])
