@@ -620,17 +620,22 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
     offs = spiral_offsets(step, rings)
     P, K = len(nl), offs.shape[0]
 
-    def run(acc):
-        search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc)  # warm-up
+    def run(acc, ahead=1):
+        search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc, lookahead=ahead)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            got = search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc)
+            got = search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=acc, lookahead=ahead)
         torch.cuda.synchronize()
         return got, (time.perf_counter() - t0) / reps * 1e3
 
     got, ms = run(accept)
     full, ms_full = run(float("inf"))
+    ahead = {}
+    for B in (2, 4):
+        g2, ms2 = run(accept, B)
+        same = bool(torch.equal(g2["best"], got["best"]) and torch.equal(g2["cand"], got["cand"]))
+        ahead[str(B)] = dict(ms=ms2, matches=int(sum(g2["matched"])), same_result=same)
     ctx.profile(True)
     search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=accept)
     prof = ctx.profile_read()
@@ -656,7 +661,8 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
                 ms=ms, windows_per_s=P / (ms / 1e3), matches=int(sum(got["matched"])),
                 exhaustive=dict(ms=ms_full, matches=P * K), speedup=ms_full / ms,
                 done_frac=float(done.mean()), max_err_px_done=float(err[done].max()) if done.any() else None,
-                max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean()), kernels=kernels), sample
+                max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean()), lookahead=ahead,
+                kernels=kernels), sample
 
 
 def cpu_baseline_search(sample, n=256, windows=range(0, 576, 16)):
@@ -901,6 +907,9 @@ def main():
             "same offset as exhaustive %.3f" % (q["ms"], q["matches"], q["exhaustive"]["ms"],
                                                 q["exhaustive"]["matches"], q["speedup"], q["done_frac"],
                                                 q["max_err_px_done"] or -1, q["same_offset_as_exhaustive"]))
+        for B, v in q["lookahead"].items():
+            log("search, %s candidates per round: %.2f ms (%d matches), same result %s"
+                % (B, v["ms"], v["matches"], v["same_result"]))
     mesh_sample = None
     if not args.no_mesh:
         log("mesh: global affines then two local-affine mesh passes on a bent stack ...")

@@ -274,9 +274,11 @@ int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, co
  * the earlier candidate on equal SNR) and gets done[w] = 1 once the kept
  * SNR reaches `accept`.  Before the first round the caller sets best_cand to
  * -1 and done to 0.  idx: device [n]; best: device [P] records; best_cand:
- * device [P] int32; done: device [P] uint8.  Entries of idx outside [0, P)
- * are ignored; the others must be distinct (one thread owns each window's
- * record), as swift_search_next's output is.  Errors: SWIFT_E_INVAL (NULL,
+ * device [P] int32; done: device [P] uint8.  Entries of idx outside [0, P),
+ * and windows already done, are left alone, so a caller may match several
+ * candidates ahead and keep them one candidate at a time.  The other entries
+ * must be distinct (one thread owns each window's record), as
+ * swift_search_next's output is.  Errors: SWIFT_E_INVAL (NULL,
  * n outside [0, P], cand < 0), SWIFT_E_HIP. */
 /* Next round of the search with an SNR stop (Section III, SNR paragraph):
  * gathers the windows w with done[w] == 0, in ascending order, into

@@ -340,7 +340,8 @@ hipError_t launch_join_break(int S, int j, const double* in, const double* left,
 // The n active windows idx[i] (of P) were matched at candidate `cand`
 // (records recs[i]): each keeps the higher-SNR of its kept record and the
 // new one (the earlier candidate on equal SNR) and is done once the kept SNR
-// reaches `accept`.  Window indices outside [0, P) are ignored.
+// reaches `accept`.  Window indices outside [0, P), and windows already
+// done (a caller matching several candidates ahead), are left alone.
 __global__ void __launch_bounds__(256) k_search_keep(int P, int n, const int32_t* __restrict__ idx,
                                                      const swift_match* __restrict__ recs, int cand, float accept,
                                                      swift_match* __restrict__ best, int32_t* __restrict__ best_cand,
@@ -348,7 +349,7 @@ __global__ void __launch_bounds__(256) k_search_keep(int P, int n, const int32_t
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int w = idx[i];
-  if (w < 0 || w >= P) return;
+  if (w < 0 || w >= P || done[w]) return;
   const swift_match r = recs[i];
   if (best_cand[w] < 0 || r.snr > best[w].snr) {
     best[w] = r;

@@ -35,15 +35,24 @@ def spiral_offsets(step: float, rings: int):
     return torch.tensor(out, dtype=torch.float32)
 
 
-def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, offsets, accept=15.0):
+def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, offsets, accept=15.0, lookahead=1):
     """Returns dict(best [P, 64] uint8 records, cand [P] int32 kept candidate,
     done [P] uint8, matched [K] windows matched per candidate).  n_list must be
     sorted (any subset of the windows then is too).  Each round is
     swift_search_next (gather the windows still searching), one match of that
-    batch, and swift_search_keep; the host reads the batch size in between."""
+    batch, and swift_search_keep; the host reads the batch size in between.
+    lookahead B > 1 (one window edge only) matches the windows still searching
+    at the next B candidates in one batch and keeps them candidate by
+    candidate: the result is the same, with fewer rounds and some matches
+    past a window's stop (counted in `matched`)."""
     dev = sw.device
     P = len(n_list)
     K = int(offsets.shape[0])
+    n_host = [int(n) for n in n_list]
+    mixed = len(set(n_host)) > 1
+    B = max(1, int(lookahead))
+    if mixed and B > 1:
+        raise ValueError("lookahead > 1 needs a single window edge (a repeated ragged batch is not sorted)")
     img_a = img_a.to(dev, torch.int32).contiguous()
     img_b = img_b.to(dev, torch.int32).contiguous()
     theta_a = theta_a.to(dev, torch.float32).contiguous()
@@ -51,30 +60,36 @@ def search_offsets(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, o
     best = torch.zeros((P, REC_BYTES), dtype=torch.uint8, device=dev)
     cand = torch.full((P,), -1, dtype=torch.int32, device=dev)
     done = torch.zeros(P, dtype=torch.uint8, device=dev)
-    idx = torch.empty(P, dtype=torch.int32, device=dev)
-    ia = torch.empty(P, dtype=torch.int32, device=dev)
-    ib = torch.empty(P, dtype=torch.int32, device=dev)
-    ta = torch.empty((P, 8), dtype=torch.float32, device=dev)
-    tb = torch.empty((P, 8), dtype=torch.float32, device=dev)
+    idx = torch.empty(B * P, dtype=torch.int32, device=dev)
+    ia = torch.empty(B * P, dtype=torch.int32, device=dev)
+    ib = torch.empty(B * P, dtype=torch.int32, device=dev)
+    ta = torch.empty((B * P, 8), dtype=torch.float32, device=dev)
+    tb = torch.empty((B * P, 8), dtype=torch.float32, device=dev)
     count = torch.zeros(1, dtype=torch.int32, device=dev)
-    recs = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
+    recs = torch.empty((B * P, REC_BYTES), dtype=torch.uint8, device=dev)
     table = sw.image_table(images)
-    n_host = [int(n) for n in n_list]
-    mixed = len(set(n_host)) > 1
     offs = offsets.tolist()
     matched = []
-    for k in range(K):
+    k = 0
+    while k < K:
         if P == 0:
             matched.append(0)
+            k += 1
             continue
         sw.search_next(done, offs[k][0], offs[k][1], img_a, img_b, theta_a, theta_b, idx, ia, ib, ta, tb, count)
         n = int(count.item())
-        matched.append(n)
         if n == 0:
-            matched.extend([0] * (K - k - 1))
+            matched.extend([0] * (K - k))
             break
+        b = min(B, K - k)
+        for c in range(1, b):  # the same windows (done is unchanged) at the next candidates
+            sw.search_next(done, offs[k + c][0], offs[k + c][1], img_a, img_b, theta_a, theta_b, idx[c * n:],
+                           ia[c * n:], ib[c * n:], ta[c * n:], tb[c * n:], count)
         sub = [n_host[i] for i in idx[:n].tolist()] if mixed else [n_host[0]] * n
-        pr = sw.make_pairs(sub, ia, ib, ta, tb)
-        sw.match_batch_raw(table, len(images), pr, params, recs[:n])
-        sw.search_keep(P, idx[:n], recs[:n], k, accept, best, cand, done)
+        pr = sw.make_pairs(sub * b, ia, ib, ta, tb)
+        sw.match_batch_raw(table, len(images), pr, params, recs[:b * n])
+        for c in range(b):
+            sw.search_keep(P, idx[c * n:(c + 1) * n], recs[c * n:(c + 1) * n], k + c, accept, best, cand, done)
+            matched.append(n)
+        k += b
     return dict(best=best, cand=cand, done=done, matched=matched)

@@ -49,18 +49,19 @@ def _exhaustive(ctx, c, params, offsets):
     return torch.stack(out)
 
 
-@pytest.mark.parametrize("accept,radius", [(15.0, 0), (30.0, 0), (0.0, 0), (float("inf"), 0), (15.0, 36)])
-def test_search_matches_exhaustive_selection(ctx, case, accept, radius):
+@pytest.mark.parametrize("accept,radius,ahead", [(15.0, 0, 1), (30.0, 0, 1), (0.0, 0, 1), (float("inf"), 0, 1),
+                                                (15.0, 36, 1), (15.0, 36, 2), (15.0, 0, 3), (30.0, 0, 4)])
+def test_search_matches_exhaustive_selection(ctx, case, accept, radius, ahead):
     import paper_1612_04787_amd as sw
     from paper_1612_04787_amd.search import search_offsets, spiral_offsets
-    print("case search accept=%g radius=%d" % (accept, radius), flush=True)
+    print("case search accept=%g radius=%d lookahead=%d" % (accept, radius, ahead), flush=True)
     params = sw.make_params(p=0.65, max_shift=radius)
     offs = spiral_offsets(64.0, 2)
     K = offs.shape[0]
     full = _exhaustive(ctx, case, params, offs)
     snr = full.view(torch.float32).view(K, -1, 16)[:, :, 5].cpu().numpy()
     got = search_offsets(ctx, [case["a"], case["b"]], case["nl"], case["ia"], case["ib"], case["ta"], case["tb"],
-                         params, offs, accept=accept)
+                         params, offs, accept=accept, lookahead=ahead)
     torch.cuda.synchronize()
     cand = got["cand"].cpu().numpy()
     done = got["done"].cpu().numpy()
@@ -74,7 +75,17 @@ def test_search_matches_exhaustive_selection(ctx, case, accept, radius):
         assert done[w] == (1 if snr[arg, w] >= accept else 0), (w, done[w])
         # the kept record is the one the whole batch produced at that candidate
         assert torch.equal(best[w], full[arg, w].cpu()), w
-    want = [int((counts > k).sum()) for k in range(K)]
+    # a round starting at candidate k matches every window still searching
+    # there at the next `ahead` candidates
+    want, k = [], 0
+    while k < K:
+        n = int((counts > k).sum())
+        if n == 0:
+            want += [0] * (K - k)
+            break
+        b = min(ahead, K - k)
+        want += [n] * b
+        k += b
     assert got["matched"] == want, (got["matched"], want)
     print("   matched per candidate:", got["matched"], "of", P * K, flush=True)
 
@@ -189,9 +200,15 @@ def test_search_keep_rules(ctx):
     assert done.tolist() == [1, 0, 1, 0]
     snr = best.view(torch.float32).view(P, 16)[:, 5].tolist()
     assert snr == [12.0, 0.0, 11.0, 0.0]
+    # a window already done is left alone, even by a better match
+    ctx.search_keep(P, torch.tensor([0, 2], dtype=torch.int32, device=dev()), _records([50.0, 60.0]), 3, 10.0, best,
+                    cand, done)
+    torch.cuda.synchronize()
+    assert cand.tolist() == [0, -1, 2, 2]
+    assert best.view(torch.float32).view(P, 16)[:, 5].tolist() == [12.0, 0.0, 11.0, 0.0]
     # n = 0 launches nothing
     e = torch.zeros(0, dtype=torch.int32, device=dev())
-    ctx.search_keep(P, e, torch.zeros((0, 64), dtype=torch.uint8, device=dev()), 3, 10.0, best, cand, done)
+    ctx.search_keep(P, e, torch.zeros((0, 64), dtype=torch.uint8, device=dev()), 4, 10.0, best, cand, done)
     # n above P and a negative candidate are rejected
     with pytest.raises(sw.SwiftError):
         ctx.search_keep(2, idx[:3], _records([1.0, 2.0, 3.0]), 0, 10.0, best[:2], cand[:2], done[:2])
