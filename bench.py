@@ -640,7 +640,18 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
     search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=accept)
     prof = ctx.profile_read()
     ctx.profile(False)
-    kernels = {name: dict(launches=cnt, avg_ms=tot / cnt, total_ms=tot) for name, (cnt, tot) in prof.items()}
+    # launches shrink round by round, so each kernel is priced over the whole
+    # search: algorithmic bytes of every match it ran over its total time
+    m_prof = int(sum(got["matched"]))
+    rows = kept_rows(n, radius, ctx.plan(n)[1])
+    kernels = {}
+    for name, (cnt, tot) in prof.items():
+        byt = variant_bytes(name, n, m_prof, rows, False)
+        kernels[name] = dict(launches=cnt, avg_ms=tot / cnt, total_ms=tot, bytes=byt, gbs=byt / (tot / 1e3) / 1e9)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    roof = dict(bound="hbm", kernel=dom, achieved=kernels[dom]["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=kernels[dom]["gbs"] / HBM_PEAK_GBS, traffic=None, matches=m_prof,
+                total_ms=kernels[dom]["total_ms"])
     rec = sw.parse_records(got["best"])
     cand = got["cand"].cpu().numpy()
     done = got["done"].cpu().numpy().astype(bool)
@@ -662,7 +673,7 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
                 exhaustive=dict(ms=ms_full, matches=P * K), speedup=ms_full / ms,
                 done_frac=float(done.mean()), max_err_px_done=float(err[done].max()) if done.any() else None,
                 max_err_px_all=float(err.max()), same_offset_as_exhaustive=float(agree.mean()), lookahead=ahead,
-                kernels=kernels), sample
+                kernels=kernels, roofline=roof), sample
 
 
 def cpu_baseline_search(sample, n=256, windows=range(0, 576, 16)):
@@ -907,6 +918,8 @@ def main():
             "same offset as exhaustive %.3f" % (q["ms"], q["matches"], q["exhaustive"]["ms"],
                                                 q["exhaustive"]["matches"], q["speedup"], q["done_frac"],
                                                 q["max_err_px_done"] or -1, q["same_offset_as_exhaustive"]))
+        log("search: %s %.1f GB/s over the search (%.2f of HBM peak)"
+            % (q["roofline"]["kernel"], q["roofline"]["achieved"], q["roofline"]["frac"]))
         for B, v in q["lookahead"].items():
             log("search, %s candidates per round: %.2f ms (%d matches), same result %s"
                 % (B, v["ms"], v["matches"], v["same_result"]))
