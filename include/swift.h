@@ -280,6 +280,10 @@ int swift_join_break(swift_ctx* ctx, int32_t S, int32_t j, const double* aff, co
  * must be distinct (one thread owns each window's record), as
  * swift_search_next's output is.  Errors: SWIFT_E_INVAL (NULL,
  * n outside [0, P], cand < 0), SWIFT_E_HIP. */
+int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, const swift_match* recs,
+                      int32_t cand, float accept, swift_match* best, int32_t* best_cand, uint8_t* done,
+                      hipStream_t stream);
+
 /* Next round of the search with an SNR stop (Section III, SNR paragraph):
  * gathers the windows w with done[w] == 0, in ascending order, into
  * idx[0..n) (their indices), img_a_out/img_b_out and theta_a_out/theta_b_out
@@ -293,10 +297,6 @@ int swift_search_next(swift_ctx* ctx, int32_t P, const uint8_t* done, float ox, 
                       const int32_t* img_b, const float* theta_a, const float* theta_b, int32_t* idx,
                       int32_t* img_a_out, int32_t* img_b_out, float* theta_a_out, float* theta_b_out,
                       int32_t* count, hipStream_t stream);
-
-int swift_search_keep(swift_ctx* ctx, int32_t P, int32_t n, const int32_t* idx, const swift_match* recs,
-                      int32_t cand, float accept, swift_match* best, int32_t* best_cand, uint8_t* done,
-                      hipStream_t stream);
 
 /* One level of the x2 source pyramid (Section III: iscale): dst(x, y) =
  * (sum of the 2x2 block at (2x, 2y) + 2) >> 2 for uint8 images; dst must be
