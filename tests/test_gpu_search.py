@@ -288,3 +288,42 @@ def test_search_mixed_window_sizes(ctx, case):
     assert got["matched"] == [sum(1 for x in counts if x > k) for k in range(K)]
     assert int(sw.parse_records(got["best"])["n"].cpu()[0]) == 64
     print("   matched per candidate:", got["matched"], flush=True)
+
+
+def test_search_bench_size_sampled(ctx):
+    # the benchmark's search: 576 windows of 256^2 on an 8192^2 pair, 25
+    # candidates 128 px apart, radius 68, stop at 15; the selection against the
+    # exhaustive search, sampled records against the oracle
+    import paper_1612_04787_amd as sw
+    from paper_1612_04787_amd.search import search_offsets, spiral_offsets
+    print("case search bench size", flush=True)
+    a, b, m, bv, nl, ia, ib, ta, tb, cen = search_pair(8192, 256, 24, device=dev())
+    params = sw.make_params(p=0.65, max_shift=68)
+    offs = spiral_offsets(128.0, 2)
+    K, P = offs.shape[0], len(nl)
+    full = []
+    for k in range(K):
+        r = ctx.match_batch([a, b], nl, ia, ib, _shifted(ta, offs[k]), tb, params)
+        full.append(r["raw"].clone())
+    full = torch.stack(full)
+    snr = full.view(torch.float32).view(K, -1, 16)[:, :, 5].cpu().numpy()
+    got = search_offsets(ctx, [a, b], nl, ia, ib, ta, tb, params, offs, accept=15.0)
+    torch.cuda.synchronize()
+    cand = got["cand"].cpu().numpy()
+    best = got["best"].cpu()
+    for w in range(P):
+        arg, _ = O.search_select(snr[:, w].tolist(), 15.0)
+        assert cand[w] == arg, (w, cand[w], arg)
+        assert torch.equal(best[w], full[arg, w].cpu()), w
+    assert bool(got["done"].all())
+    rec = sw.parse_records(got["best"])
+    an, bn = a.cpu().numpy(), b.cpu().numpy()
+    tn = ta.cpu().numpy().astype(np.float64)
+    o = offs.numpy().astype(np.float64)
+    for w in (0, 287, 575):
+        th = tn[w].copy()
+        th[4] += o[cand[w], 0]
+        th[7] += o[cand[w], 1]
+        r = O.match_pair(an, bn, th, tn[w], 256, O.Params(p=0.65, max_shift=68))
+        e = compare(gpu_record(rec, w), r, 256, tag="bench-size search window %d" % w)
+        print("   window %d cand %d:" % (w, cand[w]), e, flush=True)
