@@ -58,8 +58,24 @@ def _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac
     return ta, out, it
 
 
+def _search_start(sw, images, ia, ib, ta, tb, n, p, rings, accept):
+    """Window A parameters moved to each window's kept candidate of a search
+    with an SNR stop (Section III): candidates n/2 apart in a square spiral,
+    each scored within radius n/4 + 4 px (its own cell).  Returns (theta_a,
+    matches run)."""
+    from .search import search_offsets, spiral_offsets
+    offs = spiral_offsets(n / 2.0, rings)
+    got = search_offsets(sw, images, [n] * ta.shape[0], ia, ib, ta, tb, make_params(p=p, max_shift=n // 4 + 4), offs,
+                         accept=accept)
+    o = offs.to(ta.device)[got["cand"].long().clamp(min=0)]
+    ta = ta.clone()
+    ta[:, 4] += o[:, 0]
+    ta[:, 7] += o[:, 1]
+    return ta, int(sum(got["matched"]))
+
+
 def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), ks=(3, 3, 3), grid=8, p=0.65,
-                refine="adjoint", min_snr=6.0, tol=0.005, stop_frac=0.01, aff=None, on_pass=None):
+                refine="adjoint", min_snr=6.0, tol=0.005, stop_frac=0.01, aff=None, on_pass=None, search=None):
     """Aligns a [S, H, W] uint8 device stack.  Returns (affines [S, 6] float64
     device, level-0 aligned frame -> raw section, and a list of per-pass
     reports).  ks: model half-span per level (wider models at coarse levels
@@ -68,7 +84,12 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
     the refinement of a pass stops when at most stop_frac of the windows still
     step by tol px or more (windows on damaged or featureless content may never
     settle).
-    on_pass(report, aff), if given, is called after every pass."""
+    on_pass(report, aff), if given, is called after every pass.
+    search: None, or a dict (rings, accept) for a search with an SNR stop in
+    the first pass (Section III: early stages of an alignment): every window
+    first searches candidate offsets (search.search_offsets) and refines from
+    its kept one, so sections misplaced beyond one window's capture are
+    found."""
     S, H, W = raw.shape
     dev = raw.device
     pyr = build_pyramid(sw, raw, max(levels))
@@ -89,13 +110,17 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             images = [src[s] for s in range(S)] + [model[s] for s in range(S)]
             ia, ib, ta, tb = sw.stack_windows(aff, level, grid, hl, wl, 0, S)
             P = ta.shape[0]
+            searched = 0
+            if search is not None and not reports:
+                ta, searched = _search_start(sw, images, ia, ib, ta, tb, n, p, int(search.get("rings", 2)),
+                                             float(search.get("accept", 15.0)))
             ta, out, it = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
             status = sw.fit_sections(ta, tb, out, grid * grid, level, aff, min_snr=min_snr)
             torch.cuda.synchronize(dev)
             el = time.perf_counter() - t0
             rec = parse_records(out)
             snr = rec["snr"].float()
-            rep_d = dict(level=level, n=n, k=k, repeat=rep, pairs=P, refine_iters=it, ms=el * 1e3,
+            rep_d = dict(level=level, n=n, k=k, repeat=rep, pairs=P, search_matches=searched, refine_iters=it, ms=el * 1e3,
                          median_snr=float(snr.median()), frac_snr_gt_15=float((snr > 15).float().mean()),
                          frac_weighted=float((snr >= min_snr).float().mean()),
                          singular_sections=int((status != 0).sum()))

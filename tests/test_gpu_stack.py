@@ -149,3 +149,35 @@ def test_align_stack_reduces_misalignment(ctx, refine):
     assert n1 < 0.5 * n0
     assert rep[-1]["median_snr"] > rep[0]["median_snr"]
     assert rep[-1]["singular_sections"] == 0
+
+
+def test_align_stack_search_finds_a_misplaced_section(ctx):
+    """12 sections of 2048^2 with drift and section affines; section 6 is moved
+    by a further (150, -110) px, 37.5 px at level 2: beyond what a 64^2 window
+    captures there.  With the search in the first pass the loop aligns it;
+    without, the section stays misplaced."""
+    from datagen.evaluate import composed_points
+    from datagen.synth import make_stack
+    from datagen.workloads import stack_warps
+    from paper_1612_04787_amd.stack import align_stack
+    print("case align stack with search", flush=True)
+    S, size, j = 12, 2048, 6
+    warps = stack_warps(S, size, size, 41)
+    m, b = warps[j]
+    warps[j] = (m, b + np.array([150.0, -110.0]))
+    raw = make_stack(S, size, size, 41, device=dev(), warps=warps)
+    pts = np.array([(128 + 256 * i, 128 + 256 * k) for k in range(8) for i in range(8)], np.float64)
+
+    def pair_res(a):
+        c = composed_points(a.cpu().numpy(), warps, pts)
+        return np.sqrt(np.mean(np.sum((c[1:] - c[:-1]) ** 2, 2), 1))
+
+    kw = dict(levels=(2, 1, 0), ns=(64, 128, 256), iters=(2, 1, 1), ks=(3, 3, 3))
+    aff_s, rep_s = align_stack(ctx, raw, search=dict(rings=2, accept=15.0), **kw)
+    aff_n, rep_n = align_stack(ctx, raw, **kw)
+    r_s, r_n = pair_res(aff_s), pair_res(aff_n)
+    print("   search: %d matches; pair residuals with search max %.2f px, without: at the section %.1f / %.1f px"
+          % (rep_s[0]["search_matches"], r_s.max(), r_n[j - 1], r_n[j]), flush=True)
+    assert rep_s[0]["search_matches"] > 0 and rep_s[1]["search_matches"] == 0
+    assert r_s.max() < 1.0
+    assert min(r_n[j - 1], r_n[j]) > 20.0
