@@ -676,6 +676,46 @@ def search_block(ctx, sw, dev, size=8192, n=256, grid=24, step=128.0, rings=2, a
                 kernels=kernels, roofline=roof), sample
 
 
+def search_stack_block(ctx, dev, sections=12, size=2048, j=6, move=(150.0, -110.0)):
+    """The stack loop with and without a search in its first pass, on
+    sections with drift and section affines where section j is moved a further
+    `move` px (beyond a 64^2 window's capture at level 2).  Neighbour
+    residuals against the generator's warps."""
+    import numpy as np
+    import torch
+
+    from datagen.evaluate import composed_points
+    from datagen.synth import make_stack
+    from datagen.workloads import stack_warps
+    from paper_1612_04787_amd.stack import align_stack
+    warps = stack_warps(sections, size, size, 41)
+    m, b = warps[j]
+    warps[j] = (m, b + np.asarray(move))
+    raw = make_stack(sections, size, size, 41, device=dev, warps=warps)
+    pts = np.array([(size // 16 + size // 8 * i, size // 16 + size // 8 * k) for k in range(8) for i in range(8)],
+                   np.float64)
+
+    def pair_res(a):
+        c = composed_points(a.cpu().numpy(), warps, pts)
+        return np.sqrt(np.mean(np.sum((c[1:] - c[:-1]) ** 2, 2), 1))
+
+    kw = dict(levels=(2, 1, 0), ns=(64, 128, 256), iters=(2, 1, 1), ks=(3, 3, 3))
+    out = {}
+    for name, srch in (("with_search", dict(rings=2, accept=15.0)), ("without", None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        aff, rep = align_stack(ctx, raw, search=srch, **kw)
+        torch.cuda.synchronize()
+        r = pair_res(aff)
+        out[name] = dict(wall_ms=(time.perf_counter() - t0) * 1e3, search_matches=rep[0]["search_matches"],
+                         first_pass_ms=rep[0]["ms"], max_pair_px=float(r.max()), at_section_px=float(r[j - 1]))
+    del raw
+    torch.cuda.empty_cache()
+    out["workload"] = ("%d sections of %d^2 (drift, section affines), section %d moved a further (%g, %g) px; "
+                       "levels 2/1/0 with 64/128/256 windows, 8 x 8 per section" % (sections, size, j, move[0], move[1]))
+    return out
+
+
 def cpu_baseline_search(sample, n=256, windows=range(0, 576, 16)):
     """The oracle's search (FP64 matches over the candidate list, stopping at
     the threshold) for a few windows of the search pair, one process, in
@@ -923,6 +963,12 @@ def main():
         for B, v in q["lookahead"].items():
             log("search, %s candidates per round: %.2f ms (%d matches), same result %s"
                 % (B, v["ms"], v["matches"], v["same_result"]))
+        log("search in the stack loop: a section moved beyond one window's capture ...")
+        q["stack_loop"] = search_stack_block(ctx, dev)
+        w1, w0 = q["stack_loop"]["with_search"], q["stack_loop"]["without"]
+        log("search in the stack loop: max pair residual %.2f px with (%d search matches, %.0f ms), "
+            "%.1f px without (%.0f ms)" % (w1["max_pair_px"], w1["search_matches"], w1["wall_ms"], w0["max_pair_px"],
+                                           w0["wall_ms"]))
     mesh_sample = None
     if not args.no_mesh:
         log("mesh: global affines then two local-affine mesh passes on a bent stack ...")
