@@ -701,7 +701,9 @@ def search_stack_block(ctx, dev, sections=12, size=2048, j=6, move=(150.0, -110.
 
     kw = dict(levels=(2, 1, 0), ns=(64, 128, 256), iters=(2, 1, 1), ks=(3, 3, 3))
     out = {}
-    for name, srch in (("with_search", dict(rings=2, accept=15.0)), ("without", None)):
+    for name, srch in (("with_search", dict(rings=2, accept=15.0)), ("with_search_one_per_round",
+                                                                     dict(rings=2, accept=15.0, lookahead=1)),
+                       ("without", None)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         aff, rep = align_stack(ctx, raw, search=srch, **kw)
@@ -966,9 +968,11 @@ def main():
         log("search in the stack loop: a section moved beyond one window's capture ...")
         q["stack_loop"] = search_stack_block(ctx, dev)
         w1, w0 = q["stack_loop"]["with_search"], q["stack_loop"]["without"]
-        log("search in the stack loop: max pair residual %.2f px with (%d search matches, %.0f ms), "
-            "%.1f px without (%.0f ms)" % (w1["max_pair_px"], w1["search_matches"], w1["wall_ms"], w0["max_pair_px"],
-                                           w0["wall_ms"]))
+        w4 = q["stack_loop"]["with_search_one_per_round"]
+        log("search in the stack loop: max pair residual %.2f px with (%d search matches, %.0f ms; with one "
+            "candidate per round %.2f px, %.0f ms), %.1f px without (%.0f ms)"
+            % (w1["max_pair_px"], w1["search_matches"], w1["wall_ms"], w4["max_pair_px"], w4["wall_ms"],
+               w0["max_pair_px"], w0["wall_ms"]))
     mesh_sample = None
     if not args.no_mesh:
         log("mesh: global affines then two local-affine mesh passes on a bent stack ...")

@@ -58,7 +58,7 @@ def _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac
     return ta, out, it
 
 
-def _search_start(sw, images, ia, ib, ta, tb, n, p, rings, accept):
+def _search_start(sw, images, ia, ib, ta, tb, n, p, rings, accept, lookahead=1):
     """Window A parameters moved to each window's kept candidate of a search
     with an SNR stop (Section III): candidates n/2 apart in a square spiral,
     each scored within radius n/4 + 4 px (its own cell).  Returns (theta_a,
@@ -66,7 +66,7 @@ def _search_start(sw, images, ia, ib, ta, tb, n, p, rings, accept):
     from .search import search_offsets, spiral_offsets
     offs = spiral_offsets(n / 2.0, rings)
     got = search_offsets(sw, images, [n] * ta.shape[0], ia, ib, ta, tb, make_params(p=p, max_shift=n // 4 + 4), offs,
-                         accept=accept)
+                         accept=accept, lookahead=lookahead)
     o = offs.to(ta.device)[got["cand"].long().clamp(min=0)]
     ta = ta.clone()
     ta[:, 4] += o[:, 0]
@@ -85,11 +85,12 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
     step by tol px or more (windows on damaged or featureless content may never
     settle).
     on_pass(report, aff), if given, is called after every pass.
-    search: None, or a dict (rings, accept) for a search with an SNR stop in
+    search: None, or a dict (rings, accept, lookahead) for a search with an SNR stop in
     the first pass (Section III: early stages of an alignment): every window
     first searches candidate offsets (search.search_offsets) and refines from
     its kept one, so sections misplaced beyond one window's capture are
-    found."""
+    found.  lookahead (default 4) candidates are matched per round: the
+    coarse level's small windows make a round launch-bound."""
     S, H, W = raw.shape
     dev = raw.device
     pyr = build_pyramid(sw, raw, max(levels))
@@ -113,7 +114,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             searched = 0
             if search is not None and not reports:
                 ta, searched = _search_start(sw, images, ia, ib, ta, tb, n, p, int(search.get("rings", 2)),
-                                             float(search.get("accept", 15.0)))
+                                             float(search.get("accept", 15.0)), int(search.get("lookahead", 4)))
             ta, out, it = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
             status = sw.fit_sections(ta, tb, out, grid * grid, level, aff, min_snr=min_snr)
             torch.cuda.synchronize(dev)
