@@ -89,8 +89,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
     the first pass (Section III: early stages of an alignment): every window
     first searches candidate offsets (search.search_offsets) and refines from
     its kept one, so sections misplaced beyond one window's capture are
-    found.  lookahead (default 4) candidates are matched per round: the
-    coarse level's small windows make a round launch-bound."""
+    found.  lookahead (default 1) candidates are matched per round."""
     S, H, W = raw.shape
     dev = raw.device
     pyr = build_pyramid(sw, raw, max(levels))
@@ -114,7 +113,7 @@ def align_stack(sw, raw, levels=(2, 1, 0), ns=(128, 256, 512), iters=(2, 1, 1), 
             searched = 0
             if search is not None and not reports:
                 ta, searched = _search_start(sw, images, ia, ib, ta, tb, n, p, int(search.get("rings", 2)),
-                                             float(search.get("accept", 15.0)), int(search.get("lookahead", 4)))
+                                             float(search.get("accept", 15.0)), int(search.get("lookahead", 1)))
             ta, out, it = _match_windows(sw, images, ia, ib, ta, tb, n, params, refine, tol, stop_frac)
             status = sw.fit_sections(ta, tb, out, grid * grid, level, aff, min_snr=min_snr)
             torch.cuda.synchronize(dev)
