@@ -49,12 +49,18 @@ class Params:
                (the pruned inverse transform, a speed-up the paper names in
                Section V); 0 searches the whole surface.  The SNR background
                is the whole surface either way.
+    snr_exclude_r  R >= 0: the SNR background (mean and population std) leaves
+               out the (2R+1)^2 surface entries around the integer peak
+               (wrapped); 0 takes the whole surface (Section III, Z-score
+               paragraph: the peak is scored against the background
+               distribution of the surface).
     """
     p: float = 0.65
     eps_rel: float = 1e-4
     taper_frac: float = 0.25
     centroid_r: int = 1
     max_shift: int = 0
+    snr_exclude_r: int = 0
 
 
 # ---------------------------------------------------------------------------
@@ -122,15 +128,44 @@ def taper_2d(n, taper_frac):
     return np.outer(t, t)
 
 
-def prepare(a, T):
+DEGENERATE_REL = 1e-6
+
+
+def centre_pixel(img, theta):
+    """Value of the source pixel nearest the window centre (u = v = 0), i.e.
+    img[clamp(floor(y + 1/2))][clamp(floor(x + 1/2))] at x = cx + tx,
+    y = cy + ty.  It is the offset o about which a window's sums are taken
+    (prepare)."""
+    img = np.asarray(img)
+    h, w = img.shape
+    x = float(theta[0]) + float(theta[4])
+    y = float(theta[1]) + float(theta[7])
+    xi = int(np.clip(np.floor(x + 0.5), 0, w - 1))
+    yi = int(np.clip(np.floor(y + 0.5), 0, h - 1))
+    return float(img[yi, xi])
+
+
+def prepare(a, T, o=None):
     """Subtract the taper-weighted mean, then taper: w = (a - m_T) T with
-    m_T = sum(a T) / sum(T).  Returns (w, m_T).  For a window whose samples
-    are all equal, m_T is that value and w is exactly zero (the FP64 quotient
-    could miss the constant by an ulp and leave rounding noise in w)."""
-    if a.size and np.all(a == a.flat[0]):
-        return np.zeros_like(a, dtype=np.float64), float(a.flat[0])
-    m = float(np.sum(a * T) / np.sum(T))
-    return (a - m) * T, m
+    m_T = sum(a T) / sum(T).  Returns (w, m_T).
+
+    The sums are taken about an offset o (default: the centre sample): with
+    d = a - o and m' = sum(d T) / sum(T), w = (d - m') T and m_T = o + m',
+    the same w in exact arithmetic.  A window is degenerate (no signal to
+    match) when ||w||^2 <= 1e-6 sum((d T)^2): its samples are equal up to
+    rounding relative to their spread about o.  Its w is returned as exactly
+    zero, so its surface is zero and its record degenerate.  A window whose
+    samples all equal o has d = 0 and is degenerate exactly."""
+    a = np.asarray(a, dtype=np.float64)
+    if o is None:
+        o = float(a[a.shape[0] // 2, a.shape[1] // 2])
+    d = a - o
+    dT = d * T
+    m1 = float(np.sum(dT) / np.sum(T))
+    w = (d - m1) * T
+    if float(np.sum(w * w)) <= DEGENERATE_REL * float(np.sum(dT * dT)):
+        return np.zeros_like(w), o + m1
+    return w, o + m1
 
 
 # ---------------------------------------------------------------------------
@@ -173,18 +208,30 @@ def search_mask(n, max_shift):
     return s[:, None] & s[None, :]
 
 
-def peak_stats(c, centroid_r=1, max_shift=0):
+def background_mask(n, iy, ix, exclude_r):
+    """Surface entries of the SNR background: all of them for exclude_r 0,
+    else all but the (2R+1)^2 box around (iy, ix), wrapped."""
+    bg = np.ones((n, n), dtype=bool)
+    for dyy in range(-exclude_r, exclude_r + 1):
+        for dxx in range(-exclude_r, exclude_r + 1):
+            bg[(iy + dyy) % n, (ix + dxx) % n] = False
+    return bg
+
+
+def peak_stats(c, centroid_r=1, max_shift=0, exclude_r=0):
     """Integer peak (first maximum in row-major order among the entries of
-    search_mask), Z-score SNR over the whole surface (population std), and a
-    (2r+1)^2 centroid with weights max(c - mean, 0), shifts wrapped to
-    [-N/2, N/2)."""
+    search_mask), Z-score SNR against the background (population std; the
+    whole surface, or the surface without the (2R+1)^2 box around the peak
+    for exclude_r = R > 0), and a (2r+1)^2 centroid with weights
+    max(c - mean, 0), shifts wrapped to [-N/2, N/2)."""
     n = c.shape[0]
     cand = np.where(search_mask(n, max_shift), c, -np.inf).ravel()
     flat = int(np.argmax(cand))
     iy, ix = divmod(flat, n)
     peak = float(c[iy, ix])
-    mu = float(np.mean(c))
-    sd = float(np.sqrt(np.mean((c - mu) ** 2)))
+    bgv = c[background_mask(n, iy, ix, int(exclude_r))] if exclude_r > 0 else c
+    mu = float(np.mean(bgv))
+    sd = float(np.sqrt(np.mean((bgv - mu) ** 2)))
     status = 0
     if sd > 0:
         snr = (peak - mu) / sd
@@ -296,10 +343,10 @@ def match_pair(imgA, imgB, thetaA, thetaB, n, params: Params, return_surface=Fal
     a, clA = gather(imgA, thetaA, n)
     b, clB = gather(imgB, thetaB, n)
     T = taper_2d(n, params.taper_frac)
-    wA, _ = prepare(a, T)
-    wB, _ = prepare(b, T)
+    wA, _ = prepare(a, T, centre_pixel(imgA, thetaA))
+    wB, _ = prepare(b, T, centre_pixel(imgB, thetaB))
     c = whitened_surface(wA, wB, params.p, params.eps_rel)
-    rec = peak_stats(c, params.centroid_r, params.max_shift)
+    rec = peak_stats(c, params.centroid_r, params.max_shift, params.snr_exclude_r)
     if clA or clB:
         rec["status"] |= STATUS_CLAMPED
     if return_surface:
@@ -338,12 +385,14 @@ def match_grad(imgA, imgB, thetaA, thetaB, n, params: Params, g_peak=0.0, g_snr=
     """Returns (record, dJ/dthetaA[6], dJ/dthetaB[6]) with J = g_peak c[s*] +
     g_snr SNR + g_dx dx + g_dy dy (dx, dy: the centroid shift); the six
     entries are (a11, a12, tx, a21, a22, ty)."""
+    if params.snr_exclude_r:
+        raise NotImplementedError("the adjoint takes the whole surface as the SNR background")
     p, eps_rel = params.p, params.eps_rel
     a, _ = gather(imgA, thetaA, n)
     b, _ = gather(imgB, thetaB, n)
     T = taper_2d(n, params.taper_frac)
-    wA, _ = prepare(a, T)
-    wB, _ = prepare(b, T)
+    wA, _ = prepare(a, T, centre_pixel(imgA, thetaA))
+    wB, _ = prepare(b, T, centre_pixel(imgB, thetaB))
     M = n * n
     # forward on the full spectrum
     FA = np.fft.fft2(wA)

@@ -245,6 +245,130 @@ def test_degenerate_constant_window(value, taper, n):
     assert rec["snr"] == 0.0 and rec["status"] & STATUS_DEGENERATE
 
 
+def _taper_sums(n, taper):
+    t = O.taper_1d(n, taper)
+    T = np.outer(t, t)
+    return T, float(T.sum()), float((T * T).sum())
+
+
+def test_prepare_is_the_weighted_mean_removal_about_any_offset():
+    """w = (a - m_T) T with m_T = sum(aT)/sum(T), whatever offset the sums are
+    taken about (written out directly here, not through the offset form)."""
+    rng = np.random.default_rng(21)
+    n = 32
+    T, sT, _ = _taper_sums(n, 0.25)
+    a = rng.uniform(0, 255, (n, n))
+    mT = float((a * T).sum()) / sT
+    direct = (a - mT) * T
+    for o in (0.0, 128.0, float(a[n // 2, n // 2]), 1e4):
+        w, m = O.prepare(a, T, o)
+        np.testing.assert_allclose(w, direct, atol=1e-9 * np.abs(direct).max())
+        assert abs(m - mT) < 1e-9 * abs(mT)
+
+
+@pytest.mark.parametrize("n", [64, 512])
+def test_near_constant_window_is_scored(n):
+    """A window of 200 with one pixel at 201 is not degenerate: about the
+    centre pixel o = 200, d is one unit impulse at p, and ||w||^2 / sum (dT)^2
+    = 1 - 2 T_p / sum T + sum T^2 / (sum T)^2 (closed form, near 1)."""
+    T, sT, sT2 = _taper_sums(n, 0.25)
+    py, px = n // 3, n // 5
+    a = np.full((n, n), 200.0)
+    a[py, px] = 201.0
+    w, _ = O.prepare(a, T, 200.0)
+    Tp = T[py, px]
+    ratio = 1 - 2 * Tp / sT + sT2 / sT ** 2
+    assert abs(float((w * w).sum()) - Tp * Tp * ratio) < 1e-12 * Tp * Tp
+    rng = np.random.default_rng(2)
+    img = np.full((n + 8, n + 8), 200.0)
+    img[4 + py, 4 + px] = 201.0
+    th = ident(4 + n / 2, 4 + n / 2)
+    assert O.centre_pixel(img, th) == 200.0
+    b = img + 0.0
+    rec = O.match_pair(img, b, th, th, n, O.Params(p=0.65))
+    assert not rec["status"] & STATUS_DEGENERATE and rec["snr"] > 1.0
+    assert (rec["sx"], rec["sy"]) == (0, 0)
+    del rng
+
+
+@pytest.mark.parametrize("below", [True, False])
+def test_degeneracy_threshold_closed_form(below):
+    """d = a - o = K + delta [i = p]: ||w||^2 = delta^2 T_p^2 rho (rho as in
+    the impulse case, K drops out with the mean) while sum (dT)^2 = K^2 sum T^2
+    + 2 K delta T_p^2 + delta^2 T_p^2.  The window is degenerate exactly when
+    their ratio is at most 1e-6."""
+    n = 64
+    T, sT, sT2 = _taper_sums(n, 0.25)
+    py, px = 20, 41
+    Tp = T[py, px]
+    rho = 1 - 2 * Tp / sT + sT2 / sT ** 2
+    delta = 1.0
+    target = 0.5e-6 if below else 2e-6
+    # solve K^2 sT2 + 2 K delta Tp^2 + delta^2 Tp^2 = delta^2 Tp^2 rho / target for K > 0
+    qa, qb, qc = sT2, 2 * delta * Tp * Tp, delta * delta * Tp * Tp * (1 - rho / target)
+    K = (-qb + math.sqrt(qb * qb - 4 * qa * qc)) / (2 * qa)
+    a = np.full((n, n), 50.0 + K)
+    a[py, px] += delta
+    w, _ = O.prepare(a, T, 50.0)
+    ratio = float((w * w).sum()) / float((((a - 50.0) * T) ** 2).sum())
+    if below:
+        assert not w.any()
+    else:
+        assert w.any() and abs(ratio / target - 1) < 1e-6
+
+
+def test_constant_window_off_the_offset_is_degenerate():
+    """Columns alternate 0 and 2; at half a pixel of x translation every
+    bilinear sample is exactly 1 while the centre pixel is 0 or 2, so the
+    samples are constant but not equal to the offset: still degenerate."""
+    n = 64
+    img = np.zeros((n + 8, n + 8))
+    img[:, 1::2] = 2.0
+    th = ident(4 + n / 2, 4 + n / 2, tx=0.5)
+    a, _ = O.gather(img, th, n)
+    assert np.all(a == 1.0) and O.centre_pixel(img, th) in (0.0, 2.0)
+    rng = np.random.default_rng(4)
+    imgb = rng.uniform(0, 255, img.shape)
+    rec = O.match_pair(img, imgb, th, ident(4 + n / 2, 4 + n / 2), n, O.Params(p=0.65))
+    assert rec["status"] & STATUS_DEGENERATE and rec["snr"] == 0.0
+
+
+def test_centre_pixel_rounds_half_up_and_clamps():
+    img = np.arange(20 * 30, dtype=np.float64).reshape(20, 30)
+    assert O.centre_pixel(img, ident(10.0, 5.0, tx=0.5, ty=0.49)) == img[5, 11]
+    assert O.centre_pixel(img, ident(10.0, 5.0, tx=0.49, ty=0.5)) == img[6, 10]
+    assert O.centre_pixel(img, ident(-3.0, 5.0)) == img[5, 0]
+    assert O.centre_pixel(img, ident(10.0, 40.0)) == img[19, 10]
+
+
+def test_snr_background_exclusion_closed_form():
+    """Checkerboard surface (-1)^(x+y) on 8 x 8 with a 3 x 3 box of 5 around a
+    peak of 10 at (iy, ix) = (2, 3).  Without the box the background is the
+    55 checkerboard entries outside it: the box covers five entries of sign
+    -1 and four of +1, so they sum to +1 and their squares to 55: mean 1/55,
+    population variance 1 - 1/55^2.  The whole-surface statistics count the
+    box as well."""
+    n = 8
+    y, x = np.mgrid[0:n, 0:n]
+    c = np.where((x + y) % 2 == 0, 1.0, -1.0)
+    c[1:4, 2:5] = 5.0
+    c[2, 3] = 10.0
+    rec = O.peak_stats(c, exclude_r=1)
+    assert (rec["iy"], rec["ix"]) == (2, 3)
+    mu = 1.0 / 55.0
+    sd = math.sqrt(1.0 - mu * mu)
+    assert abs(rec["mean"] - mu) < 1e-15 and abs(rec["std"] - sd) < 1e-15
+    assert abs(rec["snr"] - (10.0 - mu) / sd) < 1e-13
+    full = O.peak_stats(c)
+    mf = (1.0 + 8 * 5.0 + 10.0) / 64.0
+    assert abs(full["mean"] - mf) < 1e-15
+    # the box wraps around the surface edge
+    c2 = np.roll(np.roll(c, -2, axis=0), -3, axis=1)
+    rec2 = O.peak_stats(c2, exclude_r=1)
+    assert (rec2["iy"], rec2["ix"]) == (0, 0)
+    assert abs(rec2["mean"] - mu) < 1e-15 and abs(rec2["std"] - sd) < 1e-15
+
+
 # ---------------------------------------------------------------- peak / centroid
 def test_centroid_closed_forms_and_wrap():
     n = 16
@@ -835,6 +959,56 @@ def test_pearson_exact_shift_sign_and_invariance():
 
 
 # --------------------------------------------------------------------------- jump repair
+def test_pearson_peak_record_closed_form():
+    """Hand-built 5 x 5 placement grid (n = 8, range R = n/4 = 2): peak 1 at
+    the range corner (sy, sx) = (2, 2), 0.5 at (1, 2) and (2, 1), 0.25 at
+    (1, 1), and 0.8 at (-2, -2), the entry a wrapped neighbour (sy or sx = 3)
+    would read.  Over the 25 placements: mean 3.05 / 25 = 0.122, population
+    variance sum g^2 / 25 - mean^2 = 2.2025 / 25 - 0.122^2 (ddof 0, not 1),
+    SNR (1 - mean) / sigma.  The 3 x 3 centroid uses only the four
+    neighbours inside the range, weights g - mean."""
+    n, R = 8, 2
+    g = np.zeros((2 * R + 1, 2 * R + 1))
+
+    def put(sy, sx, v):
+        g[sy + R, sx + R] = v
+
+    put(2, 2, 1.0)
+    put(1, 2, 0.5)
+    put(2, 1, 0.5)
+    put(1, 1, 0.25)
+    put(-2, -2, 0.8)
+    rec = O.pearson_peak(g, n, st=1.0)
+    mu = 3.05 / 25.0
+    var = 2.2025 / 25.0 - mu * mu
+    assert (rec["ix"], rec["iy"], rec["sx"], rec["sy"]) == (2, 2, 2, 2)
+    assert abs(rec["mean"] - mu) < 1e-15
+    assert abs(rec["std"] - math.sqrt(var)) < 1e-15
+    assert abs(rec["snr"] - (1.0 - mu) / math.sqrt(var)) < 1e-13
+    w11, w12, w21, w22 = 0.25 - mu, 0.5 - mu, 0.5 - mu, 1.0 - mu
+    sw = w11 + w12 + w21 + w22
+    assert abs(rec["dx"] - (2 + (-w11 - w21) / sw)) < 1e-15
+    assert abs(rec["dy"] - (2 + (-w11 - w12) / sw)) < 1e-15
+    assert rec["status"] == 0
+
+
+def test_pearson_peak_tie_order_and_degenerate():
+    """Equal best coefficients at sy = -1 and sy = +1 (sx = 0): the wrapped
+    row of sy = -1 is n - 1, so the row-major first maximum is sy = +1 and the
+    near-tie bit is set.  A zero template energy is degenerate."""
+    n, R = 16, 4
+    g = np.full((2 * R + 1, 2 * R + 1), 0.1)
+    g[-1 + R, R] = 0.9
+    g[1 + R, R] = 0.9
+    rec = O.pearson_peak(g, n, st=2.0)
+    assert (rec["sx"], rec["sy"], rec["iy"]) == (0, 1, 1)
+    assert rec["status"] & STATUS_NEAR_TIE
+    deg = O.pearson_peak(g, n, st=0.0)
+    assert deg["status"] & STATUS_DEGENERATE and deg["snr"] == 0.0
+    flat = O.pearson_peak(np.full((2 * R + 1, 2 * R + 1), 0.3), n, st=2.0)
+    assert flat["status"] & STATUS_DEGENERATE and flat["std"] == 0.0
+
+
 def test_one_sided_models_brute_force():
     rng = np.random.default_rng(51)
     st = rng.integers(0, 256, (9, 5, 7)).astype(np.uint8)
