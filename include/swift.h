@@ -125,7 +125,26 @@ typedef struct {
  *             DC bin is 0) and the population std from the whitened spectrum
  *             by Parseval, std^2 = sum_k |C(k)|^2 / n^4.  r = 0, or r >= n/2,
  *             searches the whole surface.  With 0 < r < n/2 for some size in
- *             the batch, `surfaces` must be NULL. */
+ *             the batch, `surfaces` must be NULL.
+ *  snr_exclude_r  R in [0, 8] (Section III, Z-score paragraph: the peak is
+ *             scored against the background distribution of the surface).
+ *             R = 0: the background is the whole surface.  R > 0: the mean
+ *             and population std of the record (and so the SNR and the
+ *             centroid weights c - mean) are taken over the n^2 - (2R+1)^2
+ *             entries outside the box of half-width R around the integer peak
+ *             (wrapped).  Not with SWIFT_FLAG_PEARSON; the adjoint entry
+ *             points reject R > 0 (SWIFT_E_UNSUPPORTED).
+ *
+ * Samples.  Window samples a are taken about an offset o, the source pixel
+ * nearest the window centre, before the taper-weighted mean is removed (which
+ * makes the result independent of o).  A window is degenerate (status
+ * SWIFT_ST_DEGENERATE, SNR 0, surface 0) when its taper-weighted variance
+ * ||w||^2 is at most 1e-6 of sum((a - o) T)^2: its samples are equal up to
+ * rounding (a constant window always is).  The cross power is formed from
+ * the spectra divided by ||w||, so no input scale overflows the FP32
+ * arithmetic: SWIFT_F32 pixels may take any finite values whose window sums
+ * sum((a - o) T)^2 stay below 1e36 (|a - o| below about 1e15 at n = 1024);
+ * the results (surface values, peak) carry the input's scale. */
 #define SWIFT_FLAG_CONCURRENT_SIZES 1
 #define SWIFT_FLAG_JAC_TRANSLATION 2
 #define SWIFT_FLAG_PEARSON 4
@@ -136,6 +155,8 @@ typedef struct {
   int32_t centroid_r;
   int32_t flags;
   int32_t max_shift;
+  int32_t snr_exclude_r;
+  int32_t reserved;  /* must be 0 */
 } swift_params;
 
 /* One match record (64 bytes). */
@@ -143,8 +164,9 @@ typedef struct {
   float dx, dy;      /* sub-pixel shift: wrapped integer peak + 3x3 centroid   */
   int32_t ix, iy;    /* integer peak index in the n x n surface (first maximum) */
   float peak;        /* surface value at the peak                               */
-  float snr;         /* (peak - mean) / std over the whole surface              */
-  double mean, std;  /* surface mean and population std (FP64 reduction)        */
+  float snr;         /* (peak - mean) / std                                     */
+  double mean, std;  /* background mean and population std (FP64 reduction): the
+                        whole surface, or without the snr_exclude_r box         */
   int32_t status;    /* SWIFT_ST_* bits                                         */
   int32_t n;         /* window edge of this pair                                */
   float hxx, hyy;    /* surface curvature at the peak: second differences in x, y */
@@ -152,8 +174,14 @@ typedef struct {
   int32_t reserved;
 } swift_match;
 
-/* Context: owns the device twiddle table of one GPU.  Allocates (once). */
-int swift_create(int device, swift_ctx** out);
+/* Context: owns the device twiddle table of one GPU.  Allocates (once).
+ * tune_cache_path: host string or NULL.  When given, the plan (the kernel
+ * variants per window size, see swift_plan) is read from that text file for
+ * this device (its architecture name and compute-unit count) if the file
+ * exists, and swift_autotune writes the plans it finds back into it (other
+ * devices' lines are kept).  A missing file is not an error; unreadable lines
+ * are ignored. */
+int swift_create(int device, const char* tune_cache_path, swift_ctx** out);
 void swift_destroy(swift_ctx* ctx);
 
 /* Bytes of device workspace swift_match_batch needs for this batch
@@ -307,7 +335,9 @@ int swift_pyramid(swift_ctx* ctx, const swift_image* src, const swift_image* dst
 
 /* Peak, SNR and centroid of given correlation surfaces (the scoring step of
  * swift_match_batch alone; Section III, Z-score paragraph).
- *  surfaces  device [batch][n][n] float; out device [batch]. */
+ *  surfaces  device [batch][n][n] float; out device [batch].  params: only
+ *            snr_exclude_r is used (the rest is validated).
+ * Errors: SWIFT_E_INVAL (NULL, n outside [4, 4096], batch < 0, params). */
 int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch,
               const swift_params* params, swift_match* out, hipStream_t stream);
 

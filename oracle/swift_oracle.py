@@ -889,6 +889,17 @@ def failed_spans(section_snr, frac):
     return spans
 
 
+def break_score(aff, fit, centres):
+    """How far a section's fit against its left one-sided model moves its
+    windows: the RMS over the window centres c (level-0 px) of
+    |fit(c) - aff(c)|.  A score above the break threshold starts a break
+    (design reading of the locked-match paragraph of Section III)."""
+    c = np.asarray(centres, dtype=np.float64)
+    pa = np.stack(apply_affine(aff, c[:, 0], c[:, 1]), 1)
+    pf = np.stack(apply_affine(fit, c[:, 0], c[:, 1]), 1)
+    return float(np.sqrt(np.mean(np.sum((pf - pa) ** 2, 1))))
+
+
 def join_break(aff, aff_left, j):
     """Joins the sections from j on to the frame of the sections before a
     break at j: with A_j the affine of section j and L_j its fit against the

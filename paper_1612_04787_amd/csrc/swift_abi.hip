@@ -14,7 +14,7 @@
 
 using namespace swift;
 
-static_assert(sizeof(swift_image) == 32 && sizeof(swift_params) == 24 && sizeof(swift_match) == 64,
+static_assert(sizeof(swift_image) == 32 && sizeof(swift_params) == 32 && sizeof(swift_match) == 64,
               "C ABI struct sizes");
 
 // Records a pair of HIP events around every kernel launch while enabled.
@@ -90,6 +90,8 @@ struct swift_ctx {
   // row-count variant per window size (swift_plan / swift_autotune)
   uint8_t alt_fwd[SWIFT_NSIZES] = {};
   uint8_t alt_inv[SWIFT_NSIZES] = {};
+  // tune cache: file path ("" for none) and this device's key in it
+  std::string tune_path, tune_key;
 };
 
 static constexpr size_t kMaxGraphs = 16;
@@ -249,6 +251,8 @@ int check_pairs(const swift_pairs* pairs) {
   return SWIFT_OK;
 }
 
+constexpr int kMaxExcludeR = 8;
+
 int check_params(const swift_params* pr) {
   if (!pr) return fail(SWIFT_E_INVAL, "params is NULL");
   if (!(pr->p >= 0.0f && pr->p <= 1.0f)) return fail(SWIFT_E_INVAL, "p must be in [0, 1] (got %g)", pr->p);
@@ -262,6 +266,11 @@ int check_params(const swift_params* pr) {
   if (pr->max_shift < 0) return fail(SWIFT_E_INVAL, "max_shift must be >= 0 (got %d)", pr->max_shift);
   if ((pr->flags & SWIFT_FLAG_PEARSON) && pr->max_shift != 0)
     return fail(SWIFT_E_INVAL, "max_shift must be 0 with SWIFT_FLAG_PEARSON (its range is n/4)");
+  if (pr->snr_exclude_r < 0 || pr->snr_exclude_r > kMaxExcludeR)
+    return fail(SWIFT_E_INVAL, "snr_exclude_r must be in [0, %d] (got %d)", kMaxExcludeR, pr->snr_exclude_r);
+  if ((pr->flags & SWIFT_FLAG_PEARSON) && pr->snr_exclude_r != 0)
+    return fail(SWIFT_E_INVAL, "snr_exclude_r must be 0 with SWIFT_FLAG_PEARSON");
+  if (pr->reserved != 0) return fail(SWIFT_E_INVAL, "params.reserved must be 0");
   return SWIFT_OK;
 }
 
@@ -294,11 +303,76 @@ static void fill_lane_twiddles(float2* host) {
   }
 }
 
+// ---------------------------------------------------------------- tune cache
+// A text file of plan lines "<device key> <n> <fwd variant> <inv variant>",
+// one per device and window size; '#' starts a comment.  The device key is
+// the architecture name and the compute-unit count, so a file can serve
+// several kinds of device.
+static std::string device_key(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string arch(prop.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ' || ch == '\t') ch = '_';
+  char buf[320];
+  snprintf(buf, sizeof(buf), "%s/cu%d", arch.c_str(), prop.multiProcessorCount);
+  return buf;
+}
+
+static void tune_cache_load(swift_ctx* c) {
+  FILE* f = fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[512], key[320];
+  int n, vf, vi;
+  while (fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    if (sscanf(line, "%319s %d %d %d", key, &n, &vf, &vi) != 4) continue;
+    if (c->tune_key != key || vf < 0 || vf > 1 || vi < 0 || vi > 1) continue;
+    for (int i = 0; i < SWIFT_NSIZES; ++i)
+      if (kSizes[i] == n) {
+        c->alt_fwd[i] = (uint8_t)vf;
+        c->alt_inv[i] = (uint8_t)vi;
+      }
+  }
+  fclose(f);
+}
+
+// Rewrites the file: other devices' lines (and this device's sizes not in
+// `tuned`) are kept, this device's tuned sizes get the context's plan.
+static bool tune_cache_store(const swift_ctx* c, const bool (&tuned)[SWIFT_NSIZES]) {
+  std::vector<std::string> keep;
+  if (FILE* f = fopen(c->tune_path.c_str(), "r")) {
+    char line[512], key[320];
+    int n;
+    while (fgets(line, sizeof(line), f)) {
+      if (line[0] == '#') continue;
+      if (sscanf(line, "%319s %d", key, &n) == 2 && c->tune_key == key) {
+        bool mine = false;
+        for (int i = 0; i < SWIFT_NSIZES; ++i) mine |= tuned[i] && kSizes[i] == n;
+        if (mine) continue;
+      }
+      std::string l(line);
+      if (!l.empty() && l.back() != '\n') l += '\n';
+      keep.push_back(l);
+    }
+    fclose(f);
+  }
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool good = fputs("# libswift tune cache: <device> <n> <fwd variant> <inv variant>\n", f) >= 0;
+  for (const auto& l : keep) good = good && fputs(l.c_str(), f) >= 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i)
+    if (tuned[i]) good = good && fprintf(f, "%s %d %d %d\n", c->tune_key.c_str(), kSizes[i], c->alt_fwd[i], c->alt_inv[i]) > 0;
+  good = (fclose(f) == 0) && good;
+  return good && rename(tmp.c_str(), c->tune_path.c_str()) == 0;
+}
+
 extern "C" {
 
 const char* swift_last_error(void) { return g_err.c_str(); }
 
-int swift_create(int device, swift_ctx** out) {
+int swift_create(int device, const char* tune_cache_path, swift_ctx** out) {
   if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
   *out = nullptr;
   int ndev = 0;
@@ -342,6 +416,11 @@ int swift_create(int device, swift_ctx** out) {
     ctx_release(c);
     delete c;
     return hip_fail(e, "context streams/events");
+  }
+  if (tune_cache_path && tune_cache_path[0]) {
+    c->tune_path = tune_cache_path;
+    c->tune_key = device_key(device);
+    tune_cache_load(c);
   }
   *out = c;
   return ok();
@@ -465,6 +544,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.p = params->p;
     a.eps_rel = params->eps_rel;
     a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
+    a.snr_exclude_r = pearson ? 0 : params->snr_exclude_r;
     a.npairs = g.count;
     a.nsl_fwd = fwd_blocks_n(g.n, ctx->alt_fwd[i] != 0);
     a.nsl_inv = inv_blocks_n(g.n, ctx->alt_inv[i] != 0);
@@ -480,7 +560,9 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     if (radius > 0 && radius < g.n / 2) {
       // rows |y| <= r + 1 (the centroid reads one row past the window),
       // rounded out to whole inverse row blocks of R2 rows
-      const int full = a.nsl_inv, R2 = g.n / full, rr = radius + 1;
+      // (and the rows of a wider background box, whose sums k_finalize needs)
+      const int full = a.nsl_inv, R2 = g.n / full;
+      const int rr = radius + (params->snr_exclude_r > 1 ? params->snr_exclude_r : 1);
       const int lo = rr / R2 + 1, hs = (g.n - rr) / R2;
       a.max_shift = radius;
       if (lo < hs) {
@@ -654,6 +736,8 @@ static int check_backward_common(swift_ctx* ctx, const swift_image* imgs, int32_
   if (rc) return rc;
   rc = check_params(params);
   if (rc) return rc;
+  if (params->snr_exclude_r != 0)
+    return fail(SWIFT_E_UNSUPPORTED, "the adjoint takes the whole surface as the SNR background (snr_exclude_r 0)");
   if (pairs->n_pairs == 0) {
     *empty = true;
     return ok();
@@ -809,7 +893,8 @@ int swift_snr(swift_ctx* ctx, const float* surfaces, int32_t n, int32_t batch, c
   if (!surfaces || !out) return fail(SWIFT_E_INVAL, "surfaces/out is NULL");
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
-  hipError_t e = launch_snr(surfaces, n, batch, out, stream);
+  if (2 * params->snr_exclude_r + 1 > n) return fail(SWIFT_E_INVAL, "snr_exclude_r box wider than the surface");
+  hipError_t e = launch_snr(surfaces, n, batch, params->snr_exclude_r, out, stream);
   if (e != hipSuccess) return hip_fail(e, "snr launch");
   return ok();
 }
@@ -992,6 +1077,7 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   hipStream_t st = ctx->gs[0];
+  bool tuned[SWIFT_NSIZES] = {};
   for (int k = 0; k < n_sizes; ++k) {
     const int n = sizes[k], si = size_index(n);
     // square grid of windows on one image, capped at 1 GiB of pixels
@@ -1093,7 +1179,10 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
     }
     ctx->alt_fwd[si] = (best_v & 1) != 0;
     ctx->alt_inv[si] = (best_v & 2) != 0;
+    tuned[si] = true;
   }
+  if (!ctx->tune_path.empty() && n_sizes > 0 && !tune_cache_store(ctx, tuned))
+    return fail(SWIFT_E_INVAL, "plan tuned but the tune cache %s could not be written", ctx->tune_path.c_str());
   return ok();
 }
 

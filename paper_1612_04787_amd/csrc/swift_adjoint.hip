@@ -21,6 +21,13 @@
 //   P1 = sum T G_w D, P2 = sum T D, P3 = sum T w D, Q = sum T G_w, R = sum T w
 // are plain per-pixel sums, so the row stage needs no second pass.
 //
+// The column stage works with the normalised spectra F^ = F / ||w|| of the
+// forward pass (split_bin), X^ = X s with s = 1 / (||w_A|| ||w_B||), so no
+// FP32 square overflows: h = s^p h^, h' = -(p/2) s^(p+2) h^ / d^ with
+// d^ = |X^|^2 + eps_rel^2, hence G_X = s^p [G_C (h^ + r^ h^') + conj(G_C) X^^2 h^']
+// (h^' = -(p/2) h^ / d^), dJ/d(eps^2) = s^(p+1) sum Re(conj(G_C) X^ h^') and
+// X h = s^(p-1) X^ h^ (= kw N^2 X^ h^).
+//
 // Kernels per window size: k_bwd_col (column stage), k_bwd_row (inverse row
 // FFTs + gather recomputation + sums), k_bwd_fin (per pair).
 //
@@ -128,6 +135,16 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
     }
     const float p = a.p, hp2 = -0.5f * p;
     const float inv_m = 1.0f / (float)(N * N);
+    const float e2 = a.eps_rel * a.eps_rel;
+    // per-pair scales of the normalised spectra: X h = kwm X^ h^, and
+    // G_FA = (s^p ||w_B||) conj(G_X^) F_B^, G_FB = (s^p ||w_A||) G_X^ F_A^
+    const float kwm = ps.kw * (float)(N * N);
+    float sca = 0.0f, scb = 0.0f;
+    if (!zero_all && ps.sA > 0.0f && ps.sB > 0.0f) {
+      const double sp = pow((double)ps.sA * (double)ps.sB, (double)p);
+      sca = (float)(sp / (double)ps.sB);
+      scb = (float)(sp / (double)ps.sA);
+    }
     const float mw = (w == 0 || w == N / 2) ? 1.0f : 2.0f;  // column w and its mirror N - w
     const float2 tauw = a.tau[w];
     // signed frequency of the column (Nyquist: squared terms only)
@@ -135,18 +152,12 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = t + e * T;
-      const float2 zp = v[e];
-      const float2 zm = cconj(slotB[lidx((N - ky) & (N - 1))]);
-      float2 fa = cscale(cadd(zp, zm), 0.5f);
-      const float2 dd = csub(zp, zm);
-      float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
-      const float2 tk = cmul(a.tau[ky], tauw);
-      fa = csub(fa, cscale(tk, ps.mA));
-      fb = csub(fb, cscale(tk, ps.mB));
-      const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
+      float2 fa, fb;  // F_A^, F_B^
+      split_bin(v[e], cconj(slotB[lidx((N - ky) & (N - 1))]), cmul(a.tau[ky], tauw), ps, fa, fb);
+      const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);  // X^
       const float r = X.x * X.x + X.y * X.y;
-      const float d = r + ps.eps2;
-      float h, hd;  // h and h' = dh/dd
+      const float d = r + e2;
+      float h, hd;  // h^ and h^' = dh^/dd^
       if (p == 0.0f) {
         h = 1.0f;
         hd = 0.0f;
@@ -162,7 +173,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       const float2 ph = a.tw[m * (1024 / N)];
       // surface Hessian sums: Re(X h e^{+i phi}) times the frequency products
       if (!CJ && !zero_all && !(ky == 0 && w == 0)) {
-        const float2 cc = cmul(cscale(X, h), cconj(ph));
+        const float2 cc = cmul(cscale(X, h * kwm), cconj(ph));
         const float fy = (ky < N / 2) ? (float)ky : (float)(ky - N);
         const float fym = (ky == N / 2) ? 0.0f : fy;
         hxx += mw * cc.x * fw * fw;
@@ -176,12 +187,12 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
       const bool zb = zero_all || (ky == 0 && w == 0);
       float2 gfa, gfb;
       if constexpr (!CJ) {
-        float2 gc = cscale(cadd(cscale(ph, alpha), cscale(X, gamma * h)), inv_m);
+        float2 gc = cscale(cadd(cscale(ph, alpha), cscale(X, gamma * h * kwm)), inv_m);
         if (zb) gc = make_float2(0.0f, 0.0f);
         const float2 gx = cadd(cscale(gc, hr), cmul(cconj(gc), x2h));
         dj = fmaf(gc.x, xh.x, fmaf(gc.y, xh.y, dj));
-        gfa = cmul(cconj(gx), fb);
-        gfb = cmul(gx, fa);
+        gfa = cscale(cmul(cconj(gx), fb), sca);
+        gfb = cscale(cmul(gx, fa), scb);
       } else {
         // 3 x 3 sums S = sum omega e_x^dx e_y^dy / M with e = e^{-2 pi i k/N};
         // the x part (rows of the box summed over dx) is the same for the whole
@@ -197,8 +208,8 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         const float2 gxy = cadd(cscale(gcy, hr), cmul(cconj(gcy), x2h));
         dj = fmaf(gcx.x, xh.x, fmaf(gcx.y, xh.y, dj));
         dj1 = fmaf(gcy.x, xh.x, fmaf(gcy.y, xh.y, dj1));
-        gfa = cmul(cconj(gxx), fb);  // real channel: d(dx)
-        gfb = cmul(cconj(gxy), fb);  // imaginary channel: d(dy)
+        gfa = cscale(cmul(cconj(gxx), fb), sca);  // real channel: d(dx)
+        gfb = cscale(cmul(cconj(gxy), fb), sca);  // imaginary channel: d(dy)
       }
       v[e] = make_float2(gfa.x - gfb.y, gfa.y + gfb.x);  // Q(ky, w) = G_FA + i G_FB
       // G_FA, G_FB of column w for the mirrored column (slot A is free; slot
@@ -273,7 +284,7 @@ __device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int
                                            const TileGeom& g, const RowParam* __restrict__ rp,
                                            const float* __restrict__ trow, const PixelOffsets<GatherCfg<N>::XV>& ku,
                                            const float (&tx)[GatherCfg<N>::XV], const swift_image& im, int y0,
-                                           int tid, float mean_off, bool ch1, float (&acc)[kBwdSums],
+                                           int tid, float off, float mean_off, bool ch1, float (&acc)[kBwdSums],
                                            float (&acc2)[kBwdSums]) {
   constexpr int XV = GatherCfg<N>::XV, RPI = GatherCfg<N>::RPI, ITER = R / RPI;
   const int rowb = g.wt4 * 4;
@@ -346,7 +357,7 @@ __device__ __forceinline__ void bwd_pixels(const float2* __restrict__ stage, int
       // entries from the column sums after the loop
       const float v = (float)(y0 + r - N / 2);
       const float tap = tx[c] * trow[r];
-      const float wv = (val - kSampleOffset - mean_off) * tap;
+      const float wv = ((val - off) - mean_off) * tap;
       const float2 gw = stage[r * RS + lidx(x)];
       const float g0 = ch1 ? gw.y : gw.x;
       const float tg = tap * g0, tw = tap * wv;
@@ -401,17 +412,17 @@ __device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t*
                                           const RowParam* rp, const float* trow,
                                           const PixelOffsets<GatherCfg<N>::XV>& ku,
                                           const float (&tx)[GatherCfg<N>::XV], const swift_image& im, bool trans,
-                                          int y0, int tid, float mean_off, bool ch1, float (&acc)[kBwdSums],
-                                          float (&acc2)[kBwdSums]) {
+                                          int y0, int tid, float off, float mean_off, bool ch1,
+                                          float (&acc)[kBwdSums], float (&acc2)[kBwdSums]) {
   constexpr int R = RowsCfg<N>::FWD;
   if (g.use) {
     if (trans)
-      bwd_pixels<N, R, true, true, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
+      bwd_pixels<N, R, true, true, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, off, mean_off, ch1, acc, acc2);
     else
-      bwd_pixels<N, R, true, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc,
-                                         acc2);
+      bwd_pixels<N, R, true, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, off, mean_off, ch1,
+                                         acc, acc2);
   } else {
-    bwd_pixels<N, R, false, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, mean_off, ch1, acc, acc2);
+    bwd_pixels<N, R, false, false, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, off, mean_off, ch1, acc, acc2);
   }
 }
 
@@ -549,14 +560,15 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   if (tg[0].use) tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
   __syncthreads();  // G rows and tile A visible
   // image A: channel 0 (and, in CJ mode, channel 1 on the same pixels)
-  bwd_image<N, CJ, TO>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.mA, false,
-                       acc0, acc1);
+  // w = ((a - o) - m) T: o the offset, m the weighted mean of a - o
+  bwd_image<N, CJ, TO>(stage, RS, tile, tg[0], rparam[0], trow, ku[0], tx, im[0], trans[0], y0, tid, ps.oA, ps.mA,
+                       false, acc0, acc1);
   if constexpr (!CJ) {
     __syncthreads();  // tile A consumed
     if (tg[1].use) tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
-    bwd_image<N, false, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid, ps.mB,
-                               true, acc1, acc1);
+    bwd_image<N, false, false>(stage, RS, tile, tg[1], rparam[1], trow, ku[1], tx, im[1], trans[1], y0, tid,
+                               ps.oB, ps.mB, true, acc1, acc1);
   }
   // block reduction to FP64 slice partials
   const int wv = tid >> 6, ln = tid & 63;
@@ -618,9 +630,11 @@ __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
     const double sT = ti.sum_t * ti.sum_t;
     const double e2 = (double)a.eps_rel * (double)a.eps_rel;
     // eps^2 = eps_rel^2 |w_A|^2 |w_B|^2: each channel's lambda multiplies the
-    // differentiated window's w by the other window's norm
-    const double lam = CJ ? (img == 0 ? dj : dj1) * 2.0 * e2 * (double)ps.swB
-                          : dj * 2.0 * e2 * (img == 0 ? (double)ps.swB : (double)ps.swA);
+    // differentiated window's w by the other window's norm; dJ/d(eps^2) is
+    // s^(p+1) times the column stage's normalised sums, s = 1 / (|w_A| |w_B|)
+    const double sp1 = (ps.flags & 1) ? 0.0 : pow((double)ps.swA * (double)ps.swB, -0.5 * ((double)a.p + 1.0));
+    const double lam = CJ ? (img == 0 ? dj : dj1) * sp1 * 2.0 * e2 * (double)ps.swB
+                          : dj * sp1 * 2.0 * e2 * (img == 0 ? (double)ps.swB : (double)ps.swA);
     const double* q = tot + img * kBwdSums;
     double g = q[j] + lam * q[12 + j] - (q[18] + lam * q[19]) / sT * q[6 + j];
     if (ps.flags & 1) g = 0.0;

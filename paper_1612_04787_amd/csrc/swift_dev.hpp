@@ -64,6 +64,18 @@ __device__ __forceinline__ float wave_incl_scan_f32(float v) {
   return v;
 }
 
+// Splits one bin of the packed spectrum z = a'T + i b'T into the normalised,
+// mean-free window spectra: zp = Z(k), zm = conj Z(-k), tk = tau(ky) tau(kx);
+// F_A = (zp + zm) / 2 - mA tk and F_B = (zp - zm) / (2i) - mB tk, each scaled
+// by its 1 / ||w|| (sA, sB), so products of them stay in FP32 range.
+__device__ __forceinline__ void split_bin(float2 zp, float2 zm, float2 tk, const PairStat& ps, float2& fa,
+                                          float2& fb) {
+  const float ha = 0.5f * ps.sA, hb = 0.5f * ps.sB;
+  fa = csub(cscale(cadd(zp, zm), ha), cscale(tk, ps.mA * ps.sA));
+  const float2 dd = csub(zp, zm);
+  fb = csub(make_float2(hb * dd.y, -hb * dd.x), cscale(tk, ps.mB * ps.sB));
+}
+
 struct Top2 {
   float m1;
   int i1;

@@ -8,26 +8,39 @@
 
 namespace swift {
 
-// Offset subtracted from every sample before the forward transform.  The
-// weighted mean is removed exactly in the frequency domain afterwards, so the
-// offset changes nothing mathematically; it only keeps the DC terms small.
-constexpr float kSampleOffset = 128.0f;
 constexpr float kNearTieRel = 2e-4f;
+// A window is degenerate when its taper-weighted variance ||w||^2 is at most
+// this fraction of the energy of its samples about the offset (sum (a'T)^2):
+// its samples are then equal up to rounding.
+constexpr double kDegenerateRel = 1e-6;
 
+// Every sample a of a window is taken about an offset o, a' = a - o: the
+// source pixel nearest the window centre, read alike by every block of the
+// pair.  The weighted mean is removed exactly in the frequency domain
+// afterwards, so the offset changes nothing mathematically; it keeps the sums
+// of low-contrast windows with large values free of cancellation, and makes
+// the samples of a constant window exactly zero.
+//
 // Per row-slice partial sums of the forward row pass (A then B):
-// s[0] = sum a'T, s[1] = sum (a'T)^2, s[2] = sum a'T^2   (a' = sample - offset)
+// s[0] = sum a'T, s[1] = sum (a'T)^2, s[2] = sum a'T^2.
 struct RowPart {
   double s[6];
   int32_t clamped;
-  int32_t pad[3];
+  float off[2];   // oA, oB (the same in every slice of a pair)
+  int32_t pad;
 };
 
-// Per pair, after reducing the row partials.
+// Per pair, after reducing the row partials.  The cross power is formed from
+// the normalised spectra F_A / ||w_A|| and F_B / ||w_B||, so that |X|^2 stays
+// in FP32 range for any input scale; kw restores the surface's scale.
 struct PairStat {
-  float mA, mB;   // taper-weighted means of the offset samples
-  float eps2;     // eps_rel^2 * ||w_A||^2 * ||w_B||^2
-  int32_t flags;  // bit 0: degenerate (a window is constant); bit 2: clamped
+  float mA, mB;   // taper-weighted means of the offset samples a - oA, b - oB
+  float oA, oB;   // the offsets
+  float sA, sB;   // 1 / ||w_A||, 1 / ||w_B|| (0 for a degenerate pair)
   float swA, swB; // ||w_A||^2, ||w_B||^2
+  float kw;       // (||w_A|| ||w_B||)^(1-p) / N^2 (0 for a degenerate pair)
+  int32_t flags;  // bit 0: degenerate (a window is constant); bit 2: clamped
+  int32_t pad[2];
 };
 
 // Per row-slice partials of the inverse row pass.
@@ -64,6 +77,7 @@ struct MatchArgs {
   const TaperInfo* tinfo;
   float p, eps_rel;
   int32_t L;            // taper samples per edge
+  int32_t snr_exclude_r;  // R > 0: the SNR background leaves out the (2R+1)^2 box at the peak
   int32_t npairs;
   int32_t nsl_fwd, nsl_inv;  // row blocks per pair of the forward / inverse row passes
   int32_t n_imgs;
@@ -165,7 +179,7 @@ int fwd_blocks_n(int n, bool alt);  // forward row blocks per pair
 int inv_blocks_n(int n, bool alt);  // inverse row blocks per pair
 hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);
 int col_items_per_wg(int n);  // column-pass workgroups per pair
-hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t s);
+hipError_t launch_snr(const float* surf, int n, int batch, int exclude_r, swift_match* out, hipStream_t s);
 hipError_t launch_render(const uint8_t* src, int64_t spitch, int64_t sstride, int S, int sh, int sw,
                          const double* aff, int level, uint8_t* dst, int64_t dpitch, int64_t dstride, int dh, int dw,
                          hipStream_t st, KernelTimer* kt);

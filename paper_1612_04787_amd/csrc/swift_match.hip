@@ -160,8 +160,8 @@ struct FwdStage {
 };
 
 // Gathers one image of the thread's samples into the stage (real parts for
-// A, imaginary parts for B): a' T with a' = sample - offset and T = t(x) t(y),
-// formed as (a t(x) - offset t(x)) t(y).  Adds the slice sums s1 = sum a'T,
+// A, imaginary parts for B): a' T with a' = sample - o and T = t(x) t(y),
+// formed as ((a - o) t(x)) t(y).  Adds the slice sums s1 = sum a'T,
 // s2 = sum (a'T)^2 and, per column, s3c[c] = sum_r (a'T) t(y), so that
 // sum (a'T) T = sum_c t(x_c) s3c[c].
 template <int N, int R, int FL, int NL, bool IM, bool TILE>
@@ -169,9 +169,8 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
                                             const uint32_t* __restrict__ tile, const TileGeom& g,
                                             const RowParam* __restrict__ rp, const float* __restrict__ trow,
                                             const float (&ku)[2][GatherCfg<N>::XV], const swift_image& im,
-                                            bool border, const float (&tx)[GatherCfg<N>::XV],
-                                            const float (&ntx)[GatherCfg<N>::XV], int tid, float& s1, float& s2,
-                                            float (&s3c)[GatherCfg<N>::XV], bool& cl) {
+                                            bool border, const float (&tx)[GatherCfg<N>::XV], float o, int tid,
+                                            float& s1, float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
@@ -222,7 +221,7 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
       // (1-fy)((1-fx) i00 + fx i10) + fy((1-fx) i01 + fx i11), in lerp form
       const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
       const float val = fmaf(fy, bot - top, top);
-      const float at = fmaf(val, tx[c], ntx[c]) * ty;
+      const float at = ((val - o) * tx[c]) * ty;
       s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
@@ -239,15 +238,17 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
 // window has the same bilinear weights (fx, fy), so a thread walks down its
 // columns and reuses the horizontal interpolation of each tile row for the
 // next output row.  One aligned read of a tile row gives the bytes of two
-// adjacent columns.  Same outputs and sums as gather_rows.
+// adjacent columns.  The offset enters the horizontal interpolation, h - o =
+// fx (b1 - b0) + (b0 - o), so the samples of a constant window are exactly 0.
+// Same outputs and sums as gather_rows.
 template <int N, int R, int FL, int NL, bool IM>
 __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
                                                   const uint32_t* __restrict__ tile, const TileGeom& g,
                                                   const RowParam* __restrict__ rp, const float* __restrict__ trow,
                                                   const swift_image& im, bool border,
-                                                  const float (&tx)[GatherCfg<N>::XV],
-                                                  const float (&ntx)[GatherCfg<N>::XV], int tid, float& s1,
-                                                  float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
+                                                  const float (&tx)[GatherCfg<N>::XV], float o, int tid,
+                                                  float& s1, float& s2, float (&s3c)[GatherCfg<N>::XV],
+                                                  bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
@@ -275,10 +276,10 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
       const int oc = (int)sh + c;
       const uint32_t v = __builtin_amdgcn_alignbyte(w[(oc >> 2) + 1], w[oc >> 2], (uint32_t)(oc & 3));
       const float b0 = (float)(v & 255u), b1 = (float)((v >> 8) & 255u);
-      h[c] = fmaf(fx, b1 - b0, b0);
+      h[c] = fmaf(fx, b1 - b0, b0 - o);
       if (c + 1 < XV) {
         const float b2 = (float)((v >> 16) & 255u);
-        h[c + 1] = fmaf(fx, b2 - b1, b1);
+        h[c + 1] = fmaf(fx, b2 - b1, b1 - o);
       }
     }
   };
@@ -292,9 +293,9 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
     const float ty = trow[r];
 #pragma unroll
     for (int c = 0; c < XV; ++c) {
-      const float val = fmaf(fy, h1[c] - h0[c], h0[c]);
+      const float val = fmaf(fy, h1[c] - h0[c], h0[c]);  // sample - o
       h0[c] = h1[c];
-      const float at = fmaf(val, tx[c], ntx[c]) * ty;
+      const float at = (val * tx[c]) * ty;
       s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
@@ -426,13 +427,14 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     trow[tid - 64] = a.taper[y0 + tid - 64];
   }
   using M = FwdMap<N, R>;
-  float tx[XV], ntx[XV], ku[2][2][XV];
+  // the offsets: every block of the pair reads the same centre pixels
+  const float off[2] = {centre_pixel(im[0], ra[0]), centre_pixel(im[1], ra[1])};
+  float tx[XV], ku[2][2][XV];
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     const int x = M::col(tid, c);
     const float u = (float)(x - N / 2);
     tx[c] = a.taper[x];
-    ntx[c] = -kSampleOffset * tx[c];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       ku[m][0][c] = ra[m].f11 * u;
@@ -457,30 +459,30 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
-      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], rparam[0], trow, im[0], border[0], tx, ntx,
-                                             tid, s[0], s[1], s3c[0], clamped);
+      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], rparam[0], trow, im[0], border[0], tx,
+                                             off[0], tid, s[0], s[1], s3c[0], clamped);
     else
       gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx,
-                                             ntx, tid, s[0], s[1], s3c[0], clamped);
+                                             off[0], tid, s[0], s[1], s3c[0], clamped);
   }
   if (tg[1].use) {
     if (tg[0].use) __syncthreads();  // tile of A fully consumed
     tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
-      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], rparam[1], trow, im[1], border[1], tx, ntx,
-                                            tid, s[3], s[4], s3c[1], clamped);
+      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], rparam[1], trow, im[1], border[1], tx,
+                                            off[1], tid, s[3], s[4], s3c[1], clamped);
     else
       gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx,
-                                            ntx, tid, s[3], s[4], s3c[1], clamped);
+                                            off[1], tid, s[3], s[4], s3c[1], clamped);
   }
   if (FL < R && (tg[0].use || tg[1].use) && !(tg[0].use && tg[1].use)) __syncthreads();  // tile consumed
   if (!tg[0].use)
-    gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx, ntx,
-                                           tid, s[0], s[1], s3c[0], clamped);
+    gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx,
+                                           off[0], tid, s[0], s[1], s3c[0], clamped);
   if (!tg[1].use)
-    gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx, ntx,
-                                          tid, s[3], s[4], s3c[1], clamped);
+    gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx,
+                                          off[1], tid, s[3], s[4], s3c[1], clamped);
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     s[2] = fmaf(tx[c], s3c[0][c], s[2]);
@@ -537,7 +539,9 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) rp.s[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
     rp.clamped = redc[0] | redc[1] | redc[2] | redc[3];
-    rp.pad[0] = rp.pad[1] = rp.pad[2] = 0;
+    rp.off[0] = off[0];
+    rp.off[1] = off[1];
+    rp.pad = 0;
     a.rowpart[(size_t)pair * NSLICE + slice] = rp;
   }
 
@@ -585,6 +589,7 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
   cl = __any(cl) ? 1 : 0;
   if (ln == 0) {
     const TaperInfo ti = *a.tinfo;
+    const RowPart r0 = a.rowpart[(size_t)pair * NSLICE];
     const double sT = ti.sum_t * ti.sum_t, sT2 = ti.sum_t2 * ti.sum_t2;
     const double mA = s[0] / sT, mB = s[3] / sT;
     const double wA = s[1] - 2.0 * mA * s[2] + mA * mA * sT2;
@@ -592,20 +597,35 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
     PairStat ps;
     ps.mA = (float)mA;
     ps.mB = (float)mB;
+    ps.oA = r0.off[0];
+    ps.oB = r0.off[1];
     ps.swA = (float)fmax(wA, 0.0);
     ps.swB = (float)fmax(wB, 0.0);
-    ps.flags = (cl ? 4 : 0);
-    // a window whose weighted variance vanishes to rounding is constant
-    if (!(wA > 1e-6 * s[1]) || !(wB > 1e-6 * s[4])) ps.flags |= 1;
-    const double e2 = (double)a.eps_rel * (double)a.eps_rel * fmax(wA, 0.0) * fmax(wB, 0.0);
-    ps.eps2 = (float)e2;
+    ps.pad[0] = ps.pad[1] = 0;
+    // degenerate: a window's weighted variance is at most kDegenerateRel of
+    // its energy about the offset (samples equal up to rounding; a constant
+    // window has all sums exactly 0)
+    const bool degA = !(wA > kDegenerateRel * s[1]), degB = !(wB > kDegenerateRel * s[4]);
+    ps.flags = (cl ? 4 : 0) | ((degA || degB) ? 1 : 0);
+    const double inv_m = 1.0 / ((double)N * (double)N);
     if (a.pearson) {
       // the template carries the mean (its spectrum has no DC), so window B is
       // used as gathered; only a constant template is degenerate (a constant
-      // patch of B gets a zero coefficient per placement)
+      // patch of B gets a zero coefficient per placement).  No whitening (p =
+      // 0): the spectra are used unscaled.
       ps.mB = 0.0f;
-      ps.eps2 = 0.0f;
-      ps.flags = (cl ? 4 : 0) | (!(wA > 1e-6 * s[1]) ? 1 : 0);
+      ps.flags = (cl ? 4 : 0) | (degA ? 1 : 0);
+    }
+    if (ps.flags & 1) {
+      ps.sA = ps.sB = 0.0f;
+      ps.kw = 0.0f;
+    } else if (a.pearson) {
+      ps.sA = ps.sB = 1.0f;
+      ps.kw = (float)inv_m;
+    } else {
+      ps.sA = (float)(1.0 / sqrt(wA));
+      ps.sB = (float)(1.0 / sqrt(wB));
+      ps.kw = (float)(exp(0.5 * (1.0 - (double)a.p) * (log(wA) + log(wB))) * inv_m);
     }
     a.pstat[pair] = ps;
     if (a.saved_ps) a.saved_ps[pair] = ps;
@@ -645,6 +665,30 @@ __device__ __forceinline__ void store_column(const MatchArgs& a, float2* dst, in
       if (y < a.zlo || y >= a.zhi) dst[y] = v[e];
     }
   }
+}
+
+// ---------------------------------------------------------------- whitening of one bin
+// zp = Z(k), zm = conj Z(-k) of the packed spectrum z = a'T + i b'T, tk =
+// tau(ky) tau(kx).  Splits F_A = (zp + zm) / 2, F_B = (zp - zm) / (2i),
+// removes the weighted means (F -= m tk), and scales both by 1 / ||w||, so the
+// normalised cross power X^ = conj(F_A^) F_B^ has |X^| <= N^2 whatever the
+// input scale.  With X = X^ ||w_A|| ||w_B|| and eps = eps_rel ||w_A|| ||w_B||,
+//   C = X (|X|^2 + eps^2)^(-p/2) / N^2 = X^ (|X^|^2 + eps_rel^2)^(-p/2) kw,
+// kw = (||w_A|| ||w_B||)^(1-p) / N^2.  The DC bin (and a degenerate pair) gives 0.
+__device__ __forceinline__ float2 whiten_bin(float2 zp, float2 zm, float2 tk, const PairStat& ps, float p,
+                                             float eps_rel, bool dc) {
+  float2 fa, fb;
+  split_bin(zp, zm, tk, ps, fa, fb);
+  const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
+  const float d = fmaf(X.x, X.x, fmaf(X.y, X.y, eps_rel * eps_rel));
+  float gs;
+  if (p == 0.0f) gs = 1.0f;
+  else if (!(d > 0.0f)) gs = 0.0f;
+  else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
+  else gs = __builtin_amdgcn_exp2f(-0.5f * p * __builtin_amdgcn_logf(d));
+  gs *= ps.kw;
+  if (dc) gs = 0.0f;
+  return cscale(X, gs);
 }
 
 // ---------------------------------------------------------------- column pass + whitening
@@ -694,33 +738,11 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
     const PairStat ps = a.pstat[pair];
     const float2* part = lds + (c + IPW) * SL;
     const float2 tauw = a.tau[w];
-    const float p = a.p;
-    const float hp = -0.5f * p;
-    const float inv_m = 1.0f / (float)(N * N);
-    const bool zero_all = (ps.flags & 1) != 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ky = t + e * T;
-      const float2 zp = v[e];
-      const float2 zm = cconj(part[lidx((N - ky) & (N - 1))]);
-      // F_A = (Z(k) + conj Z(-k)) / 2,  F_B = (Z(k) - conj Z(-k)) / (2i)
-      float2 fa = cscale(cadd(zp, zm), 0.5f);
-      const float2 dd = csub(zp, zm);
-      float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
-      const float2 tk = cmul(tau[e], tauw);
-      fa = csub(fa, cscale(tk, ps.mA));
-      fb = csub(fb, cscale(tk, ps.mB));
-      // X = conj(F_A) F_B, C = X (|X|^2 + eps^2)^(-p/2) / N^2
-      const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
-      const float d = X.x * X.x + X.y * X.y + ps.eps2;
-      float gs;
-      if (p == 0.0f) gs = 1.0f;
-      else if (!(d > 0.0f)) gs = 0.0f;
-      else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
-      else gs = __builtin_amdgcn_exp2f(hp * __builtin_amdgcn_logf(d));
-      gs *= inv_m;
-      if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
-      v[e] = cscale(X, gs);
+      v[e] = whiten_bin(v[e], cconj(part[lidx((N - ky) & (N - 1))]), cmul(tau[e], tauw), ps, a.p, a.eps_rel,
+                        ky == 0 && w == 0);
     }
     if constexpr (PRUNE) {
       float csq = 0.0f;
@@ -790,33 +812,11 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
 
   const PairStat ps = a.pstat[pair];
   const float2 tauw = a.tau[w];
-  const float p = a.p;
-  const float hp = -0.5f * p;
-  const float inv_m = 1.0f / (float)(N * N);
-  const bool zero_all = (ps.flags & 1) != 0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int ky = t + e * T;
-    const float2 zp = v[e];
-    const float2 zm = cconj(slot[lidx((N - ky) & (N - 1))]);
-    // F_A = (Z(k) + conj Z(-k)) / 2,  F_B = (Z(k) - conj Z(-k)) / (2i)
-    float2 fa = cscale(cadd(zp, zm), 0.5f);
-    const float2 dd = csub(zp, zm);
-    float2 fb = make_float2(0.5f * dd.y, -0.5f * dd.x);
-    const float2 tk = cmul(a.tau[ky], tauw);
-    fa = csub(fa, cscale(tk, ps.mA));
-    fb = csub(fb, cscale(tk, ps.mB));
-    // X = conj(F_A) F_B, C = X (|X|^2 + eps^2)^(-p/2) / N^2
-    const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
-    const float d = X.x * X.x + X.y * X.y + ps.eps2;
-    float gs;
-    if (p == 0.0f) gs = 1.0f;
-    else if (!(d > 0.0f)) gs = 0.0f;
-    else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
-    else gs = __builtin_amdgcn_exp2f(hp * __builtin_amdgcn_logf(d));
-    gs *= inv_m;
-    if (zero_all || (ky == 0 && w == 0)) gs = 0.0f;
-    v[e] = cscale(X, gs);
+    v[e] = whiten_bin(v[e], cconj(slot[lidx((N - ky) & (N - 1))]), cmul(a.tau[ky], tauw), ps, a.p, a.eps_rel,
+                      ky == 0 && w == 0);
   }
   if constexpr (PRUNE) {
     float csq = 0.0f;
@@ -1113,10 +1113,15 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
   const int iy = flat / N, ix = flat % N;
   const float2* Zp = a.Z + (size_t)pair * N * N;
 
-  // recompute rows iy-1, iy+1 (one complex FFT) and iy (second FFT)
-  for (int pass = 0; pass < 2; ++pass) {
-    const int ra = pass == 0 ? ((iy - 1) & (N - 1)) : iy;
-    const int rb = pass == 0 ? ((iy + 1) & (N - 1)) : -1;
+  // recompute the surface rows iy - RB .. iy + RB, two per complex FFT: the
+  // 3 x 3 neighbourhood of the peak, and with snr_exclude_r = R > 0 the sums
+  // over the (2R+1)^2 box the background leaves out
+  const int R = a.pearson ? 0 : a.snr_exclude_r, RB = R > 1 ? R : 1;
+  double bs = 0.0, bq = 0.0;
+  for (int r0 = -RB; r0 <= RB; r0 += 2) {
+    const int ra = (iy + r0) & (N - 1);
+    const bool two = r0 + 1 <= RB;
+    const int rb = two ? ((iy + r0 + 1) & (N - 1)) : -1;
     if (ln < T) {
       float2 v[E];
 #pragma unroll
@@ -1138,18 +1143,25 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
         int dxi = x - ix;
         if (dxi > N / 2) dxi -= N;
         if (dxi < -N / 2) dxi += N;
-        if (dxi >= -1 && dxi <= 1) {
-          if (pass == 0) {
-            nb[0][dxi + 1] = v[e].x;
-            nb[2][dxi + 1] = v[e].y;
-          } else {
-            nb[1][dxi + 1] = v[e].x;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int dy = r0 + h;
+          if (h == 1 && !two) continue;
+          const float cv = h == 0 ? v[e].x : v[e].y;
+          if (dxi >= -1 && dxi <= 1 && dy >= -1 && dy <= 1) nb[dy + 1][dxi + 1] = cv;
+          if (dxi >= -R && dxi <= R && dy >= -R && dy <= R) {
+            // the peak itself enters with the value the search found
+            const double c = (dxi == 0 && dy == 0) ? (double)tp.m1 : (double)cv;
+            bs += c;
+            bq += c * c;
           }
         }
       }
     }
     __syncthreads();
   }
+  bs = wave_sum(bs);
+  bq = wave_sum(bq);
 
   if (ln == 0) {
     const PairStat ps = a.pstat[pair];
@@ -1171,6 +1183,12 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
           }
         }
       count = (double)(2 * RP + 1) * (double)(2 * RP + 1);
+    }
+    if (R > 0) {
+      // background without the box: M - (2R+1)^2 entries
+      sum -= bs;
+      sq -= bq;
+      count = (double)N * (double)N - (double)(2 * R + 1) * (double)(2 * R + 1);
     }
     swift_match rec = make_record(N, tp, sum, sq, nb, (ps.flags & 4) ? SWIFT_ST_CLAMPED : 0, count);
     if (outside) rec.hxx = rec.hyy = rec.hxy = 0.0f;

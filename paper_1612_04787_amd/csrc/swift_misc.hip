@@ -6,7 +6,7 @@ namespace swift {
 // ---------------------------------------------------------------- scoring (Z-score of the peak)
 // One workgroup per surface: first maximum, top-2 margin, FP64 sum and sum of
 // squares, then the record with the 3x3 centroid read from the surface.
-__global__ void __launch_bounds__(256) k_snr(const float* __restrict__ surf, int n, swift_match* out) {
+__global__ void __launch_bounds__(256) k_snr(const float* __restrict__ surf, int n, int R, swift_match* out) {
   __shared__ float rm1[4], rm2[4];
   __shared__ int ri1[4];
   __shared__ double rs[4], rq[4];
@@ -53,12 +53,23 @@ __global__ void __launch_bounds__(256) k_snr(const float* __restrict__ surf, int
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx)
         nb[dy + 1][dx + 1] = s[(size_t)((iy + dy + n) % n) * n + ((ix + dx + n) % n)];
-    out[blockIdx.x] = make_record(n, b, rs[0] + rs[1] + rs[2] + rs[3], rq[0] + rq[1] + rq[2] + rq[3], nb, 0);
+    double sum = rs[0] + rs[1] + rs[2] + rs[3], sq = rq[0] + rq[1] + rq[2] + rq[3], count = 0.0;
+    if (R > 0) {
+      // the background leaves out the (2R+1)^2 box around the peak
+      for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+          const double c = (double)s[(size_t)(((iy + dy) % n + n) % n) * n + (((ix + dx) % n + n) % n)];
+          sum -= c;
+          sq -= c * c;
+        }
+      count = (double)n * (double)n - (double)(2 * R + 1) * (double)(2 * R + 1);
+    }
+    out[blockIdx.x] = make_record(n, b, sum, sq, nb, 0, count);
   }
 }
 
-hipError_t launch_snr(const float* surf, int n, int batch, swift_match* out, hipStream_t st) {
-  if (batch > 0) k_snr<<<batch, 256, 0, st>>>(surf, n, out);
+hipError_t launch_snr(const float* surf, int n, int batch, int exclude_r, swift_match* out, hipStream_t st) {
+  if (batch > 0) k_snr<<<batch, 256, 0, st>>>(surf, n, exclude_r, out);
   return hipGetLastError();
 }
 

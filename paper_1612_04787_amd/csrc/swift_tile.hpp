@@ -48,6 +48,17 @@ __device__ __forceinline__ RowAffine row_affine(const float* th) {
   return r;
 }
 
+// Value of the source pixel nearest the window centre (u = v = 0),
+// img[clamp(floor(y + 1/2))][clamp(floor(x + 1/2))]: the offset about which a
+// window's samples and sums are formed.
+__device__ __forceinline__ float centre_pixel(const swift_image& im, const RowAffine& ra) {
+  const double X = fmin(fmax(ra.xc, -1e9), 1e9), Y = fmin(fmax(ra.yc, -1e9), 1e9);
+  const int x = (int)fmin(fmax(floor(X + 0.5), 0.0), (double)(im.width - 1));
+  const int y = (int)fmin(fmax(floor(Y + 0.5), 0.0), (double)(im.height - 1));
+  const gptr<unsigned char> row = to_global<unsigned char>(im.data) + (int64_t)y * im.pitch;
+  return im.dtype == SWIFT_U8 ? (float)row[x] : ((gptr<float>)row)[x];
+}
+
 template <int N, int R, int BUDGET, int TRW>
 __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_image& im, int y0) {
   TileGeom g;

@@ -238,17 +238,21 @@ def repair_jumps(sw, raw, aff, level=0, n=512, grid=8, k=3, break_px=2.0, frac=0
     sc, hf = float(1 << level), (float(1 << level) - 1.0) / 2.0
     torch.cuda.synchronize(raw.device)
     t0 = time.perf_counter()
-    breaks = []
+    breaks, rounds = [], []
+    centres = None
     for _ in range(max_breaks):
         rendered = sw.render(src, aff, level)
         left = sw.project_side(rendered, k, -1)
         fit, tb, _ = _fit_against(sw, src, left, aff, level, grid, n, params, refine, tol, stop_frac, min_snr)
-        # level-0 window centres and how far the left fit moves them
+        # level-0 window centres and how far the left fit moves them (RMS)
         c = tb.view(S, g2, 8)[:, :, 0:2].double() * sc + hf
         def move(a):
             return torch.stack([a[:, None, 0] * c[..., 0] + a[:, None, 1] * c[..., 1] + a[:, None, 2],
                                 a[:, None, 3] * c[..., 0] + a[:, None, 4] * c[..., 1] + a[:, None, 5]], -1)
         score = (move(fit) - move(aff)).square().sum(-1).mean(-1).sqrt().cpu().tolist()
+        if centres is None:
+            centres = c.cpu().numpy()
+        rounds.append(dict(aff=aff.cpu().numpy(), fit=fit.cpu().numpy(), scores=score))
         j = next((s for s in range(1, S) if score[s] > break_px), None)
         if j is None:
             break
@@ -257,9 +261,11 @@ def repair_jumps(sw, raw, aff, level=0, n=512, grid=8, k=3, break_px=2.0, frac=0
     rendered = sw.render(src, aff, level)
     model = sw.project(rendered, k=k)
     _, _, out = _fit_against(sw, src, model, aff, level, grid, n, params, None, tol, stop_frac, min_snr)
-    snr = parse_records(out)["snr"].float().view(S, g2).median(dim=1).values
-    bad = (snr < frac * snr.median()).cpu().tolist()
+    # medians as the midpoint of the two middle values for even counts
+    snr = torch.quantile(parse_records(out)["snr"].double().view(S, g2), 0.5, dim=1)
+    bad = (snr < frac * torch.quantile(snr, 0.5)).cpu().tolist()
     spans = _spans(bad)
+    fits = {}
     if spans:
         idx = torch.tensor([s for s in range(S) if bad[s]], dtype=torch.long, device=raw.device)
         excl = torch.tensor(bad, dtype=torch.uint8, device=raw.device)
@@ -272,5 +278,6 @@ def repair_jumps(sw, raw, aff, level=0, n=512, grid=8, k=3, break_px=2.0, frac=0
         for (a, b) in spans:
             sw.blend_span(a, b, fits[-1], fits[1], aff)
     torch.cuda.synchronize(raw.device)
-    report = dict(breaks=breaks, spans=spans, section_snr=snr.cpu().tolist(), ms=(time.perf_counter() - t0) * 1e3)
+    report = dict(breaks=breaks, spans=spans, section_snr=snr.cpu().tolist(), ms=(time.perf_counter() - t0) * 1e3,
+                  rounds=rounds, centres=centres, side_fits={sd: f.cpu().numpy() for sd, f in fits.items()})
     return aff, report

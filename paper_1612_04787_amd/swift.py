@@ -43,11 +43,12 @@ class Pairs(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("p", C.c_float), ("eps_rel", C.c_float), ("taper_frac", C.c_float),
-                ("centroid_r", C.c_int32), ("flags", C.c_int32), ("max_shift", C.c_int32)]
+                ("centroid_r", C.c_int32), ("flags", C.c_int32), ("max_shift", C.c_int32),
+                ("snr_exclude_r", C.c_int32), ("reserved", C.c_int32)]
 
 
 REC_BYTES = 64
-assert C.sizeof(Image) == 32 and C.sizeof(Pairs) == 56 and C.sizeof(Params) == 24
+assert C.sizeof(Image) == 32 and C.sizeof(Pairs) == 56 and C.sizeof(Params) == 32
 
 _lib = None
 
@@ -61,7 +62,7 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError("libswift.so is not built (%s); run __graft_entry__.build()" % path)
     lib = C.CDLL(path)
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
-    lib.swift_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.swift_create.argtypes = [C.c_int, C.c_char_p, C.POINTER(vp)]
     lib.swift_destroy.argtypes = [vp]
     lib.swift_destroy.restype = None
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
@@ -90,21 +91,21 @@ def load_library(path: str = LIB_PATH):
     lib.swift_profile_enable.argtypes = [vp, C.c_int]
     lib.swift_profile_read.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(i32)]
     lib.swift_last_error.restype = C.c_char_p
-    for f in ("swift_create", "swift_workspace_size", "swift_match_batch", "swift_match_backward",
-              "swift_project", "swift_pyramid", "swift_snr", "swift_profile_enable", "swift_profile_read",
-              "swift_refine_update", "swift_centroid_jacobian", "swift_render", "swift_stack_windows",
-              "swift_fit_sections", "swift_match_graph", "swift_plan", "swift_autotune"):
-        getattr(lib, f).restype = C.c_int
+    for f in exported_symbols():
+        if f not in ("swift_destroy", "swift_last_error"):
+            getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
 
 
 def exported_symbols():
-    return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch",
-            "swift_match_backward", "swift_project", "swift_pyramid", "swift_snr", "swift_last_error",
-            "swift_profile_enable", "swift_profile_read", "swift_refine_update",
-            "swift_centroid_jacobian", "swift_render", "swift_stack_windows", "swift_fit_sections",
-            "swift_match_graph", "swift_plan", "swift_autotune"]
+    """Every entry point include/swift.h declares."""
+    return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch", "swift_match_graph",
+            "swift_match_backward", "swift_centroid_jacobian", "swift_project", "swift_project_side",
+            "swift_blend_span", "swift_join_break", "swift_search_keep", "swift_search_next", "swift_pyramid",
+            "swift_snr", "swift_refine_update", "swift_render", "swift_stack_windows", "swift_fit_sections",
+            "swift_render_mesh", "swift_mesh_windows", "swift_fit_mesh", "swift_plan", "swift_autotune",
+            "swift_profile_enable", "swift_profile_read", "swift_last_error"]
 
 
 def _check(rc):
@@ -116,8 +117,9 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
-def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0, max_shift=0):
-    return Params(float(p), float(eps_rel), float(taper_frac), int(centroid_r), int(flags), int(max_shift))
+def make_params(p=0.65, eps_rel=1e-4, taper_frac=0.25, centroid_r=1, flags=0, max_shift=0, snr_exclude_r=0):
+    return Params(float(p), float(eps_rel), float(taper_frac), int(centroid_r), int(flags), int(max_shift),
+                  int(snr_exclude_r), 0)
 
 
 def parse_records(rec: torch.Tensor) -> dict:
@@ -134,13 +136,16 @@ def parse_records(rec: torch.Tensor) -> dict:
 class Swift:
     """A libswift context on one GPU."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache=None):
+        """tune_cache: path of the plan file swift_autotune writes and later
+        contexts read (None: no file)."""
         if not torch.cuda.is_available():
             raise RuntimeError("libswift needs a ROCm GPU; none is visible")
         self.lib = load_library()
         self.device = torch.device("cuda", device)
         h = C.c_void_p()
-        _check(self.lib.swift_create(device, C.byref(h)))
+        path = tune_cache.encode() if tune_cache else None
+        _check(self.lib.swift_create(device, path, C.byref(h)))
         self.h = h
         self._ws = None
 

@@ -36,10 +36,15 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, f), f
 
 
+def test_binding_declares_every_entry_point():
+    from paper_1612_04787_amd import swift as S
+    assert sorted(S.exported_symbols()) == declared_functions()
+
+
 def test_binding_struct_layouts_match_header():
     from paper_1612_04787_amd import swift as S
     assert C.sizeof(S.Image) == 32
-    assert C.sizeof(S.Params) == 24
+    assert C.sizeof(S.Params) == 32
     assert S.REC_BYTES == 64
 
 

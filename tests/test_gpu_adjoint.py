@@ -55,6 +55,16 @@ def _thetas(rng, k, n, size):
 @pytest.mark.parametrize("p", [0.65, 0.0, 1.0])
 @pytest.mark.parametrize("gpgs", [(0.0, 1.0), (1.0, 0.0), (0.3, -0.7)])
 def test_adjoint_matches_oracle(ctx, pair_small, n, p, gpgs):
+    _adjoint_case(ctx, pair_small, n, p, gpgs)
+
+
+@pytest.mark.parametrize("p,gpgs", [(0.65, (0.0, 1.0)), (1.0, (0.3, -0.7)), (0.0, (1.0, 0.0))])
+def test_adjoint_matches_oracle_1024(ctx, pair_small, p, gpgs):
+    """The plain adjoint (swift_match_backward) at 1024^2."""
+    _adjoint_case(ctx, pair_small, 1024, p, gpgs)
+
+
+def _adjoint_case(ctx, pair_small, n, p, gpgs):
     import paper_1612_04787_amd as sw
     gp, gs = gpgs
     print("case adjoint n=%d p=%g g=(%g,%g)" % (n, p, gp, gs), flush=True)
@@ -227,3 +237,113 @@ def test_config4_shape_sampled(ctx):
         assert err <= GRAD_RTOL, (i, err, x, y)
         checked += 1
     assert checked >= 6
+
+
+def _fd_eligible(theta, n, h):
+    """Every sample position of the window lies more than 2h from integer
+    coordinates, so a step of h in the normalised parameters (which moves no
+    sample by more than h) crosses no bilinear kink."""
+    x, y, _, _ = O.swift_oracle.window_coords(theta, n)
+    fx, fy = x - np.floor(x), y - np.floor(y)
+    d = np.minimum(np.minimum(fx, 1 - fx), np.minimum(fy, 1 - fy))
+    return float(d.min()) > 2 * h
+
+
+def test_config4_fp32_central_fd(ctx):
+    """Config 4 on fp32 windows: 4096 windows of 256^2 on a 64 x 64 grid of
+    a 16384^2 fp32 section, window A at a perturbed affine (sub-pixel shift
+    U(-0.5, 0.5), |E| <= 1e-3), B at identity; forward SNR and adjoint for the
+    whole batch.  On sampled windows whose samples all lie more than 2h from
+    integer coordinates, the GPU gradient of the SNR against FP64 central
+    differences of the oracle's SNR, h = 1e-3 in the normalised parameters,
+    within 1e-3 relative."""
+    import paper_1612_04787_amd as sw
+    from datagen import window_grid
+    print("case config4 fp32 generate", flush=True)
+    sec = make_section(16384, 16384, 4, device=dev()).float()
+    torch.cuda.synchronize()
+    n, h = 256, 1e-3
+    cen = window_grid(16384, 16384, n, 64, spacing=256)
+    th = config4_thetas(len(cen))
+    P = len(cen)
+    ta = np.zeros((P, 8), np.float32)
+    tb = np.zeros((P, 8), np.float32)
+    ta[:, 0:2] = cen
+    ta[:, 2:] = th[:, [0, 1, 2, 3, 4, 5]]
+    tb[:, 0:2] = cen
+    tb[:, 2:] = [1, 0, 0, 0, 1, 0]
+    params = sw.make_params(p=0.65)
+    z = torch.zeros(P, dtype=torch.int32, device=dev())
+    print("case config4 fp32 forward+adjoint P=%d" % P, flush=True)
+    res = ctx.match_batch([sec], [n] * P, z, z, torch.from_numpy(ta), torch.from_numpy(tb), params, save=True)
+    ga, _ = ctx.match_backward(res, params, None, torch.ones(P, device=dev()), want_b=False)
+    torch.cuda.synchronize()
+    ga = ga.cpu().numpy()
+    step = np.array([2.0 / n, 2.0 / n, 1.0, 2.0 / n, 2.0 / n, 1.0])  # normalised -> raw parameter step
+    idx6 = [2, 3, 4, 5, 6, 7]  # (a11, a12, tx, a21, a22, ty) in theta
+    rng = np.random.default_rng(1)
+    checked = eligible = 0
+    for i in rng.permutation(P):
+        if checked >= 6:
+            break
+        cx, cy = cen[i]
+        x0, y0 = int(cx - 140), int(cy - 140)
+        if x0 < 0 or y0 < 0 or x0 + 280 > 16384 or y0 + 280 > 16384:
+            continue
+        t_a = ta[i].astype(np.float64).copy()
+        t_b = tb[i].astype(np.float64).copy()
+        t_a[0:2] -= (x0, y0)
+        t_b[0:2] -= (x0, y0)
+        if not _fd_eligible(t_a, n, h):
+            continue
+        eligible += 1
+        crop = sec[y0:y0 + 280, x0:x0 + 280].double().cpu().numpy()
+        base = O.match_pair(crop, crop, t_a, t_b, n, O.Params(p=0.65))
+        if (base["peak"] - base["second"]) <= TIE_REL * abs(base["peak"]):
+            continue
+        fd = np.zeros(6)
+        for j in range(6):
+            tp, tm = t_a.copy(), t_a.copy()
+            tp[idx6[j]] += h * step[j]
+            tm[idx6[j]] -= h * step[j]
+            rp = O.match_pair(crop, crop, tp, t_b, n, O.Params(p=0.65))
+            rm = O.match_pair(crop, crop, tm, t_b, n, O.Params(p=0.65))
+            assert (rp["ix"], rp["iy"]) == (rm["ix"], rm["iy"]) == (base["ix"], base["iy"])
+            fd[j] = (rp["snr"] - rm["snr"]) / (2 * h)
+        g = normalised(ga[i], n)
+        err = np.linalg.norm(g - fd) / np.linalg.norm(fd)
+        print("   window %d |fd| %.4g rel err %.2e" % (i, np.linalg.norm(fd), err), flush=True)
+        assert err <= GRAD_RTOL, (i, err, g, fd)
+        checked += 1
+    print("   eligible windows visited", eligible, flush=True)
+    assert checked >= 6
+
+
+@pytest.mark.parametrize("p", [0.65, 1.0])
+def test_adjoint_scale_invariance_fp32(ctx, p):
+    """fp32 sources and the same sources times 1e3: the SNR gradient is
+    unchanged (the SNR is invariant to intensity scale) and the peak gradient
+    scales by 1e3^(2 - 2p)."""
+    import paper_1612_04787_amd as sw
+    print("case adjoint fp32 scale p=%g" % p, flush=True)
+    a = make_section(700, 700, 81).float()
+    b = torch.roll(a, shifts=(2, -3), dims=(0, 1)) + 3.0 * torch.randn((700, 700),
+                                                                       generator=torch.Generator().manual_seed(8))
+    rng = np.random.default_rng(5)
+    ta, tb = _thetas(rng, 3, 256, 700)
+    params = sw.make_params(p=p)
+    z = torch.zeros(3, dtype=torch.int32)
+    out = {}
+    for scale in (1.0, 1e3):
+        imgs = [(a * scale).to(dev()), (b * scale).to(dev())]
+        res = ctx.match_batch(imgs, [256] * 3, z, z + 1, torch.from_numpy(ta), torch.from_numpy(tb), params,
+                              save=True)
+        g_snr, _ = ctx.match_backward(res, params, None, torch.ones(3, device=dev()), want_b=False)
+        g_peak, _ = ctx.match_backward(res, params, torch.ones(3, device=dev()), None, want_b=False)
+        torch.cuda.synchronize()
+        out[scale] = (g_snr.cpu().numpy().astype(np.float64), g_peak.cpu().numpy().astype(np.float64))
+    for i in range(3):
+        s1, s2 = normalised(out[1.0][0][i], 256), normalised(out[1e3][0][i], 256)
+        assert np.linalg.norm(s1 - s2) <= 1e-3 * np.linalg.norm(s1), (i, s1, s2)
+        p1, p2 = normalised(out[1.0][1][i], 256), normalised(out[1e3][1][i], 256) / 1e3 ** (2 - 2 * p)
+        assert np.linalg.norm(p1 - p2) <= 1e-3 * np.linalg.norm(p1), (i, p1, p2)

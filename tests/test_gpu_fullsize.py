@@ -185,3 +185,63 @@ def test_headline_jacobian_4096_pairs_512(ctx):
             err = np.linalg.norm(g - r) / np.linalg.norm(r)
             print("   pair %d d%s/dt rel err %.2e" % (i, "xy"[row], err), flush=True)
             assert err <= 1e-3, (i, row, g, r)
+
+
+def test_config3_ragged_batch_sampled(ctx):
+    """Config 3 at full size: a 32-section 8192^2 stack, 4 pyramid levels,
+    +-3 projections per level, 8 x 8 windows per section and level: 8192
+    pairs of 128/256/512/1024 in one ragged call (size groups concurrent).
+    Three pairs per window edge against the oracle, which builds its own
+    pyramid levels (2 x 2 box, from the raw stack bytes) and projections on
+    crops aligned to the level's blocks."""
+    import paper_1612_04787_amd as sw
+    from datagen.workloads import level_stack, ragged_level_pairs
+    from paper_1612_04787_amd.stack import build_pyramid
+    S, size, levels, k = 32, 8192, 4, 3
+    print("case config3 generate", flush=True)
+    stack = level_stack(S, size, seed=3, device=dev())
+    pyr = build_pyramid(ctx, stack, levels - 1)
+    images = []
+    refs = []
+    for lv in pyr:
+        ref = ctx.project(lv, k=k)
+        refs.append(ref)
+        images += [lv[s] for s in range(S)] + [ref[s] for s in range(S)]
+    n_list, ia, ib, ta, tb = ragged_level_pairs(S, size, levels, 8, dev())
+    P = len(n_list)
+    print("case config3 match P=%d" % P, flush=True)
+    res = ctx.match_batch(images, n_list, ia, ib, ta, tb, sw.make_params(p=0.65, flags=sw.FLAG_CONCURRENT_SIZES))
+    torch.cuda.synchronize()
+    ns = np.array(n_list)
+    for n in (128, 256, 512, 1024):
+        sel = torch.from_numpy(np.nonzero(ns == n)[0]).to(dev())
+        _check_all_records({key: v[sel] for key, v in res.items() if torch.is_tensor(v) and v.dim() == 1}, n,
+                           int(sel.numel()))
+    tha = ta.cpu().numpy()
+    iac = ia.cpu().numpy()
+    rng = np.random.default_rng(33)
+    for n in (128, 256, 512, 1024):
+        lvl = {1024: 0, 512: 1, 256: 2, 128: 3}[n]
+        side = size >> lvl
+        for i in rng.choice(np.nonzero(ns == n)[0], 3, replace=False):
+            s = int(iac[i]) - 2 * S * lvl
+            cx, cy = float(tha[i, 0]), float(tha[i, 1])
+            x0, y0, x1, y1 = _crop(cx, cy, n, side, side)
+            f = 1 << lvl
+            lo, hi = max(0, s - k), min(S, s + k + 1)
+            sub = stack[lo:hi, y0 * f:y1 * f, x0 * f:x1 * f].cpu().numpy()
+            lev = []
+            for q in range(hi - lo):
+                im = sub[q]
+                for _ in range(lvl):
+                    im = O.pyramid(im)
+                lev.append(im)
+            lev = np.stack(lev)
+            got = pyr[lvl][s, y0:y1, x0:x1].cpu().numpy()
+            assert np.array_equal(got, lev[s - lo]), ("pyramid", n, i)
+            ref_o = O.project(lev, s - lo, k)
+            assert np.array_equal(refs[lvl][s, y0:y1, x0:x1].cpu().numpy(), ref_o), ("projection", n, i)
+            th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
+            r = O.match_pair(lev[s - lo], ref_o, th, th, n, O.Params(p=0.65))
+            e = compare(gpu_record(res, int(i)), r, n, tag="config3 n=%d pair %d" % (n, i))
+            print("   n=%d pair %d (section %d):" % (n, i, s), e, flush=True)

@@ -82,6 +82,7 @@ def test_repair_joins_a_magnification_break(ctx):
     aff2, rep = repair_jumps(ctx, stack, aff.clone(), level=0, n=256, grid=8, k=3)
     r1 = pair_res(aff2)
     print("pair residuals before", np.round(r0, 2), "after", np.round(r1, 2), rep["breaks"], rep["spans"], flush=True)
+    _check_host_logic(rep)
     assert r0[j0 - 1] > 5.0  # the loop left a break
     assert [b["section"] for b in rep["breaks"]] == [j0]
     assert r1.max() < 0.25 * r0.max()
@@ -100,8 +101,55 @@ def test_repair_leaves_a_smooth_stack_alone(ctx):
     aff2, rep = repair_jumps(ctx, stack, aff, level=0, n=256, grid=8, k=3)
     torch.cuda.synchronize()
     print("breaks", rep["breaks"], "spans", rep["spans"], flush=True)
+    _check_host_logic(rep)
     assert rep["breaks"] == [] and rep["spans"] == []
     assert torch.equal(aff2, before)
+
+
+def _check_host_logic(rep, frac=0.75):
+    """The repair's host decisions against the oracle's FP64 definitions:
+    every round's break scores, and the failed spans of the section SNRs."""
+    for rd in rep["rounds"]:
+        for s in range(len(rd["scores"])):
+            ref = O.break_score(rd["aff"][s], rd["fit"][s], rep["centres"][s])
+            assert abs(rd["scores"][s] - ref) <= 1e-9 * max(ref, 1.0), (s, rd["scores"][s], ref)
+    assert rep["spans"] == O.failed_spans(rep["section_snr"], frac)
+
+
+def test_repair_blends_a_failed_span(ctx):
+    """10 sections of 2048^2 (drift, section affines, no jump) with sections
+    4 and 5 buried in noise (sigma 70): their match SNR against the two-sided
+    model falls below 0.75 of the stack median, so they form a failed span.
+    Each is fitted against the one-sided models on either side (both
+    omitting the span) and the span gets the Bezier blend of the two fits,
+    checked against the oracle's blend of the same fits; the other sections
+    keep their affines.  The break scores and the span test are checked
+    against the oracle's definitions."""
+    from datagen.workloads import jump_stack
+    from paper_1612_04787_amd.stack import align_stack, repair_jumps
+    print("case repair failed span 10 x 2048^2", flush=True)
+    S, size = 10, 2048
+    stack, _ = jump_stack(S, size, seed=19, j0=S, mag=0.0, device=dev())
+    g = torch.Generator(device=dev()).manual_seed(77)
+    for s in (4, 5):
+        noisy = stack[s].float() + 70.0 * torch.randn(stack[s].shape, generator=g, device=dev())
+        stack[s] = noisy.round().clamp(0, 255).to(torch.uint8)
+    aff, _ = align_stack(ctx, stack, levels=(1, 0), ns=(128, 256), iters=(2, 1), ks=(4, 3), grid=8)
+    before = aff.clone().cpu().numpy()
+    aff2, rep = repair_jumps(ctx, stack, aff.clone(), level=0, n=256, grid=8, k=3)
+    torch.cuda.synchronize()
+    print("breaks", rep["breaks"], "spans", rep["spans"], "section snr", np.round(rep["section_snr"], 1), flush=True)
+    _check_host_logic(rep)
+    assert rep["breaks"] == []
+    assert (4, 5) in rep["spans"]
+    got = aff2.cpu().numpy()
+    span_rows = {s for (a, b) in rep["spans"] for s in range(a, b + 1)}
+    for s in range(S):
+        if s not in span_rows:
+            np.testing.assert_array_equal(got[s], before[s])
+    for (a, b) in rep["spans"]:
+        ref = O.blend_span(rep["side_fits"][-1], rep["side_fits"][1], a, b)
+        np.testing.assert_allclose(got[a:b + 1], ref, rtol=0, atol=1e-9)
 
 
 def test_jump_entry_points_reject_bad_arguments(ctx):

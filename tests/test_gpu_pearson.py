@@ -135,6 +135,31 @@ def test_pearson_large_windows_sampled(ctx, section_pair_small, n):
         assert abs(g["dx"] - dx) < 0.5 and abs(g["dy"] - dy) < 0.5
 
 
+def test_pearson_512_records(ctx, section_pair_small):
+    """The size the bench's Pearson block times: two 512^2 pairs of real
+    section content (B a warped, noisy copy of A; one window with a small
+    affine), full records (coefficient, SNR, mean, std, centroid) against
+    the oracle's direct per-placement coefficients."""
+    print("case pearson 512 records", flush=True)
+    a, b = section_pair_small
+    n, k = 512, 2
+    tha = np.array([[800.0, 760.0, 1, 0, 0.25, 0, 1, -0.5],
+                    [700.0, 850.0, 1 + 1e-3, -8e-4, -0.375, 6e-4, 1 - 5e-4, 0.125]], np.float32)
+    thb = tha.copy()
+    thb[:, 4] += np.array([37.0, -61.5], np.float32)
+    thb[:, 7] += np.array([-22.0, 18.25], np.float32)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(tha), torch.from_numpy(thb), _params())
+    torch.cuda.synchronize()
+    an, bn = a.numpy(), b.numpy()
+    for i in range(k):
+        r = O.pearson_pair(an, bn, tha[i].astype(np.float64), thb[i].astype(np.float64), n, return_surface=True)
+        g = gpu_record(res, i)
+        print("   ", i, g, r["peak"], r["snr"], r["dx"], r["dy"], flush=True)
+        _compare(g, r, n, "pearson 512 i=%d" % i)
+        assert r["snr"] > 5.0 and r["peak"] > 0.5
+
+
 def test_pearson_degenerate_ragged_and_graph(ctx, section_pair_small):
     """A constant template is degenerate; one ragged call over 64..256 on
     the concurrent groups and as graph replays gives identical records."""

@@ -1059,6 +1059,24 @@ def test_failed_spans_runs():
     snr = [30, 31, 29, 8, 7, 30, 32, 10, 31]
     assert O.failed_spans(snr, 0.5) == [(3, 4), (7, 7)]
     assert O.failed_spans([20] * 5, 0.5) == []
+    # an even count: the median is the midpoint of the two middle values (25,
+    # threshold 12.5), not the lower one (20, threshold 10)
+    assert O.failed_spans([10, 20, 30, 40], 0.5) == [(0, 0)]
+
+
+def test_break_score_closed_forms():
+    rng = np.random.default_rng(62)
+    c = rng.uniform(0, 4096, (64, 2))
+    aff = np.array([1.001, -0.002, 3.0, 0.0015, 0.999, -4.0])
+    # a fit that only translates: every centre moves by (dx, dy)
+    fit = aff + np.array([0, 0, 1.5, 0, 0, -2.0])
+    assert abs(O.break_score(aff, fit, c) - 2.5) < 1e-12
+    assert O.break_score(aff, aff, c) == 0.0
+    # every entry scaled by (1 + e): centre c moves by e A(c), so the score is e RMS|A(c)|
+    e = 1e-3
+    fit2 = aff * np.array([1 + e, 1 + e, 1 + e, 1 + e, 1 + e, 1 + e])
+    pa = np.stack(O.apply_affine(aff, c[:, 0], c[:, 1]), 1)
+    assert abs(O.break_score(aff, fit2, c) - e * np.sqrt(np.mean(np.sum(pa ** 2, 1)))) < 1e-9
 
 
 def test_join_break_closed_forms():
