@@ -479,23 +479,33 @@ int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a
                    const swift_match* recs, int32_t level, float min_snr, const double* aff,
                    double* tri_aff, int32_t* status, hipStream_t stream);
 
-/* Row-count variants of the match kernels (a tuning choice, not in the
- * paper).  Each window size has two row counts per block for the forward row
- * pass and two for the inverse row pass (variant 0 = the default, 1 = the
- * alternative); the results agree to rounding.  swift_plan sets the variants
- * of size n (a value < 0 keeps the current one) and reports the rows per
- * block in *fwd_rows / *inv_rows (either may be NULL).  Plans are per
- * context; cached graphs are keyed by them.  Errors: SWIFT_E_INVAL. */
-int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant,
-               int32_t* fwd_rows, int32_t* inv_rows);
+/* The plan: kernel variants of the match per window size (a tuning choice,
+ * not in the paper; the results agree to rounding).
+ *  - Row-count variants: two row counts per block for the forward row pass
+ *    and two for the inverse row pass (variant 0 = the default, 1 = the
+ *    alternative).
+ *  - Chunks (1, 2, 4, 8): a size group of P pairs is split into that many
+ *    chunks of consecutive pairs whose kernel sequences alternate between two
+ *    streams of the context (forked from and joined back into the call's
+ *    stream), so that one chunk's forward row pass runs beside another's
+ *    column pass.  The records are identical to those of one chunk.
+ * swift_plan sets the variants of size n (a value < 0 keeps the current one)
+ * and reports the rows per block and the chunks (any output may be NULL).
+ * Plans are per context; cached graphs are keyed by them.  Errors:
+ * SWIFT_E_INVAL. */
+int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant, int32_t chunks,
+               int32_t* fwd_rows, int32_t* inv_rows, int32_t* chunks_out);
 
-/* Times every variant pair of each listed window size on a synthetic batch
+/* Times plan variants of each listed window size on a synthetic batch
  * (pairs_per_size translation windows of hashed uint8 noise, p = 0.65;
- * <= 0 means 512) and keeps the fastest in the context's plan.  Synchronous;
- * allocates and frees its own device buffers, so it is a set-up call, not
- * one for a capture or a serving loop.  times_ms: host [n_sizes][4] or NULL,
- * receives the mean time per batch of variant (fwd + 2 inv) = 0..3, -1 where
- * a variant equals another.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
+ * <= 0 means 512) and keeps the fastest in the context's plan (and, with a
+ * tune cache path, in that file).  Synchronous; allocates and frees its own
+ * device buffers, so it is a set-up call, not one for a capture or a serving
+ * loop.  times_ms: host [n_sizes][SWIFT_TUNE_SLOTS] or NULL, receives the mean
+ * time per batch of: slots 0..3 the row variants (fwd + 2 inv) in one chunk,
+ * slots 4..6 the fastest of those in 2, 4 and 8 chunks; -1 where a variant
+ * equals another or does not apply.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
+#define SWIFT_TUNE_SLOTS 8
 int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_t pairs_per_size,
                    float* times_ms);
 

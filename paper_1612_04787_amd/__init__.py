@@ -7,6 +7,9 @@ from .swift import (  # noqa: F401
     FLAG_CONCURRENT_SIZES,
     FLAG_JAC_TRANSLATION,
     FLAG_PEARSON,
+    ST_NEAR_TIE,
+    ST_DEGENERATE,
+    ST_CLAMPED,
     SIZES,
     Swift,
     SwiftError,

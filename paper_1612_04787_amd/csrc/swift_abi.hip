@@ -90,11 +90,19 @@ struct swift_ctx {
   // row-count variant per window size (swift_plan / swift_autotune)
   uint8_t alt_fwd[SWIFT_NSIZES] = {};
   uint8_t alt_inv[SWIFT_NSIZES] = {};
+  // chunks per size group: > 1 splits a group into chunks whose kernel
+  // sequences run on two streams, so one chunk's row pass overlaps another's
+  // column pass (created on first use)
+  uint8_t chunks[SWIFT_NSIZES] = {1, 1, 1, 1, 1};
+  hipStream_t cs[SWIFT_NSIZES][2] = {};
+  hipEvent_t cfork[SWIFT_NSIZES] = {};
+  hipEvent_t cjoin[SWIFT_NSIZES][2] = {};
   // tune cache: file path ("" for none) and this device's key in it
   std::string tune_path, tune_key;
 };
 
 static constexpr size_t kMaxGraphs = 16;
+static constexpr int kTuneSlots = SWIFT_TUNE_SLOTS;
 
 static void ctx_release(swift_ctx* c) {
   for (auto& kv : c->graphs) {
@@ -105,6 +113,11 @@ static void ctx_release(swift_ctx* c) {
   for (int i = 0; i < SWIFT_NSIZES; ++i) {
     if (c->gs[i]) (void)hipStreamDestroy(c->gs[i]);
     if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+    if (c->cfork[i]) (void)hipEventDestroy(c->cfork[i]);
+    for (int j = 0; j < 2; ++j) {
+      if (c->cs[i][j]) (void)hipStreamDestroy(c->cs[i][j]);
+      if (c->cjoin[i][j]) (void)hipEventDestroy(c->cjoin[i][j]);
+    }
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -303,6 +316,8 @@ static void fill_lane_twiddles(float2* host) {
   }
 }
 
+static bool valid_chunks(int c) { return c == 1 || c == 2 || c == 4 || c == 8; }
+
 // ---------------------------------------------------------------- tune cache
 // A text file of plan lines "<device key> <n> <fwd variant> <inv variant>",
 // one per device and window size; '#' starts a comment.  The device key is
@@ -323,15 +338,18 @@ static void tune_cache_load(swift_ctx* c) {
   FILE* f = fopen(c->tune_path.c_str(), "r");
   if (!f) return;
   char line[512], key[320];
-  int n, vf, vi;
+  int n, vf, vi, ch;
   while (fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
-    if (sscanf(line, "%319s %d %d %d", key, &n, &vf, &vi) != 4) continue;
-    if (c->tune_key != key || vf < 0 || vf > 1 || vi < 0 || vi > 1) continue;
+    const int got = sscanf(line, "%319s %d %d %d %d", key, &n, &vf, &vi, &ch);
+    if (got < 4) continue;
+    if (got == 4) ch = 1;
+    if (c->tune_key != key || vf < 0 || vf > 1 || vi < 0 || vi > 1 || !valid_chunks(ch)) continue;
     for (int i = 0; i < SWIFT_NSIZES; ++i)
       if (kSizes[i] == n) {
         c->alt_fwd[i] = (uint8_t)vf;
         c->alt_inv[i] = (uint8_t)vi;
+        c->chunks[i] = (uint8_t)ch;
       }
   }
   fclose(f);
@@ -360,10 +378,12 @@ static bool tune_cache_store(const swift_ctx* c, const bool (&tuned)[SWIFT_NSIZE
   const std::string tmp = c->tune_path + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return false;
-  bool good = fputs("# libswift tune cache: <device> <n> <fwd variant> <inv variant>\n", f) >= 0;
+  bool good = fputs("# libswift tune cache: <device> <n> <fwd variant> <inv variant> <chunks>\n", f) >= 0;
   for (const auto& l : keep) good = good && fputs(l.c_str(), f) >= 0;
   for (int i = 0; i < SWIFT_NSIZES; ++i)
-    if (tuned[i]) good = good && fprintf(f, "%s %d %d %d\n", c->tune_key.c_str(), kSizes[i], c->alt_fwd[i], c->alt_inv[i]) > 0;
+    if (tuned[i])
+      good = good && fprintf(f, "%s %d %d %d %d\n", c->tune_key.c_str(), kSizes[i], c->alt_fwd[i], c->alt_inv[i],
+                             c->chunks[i]) > 0;
   good = (fclose(f) == 0) && good;
   return good && rename(tmp.c_str(), c->tune_path.c_str()) == 0;
 }
@@ -467,6 +487,55 @@ static int check_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, 
   const Layout L = make_layout(pairs, pearson_mode(params));
   if (!ws || ws_bytes < L.total)
     return fail(SWIFT_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total, ws ? ws_bytes : (size_t)0);
+  return SWIFT_OK;
+}
+
+// The size group of `a` as nch chunks of consecutive pairs, alternating
+// between the context's two chunk streams of size i (forked from and joined
+// back into s).  Every per-pair array of a chunk is the group's array from
+// its first pair on, so the chunks' results are those of one launch.
+static int enqueue_chunks(swift_ctx* ctx, int i, const GroupLayout& g, const MatchArgs& a, int nch, hipStream_t s,
+                          KernelTimer* kt) {
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < 2 && e == hipSuccess; ++j) {
+    if (!ctx->cs[i][j]) e = hipStreamCreateWithFlags(&ctx->cs[i][j], hipStreamNonBlocking);
+    if (e == hipSuccess && !ctx->cjoin[i][j]) e = hipEventCreateWithFlags(&ctx->cjoin[i][j], hipEventDisableTiming);
+  }
+  if (e == hipSuccess && !ctx->cfork[i]) e = hipEventCreateWithFlags(&ctx->cfork[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ctx->cfork[i], s);
+  for (int j = 0; j < 2 && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->cs[i][j], ctx->cfork[i], 0);
+  if (e != hipSuccess) return hip_fail(e, "chunk fork");
+  const size_t n = (size_t)g.n, P = (size_t)g.count;
+  const bool af = ctx->alt_fwd[i] != 0, ai = ctx->alt_inv[i] != 0;
+  for (int c = 0; c < nch; ++c) {
+    const size_t p0 = P * c / nch, p1 = P * (c + 1) / nch;
+    MatchArgs b = a;
+    b.npairs = (int)(p1 - p0);
+    b.img_a += p0;
+    b.img_b += p0;
+    b.th_a += 8 * p0;
+    b.th_b += 8 * p0;
+    b.out += p0;
+    if (b.surfaces) b.surfaces += p0 * n * n;
+    b.Z += p0 * n * n;
+    b.rowpart += p0 * (size_t)a.nsl_fwd;
+    b.pstat += p0;
+    b.invpart += p0 * (size_t)a.nsl_inv;
+    b.colsq += p0 * (n / 2 + 1);
+    if (b.ncc_rows) b.ncc_rows += p0 * n * (n / 2 + 1);
+    if (b.ncc_var) b.ncc_var += p0 * (n / 2 + 1) * (n / 2 + 1);
+    if (b.saved_Z) b.saved_Z += p0 * n * n;
+    if (b.saved_ps) b.saved_ps += p0;
+    if (b.saved_rec) b.saved_rec += p0;
+    if (b.saved_nb) b.saved_nb += 9 * p0;
+    e = launch_match_group(g.n, b, af, ai, ctx->cs[i][c & 1], kt);
+    if (e != hipSuccess) return hip_fail(e, "match launch");
+  }
+  for (int j = 0; j < 2 && e == hipSuccess; ++j) {
+    e = hipEventRecord(ctx->cjoin[i][j], ctx->cs[i][j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->cjoin[i][j], 0);
+  }
+  if (e != hipSuccess) return hip_fail(e, "chunk join");
   return SWIFT_OK;
 }
 
@@ -576,8 +645,14 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    e = launch_match_group(g.n, a, ctx->alt_fwd[i] != 0, ctx->alt_inv[i] != 0, s, kt);
-    if (e != hipSuccess) return hip_fail(e, "match launch");
+    const int nch = min((int)ctx->chunks[i], g.count);
+    if (nch <= 1) {
+      e = launch_match_group(g.n, a, ctx->alt_fwd[i] != 0, ctx->alt_inv[i] != 0, s, kt);
+      if (e != hipSuccess) return hip_fail(e, "match launch");
+    } else {
+      const int rc = enqueue_chunks(ctx, i, g, a, nch, s, kt);
+      if (rc) return rc;
+    }
     if (concurrent) {
       e = hipEventRecord(ctx->join_ev[i], s);
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, ctx->join_ev[i], 0);
@@ -616,7 +691,7 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
     const void* p[9];
     int32_t n_imgs, n_pairs, counts[SWIFT_NSIZES];
     swift_params prm;
-    uint8_t plan[2 * SWIFT_NSIZES];
+    uint8_t plan[3 * SWIFT_NSIZES];
   } key;
   memset(&key, 0, sizeof(key));
   key.p[0] = imgs;
@@ -635,6 +710,7 @@ int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   for (int i = 0; i < SWIFT_NSIZES; ++i) {
     key.plan[i] = ctx->alt_fwd[i];
     key.plan[SWIFT_NSIZES + i] = ctx->alt_inv[i];
+    key.plan[2 * SWIFT_NSIZES + i] = ctx->chunks[i];
   }
   const std::string k((const char*)&key, sizeof(key));
   auto it = ctx->graphs.find(k);
@@ -1033,16 +1109,19 @@ static int size_index(int n) {
   return -1;
 }
 
-int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant, int32_t* fwd_rows,
-               int32_t* inv_rows) {
+int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_variant, int32_t chunks,
+               int32_t* fwd_rows, int32_t* inv_rows, int32_t* chunks_out) {
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   const int i = size_index(n);
   if (i < 0) return fail(SWIFT_E_INVAL, "n must be one of 64, 128, 256, 512, 1024 (got %d)", n);
   if (fwd_variant > 1 || inv_variant > 1) return fail(SWIFT_E_INVAL, "variants are 0, 1 or -1 (keep)");
+  if (chunks >= 0 && !valid_chunks(chunks)) return fail(SWIFT_E_INVAL, "chunks are 1, 2, 4, 8 or -1 (keep)");
   if (fwd_variant >= 0) ctx->alt_fwd[i] = (uint8_t)fwd_variant;
   if (inv_variant >= 0) ctx->alt_inv[i] = (uint8_t)inv_variant;
+  if (chunks >= 0) ctx->chunks[i] = (uint8_t)chunks;
   if (fwd_rows) *fwd_rows = n / fwd_blocks_n(n, ctx->alt_fwd[i] != 0);
   if (inv_rows) *inv_rows = n / inv_blocks_n(n, ctx->alt_inv[i] != 0);
+  if (chunks_out) *chunks_out = ctx->chunks[i];
   return ok();
 }
 
@@ -1142,17 +1221,22 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
       return fail(SWIFT_E_HIP, "autotune events");
     }
     float best = 0.0f;
-    int best_v = 0;
-    const uint8_t keep_f = ctx->alt_fwd[si], keep_i = ctx->alt_inv[si];
+    int best_v = 0, best_c = 1;
+    const uint8_t keep_f = ctx->alt_fwd[si], keep_i = ctx->alt_inv[si], keep_c = ctx->chunks[si];
     int rc = SWIFT_OK;
-    for (int v = 0; v < 4 && rc == SWIFT_OK; ++v) {
-      const bool af = (v & 1) != 0, ai = (v & 2) != 0;
+    // slots 0..3: the row variants in one chunk; 4..6: the best of them in
+    // 2, 4, 8 chunks on two streams
+    for (int v = 0; v < kTuneSlots && rc == SWIFT_OK; ++v) {
+      const int vv = v < 4 ? v : best_v;
+      const int ch = v < 4 ? 1 : (v == 4 ? 2 : v == 5 ? 4 : v == 6 ? 8 : 0);
+      const bool af = (vv & 1) != 0, ai = (vv & 2) != 0;
       float ms = -1.0f;
-      const bool distinct = (!af || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
+      const bool distinct = ch > 0 && ch <= P && (!af || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
                             (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false));
       if (distinct) {
         ctx->alt_fwd[si] = af;
         ctx->alt_inv[si] = ai;
+        ctx->chunks[si] = (uint8_t)ch;
         rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
                            b.p[5], st, false, nullptr);  // warm-up
         if (rc == SWIFT_OK) rc = hipEventRecord(e0, st) == hipSuccess ? SWIFT_OK : fail(SWIFT_E_HIP, "event");
@@ -1165,20 +1249,23 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
         ms /= 3.0f;
         if (rc == SWIFT_OK && (v == 0 || ms < best)) {  // variant 0 (the defaults) always runs first
           best = ms;
-          best_v = v;
+          best_v = vv;
+          best_c = ch;
         }
       }
-      if (times_ms) times_ms[k * 4 + v] = ms;
+      if (times_ms) times_ms[k * kTuneSlots + v] = ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SWIFT_OK) {
       ctx->alt_fwd[si] = keep_f;
       ctx->alt_inv[si] = keep_i;
+      ctx->chunks[si] = keep_c;
       return rc;
     }
     ctx->alt_fwd[si] = (best_v & 1) != 0;
     ctx->alt_inv[si] = (best_v & 2) != 0;
+    ctx->chunks[si] = (uint8_t)best_c;
     tuned[si] = true;
   }
   if (!ctx->tune_path.empty() && n_sizes > 0 && !tune_cache_store(ctx, tuned))

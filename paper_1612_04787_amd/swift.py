@@ -48,6 +48,7 @@ class Params(C.Structure):
 
 
 REC_BYTES = 64
+TUNE_SLOTS = 8
 assert C.sizeof(Image) == 32 and C.sizeof(Pairs) == 56 and C.sizeof(Params) == 32
 
 _lib = None
@@ -68,7 +69,7 @@ def load_library(path: str = LIB_PATH):
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
     lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
     lib.swift_match_graph.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
-    lib.swift_plan.argtypes = [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+    lib.swift_plan.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.swift_autotune.argtypes = [vp, C.POINTER(i32), i32, i32, C.POINTER(C.c_float)]
     lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
                                          vp, vp, sz, vp]
@@ -343,21 +344,25 @@ class Swift:
                                             float(max_step), _ptr(step_out), self.stream()))
 
     # ------------------------------------------------------------------ tuning
-    def plan(self, n, fwd_variant=-1, inv_variant=-1):
-        """Sets (values >= 0) and returns the row-count variants of size n as
-        (forward rows per block, inverse rows per block)."""
-        fr, ir = C.c_int32(), C.c_int32()
-        _check(self.lib.swift_plan(self.h, int(n), int(fwd_variant), int(inv_variant), C.byref(fr), C.byref(ir)))
+    def plan(self, n, fwd_variant=-1, inv_variant=-1, chunks=-1, full=False):
+        """Sets (values >= 0) and returns the plan of size n as (forward rows
+        per block, inverse rows per block), with full=True also the chunks."""
+        fr, ir, ch = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self.lib.swift_plan(self.h, int(n), int(fwd_variant), int(inv_variant), int(chunks), C.byref(fr),
+                                   C.byref(ir), C.byref(ch)))
+        if full:
+            return fr.value, ir.value, ch.value
         return fr.value, ir.value
 
     def autotune(self, sizes=SIZES, pairs_per_size=512):
-        """Times the row-count variants of each size and keeps the fastest.
-        Returns {n: (times_ms[4], (fwd_rows, inv_rows))}."""
+        """Times the plan variants of each size and keeps the fastest.
+        Returns {n: (times_ms[TUNE_SLOTS], (fwd_rows, inv_rows, chunks))}."""
         sizes = [int(n) for n in sizes]
         arr = (C.c_int32 * len(sizes))(*sizes)
-        times = (C.c_float * (4 * len(sizes)))()
+        times = (C.c_float * (TUNE_SLOTS * len(sizes)))()
         _check(self.lib.swift_autotune(self.h, arr, len(sizes), int(pairs_per_size), times))
-        return {n: (list(times[4 * k:4 * k + 4]), self.plan(n)) for k, n in enumerate(sizes)}
+        return {n: (list(times[TUNE_SLOTS * k:TUNE_SLOTS * k + TUNE_SLOTS]), self.plan(n, full=True))
+                for k, n in enumerate(sizes)}
 
     # ------------------------------------------------------------------ stack loop
     def render(self, src, aff, level, out_hw=None, out=None):

@@ -55,7 +55,7 @@ def test_validation_without_gpu(lib):
     ws = C.c_size_t()
     assert lib.swift_workspace_size(None, C.byref(pr), C.byref(pa), C.byref(ws), None) == -1
     assert b"ctx" in lib.swift_last_error()
-    assert lib.swift_plan(None, 512, 0, 0, None, None) == -1
+    assert lib.swift_plan(None, 512, 0, 0, -1, None, None, None) == -1
     assert lib.swift_autotune(None, None, 0, 0, None) == -1
     assert lib.swift_match_batch(None, None, 0, C.byref(pr), C.byref(pa), None, None, None, None, 0, None) == -1
     assert lib.swift_match_graph(None, None, 0, C.byref(pr), C.byref(pa), None, None, None, None, 0, None) == -1

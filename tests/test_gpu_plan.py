@@ -66,13 +66,62 @@ def test_variants_match_oracle(ctx, pair, n, variant):
 def test_autotune_picks_a_timed_variant(ctx):
     print("case autotune", flush=True)
     out = ctx.autotune(SIZES, pairs_per_size=128)
-    for n, (times, rows) in out.items():
-        print("   n=%d times_ms=%s -> rows %s" % (n, ["%.3f" % t for t in times], rows), flush=True)
+    for n, (times, plan) in out.items():
+        print("   n=%d times_ms=%s -> plan %s" % (n, ["%.3f" % t for t in times], plan), flush=True)
         assert times[0] > 0
         valid = [(t, v) for v, t in enumerate(times) if t > 0]
         best = min(valid)[1]
-        assert rows == ctx.plan(n)
-        ctx.plan(n, best & 1, best >> 1)
-        assert ctx.plan(n) == rows
+        assert plan == ctx.plan(n, full=True)
+        if best < 4:
+            ctx.plan(n, best & 1, best >> 1, 1)
+        else:
+            # a chunked slot times the best row variant of slots 0..3
+            rv = min((t, v) for v, t in enumerate(times[:4]) if t > 0)[1]
+            ctx.plan(n, rv & 1, rv >> 1, {4: 2, 5: 4, 6: 8}[best])
+        assert ctx.plan(n, full=True) == plan
     for n in SIZES:
-        ctx.plan(n, 0, 0)
+        ctx.plan(n, 0, 0, 1)
+
+
+@pytest.mark.parametrize("n", [64, 256, 512])
+@pytest.mark.parametrize("chunks", [2, 4, 8])
+def test_chunked_groups_are_bit_identical(ctx, pair, n, chunks):
+    """A size group split into chunks on two streams gives the records,
+    surfaces and saved state of one launch, also under graph replay and with
+    a search radius."""
+    import paper_1612_04787_amd as sw
+    print("case chunks n=%d chunks=%d" % (n, chunks), flush=True)
+    a, b = pair
+    rng = np.random.default_rng(900 + n + chunks)
+    k = 11
+    th = np.zeros((k, 8), np.float32)
+    for i in range(k):
+        th[i] = [rng.uniform(n / 2 + 8, 1500 - n / 2 - 8), rng.uniform(n / 2 + 8, 1500 - n / 2 - 8), 1, 0,
+                 rng.uniform(-2, 2), 0, 1, rng.uniform(-2, 2)]
+    thb = th.copy()
+    thb[:, 4] += 0.7
+    args = ([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32), torch.ones(k, dtype=torch.int32),
+            torch.from_numpy(th), torch.from_numpy(thb))
+    try:
+        for params in (sw.make_params(p=0.65), sw.make_params(p=0.65, max_shift=n // 8)):
+            surf = params.max_shift == 0
+            ctx.plan(n, 0, 0, 1)
+            ref = ctx.match_batch(*args, params, surfaces=surf, save=surf)
+            ctx.plan(n, 0, 0, chunks)
+            got = ctx.match_batch(*args, params, surfaces=surf, save=surf)
+            torch.cuda.synchronize()
+            assert torch.equal(ref["raw"], got["raw"])
+            if surf:
+                assert torch.equal(ref["surfaces"], got["surfaces"])
+                one = torch.ones(k, device=dev())
+                ga_ref, _ = ctx.match_backward(ref, params, None, one)
+                ga_got, _ = ctx.match_backward(got, params, None, one)
+                assert torch.equal(ga_ref, ga_got)
+            prep = ctx.prepare(*args)
+            for rep in range(3):
+                out = torch.empty((k, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev())
+                ctx.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, graph=True)
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref["raw"]), rep
+    finally:
+        ctx.plan(n, 0, 0, 1)
