@@ -161,16 +161,16 @@ struct FwdStage {
 
 // Gathers one image of the thread's samples into the stage (real parts for
 // A, imaginary parts for B): a' T with a' = sample - o and T = t(x) t(y),
-// formed as ((a - o) t(x)) t(y).  Adds the slice sums s1 = sum a'T,
-// s2 = sum (a'T)^2 and, per column, s3c[c] = sum_r (a'T) t(y), so that
-// sum (a'T) T = sum_c t(x_c) s3c[c].
+// formed as ((a - o) t(x)) t(y).  Adds the slice sum s2 = sum (a'T)^2 and,
+// per column, s3c[c] = sum_r (a'T) t(y), so that sum (a'T) T =
+// sum_c t(x_c) s3c[c].  (sum a'T is the DC bin of the row transforms.)
 template <int N, int R, int FL, int NL, bool IM, bool TILE>
 __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
                                             const uint32_t* __restrict__ tile, const TileGeom& g,
                                             const RowParam* __restrict__ rp, const float* __restrict__ trow,
                                             const float (&ku)[2][GatherCfg<N>::XV], const swift_image& im,
                                             bool border, const float (&tx)[GatherCfg<N>::XV], float o, int tid,
-                                            float& s1, float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
+                                            float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
@@ -222,7 +222,6 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
       const float top = fmaf(fx, i10 - i00, i00), bot = fmaf(fx, i11 - i01, i01);
       const float val = fmaf(fy, bot - top, top);
       const float at = ((val - o) * tx[c]) * ty;
-      s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
       sink(r, c, at);
@@ -240,21 +239,21 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
 // next output row.  One aligned read of a tile row gives the bytes of two
 // adjacent columns.  The offset enters the horizontal interpolation, h - o =
 // fx (b1 - b0) + (b0 - o), so the samples of a constant window are exactly 0.
-// Same outputs and sums as gather_rows.
+// p0: the sampling parameters of the thread's first row r0 (bx, by in tile
+// coordinates; fx, fy the same on every row).  Same outputs and sums as
+// gather_rows.
 template <int N, int R, int FL, int NL, bool IM>
 __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
                                                   const uint32_t* __restrict__ tile, const TileGeom& g,
-                                                  const RowParam* __restrict__ rp, const float* __restrict__ trow,
+                                                  const RowParam& p0, const float* __restrict__ trow,
                                                   const swift_image& im, bool border,
                                                   const float (&tx)[GatherCfg<N>::XV], float o, int tid,
-                                                  float& s1, float& s2, float (&s3c)[GatherCfg<N>::XV],
-                                                  bool& cl) {
+                                                  float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
   const int rowb = g.wt4 * 4;
   const int r0 = M::row0(tid);
   float* st = (float*)stage + (IM ? 1 : 0);
-  const RowParam p0 = rp[r0];
   const float fx = p0.fx, fy = p0.fy;  // the same for every row of the window
   // first column's byte in the tile row; the thread reads bytes ix .. ix + XV
   const int xs = p0.bx + (M::col(tid, 0) - N / 2);
@@ -296,7 +295,6 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
       const float val = fmaf(fy, h1[c] - h0[c], h0[c]);  // sample - o
       h0[c] = h1[c];
       const float at = (val * tx[c]) * ty;
-      s1 += at;
       s2 = fmaf(at, at, s2);
       s3c[c] = fmaf(at, ty, s3c[c]);
       sink(r, c, at);
@@ -388,13 +386,33 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
   RowAffine ra[2];
   TileGeom tg[2];
-  bool border[2];
+  bool border[2], trans[2];
+  RowParam pt[2];  // translation windows: the sampling parameters of the thread's first row
+  using M = FwdMap<N, R>;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET, TRW>(ra[m], im[m], y0);
+    // translation windows (identity linear part) take the constant-weight
+    // gather, and their tile geometry and row parameters are integer offsets
+    // from floor(cx + tx), floor(cy + ty)
+    trans[m] = ra[m].a11 == 1.0 && ra[m].a12 == 0.0 && ra[m].a21 == 0.0 && ra[m].a22 == 1.0;
+    if (trans[m]) {
+      const double X = fmin(fmax(ra[m].xc, -1e9), 1e9), Y = fmin(fmax(ra[m].yc, -1e9), 1e9);
+      const double fxd = floor(X), fyd = floor(Y);
+      const bool finite = fabs(X) < 1e8 && fabs(Y) < 1e8;
+      const int bx0 = (int)fxd, by0 = (int)fyd;
+      tg[m] = tile_geom_trans<N, R, BUDGET, TRW>(bx0, by0, finite, im[m], y0);
+      pt[m].bx = bx0 - (tg[m].use ? tg[m].xlo : 0);
+      pt[m].by = by0 + (y0 + M::row0(tid) - N / 2) - (tg[m].use ? tg[m].ylo : 0);
+      pt[m].fx = (float)(X - fxd);
+      pt[m].fy = (float)(Y - fyd);
+    } else {
+      tg[m] = tile_geom<N, R, BUDGET, TRW>(ra[m], im[m], y0);
+      pt[m].bx = pt[m].by = 0;
+      pt[m].fx = pt[m].fy = 0.0f;
+    }
     // could any sample read outside the image?  (one pixel of slack for rounding)
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
@@ -403,8 +421,9 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   uint4 bufA[TRW], bufB[TRW];
   if (tg[0].use) tile_fetch<tile_cw<N>()>(bufA, tg[0], im[0], tid);
   if (tg[1].use) tile_fetch<tile_cw<N>()>(bufB, tg[1], im[1], tid);
-  // per-row parameters (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
-  if (tid < 2 * R) {
+  // per-row parameters of the windows not gathered by translation from a tile
+  // (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
+  if (tid < 2 * R && !(tid >= R ? (trans[1] && tg[1].use) : (trans[0] && tg[0].use))) {
     // image chosen by value selects (an index into the per-image arrays would
     // send them to per-lane scratch memory)
     const bool mb = tid >= R;
@@ -423,10 +442,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     p.fx = (float)(X - bxd);
     p.fy = (float)(Y - byd);
     rparam[mb ? 1 : 0][r] = p;
-  } else if (tid >= 64 && tid < 64 + R) {
-    trow[tid - 64] = a.taper[y0 + tid - 64];
   }
-  using M = FwdMap<N, R>;
+  if (tid >= 64 && tid < 64 + R) trow[tid - 64] = a.taper[y0 + tid - 64];
   // the offsets: every block of the pair reads the same centre pixels
   const float off[2] = {centre_pixel(im[0], ra[0]), centre_pixel(im[1], ra[1])};
   float tx[XV], ku[2][2][XV];
@@ -447,9 +464,6 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   for (int c = 0; c < XV; ++c) s3c[0][c] = s3c[1][c] = 0.0f;
   float lateA[NL][XV], lateB[NL][XV];  // stage rows [FL, R) of each image
   bool clamped = false;
-  // translation windows (identity linear part) take the constant-weight gather
-  const bool trans[2] = {ra[0].a11 == 1.0 && ra[0].a12 == 0.0 && ra[0].a21 == 0.0 && ra[0].a22 == 1.0,
-                         ra[1].a11 == 1.0 && ra[1].a12 == 0.0 && ra[1].a21 == 0.0 && ra[1].a22 == 1.0};
 
   __syncthreads();  // row parameters visible
   // Tiled images first: their tile sits at the end of the stage (when FL <
@@ -459,30 +473,30 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
-      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], rparam[0], trow, im[0], border[0], tx,
-                                             off[0], tid, s[0], s[1], s3c[0], clamped);
+      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], pt[0], trow, im[0], border[0], tx,
+                                             off[0], tid, s[1], s3c[0], clamped);
     else
       gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx,
-                                             off[0], tid, s[0], s[1], s3c[0], clamped);
+                                             off[0], tid, s[1], s3c[0], clamped);
   }
   if (tg[1].use) {
     if (tg[0].use) __syncthreads();  // tile of A fully consumed
     tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
-      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], rparam[1], trow, im[1], border[1], tx,
-                                            off[1], tid, s[3], s[4], s3c[1], clamped);
+      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], pt[1], trow, im[1], border[1], tx,
+                                            off[1], tid, s[4], s3c[1], clamped);
     else
       gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx,
-                                            off[1], tid, s[3], s[4], s3c[1], clamped);
+                                            off[1], tid, s[4], s3c[1], clamped);
   }
   if (FL < R && (tg[0].use || tg[1].use) && !(tg[0].use && tg[1].use)) __syncthreads();  // tile consumed
   if (!tg[0].use)
     gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx,
-                                           off[0], tid, s[0], s[1], s3c[0], clamped);
+                                           off[0], tid, s[1], s3c[0], clamped);
   if (!tg[1].use)
     gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx,
-                                          off[1], tid, s[3], s[4], s3c[1], clamped);
+                                          off[1], tid, s[4], s3c[1], clamped);
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     s[2] = fmaf(tx[c], s3c[0][c], s[2]);
@@ -510,6 +524,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   // row FFTs in place: transform g of iteration it owns stage row g + it*G
   Twiddles<N> tw;
   tw_load<N>(tw, t, a.tw);
+  // the DC bins (lane t = 0 of each transform) sum a'T and b'T over the rows
+  float dcA = 0.0f, dcB = 0.0f;
 #pragma unroll 1
   for (int it = 0; it < R / G; ++it) {
     float2* row = stage + (g + it * G) * RS;
@@ -520,7 +536,11 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     fft_wave<N, false>(d, row, t, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) row[lidx(t + e * T)] = d[e];
+    dcA += t == 0 ? d[0].x : 0.0f;
+    dcB += t == 0 ? d[0].y : 0.0f;
   }
+  if constexpr (!PEARSON) s[0] = dcA;  // (the Pearson template sum comes from pearson_rows)
+  s[3] = dcB;
 
   // slice sums
   const int wv = tid >> 6, ln = tid & 63;

@@ -89,6 +89,31 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   return g;
 }
 
+// tile_geom for a translation window (identity linear part): the footprint of
+// rows [y0, y0 + R) is x in [xc - N/2, xc + N/2 - 1], y in [yc + y0 - N/2,
+// yc + y0 + R - 1 - N/2], so with bx0 = floor(xc), by0 = floor(yc) the
+// geometry is integer arithmetic (the same tile as tile_geom's).
+template <int N, int R, int BUDGET, int TRW>
+__device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finite, const swift_image& im, int y0) {
+  TileGeom g;
+  g.use = false;
+  g.xlo = g.ylo = 0;
+  g.wt4 = g.ht = 0;
+  if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || im.width < 16 || (im.width & 15) || (im.pitch & 15) ||
+      (((uintptr_t)im.data) & 15))
+    return g;
+  const int xl = bx0 - N / 2 - 1, xh = bx0 + N / 2 + 1;
+  const int yl = by0 + y0 - N / 2 - 1, yh = by0 + y0 + R + 1 - N / 2;
+  g.xlo = xl - (((xl % 16) + 16) % 16);
+  g.ylo = yl;
+  const int w16 = (xh - g.xlo + 16) / 16;
+  g.wt4 = 4 * w16;
+  g.ht = yh - yl + 1;
+  constexpr int CW = tile_cw<N>();
+  g.use = w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
+  return g;
+}
+
 // Tiles are fetched in two steps so all loads are in flight at once:
 // tile_fetch issues every global load of a thread into registers and nothing
 // consumes them until tile_store writes them to LDS.  Lane l of wave w takes

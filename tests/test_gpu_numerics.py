@@ -42,9 +42,10 @@ def _ident(cx, cy, tx=0.0, ty=0.0):
 
 
 def test_near_constant_window_is_scored(ctx):
-    """64^2 window of 200 with one pixel at 201 (uint8): scored, not
-    degenerate, record and surface as the oracle's; a constant window is
-    degenerate on both sides."""
+    """64^2 window of 200 with one pixel at 201 (uint8) matched against a
+    shifted window of the same image, at whole and at fractional offsets:
+    scored, not degenerate, record and surface as the oracle's; a constant
+    window is degenerate on both sides."""
     import paper_1612_04787_amd as sw
     print("case near-constant 64", flush=True)
     n = 64
@@ -54,10 +55,10 @@ def test_near_constant_window_is_scored(ctx):
     other = rng.integers(0, 256, (96, 96)).astype(np.uint8)
     const = np.full((96, 96), 200, np.uint8)
     tha = np.array([_ident(48, 48), _ident(48, 48, 0.25, -0.5), _ident(48, 48)], np.float32)
-    thb = np.array([_ident(48, 48, 1.0, 2.0), _ident(48, 48), _ident(48, 48)], np.float32)
+    thb = np.array([_ident(48, 48, 1.0, 2.0), _ident(48, 48, -2.0, 1.5), _ident(48, 48)], np.float32)
     imgs = [torch.from_numpy(img), torch.from_numpy(other), torch.from_numpy(const)]
     ia = torch.tensor([0, 0, 2], dtype=torch.int32)
-    ib = torch.tensor([0, 1, 1], dtype=torch.int32)
+    ib = torch.tensor([0, 0, 1], dtype=torch.int32)
     res = _run(ctx, imgs, n, tha, thb, sw.make_params(p=0.65), ia=ia, ib=ib)
     surf = res["surfaces"].view(3, n, n).cpu().numpy()
     srcs = [img, other, const]
