@@ -212,6 +212,24 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
                       swift_match* out, float* surfaces, void* saved, void* ws,
                       size_t ws_bytes, hipStream_t stream);
 
+/* swift_match_batch for callers that cannot allocate (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): no
+ * workspace argument, no surfaces, no saved state.  The workspace is a
+ * fixed device array of SWIFT_NOALLOC_SCRATCH_BYTES (128 MiB) that the library
+ * holds on every GPU it runs on until the process ends; the call creates,
+ * allocates and frees nothing (one launch sequence per size group on
+ * `stream`; kernel timing does not apply).  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other streams, other
+ * host threads, other contexts) race and must not be issued.  The kernels
+ * write every scratch byte they read within the call, so nothing needs
+ * clearing between calls.  Records are those of swift_match_batch.
+ * Errors: as swift_match_batch; SWIFT_E_WORKSPACE when the batch needs more
+ * than the array holds (swift_workspace_size tells how much it needs). */
+#define SWIFT_NOALLOC_SCRATCH_BYTES (128u << 20)
+int swift_match_batch_noalloc(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs,
+                              const swift_pairs* pairs, const swift_params* params,
+                              swift_match* out, hipStream_t stream);
+
 /* swift_match_batch as one hipGraph launch (ragged batching, not in the
  * paper): the first call with a given argument tuple (every pointer, n_imgs,
  * size_count, params) captures the whole batch, with all size groups as

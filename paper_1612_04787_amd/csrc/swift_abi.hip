@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -99,6 +100,8 @@ struct swift_ctx {
   hipEvent_t cjoin[SWIFT_NSIZES][2] = {};
   // tune cache: file path ("" for none) and this device's key in it
   std::string tune_path, tune_key;
+  // device address of this GPU's fixed scratch array (swift_match_batch_noalloc)
+  void* scratch = nullptr;
 };
 
 static constexpr size_t kMaxGraphs = 16;
@@ -318,6 +321,31 @@ static void fill_lane_twiddles(float2* host) {
 
 static bool valid_chunks(int c) { return c == 1 || c == 2 || c == 4 || c == 8; }
 
+// ---------------------------------------------------------------- fixed scratch
+// Workspace of swift_match_batch_noalloc: a file-scope device array, one per
+// GPU the library runs on, held until the process ends.  Host code uses its
+// device address, read once per device by swift_create.
+constexpr size_t kScratchBytes = SWIFT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// With `device` current: the device address of this GPU's scratch array.
+static hipError_t scratch_address(int device, void** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------- tune cache
 // A text file of plan lines "<device key> <n> <fwd variant> <inv variant>",
 // one per device and window size; '#' starts a comment.  The device key is
@@ -437,6 +465,12 @@ int swift_create(int device, const char* tune_cache_path, swift_ctx** out) {
     delete c;
     return hip_fail(e, "context streams/events");
   }
+  e = scratch_address(device, &c->scratch);
+  if (e != hipSuccess) {
+    ctx_release(c);
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  }
   if (tune_cache_path && tune_cache_path[0]) {
     c->tune_path = tune_cache_path;
     c->tune_key = device_key(device);
@@ -545,7 +579,7 @@ static int enqueue_chunks(swift_ctx* ctx, int i, const GroupLayout& g, const Mat
 // an event and joined back into it.
 static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
                          const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
-                         hipStream_t stream, bool concurrent, KernelTimer* kt) {
+                         hipStream_t stream, bool concurrent, KernelTimer* kt, bool allow_chunks = true) {
   const bool pearson = pearson_mode(params);
   const Layout L = make_layout(pairs, pearson);
   int groups = 0;
@@ -645,7 +679,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    const int nch = min((int)ctx->chunks[i], g.count);
+    const int nch = allow_chunks ? min((int)ctx->chunks[i], g.count) : 1;
     if (nch <= 1) {
       e = launch_match_group(g.n, a, ctx->alt_fwd[i] != 0, ctx->alt_inv[i] != 0, s, kt);
       if (e != hipSuccess) return hip_fail(e, "match launch");
@@ -674,6 +708,29 @@ int swift_match_batch(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, c
   if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
   return enqueue_match(ctx, imgs, n_imgs, pairs, params, out, surfaces, saved, ws, stream,
                        (params->flags & SWIFT_FLAG_CONCURRENT_SIZES) != 0, ctx->kt());
+}
+
+int swift_match_batch_noalloc(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
+                              const swift_params* params, swift_match* out, hipStream_t stream) {
+  if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
+  int rc = check_pairs(pairs);
+  if (rc) return rc;
+  rc = check_params(params);
+  if (rc) return rc;
+  if (pairs->n_pairs == 0) return ok();
+  if (!imgs || n_imgs <= 0) return fail(SWIFT_E_INVAL, "image table is empty");
+  if (!out) return fail(SWIFT_E_INVAL, "out is NULL");
+  const Layout L = make_layout(pairs, pearson_mode(params));
+  if (L.total > kScratchBytes)
+    return fail(SWIFT_E_WORKSPACE, "batch needs %zu bytes of workspace; the fixed scratch holds %zu", L.total,
+                kScratchBytes);
+  if (!ctx->scratch) return fail(SWIFT_E_HIP, "no scratch address for device %d", ctx->device);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(SWIFT_E_HIP, "cannot select device %d", ctx->device);
+  // one stream, one launch sequence per size group, no kernel timing: nothing
+  // is created or allocated
+  return enqueue_match(ctx, imgs, n_imgs, pairs, params, out, nullptr, nullptr, ctx->scratch, stream, false,
+                       nullptr, false);
 }
 
 int swift_match_graph(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,

@@ -69,6 +69,7 @@ def load_library(path: str = LIB_PATH):
     lib.swift_workspace_size.argtypes = [vp, C.POINTER(Pairs), C.POINTER(Params), C.POINTER(sz), C.POINTER(sz)]
     lib.swift_match_batch.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
     lib.swift_match_graph.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, sz, vp]
+    lib.swift_match_batch_noalloc.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp]
     lib.swift_plan.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.swift_autotune.argtypes = [vp, C.POINTER(i32), i32, i32, C.POINTER(C.c_float)]
     lib.swift_match_backward.argtypes = [vp, vp, i32, C.POINTER(Pairs), C.POINTER(Params), vp, vp, vp, vp, vp,
@@ -101,7 +102,8 @@ def load_library(path: str = LIB_PATH):
 
 def exported_symbols():
     """Every entry point include/swift.h declares."""
-    return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch", "swift_match_graph",
+    return ["swift_create", "swift_destroy", "swift_workspace_size", "swift_match_batch", "swift_match_batch_noalloc",
+            "swift_match_graph",
             "swift_match_backward", "swift_centroid_jacobian", "swift_project", "swift_project_side",
             "swift_blend_span", "swift_join_break", "swift_search_keep", "swift_search_next", "swift_pyramid",
             "swift_snr", "swift_refine_update", "swift_render", "swift_stack_windows", "swift_fit_sections",
