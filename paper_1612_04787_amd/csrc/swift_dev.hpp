@@ -64,6 +64,15 @@ __device__ __forceinline__ float wave_incl_scan_f32(float v) {
   return v;
 }
 
+// Layout of the row spectra exchanged between the forward row pass and the
+// column pass (and of the column pass's output for the inverse row pass):
+// tiles of 8 rows, Z[pair][y / 8][kx][y % 8].  A row block of 8 rows writes
+// one contiguous 8 N-element region; a column is read as runs of 8 elements.
+template <int N>
+__device__ __forceinline__ size_t ztile(int kx, int y) {
+  return (size_t)(y >> 3) * (8 * N) + (size_t)kx * 8 + (y & 7);
+}
+
 // Splits one bin of the packed spectrum z = a'T + i b'T into the normalised,
 // mean-free window spectra: zp = Z(k), zm = conj Z(-k), tk = tau(ky) tau(kx);
 // F_A = (zp + zm) / 2 - mA tk and F_B = (zp - zm) / (2i) - mB tk, each scaled

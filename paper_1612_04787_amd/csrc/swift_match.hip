@@ -9,7 +9,8 @@
 // z = a'T + i b'T (a' = a - offset, T the separable taper), so the forward 2-D
 // transform is a single complex FFT.  Five kernels per window size N:
 //   k_row_fwd   gather (bilinear affine, uint8/fp32 -> fp32), taper, row FFTs,
-//               per-slice sums; writes the row spectra transposed ([kx][y]).
+//               per-slice sums; writes the row spectra in tiles of 8 rows
+//               ([y/8][kx][y%8], see ztile), one contiguous region per block.
 //   k_pair_stats  reduces the sums to the weighted means and eps^2.
 //   k_col_pair  column FFTs of kx and N-kx, split into F_A and F_B, removes the
 //               weighted mean in the spectrum (F -= m * tau(ky) tau(kx)),
@@ -565,28 +566,24 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     a.rowpart[(size_t)pair * NSLICE + slice] = rp;
   }
 
-  // transposed store: Z[pair][kx][y0 + r]
-  if constexpr (256 % (16 * R) == 0) {
-    // thread: row r = tid % R, columns kx0 + j KS.  KS is a multiple of 16, so
-    // the LDS index advances by the constant lidx(KS) and every read takes an
-    // immediate offset; the global address is the pair's base (uniform) plus
-    // a 32-bit byte offset.
-    constexpr int KS = 256 / R;
-    const int r = tid % R, kx0 = tid / R;
-    const float2* sp = stage + r * RS + lidx(kx0);
-    char* zb = reinterpret_cast<char*>(a.Z + (size_t)pair * N * N);
-    uint32_t off = (uint32_t)(kx0 * N + y0 + r) * (uint32_t)sizeof(float2);
-#pragma unroll
-    for (int j = 0; j < N / KS; ++j) {
-      *reinterpret_cast<float2*>(zb + off) = sp[j * lidx(KS)];
-      off += (uint32_t)(KS * N * sizeof(float2));
-    }
-  } else {
-    float2* Zp = a.Z + (size_t)pair * N * N;
+  // store in the tiled layout: Z[pair][y / 8][kx][y % 8].  A thread writes
+  // the float4 of rows (r, r + 1) at bin kx; with R >= 8 the block's region is
+  // contiguous and consecutive threads write consecutive 16-byte chunks.
+  {
+    float4* zb = reinterpret_cast<float4*>(a.Z + (size_t)pair * N * N);
 #pragma unroll 4
-    for (int idx = tid; idx < R * N; idx += 256) {
-      const int r = idx % R, kx = idx / R;
-      Zp[(size_t)kx * N + y0 + r] = stage[r * RS + lidx(kx)];
+    for (int q = tid; q < N * R / 2; q += 256) {
+      int kx, r;
+      if constexpr (R >= 8) {
+        const int yt = q / (4 * N), rem = q % (4 * N);
+        kx = rem >> 2;
+        r = 8 * yt + 2 * (rem & 3);
+      } else {
+        kx = q / (R / 2);
+        r = 2 * (q % (R / 2));
+      }
+      const float2 v0 = stage[r * RS + lidx(kx)], v1 = stage[(r + 1) * RS + lidx(kx)];
+      zb[ztile<N>(kx, y0 + r) >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
     }
   }
 }
@@ -673,16 +670,18 @@ __device__ __forceinline__ void col_sumsq(const MatchArgs& a, int pair, int w, i
   if (t == 0) a.colsq[(size_t)pair * (N / 2 + 1) + w] = (double)tot * ((w == 0 || w == N / 2) ? 1.0 : 2.0);
 }
 
+// Column w of the inverse column transform, back into the tiled layout (with
+// a search radius only the rows the inverse row blocks read).
 template <int N, int T, int E, bool PRUNE>
-__device__ __forceinline__ void store_column(const MatchArgs& a, float2* dst, int t, const float2 (&v)[E]) {
+__device__ __forceinline__ void store_column(const MatchArgs& a, float2* Zp, int w, int t, const float2 (&v)[E]) {
   if (!PRUNE || a.zlo >= N) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) dst[t + e * T] = v[e];
+    for (int e = 0; e < E; ++e) Zp[ztile<N>(w, t + e * T)] = v[e];
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int y = t + e * T;
-      if (y < a.zlo || y >= a.zhi) dst[y] = v[e];
+      if (y < a.zlo || y >= a.zhi) Zp[ztile<N>(w, y)] = v[e];
     }
   }
 }
@@ -737,9 +736,8 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
 
   float2 tau[E];
   if (valid) {
-    const float2* src = Zp + (size_t)col * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
+    for (int e = 0; e < E; ++e) v[e] = Zp[ztile<N>(col, t + e * T)];
 #pragma unroll
     for (int e = 0; e < E; ++e) tau[e] = a.tau[t + e * T];
     fft_wave<N, false>(v, slot, t, tw);
@@ -771,7 +769,7 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
       col_sumsq<N, T>(a, pair, w, t, csq);
     }
     fft_wave<N, true>(v, slot, t, tw);
-    store_column<N, T, E, PRUNE>(a, Zp + (size_t)w * N, t, v);
+    store_column<N, T, E, PRUNE>(a, Zp, w, t, v);
   }
 }
 
@@ -798,19 +796,15 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   tw_load<N>(tw, t, a.tw);
 
   float2 v[E], u[E];
-  {
-    const float2* src = Zp + (size_t)w * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = src[t + e * T];
-  }
+  for (int e = 0; e < E; ++e) v[e] = Zp[ztile<N>(w, t + e * T)];
   fft_wave<N, false>(v, slot, t, tw);
   wave_lds_sync();
   if (wm != w) {
     // the mirror column is loaded only now, so it is not live during the
     // first transform
-    const float2* srm = Zp + (size_t)wm * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = srm[t + e * T];
+    for (int e = 0; e < E; ++e) u[e] = Zp[ztile<N>(wm, t + e * T)];
     fft_wave<N, false>(u, slot, t, tw);
     wave_lds_sync();
   } else {
@@ -846,7 +840,7 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   }
   wave_lds_sync();  // every lane has read its mirror values
   fft_wave<N, true>(v, slot, t, tw);
-  store_column<N, T, E, PRUNE>(a, Zp + (size_t)w * N, t, v);
+  store_column<N, T, E, PRUNE>(a, Zp, w, t, v);
 }
 
 // ---------------------------------------------------------------- Pearson patch energies
@@ -938,15 +932,17 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
     static_assert(256 % R2 == 0, "rows per block divide the block");
     constexpr int CPL = 256 / R2, LD = (NH + CPL - 1) / CPL;
     const int r = tid % R2, c0 = tid / R2;
+    // tiled layout: column c of row y at ztile(c, y), so the k-th load is a
+    // constant 8 CPL elements past the first
     const char* zb = reinterpret_cast<const char*>(Zp);
-    const uint32_t off0 = (uint32_t)(c0 * N + y0 + r) * (uint32_t)sizeof(float2);
+    const uint32_t off0 = (uint32_t)ztile<N>(c0, y0 + r) * (uint32_t)sizeof(float2);
     float2 buf[LD];
 #pragma unroll
     for (int k = 0; k < LD - 1; ++k)
-      buf[k] = *reinterpret_cast<const float2*>(zb + off0 + (uint32_t)(k * CPL * N * sizeof(float2)));
+      buf[k] = *reinterpret_cast<const float2*>(zb + off0 + (uint32_t)(k * CPL * 8 * sizeof(float2)));
     {
       const int cl = min(c0 + (LD - 1) * CPL, NH - 1);
-      buf[LD - 1] = Zp[(size_t)cl * N + y0 + r];
+      buf[LD - 1] = Zp[ztile<N>(cl, y0 + r)];
     }
     float2* sp = stage + r * RS2 + c0;
 #pragma unroll
@@ -1148,8 +1144,8 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
       for (int e = 0; e < E; ++e) {
         const int k = ln + e * T;
         const int kk = k <= N / 2 ? k : N - k;
-        float2 g1 = Zp[(size_t)kk * N + ra];
-        float2 g2 = rb >= 0 ? Zp[(size_t)kk * N + rb] : make_float2(0.f, 0.f);
+        float2 g1 = Zp[ztile<N>(kk, ra)];
+        float2 g2 = rb >= 0 ? Zp[ztile<N>(kk, rb)] : make_float2(0.f, 0.f);
         if (k > N / 2) {
           g1 = cconj(g1);
           g2 = cconj(g2);
