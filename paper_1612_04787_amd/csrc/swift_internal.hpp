@@ -144,13 +144,13 @@ constexpr int kDpart = 6;     // dJ0/de2, dJ1/de2, hxx, hyy, hxy, unused
 // rows).  FWD2 / INV2 (with TILE2, TRW2) are the alternative row counts
 // swift_autotune can choose; the defaults are FWD / INV.
 template <int N> struct RowsCfg;
-template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4096,  TRW = 2,
-                                   FWD2 = 32, INV2 = 32, TILE2 = 4096, TRW2 = 2; };
+template <> struct RowsCfg<64>   { static constexpr int FWD = 32, INV = 64, TILE = 4608,  TRW = 2,
+                                   FWD2 = 32, INV2 = 32, TILE2 = 4608, TRW2 = 2; };
 template <> struct RowsCfg<128>  { static constexpr int FWD = 16, INV = 32, TILE = 6144,  TRW = 2,
-                                   FWD2 = 32, INV2 = 64, TILE2 = 6720, TRW2 = 3; };
-template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9216,  TRW = 4,
+                                   FWD2 = 32, INV2 = 64, TILE2 = 8960, TRW2 = 3; };
+template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE = 9728,  TRW = 4,
                                    FWD2 = 8,  INV2 = 32, TILE2 = 5632, TRW2 = 3; };
-template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 10240, TRW = 5,
+template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 11264, TRW = 5,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 8576, TRW2 = 4; };
 template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 0,    TRW2 = 1; };

@@ -174,7 +174,7 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
                                             float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
-  const int rowb = g.wt4 * 4;
+  const int rowb = g.ts * 4;
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
   const int r0 = M::row0(tid);
   float* st = (float*)stage + (IM ? 1 : 0);
@@ -246,30 +246,30 @@ __device__ __forceinline__ void gather_rows(float2* __restrict__ stage, float (&
 template <int N, int R, int FL, int NL, bool IM>
 __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, float (&late)[NL][GatherCfg<N>::XV],
                                                   const uint32_t* __restrict__ tile, const TileGeom& g,
-                                                  const RowParam& p0, const float* __restrict__ trow,
+                                                  const RowParam& p0, const float* __restrict__ taper, int y0,
                                                   const swift_image& im, bool border,
                                                   const float (&tx)[GatherCfg<N>::XV], float o, int tid,
                                                   float& s2, float (&s3c)[GatherCfg<N>::XV], bool& cl) {
   using M = FwdMap<N, R>;
   constexpr int XV = M::XV, ITER = M::ITER, RS = fwd_stride<N, R>();
-  const int rowb = g.wt4 * 4;
+  constexpr int TS = 4 * tile_cw<N>();  // dwords between tile rows (tile_geom_trans)
   const int r0 = M::row0(tid);
   float* st = (float*)stage + (IM ? 1 : 0);
   const float fx = p0.fx, fy = p0.fy;  // the same for every row of the window
-  // first column's byte in the tile row; the thread reads bytes ix .. ix + XV
-  const int xs = p0.bx + (M::col(tid, 0) - N / 2);
-  const int ix = min(max(xs, 0), rowb - 1 - XV);
-  // samples span columns xs .. xs + XV and rows p0.by .. p0.by + ITER (tile
+  // first column's byte in the tile row; the thread reads bytes ix .. ix + XV.
+  // tile_geom_trans leaves a pixel of margin on every side, so rows p0.by ..
+  // p0.by + ITER and these bytes lie inside the tile: no clamping
+  const int ix = p0.bx + (M::col(tid, 0) - N / 2);
+  // samples span columns ix .. ix + XV and rows p0.by .. p0.by + ITER (tile
   // coordinates), so one range test gives the clamp flag of all of them
   if (border)
-    cl |= (xs + g.xlo < 0) | (xs + XV - 1 + g.xlo > im.width - 2) | (p0.by + g.ylo < 0) |
+    cl |= (ix + g.xlo < 0) | (ix + XV - 1 + g.xlo > im.width - 2) | (p0.by + g.ylo < 0) |
           (p0.by + ITER - 1 + g.ylo > im.height - 2);
-  // rows start on dword boundaries (rowb is a multiple of 16): the row part
-  // of the dword index is uniform, the lane part and the byte shift fixed
-  const int ixd = ix >> 2;
   const uint32_t sh = (uint32_t)(ix & 3);
-  auto hrow = [&](int yy, float (&h)[XV]) {
-    const uint32_t* w = tile + min(max(yy, 0), g.ht - 1) * g.wt4 + ixd;
+  // the thread's bytes of every row sit a constant TS dwords apart
+  const uint32_t* wb = tile + p0.by * TS + (ix >> 2);
+  auto hrow = [&](int i, float (&h)[XV]) {
+    const uint32_t* w = wb + i * TS;
 #pragma unroll
     for (int c = 0; c < XV; c += 2) {
       // bytes ix + c .. ix + c + 3
@@ -284,13 +284,13 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
     }
   };
   float h0[XV];
-  hrow(p0.by, h0);
+  hrow(0, h0);
   constexpr int FLI = FL < ITER ? FL : ITER;
   auto row = [&](int i, auto sink) {
-    const int r = r0 + i, y0 = p0.by + i;
+    const int r = r0 + i;
     float h1[XV];
-    hrow(y0 + 1, h1);
-    const float ty = trow[r];
+    hrow(i + 1, h1);
+    const float ty = taper[y0 + r];
 #pragma unroll
     for (int c = 0; c < XV; ++c) {
       const float val = fmaf(fy, h1[c] - h0[c], h0[c]);  // sample - o
@@ -301,7 +301,7 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
       sink(r, c, at);
     }
   };
-#pragma unroll 4
+#pragma unroll
   for (int i = 0; i < FLI; ++i) row(i, [&](int r, int c, float at) { st[2 * (r * RS + lidx(M::col(tid, c)))] = at; });
 #pragma unroll
   for (int i = FLI; i < ITER; ++i) row(i, [&](int r, int c, float at) { late[r - FL][c] = at; });
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
     __syncthreads();
     if (trans[0])
-      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], pt[0], trow, im[0], border[0], tx,
+      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], pt[0], a.taper, y0, im[0], border[0], tx,
                                              off[0], tid, s[1], s3c[0], clamped);
     else
       gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx,
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
     __syncthreads();
     if (trans[1])
-      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], pt[1], trow, im[1], border[1], tx,
+      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], pt[1], a.taper, y0, im[1], border[1], tx,
                                             off[1], tid, s[4], s3c[1], clamped);
     else
       gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx,

@@ -13,7 +13,8 @@ namespace swift {
 // 64 / CW tile rows of CW chunks each (CW = tile_cw<N>, a power of two).
 struct TileGeom {
   int xlo, ylo;   // tile origin in image pixels (xlo a multiple of 16)
-  int wt4, ht;    // dwords per tile row (a multiple of 4), tile rows
+  int wt4, ht;    // dwords of footprint per tile row (a multiple of 4), tile rows
+  int ts;         // dwords between tile rows in LDS (wt4, or tile_cw * 4 for translation windows)
   bool use;       // the footprint fits the budget and the image allows 16-byte loads
 };
 
@@ -71,7 +72,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   const bool finite = fabs(xmin) < 1e8 && fabs(xmax) < 1e8 && fabs(ymin) < 1e8 && fabs(ymax) < 1e8;
   g.use = false;
   g.xlo = g.ylo = 0;
-  g.wt4 = g.ht = 0;
+  g.wt4 = g.ht = g.ts = 0;
   // every 16-byte chunk is either inside the image or wholly outside it
   if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || im.width < 16 || (im.width & 15) || (im.pitch & 15) ||
       (((uintptr_t)im.data) & 15))
@@ -83,6 +84,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.ylo = yl;
   const int w16 = (xh - g.xlo + 16) / 16;
   g.wt4 = 4 * w16;
+  g.ts = g.wt4;
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
   g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
@@ -92,13 +94,15 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
 // tile_geom for a translation window (identity linear part): the footprint of
 // rows [y0, y0 + R) is x in [xc - N/2, xc + N/2 - 1], y in [yc + y0 - N/2,
 // yc + y0 + R - 1 - N/2], so with bx0 = floor(xc), by0 = floor(yc) the
-// geometry is integer arithmetic (the same tile as tile_geom's).
+// geometry is integer arithmetic (the same footprint as tile_geom's).  Its
+// LDS rows are a fixed tile_cw<N> chunks apart, so the gather addresses
+// every row at a constant offset.
 template <int N, int R, int BUDGET, int TRW>
 __device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finite, const swift_image& im, int y0) {
   TileGeom g;
   g.use = false;
   g.xlo = g.ylo = 0;
-  g.wt4 = g.ht = 0;
+  g.wt4 = g.ht = g.ts = 0;
   if (BUDGET == 0 || !finite || im.dtype != SWIFT_U8 || im.width < 16 || (im.width & 15) || (im.pitch & 15) ||
       (((uintptr_t)im.data) & 15))
     return g;
@@ -110,7 +114,8 @@ __device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finit
   g.wt4 = 4 * w16;
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
-  g.use = w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
+  g.ts = 4 * CW;
+  g.use = CW * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
   return g;
 }
 
@@ -151,13 +156,13 @@ __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const ui
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
     const int ty = (4 * j + wv) * RPL + sr;
-    if (ty < g.ht && 4 * c < g.wt4) {
+    if (ty < g.ht && 4 * c < g.ts) {
       uint4 v = buf[j];
       if (left | right) {
         const uint32_t sp = (left ? (v.x & 255u) : (v.w >> 24)) * 0x01010101u;
         v = make_uint4(sp, sp, sp, sp);
       }
-      *reinterpret_cast<uint4*>(tile + ty * g.wt4 + 4 * c) = v;
+      *reinterpret_cast<uint4*>(tile + ty * g.ts + 4 * c) = v;
     }
   }
 }
