@@ -502,6 +502,12 @@ int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a
  *  - Row-count variants: two row counts per block for the forward row pass
  *    and two for the inverse row pass (variant 0 = the default, 1 = the
  *    alternative).
+ *  - Forward variant 2, for n <= 128 (whitened match; a Pearson batch keeps
+ *    the five-kernel path): the whole pair in one workgroup, its packed
+ *    spectrum resident in LDS from the gather to the record, so no spectrum
+ *    crosses device memory (the inverse variant is then unused and the rows
+ *    per block reported are n).  A new context uses it at n = 64 and the
+ *    five-kernel path (variants 0, 0, one chunk) at the other sizes.
  *  - Chunks (1, 2, 4, 8): a size group of P pairs is split into that many
  *    chunks of consecutive pairs whose kernel sequences alternate between two
  *    streams of the context (forked from and joined back into the call's
@@ -521,8 +527,9 @@ int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_varia
  * device buffers, so it is a set-up call, not one for a capture or a serving
  * loop.  times_ms: host [n_sizes][SWIFT_TUNE_SLOTS] or NULL, receives the mean
  * time per batch of: slots 0..3 the row variants (fwd + 2 inv) in one chunk,
- * slots 4..6 the fastest of those in 2, 4 and 8 chunks; -1 where a variant
- * equals another or does not apply.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
+ * slots 4..6 the fastest of those in 2, 4 and 8 chunks, slot 7 the
+ * one-workgroup kernel (n <= 128); -1 where a variant equals another or does
+ * not apply.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
 #define SWIFT_TUNE_SLOTS 8
 int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_t pairs_per_size,
                    float* times_ms);

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libswift.so")
-SOURCES = ["swift_match.hip", "swift_adjoint.hip", "swift_misc.hip", "swift_stack.hip", "swift_abi.hip"]
+SOURCES = ["swift_match.hip", "swift_fused.hip", "swift_adjoint.hip", "swift_misc.hip", "swift_stack.hip", "swift_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.

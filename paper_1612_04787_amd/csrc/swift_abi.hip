@@ -89,7 +89,9 @@ struct swift_ctx {
   std::map<std::string, GraphEntry> graphs;
   uint64_t tick = 0;
   // row-count variant per window size (swift_plan / swift_autotune)
-  uint8_t alt_fwd[SWIFT_NSIZES] = {};
+  // default plan: the one-workgroup kernel at n = 64 (faster there on MI355X),
+  // the five-kernel path elsewhere
+  uint8_t alt_fwd[SWIFT_NSIZES] = {kFusedVariant, 0, 0, 0, 0};
   uint8_t alt_inv[SWIFT_NSIZES] = {};
   // chunks per size group: > 1 splits a group into chunks whose kernel
   // sequences run on two streams, so one chunk's row pass overlaps another's
@@ -372,7 +374,8 @@ static void tune_cache_load(swift_ctx* c) {
     const int got = sscanf(line, "%319s %d %d %d %d", key, &n, &vf, &vi, &ch);
     if (got < 4) continue;
     if (got == 4) ch = 1;
-    if (c->tune_key != key || vf < 0 || vf > 1 || vi < 0 || vi > 1 || !valid_chunks(ch)) continue;
+    const int vf_max = n <= kFusedMaxN ? kFusedVariant : 1;
+    if (c->tune_key != key || vf < 0 || vf > vf_max || vi < 0 || vi > 1 || !valid_chunks(ch)) continue;
     for (int i = 0; i < SWIFT_NSIZES; ++i)
       if (kSizes[i] == n) {
         c->alt_fwd[i] = (uint8_t)vf;
@@ -540,7 +543,8 @@ static int enqueue_chunks(swift_ctx* ctx, int i, const GroupLayout& g, const Mat
   for (int j = 0; j < 2 && e == hipSuccess; ++j) e = hipStreamWaitEvent(ctx->cs[i][j], ctx->cfork[i], 0);
   if (e != hipSuccess) return hip_fail(e, "chunk fork");
   const size_t n = (size_t)g.n, P = (size_t)g.count;
-  const bool af = ctx->alt_fwd[i] != 0, ai = ctx->alt_inv[i] != 0;
+  const int af = ctx->alt_fwd[i];
+  const bool ai = ctx->alt_inv[i] != 0;
   for (int c = 0; c < nch; ++c) {
     const size_t p0 = P * c / nch, p1 = P * (c + 1) / nch;
     MatchArgs b = a;
@@ -649,7 +653,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.L = (int)floor((double)params->taper_frac * g.n / 2.0 + 0.5);
     a.snr_exclude_r = pearson ? 0 : params->snr_exclude_r;
     a.npairs = g.count;
-    a.nsl_fwd = fwd_blocks_n(g.n, ctx->alt_fwd[i] != 0);
+    a.nsl_fwd = fwd_blocks_n(g.n, ctx->alt_fwd[i] == 1);
     a.nsl_inv = inv_blocks_n(g.n, ctx->alt_inv[i] != 0);
     a.colsq = (double*)(base + g.colsq);
     a.max_shift = 0;
@@ -681,7 +685,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
     const int nch = allow_chunks ? min((int)ctx->chunks[i], g.count) : 1;
     if (nch <= 1) {
-      e = launch_match_group(g.n, a, ctx->alt_fwd[i] != 0, ctx->alt_inv[i] != 0, s, kt);
+      e = launch_match_group(g.n, a, ctx->alt_fwd[i], ctx->alt_inv[i] != 0, s, kt);
       if (e != hipSuccess) return hip_fail(e, "match launch");
     } else {
       const int rc = enqueue_chunks(ctx, i, g, a, nch, s, kt);
@@ -1171,13 +1175,18 @@ int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_varia
   if (!ctx) return fail(SWIFT_E_INVAL, "ctx is NULL");
   const int i = size_index(n);
   if (i < 0) return fail(SWIFT_E_INVAL, "n must be one of 64, 128, 256, 512, 1024 (got %d)", n);
-  if (fwd_variant > 1 || inv_variant > 1) return fail(SWIFT_E_INVAL, "variants are 0, 1 or -1 (keep)");
+  if (fwd_variant > 1 || inv_variant > 1) {
+    if (!(fwd_variant == kFusedVariant && n <= kFusedMaxN && inv_variant <= 1))
+      return fail(SWIFT_E_INVAL, "variants are 0, 1 or -1 (keep), and forward variant 2 (one workgroup per pair) "
+                                 "for n <= %d", kFusedMaxN);
+  }
   if (chunks >= 0 && !valid_chunks(chunks)) return fail(SWIFT_E_INVAL, "chunks are 1, 2, 4, 8 or -1 (keep)");
   if (fwd_variant >= 0) ctx->alt_fwd[i] = (uint8_t)fwd_variant;
   if (inv_variant >= 0) ctx->alt_inv[i] = (uint8_t)inv_variant;
   if (chunks >= 0) ctx->chunks[i] = (uint8_t)chunks;
-  if (fwd_rows) *fwd_rows = n / fwd_blocks_n(n, ctx->alt_fwd[i] != 0);
-  if (inv_rows) *inv_rows = n / inv_blocks_n(n, ctx->alt_inv[i] != 0);
+  const bool fused = ctx->alt_fwd[i] == kFusedVariant;
+  if (fwd_rows) *fwd_rows = fused ? n : n / fwd_blocks_n(n, ctx->alt_fwd[i] == 1);
+  if (inv_rows) *inv_rows = fused ? n : n / inv_blocks_n(n, ctx->alt_inv[i] != 0);
   if (chunks_out) *chunks_out = ctx->chunks[i];
   return ok();
 }
@@ -1282,16 +1291,20 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
     const uint8_t keep_f = ctx->alt_fwd[si], keep_i = ctx->alt_inv[si], keep_c = ctx->chunks[si];
     int rc = SWIFT_OK;
     // slots 0..3: the row variants in one chunk; 4..6: the best of them in
-    // 2, 4, 8 chunks on two streams
+    // 2, 4, 8 chunks on two streams; 7 (n <= kFusedMaxN): one workgroup per
+    // pair.  vv: bit 0 the alternative forward rows, bit 1 the alternative
+    // inverse rows, 4 the one-workgroup kernel.
     for (int v = 0; v < kTuneSlots && rc == SWIFT_OK; ++v) {
-      const int vv = v < 4 ? v : best_v;
-      const int ch = v < 4 ? 1 : (v == 4 ? 2 : v == 5 ? 4 : v == 6 ? 8 : 0);
-      const bool af = (vv & 1) != 0, ai = (vv & 2) != 0;
+      const int vv = v < 4 ? v : v == 7 ? 4 : best_v;
+      const int ch = v < 4 || v == 7 ? 1 : (v == 4 ? 2 : v == 5 ? 4 : 8);
+      const int af = vv == 4 ? kFusedVariant : (vv & 1);
+      const bool ai = vv != 4 && (vv & 2) != 0;
       float ms = -1.0f;
-      const bool distinct = ch > 0 && ch <= P && (!af || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
-                            (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false));
+      const bool distinct = ch <= P && (af != 1 || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
+                            (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false)) &&
+                            (vv != 4 || n <= kFusedMaxN) && !(v >= 4 && v < 7 && best_v == 4);
       if (distinct) {
-        ctx->alt_fwd[si] = af;
+        ctx->alt_fwd[si] = (uint8_t)af;
         ctx->alt_inv[si] = ai;
         ctx->chunks[si] = (uint8_t)ch;
         rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
@@ -1320,8 +1333,8 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
       ctx->chunks[si] = keep_c;
       return rc;
     }
-    ctx->alt_fwd[si] = (best_v & 1) != 0;
-    ctx->alt_inv[si] = (best_v & 2) != 0;
+    ctx->alt_fwd[si] = best_v == 4 ? kFusedVariant : (best_v & 1);
+    ctx->alt_inv[si] = best_v != 4 && (best_v & 2) != 0;
     ctx->chunks[si] = (uint8_t)best_c;
     tuned[si] = true;
   }

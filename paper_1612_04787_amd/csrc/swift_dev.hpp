@@ -85,6 +85,76 @@ __device__ __forceinline__ void split_bin(float2 zp, float2 zm, float2 tk, const
   fb = csub(make_float2(hb * dd.y, -hb * dd.x), cscale(tk, ps.mB * ps.sB));
 }
 
+// Pair statistics from the window sums of the whole pair (s as in RowPart,
+// summed over the row slices): taper-weighted means m = sum a'T / (sum T)^2,
+// energies ||w||^2 = sum (a'T)^2 - 2 m sum a'T^2 + m^2 (sum T^2)^2, the
+// degeneracy test and the whitening scales.
+__device__ inline PairStat make_pair_stat(const double (&s)[6], bool clamped, const TaperInfo& ti, float oA, float oB,
+                                          int n, bool pearson, float p) {
+  const double sT = ti.sum_t * ti.sum_t, sT2 = ti.sum_t2 * ti.sum_t2;
+  const double mA = s[0] / sT, mB = s[3] / sT;
+  const double wA = s[1] - 2.0 * mA * s[2] + mA * mA * sT2;
+  const double wB = s[4] - 2.0 * mB * s[5] + mB * mB * sT2;
+  PairStat ps;
+  ps.mA = (float)mA;
+  ps.mB = (float)mB;
+  ps.oA = oA;
+  ps.oB = oB;
+  ps.swA = (float)fmax(wA, 0.0);
+  ps.swB = (float)fmax(wB, 0.0);
+  ps.pad[0] = ps.pad[1] = 0;
+  // degenerate: a window's weighted variance is at most kDegenerateRel of
+  // its energy about the offset (samples equal up to rounding; a constant
+  // window has all sums exactly 0)
+  const bool degA = !(wA > kDegenerateRel * s[1]), degB = !(wB > kDegenerateRel * s[4]);
+  ps.flags = (clamped ? 4 : 0) | ((degA || degB) ? 1 : 0);
+  const double inv_m = 1.0 / ((double)n * (double)n);
+  if (pearson) {
+    // the template carries the mean (its spectrum has no DC), so window B is
+    // used as gathered; only a constant template is degenerate (a constant
+    // patch of B gets a zero coefficient per placement).  No whitening (p =
+    // 0): the spectra are used unscaled.
+    ps.mB = 0.0f;
+    ps.flags = (clamped ? 4 : 0) | (degA ? 1 : 0);
+  }
+  if (ps.flags & 1) {
+    ps.sA = ps.sB = 0.0f;
+    ps.kw = 0.0f;
+  } else if (pearson) {
+    ps.sA = ps.sB = 1.0f;
+    ps.kw = (float)inv_m;
+  } else {
+    ps.sA = (float)(1.0 / sqrt(wA));
+    ps.sB = (float)(1.0 / sqrt(wB));
+    ps.kw = (float)(exp(0.5 * (1.0 - (double)p) * (log(wA) + log(wB))) * inv_m);
+  }
+  return ps;
+}
+
+// Whitening of one bin.
+// zp = Z(k), zm = conj Z(-k) of the packed spectrum z = a'T + i b'T, tk =
+// tau(ky) tau(kx).  Splits F_A = (zp + zm) / 2, F_B = (zp - zm) / (2i),
+// removes the weighted means (F -= m tk), and scales both by 1 / ||w||, so the
+// normalised cross power X^ = conj(F_A^) F_B^ has |X^| <= N^2 whatever the
+// input scale.  With X = X^ ||w_A|| ||w_B|| and eps = eps_rel ||w_A|| ||w_B||,
+//   C = X (|X|^2 + eps^2)^(-p/2) / N^2 = X^ (|X^|^2 + eps_rel^2)^(-p/2) kw,
+// kw = (||w_A|| ||w_B||)^(1-p) / N^2.  The DC bin (and a degenerate pair) gives 0.
+__device__ __forceinline__ float2 whiten_bin(float2 zp, float2 zm, float2 tk, const PairStat& ps, float p,
+                                             float eps_rel, bool dc) {
+  float2 fa, fb;
+  split_bin(zp, zm, tk, ps, fa, fb);
+  const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
+  const float d = fmaf(X.x, X.x, fmaf(X.y, X.y, eps_rel * eps_rel));
+  float gs;
+  if (p == 0.0f) gs = 1.0f;
+  else if (!(d > 0.0f)) gs = 0.0f;
+  else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
+  else gs = __builtin_amdgcn_exp2f(-0.5f * p * __builtin_amdgcn_logf(d));
+  gs *= ps.kw;
+  if (dc) gs = 0.0f;
+  return cscale(X, gs);
+}
+
 struct Top2 {
   float m1;
   int i1;

@@ -201,10 +201,31 @@ __device__ __forceinline__ void tw_load(Twiddles<N>& tw, int t, const float2* __
 }
 
 // ---------------------------------------------------------------- Stockham pass
+// Where a transform's scratch element i lives: lidx(i) of a private row (the
+// default), or row col_swz(i) of a column of a larger LDS array whose rows
+// are `stride` complex values apart.  col_swz permutes the rows within the
+// column (XOR of the low bits with a function of the high bits) so that the
+// T lanes of an FFT group hit T different banks in every exchange of the
+// Stockham passes, including the first pass's writes 8 elements apart, which
+// a plain strided column sends to one or two banks.
+template <int N> __device__ __forceinline__ int col_swz(int i);
+template <> __device__ __forceinline__ int col_swz<64>(int i) { return i ^ ((i >> 3) & 7); }
+template <> __device__ __forceinline__ int col_swz<128>(int i) { return i ^ (((i >> 4) + ((i >> 6) << 3)) & 15); }
+
+struct PaddedIdx {
+  __device__ __forceinline__ int operator()(int i) const { return lidx(i); }
+};
+template <int N>
+struct ColumnIdx {
+  int stride;
+  __device__ __forceinline__ int operator()(int i) const { return col_swz<N>(i) * stride; }
+};
+
 // REG: twiddles from registers (twr), otherwise loaded from the table per pass.
-template <int N, bool INV, int P, int NS, bool REG>
+template <int N, bool INV, int P, int NS, bool REG, class IX = PaddedIdx>
 __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
-                                         const Twiddles<N>* __restrict__ twr, const float2* __restrict__ tab) {
+                                         const Twiddles<N>* __restrict__ twr, const float2* __restrict__ tab,
+                                         IX ix = IX()) {
   using C = FftCfg<N>;
   constexpr int R = C::rad(P), E = C::E, T = C::T, B = E / R;
   constexpr bool LAST = (P == C::NP - 1);
@@ -233,15 +254,15 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __re
     } else {
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[lidx(base + q * NS)] = u[q];
+      for (int q = 0; q < R; ++q) lds[ix(base + q * NS)] = u[q];
     }
   }
   if constexpr (!LAST) {
     wave_lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds[lidx(t + e * T)];
+    for (int e = 0; e < E; ++e) v[e] = lds[ix(t + e * T)];
     wave_lds_sync();
-    fft_pass<N, INV, P + 1, NS * R, REG>(v, lds, t, twr, tab);
+    fft_pass<N, INV, P + 1, NS * R, REG, IX>(v, lds, t, twr, tab, ix);
   }
 }
 
@@ -252,6 +273,20 @@ template <int N, bool INV>
 __device__ __forceinline__ void fft_wave(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
                                          const Twiddles<N>& tw) {
   fft_pass<N, INV, 0, 1, true>(v, lds, t, &tw, nullptr);
+}
+
+// Full transform with register twiddles whose scratch is a column of a
+// larger LDS array: element i of the scratch at lds[col_swz<N>(i) * stride]
+// (N = 64, 128).
+// The lane index goes through an empty asm statement so that each call
+// recomputes its scratch addresses instead of keeping those of earlier calls
+// live in registers.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_wave_column(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
+                                                const Twiddles<N>& tw, int stride) {
+  int tl = t;
+  asm volatile("" : "+v"(tl));
+  fft_pass<N, INV, 0, 1, true, ColumnIdx<N>>(v, lds, tl, &tw, nullptr, ColumnIdx<N>{stride});
 }
 
 // Same, reading twiddles from the W_1024 table in every pass.

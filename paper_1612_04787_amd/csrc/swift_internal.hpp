@@ -172,9 +172,14 @@ struct KernelTimer {
 // n/2 template box, box sums).
 hipError_t launch_taper(int n, float taper_frac, float2* tau, float* taper, TaperInfo* info, hipStream_t s,
                         bool box = false);
-// alt_fwd / alt_inv select the alternative row counts (FWD2 / INV2); the
-// slice counts a.nsl_fwd and a.nsl_inv must match the choice.
-hipError_t launch_match_group(int n, const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt);
+// fwd_variant 0 / 1 and alt_inv select the row counts of the five-kernel
+// path (FWD / FWD2, INV / INV2; the slice counts a.nsl_fwd and a.nsl_inv must
+// match the choice).  fwd_variant 2 (n <= kFusedMaxN, not Pearson) runs the
+// whole pair in one workgroup (launch_fused_group).
+constexpr int kFusedVariant = 2;
+constexpr int kFusedMaxN = 128;
+hipError_t launch_match_group(int n, const MatchArgs& a, int fwd_variant, bool alt_inv, hipStream_t s, KernelTimer* kt);
+hipError_t launch_fused_group(int n, const MatchArgs& a, hipStream_t s, KernelTimer* kt);
 int fwd_blocks_n(int n, bool alt);  // forward row blocks per pair
 int inv_blocks_n(int n, bool alt);  // inverse row blocks per pair
 hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);

@@ -605,45 +605,8 @@ __global__ void __launch_bounds__(64) k_pair_stats(MatchArgs a) {
   for (int q = 0; q < 6; ++q) s[q] = wave_sum(s[q]);
   cl = __any(cl) ? 1 : 0;
   if (ln == 0) {
-    const TaperInfo ti = *a.tinfo;
     const RowPart r0 = a.rowpart[(size_t)pair * NSLICE];
-    const double sT = ti.sum_t * ti.sum_t, sT2 = ti.sum_t2 * ti.sum_t2;
-    const double mA = s[0] / sT, mB = s[3] / sT;
-    const double wA = s[1] - 2.0 * mA * s[2] + mA * mA * sT2;
-    const double wB = s[4] - 2.0 * mB * s[5] + mB * mB * sT2;
-    PairStat ps;
-    ps.mA = (float)mA;
-    ps.mB = (float)mB;
-    ps.oA = r0.off[0];
-    ps.oB = r0.off[1];
-    ps.swA = (float)fmax(wA, 0.0);
-    ps.swB = (float)fmax(wB, 0.0);
-    ps.pad[0] = ps.pad[1] = 0;
-    // degenerate: a window's weighted variance is at most kDegenerateRel of
-    // its energy about the offset (samples equal up to rounding; a constant
-    // window has all sums exactly 0)
-    const bool degA = !(wA > kDegenerateRel * s[1]), degB = !(wB > kDegenerateRel * s[4]);
-    ps.flags = (cl ? 4 : 0) | ((degA || degB) ? 1 : 0);
-    const double inv_m = 1.0 / ((double)N * (double)N);
-    if (a.pearson) {
-      // the template carries the mean (its spectrum has no DC), so window B is
-      // used as gathered; only a constant template is degenerate (a constant
-      // patch of B gets a zero coefficient per placement).  No whitening (p =
-      // 0): the spectra are used unscaled.
-      ps.mB = 0.0f;
-      ps.flags = (cl ? 4 : 0) | (degA ? 1 : 0);
-    }
-    if (ps.flags & 1) {
-      ps.sA = ps.sB = 0.0f;
-      ps.kw = 0.0f;
-    } else if (a.pearson) {
-      ps.sA = ps.sB = 1.0f;
-      ps.kw = (float)inv_m;
-    } else {
-      ps.sA = (float)(1.0 / sqrt(wA));
-      ps.sB = (float)(1.0 / sqrt(wB));
-      ps.kw = (float)(exp(0.5 * (1.0 - (double)a.p) * (log(wA) + log(wB))) * inv_m);
-    }
+    const PairStat ps = make_pair_stat(s, cl != 0, *a.tinfo, r0.off[0], r0.off[1], N, a.pearson != 0, a.p);
     a.pstat[pair] = ps;
     if (a.saved_ps) a.saved_ps[pair] = ps;
   }
@@ -684,30 +647,6 @@ __device__ __forceinline__ void store_column(const MatchArgs& a, float2* Zp, int
       if (y < a.zlo || y >= a.zhi) Zp[ztile<N>(w, y)] = v[e];
     }
   }
-}
-
-// ---------------------------------------------------------------- whitening of one bin
-// zp = Z(k), zm = conj Z(-k) of the packed spectrum z = a'T + i b'T, tk =
-// tau(ky) tau(kx).  Splits F_A = (zp + zm) / 2, F_B = (zp - zm) / (2i),
-// removes the weighted means (F -= m tk), and scales both by 1 / ||w||, so the
-// normalised cross power X^ = conj(F_A^) F_B^ has |X^| <= N^2 whatever the
-// input scale.  With X = X^ ||w_A|| ||w_B|| and eps = eps_rel ||w_A|| ||w_B||,
-//   C = X (|X|^2 + eps^2)^(-p/2) / N^2 = X^ (|X^|^2 + eps_rel^2)^(-p/2) kw,
-// kw = (||w_A|| ||w_B||)^(1-p) / N^2.  The DC bin (and a degenerate pair) gives 0.
-__device__ __forceinline__ float2 whiten_bin(float2 zp, float2 zm, float2 tk, const PairStat& ps, float p,
-                                             float eps_rel, bool dc) {
-  float2 fa, fb;
-  split_bin(zp, zm, tk, ps, fa, fb);
-  const float2 X = make_float2(fa.x * fb.x + fa.y * fb.y, fa.x * fb.y - fa.y * fb.x);
-  const float d = fmaf(X.x, X.x, fmaf(X.y, X.y, eps_rel * eps_rel));
-  float gs;
-  if (p == 0.0f) gs = 1.0f;
-  else if (!(d > 0.0f)) gs = 0.0f;
-  else if (p == 1.0f) gs = __builtin_amdgcn_rsqf(d);
-  else gs = __builtin_amdgcn_exp2f(-0.5f * p * __builtin_amdgcn_logf(d));
-  gs *= ps.kw;
-  if (dc) gs = 0.0f;
-  return cscale(X, gs);
 }
 
 // ---------------------------------------------------------------- column pass + whitening
@@ -1327,7 +1266,9 @@ int inv_blocks_n(int n, bool alt) {
   }
 }
 
-hipError_t launch_match_group(int n, const MatchArgs& a, bool alt_fwd, bool alt_inv, hipStream_t s, KernelTimer* kt) {
+hipError_t launch_match_group(int n, const MatchArgs& a, int fwd_variant, bool alt_inv, hipStream_t s, KernelTimer* kt) {
+  if (fwd_variant == kFusedVariant && n <= kFusedMaxN && !a.pearson) return launch_fused_group(n, a, s, kt);
+  const bool alt_fwd = fwd_variant == 1;
   switch (n) {
     case 64: return launch_group_t<64>(a, alt_fwd, alt_inv, s, kt);
     case 128: return launch_group_t<128>(a, alt_fwd, alt_inv, s, kt);

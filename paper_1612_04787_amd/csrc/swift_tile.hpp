@@ -60,7 +60,8 @@ __device__ __forceinline__ float centre_pixel(const swift_image& im, const RowAf
   return im.dtype == SWIFT_U8 ? (float)row[x] : ((gptr<float>)row)[x];
 }
 
-template <int N, int R, int BUDGET, int TRW>
+// NWV: waves of the workgroup that fetch the tile (tile_fetch).
+template <int N, int R, int BUDGET, int TRW, int NWV = 4>
 __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_image& im, int y0) {
   TileGeom g;
   const double ulo = -N / 2, uhi = N / 2 - 1;
@@ -87,7 +88,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.ts = g.wt4;
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
-  g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
+  g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * NWV * (64 / CW) && w16 <= CW;
   return g;
 }
 
@@ -97,7 +98,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
 // geometry is integer arithmetic (the same footprint as tile_geom's).  Its
 // LDS rows are a fixed tile_cw<N> chunks apart, so the gather addresses
 // every row at a constant offset.
-template <int N, int R, int BUDGET, int TRW>
+template <int N, int R, int BUDGET, int TRW, int NWV = 4>
 __device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finite, const swift_image& im, int y0) {
   TileGeom g;
   g.use = false;
@@ -115,20 +116,20 @@ __device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finit
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
   g.ts = 4 * CW;
-  g.use = CW * 16 * g.ht <= BUDGET && g.ht <= TRW * 4 * (64 / CW) && w16 <= CW;
+  g.use = CW * 16 * g.ht <= BUDGET && g.ht <= TRW * NWV * (64 / CW) && w16 <= CW;
   return g;
 }
 
 // Tiles are fetched in two steps so all loads are in flight at once:
 // tile_fetch issues every global load of a thread into registers and nothing
 // consumes them until tile_store writes them to LDS.  Lane l of wave w takes
-// chunk c = l % CW of tile row (4 j + w) (64 / CW) + l / CW in load j (rows
+// chunk c = l % CW of tile row (NWV j + w) (64 / CW) + l / CW in load j (rows
 // past the tile repeat its last row, which the cache serves).  Loads are
 // unconditional and in bounds: rows are clamped into the image and a chunk
 // left or right of the image is read at the nearest in-image chunk; on
 // workgroups whose tile crosses the border, tile_store replaces such a chunk
 // by its edge byte repeated, so byte i holds img[clamp(y)][clamp(x + i)].
-template <int CW, int RW>
+template <int CW, int RW, int NWV = 4>
 __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, const swift_image& im, int tid) {
   constexpr int RPL = 64 / CW;  // tile rows per load of a wave
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
@@ -138,7 +139,7 @@ __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, 
   const uint32_t xc = (uint32_t)min(max(g.xlo + 16 * c, 0), im.width - 16);
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int ty = (4 * j + wv) * RPL + sr;
+    const int ty = (NWV * j + wv) * RPL + sr;
     const int yy = min(max(g.ylo + min(ty, g.ht - 1), 0), im.height - 1);
     const gptr<unsigned char> row = base + (int64_t)yy * im.pitch;
     const u32x4 v = *(gptr<u32x4>)(row + xc);
@@ -146,7 +147,7 @@ __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, 
   }
 }
 
-template <int CW, int RW>
+template <int CW, int RW, int NWV = 4>
 __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint4 (&buf)[RW], const TileGeom& g,
                                            const swift_image& im, bool border, int tid) {
   constexpr int RPL = 64 / CW;
@@ -155,7 +156,7 @@ __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const ui
   const bool left = border && x < 0, right = border && x >= im.width;
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int ty = (4 * j + wv) * RPL + sr;
+    const int ty = (NWV * j + wv) * RPL + sr;
     if (ty < g.ht && 4 * c < g.ts) {
       uint4 v = buf[j];
       if (left | right) {

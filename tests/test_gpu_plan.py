@@ -69,10 +69,14 @@ def test_autotune_picks_a_timed_variant(ctx):
     for n, (times, plan) in out.items():
         print("   n=%d times_ms=%s -> plan %s" % (n, ["%.3f" % t for t in times], plan), flush=True)
         assert times[0] > 0
+        assert (times[7] > 0) == (n <= 128)  # slot 7: the one-workgroup kernel
         valid = [(t, v) for v, t in enumerate(times) if t > 0]
         best = min(valid)[1]
         assert plan == ctx.plan(n, full=True)
-        if best < 4:
+        if best == 7:
+            assert n <= 128  # the one-workgroup kernel
+            ctx.plan(n, 2, 0, 1)
+        elif best < 4:
             ctx.plan(n, best & 1, best >> 1, 1)
         else:
             # a chunked slot times the best row variant of slots 0..3
