@@ -35,6 +35,9 @@ S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
 PRUNE_R = N // 8  # search radius of the pruned-inverse variant (64 px at 512^2)
 REFINE_R = 8      # search radius of the pruned refinement (its shifts stay below a pixel)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_match_512_headline.txt")
+LDS_FILE = os.path.join(ROOT, "profiles", "lds_match_512_headline.txt")
+# LDS peak: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
 
 
 def kernel_bytes(name: str, n: int, pairs: int, sections: int, size: int) -> float:
@@ -140,6 +143,26 @@ def pair_flops(n: int) -> float:
     return 7.5 * n * n * math.log2(n * n) + 40.0 * n * n
 
 
+def median_event_ms(fn, reps, warm=2):
+    """Median over `reps` calls of fn, each bracketed by HIP events on the
+    current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 # --------------------------------------------------------------------------- CPU oracle leg
 def _oracle_worker(job):
     import numpy as np
@@ -153,15 +176,31 @@ def _oracle_worker(job):
     return out, time.perf_counter() - t0
 
 
-def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=8, cores=None):
-    """Times the FP64 oracle (one process per core) on a bounded sample of the
-    same pairs.  Windows are cropped with a margin so clamped reads at the
-    section border are reproduced exactly."""
-    import multiprocessing as mp
+def host_cores():
+    """(cores used, cores this process may run on, logical CPUs of the host).
+    The CPU legs use every core the process may run on, at most 16 (the host
+    share of one GPU on the benchmark machines)."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return min(16, aff), aff, os.cpu_count() or 1
 
+
+def _fp32_worker(job):
+    from oracle import cpu_fp32
+    t0 = time.perf_counter()
+    out = []
+    # every pair is its own crop, so each is a batch of one
+    for (a, b, tha, thb, n, p) in job:
+        r = cpu_fp32.match_batch(a, b, tha[None], thb[None], n, p=p, workers=1)
+        out.append((int(r["ix"][0]), int(r["iy"][0]), float(r["snr"][0])))
+    return out, time.perf_counter() - t0
+
+
+def _sample_jobs(stack_cpu, refs_cpu, centres, n_sample_sections, per_section, seed=0):
+    """Pairs of the benchmark batch cropped with a margin (so clamped reads at
+    the section border are reproduced exactly), with their crop-relative
+    affines."""
     import numpy as np
-    cores = cores or min(16, os.cpu_count() or 1)
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     jobs = []
     H = stack_cpu.shape[1]
     m = 4
@@ -172,27 +211,53 @@ def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section
             x1, y1 = int(min(cx + N // 2 + m, H)), int(min(cy + N // 2 + m, H))
             th = np.array([cx - x0, cy - y0, 1, 0, 0, 0, 1, 0], np.float64)
             jobs.append((stack_cpu[s, y0:y1, x0:x1].copy(), refs_cpu[s, y0:y1, x0:x1].copy(), th, th, N, P_WHITEN))
+    return jobs
+
+
+def _pool_time(worker, jobs, cores):
+    import multiprocessing as mp
     chunks = [jobs[i::cores] for i in range(cores)]
     ctx = mp.get_context("spawn")
     env_keep = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     try:
         with ctx.Pool(cores) as pool:
-            pool.map(_oracle_worker, [c[:1] for c in chunks])  # warm the workers (imports)
+            pool.map(worker, [c[:1] for c in chunks])  # warm the workers (imports)
             t0 = time.perf_counter()
-            res = pool.map(_oracle_worker, chunks)
+            res = pool.map(worker, chunks)
             wall = time.perf_counter() - t0
     finally:
         if env_keep is None:
             os.environ.pop("OMP_NUM_THREADS", None)
         else:
             os.environ["OMP_NUM_THREADS"] = env_keep
-    cpu_s = sum(r[1] for r in res)
+    return wall, sum(r[1] for r in res)
+
+
+def cpu_fp32_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=16):
+    """The same pairs through the CPU FP32 implementation (SciPy pocketfft in
+    single precision, one process per core): the fast CPU reference point."""
+    cores, aff, logical = host_cores()
+    jobs = _sample_jobs(stack_cpu, refs_cpu, centres, n_sample_sections, per_section, seed=1)
+    wall, cpu_s = _pool_time(_fp32_worker, jobs, cores)
+    return dict(value=len(jobs) / wall, unit="pairs/s", cores=cores, kind="scipy_fp32",
+                sample="%d pairs of %d^2 of the benchmark batch, FP32 SciPy pocketfft, one process per core; "
+                       "%.1f s of CPU work" % (len(jobs), N, cpu_s), cpu_seconds=cpu_s)
+
+
+def cpu_baseline(stack_cpu, refs_cpu, centres, n_sample_sections=64, per_section=8):
+    """Times the FP64 oracle (one process per core) on a bounded sample of the
+    same pairs."""
+    cores, aff, logical = host_cores()
+    jobs = _sample_jobs(stack_cpu, refs_cpu, centres, n_sample_sections, per_section, seed=0)
+    wall, cpu_s = _pool_time(_oracle_worker, jobs, cores)
     return dict(value=len(jobs) / wall, unit="pairs/s", cores=cores, kind="oracle",
                 sample="%d pairs of %d^2 (%d sections x %d windows) of the benchmark batch, FP64 NumPy, "
                        "one process per core; %.1f s of CPU work" % (len(jobs), N, n_sample_sections,
                                                                      per_section, cpu_s),
-                cpu_seconds=cpu_s, mpx_per_s_per_core=len(jobs) * N * N / cpu_s / 1e6)
+                cpu_seconds=cpu_s, mpx_per_s_per_core=len(jobs) * N * N / cpu_s / 1e6,
+                host={"cores_allowed": aff, "logical_cpus": logical,
+                      "note": "every allowed core up to 16, the host share of one GPU"})
 
 
 # --------------------------------------------------------------------------- refinement comparison
@@ -268,7 +333,22 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9, 
 
 
 # --------------------------------------------------------------------------- ragged levels
-def ragged_levels(ctx, sw, dev, sections=32, size=8192, reps=20):
+def config3_images(ctx, dev, sections=32, size=8192):
+    """The multi-level input: a 32 x 8192^2 stack, its x2 pyramid (4 levels)
+    and the +-3 projections of every level.  Image table layout: level l's
+    sections at 2 S l + s, their references at 2 S l + S + s."""
+    from datagen.workloads import level_stack
+    from paper_1612_04787_amd.stack import build_pyramid
+    stack = level_stack(sections, size, seed=3, device=dev)
+    pyr = build_pyramid(ctx, stack, 3)
+    images = []
+    for lv in pyr:
+        ref = ctx.project(lv, k=K_PROJ)
+        images += [lv[s] for s in range(sections)] + [ref[s] for s in range(sections)]
+    return images
+
+
+def ragged_levels(ctx, sw, dev, images, sections=32, size=8192, reps=20):
     """Every pyramid level of a 32 x 8192^2 stack at once: 8 x 8 windows per
     section and level (1024^2 at level 0 down to 128^2 at level 3), 8192
     pairs against +-3 projections of each level.  Compares four plain calls
@@ -277,14 +357,7 @@ def ragged_levels(ctx, sw, dev, sections=32, size=8192, reps=20):
     Median of `reps` runs each."""
     import torch
 
-    from datagen.workloads import level_stack, ragged_level_pairs
-    from paper_1612_04787_amd.stack import build_pyramid
-    stack = level_stack(sections, size, seed=3, device=dev)
-    pyr = build_pyramid(ctx, stack, 3)
-    images = []
-    for lv in pyr:
-        ref = ctx.project(lv, k=K_PROJ)
-        images += [lv[s] for s in range(sections)] + [ref[s] for s in range(sections)]
+    from datagen.workloads import ragged_level_pairs
     n_list, ia, ib, ta, tb = ragged_level_pairs(sections, size, 4, 8, dev)
     P = len(n_list)
     params = sw.make_params(p=P_WHITEN, flags=sw.FLAG_CONCURRENT_SIZES)
@@ -314,7 +387,38 @@ def ragged_levels(ctx, sw, dev, sections=32, size=8192, reps=20):
     def graph():
         ctx.match_batch_raw(prep["table"], len(images), prep["pairs"], params, out, ws=ws, graph=True)
 
-    res = {}
+    # per-size kernel time of the sequential calls (HIP events on the launch
+    # stream) against each size's bound: the FP32 vector ALUs for 64 / 128
+    # (the one-workgroup kernel keeps spectra in LDS), HBM for >= 256
+    per_level()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(5):
+        per_level()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    sizes = {}
+    for name, (cnt, tot) in prof.items():
+        nn = int(name.split("<")[1].rstrip(">")) if "<" in name else 0
+        if nn:
+            d = sizes.setdefault(nn, dict(kernels={}, ms=0.0))
+            d["kernels"][name] = tot / 5
+            d["ms"] += tot / 5
+    for nn, d in sizes.items():
+        cnt = n_list.count(nn)
+        d["pairs"] = cnt
+        d["pairs_per_s"] = cnt / (d["ms"] / 1e3)
+        d["plan"] = dict(zip(("fwd_rows", "inv_rows", "chunks"), ctx.plan(nn, full=True)))
+        if nn <= 128:
+            tf = cnt * pair_flops(nn) / (d["ms"] / 1e3) / 1e12
+            d["roofline"] = dict(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                 frac=tf / FP32_PEAK_TFLOPS)
+        else:
+            gbs = cnt * pair_bytes(nn) / (d["ms"] / 1e3) / 1e9
+            d["roofline"] = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
+
+    res = {"per_size": {str(k): v for k, v in sorted(sizes.items())}}
     for name, fn in (("per_level_calls", per_level), ("one_call_concurrent", one_call), ("graph", graph)):
         fn()
         torch.cuda.synchronize()
@@ -333,6 +437,164 @@ def ragged_levels(ctx, sw, dev, sections=32, size=8192, reps=20):
     res["median_snr"] = float(r["snr"].float().median())
     res["graph_speedup_vs_per_level"] = res["per_level_calls"]["ms"] / res["graph"]["ms"]
     return res
+
+
+# --------------------------------------------------------------------------- config 2: 1024^2 windows
+def config2_block(ctx, sw, dev, reps=20):
+    """A 16384^2 section pair (B = bilinear affine warp of A about the centre,
+    rotation <= 0.5 deg, scale 1 +- 0.002, shift <= 40 px, plus noise sigma 8)
+    and a 16 x 16 grid of 1024^2 windows at identity affines: 256 pairs,
+    p = 0.65.  Median of `reps` replays of the batch as one hipGraph, the
+    per-kernel HIP-event timing with the HBM roofline of the longest kernel,
+    the whole-path roofline, and the shifts against the generator's warp at
+    the window centres."""
+    import numpy as np
+    import torch
+
+    from datagen.workloads import section_pair_1024
+    n = 1024
+    a, b, m, bv, n_list, ia, ib, ta, tb = section_pair_1024(16384, dev)
+    P = len(n_list)
+    prep = ctx.prepare([a, b], n_list, ia, ib, ta, tb)
+    params = sw.make_params(p=P_WHITEN)
+    need, _ = ctx.workspace_size(prep["pairs"], params)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
+    ms = median_event_ms(lambda: ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws,
+                                                     graph=True), reps)
+    ctx.profile(True)
+    for _ in range(5):
+        ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws)
+    torch.cuda.synchronize()
+    kernels, roof = variant_kernels(ctx.profile_read(), n, P, n, False)
+    ctx.profile(False)
+    r = sw.parse_records(out)
+    # B(q) = A(M q + b): window B's content at centre q sits at M q + b in A,
+    # so the match shift is q - (M q + b)
+    cen = ta[:, :2].double().cpu().numpy()
+    mm, bb = np.asarray(m, np.float64), np.asarray(bv, np.float64)
+    expect = cen - (cen @ mm.T + bb)
+    got = np.stack([r["dx"].double().cpu().numpy(), r["dy"].double().cpu().numpy()], 1)
+    err = np.linalg.norm(got - expect, axis=1)
+    rate = P / (ms / 1e3)
+    del ws, a, b
+    return dict(workload="256 pairs of 1024^2: 16 x 16 windows of a 16384^2 uint8 section pair (B = bilinear affine "
+                         "warp of A plus noise), identity affines, p = 0.65",
+                replays=reps, median_ms=ms, pairs_per_s=rate, kernels=kernels, roofline=roof,
+                path_roofline=path_roofline(rate, n), hbm_floor_ms=P * pair_bytes(n) / (HBM_PEAK_GBS * 1e9) * 1e3,
+                shift_error_px={"median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
+                                "max": float(err.max()),
+                                "note": "against the warp's displacement at the window centre; the warp's rotation "
+                                        "moves the window's far corners up to ~4 px more, so this is not the "
+                                        "sub-pixel parity bound"},
+                median_snr=float(r["snr"].median()))
+
+
+# --------------------------------------------------------------------------- refinement on the ragged levels
+def refine_levels(ctx, sw, dev, images, sections=32, size=8192, tol=0.005, target=0.01, seed=9, max_plain=80,
+                  max_adjoint=20):
+    """Refinement of the 8192 ragged windows of the multi-level input to a
+    known sub-pixel truth: window B samples its level image at a fractional
+    translation t* (U(-0.5, 0.5)^2), window A the same image starting
+    U(-0.5, 0.5)^2 px away from t*, so A's aligned translation is t*.
+      plain    per iteration one call per level (four sizes in sequence) and
+               a centroid update per level; the host reads the longest step.
+      batched+adjoint  per iteration one replayed graph of the whole ragged
+               batch (match, centroid Jacobian on Newton iterations, update,
+               the steps copied to pinned host memory); centroid steps until
+               the longest is below 0.25 px, then Newton steps.
+    Both stop when the longest step is below `tol`.  Reports wall time,
+    iterations, final RMS / max error, and the iteration and wall time at
+    which the RMS error over all windows first reaches `target` (from theta
+    recorded after every iteration), with windows/s to that point."""
+    import numpy as np
+    import torch
+
+    from datagen.workloads import ragged_level_pairs
+    from paper_1612_04787_amd.refine import CENTROID, refine_adjoint_graph
+    n_list, ia, _, _, tb = ragged_level_pairs(sections, size, 4, 8, dev)
+    P = len(n_list)
+    rng = np.random.default_rng(seed)
+    tbn = tb.cpu().numpy().copy()
+    tbn[:, 4] = rng.uniform(-0.5, 0.5, P)
+    tbn[:, 7] = rng.uniform(-0.5, 0.5, P)
+    tan = tbn.copy()
+    tan[:, 4] += rng.uniform(-0.5, 0.5, P)
+    tan[:, 7] += rng.uniform(-0.5, 0.5, P)
+    tha0 = torch.from_numpy(tan.astype(np.float32)).to(dev)
+    thb = torch.from_numpy(tbn.astype(np.float32)).to(dev)
+    truth = thb[:, [4, 7]].clone()
+    ib = ia.clone()  # both windows on the same level image
+
+    def rms_of(trace_rows):
+        e = (trace_rows[..., [4, 7]] - truth).norm(dim=-1)
+        return e.pow(2).mean(-1).sqrt().cpu().numpy(), e.max(-1).values.cpu().numpy()
+
+    res = {}
+    # plain: one call per level per iteration
+    params = sw.make_params(p=P_WHITEN)
+    prep = ctx.prepare(images, n_list, ia, ib, tha0.clone(), thb)
+    th = prep["keep"][2]
+    need, _ = ctx.workspace_size(prep["pairs"], params)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
+    step = torch.empty(P, dtype=torch.float32, device=dev)
+    lv = []
+    off = 0
+    for n in sorted(set(n_list)):
+        c = n_list.count(n)
+        sl = slice(off, off + c)
+        lv.append((sl, ctx.make_pairs(n_list[sl], prep["keep"][0][sl], prep["keep"][1][sl], th[sl],
+                                      prep["keep"][3][sl])))
+        off += c
+
+    def plain_iter():
+        for sl, pr in lv:
+            ctx.match_batch_raw(prep["table"], len(images), pr, params, out[sl], ws=ws)
+            ctx.refine_update(out[sl], th[sl], CENTROID, None, 0.5, step[sl])
+
+    plain_iter()  # warm-up
+    torch.cuda.synchronize()
+    th.copy_(tha0)
+    trace = torch.empty((max_plain, P, 8), dtype=torch.float32, device=dev)
+    times = []
+    t0 = time.perf_counter()
+    iters = max_plain
+    for it in range(1, max_plain + 1):
+        plain_iter()
+        trace[it - 1].copy_(th)
+        m = float(step.max())
+        times.append(time.perf_counter() - t0)
+        if m < tol:
+            iters = it
+            break
+    rms, mx = rms_of(trace[:iters])
+    res["plain"] = _refine_summary(P, iters, times, rms, mx, target)
+    del trace, ws
+    # batched + adjoint: one replayed graph of the ragged batch per iteration
+    pc = sw.make_params(p=P_WHITEN, flags=sw.FLAG_CONCURRENT_SIZES)
+    trace = torch.empty((max_adjoint, P, 8), dtype=torch.float32, device=dev)
+    _, iters, hist, times = refine_adjoint_graph(ctx, images, n_list, ia, ib, tha0, thb, pc, tol=tol,
+                                                 max_iter=max_adjoint, theta_trace=trace)
+    rms, mx = rms_of(trace[:iters])
+    res["batched_adjoint"] = _refine_summary(P, iters, times, rms, mx, target)
+    res["workload"] = ("%d windows of the multi-level input (2048 each of 128/256/512/1024), truth = fractional "
+                       "translation of window B, start U(-0.5, 0.5)^2 px away" % P)
+    r0 = float((tha0[:, [4, 7]] - truth).norm(dim=1).pow(2).mean().sqrt())
+    res.update(start_rms_px=r0, tol_px=tol, target_rms_px=target)
+    a, b = res["plain"], res["batched_adjoint"]
+    if a["ms_to_target"] and b["ms_to_target"]:
+        res["speedup_to_target"] = a["ms_to_target"] / b["ms_to_target"]
+    return res
+
+
+def _refine_summary(P, iters, times, rms, mx, target):
+    hit = next((i for i in range(iters) if rms[i] <= target), None)
+    ms_hit = times[hit] * 1e3 if hit is not None else None
+    return dict(iterations=iters, wall_ms=times[iters - 1] * 1e3, rms_px=float(rms[iters - 1]),
+                max_px=float(mx[iters - 1]), rms_by_iteration=[float(v) for v in rms],
+                iters_to_target=(hit + 1) if hit is not None else None, ms_to_target=ms_hit,
+                windows_per_s_to_target=(P / (ms_hit / 1e3)) if ms_hit else None)
 
 
 # --------------------------------------------------------------------------- stack loop
@@ -760,6 +1022,7 @@ def main():
     ap.add_argument("--no-pearson", action="store_true", help="skip the Pearson-normalised correlation variant")
     ap.add_argument("--no-jump", action="store_true", help="skip the jump-repair run")
     ap.add_argument("--no-search", action="store_true", help="skip the SNR-stop search run")
+    ap.add_argument("--no-config2", action="store_true", help="skip the 256 x 1024^2 section-pair batch")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -795,10 +1058,10 @@ def main():
     log("pairs: %d of %d^2, workspace %.2f GB" % (P, N, need / 1e9))
     # row-count variants chosen on the device (synthetic batch, untimed set-up)
     if args.no_autotune:
-        tuned = {n: ([], ctx.plan(n)) for n in sw.SIZES}
+        tuned = {n: ([], ctx.plan(n, full=True)) for n in sw.SIZES}
     else:
         tuned = ctx.autotune(sw.SIZES, pairs_per_size=2048)
-    log("plan: " + ", ".join("%d: rows %s" % (n, v[1]) for n, v in tuned.items()))
+    log("plan: " + ", ".join("%d: (fwd rows, inv rows, chunks) %s" % (n, v[1]) for n, v in tuned.items()))
 
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
@@ -825,6 +1088,15 @@ def main():
     value = P / (ms / 1e3)
     log("timed: %d steps, %.3f ms/step, %.0f pairs/s" % (args.steps, ms, value))
 
+    # the same step with the match as one replayed hipGraph: each of 20
+    # replays timed on its own (HIP events on the launch stream), median
+    def step_graph():
+        ctx.project(stack, k=K_PROJ, out=refs)
+        ctx.match_batch_raw(table, len(images), pairs, params, out, None, ws, graph=True)
+
+    graph_rep = median_event_ms(step_graph, 20)
+    log("graph replays: median %.3f ms/step, %.0f pairs/s" % (graph_rep, P / (graph_rep / 1e3)))
+
     # live per-kernel timing (HIP events on the launch stream), same work
     ctx.profile(True)
     prof_steps = max(3, min(args.steps, 10))
@@ -844,11 +1116,26 @@ def main():
     # WRITE_SIZE, copy-calibrated), valid only for the kernel sources it was taken on
     from paper_1612_04787_amd.counters import read_traffic, source_digest
     traffic, digest = read_traffic(TRAFFIC_FILE, dom)
-    if digest != source_digest():
+    digest_now = source_digest()
+    if digest != digest_now:
         traffic = None
     roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=d["gbs"] / HBM_PEAK_GBS, traffic=traffic,
                 bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
+    # LDS bytes per launch of the three passes (rocprofv3 LDS load/store
+    # bandwidth counters, valid for the kernel sources they were taken on)
+    # over the live launch times
+    from paper_1612_04787_amd.counters import read_lds
+    lds_rate = {}
+    for kname, kv in kernels.items():
+        if not kname.startswith(("k_row_fwd", "k_col", "k_row_inv")):
+            continue
+        b, busy, dg = read_lds(LDS_FILE, kname)
+        if b is None or dg != digest_now:
+            continue
+        gbs = b / (kv["avg_ms"] / 1e3) / 1e9
+        lds_rate[kname] = dict(bytes_per_launch=b, gbs=gbs, peak_gbs=LDS_PEAK_GBS, frac=gbs / LDS_PEAK_GBS,
+                               busy_frac_counter=busy)
     res = sw.parse_records(out)
     snr = res["snr"].float()
     step_bytes = P * pair_bytes(N) + kernel_bytes("k_project", N, P, S_SECTIONS, SIZE)
@@ -914,8 +1201,13 @@ def main():
         # the binding bound, and the stricter bound of the inputs alone
         "path_roofline": path_roofline(value, N),
         "kernels": kernels,
-        "plan": {str(n): {"fwd_rows": v[1][0], "inv_rows": v[1][1], "variant_ms": v[0]} for n, v in tuned.items()},
+        "lds": lds_rate or None,
+        "plan": {str(n): {"fwd_rows": v[1][0], "inv_rows": v[1][1], "chunks": v[1][2],
+                          "one_workgroup": v[1][0] == n, "slot_ms": v[0]} for n, v in tuned.items()},
         "match_quality": {"median_snr": float(snr.median()), "frac_snr_gt_15": float((snr > 15).float().mean())},
+        "graph_replays": {"replays": 20, "median_ms_per_step": graph_rep, "pairs_per_s": P / (graph_rep / 1e3),
+                          "note": "projection + the match as one replayed hipGraph, each replay timed with HIP "
+                                  "events on the launch stream"},
     }
     if pruned is not None:
         line["pruned"] = pruned
@@ -928,7 +1220,7 @@ def main():
                                  pb["median_snr_whitened"]))
     if not args.no_refine:
         log("refinement: plain vs batched + adjoint to 0.01 px ...")
-        del ws
+        ws = None
         line["refine"] = refine_comparison(ctx, sw, stack, cen, dev)
         line["refine_pruned"] = refine_comparison(ctx, sw, stack, cen, dev, max_shift=REFINE_R)
         for key in ("refine", "refine_pruned"):
@@ -987,6 +1279,9 @@ def main():
         log("cpu baseline: timing the FP64 oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)
         log("cpu baseline: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
+        line["cpu_baseline"]["fp32_scipy"] = cpu_fp32_baseline(stack.cpu().numpy(), refs.cpu().numpy(), cen)
+        log("cpu baseline, FP32 SciPy: %.1f pairs/s on %d cores" % (line["cpu_baseline"]["fp32_scipy"]["value"],
+                                                                   line["cpu_baseline"]["fp32_scipy"]["cores"]))
         if mesh_sample is not None:
             line["cpu_baseline"]["mesh_render"] = cpu_baseline_mesh(mesh_sample)
         if jump_sample is not None:
@@ -995,14 +1290,38 @@ def main():
             line["cpu_baseline"]["search"] = cpu_baseline_search(search_sample)
         if not (args.no_prune and args.no_pearson):
             line["cpu_baseline"].update(cpu_baseline_variants(stack.cpu().numpy(), refs.cpu().numpy(), cen))
+    if not args.no_config2:
+        log("config 2: 256 pairs of 1024^2 from a 16384^2 section pair ...")
+        ws = None
+        torch.cuda.empty_cache()
+        line["config2_1024"] = config2_block(ctx, sw, dev)
+        c2 = line["config2_1024"]
+        log("config 2: median %.3f ms (%.0f pairs/s, %.2f of the path's HBM bound); %s %.0f GB/s (%.2f of peak); "
+            "median shift error %.3f px" % (c2["median_ms"], c2["pairs_per_s"], c2["path_roofline"]["frac"],
+                                            c2["roofline"]["kernel"], c2["roofline"]["achieved"],
+                                            c2["roofline"]["frac"], c2["shift_error_px"]["median"]))
+        torch.cuda.empty_cache()
     if not args.no_ragged:
         log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
         del stack, refs, images, table, out
         torch.cuda.empty_cache()
-        line["ragged"] = ragged_levels(ctx, sw, dev)
+        images3 = config3_images(ctx, dev)
+        line["ragged"] = ragged_levels(ctx, sw, dev, images3)
         g = line["ragged"]
         log("ragged levels: per-level %.2f ms, one call %.2f ms, graph %.2f ms"
             % (g["per_level_calls"]["ms"], g["one_call_concurrent"]["ms"], g["graph"]["ms"]))
+        for k, v in g["per_size"].items():
+            log("  n=%s: %.3f ms for %d pairs, %s %.1f %s (%.3f of peak), plan %s"
+                % (k, v["ms"], v["pairs"], v["roofline"]["bound"], v["roofline"]["achieved"], v["roofline"]["unit"],
+                   v["roofline"]["frac"], v["plan"]))
+        if not args.no_refine:
+            log("refinement on the ragged levels: plain per-level calls vs one graph per iteration + adjoint ...")
+            line["refine_levels"] = refine_levels(ctx, sw, dev, images3)
+            q = line["refine_levels"]
+            log("refine levels: to %.2f px rms plain %s it %s ms | batched+adjoint %s it %s ms"
+                % (q["target_rms_px"], q["plain"]["iters_to_target"], q["plain"]["ms_to_target"],
+                   q["batched_adjoint"]["iters_to_target"], q["batched_adjoint"]["ms_to_target"]))
+        del images3
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -3,6 +3,7 @@
   python -m paper_1612_04787_amd.counters stats  KERNEL_STATS_CSV
   python -m paper_1612_04787_amd.counters pmc    COUNTER_COLLECTION_CSV [--largest-grid]
   python -m paper_1612_04787_amd.counters traffic FETCH_CSV WRITE_CSV [--copy-bytes B]
+  python -m paper_1612_04787_amd.counters lds    COUNTER_COLLECTION_CSV [--cus 256]
 
 `stats` condenses a `--kernel-trace --stats` run to one line per kernel
 (calls, average and total duration).  `pmc` averages every counter per
@@ -11,7 +12,11 @@ WRITE_SIZE run (KiB per dispatch; each kernel's largest-grid dispatches)
 into HBM bytes per launch, each scaled by
 the factor that makes the same counter read exactly `copy-bytes` for a plain
 device-to-device copy of that size launched in the same program, and records
-the digest of the kernel sources the numbers belong to.
+the digest of the kernel sources the numbers belong to.  `lds` turns one run of
+SQ_INSTS_LDS_LOAD_BANDWIDTH, SQ_INSTS_LDS_STORE_BANDWIDTH (64-byte units moved
+by LDS loads and stores), SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT and
+GRBM_GUI_ACTIVE into LDS bytes per launch, the LDS busy fraction and the bank
+conflict cycles per active cycle, with the source digest.
 
 Kernel names are shortened to `name<N>` (the first template argument is the
 window size), the form the library's own HIP-event timer uses; the instances
@@ -154,6 +159,47 @@ def traffic(fetch_csv, write_csv, copy_bytes):
     return "\n".join(lines)
 
 
+def lds(path, cus=256):
+    d = per_kernel_counters(path, largest_grid=True)
+
+    def mean(name, ctr):
+        v = d[name].get(ctr, [])
+        return sum(v) / len(v) if v else None
+
+    lines = ["source_digest %s" % source_digest(),
+             "%-26s %16s %16s %16s %10s %12s" % ("kernel", "lds_read_B", "lds_write_B", "lds_B/launch", "lds_busy",
+                                                   "bank_confl")]
+    for name in sorted(k for k in d if not k.startswith("copy:")):
+        ld, st = mean(name, "SQ_INSTS_LDS_LOAD_BANDWIDTH"), mean(name, "SQ_INSTS_LDS_STORE_BANDWIDTH")
+        act, bc, gui = mean(name, "SQ_LDS_IDX_ACTIVE"), mean(name, "SQ_LDS_BANK_CONFLICT"), mean(name, "GRBM_GUI_ACTIVE")
+        if ld is None or st is None:
+            continue
+        busy = act / (gui * cus) if act is not None and gui else float("nan")
+        conf = bc / (act - bc) if act is not None and bc is not None and act > bc else float("nan")
+        lines.append("%-26s %16.4g %16.4g %16.4g %10.3f %12.3f" % (name, ld * 64.0, st * 64.0, (ld + st) * 64.0, busy,
+                                                                   conf))
+    return "\n".join(lines)
+
+
+def read_lds(path, kernel):
+    """(LDS bytes per launch of `kernel`, busy fraction, digest) from an `lds`
+    summary, or (None, None, None)."""
+    if not os.path.exists(path):
+        return None, None, None
+    digest, val, busy = None, None, None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] == "source_digest":
+                digest = parts[1]
+            if len(parts) == 6 and parts[0] == kernel:
+                try:
+                    val, busy = float(parts[3]), float(parts[4])
+                except ValueError:
+                    pass
+    return val, busy, digest
+
+
 def read_traffic(path, kernel):
     """(traffic bytes per launch of `kernel`, digest) from a `traffic` summary,
     or (None, None) if the file or the kernel is absent."""
@@ -185,11 +231,16 @@ def main(argv=None):
     a.add_argument("fetch_csv")
     a.add_argument("write_csv")
     a.add_argument("--copy-bytes", type=int, default=1 << 30)
+    a = sub.add_parser("lds")
+    a.add_argument("csv")
+    a.add_argument("--cus", type=int, default=256)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats(args.csv))
     elif args.cmd == "pmc":
         print(pmc(args.csv, args.largest_grid))
+    elif args.cmd == "lds":
+        print(lds(args.csv, args.cus))
     else:
         print(traffic(args.fetch_csv, args.write_csv, args.copy_bytes))
 

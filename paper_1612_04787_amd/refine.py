@@ -101,3 +101,76 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
             # fraction of windows may still step further (as in _done)
             newton = _done(step, newton_below, stop_frac)[1]
     return th, max_iter, hist
+
+
+def refine_adjoint_graph(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
+                         max_step=0.5, newton_below=0.25, theta_trace=None):
+    """refine_adjoint with every iteration one replayed graph: the match of the
+    whole (ragged) batch, for Newton iterations the centroid Jacobian, the
+    update of theta_a, and the copy of the per-window steps into pinned host
+    memory, from which the host reads the stop test (one synchronisation per
+    iteration, no host-side launches).  Two graphs are captured once per call:
+    the centroid iteration and the Newton iteration.  theta_trace, if given
+    ([max_iter, P, 8] device), receives theta_a after each iteration.
+    Returns (theta_a [P, 8], iterations, list of longest steps, list of host
+    times in seconds after each iteration, measured from the first replay)."""
+    import time
+
+    from .swift import FLAG_JAC_TRANSLATION, make_params
+    jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
+                          params.flags | FLAG_JAC_TRANSLATION, params.max_shift)
+    prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
+    P = prep["pairs"].n_pairs
+    dev = sw.device
+    out = torch.empty((P, REC_BYTES), dtype=torch.uint8, device=dev)
+    need, sv = sw.workspace_size(prep["pairs"], params)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    saved = torch.empty(max(sv, 256), dtype=torch.uint8, device=dev)
+    jac = torch.empty((P, 2, 6), dtype=torch.float32, device=dev)
+    step = torch.empty(P, dtype=torch.float32, device=dev)
+    host_step = torch.empty(P, dtype=torch.float32, pin_memory=True)
+
+    def body(newton):
+        if newton:
+            sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, saved=saved, ws=ws)
+            sw.centroid_jacobian_raw(prep["table"], prep["n_imgs"], prep["pairs"], jparams, saved, jac, ws=ws)
+            sw.refine_update(out, th, NEWTON, jac, max_step, step)
+        else:
+            sw.match_batch_raw(prep["table"], prep["n_imgs"], prep["pairs"], params, out, ws=ws)
+            sw.refine_update(out, th, CENTROID, None, max_step, step)
+        host_step.copy_(step, non_blocking=True)
+
+    # capture on a side stream (theta is restored after the warm-up runs that
+    # precede each capture; a capture itself executes nothing)
+    th0 = th.clone()
+    graphs = {}
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        for newton in (False, True):
+            body(newton)
+            torch.cuda.current_stream(dev).synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                body(newton)
+            graphs[newton] = g
+    torch.cuda.current_stream(dev).wait_stream(side)
+    th.copy_(th0)
+    torch.cuda.synchronize(dev)
+
+    hist, times = [], []
+    newton = False
+    t0 = time.perf_counter()
+    for it in range(1, max_iter + 1):
+        graphs[newton].replay()
+        if theta_trace is not None:
+            theta_trace[it - 1].copy_(th)
+        torch.cuda.current_stream(dev).synchronize()
+        m = float(host_step.max()) if P else 0.0
+        hist.append(m)
+        times.append(time.perf_counter() - t0)
+        if newton and m < tol:
+            return th, it, hist, times
+        if not newton:
+            newton = m < newton_below
+    return th, max_iter, hist, times
