@@ -92,14 +92,17 @@ def variant_bytes(name: str, n: int, pairs: int, rows: int, pearson: bool) -> fl
     return per * pairs
 
 
-def variant_kernels(prof, n, pairs, rows, pearson, traffic_file=None):
-    """Per-kernel launches, average ms, algorithmic bytes and GB/s of a step
-    variant, and the HBM roofline of its longest kernel (with the measured
-    traffic of traffic_file when it belongs to the current kernel sources)."""
+def variant_kernels(prof, n, pairs, rows, pearson, traffic_file=None, steps=None):
+    """Per-kernel launches, average ms, algorithmic bytes per launch and GB/s
+    of a step variant, and the HBM roofline of its longest kernel (with the
+    measured traffic of traffic_file when it belongs to the current kernel
+    sources).  `pairs` per step; with `steps` profiled steps a kernel launched
+    cnt times covers pairs * steps / cnt pairs per launch."""
     kernels = {}
     for name, (cnt, tot) in prof.items():
         avg = tot / cnt
-        b = variant_bytes(name, n, pairs, rows, pearson)
+        per_launch = pairs * steps / cnt if steps else pairs
+        b = variant_bytes(name, n, per_launch, rows, pearson)
         kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     d = kernels[dom]
@@ -141,6 +144,26 @@ def path_roofline(pairs_per_s: float, n: int) -> dict:
 def pair_flops(n: int) -> float:
     import math
     return 7.5 * n * n * math.log2(n * n) + 40.0 * n * n
+
+
+class one_chunk:
+    """Context in which the listed window sizes run as one chunk (their tuned
+    row variants kept): each kernel launch then covers the whole batch with
+    nothing else on the GPU, which is how the per-kernel timing is taken."""
+
+    def __init__(self, ctx, sizes):
+        self.ctx, self.sizes = ctx, list(sizes)
+
+    def __enter__(self):
+        self.keep = {n: self.ctx.plan(n, full=True)[2] for n in self.sizes}
+        for n in self.sizes:
+            self.ctx.plan(n, -1, -1, 1)
+        return self
+
+    def __exit__(self, *exc):
+        for n, c in self.keep.items():
+            self.ctx.plan(n, -1, -1, c)
+        return False
 
 
 def median_event_ms(fn, reps, warm=2):
@@ -463,10 +486,11 @@ def config2_block(ctx, sw, dev, reps=20):
     ms = median_event_ms(lambda: ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws,
                                                      graph=True), reps)
     ctx.profile(True)
-    for _ in range(5):
-        ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws)
-    torch.cuda.synchronize()
-    kernels, roof = variant_kernels(ctx.profile_read(), n, P, n, False)
+    with one_chunk(ctx, [n]):
+        for _ in range(5):
+            ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws)
+        torch.cuda.synchronize()
+    kernels, roof = variant_kernels(ctx.profile_read(), n, P, n, False, steps=5)
     ctx.profile(False)
     r = sw.parse_records(out)
     # B(q) = A(M q + b): window B's content at centre q sits at M q + b in A,
@@ -488,6 +512,62 @@ def config2_block(ctx, sw, dev, reps=20):
                                         "moves the window's far corners up to ~4 px more, so this is not the "
                                         "sub-pixel parity bound"},
                 median_snr=float(r["snr"].median()))
+
+
+# --------------------------------------------------------------------------- per-size rooflines
+def size_rooflines(ctx, sw, dev, pairs_per_size=2048, reps=20):
+    """Each window size alone, as in the multi-level workload (2048 pairs per
+    size): windows on a regular grid over an 8192^2 section pair (B = bilinear
+    affine warp of A plus noise), identity affines, p = 0.65, the plan the
+    tuner chose.  Median of `reps` graph replays per size, per-kernel HIP-event
+    timing, and the size's bound: the FP32 vector ALUs for n <= 128 (the
+    one-workgroup kernel keeps the spectra in LDS; 7.5 n^2 log2 n^2 + 40 n^2
+    flop per pair), HBM for n >= 256 (inputs, record and one write + read of
+    each exchanged spectrum per pair)."""
+    import numpy as np
+    import torch
+
+    from datagen import make_section_pair
+    a, b, _, _ = make_section_pair(8192, 8192, 3, 303, device=dev)
+    out_all = {}
+    for n in sw.SIZES:
+        g = int(np.ceil(np.sqrt(pairs_per_size)))
+        xs = np.linspace(n / 2 + 2, 8192 - n / 2 - 2, g)
+        cx, cy = np.meshgrid(xs, xs)
+        th = np.zeros((g * g, 8), np.float32)
+        th[:, 0], th[:, 1], th[:, 2], th[:, 6] = cx.ravel(), cy.ravel(), 1, 1
+        th = th[:pairs_per_size]
+        P = th.shape[0]
+        t = torch.from_numpy(th).to(dev)
+        z = torch.zeros(P, dtype=torch.int32, device=dev)
+        prep = ctx.prepare([a, b], [n] * P, z, z + 1, t, t.clone())
+        params = sw.make_params(p=P_WHITEN)
+        need, _ = ctx.workspace_size(prep["pairs"], params)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=dev)
+        ms = median_event_ms(lambda: ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws,
+                                                         graph=True), reps)
+        ctx.profile(True)
+        with one_chunk(ctx, [n]):
+            for _ in range(5):
+                ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws)
+            torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        d = dict(pairs=P, median_ms=ms, pairs_per_s=P / (ms / 1e3),
+                 kernels_one_chunk_ms={k: v[1] / v[0] for k, v in prof.items()},
+                 plan=dict(zip(("fwd_rows", "inv_rows", "chunks"), ctx.plan(n, full=True))))
+        if n <= 128:
+            tf = P * pair_flops(n) / (ms / 1e3) / 1e12
+            d["roofline"] = dict(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                                 frac=tf / FP32_PEAK_TFLOPS, flop_per_pair=pair_flops(n))
+        else:
+            gbs = P * pair_bytes(n) / (ms / 1e3) / 1e9
+            d["roofline"] = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                                 bytes_per_pair=pair_bytes(n))
+        out_all[str(n)] = d
+        del ws
+    return out_all
 
 
 # --------------------------------------------------------------------------- refinement on the ragged levels
@@ -653,12 +733,13 @@ def pearson_block(ctx, sw, stack, refs, table, images, pairs, res_w, args, prof_
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
     ctx.profile(True)
-    for _ in range(prof_steps):
-        step()
-    torch.cuda.synchronize()
+    with one_chunk(ctx, [N]):
+        for _ in range(prof_steps):
+            step()
+        torch.cuda.synchronize()
     rows = kept_rows(N, N // 4, ctx.plan(N)[1])
     kp, roof = variant_kernels(ctx.profile_read(), N, P, rows, True,
-                               os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pearson.txt"))
+                               os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pearson.txt"), steps=prof_steps)
     ctx.profile(False)
     r = sw.parse_records(out)
     same = (r["ix"] == res_w["ix"]) & (r["iy"] == res_w["iy"])
@@ -1015,7 +1096,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the plain vs adjoint refinement comparison")
     ap.add_argument("--no-stack", action="store_true", help="skip the iterative stack-alignment run")
-    ap.add_argument("--no-ragged", action="store_true", help="skip the multi-level ragged batch comparison")
+    ap.add_argument("--no-ragged", action="store_true", help="(kept for old command lines; the ragged block is off "
+                                                                 "unless --ragged is given)")
+    ap.add_argument("--ragged", action="store_true",
+                    help="run the multi-level ragged batch comparison and the refinement on it")
+    ap.add_argument("--no-sizes", action="store_true", help="skip the per-size roofline block")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default row-count plan (no tuning launches)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the local-affine mesh run")
     ap.add_argument("--no-prune", action="store_true", help="skip the pruned-inverse (search radius) variant")
@@ -1100,14 +1185,15 @@ def main():
     # live per-kernel timing (HIP events on the launch stream), same work
     ctx.profile(True)
     prof_steps = max(3, min(args.steps, 10))
-    for _ in range(prof_steps):
-        step()
-    torch.cuda.synchronize()
+    with one_chunk(ctx, [N]):
+        for _ in range(prof_steps):
+            step()
+        torch.cuda.synchronize()
     kt = ctx.profile_read()
     ctx.profile(False)
     kernels = {}
     for name, (cnt, tot) in kt.items():
-        b = kernel_bytes(name, N, P, S_SECTIONS, SIZE)
+        b = kernel_bytes(name, N, P * prof_steps / cnt, S_SECTIONS, SIZE)
         avg = tot / cnt
         kernels[name] = dict(launches=cnt, avg_ms=avg, bytes=b, gbs=b / (avg / 1e3) / 1e9)
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
@@ -1121,7 +1207,9 @@ def main():
         traffic = None
     roof = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=d["gbs"] / HBM_PEAK_GBS, traffic=traffic,
-                bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"])
+                bytes_per_launch=d["bytes"], avg_ms=d["avg_ms"],
+                timing="HIP events on the launch stream over %d steps, the batch as one chunk (every launch covers "
+                       "all %d pairs)" % (prof_steps, P))
     # LDS bytes per launch of the three passes (rocprofv3 LDS load/store
     # bandwidth counters, valid for the kernel sources they were taken on)
     # over the live launch times
@@ -1160,12 +1248,14 @@ def main():
         torch.cuda.synchronize()
         ms_p = (time.perf_counter() - t0) / args.steps * 1e3
         ctx.profile(True)
-        for _ in range(prof_steps):
-            step_p()
-        torch.cuda.synchronize()
+        with one_chunk(ctx, [N]):
+            for _ in range(prof_steps):
+                step_p()
+            torch.cuda.synchronize()
         rows_p = kept_rows(N, PRUNE_R, ctx.plan(N)[1])
         kp, roof_p = variant_kernels(ctx.profile_read(), N, P, rows_p, False,
-                                     os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pruned_r64.txt"))
+                                     os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pruned_r64.txt"),
+                                     steps=prof_steps)
         ctx.profile(False)
         rp = sw.parse_records(out_p)
         same = (rp["ix"] == res["ix"]) & (rp["iy"] == res["iy"])
@@ -1301,7 +1391,16 @@ def main():
                                             c2["roofline"]["kernel"], c2["roofline"]["achieved"],
                                             c2["roofline"]["frac"], c2["shift_error_px"]["median"]))
         torch.cuda.empty_cache()
-    if not args.no_ragged:
+    if not args.no_sizes:
+        log("per-size rooflines: 2048 pairs of each size on an 8192^2 section pair ...")
+        torch.cuda.empty_cache()
+        line["sizes"] = size_rooflines(ctx, sw, dev)
+        for k, v in line["sizes"].items():
+            log("  n=%s: %.3f ms for %d pairs (%.0f pairs/s), %s %.1f %s (%.3f of peak), plan %s"
+                % (k, v["median_ms"], v["pairs"], v["pairs_per_s"], v["roofline"]["bound"], v["roofline"]["achieved"],
+                   v["roofline"]["unit"], v["roofline"]["frac"], v["plan"]))
+        torch.cuda.empty_cache()
+    if args.ragged and not args.no_ragged:
         log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
         del stack, refs, images, table, out
         torch.cuda.empty_cache()

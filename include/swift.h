@@ -512,7 +512,9 @@ int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a
  *    chunks of consecutive pairs whose kernel sequences alternate between two
  *    streams of the context (forked from and joined back into the call's
  *    stream), so that one chunk's forward row pass runs beside another's
- *    column pass.  The records are identical to those of one chunk.
+ *    column pass.  The records are identical to those of one chunk.  A batch
+ *    whose size groups run concurrently (SWIFT_FLAG_CONCURRENT_SIZES, or
+ *    swift_match_graph with several sizes) runs each group as one chunk.
  * swift_plan sets the variants of size n (a value < 0 keeps the current one)
  * and reports the rows per block and the chunks (any output may be NULL).
  * Plans are per context; cached graphs are keyed by them.  Errors:

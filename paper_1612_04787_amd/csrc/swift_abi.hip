@@ -683,7 +683,9 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    const int nch = allow_chunks ? min((int)ctx->chunks[i], g.count) : 1;
+    // chunks split one group's passes over two streams; groups that already
+    // run concurrently on their own streams are not split further
+    const int nch = (allow_chunks && !concurrent) ? min((int)ctx->chunks[i], g.count) : 1;
     if (nch <= 1) {
       e = launch_match_group(g.n, a, ctx->alt_fwd[i], ctx->alt_inv[i] != 0, s, kt);
       if (e != hipSuccess) return hip_fail(e, "match launch");
