@@ -1218,7 +1218,10 @@ def main():
     for kname, kv in kernels.items():
         if not kname.startswith(("k_row_fwd", "k_col", "k_row_inv")):
             continue
-        b, busy, dg = read_lds(LDS_FILE, kname)
+        # the library's timer names the column pass k_col<N>; rocprofv3 sees
+        # the instance that runs below 1024^2, k_col_pair<N>
+        lname = kname.replace("k_col<", "k_col_pair<") if N < 1024 else kname
+        b, busy, dg = read_lds(LDS_FILE, lname)
         if b is None or dg != digest_now:
             continue
         gbs = b / (kv["avg_ms"] / 1e3) / 1e9
@@ -1254,7 +1257,7 @@ def main():
             torch.cuda.synchronize()
         rows_p = kept_rows(N, PRUNE_R, ctx.plan(N)[1])
         kp, roof_p = variant_kernels(ctx.profile_read(), N, P, rows_p, False,
-                                     os.path.join(ROOT, "profiles", "hbm_traffic_match_512_pruned_r64.txt"),
+                                     TRAFFIC_FILE,
                                      steps=prof_steps)
         ctx.profile(False)
         rp = sw.parse_records(out_p)

@@ -278,10 +278,11 @@ int swift_project(swift_ctx* ctx, const uint8_t* stack, int32_t S, int32_t heigh
                   int64_t pitch, int64_t section_stride, const uint8_t* exclude, int32_t k,
                   uint8_t* out, int64_t out_pitch, int64_t out_section_stride, hipStream_t stream);
 
-/* Jump repair (Section III, model paragraphs): where an abrupt content or
- * magnification change locks a section's match to one side of its model, the
- * offending sections are matched separately to the models on either side and
- * a smoothing curve is built across the failed span.
+/* Jump repair (Section III, model paragraphs).  An abrupt change of content
+ * or magnification can make a section's match lock to one side of its model.
+ * The sections involved are then fitted against a left-only and a right-only
+ * model, and the affines across the failed span follow a smooth curve between
+ * the two fits.
  *
  * One-sided models: as swift_project, but out[s] is the rounded mean of the
  * included sections s-k..s-1 (side = -1) or s+1..s+k (side = +1) only.

@@ -826,11 +826,11 @@ def pearson_pair(imgA, imgB, thetaA, thetaB, n, return_surface=False):
 
 
 # ---------------------------------------------------------------------------
-# Jump repair (Section III, model paragraphs): where an abrupt content or
-# magnification change makes a section's match lock to one side of its
-# two-sided model, the offending sections are matched separately to the
-# models on either side, and a smoothing curve is built across the failed
-# span.  Design readings: the one-sided models are the rounded means of the
+# Jump repair (Section III, model paragraphs).  An abrupt change of content
+# or magnification can lock a section's match to one side of its two-sided
+# model.  The sections involved are then fitted against a left-only and a
+# right-only model, and the affines across the failed span follow a smooth
+# curve between the two fits.  Design readings: the one-sided models are the rounded means of the
 # k sections before (side -1) or after (side +1), offending ones omitted; the
 # curve is the cubic Bezier with control values 0, 0, 1, 1 (zero slope at
 # both ends) blending, per affine entry, the left-model fit into the

@@ -36,18 +36,28 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
+def _code_only(text: str) -> bytes:
+    """The source without its comments and blank lines (comments change
+    nothing the counters measure)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.strip() for ln in text.splitlines()]
+    return "\n".join(ln for ln in lines if ln).encode()
+
+
 def source_digest() -> str:
-    """SHA-256 over the HIP sources and headers of the library (sorted by name)."""
+    """SHA-256 over the code of the library's HIP sources and headers (sorted
+    by name), comments and blank lines left out."""
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
         if f.endswith((".hip", ".hpp", ".h")):
             h.update(f.encode())
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+                h.update(_code_only(fh.read()))
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "swift.h")
     if os.path.exists(inc):
-        with open(inc, "rb") as fh:
-            h.update(fh.read())
+        with open(inc, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()))
     return h.hexdigest()
 
 
