@@ -431,7 +431,10 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
   constexpr int RS = lidx(N) + 1;
-  constexpr int BUDGET = RowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
+  // the adjoint's row pass keeps its stage and tile in separate arrays; at
+  // 1024^2 both would not leave room for two workgroups per CU, so it
+  // gathers from memory there
+  constexpr int BUDGET = N >= 1024 ? 0 : RowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
   __shared__ __align__(16) uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair

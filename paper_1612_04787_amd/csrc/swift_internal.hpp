@@ -152,8 +152,8 @@ template <> struct RowsCfg<256>  { static constexpr int FWD = 16, INV = 16, TILE
                                    FWD2 = 8,  INV2 = 32, TILE2 = 5632, TRW2 = 3; };
 template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE = 11264, TRW = 5,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 8576, TRW2 = 4; };
-template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 0,     TRW = 1,
-                                   FWD2 = 4,  INV2 = 8,  TILE2 = 0,    TRW2 = 1; };
+template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 24576, TRW = 6,
+                                   FWD2 = 4,  INV2 = 8,  TILE2 = 16384, TRW2 = 4; };
 
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 

@@ -20,13 +20,21 @@ struct TileGeom {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Chunks per tile row that one load covers: a power of two >= N/16 + 2 (the
-// chunks of a translation window's rows), at most 64.
+// Chunks per tile row: a power of two >= N/16 + 2 (the chunks of a
+// translation window's rows), at most 128.  Up to 64 a wave load covers
+// 64 / CW whole rows; at 128 (N = 1024) a row takes two wave loads.
 template <int N>
 __host__ __device__ constexpr int tile_cw() {
   int c = 1;
-  while (c < N / 16 + 2 && c < 64) c *= 2;
+  while (c < N / 16 + 2 && c < 128) c *= 2;
   return c;
+}
+// Tile rows per wave load, and wave loads per tile row.
+template <int CW> __host__ __device__ constexpr int tile_rpl() { return CW <= 64 ? 64 / CW : 1; }
+template <int CW> __host__ __device__ constexpr int tile_lpr() { return CW <= 64 ? 1 : CW / 64; }
+// Tile rows that TRW loads per thread of NWV waves cover.
+template <int CW, int TRW, int NWV> __host__ __device__ constexpr int tile_rows_cap() {
+  return TRW * NWV * tile_rpl<CW>() / tile_lpr<CW>();
 }
 
 // Per image and workgroup: affine of the window rows [y0, y0 + R).
@@ -88,7 +96,7 @@ __device__ __forceinline__ TileGeom tile_geom(const RowAffine& ra, const swift_i
   g.ts = g.wt4;
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
-  g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= TRW * NWV * (64 / CW) && w16 <= CW;
+  g.use = (long long)w16 * 16 * g.ht <= BUDGET && g.ht <= tile_rows_cap<CW, TRW, NWV>() && w16 <= CW;
   return g;
 }
 
@@ -116,30 +124,44 @@ __device__ __forceinline__ TileGeom tile_geom_trans(int bx0, int by0, bool finit
   g.ht = yh - yl + 1;
   constexpr int CW = tile_cw<N>();
   g.ts = 4 * CW;
-  g.use = CW * 16 * g.ht <= BUDGET && g.ht <= TRW * NWV * (64 / CW) && w16 <= CW;
+  g.use = CW * 16 * g.ht <= BUDGET && g.ht <= tile_rows_cap<CW, TRW, NWV>() && w16 <= CW;
   return g;
 }
 
 // Tiles are fetched in two steps so all loads are in flight at once:
 // tile_fetch issues every global load of a thread into registers and nothing
-// consumes them until tile_store writes them to LDS.  Lane l of wave w takes
-// chunk c = l % CW of tile row (NWV j + w) (64 / CW) + l / CW in load j (rows
-// past the tile repeat its last row, which the cache serves).  Loads are
-// unconditional and in bounds: rows are clamped into the image and a chunk
-// left or right of the image is read at the nearest in-image chunk; on
-// workgroups whose tile crosses the border, tile_store replaces such a chunk
-// by its edge byte repeated, so byte i holds img[clamp(y)][clamp(x + i)].
+// consumes them until tile_store writes them to LDS.  With CW <= 64, lane l
+// of wave w takes chunk c = l % CW of tile row (NWV j + w) (64 / CW) + l / CW
+// in load j; with CW = 128, loads 2i and 2i + 1 take chunks l and l + 64 of
+// tile row NWV i + w (rows past the tile repeat its last row, which the cache
+// serves).  Loads are unconditional and in bounds: rows are clamped into the
+// image and a chunk left or right of the image is read at the nearest
+// in-image chunk; on workgroups whose tile crosses the border, tile_store
+// replaces such a chunk by its edge byte repeated, so byte i holds
+// img[clamp(y)][clamp(x + i)].
+template <int CW>
+__device__ __forceinline__ void tile_slot(int j, int wv, int ln, int nwv, int& ty, int& c) {
+  constexpr int RPL = tile_rpl<CW>(), LPR = tile_lpr<CW>();
+  if constexpr (LPR == 1) {
+    c = ln % CW;
+    ty = (nwv * j + wv) * RPL + ln / CW;
+  } else {
+    c = ln + 64 * (j % LPR);
+    ty = nwv * (j / LPR) + wv;
+  }
+}
+
 template <int CW, int RW, int NWV = 4>
 __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, const swift_image& im, int tid) {
-  constexpr int RPL = 64 / CW;  // tile rows per load of a wave
   const gptr<unsigned char> base = to_global<unsigned char>(im.data);
-  // the wave index is uniform: with one tile row per load (RPL = 1) the row
-  // address is scalar and a load adds only the lane's 32-bit offset
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63, c = ln % CW, sr = ln / CW;
-  const uint32_t xc = (uint32_t)min(max(g.xlo + 16 * c, 0), im.width - 16);
+  // the wave index is uniform: with one tile row per load the row address is
+  // scalar and a load adds only the lane's 32-bit offset
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int ty = (NWV * j + wv) * RPL + sr;
+    int ty, c;
+    tile_slot<CW>(j, wv, ln, NWV, ty, c);
+    const uint32_t xc = (uint32_t)min(max(g.xlo + 16 * c, 0), im.width - 16);
     const int yy = min(max(g.ylo + min(ty, g.ht - 1), 0), im.height - 1);
     const gptr<unsigned char> row = base + (int64_t)yy * im.pitch;
     const u32x4 v = *(gptr<u32x4>)(row + xc);
@@ -150,13 +172,13 @@ __device__ __forceinline__ void tile_fetch(uint4 (&buf)[RW], const TileGeom& g, 
 template <int CW, int RW, int NWV = 4>
 __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const uint4 (&buf)[RW], const TileGeom& g,
                                            const swift_image& im, bool border, int tid) {
-  constexpr int RPL = 64 / CW;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63, c = ln % CW, sr = ln / CW;
-  const int x = g.xlo + 16 * c;
-  const bool left = border && x < 0, right = border && x >= im.width;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;
 #pragma unroll
   for (int j = 0; j < RW; ++j) {
-    const int ty = (NWV * j + wv) * RPL + sr;
+    int ty, c;
+    tile_slot<CW>(j, wv, ln, NWV, ty, c);
+    const int x = g.xlo + 16 * c;
+    const bool left = border && x < 0, right = border && x >= im.width;
     if (ty < g.ht && 4 * c < g.ts) {
       uint4 v = buf[j];
       if (left | right) {
