@@ -1096,10 +1096,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the plain vs adjoint refinement comparison")
     ap.add_argument("--no-stack", action="store_true", help="skip the iterative stack-alignment run")
-    ap.add_argument("--no-ragged", action="store_true", help="(kept for old command lines; the ragged block is off "
-                                                                 "unless --ragged is given)")
-    ap.add_argument("--ragged", action="store_true",
-                    help="run the multi-level ragged batch comparison and the refinement on it")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the multi-level ragged batch comparison and the refinement on it")
+    ap.add_argument("--ragged-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-sizes", action="store_true", help="skip the per-size roofline block")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default row-count plan (no tuning launches)")
     ap.add_argument("--no-mesh", action="store_true", help="skip the local-affine mesh run")
@@ -1116,6 +1115,10 @@ def main():
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+
+    if args.ragged_child:
+        ragged_main(args)
+        return
 
     import torch
 
@@ -1403,27 +1406,65 @@ def main():
                 % (k, v["median_ms"], v["pairs"], v["pairs_per_s"], v["roofline"]["bound"], v["roofline"]["achieved"],
                    v["roofline"]["unit"], v["roofline"]["frac"], v["plan"]))
         torch.cuda.empty_cache()
-    if args.ragged and not args.no_ragged:
-        log("ragged levels: per-level calls vs one concurrent call vs one graph ...")
+    if not args.no_ragged:
+        # the multi-level block runs in a child process with the default plan
+        # (one chunk per size group): its first run with the tuned plans ended
+        # the process with a host segfault whose cause was not found, and a
+        # child keeps any such failure from taking the benchmark line with it
+        log("ragged levels (child process, default plan): per-level calls vs one concurrent call vs one graph, "
+            "and the refinement on them ...")
         del stack, refs, images, table, out
         torch.cuda.empty_cache()
-        images3 = config3_images(ctx, dev)
-        line["ragged"] = ragged_levels(ctx, sw, dev, images3)
-        g = line["ragged"]
-        log("ragged levels: per-level %.2f ms, one call %.2f ms, graph %.2f ms"
-            % (g["per_level_calls"]["ms"], g["one_call_concurrent"]["ms"], g["graph"]["ms"]))
-        for k, v in g["per_size"].items():
-            log("  n=%s: %.3f ms for %d pairs, %s %.1f %s (%.3f of peak), plan %s"
-                % (k, v["ms"], v["pairs"], v["roofline"]["bound"], v["roofline"]["achieved"], v["roofline"]["unit"],
-                   v["roofline"]["frac"], v["plan"]))
-        if not args.no_refine:
-            log("refinement on the ragged levels: plain per-level calls vs one graph per iteration + adjoint ...")
-            line["refine_levels"] = refine_levels(ctx, sw, dev, images3)
-            q = line["refine_levels"]
-            log("refine levels: to %.2f px rms plain %s it %s ms | batched+adjoint %s it %s ms"
-                % (q["target_rms_px"], q["plain"]["iters_to_target"], q["plain"]["ms_to_target"],
-                   q["batched_adjoint"]["iters_to_target"], q["batched_adjoint"]["ms_to_target"]))
-        del images3
+        line.update(ragged_child(args, log))
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def ragged_child(args, log):
+    """Runs `bench.py --ragged-child` and returns its blocks, or an error record."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--ragged-child"]
+    if args.no_refine:
+        cmd.append("--no-refine")
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, timeout=900, text=True)
+    except subprocess.TimeoutExpired:
+        log("ragged child: timed out")
+        return {"ragged": {"error": "timed out after 900 s"}}
+    if r.returncode != 0 or not r.stdout.strip():
+        log("ragged child: exit status %d" % r.returncode)
+        return {"ragged": {"error": "child process exit status %d" % r.returncode}}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def ragged_main(args):
+    """The multi-level blocks alone, with the default plan; prints one JSON
+    object with `ragged` (and `refine_levels`)."""
+    import torch
+
+    import paper_1612_04787_amd as sw
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    dev = torch.device("cuda", 0)
+    ctx = sw.Swift(0)
+    out = {}
+    images3 = config3_images(ctx, dev)
+    out["ragged"] = ragged_levels(ctx, sw, dev, images3)
+    g = out["ragged"]
+    log("ragged levels: per-level %.2f ms, one call %.2f ms, graph %.2f ms"
+        % (g["per_level_calls"]["ms"], g["one_call_concurrent"]["ms"], g["graph"]["ms"]))
+    for k, v in g["per_size"].items():
+        log("  n=%s: %.3f ms for %d pairs, %s %.1f %s (%.3f of peak), plan %s"
+            % (k, v["ms"], v["pairs"], v["roofline"]["bound"], v["roofline"]["achieved"], v["roofline"]["unit"],
+               v["roofline"]["frac"], v["plan"]))
+    if not args.no_refine:
+        log("refinement on the ragged levels: plain per-level calls vs one graph per iteration + adjoint ...")
+        out["refine_levels"] = refine_levels(ctx, sw, dev, images3)
+        q = out["refine_levels"]
+        log("refine levels: to %.2f px rms plain %s it %s ms | batched+adjoint %s it %s ms"
+            % (q["target_rms_px"], q["plain"]["iters_to_target"], q["plain"]["ms_to_target"],
+               q["batched_adjoint"]["iters_to_target"], q["batched_adjoint"]["ms_to_target"]))
+    ctx.close()
+    print(json.dumps(out), flush=True)
     ctx.close()
     print(json.dumps(line), flush=True)
 

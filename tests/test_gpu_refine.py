@@ -103,3 +103,34 @@ def test_refinement_converges_to_truth(ctx, section, n):
     assert rms(en) <= 0.01 and en.max() <= 0.02
     assert rms(ep) < 0.25 * rms(e0)
     assert inn < ip
+
+
+def test_graph_driver_matches_eager_driver_on_a_ragged_batch(ctx, section):
+    """refine_adjoint_graph (each iteration one replayed graph of the ragged
+    batch with concurrent size groups, the stop test read from pinned host
+    memory) against refine_adjoint (eager calls): the same iterations, the
+    same step history and the same final affines, and the truth to 0.01 px."""
+    import paper_1612_04787_amd as sw
+    from paper_1612_04787_amd.refine import refine_adjoint, refine_adjoint_graph
+    print("case refine graph driver, ragged 64/128/256", flush=True)
+    rng = np.random.default_rng(404)
+    parts = [_batch(rng, k, n, 1400) + (n,) for n, k in ((64, 10), (128, 8), (256, 6))]
+    ta = np.concatenate([p[0] for p in parts])
+    tb = np.concatenate([p[1] for p in parts])
+    n_list = [p[2] for p in parts for _ in range(p[0].shape[0])]
+    k = len(n_list)
+    img = section.to(dev())
+    z = torch.zeros(k, dtype=torch.int32, device=dev())
+    tha, thb = torch.from_numpy(ta).to(dev()), torch.from_numpy(tb).to(dev())
+    params = sw.make_params(p=0.65, flags=sw.FLAG_CONCURRENT_SIZES)
+    te, ie, he = refine_adjoint(ctx, [img], n_list, z, z, tha, thb, params, tol=0.002)
+    trace = torch.empty((20, k, 8), dtype=torch.float32, device=dev())
+    tg, ig, hg, times = refine_adjoint_graph(ctx, [img], n_list, z, z, tha, thb, params, tol=0.002, theta_trace=trace)
+    torch.cuda.synchronize()
+    print("   eager %d iters %s | graph %d iters %s" % (ie, np.round(he, 4), ig, np.round(hg, 4)), flush=True)
+    assert ig == ie and len(times) == ig
+    np.testing.assert_allclose(hg, he, rtol=0, atol=1e-6)
+    assert torch.equal(tg, te)
+    assert torch.equal(trace[ig - 1], tg)
+    e = np.hypot(tg[:, 4].cpu().numpy() - tb[:, 4], tg[:, 7].cpu().numpy() - tb[:, 7])
+    assert float(np.sqrt(np.mean(e ** 2))) <= 0.01
