@@ -1465,8 +1465,6 @@ def ragged_main(args):
                q["batched_adjoint"]["iters_to_target"], q["batched_adjoint"]["ms_to_target"]))
     ctx.close()
     print(json.dumps(out), flush=True)
-    ctx.close()
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
