@@ -173,7 +173,7 @@ struct GroupLayout {
   int count = 0;
   int first = 0;  // index of the group's first pair
   // forward
-  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, colsq = 0, ncc_rows = 0, ncc_var = 0;
+  size_t z = 0, rowpart = 0, pstat = 0, invpart = 0, colsq = 0, ncc_rows = 0, ncc_var = 0, geom = 0;
   // adjoint
   size_t y = 0, dpart = 0, rpart = 0;
   // saved state (offsets into the saved buffer)
@@ -228,6 +228,8 @@ Layout make_layout(const swift_pairs* pairs, bool pearson = false) {
     fo += align256(P * (size_t)max(inv_blocks_n(g.n, false), inv_blocks_n(g.n, true)) * sizeof(InvPart));
     g.colsq = fo;
     fo += align256(P * (n / 2 + 1) * sizeof(double));
+    g.geom = fo;
+    fo += align256(P * sizeof(PairGeom));
     if (pearson) {
       g.ncc_rows = fo;
       fo += align256(P * n * (n / 2 + 1) * sizeof(float2));
@@ -558,6 +560,7 @@ static int enqueue_chunks(swift_ctx* ctx, int i, const GroupLayout& g, const Mat
     b.Z += p0 * n * n;
     b.rowpart += p0 * (size_t)a.nsl_fwd;
     b.pstat += p0;
+    b.geom += p0;
     b.invpart += p0 * (size_t)a.nsl_inv;
     b.colsq += p0 * (n / 2 + 1);
     if (b.ncc_rows) b.ncc_rows += p0 * n * (n / 2 + 1);
@@ -644,6 +647,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.rowpart = (RowPart*)(base + g.rowpart);
     a.pstat = (PairStat*)(base + g.pstat);
     a.invpart = (InvPart*)(base + g.invpart);
+    a.geom = (PairGeom*)(base + g.geom);
     a.tw = ctx->tw;
     a.tau = tau;
     a.taper = taper;

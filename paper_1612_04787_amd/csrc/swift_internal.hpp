@@ -43,6 +43,19 @@ struct PairStat {
   int32_t pad[2];
 };
 
+// Per pair and image, computed once per pair before the forward row pass:
+// the window's origin split into integer and fractional parts, whether its
+// linear part is the identity, and its offset (the centre pixel).
+struct WinGeom {
+  int32_t bx0, by0;  // floor(cx + tx), floor(cy + ty) (clamped to +-1e9)
+  float fx, fy;      // the fractional parts
+  float off;         // img[clamp(floor(y + 1/2))][clamp(floor(x + 1/2))]
+  int32_t flags;     // bit 0: translation window; bit 1: origin within +-1e8
+};
+struct PairGeom {
+  WinGeom w[2];      // A, B
+};
+
 // Per row-slice partials of the inverse row pass.
 struct InvPart {
   float m1;       // largest value
@@ -71,6 +84,7 @@ struct MatchArgs {
   RowPart* rowpart;     // [P][NSLICE]
   PairStat* pstat;      // [P]
   InvPart* invpart;     // [P][NSL2]
+  PairGeom* geom;       // [P]
   const float2* tw;     // W_1024 table
   const float2* tau;    // [N]
   const float* taper;   // [N] t(i)

@@ -359,6 +359,37 @@ __device__ void pearson_rows(float2* __restrict__ stage, const MatchArgs& a, int
   s[2] = s[0];  // sum a' T^2 with a 0/1 template mask
 }
 
+// ---------------------------------------------------------------- per-pair geometry
+// One thread per pair: the FP64 part of the window set-up that every row
+// block of the pair would otherwise repeat (origin split, translation test,
+// centre pixel).
+__global__ void __launch_bounds__(256) k_pair_geom(MatchArgs a) {
+  const int pair = blockIdx.x * 256 + threadIdx.x;
+  if (pair >= a.npairs) return;
+  const int kk[2] = {min(max(a.img_a[pair], 0), a.n_imgs - 1), min(max(a.img_b[pair], 0), a.n_imgs - 1)};
+  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  PairGeom pg;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    swift_image im = a.imgs[kk[m]];
+    im.width = max(im.width, 2);
+    im.height = max(im.height, 2);
+    const RowAffine ra = row_affine(th[m]);
+    const bool trans = ra.a11 == 1.0 && ra.a12 == 0.0 && ra.a21 == 0.0 && ra.a22 == 1.0;
+    const double X = fmin(fmax(ra.xc, -1e9), 1e9), Y = fmin(fmax(ra.yc, -1e9), 1e9);
+    const double fxd = floor(X), fyd = floor(Y);
+    WinGeom w;
+    w.bx0 = (int)fxd;
+    w.by0 = (int)fyd;
+    w.fx = (float)(X - fxd);
+    w.fy = (float)(Y - fyd);
+    w.off = centre_pixel(im, ra);
+    w.flags = (trans ? 1 : 0) | ((fabs(X) < 1e8 && fabs(Y) < 1e8) ? 2 : 0);
+    pg.w[m] = w;
+  }
+  a.geom[pair] = pg;
+}
+
 template <int N, int R, int BUDGET, int TRW, bool PEARSON>
 __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   using C = FftCfg<N>;
@@ -385,6 +416,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
   swift_image im[2] = {a.imgs[ka], a.imgs[kb]};
   const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  const PairGeom pg = a.geom[pair];  // origin split, translation test, offsets (k_pair_geom)
   RowAffine ra[2];
   TileGeom tg[2];
   bool border[2], trans[2];
@@ -394,22 +426,24 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   for (int m = 0; m < 2; ++m) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
-    ra[m] = row_affine(th[m]);
     // translation windows (identity linear part) take the constant-weight
     // gather, and their tile geometry and row parameters are integer offsets
-    // from floor(cx + tx), floor(cy + ty)
-    trans[m] = ra[m].a11 == 1.0 && ra[m].a12 == 0.0 && ra[m].a21 == 0.0 && ra[m].a22 == 1.0;
+    // from floor(cx + tx), floor(cy + ty); only other windows need the affine
+    trans[m] = (pg.w[m].flags & 1) != 0;
     if (trans[m]) {
-      const double X = fmin(fmax(ra[m].xc, -1e9), 1e9), Y = fmin(fmax(ra[m].yc, -1e9), 1e9);
-      const double fxd = floor(X), fyd = floor(Y);
-      const bool finite = fabs(X) < 1e8 && fabs(Y) < 1e8;
-      const int bx0 = (int)fxd, by0 = (int)fyd;
-      tg[m] = tile_geom_trans<N, R, BUDGET, TRW>(bx0, by0, finite, im[m], y0);
+      const int bx0 = pg.w[m].bx0, by0 = pg.w[m].by0;
+      tg[m] = tile_geom_trans<N, R, BUDGET, TRW>(bx0, by0, (pg.w[m].flags & 2) != 0, im[m], y0);
       pt[m].bx = bx0 - (tg[m].use ? tg[m].xlo : 0);
       pt[m].by = by0 + (y0 + M::row0(tid) - N / 2) - (tg[m].use ? tg[m].ylo : 0);
-      pt[m].fx = (float)(X - fxd);
-      pt[m].fy = (float)(Y - fyd);
+      pt[m].fx = pg.w[m].fx;
+      pt[m].fy = pg.w[m].fy;
+      ra[m].xc = ra[m].yc = 0.0;
+      ra[m].a11 = ra[m].a22 = 1.0;
+      ra[m].a12 = ra[m].a21 = 0.0;
+      ra[m].f11 = 1.0f;
+      ra[m].f21 = 0.0f;
     } else {
+      ra[m] = row_affine(th[m]);
       tg[m] = tile_geom<N, R, BUDGET, TRW>(ra[m], im[m], y0);
       pt[m].bx = pt[m].by = 0;
       pt[m].fx = pt[m].fy = 0.0f;
@@ -429,24 +463,33 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     // send them to per-lane scratch memory)
     const bool mb = tid >= R;
     const int r = tid % R;
-    const double xc = mb ? ra[1].xc : ra[0].xc, yc = mb ? ra[1].yc : ra[0].yc;
-    const double a12 = mb ? ra[1].a12 : ra[0].a12, a22 = mb ? ra[1].a22 : ra[0].a22;
     const int xo = mb ? (tg[1].use ? tg[1].xlo : 0) : (tg[0].use ? tg[0].xlo : 0);
     const int yo = mb ? (tg[1].use ? tg[1].ylo : 0) : (tg[0].use ? tg[0].ylo : 0);
-    const double v = (double)(y0 + r - N / 2);
-    const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
-    const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
-    const double bxd = floor(X), byd = floor(Y);
     RowParam p;
-    p.bx = (int)bxd - xo;
-    p.by = (int)byd - yo;
-    p.fx = (float)(X - bxd);
-    p.fy = (float)(Y - byd);
+    if (mb ? trans[1] : trans[0]) {
+      // a translation window's row r is its origin moved down by v rows
+      const WinGeom& w = mb ? pg.w[1] : pg.w[0];
+      p.bx = w.bx0 - xo;
+      p.by = w.by0 + (y0 + r - N / 2) - yo;
+      p.fx = w.fx;
+      p.fy = w.fy;
+    } else {
+      const double xc = mb ? ra[1].xc : ra[0].xc, yc = mb ? ra[1].yc : ra[0].yc;
+      const double a12 = mb ? ra[1].a12 : ra[0].a12, a22 = mb ? ra[1].a22 : ra[0].a22;
+      const double v = (double)(y0 + r - N / 2);
+      const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
+      const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
+      const double bxd = floor(X), byd = floor(Y);
+      p.bx = (int)bxd - xo;
+      p.by = (int)byd - yo;
+      p.fx = (float)(X - bxd);
+      p.fy = (float)(Y - byd);
+    }
     rparam[mb ? 1 : 0][r] = p;
   }
   if (tid >= 64 && tid < 64 + R) trow[tid - 64] = a.taper[y0 + tid - 64];
-  // the offsets: every block of the pair reads the same centre pixels
-  const float off[2] = {centre_pixel(im[0], ra[0]), centre_pixel(im[1], ra[1])};
+  // the offsets: the centre pixels, the same for every block of the pair
+  const float off[2] = {pg.w[0].off, pg.w[1].off};
   float tx[XV], ku[2][2][XV];
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
@@ -1188,6 +1231,10 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   if (a.max_shift > 0 ? (a.nsl_inv > N / R2 || a.nsl_lo > a.nsl_inv) : (a.nsl_inv != N / R2))
     return hipErrorInvalidValue;
   if (a.pearson && a.max_shift != N / 4) return hipErrorInvalidValue;
+  {
+    TimerScope ts(kt, "k_pair_geom", N, s);
+    k_pair_geom<<<(P + 255) / 256, 256, 0, s>>>(a);
+  }
   {
     TimerScope ts(kt, "k_row_fwd", N, s);
     if (a.pearson)
