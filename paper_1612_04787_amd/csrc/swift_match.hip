@@ -275,10 +275,15 @@ __device__ __forceinline__ void gather_rows_trans(float2* __restrict__ stage, fl
       // bytes ix + c .. ix + c + 3
       const int oc = (int)sh + c;
       const uint32_t v = __builtin_amdgcn_alignbyte(w[(oc >> 2) + 1], w[oc >> 2], (uint32_t)(oc & 3));
-      const float b0 = (float)(v & 255u), b1 = (float)((v >> 8) & 255u);
+      // the converted bytes go through an empty asm so that b1 - b0 is one
+      // FP32 subtraction of values converted anyway, not an integer
+      // difference converted again
+      float b0 = (float)(v & 255u), b1 = (float)((v >> 8) & 255u);
+      asm("" : "+v"(b0), "+v"(b1));
       h[c] = fmaf(fx, b1 - b0, b0 - o);
       if (c + 1 < XV) {
-        const float b2 = (float)((v >> 16) & 255u);
+        float b2 = (float)((v >> 16) & 255u);
+        asm("" : "+v"(b2));
         h[c + 1] = fmaf(fx, b2 - b1, b1 - o);
       }
     }
@@ -390,104 +395,90 @@ __global__ void __launch_bounds__(256) k_pair_geom(MatchArgs a) {
   a.geom[pair] = pg;
 }
 
-template <int N, int R, int BUDGET, int TRW, bool PEARSON>
-__global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
+// LDS of the forward row pass (one object per workgroup, shared by both
+// variants of the body).
+template <int N, int R, int BUDGET>
+struct FwdLds {
+  using SL = FwdStage<N, R, BUDGET>;
+  __align__(16) float2 stage[R * SL::RS];
+  // + 1: tile_pair reads the dword after a pair
+  __align__(16) uint32_t tile_own[(BUDGET > 0 && !SL::ALIAS) ? BUDGET / 4 + 1 : 1];
+  RowParam rparam[2][R];
+  float trow[R];
+  double red[4][6];
+  int redc[4];
+};
+
+// Per-workgroup set-up of the two windows (image, affine, tile geometry,
+// border test, translation test, first-row parameters of a translation).
+struct FwdWin {
+  swift_image im[2];
+  RowAffine ra[2];
+  TileGeom tg[2];
+  RowParam pt[2];
+  bool border[2], trans[2];
+};
+
+// Body of the forward row pass.  FAST: both windows are translations whose
+// tiles are in use and lie inside their images (the common case), so the
+// gather takes the constant-weight path with no clamping and no per-row
+// parameters; the body is compiled once with these facts as constants and
+// once for the general case.
+template <int N, int R, int BUDGET, int TRW, bool PEARSON, bool FAST>
+__device__ __forceinline__ void row_fwd_body(const MatchArgs& a, FwdLds<N, R, BUDGET>& sh, const FwdWin& wn,
+                                             const PairGeom& pg, int pair, int slice, int y0, int tid) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NSLICE = N / R;
   using SL = FwdStage<N, R, BUDGET>;
   constexpr int RS = SL::RS, FL = SL::FL, NL = SL::NL;
   constexpr int XV = GatherCfg<N>::XV;
-  static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
-  __shared__ __align__(16) float2 stage[R * RS];
-  // + 1: tile_pair reads the dword after a pair
-  __shared__ __align__(16) uint32_t tile_own[(BUDGET > 0 && !SL::ALIAS) ? BUDGET / 4 + 1 : 1];
-  uint32_t* const tile = SL::ALIAS ? reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(stage) + SL::TOFF) : tile_own;
-  __shared__ RowParam rparam[2][R];
-  __shared__ float trow[R];
-  __shared__ double red[4][6];
-  __shared__ int redc[4];
-
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
-  const int tid = threadIdx.x, g = tid / T, t = tid % T;
-
-  // image indices are clamped into the table so a bad index cannot read past it
-  const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
-  const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
-  swift_image im[2] = {a.imgs[ka], a.imgs[kb]};
-  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
-  const PairGeom pg = a.geom[pair];  // origin split, translation test, offsets (k_pair_geom)
-  RowAffine ra[2];
-  TileGeom tg[2];
-  bool border[2], trans[2];
-  RowParam pt[2];  // translation windows: the sampling parameters of the thread's first row
   using M = FwdMap<N, R>;
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    im[m].width = max(im[m].width, 2);
-    im[m].height = max(im[m].height, 2);
-    // translation windows (identity linear part) take the constant-weight
-    // gather, and their tile geometry and row parameters are integer offsets
-    // from floor(cx + tx), floor(cy + ty); only other windows need the affine
-    trans[m] = (pg.w[m].flags & 1) != 0;
-    if (trans[m]) {
-      const int bx0 = pg.w[m].bx0, by0 = pg.w[m].by0;
-      tg[m] = tile_geom_trans<N, R, BUDGET, TRW>(bx0, by0, (pg.w[m].flags & 2) != 0, im[m], y0);
-      pt[m].bx = bx0 - (tg[m].use ? tg[m].xlo : 0);
-      pt[m].by = by0 + (y0 + M::row0(tid) - N / 2) - (tg[m].use ? tg[m].ylo : 0);
-      pt[m].fx = pg.w[m].fx;
-      pt[m].fy = pg.w[m].fy;
-      ra[m].xc = ra[m].yc = 0.0;
-      ra[m].a11 = ra[m].a22 = 1.0;
-      ra[m].a12 = ra[m].a21 = 0.0;
-      ra[m].f11 = 1.0f;
-      ra[m].f21 = 0.0f;
-    } else {
-      ra[m] = row_affine(th[m]);
-      tg[m] = tile_geom<N, R, BUDGET, TRW>(ra[m], im[m], y0);
-      pt[m].bx = pt[m].by = 0;
-      pt[m].fx = pt[m].fy = 0.0f;
-    }
-    // could any sample read outside the image?  (one pixel of slack for rounding)
-    border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
-                  tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
-  }
+  float2* const stage = sh.stage;
+  uint32_t* const tile =
+      SL::ALIAS ? reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(sh.stage) + SL::TOFF) : sh.tile_own;
+  const int g = tid / T, t = tid % T;
+  const bool use0 = FAST || wn.tg[0].use, use1 = FAST || wn.tg[1].use;
+  const bool tr0 = FAST || wn.trans[0], tr1 = FAST || wn.trans[1];
+  const bool bd0 = !FAST && wn.border[0], bd1 = !FAST && wn.border[1];
+
   // all tile loads of both images in flight before anything waits on them
   uint4 bufA[TRW], bufB[TRW];
-  if (tg[0].use) tile_fetch<tile_cw<N>()>(bufA, tg[0], im[0], tid);
-  if (tg[1].use) tile_fetch<tile_cw<N>()>(bufB, tg[1], im[1], tid);
-  // per-row parameters of the windows not gathered by translation from a tile
-  // (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
-  if (tid < 2 * R && !(tid >= R ? (trans[1] && tg[1].use) : (trans[0] && tg[0].use))) {
-    // image chosen by value selects (an index into the per-image arrays would
-    // send them to per-lane scratch memory)
-    const bool mb = tid >= R;
-    const int r = tid % R;
-    const int xo = mb ? (tg[1].use ? tg[1].xlo : 0) : (tg[0].use ? tg[0].xlo : 0);
-    const int yo = mb ? (tg[1].use ? tg[1].ylo : 0) : (tg[0].use ? tg[0].ylo : 0);
-    RowParam p;
-    if (mb ? trans[1] : trans[0]) {
-      // a translation window's row r is its origin moved down by v rows
-      const WinGeom& w = mb ? pg.w[1] : pg.w[0];
-      p.bx = w.bx0 - xo;
-      p.by = w.by0 + (y0 + r - N / 2) - yo;
-      p.fx = w.fx;
-      p.fy = w.fy;
-    } else {
-      const double xc = mb ? ra[1].xc : ra[0].xc, yc = mb ? ra[1].yc : ra[0].yc;
-      const double a12 = mb ? ra[1].a12 : ra[0].a12, a22 = mb ? ra[1].a22 : ra[0].a22;
-      const double v = (double)(y0 + r - N / 2);
-      const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
-      const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
-      const double bxd = floor(X), byd = floor(Y);
-      p.bx = (int)bxd - xo;
-      p.by = (int)byd - yo;
-      p.fx = (float)(X - bxd);
-      p.fy = (float)(Y - byd);
+  if (use0) tile_fetch<tile_cw<N>()>(bufA, wn.tg[0], wn.im[0], tid);
+  if (use1) tile_fetch<tile_cw<N>()>(bufB, wn.tg[1], wn.im[1], tid);
+  if constexpr (!FAST) {
+    // per-row parameters of the windows not gathered by translation from a
+    // tile (lanes 0..2R-1 of wave 0) and row tapers (wave 1)
+    if (tid < 2 * R && !(tid >= R ? (tr1 && use1) : (tr0 && use0))) {
+      // image chosen by value selects (an index into the per-image arrays would
+      // send them to per-lane scratch memory)
+      const bool mb = tid >= R;
+      const int r = tid % R;
+      const int xo = mb ? (use1 ? wn.tg[1].xlo : 0) : (use0 ? wn.tg[0].xlo : 0);
+      const int yo = mb ? (use1 ? wn.tg[1].ylo : 0) : (use0 ? wn.tg[0].ylo : 0);
+      RowParam p;
+      if (mb ? tr1 : tr0) {
+        // a translation window's row r is its origin moved down by v rows
+        const WinGeom& w = mb ? pg.w[1] : pg.w[0];
+        p.bx = w.bx0 - xo;
+        p.by = w.by0 + (y0 + r - N / 2) - yo;
+        p.fx = w.fx;
+        p.fy = w.fy;
+      } else {
+        const double xc = mb ? wn.ra[1].xc : wn.ra[0].xc, yc = mb ? wn.ra[1].yc : wn.ra[0].yc;
+        const double a12 = mb ? wn.ra[1].a12 : wn.ra[0].a12, a22 = mb ? wn.ra[1].a22 : wn.ra[0].a22;
+        const double v = (double)(y0 + r - N / 2);
+        const double X = fmin(fmax(xc + a12 * v, -1e9), 1e9);
+        const double Y = fmin(fmax(yc + a22 * v, -1e9), 1e9);
+        const double bxd = floor(X), byd = floor(Y);
+        p.bx = (int)bxd - xo;
+        p.by = (int)byd - yo;
+        p.fx = (float)(X - bxd);
+        p.fy = (float)(Y - byd);
+      }
+      sh.rparam[mb ? 1 : 0][r] = p;
     }
-    rparam[mb ? 1 : 0][r] = p;
+    if (tid >= 64 && tid < 64 + R) sh.trow[tid - 64] = a.taper[y0 + tid - 64];
   }
-  if (tid >= 64 && tid < 64 + R) trow[tid - 64] = a.taper[y0 + tid - 64];
   // the offsets: the centre pixels, the same for every block of the pair
   const float off[2] = {pg.w[0].off, pg.w[1].off};
   float tx[XV], ku[2][2][XV];
@@ -498,8 +489,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
     tx[c] = a.taper[x];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      ku[m][0][c] = ra[m].f11 * u;
-      ku[m][1][c] = ra[m].f21 * u;
+      ku[m][0][c] = wn.ra[m].f11 * u;
+      ku[m][1][c] = wn.ra[m].f21 * u;
     }
   }
   float s[6] = {0, 0, 0, 0, 0, 0};
@@ -509,38 +500,40 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   float lateA[NL][XV], lateB[NL][XV];  // stage rows [FL, R) of each image
   bool clamped = false;
 
-  __syncthreads();  // row parameters visible
+  if constexpr (!FAST) __syncthreads();  // row parameters visible
   // Tiled images first: their tile sits at the end of the stage (when FL <
   // R), so an image gathered straight from memory writes all its rows only
   // after every tile has been consumed.
-  if (tg[0].use) {
-    tile_store<tile_cw<N>()>(tile, bufA, tg[0], im[0], border[0], tid);
+  if (use0) {
+    tile_store<tile_cw<N>()>(tile, bufA, wn.tg[0], wn.im[0], bd0, tid);
     __syncthreads();
-    if (trans[0])
-      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, tg[0], pt[0], a.taper, y0, im[0], border[0], tx,
+    if (tr0)
+      gather_rows_trans<N, R, FL, NL, false>(stage, lateA, tile, wn.tg[0], wn.pt[0], a.taper, y0, wn.im[0], bd0, tx,
                                              off[0], tid, s[1], s3c[0], clamped);
     else
-      gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], border[0], tx,
-                                             off[0], tid, s[1], s3c[0], clamped);
+      gather_rows<N, R, FL, NL, false, true>(stage, lateA, tile, wn.tg[0], sh.rparam[0], sh.trow, ku[0], wn.im[0],
+                                             bd0, tx, off[0], tid, s[1], s3c[0], clamped);
   }
-  if (tg[1].use) {
-    if (tg[0].use) __syncthreads();  // tile of A fully consumed
-    tile_store<tile_cw<N>()>(tile, bufB, tg[1], im[1], border[1], tid);
+  if (use1) {
+    if (use0) __syncthreads();  // tile of A fully consumed
+    tile_store<tile_cw<N>()>(tile, bufB, wn.tg[1], wn.im[1], bd1, tid);
     __syncthreads();
-    if (trans[1])
-      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, tg[1], pt[1], a.taper, y0, im[1], border[1], tx,
+    if (tr1)
+      gather_rows_trans<N, R, FL, NL, true>(stage, lateB, tile, wn.tg[1], wn.pt[1], a.taper, y0, wn.im[1], bd1, tx,
                                             off[1], tid, s[4], s3c[1], clamped);
     else
-      gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], border[1], tx,
-                                            off[1], tid, s[4], s3c[1], clamped);
+      gather_rows<N, R, FL, NL, true, true>(stage, lateB, tile, wn.tg[1], sh.rparam[1], sh.trow, ku[1], wn.im[1],
+                                            bd1, tx, off[1], tid, s[4], s3c[1], clamped);
   }
-  if (FL < R && (tg[0].use || tg[1].use) && !(tg[0].use && tg[1].use)) __syncthreads();  // tile consumed
-  if (!tg[0].use)
-    gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, tg[0], rparam[0], trow, ku[0], im[0], true, tx,
-                                           off[0], tid, s[1], s3c[0], clamped);
-  if (!tg[1].use)
-    gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, tg[1], rparam[1], trow, ku[1], im[1], true, tx,
-                                          off[1], tid, s[4], s3c[1], clamped);
+  if constexpr (!FAST) {
+    if (FL < R && (use0 || use1) && !(use0 && use1)) __syncthreads();  // tile consumed
+    if (!use0)
+      gather_rows<N, R, R, NL, false, false>(stage, lateA, tile, wn.tg[0], sh.rparam[0], sh.trow, ku[0], wn.im[0],
+                                             true, tx, off[0], tid, s[1], s3c[0], clamped);
+    if (!use1)
+      gather_rows<N, R, R, NL, true, false>(stage, lateB, tile, wn.tg[1], sh.rparam[1], sh.trow, ku[1], wn.im[1],
+                                            true, tx, off[1], tid, s[4], s3c[1], clamped);
+  }
 #pragma unroll
   for (int c = 0; c < XV; ++c) {
     s[2] = fmaf(tx[c], s3c[0][c], s[2]);
@@ -548,15 +541,15 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   }
   if constexpr (FL < R) {
     // rows [FL, R) of the tiled images (they overlap the tile)
-    if (tg[0].use && tg[1].use) __syncthreads();  // tile of B fully consumed
+    if (use0 && use1) __syncthreads();  // tile of B fully consumed
     float* st = reinterpret_cast<float*>(stage);
 #pragma unroll
     for (int i = 0; i < R - FL; ++i)
 #pragma unroll
       for (int c = 0; c < XV; ++c) {
         const int q = 2 * ((FL + i) * RS + lidx(FwdMap<N, R>::col(tid, c)));
-        if (tg[0].use) st[q] = lateA[i][c];
-        if (tg[1].use) st[q + 1] = lateB[i][c];
+        if (use0) st[q] = lateA[i][c];
+        if (use1) st[q + 1] = lateB[i][c];
       }
   }
   __syncthreads();
@@ -586,23 +579,28 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
   if constexpr (!PEARSON) s[0] = dcA;  // (the Pearson template sum comes from pearson_rows)
   s[3] = dcB;
 
-  // slice sums
+  // slice sums; with one transform per wave only lane 0 holds the DC sums
   const int wv = tid >> 6, ln = tid & 63;
   double acc[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[i] = (double)wave_sum_f32(s[i]);
+  for (int i = 0; i < 6; ++i) {
+    if (T == 64 && (i == 3 || (i == 0 && !PEARSON)))
+      acc[i] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(s[i]), 0));
+    else
+      acc[i] = (double)wave_sum_f32(s[i]);
+  }
   const int anyc = __any(clamped) ? 1 : 0;
   if (ln == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) red[wv][i] = acc[i];
-    redc[wv] = anyc;
+    for (int i = 0; i < 6; ++i) sh.red[wv][i] = acc[i];
+    sh.redc[wv] = anyc;
   }
   __syncthreads();
   if (tid == 0) {
     RowPart rp;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) rp.s[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
-    rp.clamped = redc[0] | redc[1] | redc[2] | redc[3];
+    for (int i = 0; i < 6; ++i) rp.s[i] = sh.red[0][i] + sh.red[1][i] + sh.red[2][i] + sh.red[3][i];
+    rp.clamped = sh.redc[0] | sh.redc[1] | sh.redc[2] | sh.redc[3];
     rp.off[0] = off[0];
     rp.off[1] = off[1];
     rp.pad = 0;
@@ -611,24 +609,87 @@ __global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
 
   // store in the tiled layout: Z[pair][y / 8][kx][y % 8].  A thread writes
   // the float4 of rows (r, r + 1) at bin kx; with R >= 8 the block's region is
-  // contiguous and consecutive threads write consecutive 16-byte chunks.
+  // contiguous and consecutive threads write consecutive 16-byte chunks.  The
+  // thread's chunk of round i is a constant distance from that of round 0
+  // (in the stage and in Z), so the rounds differ by immediate offsets.
   {
-    float4* zb = reinterpret_cast<float4*>(a.Z + (size_t)pair * N * N);
-#pragma unroll 4
-    for (int q = tid; q < N * R / 2; q += 256) {
-      int kx, r;
-      if constexpr (R >= 8) {
-        const int yt = q / (4 * N), rem = q % (4 * N);
-        kx = rem >> 2;
-        r = 8 * yt + 2 * (rem & 3);
-      } else {
-        kx = q / (R / 2);
-        r = 2 * (q % (R / 2));
-      }
-      const float2 v0 = stage[r * RS + lidx(kx)], v1 = stage[(r + 1) * RS + lidx(kx)];
-      zb[ztile<N>(kx, y0 + r) >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
+    constexpr int Q = N * R / 2;
+    static_assert(Q % 256 == 0 && (R >= 8 || 8 % R == 0), "store rounds");
+    // round 0: kx0 = thread's bin, r0 its first row (of a pair)
+    constexpr int RP = R >= 8 ? 4 : R / 2;  // row pairs per column in one round
+    const int kx0 = tid / RP, r0 = 2 * (tid % RP);
+    float4* zb = reinterpret_cast<float4*>(a.Z + (size_t)pair * N * N) +
+                 (ztile<N>(kx0, (y0 & ~7) + ((R >= 8 ? 0 : y0 & 7) + r0)) >> 1);
+    const float2* sb = stage + r0 * RS + lidx(kx0);
+#pragma unroll
+    for (int i = 0; i < Q / 256; ++i) {
+      // round i adds dq = 256 i to the chunk index q = (y / 8) 4N + kx RP + (r / 2) (R >= 8)
+      // or q = kx RP + r / 2 (R < 8)
+      const int dq = 256 * i;
+      const int dyt = R >= 8 ? dq / (4 * N) : 0;        // whole 8-row tiles
+      const int dkx = (R >= 8 ? dq % (4 * N) : dq) / RP;  // a multiple of 16
+      const float2 v0 = sb[dyt * 8 * RS + dkx + dkx / 16], v1 = sb[(dyt * 8 + 1) * RS + dkx + dkx / 16];
+      zb[(dyt * 8 * N + dkx * 8) >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
     }
   }
+}
+
+template <int N, int R, int BUDGET, int TRW, bool PEARSON>
+__global__ void __launch_bounds__(256) k_row_fwd(MatchArgs a) {
+  using C = FftCfg<N>;
+  constexpr int T = C::T, G = 256 / T, NSLICE = N / R;
+  static_assert(R % G == 0 && (N * R) % 256 == 0 && 2 * R <= 64, "row split");
+  __shared__ FwdLds<N, R, BUDGET> sh;
+
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = blk / NSLICE, slice = blk % NSLICE, y0 = slice * R;
+  const int tid = threadIdx.x;
+
+  // image indices are clamped into the table so a bad index cannot read past it
+  const int ka = min(max(a.img_a[pair], 0), a.n_imgs - 1);
+  const int kb = min(max(a.img_b[pair], 0), a.n_imgs - 1);
+  FwdWin wn;
+  wn.im[0] = a.imgs[ka];
+  wn.im[1] = a.imgs[kb];
+  const float* th[2] = {a.th_a + 8 * (size_t)pair, a.th_b + 8 * (size_t)pair};
+  const PairGeom pg = a.geom[pair];  // origin split, translation test, offsets (k_pair_geom)
+  using M = FwdMap<N, R>;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    wn.im[m].width = max(wn.im[m].width, 2);
+    wn.im[m].height = max(wn.im[m].height, 2);
+    // translation windows (identity linear part) take the constant-weight
+    // gather, and their tile geometry and row parameters are integer offsets
+    // from floor(cx + tx), floor(cy + ty); only other windows need the affine
+    wn.trans[m] = (pg.w[m].flags & 1) != 0;
+    if (wn.trans[m]) {
+      const int bx0 = pg.w[m].bx0, by0 = pg.w[m].by0;
+      wn.tg[m] = tile_geom_trans<N, R, BUDGET, TRW>(bx0, by0, (pg.w[m].flags & 2) != 0, wn.im[m], y0);
+      wn.pt[m].bx = bx0 - (wn.tg[m].use ? wn.tg[m].xlo : 0);
+      wn.pt[m].by = by0 + (y0 + M::row0(tid) - N / 2) - (wn.tg[m].use ? wn.tg[m].ylo : 0);
+      wn.pt[m].fx = pg.w[m].fx;
+      wn.pt[m].fy = pg.w[m].fy;
+      wn.ra[m].xc = wn.ra[m].yc = 0.0;
+      wn.ra[m].a11 = wn.ra[m].a22 = 1.0;
+      wn.ra[m].a12 = wn.ra[m].a21 = 0.0;
+      wn.ra[m].f11 = 1.0f;
+      wn.ra[m].f21 = 0.0f;
+    } else {
+      wn.ra[m] = row_affine(th[m]);
+      wn.tg[m] = tile_geom<N, R, BUDGET, TRW>(wn.ra[m], wn.im[m], y0);
+      wn.pt[m].bx = wn.pt[m].by = 0;
+      wn.pt[m].fx = wn.pt[m].fy = 0.0f;
+    }
+    // could any sample read outside the image?  (one pixel of slack for rounding)
+    const TileGeom& tg = wn.tg[m];
+    wn.border[m] = !(tg.use && tg.xlo >= 0 && tg.xlo + 4 * tg.wt4 <= wn.im[m].width && tg.ylo >= 0 &&
+                     tg.ylo + tg.ht <= wn.im[m].height);
+  }
+  const bool fast = wn.trans[0] && wn.trans[1] && wn.tg[0].use && wn.tg[1].use && !wn.border[0] && !wn.border[1];
+  if (fast)
+    row_fwd_body<N, R, BUDGET, TRW, PEARSON, true>(a, sh, wn, pg, pair, slice, y0, tid);
+  else
+    row_fwd_body<N, R, BUDGET, TRW, PEARSON, false>(a, sh, wn, pg, pair, slice, y0, tid);
 }
 
 // ---------------------------------------------------------------- pair statistics
