@@ -23,7 +23,7 @@ def dev():
     return torch.device("cuda", 0)
 
 
-@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 8])
 @pytest.mark.parametrize("w", [48, 45])
 def test_project_side_bit_exact(ctx, k, w):
     print("case project_side k=%d w=%d" % (k, w), flush=True)

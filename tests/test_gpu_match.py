@@ -200,7 +200,7 @@ def test_snr_entry_point(ctx):
 
 
 @pytest.mark.parametrize("w", [48, 45])
-@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 8])
 def test_project_bit_exact(ctx, w, k):
     print("case project w=%d k=%d" % (w, k), flush=True)
     rng = np.random.default_rng(w * 10 + k)
@@ -216,6 +216,28 @@ def test_project_bit_exact(ctx, w, k):
         except ValueError:
             ref = np.zeros_like(st[0])
         np.testing.assert_array_equal(got[s], ref, err_msg="s=%d" % s)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_project_extremes(ctx, k):
+    # near-saturated sums and every neighbour count from 1 to 2k: sections of
+    # 255 with a sprinkling of 254/0 pixels, 14 sections (a whole number of
+    # rounds for k = 3) and an exclusion pattern that thins the windows
+    print("case project extremes k=%d" % k, flush=True)
+    rng = np.random.default_rng(400 + k)
+    S = 14
+    st = np.full((S, 9, 64), 255, np.uint8)
+    st[rng.random(st.shape) < 0.2] = 254
+    st[rng.random(st.shape) < 0.05] = 0
+    excl = np.zeros(S, bool)
+    excl[[1, 5, 6, 12]] = True
+    out = ctx.project(torch.from_numpy(st).to(dev()), k=k, exclude=excl).cpu().numpy()
+    for s in range(S):
+        try:
+            ref = O.project(st, s, k, excl)
+        except ValueError:
+            ref = np.zeros_like(st[0])
+        np.testing.assert_array_equal(out[s], ref, err_msg="s=%d" % s)
 
 
 @pytest.mark.parametrize("hw", [(64, 96), (37, 51)])
