@@ -141,6 +141,34 @@ def path_roofline(pairs_per_s: float, n: int) -> dict:
                 input_only_bound_pairs_per_s=inp, input_only_frac=pairs_per_s / inp)
 
 
+def hbm_reference(dev, reps: int = 20) -> dict:
+    """Bandwidth a plain streaming kernel reaches on this GPU: torch's
+    elementwise FP32 multiply reading and writing 1 GiB each, median of `reps`
+    runs timed with HIP events on the current stream.  The practical
+    counterpart of the 8 TB/s peak for kernels that read and write."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(x, 1.0, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    ms = ts[len(ts) // 2]
+    nbytes = 2 * x.numel() * x.element_size()
+    del x, y
+    return dict(elementwise_rw_gbs=nbytes / (ms / 1e3) / 1e9, ms=ms, bytes=nbytes,
+                note="torch.mul(x, 1.0, out=y), 1 GiB read + 1 GiB written, FP32")
+
+
 def pair_flops(n: int) -> float:
     import math
     return 7.5 * n * n * math.log2(n * n) + 40.0 * n * n
@@ -1305,6 +1333,12 @@ def main():
                           "note": "projection + the match as one replayed hipGraph, each replay timed with HIP "
                                   "events on the launch stream"},
     }
+    ref = hbm_reference(dev)
+    ref["roofline_kernel_frac_of_reference"] = roof["achieved"] / ref["elementwise_rw_gbs"] if roof else None
+    ref["path_frac_of_reference"] = line["hbm_gbs"] / ref["elementwise_rw_gbs"]
+    line["hbm_reference"] = ref
+    log("HBM reference (elementwise read + write of 1 GiB): %.0f GB/s; headline step %.0f GB/s (%.2f of it)"
+        % (ref["elementwise_rw_gbs"], line["hbm_gbs"], ref["path_frac_of_reference"]))
     if pruned is not None:
         line["pruned"] = pruned
     if not args.no_pearson:

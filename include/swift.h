@@ -526,13 +526,16 @@ int swift_plan(swift_ctx* ctx, int32_t n, int32_t fwd_variant, int32_t inv_varia
 /* Times plan variants of each listed window size on a synthetic batch
  * (pairs_per_size translation windows of hashed uint8 noise, p = 0.65;
  * <= 0 means 512) and keeps the fastest in the context's plan (and, with a
- * tune cache path, in that file).  Synchronous; allocates and frees its own
- * device buffers, so it is a set-up call, not one for a capture or a serving
- * loop.  times_ms: host [n_sizes][SWIFT_TUNE_SLOTS] or NULL, receives the mean
- * time per batch of: slots 0..3 the row variants (fwd + 2 inv) in one chunk,
- * slots 4..6 the fastest of those in 2, 4 and 8 chunks, slot 7 the
- * one-workgroup kernel (n <= 128); -1 where a variant equals another or does
- * not apply.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
+ * tune cache path, in that file).  Each variant's time is the fastest of 3
+ * rounds that visit the variants in turn, a round timing the mean of 3
+ * batches; a variant replaces the defaults (slot 0), and a chunk count the
+ * best row variant, only when at least 2% faster.  Synchronous; allocates
+ * and frees its own device buffers, so it is a set-up call, not one for a
+ * capture or a serving loop.  times_ms: host [n_sizes][SWIFT_TUNE_SLOTS] or
+ * NULL, receives those times per batch for: slots 0..3 the row variants
+ * (fwd + 2 inv) in one chunk, slots 4..6 the chosen row variant in 2, 4 and
+ * 8 chunks, slot 7 the one-workgroup kernel (n <= 128); -1 where a variant
+ * equals another or does not apply.  Errors: SWIFT_E_INVAL, SWIFT_E_HIP. */
 #define SWIFT_TUNE_SLOTS 8
 int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_t pairs_per_size,
                    float* times_ms);

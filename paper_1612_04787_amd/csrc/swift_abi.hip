@@ -108,6 +108,8 @@ struct swift_ctx {
 
 static constexpr size_t kMaxGraphs = 16;
 static constexpr int kTuneSlots = SWIFT_TUNE_SLOTS;
+static constexpr int kTuneRounds = 3;           // timing rounds over the slots
+static constexpr float kTuneMargin = 0.02f;     // relative gain needed to leave a choice
 
 static void ctx_release(swift_ctx* c) {
   for (auto& kv : c->graphs) {
@@ -1292,45 +1294,77 @@ int swift_autotune(swift_ctx* ctx, const int32_t* sizes, int32_t n_sizes, int32_
       if (e0) (void)hipEventDestroy(e0);
       return fail(SWIFT_E_HIP, "autotune events");
     }
-    float best = 0.0f;
-    int best_v = 0, best_c = 1;
     const uint8_t keep_f = ctx->alt_fwd[si], keep_i = ctx->alt_inv[si], keep_c = ctx->chunks[si];
     int rc = SWIFT_OK;
     // slots 0..3: the row variants in one chunk; 4..6: the best of them in
     // 2, 4, 8 chunks on two streams; 7 (n <= kFusedMaxN): one workgroup per
     // pair.  vv: bit 0 the alternative forward rows, bit 1 the alternative
-    // inverse rows, 4 the one-workgroup kernel.
-    for (int v = 0; v < kTuneSlots && rc == SWIFT_OK; ++v) {
-      const int vv = v < 4 ? v : v == 7 ? 4 : best_v;
-      const int ch = v < 4 || v == 7 ? 1 : (v == 4 ? 2 : v == 5 ? 4 : 8);
-      const int af = vv == 4 ? kFusedVariant : (vv & 1);
-      const bool ai = vv != 4 && (vv & 2) != 0;
+    // inverse rows, 4 the one-workgroup kernel.  Each slot is timed as the
+    // mean of 3 batches, in kTuneRounds rounds that visit the slots in turn
+    // (so slow drifts of the clock touch every slot alike), and keeps its
+    // fastest round.  A slot replaces the current choice only when it is at
+    // least kTuneMargin faster: differences within the run-to-run spread do
+    // not move the plan off the defaults.
+    float tmin[kTuneSlots];
+    for (int v = 0; v < kTuneSlots; ++v) tmin[v] = -1.0f;
+    int best_v = 0, best_c = 1;
+    auto slot_cfg = [&](int v, int& af, bool& ai, int& ch, int& vv) {
+      vv = v < 4 ? v : v == 7 ? 4 : best_v;
+      ch = v < 4 || v == 7 ? 1 : (v == 4 ? 2 : v == 5 ? 4 : 8);
+      af = vv == 4 ? kFusedVariant : (vv & 1);
+      ai = vv != 4 && (vv & 2) != 0;
+      return ch <= P && (af != 1 || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
+             (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false)) && (vv != 4 || n <= kFusedMaxN) &&
+             !(v >= 4 && v < 7 && best_v == 4);
+    };
+    auto time_slot = [&](int v, bool warm) {
+      int af, ch, vv;
+      bool ai;
+      if (!slot_cfg(v, af, ai, ch, vv)) return;
+      ctx->alt_fwd[si] = (uint8_t)af;
+      ctx->alt_inv[si] = ai;
+      ctx->chunks[si] = (uint8_t)ch;
       float ms = -1.0f;
-      const bool distinct = ch <= P && (af != 1 || fwd_blocks_n(n, true) != fwd_blocks_n(n, false)) &&
-                            (!ai || inv_blocks_n(n, true) != inv_blocks_n(n, false)) &&
-                            (vv != 4 || n <= kFusedMaxN) && !(v >= 4 && v < 7 && best_v == 4);
-      if (distinct) {
-        ctx->alt_fwd[si] = (uint8_t)af;
-        ctx->alt_inv[si] = ai;
-        ctx->chunks[si] = (uint8_t)ch;
+      if (warm)
         rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
-                           b.p[5], st, false, nullptr);  // warm-up
-        if (rc == SWIFT_OK) rc = hipEventRecord(e0, st) == hipSuccess ? SWIFT_OK : fail(SWIFT_E_HIP, "event");
-        for (int r = 0; r < 3 && rc == SWIFT_OK; ++r)
-          rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
-                             b.p[5], st, false, nullptr);
-        if (rc == SWIFT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = fail(SWIFT_E_HIP, "autotune timing");
+                           b.p[5], st, false, nullptr);
+      if (rc == SWIFT_OK) rc = hipEventRecord(e0, st) == hipSuccess ? SWIFT_OK : fail(SWIFT_E_HIP, "event");
+      for (int r = 0; r < 3 && rc == SWIFT_OK; ++r)
+        rc = enqueue_match(ctx, (const swift_image*)b.p[1], 1, &pr, &prm, (swift_match*)b.p[4], nullptr, nullptr,
+                           b.p[5], st, false, nullptr);
+      if (rc == SWIFT_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(SWIFT_E_HIP, "autotune timing");
+      if (rc == SWIFT_OK) {
         ms /= 3.0f;
-        if (rc == SWIFT_OK && (v == 0 || ms < best)) {  // variant 0 (the defaults) always runs first
-          best = ms;
-          best_v = vv;
-          best_c = ch;
-        }
+        tmin[v] = tmin[v] < 0.0f ? ms : fminf(tmin[v], ms);
       }
-      if (times_ms) times_ms[k * kTuneSlots + v] = ms;
+    };
+    // the row variants and the one-workgroup kernel, then the chunk counts of
+    // the winner
+    const int phase_a[5] = {0, 1, 2, 3, 7}, phase_b[3] = {4, 5, 6};
+    for (int r = 0; r < kTuneRounds && rc == SWIFT_OK; ++r)
+      for (int i = 0; i < 5 && rc == SWIFT_OK; ++i) time_slot(phase_a[i], r == 0);
+    float best = tmin[0];
+    for (int i = 1; i < 5 && rc == SWIFT_OK; ++i) {
+      const int v = phase_a[i];
+      if (tmin[v] > 0.0f && tmin[v] < best * (1.0f - kTuneMargin)) {
+        best = tmin[v];
+        best_v = v < 4 ? v : 4;
+      }
     }
+    for (int r = 0; r < kTuneRounds && rc == SWIFT_OK; ++r)
+      for (int i = 0; i < 3 && rc == SWIFT_OK; ++i) time_slot(phase_b[i], r == 0);
+    const float row_best = best;
+    for (int i = 0; i < 3 && rc == SWIFT_OK; ++i) {
+      const int v = phase_b[i];
+      if (tmin[v] > 0.0f && tmin[v] < row_best * (1.0f - kTuneMargin) && tmin[v] < best) {
+        best = tmin[v];
+        best_c = v == 4 ? 2 : v == 5 ? 4 : 8;
+      }
+    }
+    if (times_ms)
+      for (int v = 0; v < kTuneSlots; ++v) times_ms[k * kTuneSlots + v] = tmin[v];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SWIFT_OK) {

@@ -70,18 +70,26 @@ def test_autotune_picks_a_timed_variant(ctx):
         print("   n=%d times_ms=%s -> plan %s" % (n, ["%.3f" % t for t in times], plan), flush=True)
         assert times[0] > 0
         assert (times[7] > 0) == (n <= 128)  # slot 7: the one-workgroup kernel
-        valid = [(t, v) for v, t in enumerate(times) if t > 0]
-        best = min(valid)[1]
         assert plan == ctx.plan(n, full=True)
-        if best == 7:
+        # the selection rule (FP32, as the library): a slot replaces the
+        # running choice only when 2% faster; slot 0 (the defaults) first,
+        # then the row variants and the one-workgroup kernel, then the chunk
+        # counts of the chosen row variant
+        f32 = np.float32
+        keep = f32(1.0) - f32(0.02)
+        best_t, best_v = f32(times[0]), 0
+        for v in (1, 2, 3, 7):
+            if times[v] > 0 and f32(times[v]) < best_t * keep:
+                best_t, best_v = f32(times[v]), v
+        row_best, chunks = best_t, 1
+        for v in (4, 5, 6):
+            if times[v] > 0 and f32(times[v]) < row_best * keep and f32(times[v]) < best_t:
+                best_t, chunks = f32(times[v]), {4: 2, 5: 4, 6: 8}[v]
+        if best_v == 7:
             assert n <= 128  # the one-workgroup kernel
             ctx.plan(n, 2, 0, 1)
-        elif best < 4:
-            ctx.plan(n, best & 1, best >> 1, 1)
         else:
-            # a chunked slot times the best row variant of slots 0..3
-            rv = min((t, v) for v, t in enumerate(times[:4]) if t > 0)[1]
-            ctx.plan(n, rv & 1, rv >> 1, {4: 2, 5: 4, 6: 8}[best])
+            ctx.plan(n, best_v & 1, best_v >> 1, chunks)
         assert ctx.plan(n, full=True) == plan
     for n in SIZES:
         ctx.plan(n, 0, 0, 1)
