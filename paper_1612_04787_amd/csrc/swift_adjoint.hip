@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T;
   constexpr int NI = N / 2 + 1, NW = bwd_col_blocks<N>();
-  constexpr int SL = lidx(N);
+  constexpr int SL = fft_scratch<N>();
   __shared__ float2 lds[2 * G * SL];
   __shared__ double red[4][kDpart];
 
@@ -430,7 +430,7 @@ template <int N, bool CJ, bool TO>
 __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
-  constexpr int RS = lidx(N) + 1;
+  constexpr int RS = rows_stride<R>(fft_scratch<N>());
   // the adjoint's row pass keeps its stage and tile in separate arrays; at
   // 1024^2 both would not leave room for two workgroups per CU, so it
   // gathers from memory there
@@ -509,8 +509,8 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 
   // stage[r][kx] = Y[kx][y0 + r], then the inverse row FFTs of G_w in place
   const float2* Yp = a.Y + (size_t)pair * N * N;
-  if constexpr (256 % (16 * R) == 0) {
-    // thread: row r = tid % R of columns c0 + k CPL (CPL a multiple of 16, so
+  if constexpr (256 % (32 * R) == 0) {
+    // thread: row r = tid % R of columns c0 + k CPL (CPL a multiple of 32, so
     // the stage index advances by the constant lidx(CPL)); the global address
     // is the pair's base plus a 32-bit offset
     constexpr int CPL = 256 / R, LD = N / CPL;

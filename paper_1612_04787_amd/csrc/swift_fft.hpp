@@ -33,8 +33,10 @@ __device__ __forceinline__ float2 mul_mi(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-// LDS index with one padding slot every 16 complex values (bank spreading).
-__host__ __device__ constexpr int lidx(int i) { return i + (i >> 4); }
+// LDS index with one padding slot every 32 complex values.  LDS has 64
+// banks of 4 bytes and an 8-byte access serves 32 lanes per cycle, so any 32
+// consecutive indices then fall on 32 distinct bank pairs.
+__host__ __device__ constexpr int lidx(int i) { return i + (i >> 5); }
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -201,7 +203,7 @@ __device__ __forceinline__ void tw_load(Twiddles<N>& tw, int t, const float2* __
 }
 
 // ---------------------------------------------------------------- Stockham pass
-// Where a transform's scratch element i lives: lidx(i) of a private row (the
+// Where a transform's scratch element i lives: ExchIdx of a private row (the
 // default), or row col_swz(i) of a column of a larger LDS array whose rows
 // are `stride` complex values apart.  col_swz permutes the rows within the
 // column (XOR of the low bits with a function of the high bits) so that the
@@ -212,17 +214,53 @@ template <int N> __device__ __forceinline__ int col_swz(int i);
 template <> __device__ __forceinline__ int col_swz<64>(int i) { return i ^ ((i >> 3) & 7); }
 template <> __device__ __forceinline__ int col_swz<128>(int i) { return i ^ (((i >> 4) + ((i >> 6) << 3)) & 15); }
 
-struct PaddedIdx {
-  __device__ __forceinline__ int operator()(int i) const { return lidx(i); }
+// Exchange layouts of a private scratch row, per pass (N >= 256).  On this
+// LDS an 8-byte read serves 32 lanes per cycle over 64 banks, an 8-byte write
+// 16 lanes over 32 banks.  After pass 0 (writes 8t + q or 16t + q, reads
+// t + e T) i + i/16 keeps the writes conflict-free, at the price of a 2-way
+// conflict on the reads (the cheaper of the two: a write takes twice the
+// cycles of a read).  After pass 1 a lane writes the NS1 = rad(0) consecutive
+// elements of a block of NS1 rad(1) at stride NS1, and the lanes of a cycle
+// span several such blocks, which a padding of one slot per 16 or 32 sends to
+// the same banks; shifting block b by NS1 b makes both the writes and the
+// reads conflict-free.  Below 256 (several transforms per wavefront) lidx
+// serves both exchanges.
+template <int N>
+struct ExchIdx {
+  template <int P>
+  __device__ __forceinline__ int at(int i) const {
+    if constexpr (N < 256) {
+      return lidx(i);
+    } else if constexpr (P == 0) {
+      return i + (i >> 4);
+    } else {
+      constexpr int NS1 = FftCfg<N>::rad(0), BL = NS1 * FftCfg<N>::rad(1);
+      return i + NS1 * (i / BL);
+    }
+  }
 };
+// Scratch elements a transform needs in its private row: the callers' lidx
+// layout and every exchange layout.
+template <int N>
+__host__ __device__ constexpr int fft_scratch() {
+  const int a = lidx(N - 1) + 1;
+  if (N < 256) return a;
+  const int NS1 = FftCfg<N>::rad(0), BL = NS1 * FftCfg<N>::rad(1);
+  const int b = (N - 1) + NS1 * ((N - 1) / BL) + 1, c = (N - 1) + ((N - 1) >> 4) + 1;
+  const int m = a > b ? a : b;
+  return m > c ? m : c;
+}
 template <int N>
 struct ColumnIdx {
   int stride;
-  __device__ __forceinline__ int operator()(int i) const { return col_swz<N>(i) * stride; }
+  template <int P>
+  __device__ __forceinline__ int at(int i) const {
+    return col_swz<N>(i) * stride;
+  }
 };
 
 // REG: twiddles from registers (twr), otherwise loaded from the table per pass.
-template <int N, bool INV, int P, int NS, bool REG, class IX = PaddedIdx>
+template <int N, bool INV, int P, int NS, bool REG, class IX = ExchIdx<N>>
 __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,
                                          const Twiddles<N>* __restrict__ twr, const float2* __restrict__ tab,
                                          IX ix = IX()) {
@@ -254,20 +292,20 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[FftCfg<N>::E], float2* __re
     } else {
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[ix(base + q * NS)] = u[q];
+      for (int q = 0; q < R; ++q) lds[ix.template at<P>(base + q * NS)] = u[q];
     }
   }
   if constexpr (!LAST) {
     wave_lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds[ix(t + e * T)];
+    for (int e = 0; e < E; ++e) v[e] = lds[ix.template at<P>(t + e * T)];
     wave_lds_sync();
     fft_pass<N, INV, P + 1, NS * R, REG, IX>(v, lds, t, twr, tab, ix);
   }
 }
 
 // Full transform with register twiddles.  lds: this transform's private
-// scratch of lidx(N) float2.  Forward: X[k] = sum_n x[n] exp(-2 pi i k n / N);
+// scratch of fft_scratch<N>() float2.  Forward: X[k] = sum_n x[n] exp(-2 pi i k n / N);
 // inverse: exp(+...), unscaled.
 template <int N, bool INV>
 __device__ __forceinline__ void fft_wave(float2 (&v)[FftCfg<N>::E], float2* __restrict__ lds, int t,

@@ -627,8 +627,9 @@ __device__ __forceinline__ void row_fwd_body(const MatchArgs& a, FwdLds<N, R, BU
       // or q = kx RP + r / 2 (R < 8)
       const int dq = 256 * i;
       const int dyt = R >= 8 ? dq / (4 * N) : 0;        // whole 8-row tiles
-      const int dkx = (R >= 8 ? dq % (4 * N) : dq) / RP;  // a multiple of 16
-      const float2 v0 = sb[dyt * 8 * RS + dkx + dkx / 16], v1 = sb[(dyt * 8 + 1) * RS + dkx + dkx / 16];
+      const int dkx = (R >= 8 ? dq % (4 * N) : dq) / RP;  // a multiple of 64
+      // lidx(kx0 + dkx) = lidx(kx0) + lidx(dkx) for dkx a multiple of 32
+      const float2 v0 = sb[dyt * 8 * RS + lidx(dkx)], v1 = sb[(dyt * 8 + 1) * RS + lidx(dkx)];
       zb[(dyt * 8 * N + dkx * 8) >> 1] = make_float4(v0.x, v0.y, v1.x, v1.y);
     }
   }
@@ -763,7 +764,7 @@ __global__ void __launch_bounds__(256) k_col(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
   constexpr int NI = N / 2 + 1, NW = (NI + IPW - 1) / IPW;
-  constexpr int SL = lidx(N);
+  constexpr int SL = fft_scratch<N>();
   __shared__ float2 lds[G * SL];
 
   const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
@@ -825,7 +826,7 @@ __global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T;
   constexpr int NI = N / 2 + 1, NW = (NI + G - 1) / G;
-  constexpr int SL = lidx(N);
+  constexpr int SL = fft_scratch<N>();
   __shared__ float2 lds[G * SL];
 
   const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
@@ -952,8 +953,10 @@ __global__ void __launch_bounds__(256) k_row_inv(MatchArgs a) {
   static_assert(PRUNE || !PEARSON, "the Pearson search runs on the pruned rows");
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T, NT = R2 / 2, NSL2 = N / R2;
-  constexpr int NH = N / 2 + 1, RS2 = N / 2 + N / 32 + 1;
-  static_assert(2 * RS2 >= lidx(N - 1) + 1, "row pair must hold the FFT scratch");
+  // a row pair holds a transform's scratch; the stage load (thread row
+  // tid % R2) hits distinct banks
+  constexpr int NH = N / 2 + 1, RS2 = rows_stride<R2>((fft_scratch<N>() + 1) / 2 > NH ? (fft_scratch<N>() + 1) / 2 : NH);
+  static_assert(2 * RS2 >= fft_scratch<N>(), "row pair must hold the FFT scratch");
   __shared__ float2 stage[R2 * RS2];
   __shared__ float rm1[4], rm2[4];
   __shared__ int ri1[4];
@@ -1136,7 +1139,7 @@ __global__ void __launch_bounds__(64) k_finalize(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E;
   const int NSL2 = a.nsl_inv;
-  constexpr int SL = lidx(N);
+  constexpr int SL = fft_scratch<N>();
   __shared__ float2 lds[SL];
   __shared__ float nb[3][3];
   const int pair = blockIdx.x, ln = threadIdx.x;

@@ -190,13 +190,29 @@ __device__ __forceinline__ void tile_store(uint32_t* __restrict__ tile, const ui
   }
 }
 
-// Row stride (float2) of the forward stage: >= lidx(N), chosen so that the
-// transposed read-out (rows fastest) hits distinct LDS banks.
+// Row stride (float2) of the forward stage: at least a transform's scratch,
+// and chosen so that the read-out in 8-row tiles hits distinct bank pairs: a
+// thread takes rows r and r + 1 of one bin, and the 32 lanes of an 8-byte
+// access span RP row pairs and 32 / RP consecutive bins, so the offsets
+// 2 p RS (p < RP) must be distinct multiples of 32 / RP modulo 32, i.e.
+// RS = 16 / RP (mod 32 / RP).
 template <int N, int R>
 __host__ __device__ constexpr int fwd_stride() {
-  const int target = R >= 16 ? 1 : 16 / R;
-  int rs = lidx(N);
-  while ((rs & 15) != target) ++rs;
+  const int RP = R >= 8 ? 4 : R / 2;
+  int rs = fft_scratch<N>();
+  while (rs % (32 / RP) != 16 / RP) ++rs;
+  return rs;
+}
+
+// Row stride (float2) of a stage that thread r = tid % R fills at consecutive
+// columns (the 32 lanes of an 8-byte access span R' = min(R, 32) rows and
+// 32 / R' columns): at least `need`, and an odd multiple of 32 / R', so that
+// those lanes hit distinct bank pairs.
+template <int R>
+__host__ __device__ constexpr int rows_stride(int need) {
+  const int Rp = R < 32 ? R : 32;
+  int rs = need;
+  while (rs % (64 / Rp) != 32 / Rp) ++rs;
   return rs;
 }
 
