@@ -487,6 +487,49 @@ def ragged_levels(ctx, sw, dev, images, sections=32, size=8192, reps=20):
                        % (sections, size, "/".join(str(n_list.count(n)) for n in sorted(set(n_list)))))
     res["median_snr"] = float(r["snr"].float().median())
     res["graph_speedup_vs_per_level"] = res["per_level_calls"]["ms"] / res["graph"]["ms"]
+
+    # The same levels with a small batch (the first `k` windows of every size):
+    # four per-level calls are then bound by their launches and host calls,
+    # which one replayed graph of the whole ragged batch removes.
+    k = 16
+    sel, off = [], 0
+    for n in sorted(set(n_list)):
+        sel.extend(range(off, off + k))
+        off += n_list.count(n)
+    idx = torch.tensor(sel, device=dev)
+    keep = [prep["keep"][i][idx].contiguous() for i in range(4)]  # alive while the descriptors are used
+    n_small = [n_list[i] for i in sel]
+    small_pairs = ctx.make_pairs(n_small, *keep)
+    small_levels, off = [], 0
+    for n in sorted(set(n_small)):
+        sl = slice(off, off + k)
+        small_levels.append((ctx.make_pairs(n_small[sl], keep[0][sl], keep[1][sl], keep[2][sl], keep[3][sl]),
+                             out[sl]))
+        off += k
+
+    def small_per_level():
+        for pr, o in small_levels:
+            ctx.match_batch_raw(prep["table"], len(images), pr, params_seq, o, ws=ws)
+
+    def small_graph():
+        ctx.match_batch_raw(prep["table"], len(images), small_pairs, params, out[:len(sel)], ws=ws, graph=True)
+
+    small = {}
+    for name, fn in (("per_level_calls", small_per_level), ("graph", small_graph)):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5 * reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        med = times[len(times) // 2]
+        small[name] = dict(ms=med * 1e3, pairs_per_s=len(sel) / med)
+    small["workload"] = "%d pairs of each of 128/256/512/1024 from the same levels" % k
+    small["graph_speedup_vs_per_level"] = small["per_level_calls"]["ms"] / small["graph"]["ms"]
+    res["small_batch"] = small
     return res
 
 
@@ -1490,6 +1533,9 @@ def ragged_main(args):
         log("  n=%s: %.3f ms for %d pairs, %s %.1f %s (%.3f of peak), plan %s"
             % (k, v["ms"], v["pairs"], v["roofline"]["bound"], v["roofline"]["achieved"], v["roofline"]["unit"],
                v["roofline"]["frac"], v["plan"]))
+    sb = g["small_batch"]
+    log("ragged levels, small batch (%s): per-level %.3f ms, graph %.3f ms (%.2fx)"
+        % (sb["workload"], sb["per_level_calls"]["ms"], sb["graph"]["ms"], sb["graph_speedup_vs_per_level"]))
     if not args.no_refine:
         log("refinement on the ragged levels: plain per-level calls vs one graph per iteration + adjoint ...")
         out["refine_levels"] = refine_levels(ctx, sw, dev, images3)
