@@ -35,6 +35,7 @@ S_SECTIONS, SIZE, N, GRID, K_PROJ, P_WHITEN = 64, 4096, 512, 8, 3, 0.65
 PRUNE_R = N // 8  # search radius of the pruned-inverse variant (64 px at 512^2)
 REFINE_R = 8      # search radius of the pruned refinement (its shifts stay below a pixel)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_match_512_headline.txt")
+CONFIG2_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_section_pair_1024.txt")
 LDS_FILE = os.path.join(ROOT, "profiles", "lds_match_512_headline.txt")
 # LDS peak: 256 CUs x 128 bytes per clock x 2.4 GHz
 LDS_PEAK_GBS = 256 * 128 * 2.4
@@ -561,7 +562,7 @@ def config2_block(ctx, sw, dev, reps=20):
         for _ in range(5):
             ctx.match_batch_raw(prep["table"], 2, prep["pairs"], params, out, None, ws)
         torch.cuda.synchronize()
-    kernels, roof = variant_kernels(ctx.profile_read(), n, P, n, False, steps=5)
+    kernels, roof = variant_kernels(ctx.profile_read(), n, P, n, False, traffic_file=CONFIG2_TRAFFIC_FILE, steps=5)
     ctx.profile(False)
     r = sw.parse_records(out)
     # B(q) = A(M q + b): window B's content at centre q sits at M q + b in A,

@@ -141,7 +141,14 @@ def pmc(path, largest_grid=False):
     return "\n".join(lines)
 
 
-def traffic(fetch_csv, write_csv, copy_bytes):
+def traffic(fetch_csv, write_csv, copy_bytes, ref_kernel=None, ref_bytes=None):
+    """Bytes read and written per launch from FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled so that a reference reads (writes) exactly its
+    known bytes: the program's largest device-to-device copy of `copy_bytes`,
+    or with ref_kernel a kernel of the library that reads and writes
+    `ref_bytes` each per launch.  On this GPU FETCH_SIZE can count half the
+    bytes of 128-byte requests, and which request size a copy uses varies, so
+    the reference should issue requests like the kernels it calibrates."""
     f = per_kernel_counters(fetch_csv, largest_grid=True)
     w = per_kernel_counters(write_csv, largest_grid=True)
 
@@ -149,16 +156,25 @@ def traffic(fetch_csv, write_csv, copy_bytes):
         v = d.get(name, {}).get(ctr, [])
         return sum(v) / len(v) if v else None
 
-    copies = [k for k in f if k.startswith("copy:")]
-    if not copies:
-        raise SystemExit("no copy kernel in %s: run the program with its calibration copy" % fetch_csv)
-    # the calibration copy is the largest copy dispatch
-    cf = max(max(f[k]["FETCH_SIZE"]) for k in copies)
-    cw = max(max(w[k]["WRITE_SIZE"]) for k in copies if k in w)
-    kf = copy_bytes / (cf * 1024.0)
-    kw = copy_bytes / (cw * 1024.0)
-    lines = ["calibration: %d-byte copy reads FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB" % (copy_bytes, cf, cw),
-             "scale_fetch %.4f" % kf, "scale_write %.4f" % kw, "source_digest %s" % source_digest(),
+    if ref_kernel:
+        cf, cw = mean(f, ref_kernel, "FETCH_SIZE"), mean(w, ref_kernel, "WRITE_SIZE")
+        if cf is None or cw is None:
+            raise SystemExit("no %s in the counter files" % ref_kernel)
+        kf = ref_bytes / (cf * 1024.0)
+        kw = ref_bytes / (cw * 1024.0)
+        head = "calibration: %s reads and writes %d bytes per launch: FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB" % (
+            ref_kernel, ref_bytes, cf, cw)
+    else:
+        copies = [k for k in f if k.startswith("copy:")]
+        if not copies:
+            raise SystemExit("no copy kernel in %s: run the program with its calibration copy" % fetch_csv)
+        # the calibration copy is the largest copy dispatch
+        cf = max(max(f[k]["FETCH_SIZE"]) for k in copies)
+        cw = max(max(w[k]["WRITE_SIZE"]) for k in copies if k in w)
+        kf = copy_bytes / (cf * 1024.0)
+        kw = copy_bytes / (cw * 1024.0)
+        head = "calibration: %d-byte copy reads FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB" % (copy_bytes, cf, cw)
+    lines = [head, "scale_fetch %.4f" % kf, "scale_write %.4f" % kw, "source_digest %s" % source_digest(),
              "%-26s %16s %16s %16s" % ("kernel", "read_B/launch", "write_B/launch", "traffic_B/launch")]
     for name in sorted(k for k in f if not k.startswith("copy:")):
         fr, wr = mean(f, name, "FETCH_SIZE"), mean(w, name, "WRITE_SIZE")
@@ -241,6 +257,8 @@ def main(argv=None):
     a.add_argument("fetch_csv")
     a.add_argument("write_csv")
     a.add_argument("--copy-bytes", type=int, default=1 << 30)
+    a.add_argument("--ref-kernel", default=None, help="calibrate against this kernel instead of the copy")
+    a.add_argument("--ref-bytes", type=int, default=1 << 30, help="bytes the reference kernel reads and writes")
     a = sub.add_parser("lds")
     a.add_argument("csv")
     a.add_argument("--cus", type=int, default=256)
@@ -252,7 +270,7 @@ def main(argv=None):
     elif args.cmd == "lds":
         print(lds(args.csv, args.cus))
     else:
-        print(traffic(args.fetch_csv, args.write_csv, args.copy_bytes))
+        print(traffic(args.fetch_csv, args.write_csv, args.copy_bytes, args.ref_kernel, args.ref_bytes))
 
 
 if __name__ == "__main__":
