@@ -191,13 +191,14 @@ struct Layout {
 // Per window size: tau[1024] float2, taper[1024] float, TaperInfo.
 constexpr size_t kTaperSlot = 1024 * sizeof(float2) + 1024 * sizeof(float) + 256;
 
+// row slices of the adjoint's row pass (its partial sums per pair)
 size_t nslice(int n) {
   switch (n) {
-    case 64: return 64 / RowsCfg<64>::FWD;
-    case 128: return 128 / RowsCfg<128>::FWD;
-    case 256: return 256 / RowsCfg<256>::FWD;
-    case 512: return 512 / RowsCfg<512>::FWD;
-    default: return 1024 / RowsCfg<1024>::FWD;
+    case 64: return 64 / BwdRowsCfg<64>::R;
+    case 128: return 128 / BwdRowsCfg<128>::R;
+    case 256: return 256 / BwdRowsCfg<256>::R;
+    case 512: return 512 / BwdRowsCfg<512>::R;
+    default: return 1024 / BwdRowsCfg<1024>::R;
   }
 }
 size_t ncolwg(int n) {

@@ -83,7 +83,6 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
   wave_lds_sync();
 
   float dj = 0.0f, dj1 = 0.0f, hxx = 0.0f, hyy = 0.0f, hxy = 0.0f;
-  float2 gb[E];
   if (valid) {
     const PairStat ps = a.ps[pair];
     const swift_match rec = a.rec[pair];
@@ -212,36 +211,24 @@ __global__ void __launch_bounds__(256) k_bwd_col(BwdArgs a) {
         gfb = cscale(cmul(cconj(gxy), fb), sca);  // imaginary channel: d(dy)
       }
       v[e] = make_float2(gfa.x - gfb.y, gfa.y + gfb.x);  // Q(ky, w) = G_FA + i G_FB
-      // G_FA, G_FB of column w for the mirrored column (slot A is free; slot
-      // B still holds mirror spectra other lanes read)
-      slotA[lidx(ky)] = gfa;
-      gb[e] = gfb;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int e = 0; e < E; ++e) slotB[lidx(t + e * T)] = gb[e];
-    wave_lds_sync();
-    if (wm != w) {
-      // Q(ky, N - w) = conj(G_FA(-ky, w)) + i conj(G_FB(-ky, w))
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int ky = t + e * T;
-        const float2 ga = cconj(slotA[lidx((N - ky) & (N - 1))]);
-        const float2 gbm = cconj(slotB[lidx((N - ky) & (N - 1))]);
-        u[e] = make_float2(ga.x - gbm.y, ga.y + gbm.x);
-      }
+      // the mirrored column's bin N - ky, Q(N - ky, N - w) = conj(G_FA(ky, w))
+      // + i conj(G_FB(ky, w)), goes to slot A (free; slot B still holds mirror
+      // spectra other lanes read), so no gradient is held in registers
+      slotA[lidx((N - ky) & (N - 1))] = make_float2(gfa.x + gfb.y, gfb.x - gfa.y);
     }
     wave_lds_sync();
     // twiddles loaded only now: they are not live during the gradient loop
     Twiddles<N> tw;
     tw_load<N>(tw, t, a.tw);
     float2* dst = a.Y + (size_t)pair * N * N;
-    fft_wave<N, true>(v, slotA, t, tw);
+    fft_wave<N, true>(v, slotB, t, tw);  // slot B is free once the loop is done
 #pragma unroll
     for (int e = 0; e < E; ++e) dst[(size_t)w * N + t + e * T] = v[e];
     if (wm != w) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) u[e] = slotA[lidx(t + e * T)];
       wave_lds_sync();
-      fft_wave<N, true>(u, slotB, t, tw);
+      fft_wave<N, true>(u, slotA, t, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) dst[(size_t)wm * N + t + e * T] = u[e];
     }
@@ -414,7 +401,7 @@ __device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t*
                                           const float (&tx)[GatherCfg<N>::XV], const swift_image& im, bool trans,
                                           int y0, int tid, float off, float mean_off, bool ch1,
                                           float (&acc)[kBwdSums], float (&acc2)[kBwdSums]) {
-  constexpr int R = RowsCfg<N>::FWD;
+  constexpr int R = BwdRowsCfg<N>::R;
   if (g.use) {
     if (trans)
       bwd_pixels<N, R, true, true, TWO, TO>(stage, RS, tile, g, rp, trow, ku, tx, im, y0, tid, off, mean_off, ch1, acc, acc2);
@@ -429,12 +416,9 @@ __device__ __forceinline__ void bwd_image(const float2* stage, int RS, uint32_t*
 template <int N, bool CJ, bool TO>
 __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
   using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, G = 256 / T, R = RowsCfg<N>::FWD, NSLICE = N / R;
+  constexpr int T = C::T, E = C::E, G = 256 / T, R = BwdRowsCfg<N>::R, NSLICE = N / R;
   constexpr int RS = rows_stride<R>(fft_scratch<N>());
-  // the adjoint's row pass keeps its stage and tile in separate arrays; at
-  // 1024^2 both would not leave room for two workgroups per CU, so it
-  // gathers from memory there
-  constexpr int BUDGET = N >= 1024 ? 0 : RowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
+  constexpr int BUDGET = BwdRowsCfg<N>::TILE, XV = GatherCfg<N>::XV;
   static_assert(R % G == 0 && 2 * R <= 64, "row split");
   __shared__ float2 stage[R * RS];
   __shared__ __align__(16) uint32_t tile[BUDGET > 0 ? BUDGET / 4 + 1 : 1];  // + 1: tile_pair reads the dword after a pair
@@ -459,12 +443,12 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
     im[m].width = max(im[m].width, 2);
     im[m].height = max(im[m].height, 2);
     ra[m] = row_affine(th[m]);
-    tg[m] = tile_geom<N, R, BUDGET, RowsCfg<N>::TRW>(ra[m], im[m], y0);
+    tg[m] = tile_geom<N, R, BUDGET, BwdRowsCfg<N>::TRW>(ra[m], im[m], y0);
     // tiles that reach past the image edge need their edge bytes replicated
     border[m] = !(tg[m].use && tg[m].xlo >= 0 && tg[m].xlo + 4 * tg[m].wt4 <= im[m].width &&
                   tg[m].ylo >= 0 && tg[m].ylo + tg[m].ht <= im[m].height);
   }
-  constexpr int TRW = RowsCfg<N>::TRW;
+  constexpr int TRW = BwdRowsCfg<N>::TRW;
   uint4 bufA[TRW], bufB[TRW];
   if (tg[0].use) tile_fetch<tile_cw<N>()>(bufA, tg[0], im[0], tid);
   if (!CJ && tg[1].use) tile_fetch<tile_cw<N>()>(bufB, tg[1], im[1], tid);
@@ -598,7 +582,7 @@ __global__ void __launch_bounds__(256) k_bwd_row(BwdArgs a) {
 template <int N, bool CJ>
 __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
   constexpr int NW = bwd_col_blocks<N>();
-  constexpr int NSLICE = N / RowsCfg<N>::FWD;
+  constexpr int NSLICE = N / BwdRowsCfg<N>::R;
   __shared__ double tot[2 * kBwdSums];
   const int pair = blockIdx.x, ln = threadIdx.x;
   double dj = 0.0, dj1 = 0.0, hs[3] = {0.0, 0.0, 0.0};
@@ -654,7 +638,7 @@ __global__ void __launch_bounds__(64) k_bwd_fin(BwdArgs a) {
 template <int N, bool CJ>
 static hipError_t launch_bwd_t(const BwdArgs& a, hipStream_t s, KernelTimer* kt) {
   constexpr int NW = bwd_col_blocks<N>();
-  constexpr int NSLICE = N / RowsCfg<N>::FWD;
+  constexpr int NSLICE = N / BwdRowsCfg<N>::R;
   const unsigned P = (unsigned)a.npairs;
   if (kt) kt->begin(CJ ? "k_cj_col" : "k_bwd_col", N, s);
   k_bwd_col<N, CJ><<<P * NW, 256, 0, s>>>(a);

@@ -169,6 +169,16 @@ template <> struct RowsCfg<512>  { static constexpr int FWD = 8,  INV = 16, TILE
 template <> struct RowsCfg<1024> { static constexpr int FWD = 8,  INV = 16, TILE = 24576, TRW = 6,
                                    FWD2 = 4,  INV2 = 8,  TILE2 = 16384, TRW2 = 4; };
 
+// Rows per workgroup of the adjoint's row pass, its uint8 tile budget and
+// tile loads per thread.  The pass keeps the stage and the tile in separate
+// LDS arrays; at 1024^2 it takes four rows, so that both fit three
+// workgroups per CU; otherwise the forward row pass's defaults.
+template <int N> struct BwdRowsCfg {
+  static constexpr int R = N >= 1024 ? RowsCfg<N>::FWD2 : RowsCfg<N>::FWD;
+  static constexpr int TILE = N >= 1024 ? RowsCfg<N>::TILE2 : RowsCfg<N>::TILE;
+  static constexpr int TRW = N >= 1024 ? RowsCfg<N>::TRW2 : RowsCfg<N>::TRW;
+};
+
 constexpr int kSizes[SWIFT_NSIZES] = {64, 128, 256, 512, 1024};
 
 size_t align256(size_t x);

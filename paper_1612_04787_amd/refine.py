@@ -4,9 +4,10 @@ is repeated, each time from the updated alignment, until the scores settle).
 Two drivers over the same library calls:
   refine_plain    match, then move each window A by its centroid shift;
   refine_adjoint  centroid steps while the batch's longest step is at least
-                  `newton_below` px (far from the solution the centroid step
-                  is cheap and halves the error, and the Jacobian measured
-                  there does not hold at the solution), then match + one
+                  `newton_below` px, by default the step clamp of half a pixel
+                  (far from the solution the centroid step is cheap and halves
+                  the error, and the Jacobian measured there does not hold at
+                  the solution; once no step is clamped it does), then match + one
                   adjoint pass for the Jacobian J of the centroid shift d with
                   respect to the translation of window A and a Newton step
                   t <- t - J^-1 d on d(t) = 0 (centroid step while the integer
@@ -65,7 +66,7 @@ def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol
 
 
 def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                   max_step=0.5, stop_frac=0.0, newton_below=0.25):
+                   max_step=0.5, stop_frac=0.0, newton_below=0.5):
     """Returns (theta_a [P, 8], iterations, list of longest steps).  Centroid
     steps until the longest step of the batch is below newton_below px, Newton
     steps from then on.  The Jacobian is recomputed every Newton iteration: it
@@ -104,7 +105,7 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
 
 
 def refine_adjoint_graph(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                         max_step=0.5, newton_below=0.25, theta_trace=None):
+                         max_step=0.5, newton_below=0.5, theta_trace=None):
     """refine_adjoint with every iteration one replayed graph: the match of the
     whole (ragged) batch, for Newton iterations the centroid Jacobian, the
     update of theta_a, and the copy of the per-window steps into pinned host
