@@ -730,6 +730,8 @@ def refine_levels(ctx, sw, dev, images, sections=32, size=8192, tol=0.005, targe
                                                  max_iter=max_adjoint, theta_trace=trace)
     rms, mx = rms_of(trace[:iters])
     res["batched_adjoint"] = _refine_summary(P, iters, times, rms, mx, target)
+    del trace
+    res["iteration_kernels"] = iteration_kernels(ctx, sw, images, n_list, ia, ib, tha0, thb, pc)
     res["workload"] = ("%d windows of the multi-level input (2048 each of 128/256/512/1024), truth = fractional "
                        "translation of window B, start U(-0.5, 0.5)^2 px away" % P)
     r0 = float((tha0[:, [4, 7]] - truth).norm(dim=1).pow(2).mean().sqrt())
@@ -737,6 +739,49 @@ def refine_levels(ctx, sw, dev, images, sections=32, size=8192, tol=0.005, targe
     a, b = res["plain"], res["batched_adjoint"]
     if a["ms_to_target"] and b["ms_to_target"]:
         res["speedup_to_target"] = a["ms_to_target"] / b["ms_to_target"]
+    return res
+
+
+def iteration_kernels(ctx, sw, images, n_list, ia, ib, tha, thb, params, reps=5):
+    """Per-kernel HIP-event times (ms per iteration, mean of `reps` eager
+    runs on the launch stream) of the two iterations of the adjoint driver
+    over the whole batch: the centroid iteration's match, and the Newton
+    iteration's match with saved state plus the centroid-Jacobian pass."""
+    import torch
+    jp = sw.make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
+                        params.flags | sw.FLAG_JAC_TRANSLATION, params.max_shift)
+    plain = sw.make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r, 0, params.max_shift)
+    prep = ctx.prepare(images, n_list, ia, ib, tha.clone(), thb)
+    P = prep["pairs"].n_pairs
+    need, sv = ctx.workspace_size(prep["pairs"], plain)
+    ws = torch.empty(need, dtype=torch.uint8, device=ctx.device)
+    saved = torch.empty(sv, dtype=torch.uint8, device=ctx.device)
+    out = torch.empty((P, sw.swift.REC_BYTES), dtype=torch.uint8, device=ctx.device)
+    jac = torch.empty((P, 2, 6), dtype=torch.float32, device=ctx.device)
+    calls = {
+        "match": lambda: ctx.match_batch_raw(prep["table"], len(images), prep["pairs"], plain, out, ws=ws),
+        "match_saved": lambda: ctx.match_batch_raw(prep["table"], len(images), prep["pairs"], plain, out,
+                                                   saved=saved, ws=ws),
+        "jacobian": lambda: ctx.centroid_jacobian_raw(prep["table"], len(images), prep["pairs"], jp, saved, jac,
+                                                      ws=ws),
+    }
+    res = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ks = {k: round(v[1] / reps, 4) for k, v in sorted(prof.items(), key=lambda x: -x[1][1])}
+        res[name] = {"ms": round(sum(ks.values()), 3), "kernels": ks}
+    res["centroid_iteration_ms"] = res["match"]["ms"]
+    res["newton_iteration_ms"] = round(res["match_saved"]["ms"] + res["jacobian"]["ms"], 3)
+    res["note"] = ("kernel times only, size groups in sequence; the refinement's graphs run the groups "
+                   "concurrently and add the update and the step copy")
+    del ws, saved
     return res
 
 
@@ -1544,6 +1589,10 @@ def ragged_main(args):
         log("refine levels: to %.2f px rms plain %s it %s ms | batched+adjoint %s it %s ms"
             % (q["target_rms_px"], q["plain"]["iters_to_target"], q["plain"]["ms_to_target"],
                q["batched_adjoint"]["iters_to_target"], q["batched_adjoint"]["ms_to_target"]))
+        ik = q["iteration_kernels"]
+        log("refine levels, kernel time per iteration: centroid %.2f ms, Newton %.2f ms (match with saved state "
+            "%.2f + Jacobian %.2f)" % (ik["centroid_iteration_ms"], ik["newton_iteration_ms"], ik["match_saved"]["ms"],
+                                       ik["jacobian"]["ms"]))
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -109,6 +109,25 @@ def stats(path):
     return "\n".join(lines)
 
 
+def grids(path):
+    """Kernel trace (run_kernel_trace.csv) summed per kernel and launch size:
+    a kernel launched at several batch sizes gets one line per grid."""
+    acc = collections.defaultdict(list)
+    for r in _rows(path):
+        name = short_name(r.get("Kernel_Name", ""))
+        if not name:
+            continue
+        grid = int(float(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0))
+        wg = int(float(r.get("Workgroup_Size_X", r.get("Workgroup_Size", 0)) or 0))
+        dur = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        acc[(name, grid // wg if wg else grid)].append(dur)
+    out = sorted(((k[0], k[1], len(v), sum(v) / len(v), sum(v)) for k, v in acc.items()), key=lambda x: -x[4])
+    lines = ["%-26s %10s %7s %12s %12s" % ("kernel", "workgroups", "calls", "avg_ms", "total_ms")]
+    for name, g, calls, avg, tot in out:
+        lines.append("%-26s %10d %7d %12.4f %12.3f" % (name, g, calls, avg / 1e6, tot / 1e6))
+    return "\n".join(lines)
+
+
 def per_kernel_counters(path, largest_grid=False):
     """{kernel: {counter: [value per dispatch]}}; with largest_grid only the
     dispatches of each kernel's largest grid (the production batch, not the
@@ -156,8 +175,15 @@ def traffic(fetch_csv, write_csv, copy_bytes, ref_kernel=None, ref_bytes=None):
         v = d.get(name, {}).get(ctr, [])
         return sum(v) / len(v) if v else None
 
+    def full(d, name, ctr):
+        # the reference's full-size launches: a program may also launch it on
+        # fewer sections with the same grid
+        v = d.get(name, {}).get(ctr, [])
+        top = [x for x in v if x >= 0.9 * max(v)] if v else []
+        return sum(top) / len(top) if top else None
+
     if ref_kernel:
-        cf, cw = mean(f, ref_kernel, "FETCH_SIZE"), mean(w, ref_kernel, "WRITE_SIZE")
+        cf, cw = full(f, ref_kernel, "FETCH_SIZE"), full(w, ref_kernel, "WRITE_SIZE")
         if cf is None or cw is None:
             raise SystemExit("no %s in the counter files" % ref_kernel)
         kf = ref_bytes / (cf * 1024.0)
@@ -250,6 +276,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("stats")
     a.add_argument("csv")
+    a = sub.add_parser("grids")
+    a.add_argument("csv")
     a = sub.add_parser("pmc")
     a.add_argument("csv")
     a.add_argument("--largest-grid", action="store_true", help="only each kernel's largest-grid dispatches")
@@ -265,6 +293,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats(args.csv))
+    elif args.cmd == "grids":
+        print(grids(args.csv))
     elif args.cmd == "pmc":
         print(pmc(args.csv, args.largest_grid))
     elif args.cmd == "lds":
