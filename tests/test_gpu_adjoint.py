@@ -138,7 +138,41 @@ def test_centroid_jacobian_matches_oracle(ctx, pair_small, n, p):
     assert checked >= 1
 
 
-@pytest.mark.parametrize("n", [64, 256, 512])
+@pytest.mark.parametrize("n", [512, 1024])
+def test_centroid_jacobian_translation_windows(ctx, pair_small, n):
+    """Both windows at identity linear parts (the refinement's case): the
+    adjoint's row pass then samples window A with one set of bilinear weights
+    from its uint8 source tile (at 1024^2 four rows per workgroup)."""
+    import paper_1612_04787_amd as sw
+    print("case centroid jacobian, translation windows n=%d" % n, flush=True)
+    a, b = pair_small
+    rng = np.random.default_rng(17 * n)
+    k = 2
+    ta, tb = _thetas(rng, k, n, 1200)
+    ta[:, [2, 3, 5, 6]] = [1, 0, 0, 1]
+    params = sw.make_params(p=0.65)
+    res = ctx.match_batch([a.to(dev()), b.to(dev())], [n] * k, torch.zeros(k, dtype=torch.int32),
+                          torch.ones(k, dtype=torch.int32), torch.from_numpy(ta), torch.from_numpy(tb), params,
+                          save=True)
+    jac = ctx.centroid_jacobian(res, sw.make_params(p=0.65, flags=sw.FLAG_JAC_TRANSLATION)).cpu().numpy()
+    an, bn = a.numpy(), b.numpy()
+    checked = 0
+    for i in range(k):
+        rec, ref = O.centroid_jacobian(an, bn, ta[i].astype(np.float64), tb[i].astype(np.float64), n,
+                                       O.Params(p=0.65))
+        if (rec["peak"] - rec["second"]) <= TIE_REL * abs(rec["peak"]):
+            continue
+        assert (int(res["ix"][i]), int(res["iy"][i])) == (rec["ix"], rec["iy"])
+        for row in range(2):
+            x, y = jac[i, row, [2, 5]], np.asarray(ref[row], np.float64)[[2, 5]]
+            err = np.linalg.norm(x - y) / np.linalg.norm(y)
+            print("   ", i, "d%s/dt rel err %.2e" % ("xy"[row], err), flush=True)
+            assert err <= GRAD_RTOL, (i, row, err, x, y)
+        checked += 1
+    assert checked >= 1
+
+
+@pytest.mark.parametrize("n", [64, 256, 512, 1024])
 def test_centroid_jacobian_translation_only(ctx, pair_small, n):
     """SWIFT_FLAG_JAC_TRANSLATION: the translation columns equal those of the
     full pass (same sums in the same order), the other four are zero; an
