@@ -92,9 +92,13 @@ typedef struct {
  *  centroid_r half-width of the sub-pixel centroid box; only 1 is supported.
  *  flags      an OR of
  *             SWIFT_FLAG_CONCURRENT_SIZES: the size groups of a ragged batch
- *               run concurrently on the context's own streams (forked from
- *               and joined back into the call's stream with events, so the
- *               call stays stream-ordered and capturable);
+ *               that are too small to fill the GPU (forward row pass below
+ *               8192 workgroups, i.e. pairs x n / rows per block) run
+ *               concurrently on the context's own streams, forked from and
+ *               joined back into the call's stream with events, so the call
+ *               stays stream-ordered and capturable; larger groups run on the
+ *               call's stream one after another (beside each other they would
+ *               only share the CUs);
  *             SWIFT_FLAG_JAC_TRANSLATION: swift_centroid_jacobian computes
  *               only the translation columns (tx, ty) of the Jacobian, the
  *               ones the Newton refinement step uses, and writes zeros in
@@ -232,8 +236,9 @@ int swift_match_batch_noalloc(swift_ctx* ctx, const swift_image* imgs, int32_t n
 
 /* swift_match_batch as one hipGraph launch (ragged batching, not in the
  * paper): the first call with a given argument tuple (every pointer, n_imgs,
- * size_count, params) captures the whole batch, with all size groups as
- * concurrent branches, and instantiates it; later calls with the same tuple
+ * size_count, params) captures the whole batch, scheduled as with
+ * SWIFT_FLAG_CONCURRENT_SIZES (groups too small to fill the GPU as concurrent
+ * branches), and instantiates it; later calls with the same tuple
  * only launch the cached graph on `stream`.  Buffer contents may change
  * between calls (the image table, pairs and thetas are read when the graph
  * runs); pointers and counts may not without a new capture.  Up to 16 graphs
@@ -514,8 +519,9 @@ int swift_fit_mesh(swift_ctx* ctx, int32_t S, int32_t grid, const float* theta_a
  *    streams of the context (forked from and joined back into the call's
  *    stream), so that one chunk's forward row pass runs beside another's
  *    column pass.  The records are identical to those of one chunk.  A batch
- *    whose size groups run concurrently (SWIFT_FLAG_CONCURRENT_SIZES, or
- *    swift_match_graph with several sizes) runs each group as one chunk.
+ *    with size groups running beside each other (SWIFT_FLAG_CONCURRENT_SIZES,
+ *    or swift_match_graph, with several sizes one of which is too small to
+ *    fill the GPU) runs every group as one chunk.
  * swift_plan sets the variants of size n (a value < 0 keeps the current one)
  * and reports the rows per block and the chunks (any output may be NULL).
  * Plans are per context; cached graphs are keyed by them.  Errors:

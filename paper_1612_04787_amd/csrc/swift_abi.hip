@@ -583,18 +583,33 @@ static int enqueue_chunks(swift_ctx* ctx, int i, const GroupLayout& g, const Mat
   return SWIFT_OK;
 }
 
+// A size group whose forward row pass launches at least this many
+// workgroups (32 per CU) keeps the whole GPU busy by itself: running it beside
+// other groups only makes them share the CUs.
+constexpr long long kFillBlocks = 8192;
+
 // Enqueues the whole batch on `stream`: per size group the taper tables and
 // the five match kernels.  With `concurrent` and more than one group, each
-// group runs on the context's stream for its size, forked from `stream` by
-// an event and joined back into it.
+// group too small to fill the GPU runs on the context's stream for its size,
+// forked from `stream` by an event and joined back into it; the others run on
+// `stream` itself, one after another.
 static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs, const swift_pairs* pairs,
                          const swift_params* params, swift_match* out, float* surfaces, void* saved, void* ws,
                          hipStream_t stream, bool concurrent, KernelTimer* kt, bool allow_chunks = true) {
   const bool pearson = pearson_mode(params);
   const Layout L = make_layout(pairs, pearson);
-  int groups = 0;
-  for (int i = 0; i < SWIFT_NSIZES; ++i) groups += L.g[i].count > 0 ? 1 : 0;
-  concurrent = concurrent && groups > 1;
+  bool side[SWIFT_NSIZES];
+  int groups = 0, small = 0;
+  for (int i = 0; i < SWIFT_NSIZES; ++i) {
+    groups += L.g[i].count > 0 ? 1 : 0;
+    const long long blocks = (long long)L.g[i].count * fwd_blocks_n(L.g[i].n, ctx->alt_fwd[i] == 1);
+    side[i] = L.g[i].count > 0 && blocks < kFillBlocks;
+    small += side[i] ? 1 : 0;
+  }
+  // a single group, or only groups that fill the GPU: nothing runs beside them
+  concurrent = concurrent && groups > 1 && small > 0;
+  if (!concurrent)
+    for (int i = 0; i < SWIFT_NSIZES; ++i) side[i] = false;
   hipError_t e = hipSuccess;
   if (concurrent) {
     e = hipEventRecord(ctx->fork_ev, stream);
@@ -627,7 +642,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     if (g.count == 0) continue;
     const size_t surf_off = surf_at[i];
     hipStream_t s = stream;
-    if (concurrent) {
+    if (side[i]) {
       s = ctx->gs[i];
       e = hipStreamWaitEvent(s, ctx->fork_ev, 0);
       if (e != hipSuccess) return hip_fail(e, "fork wait");
@@ -690,8 +705,9 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
     a.saved_ps = saved ? (PairStat*)((char*)saved + g.sps) : nullptr;
     a.saved_rec = saved ? (swift_match*)((char*)saved + g.srec) : nullptr;
     a.saved_nb = saved ? (float*)((char*)saved + g.snb) : nullptr;
-    // chunks split one group's passes over two streams; groups that already
-    // run concurrently on their own streams are not split further
+    // chunks split one group's passes over two streams; in a call whose
+    // groups run concurrently no group is split (also not those on the call's
+    // stream)
     const int nch = (allow_chunks && !concurrent) ? min((int)ctx->chunks[i], g.count) : 1;
     if (nch <= 1) {
       e = launch_match_group(g.n, a, ctx->alt_fwd[i], ctx->alt_inv[i] != 0, s, kt);
@@ -700,7 +716,7 @@ static int enqueue_match(swift_ctx* ctx, const swift_image* imgs, int32_t n_imgs
       const int rc = enqueue_chunks(ctx, i, g, a, nch, s, kt);
       if (rc) return rc;
     }
-    if (concurrent) {
+    if (side[i]) {
       e = hipEventRecord(ctx->join_ev[i], s);
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, ctx->join_ev[i], 0);
       if (e != hipSuccess) return hip_fail(e, "join");

@@ -71,6 +71,53 @@ def test_concurrent_and_graph_match_sequential(ctx):
         print("   replay %d: %d records equal" % (rep, P), flush=True)
 
 
+def test_mixed_group_sizes_match_sequential(ctx):
+    """A ragged batch with one size group large enough to fill the GPU (130
+    pairs of 512^2: 8320 forward row workgroups), which the concurrent flag
+    keeps on the call's stream, beside small groups of 128^2 and 256^2 on the
+    context's streams: the same records as the sequential call, direct and
+    as graph replays."""
+    import paper_1612_04787_amd as sw
+    from datagen import make_section_pair
+    print("case graph mixed group sizes", flush=True)
+    a, b, _, _ = make_section_pair(1400, 1400, 53, 553, device=dev(), max_shift=5.0)
+    rng = np.random.default_rng(12)
+    ns, th = [], []
+    for n, k in ((128, 3), (256, 3), (512, 130)):
+        for _ in range(k):
+            cx = rng.uniform(n / 2 + 8, 1400 - n / 2 - 8)
+            cy = rng.uniform(n / 2 + 8, 1400 - n / 2 - 8)
+            th.append([cx, cy, 1, 0, rng.uniform(-3, 3), 0, 1, rng.uniform(-3, 3)])
+            ns.append(n)
+    th = np.array(th, np.float32)
+    P = len(ns)
+    tha = torch.from_numpy(th).to(dev())
+    thb = tha.clone()
+    thb[:, 7] -= 1.25
+    z = torch.zeros(P, dtype=torch.int32, device=dev())
+    prep = ctx.prepare([a, b], ns, z, z + 1, tha, thb)
+    table, pr = prep["table"], prep["pairs"]
+    need, _ = ctx.workspace_size(pr, sw.make_params())
+    ws = torch.empty(need, dtype=torch.uint8, device=dev())
+    ref = torch.empty((P, 64), dtype=torch.uint8, device=dev())
+    con = torch.empty_like(ref)
+    gra = torch.empty_like(ref)
+    p_con = sw.make_params(p=0.65, flags=sw.FLAG_CONCURRENT_SIZES)
+    ctx.match_batch_raw(table, 2, pr, sw.make_params(p=0.65), ref, ws=ws)
+    torch.cuda.synchronize()
+    ctx.match_batch_raw(table, 2, pr, p_con, con, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(con, ref)
+    for rep in range(3):
+        gra.zero_()
+        ctx.match_batch_raw(table, 2, pr, p_con, gra, ws=ws, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(gra, ref), rep
+    r = sw.parse_records(ref)
+    assert bool((r["n"].cpu() == torch.tensor(ns, dtype=torch.int32)).all())
+    assert float(r["snr"].min()) > 0
+
+
 def test_graph_cache_keys(ctx):
     """Different outputs or parameters make different graphs; each stays
     correct after the others have run."""
