@@ -1339,8 +1339,8 @@ def main():
         if not kname.startswith(("k_row_fwd", "k_col", "k_row_inv")):
             continue
         # the library's timer names the column pass k_col<N>; rocprofv3 sees
-        # the instance that runs below 1024^2, k_col_pair<N>
-        lname = kname.replace("k_col<", "k_col_pair<") if N < 1024 else kname
+        # the kernel, k_col_pair<N>
+        lname = kname.replace("k_col<", "k_col_pair<")
         b, busy, dg = read_lds(LDS_FILE, lname)
         if b is None or dg != digest_now:
             continue

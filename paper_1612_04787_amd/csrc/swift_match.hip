@@ -15,8 +15,7 @@
 //   k_col_pair  column FFTs of kx and N-kx, split into F_A and F_B, removes the
 //               weighted mean in the spectrum (F -= m * tau(ky) tau(kx)),
 //               whitens the cross power, inverse column FFT; writes in place
-//               (one FFT group per column pair; k_col, two groups per pair of
-//               columns, at N = 1024).
+//               (one FFT group per column pair).
 //   k_row_inv   inverse row FFTs (two real rows per complex FFT), per-slice
 //               top-2 / argmax and FP64 sum, sum of squares; optional surface.
 //               With a search radius r (the pruned inverse) only the row
@@ -755,74 +754,14 @@ __device__ __forceinline__ void store_column(const MatchArgs& a, float2* Zp, int
 }
 
 // ---------------------------------------------------------------- column pass + whitening
-// Two FFT groups per column pair (used at N = 1024, where a group is a whole
-// wavefront of 16 elements per lane): group 0 transforms column kx, group 1
-// its mirror N - kx and hands it over through LDS behind a workgroup barrier;
-// group 0 then splits, whitens and inverse-transforms column kx.
-template <int N, bool PRUNE>
-__global__ void __launch_bounds__(256) k_col(MatchArgs a) {
-  using C = FftCfg<N>;
-  constexpr int T = C::T, E = C::E, G = 256 / T, IPW = G / 2;
-  constexpr int NI = N / 2 + 1, NW = (NI + IPW - 1) / IPW;
-  constexpr int SL = fft_scratch<N>();
-  __shared__ float2 lds[G * SL];
-
-  const int pair = blockIdx.x / NW, wg = blockIdx.x % NW;
-  const int tid = threadIdx.x, c = tid / T, t = tid % T;
-  const int which = c / IPW, item = c % IPW, w = wg * IPW + item;
-  const bool valid = w < NI;
-  const int col = which == 0 ? w : ((N - w) & (N - 1));
-  float2* Zp = a.Z + (size_t)pair * N * N;
-  float2* slot = lds + c * SL;
-  float2 v[E];
-  Twiddles<N> tw;
-  tw_load<N>(tw, t, a.tw);
-
-  float2 tau[E];
-  if (valid) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = Zp[ztile<N>(col, t + e * T)];
-#pragma unroll
-    for (int e = 0; e < E; ++e) tau[e] = a.tau[t + e * T];
-    fft_wave<N, false>(v, slot, t, tw);
-    if (a.saved_Z && (which == 0 || (col != w))) {
-      float2* sz = a.saved_Z + (size_t)pair * N * N + (size_t)col * N;
-#pragma unroll
-      for (int e = 0; e < E; ++e) sz[t + e * T] = v[e];
-    }
-    if (which == 1) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) slot[lidx(t + e * T)] = v[e];
-    }
-  }
-  __syncthreads();
-  if (valid && which == 0) {
-    const PairStat ps = a.pstat[pair];
-    const float2* part = lds + (c + IPW) * SL;
-    const float2 tauw = a.tau[w];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int ky = t + e * T;
-      v[e] = whiten_bin(v[e], cconj(part[lidx((N - ky) & (N - 1))]), cmul(tau[e], tauw), ps, a.p, a.eps_rel,
-                        ky == 0 && w == 0);
-    }
-    if constexpr (PRUNE) {
-      float csq = 0.0f;
-#pragma unroll
-      for (int e = 0; e < E; ++e) csq = fmaf(v[e].x, v[e].x, fmaf(v[e].y, v[e].y, csq));
-      col_sumsq<N, T>(a, pair, w, t, csq);
-    }
-    fft_wave<N, true>(v, slot, t, tw);
-    store_column<N, T, E, PRUNE>(a, Zp, w, t, v);
-  }
-}
-
 // Column pass with one FFT group per column pair: the group transforms
 // columns N - kx and kx, splits, whitens and inverse-transforms column kx,
 // exchanging the mirror column through its own LDS slot (no block barrier,
-// no idle groups).  Same results as k_col.
+// no idle groups).  At 1024^2 (16 elements per lane, two columns in flight)
+// the register budget is held to 168 VGPRs, three workgroups per CU, which
+// the LDS slots allow.
 template <int N, bool PRUNE>
-__global__ void __launch_bounds__(256) k_col_pair(MatchArgs a) {
+__global__ void __launch_bounds__(256, N >= 1024 ? 3 : 1) k_col_pair(MatchArgs a) {
   using C = FftCfg<N>;
   constexpr int T = C::T, E = C::E, G = 256 / T;
   constexpr int NI = N / 2 + 1, NW = (NI + G - 1) / G;
@@ -1289,7 +1228,7 @@ struct TimerScope {
 template <int N, int R, int BUDGET, int TRW, int R2>
 static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer* kt) {
   using C = FftCfg<N>;
-  constexpr int G = 256 / C::T, IPW = G / 2, NW = (N / 2 + 1 + IPW - 1) / IPW;
+  constexpr int G = 256 / C::T;
   const unsigned P = (unsigned)a.npairs;
   if (a.nsl_fwd != N / R) return hipErrorInvalidValue;
   if (a.max_shift > 0 ? (a.nsl_inv > N / R2 || a.nsl_lo > a.nsl_inv) : (a.nsl_inv != N / R2))
@@ -1317,18 +1256,11 @@ static hipError_t launch_group_v(const MatchArgs& a, hipStream_t s, KernelTimer*
   }
   {
     TimerScope ts(kt, "k_col", N, s);
-    if constexpr (N <= 512) {
-      constexpr int NW2 = (N / 2 + 1 + G - 1) / G;
-      if (a.max_shift > 0)
-        k_col_pair<N, true><<<P * NW2, 256, 0, s>>>(a);
-      else
-        k_col_pair<N, false><<<P * NW2, 256, 0, s>>>(a);
-    } else {
-      if (a.max_shift > 0)
-        k_col<N, true><<<P * NW, 256, 0, s>>>(a);
-      else
-        k_col<N, false><<<P * NW, 256, 0, s>>>(a);
-    }
+    constexpr int NW2 = (N / 2 + 1 + G - 1) / G;
+    if (a.max_shift > 0)
+      k_col_pair<N, true><<<P * NW2, 256, 0, s>>>(a);
+    else
+      k_col_pair<N, false><<<P * NW2, 256, 0, s>>>(a);
   }
   {
     TimerScope ts(kt, "k_row_inv", N, s);
