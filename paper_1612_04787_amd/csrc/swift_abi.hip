@@ -191,20 +191,6 @@ struct Layout {
 // Per window size: tau[1024] float2, taper[1024] float, TaperInfo.
 constexpr size_t kTaperSlot = 1024 * sizeof(float2) + 1024 * sizeof(float) + 256;
 
-// row slices of the adjoint's row pass (its partial sums per pair)
-size_t nslice(int n) {
-  switch (n) {
-    case 64: return 64 / BwdRowsCfg<64>::R;
-    case 128: return 128 / BwdRowsCfg<128>::R;
-    case 256: return 256 / BwdRowsCfg<256>::R;
-    case 512: return 512 / BwdRowsCfg<512>::R;
-    default: return 1024 / BwdRowsCfg<1024>::R;
-  }
-}
-size_t ncolwg(int n) {
-  const int ipw = col_items_per_wg(n);
-  return (size_t)((n / 2 + 1 + ipw - 1) / ipw);
-}
 
 // pearson: room for the Pearson row sums and patch energies.
 Layout make_layout(const swift_pairs* pairs, bool pearson = false) {
@@ -242,9 +228,9 @@ Layout make_layout(const swift_pairs* pairs, bool pearson = false) {
     g.y = bo;
     bo += align256(P * n * n * sizeof(float2));
     g.dpart = bo;
-    bo += align256(P * ncolwg(g.n) * kDpart * sizeof(double));
+    bo += align256(P * (size_t)bwd_col_blocks_n(g.n) * kDpart * sizeof(double));
     g.rpart = bo;
-    bo += align256(P * nslice(g.n) * 2 * kBwdSums * sizeof(double));
+    bo += align256(P * (size_t)bwd_row_blocks_n(g.n) * 2 * kBwdSums * sizeof(double));
     g.sz = so;
     so += align256(P * n * n * sizeof(float2));
     g.sps = so;

@@ -675,4 +675,24 @@ hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hip
   return centroid_jac ? launch_bwd_n<true>(n, a, s, kt) : launch_bwd_n<false>(n, a, s, kt);
 }
 
+int bwd_col_blocks_n(int n) {
+  switch (n) {
+    case 64: return bwd_col_blocks<64>();
+    case 128: return bwd_col_blocks<128>();
+    case 256: return bwd_col_blocks<256>();
+    case 512: return bwd_col_blocks<512>();
+    default: return bwd_col_blocks<1024>();
+  }
+}
+
+int bwd_row_blocks_n(int n) {
+  switch (n) {
+    case 64: return 64 / BwdRowsCfg<64>::R;
+    case 128: return 128 / BwdRowsCfg<128>::R;
+    case 256: return 256 / BwdRowsCfg<256>::R;
+    case 512: return 512 / BwdRowsCfg<512>::R;
+    default: return 1024 / BwdRowsCfg<1024>::R;
+  }
+}
+
 }  // namespace swift

@@ -207,7 +207,8 @@ hipError_t launch_fused_group(int n, const MatchArgs& a, hipStream_t s, KernelTi
 int fwd_blocks_n(int n, bool alt);  // forward row blocks per pair
 int inv_blocks_n(int n, bool alt);  // inverse row blocks per pair
 hipError_t launch_backward_group(int n, const BwdArgs& a, bool centroid_jac, hipStream_t s, KernelTimer* kt);
-int col_items_per_wg(int n);  // column-pass workgroups per pair
+int bwd_col_blocks_n(int n);  // adjoint column-stage workgroups per pair
+int bwd_row_blocks_n(int n);  // adjoint row-stage workgroups (row slices) per pair
 hipError_t launch_snr(const float* surf, int n, int batch, int exclude_r, swift_match* out, hipStream_t s);
 hipError_t launch_render(const uint8_t* src, int64_t spitch, int64_t sstride, int S, int sh, int sw,
                          const double* aff, int level, uint8_t* dst, int64_t dpitch, int64_t dstride, int dh, int dw,

@@ -1287,8 +1287,6 @@ static hipError_t launch_group_t(const MatchArgs& a, bool alt_fwd, bool alt_inv,
   return launch_group_v<N, RC::FWD2, RC::TILE2, RC::TRW2, RC::INV2>(a, s, kt);
 }
 
-int col_items_per_wg(int n) { return (256 / (n <= 512 ? n / 8 : 64)) / 2; }
-
 int fwd_blocks_n(int n, bool alt) {
   switch (n) {
     case 64: return 64 / (alt ? RowsCfg<64>::FWD2 : RowsCfg<64>::FWD);
