@@ -377,7 +377,7 @@ def refine_comparison(ctx, sw, stack, cen, dev, tol=0.005, target=0.01, seed=9, 
         out[name] = dict(iterations=iters, wall_ms=wall * 1e3, rms_px=r, max_px=mx,
                          iters_to_target=hit, ms_to_target=hit_ms, windows_per_s=P / wall)
     r0 = rms_max(tha)[0]
-    return dict(note="adjoint: centroid steps until the longest step is below 0.25 px, then Newton steps on the "
+    return dict(note="adjoint: centroid steps until the longest step is below the 0.5 px clamp, then Newton steps on the "
                      "centroid shift with the Jacobian (translation columns) from one adjoint pass per iteration",
                 workload="%d windows of %d^2 (the benchmark's window grid), truth = fractional translation of "
                          "window B, start U(-0.5, 0.5)^2 px away" % (P, N),
@@ -783,6 +783,57 @@ def iteration_kernels(ctx, sw, images, n_list, ia, ib, tha, thb, params, reps=5)
                    "concurrently and add the update and the step copy")
     del ws, saved
     return res
+
+
+def refine_generator_bias(ctx, sw, dev, size=2048, n=512, seed=21,
+                          shifts=((0.31, -0.22), (-0.44, 0.17), (0.12, 0.41), (-0.27, -0.36))):
+    """Sensitivity of the refinement's fixed point to how the sub-pixel truth
+    is generated: image B is image A (a 2048^2 section) moved by a fractional
+    shift d, B(q) = A(q - d), resampled by SciPy as a cubic B-spline
+    (ndimage.shift, order 3) or bilinearly (order 1, the gather's own
+    convention), both kept in FP32.  A 3 x 3 grid of 512^2 windows per shift
+    and generator, window B at identity, window A starting U(-0.5, 0.5)^2 px
+    from its aligned translation -d; the adjoint driver runs until its longest
+    step is below 1e-4 px.  Reports the converged error |t + d| per generator."""
+    import numpy as np
+    import torch
+    from scipy import ndimage
+
+    from datagen import make_section
+    from paper_1612_04787_amd.refine import refine_adjoint
+    a = make_section(size, size, seed).numpy().astype(np.float64)
+    images = [torch.from_numpy(a.astype(np.float32)).to(dev)]
+    rng = np.random.default_rng(seed)
+    cs = [size / 2 - 600, size / 2, size / 2 + 600]
+    ta, tb, ia, ib, gen, dd = [], [], [], [], [], []
+    for (dx, dy) in shifts:
+        for order in (3, 1):
+            b = ndimage.shift(a, (dy, dx), order=order, mode="nearest")
+            images.append(torch.from_numpy(b.astype(np.float32)).to(dev))
+            for cy in cs:
+                for cx in cs:
+                    tb.append([cx, cy, 1, 0, 0, 0, 1, 0])
+                    ta.append([cx, cy, 1, 0, -dx + rng.uniform(-0.5, 0.5), 0, 1, -dy + rng.uniform(-0.5, 0.5)])
+                    ia.append(0)
+                    ib.append(len(images) - 1)
+                    gen.append(order)
+                    dd.append((dx, dy))
+    P = len(ta)
+    tha = torch.tensor(ta, dtype=torch.float32, device=dev)
+    thb = torch.tensor(tb, dtype=torch.float32, device=dev)
+    ia_t = torch.tensor(ia, dtype=torch.int32, device=dev)
+    ib_t = torch.tensor(ib, dtype=torch.int32, device=dev)
+    th, iters, _ = refine_adjoint(ctx, images, [n] * P, ia_t, ib_t, tha, thb, sw.make_params(p=P_WHITEN),
+                                  tol=1e-4, max_iter=30)
+    t = th[:, [4, 7]].double().cpu().numpy()
+    err = np.linalg.norm(t + np.asarray(dd, np.float64), axis=1)
+    gen = np.asarray(gen)
+    out = {}
+    for order, name in ((3, "cubic"), (1, "bilinear")):
+        e = err[gen == order]
+        out[name] = dict(mean_px=float(e.mean()), max_px=float(e.max()), windows=int(e.size))
+    return dict(workload="%d windows of %d^2 on a %d^2 section moved by %d fractional shifts, p = %.2f"
+                         % (P, n, size, len(shifts), P_WHITEN), iterations=iters, **out)
 
 
 def _refine_summary(P, iters, times, rms, mx, target):
@@ -1442,6 +1493,10 @@ def main():
         ws = None
         line["refine"] = refine_comparison(ctx, sw, stack, cen, dev)
         line["refine_pruned"] = refine_comparison(ctx, sw, stack, cen, dev, max_shift=REFINE_R)
+        line["refine_generator_bias"] = gb = refine_generator_bias(ctx, sw, dev)
+        log("refine, truth generator sensitivity: converged error %.4f px mean (%.4f max) with a cubic-spline "
+            "shifted image, %.1e px with a bilinear one" % (gb["cubic"]["mean_px"], gb["cubic"]["max_px"],
+                                                           gb["bilinear"]["mean_px"]))
         for key in ("refine", "refine_pruned"):
             rf = line[key]
             log("%s: to 0.01 px plain %s it %.1f ms | adjoint %s it %.1f ms; final rms plain %.2e adjoint %.2e"
