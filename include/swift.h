@@ -41,7 +41,7 @@ extern "C" {
 
 #define SWIFT_OK             0
 #define SWIFT_E_INVAL       -1 /* bad argument (NULL, size, range, ordering)   */
-#define SWIFT_E_UNSUPPORTED -2 /* valid request this build does not implement  */
+#define SWIFT_E_UNSUPPORTED -2 /* valid request the library does not implement */
 #define SWIFT_E_WORKSPACE   -3 /* workspace or saved buffer too small          */
 #define SWIFT_E_HIP         -4 /* HIP runtime error (message has its string)   */
 #define SWIFT_E_CAPTURE     -5 /* hipGraph capture/instantiate/launch failed    */
