@@ -4,7 +4,7 @@ is repeated, each time from the updated alignment, until the scores settle).
 Two drivers over the same library calls:
   refine_plain    match, then move each window A by its centroid shift;
   refine_adjoint  centroid steps while the batch's longest step is at least
-                  `newton_below` px, by default the step clamp of half a pixel
+                  `newton_below` px, by default the step clamp (half a pixel)
                   (far from the solution the centroid step is cheap and halves
                   the error, and the Jacobian measured there does not hold at
                   the solution; once no step is clamped it does), then match + one
@@ -66,14 +66,17 @@ def refine_plain(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol
 
 
 def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                   max_step=0.5, stop_frac=0.0, newton_below=0.5):
+                   max_step=0.5, stop_frac=0.0, newton_below=None):
     """Returns (theta_a [P, 8], iterations, list of longest steps).  Centroid
-    steps until the longest step of the batch is below newton_below px, Newton
+    steps until the longest step of the batch is below newton_below px (None:
+    max_step, i.e. until no step is clamped), Newton
     steps from then on.  The Jacobian is recomputed every Newton iteration: it
     changes across a pixel cell (bilinear sampling), and reusing an earlier
     one (chord steps) stalls.  Only its translation columns are computed (the
     Newton step uses no others)."""
     from .swift import FLAG_JAC_TRANSLATION, make_params
+    if newton_below is None:
+        newton_below = max_step
     jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
                           params.flags | FLAG_JAC_TRANSLATION, params.max_shift)
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
@@ -105,7 +108,7 @@ def refine_adjoint(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, t
 
 
 def refine_adjoint_graph(sw, images, n_list, img_a, img_b, theta_a, theta_b, params, tol=0.005, max_iter=20,
-                         max_step=0.5, newton_below=0.5, theta_trace=None):
+                         max_step=0.5, newton_below=None, theta_trace=None):
     """refine_adjoint with every iteration one replayed graph: the match of the
     whole (ragged) batch, for Newton iterations the centroid Jacobian, the
     update of theta_a, and the copy of the per-window steps into pinned host
@@ -118,6 +121,8 @@ def refine_adjoint_graph(sw, images, n_list, img_a, img_b, theta_a, theta_b, par
     import time
 
     from .swift import FLAG_JAC_TRANSLATION, make_params
+    if newton_below is None:
+        newton_below = max_step
     jparams = make_params(params.p, params.eps_rel, params.taper_frac, params.centroid_r,
                           params.flags | FLAG_JAC_TRANSLATION, params.max_shift)
     prep, th = _state(sw, images, n_list, img_a, img_b, theta_a.clone(), theta_b)
